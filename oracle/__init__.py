@@ -1,0 +1,147 @@
+"""FP64 CPU oracle of the MPDATA time step -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  The product path (the HIP library and its Python
+binding) never imports it.
+
+Thin ctypes wrapper over liboracle.so (built from mpdata_oracle*.c by
+oracle/build.py).  Arrays are numpy float64, C-contiguous, last dimension
+fastest.  The advector component c[d] has n[d]+1 entries along dimension d.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+BC_PERIODIC, BC_OPEN = 0, 1
+OPT_FCT, OPT_IGA, OPT_TOT = 1, 2, 4
+
+_LIB = None
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.OUT
+        srcs = [os.path.join(_build.HERE, s) for s in _build.SOURCES]
+        newest = max(os.path.getmtime(s) for s in srcs if os.path.exists(s))
+        if not os.path.exists(path) or os.path.getmtime(path) < newest:
+            _build.build()
+        lib = ctypes.CDLL(path)
+        L3 = ctypes.c_long * 3
+        I3 = ctypes.c_int * 3
+        lib.orc_step.argtypes = [ctypes.c_int, L3, I3, ctypes.c_int, ctypes.c_uint,
+                                 _DP, _DP, _DP, _DP, _DP, ctypes.c_long]
+        lib.orc_diag.argtypes = [ctypes.c_int, L3, _DP, _DP, _DP,
+                                 ctypes.POINTER(ctypes.c_long)]
+        lib.orc_courant_max.argtypes = [ctypes.c_int, L3, I3, _DP, _DP, _DP, _DP, _DP]
+        if hasattr(lib, "orc_adjoint"):
+            lib.orc_adjoint.argtypes = [ctypes.c_int, L3, I3, ctypes.c_int, ctypes.c_uint,
+                                        _DP, _DP, _DP, _DP, _DP, ctypes.c_long, ctypes.c_long,
+                                        _DP, _DP, _DP, _DP, _DP]
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a):
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dims(psi_shape, bc):
+    ndims = len(psi_shape)
+    n = [int(s) for s in psi_shape] + [1] * (3 - ndims)
+    if isinstance(bc, int):
+        bc = [bc] * ndims
+    bcs = list(bc) + [0] * (3 - ndims)
+    return ndims, (ctypes.c_long * 3)(*n), (ctypes.c_int * 3)(*bcs)
+
+
+def _check_c(psi_shape, c):
+    ndims = len(psi_shape)
+    if len(c) != ndims:
+        raise ValueError("need one advector component per dimension")
+    for d, cd in enumerate(c):
+        want = list(psi_shape)
+        want[d] += 1
+        if tuple(cd.shape) != tuple(want):
+            raise ValueError(f"c[{d}] has shape {cd.shape}, expected {tuple(want)}")
+
+
+def step(psi, c, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1):
+    """Return psi advanced by n_steps MPDATA steps (input not modified)."""
+    psi = np.array(psi, dtype=np.float64, copy=True, order="C")
+    c = [_f64(x) for x in c]
+    _check_c(psi.shape, c)
+    g = _f64(g)
+    ndims, n, bcs = _dims(psi.shape, bc)
+    cc = c + [None] * (3 - ndims)
+    rc = _lib().orc_step(ndims, n, bcs, int(n_iters), int(opts), _ptr(psi), _ptr(g),
+                         _ptr(cc[0]), _ptr(cc[1]), _ptr(cc[2]), int(n_steps))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return psi
+
+
+def diag(psi, g=None):
+    """(sum of G*psi, min, max, count of non-finite values)."""
+    psi = _f64(psi)
+    g = _f64(g)
+    ndims, n, _ = _dims(psi.shape, 0)
+    out = np.zeros(3)
+    bad = ctypes.c_long(0)
+    rc = _lib().orc_diag(ndims, n, _ptr(psi), _ptr(g), _ptr(out), ctypes.byref(bad))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return float(out[0]), float(out[1]), float(out[2]), int(bad.value)
+
+
+def courant_max(psi_shape, c, g=None, bc=BC_PERIODIC):
+    c = [_f64(x) for x in c]
+    _check_c(psi_shape, c)
+    g = _f64(g)
+    ndims, n, bcs = _dims(psi_shape, bc)
+    cc = c + [None] * (3 - ndims)
+    out = ctypes.c_double(0.0)
+    rc = _lib().orc_courant_max(ndims, n, bcs, _ptr(g), _ptr(cc[0]), _ptr(cc[1]),
+                                _ptr(cc[2]), ctypes.byref(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return float(out.value)
+
+
+def adjoint(psi0, c, lambda_T, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1,
+            ckpt_every=0):
+    """Reverse-mode gradient of J through n_steps steps, given dJ/dpsi_T.
+
+    Returns (grad_psi0, [grad_c0, grad_c1, ...])."""
+    psi0 = _f64(psi0)
+    c = [_f64(x) for x in c]
+    _check_c(psi0.shape, c)
+    g = _f64(g)
+    lam = _f64(lambda_T)
+    ndims, n, bcs = _dims(psi0.shape, bc)
+    gpsi = np.zeros_like(psi0)
+    gc = [np.zeros_like(x) for x in c]
+    cc = c + [None] * (3 - ndims)
+    gg = gc + [None] * (3 - ndims)
+    lib = _lib()
+    if not hasattr(lib, "orc_adjoint"):
+        raise RuntimeError("oracle built without the adjoint")
+    rc = lib.orc_adjoint(ndims, n, bcs, int(n_iters), int(opts), _ptr(psi0), _ptr(g),
+                         _ptr(cc[0]), _ptr(cc[1]), _ptr(cc[2]), int(n_steps),
+                         int(ckpt_every if ckpt_every else n_steps or 1), _ptr(lam),
+                         _ptr(gpsi), _ptr(gg[0]), _ptr(gg[1]), _ptr(gg[2]))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return gpsi, gc

@@ -1,0 +1,571 @@
+/*
+ * mpdata_oracle.c -- plain, slow, FP64 CPU reference of the MPDATA time step
+ * (libmpdata++ 0.1 paper, Sect. 3.1).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark.  It shares no code with the HIP library.
+ *
+ * Organisation: every stage of the method is one loop over the whole grid
+ * that reads full arrays through a boundary map and writes a full array, in
+ * the order the method states (donor-cell pass, then per corrective pass the
+ * pseudo-velocity, the optional limiter and the corrective donor-cell pass).
+ * No blocking, no fusion, no reordering.
+ *
+ * Readings where the paper only cites the formulae (frozen; the GPU path
+ * obeys the same ones):
+ *   - boundaries (Sect. 2.2, "cyclic" / "open"): every array, including the
+ *     intermediate ones (pseudo-velocities, limiter coefficients), is read
+ *     through the same map: periodic wraps cell q to q mod n and wall f to
+ *     f mod n (so wall n is wall 0); open clamps cell q into [0, n-1] and
+ *     wall f into [0, n];
+ *   - psi-fractions n/d are 0 when d == 0, with no epsilon; under the infinite
+ *     gauge they become n/m with m the number of values summed in d;
+ *   - multi-dimensional cross terms, third-order terms and the limiter follow
+ *     the forms written next to each function below.
+ */
+#include "mpdata_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int ndims;
+    long n[3];
+    int bc[3];
+    int iga, tot, fct;
+} grid_t;
+
+/* ------------------------------------------------------------------------ */
+/* boundary map (Sect. 2.2 boundary conditions; Sect. 2.3 grid)             */
+/* ------------------------------------------------------------------------ */
+
+static long map_cell(const grid_t *g, int d, long q)
+{
+    long n = g->n[d];
+    if (g->bc[d] == ORC_BC_PERIODIC) {
+        q %= n;
+        if (q < 0) q += n;
+        return q;
+    }
+    if (q < 0) return 0;
+    if (q > n - 1) return n - 1;
+    return q;
+}
+
+static long map_wall(const grid_t *g, int d, long f)
+{
+    long n = g->n[d];
+    if (g->bc[d] == ORC_BC_PERIODIC) {
+        f %= n;
+        if (f < 0) f += n;
+        return f;
+    }
+    if (f < 0) return 0;
+    if (f > n) return n;
+    return f;
+}
+
+static long cells(const grid_t *g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+static long walls(const grid_t *g, int d)
+{
+    long e[3] = {g->n[0], g->n[1], g->n[2]};
+    e[d] += 1;
+    return e[0] * e[1] * e[2];
+}
+
+/* flat index of the cell at p (after the boundary map) */
+static long cidx(const grid_t *g, const long p[3])
+{
+    long i = map_cell(g, 0, p[0]), j = map_cell(g, 1, p[1]),
+         k = map_cell(g, 2, p[2]);
+    return (i * g->n[1] + j) * g->n[2] + k;
+}
+
+/* flat index of the wall p of a dimension-d wall array; p[d] is the wall
+ * index (wall f separates cells f-1 and f), the other entries are cells. */
+static long widx(const grid_t *g, int d, const long p[3])
+{
+    long e[3] = {g->n[0], g->n[1], g->n[2]};
+    long q[3];
+    e[d] += 1;
+    for (int t = 0; t < 3; t++)
+        q[t] = (t == d) ? map_wall(g, t, p[t]) : map_cell(g, t, p[t]);
+    return (q[0] * e[1] + q[1]) * e[2] + q[2];
+}
+
+static double at(const grid_t *g, const double *a, const long p[3])
+{
+    return a[cidx(g, p)];
+}
+
+static double gat(const grid_t *g, const double *G, const long p[3])
+{
+    return G ? G[cidx(g, p)] : 1.0;
+}
+
+static double wat(const grid_t *g, int d, const double *a, const long p[3])
+{
+    return a[widx(g, d, p)];
+}
+
+/* p shifted by s along dimension d */
+static void sh(long out[3], const long p[3], int d, long s)
+{
+    out[0] = p[0];
+    out[1] = p[1];
+    out[2] = p[2];
+    out[d] += s;
+}
+
+/* p shifted by s along d and t along e */
+static void sh2(long out[3], const long p[3], int d, long s, int e, long t)
+{
+    sh(out, p, d, s);
+    out[e] += t;
+}
+
+static double pos(double u) { return u > 0.0 ? u : 0.0; } /* [u]^+ */
+static double neg(double u) { return u < 0.0 ? u : 0.0; } /* [u]^- */
+
+/* psi-fraction of the pseudo-velocity formulae (eq. adf_vel): num/den, or 0
+ * for a zero denominator; the infinite-gauge variant (Sect. 3.1.5) replaces
+ * the denominator by the count m of summed values. */
+static double frac(const grid_t *g, double num, double den, double m)
+{
+    if (g->iga) return num / m;
+    return den == 0.0 ? 0.0 : num / den;
+}
+
+/* ------------------------------------------------------------------------ */
+/* donor-cell pass, eq. (upstream) with the flux function eq. (F)            */
+/* ------------------------------------------------------------------------ */
+
+/* flux through wall p of dimension d: [c]^+ x(left) + [c]^- x(right) */
+static double donor_flux(const grid_t *g, int d, const double *x,
+                         const double *c, const long p[3])
+{
+    long L[3], R[3];
+    sh(L, p, d, -1);
+    sh(R, p, d, 0);
+    double u = wat(g, d, c, p);
+    return pos(u) * at(g, x, L) + neg(u) * at(g, x, R);
+}
+
+/* out(i) = x(i) - [sum_d (F_d(i+1/2) - F_d(i-1/2))] / G(i), dimensions summed
+ * in increasing order.  When iga_flux is set the corrective-pass flux is the
+ * pseudo-velocity itself (infinite-gauge limit, F = V). */
+static void donor_pass(const grid_t *g, const double *x, double *const c[3],
+                       const double *G, int iga_flux, double *out)
+{
+    long p[3];
+    for (p[0] = 0; p[0] < g->n[0]; p[0]++)
+        for (p[1] = 0; p[1] < g->n[1]; p[1]++)
+            for (p[2] = 0; p[2] < g->n[2]; p[2]++) {
+                double acc = 0.0;
+                for (int d = 0; d < g->ndims; d++) {
+                    long lo[3], hi[3];
+                    sh(lo, p, d, 0);
+                    sh(hi, p, d, 1);
+                    double flo, fhi;
+                    if (iga_flux) {
+                        flo = wat(g, d, c[d], lo);
+                        fhi = wat(g, d, c[d], hi);
+                    } else {
+                        flo = donor_flux(g, d, x, c[d], lo);
+                        fhi = donor_flux(g, d, x, c[d], hi);
+                    }
+                    acc += fhi - flo;
+                }
+                double r = G ? acc / at(g, G, p) : acc;
+                out[cidx(g, p)] = at(g, x, p) - r;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* antidiffusive pseudo-velocity (eq. adf_vel and its multi-D / third-order  */
+/* extensions cited in Sects. 3.1.1-3.1.2)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Mean of the dimension-o advector over the four walls of cells L and R that
+ * are normal to o (the cross-velocity at a dimension-d wall). */
+static double cross_mean(const grid_t *g, int o, const double *co,
+                         const long L[3], const long R[3])
+{
+    long a[3], b[3], e[3], f[3];
+    sh(a, L, o, 0);
+    sh(b, L, o, 1);
+    sh(e, R, o, 0);
+    sh(f, R, o, 1);
+    return 0.25 * (wat(g, o, co, a) + wat(g, o, co, b) + wat(g, o, co, e) +
+                   wat(g, o, co, f));
+}
+
+/* Pseudo-velocity at wall p of dimension d from the previous pass's field x
+ * and advector c.  With Gb = (G(L)+G(R))/2 and cb_o the cross means:
+ *   V  = (|c| - c^2/Gb) A                                   (eq. adf_vel)
+ *      - sum_{o!=d} c cb_o / (2 Gb) B_o                     (cross terms)
+ * and with the third-order option:
+ *   V += (3c|c|/Gb - 2c^3/Gb^2 - c)/3 D
+ *      + sum_{o!=d} (|c| cb_o/Gb - 2 c^2 cb_o/Gb^2) E_o
+ *      - (2/3) c cb_o1 cb_o2 / Gb^2 T                      (3-D only)
+ * where A, B_o, D, E_o, T are psi-fractions of the first difference along d,
+ * the centred difference along o, the third difference along d, the mixed
+ * d-o difference and the mixed o1-o2 difference. */
+static double pseudo_velocity(const grid_t *g, int d, const double *x,
+                              double *const c[3], const double *G,
+                              const long p[3])
+{
+    long L[3], R[3];
+    sh(L, p, d, -1);
+    sh(R, p, d, 0);
+    double u = wat(g, d, c[d], p);
+    double Gb = 0.5 * (gat(g, G, L) + gat(g, G, R));
+    double xL = at(g, x, L), xR = at(g, x, R);
+
+    double A = frac(g, xR - xL, xR + xL, 2.0);
+    double V = (fabs(u) - u * u / Gb) * A;
+
+    double cb[3] = {0.0, 0.0, 0.0};
+    for (int o = 0; o < g->ndims; o++) {
+        if (o == d) continue;
+        cb[o] = cross_mean(g, o, c[o], L, R);
+        long Rp[3], Lp[3], Rm[3], Lm[3];
+        sh(Rp, R, o, 1);
+        sh(Lp, L, o, 1);
+        sh(Rm, R, o, -1);
+        sh(Lm, L, o, -1);
+        double a = at(g, x, Rp), b = at(g, x, Lp), e = at(g, x, Rm),
+               f = at(g, x, Lm);
+        double B = frac(g, a + b - e - f, a + b + e + f, 4.0);
+        V -= 0.5 * u * cb[o] / Gb * B;
+    }
+
+    if (g->tot) {
+        long R2[3], L2[3];
+        sh(R2, R, d, 1);
+        sh(L2, L, d, -1);
+        double xR2 = at(g, x, R2), xL2 = at(g, x, L2);
+        double D = frac(g, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, 4.0);
+        V += (3.0 * u * fabs(u) / Gb - 2.0 * u * u * u / (Gb * Gb) - u) /
+             3.0 * D;
+
+        for (int o = 0; o < g->ndims; o++) {
+            if (o == d) continue;
+            long Rp[3], Lp[3], Rm[3], Lm[3];
+            sh(Rp, R, o, 1);
+            sh(Lp, L, o, 1);
+            sh(Rm, R, o, -1);
+            sh(Lm, L, o, -1);
+            double a = at(g, x, Rp), b = at(g, x, Lp), e = at(g, x, Rm),
+                   f = at(g, x, Lm);
+            double E = frac(g, a - b - e + f, a + b + e + f, 4.0);
+            V += (fabs(u) * cb[o] / Gb - 2.0 * u * u * cb[o] / (Gb * Gb)) * E;
+        }
+
+        if (g->ndims == 3) {
+            int o1 = (d == 0) ? 1 : 0;
+            int o2 = (d == 2) ? 1 : 2;
+            double num = 0.0, den = 0.0;
+            const long *side[2] = {L, R};
+            for (int s = 0; s < 2; s++) {
+                long pp[3], mp[3], pm[3], mm[3];
+                sh2(pp, side[s], o1, 1, o2, 1);
+                sh2(mp, side[s], o1, -1, o2, 1);
+                sh2(pm, side[s], o1, 1, o2, -1);
+                sh2(mm, side[s], o1, -1, o2, -1);
+                double vpp = at(g, x, pp), vmp = at(g, x, mp),
+                       vpm = at(g, x, pm), vmm = at(g, x, mm);
+                num += vpp - vmp - vpm + vmm;
+                den += vpp + vmp + vpm + vmm;
+            }
+            double T = frac(g, num, den, 8.0);
+            V += -(2.0 / 3.0) * u * cb[o1] * cb[o2] / (Gb * Gb) * T;
+        }
+    }
+    return V;
+}
+
+static void antidiffusive_velocity(const grid_t *g, const double *x,
+                                   double *const c[3], const double *G,
+                                   double *V[3])
+{
+    for (int d = 0; d < g->ndims; d++) {
+        long e[3] = {g->n[0], g->n[1], g->n[2]};
+        e[d] += 1;
+        long p[3];
+        for (p[0] = 0; p[0] < e[0]; p[0]++)
+            for (p[1] = 0; p[1] < e[1]; p[1]++)
+                for (p[2] = 0; p[2] < e[2]; p[2]++)
+                    V[d][(p[0] * e[1] + p[1]) * e[2] + p[2]] =
+                        pseudo_velocity(g, d, x, c, G, p);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* non-oscillatory option (Sect. 3.1.4): flux-corrected limiting of V        */
+/* ------------------------------------------------------------------------ */
+
+/* Local bounds from the step's input field psi_n and the previous pass's x
+ * over the cell and its face neighbours; inflow/outflow sums of the
+ * corrective fluxes (weight x, or 1 under the infinite gauge); limiter
+ * coefficients
+ *   beta_up = G (psi_max - x) / f_in   (1 when f_in == 0)
+ *   beta_dn = G (x - psi_min) / f_out  (1 when f_out == 0)
+ * and the limited pseudo-velocity at the wall between cells L and R:
+ *   [V]^+ min(1, beta_dn(L), beta_up(R)) + [V]^- min(1, beta_up(L), beta_dn(R)).
+ */
+static void fct_limit(const grid_t *g, const double *psi_n, const double *x,
+                      const double *G, double *V[3], double *const Vlim[3],
+                      double *beta_up, double *beta_dn)
+{
+    long p[3];
+    for (p[0] = 0; p[0] < g->n[0]; p[0]++)
+        for (p[1] = 0; p[1] < g->n[1]; p[1]++)
+            for (p[2] = 0; p[2] < g->n[2]; p[2]++) {
+                double mx = at(g, psi_n, p), mn = mx;
+                double v = at(g, x, p);
+                if (v > mx) mx = v;
+                if (v < mn) mn = v;
+                for (int d = 0; d < g->ndims; d++)
+                    for (int s = -1; s <= 1; s += 2) {
+                        long q[3];
+                        sh(q, p, d, s);
+                        double a = at(g, psi_n, q), b = at(g, x, q);
+                        if (a > mx) mx = a;
+                        if (a < mn) mn = a;
+                        if (b > mx) mx = b;
+                        if (b < mn) mn = b;
+                    }
+
+                double fin = 0.0, fout = 0.0;
+                double xi = at(g, x, p);
+                for (int d = 0; d < g->ndims; d++) {
+                    long lo[3], hi[3], qm[3], qp[3];
+                    sh(lo, p, d, 0);
+                    sh(hi, p, d, 1);
+                    sh(qm, p, d, -1);
+                    sh(qp, p, d, 1);
+                    double vlo = wat(g, d, V[d], lo), vhi = wat(g, d, V[d], hi);
+                    double wm = g->iga ? 1.0 : at(g, x, qm);
+                    double wp = g->iga ? 1.0 : at(g, x, qp);
+                    double wi = g->iga ? 1.0 : xi;
+                    fin += pos(vlo) * wm - neg(vhi) * wp;
+                    fout += pos(vhi) * wi - neg(vlo) * wi;
+                }
+                double Gi = gat(g, G, p);
+                long k = cidx(g, p);
+                beta_up[k] = fin > 0.0 ? Gi * (mx - xi) / fin : 1.0;
+                beta_dn[k] = fout > 0.0 ? Gi * (xi - mn) / fout : 1.0;
+            }
+
+    for (int d = 0; d < g->ndims; d++) {
+        long e[3] = {g->n[0], g->n[1], g->n[2]};
+        e[d] += 1;
+        for (p[0] = 0; p[0] < e[0]; p[0]++)
+            for (p[1] = 0; p[1] < e[1]; p[1]++)
+                for (p[2] = 0; p[2] < e[2]; p[2]++) {
+                    long L[3], R[3];
+                    sh(L, p, d, -1);
+                    sh(R, p, d, 0);
+                    double v = wat(g, d, V[d], p);
+                    double up = 1.0, dn = 1.0;
+                    /* positive V: leaves L, enters R */
+                    if (at(g, beta_dn, L) < up) up = at(g, beta_dn, L);
+                    if (at(g, beta_up, R) < up) up = at(g, beta_up, R);
+                    /* negative V: leaves R, enters L */
+                    if (at(g, beta_up, L) < dn) dn = at(g, beta_up, L);
+                    if (at(g, beta_dn, R) < dn) dn = at(g, beta_dn, R);
+                    Vlim[d][(p[0] * e[1] + p[1]) * e[2] + p[2]] =
+                        pos(v) * up + neg(v) * dn;
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* one step and the driver                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double *x, *y;          /* pass input / output */
+    double *V[3], *W[3];    /* raw and limited pseudo-velocities */
+    double *cprev[3];       /* advector of the previous pass (own copy) */
+    double *bup, *bdn;
+} work_t;
+
+static int work_alloc(const grid_t *g, work_t *w)
+{
+    memset(w, 0, sizeof *w);
+    long N = cells(g);
+    w->x = malloc(sizeof(double) * N);
+    w->y = malloc(sizeof(double) * N);
+    w->bup = malloc(sizeof(double) * N);
+    w->bdn = malloc(sizeof(double) * N);
+    if (!w->x || !w->y || !w->bup || !w->bdn) return -1;
+    for (int d = 0; d < g->ndims; d++) {
+        long M = walls(g, d);
+        w->V[d] = malloc(sizeof(double) * M);
+        w->W[d] = malloc(sizeof(double) * M);
+        w->cprev[d] = malloc(sizeof(double) * M);
+        if (!w->V[d] || !w->W[d] || !w->cprev[d]) return -1;
+    }
+    return 0;
+}
+
+static void work_free(work_t *w)
+{
+    free(w->x);
+    free(w->y);
+    free(w->bup);
+    free(w->bdn);
+    for (int d = 0; d < 3; d++) {
+        free(w->V[d]);
+        free(w->W[d]);
+        free(w->cprev[d]);
+    }
+}
+
+/* psi_out = one MPDATA step of psi_n: donor-cell pass with the advector c,
+ * then n_iters-1 corrective passes, each advecting the previous pass's result
+ * with the (optionally limited) pseudo-velocity computed from it; the
+ * pseudo-velocity of a pass is the advector of the next. */
+static void one_step(const grid_t *g, int n_iters, const double *psi_n,
+                     const double *G, double *const c[3], work_t *w,
+                     double *psi_out)
+{
+    long N = cells(g);
+    donor_pass(g, psi_n, c, G, 0, w->y);
+    for (int d = 0; d < g->ndims; d++)
+        memcpy(w->cprev[d], c[d], sizeof(double) * walls(g, d));
+    for (int it = 2; it <= n_iters; it++) {
+        memcpy(w->x, w->y, sizeof(double) * N);
+        antidiffusive_velocity(g, w->x, w->cprev, G, w->V);
+        double **adv = w->V;
+        if (g->fct) {
+            fct_limit(g, psi_n, w->x, G, w->V, w->W, w->bup, w->bdn);
+            adv = w->W;
+        }
+        donor_pass(g, w->x, adv, G, g->iga, w->y);
+        for (int d = 0; d < g->ndims; d++)
+            memcpy(w->cprev[d], adv[d], sizeof(double) * walls(g, d));
+    }
+    memcpy(psi_out, w->y, sizeof(double) * N);
+}
+
+static int make_grid(grid_t *g, int ndims, const long n[3], const int bc[3],
+                     unsigned opts)
+{
+    if (ndims < 1 || ndims > 3) return -1;
+    if (opts & ~(unsigned)(ORC_OPT_FCT | ORC_OPT_IGA | ORC_OPT_TOT)) return -1;
+    g->ndims = ndims;
+    for (int d = 0; d < 3; d++) {
+        g->n[d] = d < ndims ? n[d] : 1;
+        g->bc[d] = d < ndims ? bc[d] : ORC_BC_PERIODIC;
+        if (g->n[d] < 1) return -1;
+        if (g->bc[d] != ORC_BC_PERIODIC && g->bc[d] != ORC_BC_OPEN) return -1;
+    }
+    g->fct = (opts & ORC_OPT_FCT) != 0;
+    g->iga = (opts & ORC_OPT_IGA) != 0;
+    g->tot = (opts & ORC_OPT_TOT) != 0;
+    return 0;
+}
+
+int orc_step(int ndims, const long n[3], const int bc[3], int n_iters,
+             unsigned opts, double *psi, const double *g_,
+             const double *c0, const double *c1, const double *c2,
+             long n_steps)
+{
+    grid_t g;
+    if (make_grid(&g, ndims, n, bc, opts)) return -1;
+    if (n_iters < 1 || n_steps < 0 || !psi) return -1;
+    if (g.iga && n_iters > 2) return -1;
+    double *c[3] = {(double *)c0, (double *)c1, (double *)c2};
+    for (int d = 0; d < ndims; d++)
+        if (!c[d]) return -1;
+    work_t w;
+    if (work_alloc(&g, &w)) {
+        work_free(&w);
+        return -1;
+    }
+    double *tmp = malloc(sizeof(double) * cells(&g));
+    if (!tmp) {
+        work_free(&w);
+        return -1;
+    }
+    for (long s = 0; s < n_steps; s++) {
+        memcpy(tmp, psi, sizeof(double) * cells(&g));
+        one_step(&g, n_iters, tmp, g_, c, &w, psi);
+    }
+    free(tmp);
+    work_free(&w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+int orc_diag(int ndims, const long n[3], const double *psi, const double *G,
+             double out[3], long *n_nonfinite)
+{
+    if (ndims < 1 || ndims > 3 || !psi || !out || !n_nonfinite) return -1;
+    long N = 1;
+    for (int d = 0; d < ndims; d++) N *= n[d];
+    double s = 0.0, comp = 0.0;
+    double mn = INFINITY, mx = -INFINITY;
+    long bad = 0;
+    for (long k = 0; k < N; k++) {
+        double v = psi[k];
+        if (!isfinite(v)) {
+            bad++;
+            continue;
+        }
+        double term = G ? G[k] * v : v;
+        double t = s + term; /* Neumaier compensated summation */
+        if (fabs(s) >= fabs(term))
+            comp += (s - t) + term;
+        else
+            comp += (term - t) + s;
+        s = t;
+        if (v < mn) mn = v;
+        if (v > mx) mx = v;
+    }
+    out[0] = s + comp;
+    out[1] = mn;
+    out[2] = mx;
+    *n_nonfinite = bad;
+    return 0;
+}
+
+int orc_courant_max(int ndims, const long n[3], const int bc[3],
+                    const double *G, const double *c0, const double *c1,
+                    const double *c2, double *out)
+{
+    grid_t g;
+    if (make_grid(&g, ndims, n, bc, 0) || !out) return -1;
+    const double *c[3] = {c0, c1, c2};
+    for (int d = 0; d < ndims; d++)
+        if (!c[d]) return -1;
+    double best = 0.0;
+    long p[3];
+    for (p[0] = 0; p[0] < g.n[0]; p[0]++)
+        for (p[1] = 0; p[1] < g.n[1]; p[1]++)
+            for (p[2] = 0; p[2] < g.n[2]; p[2]++) {
+                double s = 0.0;
+                for (int d = 0; d < ndims; d++) {
+                    long lo[3], hi[3];
+                    sh(lo, p, d, 0);
+                    sh(hi, p, d, 1);
+                    double a = fabs(wat(&g, d, c[d], lo));
+                    double b = fabs(wat(&g, d, c[d], hi));
+                    s += a > b ? a : b;
+                }
+                s /= gat(&g, G, p);
+                if (s > best) best = s;
+            }
+    *out = best;
+    return 0;
+}
+
+/* The reverse-mode gradient lives in mpdata_oracle_adj.c. */

@@ -1,0 +1,535 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test names the property it checks and the passage it rests on.  None of
+them re-types the oracle's formulae: they use hand-derived worked examples,
+closed forms (upwind scheme, Fourier amplification factors), invariants of the
+method (conservation, sign preservation, constant-state preservation, exact
+shifts, boundedness, homogeneity, linearity of the infinite gauge, the gauge
+limit), symmetry, convergence orders, and an exact-rational second coding on
+tiny grids.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+from itertools import product
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1407_1309_amd import synth
+from tests.bruteforce import mpdata_exact
+
+FCT, IGA, TOT = oracle.OPT_FCT, oracle.OPT_IGA, oracle.OPT_TOT
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ALL_OPTS = [0, FCT, TOT, FCT | TOT, IGA, IGA | FCT, IGA | TOT, IGA | TOT | FCT]
+
+
+def _fr(s):
+    return float(Fraction(s))
+
+
+# ---------------------------------------------------------------- worked example
+def test_worked_example_1d():
+    """Hand-derived one-step values (eqs. upstream, F, adf_vel; Sects. 3.1.4-3.1.5)."""
+    gold = json.load(open(os.path.join(GOLDEN, "worked_1d.json")))
+    psi0 = np.array(gold["psi0"], dtype=float)
+    c = [np.full(5, 0.5)]
+    p1 = oracle.step(psi0, c, n_iters=1)
+    np.testing.assert_array_equal(p1, [_fr(s) for s in gold["psi1"]])
+    for key, opts in (("basic", 0), ("fct", FCT), ("iga", IGA)):
+        out = oracle.step(psi0, c, n_iters=2, opts=opts)
+        np.testing.assert_allclose(out, [_fr(s) for s in gold[key]["psi2"]], rtol=0, atol=4e-16)
+
+
+# ---------------------------------------------------------------- P1 upwind closed form
+@pytest.mark.parametrize("cour", [0.3, -0.7, 1.0])
+def test_donor_cell_is_upwind_1d(cour):
+    """n_iters=1 is the first-order upwind scheme (eq. upstream with eq. F)."""
+    gen = synth.rng(11)
+    psi = gen.uniform(0.1, 2.0, size=37)
+    out = oracle.step(psi, [np.full(38, cour)], n_iters=1)
+    if cour > 0:
+        ref = psi - cour * (psi - np.roll(psi, 1))
+    else:
+        ref = psi - cour * (np.roll(psi, -1) - psi)
+    np.testing.assert_allclose(out, ref, rtol=4e-16, atol=4e-16)
+
+
+def test_donor_cell_is_upwind_2d_variable_g():
+    """Donor pass with divergent, sign-varying walls and variable G equals the
+    upwind flux-form update computed with np.roll (periodic)."""
+    gen = synth.rng(12)
+    shape = (9, 7)
+    psi = gen.uniform(0.1, 2.0, size=shape)
+    g = gen.uniform(0.5, 2.0, size=shape)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.8, gen))
+    out = oracle.step(psi, c, g=g, n_iters=1)
+    tend = np.zeros(shape)
+    for d in range(2):
+        cd = np.take(c[d], range(shape[d]), axis=d)       # wall f (left wall of cell f)
+        left = np.roll(psi, 1, axis=d)
+        flux = np.maximum(cd, 0) * left + np.minimum(cd, 0) * psi
+        tend += np.roll(flux, -1, axis=d) - flux
+    np.testing.assert_allclose(out, psi - tend / g, rtol=1e-14, atol=1e-15)
+
+
+# ---------------------------------------------------------------- brute force (P14)
+def _to_frac_case(shape, bc, seed, with_g, sign):
+    gen = synth.rng(seed)
+    psi = gen.integers(1, 9, size=shape).astype(float)
+    if sign:
+        psi = psi - 5.0
+    psi = psi / 8.0
+    c = []
+    for d in range(len(shape)):
+        s = list(shape)
+        s[d] += 1
+        c.append(gen.integers(-3, 4, size=s).astype(float) / 16.0)
+    if bc == 0:
+        c = synth.periodic_fix(c)
+    g = gen.integers(2, 6, size=shape).astype(float) / 4.0 if with_g else None
+    return psi, c, g
+
+
+def _dict(a):
+    return {tuple(int(v) for v in idx): Fraction(float(a[idx])) for idx in np.ndindex(a.shape)}
+
+
+BF_CASES = [((8,), 0), ((8,), 1), ((5, 4), 0), ((5, 4), 1), ((4, 3, 3), 0), ((3, 4, 3), 1)]
+# exact rationals grow fast through the limiter's divisions: keep the number
+# of passes x steps small in 2-D / 3-D
+
+
+@pytest.mark.parametrize("shape,bc", BF_CASES)
+@pytest.mark.parametrize("opts", ALL_OPTS)
+def test_bruteforce_exact(shape, bc, opts):
+    """Oracle == exact-rational second coding, every option, 1/2/3-D, both BCs."""
+    iga = bool(opts & IGA)
+    n_iters = 2 if (iga or len(shape) == 3) else 3
+    with_g = len(shape) != 1 or bc == 1
+    psi, c, g = _to_frac_case(shape, bc, seed=hash((shape, bc, opts)) % 1000, with_g=with_g,
+                              sign=iga)
+    n_steps = 2 if len(shape) == 1 else 1
+    exact = mpdata_exact(_dict(psi), [_dict(x) for x in c], _dict(g) if g is not None else None,
+                         shape, bc, n_iters, bool(opts & FCT), iga, bool(opts & TOT), n_steps)
+    ref = np.zeros(shape)
+    for k, v in exact.items():
+        ref[k] = float(v)
+    out = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=n_steps)
+    scale = max(1.0, np.abs(ref).max())
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-13 * scale)
+
+
+# ---------------------------------------------------------------- P3 conservation
+@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("shape", [(64,), (24, 20), (10, 9, 8)])
+def test_conservation_periodic(opts, shape):
+    """Flux form conserves sum(G psi) to round-off (Sect. 1; eq. gte)."""
+    gen = synth.rng(21)
+    g = gen.uniform(0.5, 1.5, size=shape)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.5, gen))
+    psi = gen.uniform(0.0, 1.0, size=shape)
+    if opts & IGA:
+        psi -= 0.5
+    n_iters = 2 if opts & IGA else 3
+    out = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, n_steps=5)
+    s0, s1 = np.sum(g * psi), np.sum(g * out)
+    assert abs(s1 - s0) / np.sum(np.abs(g * psi)) <= 1e-13
+
+
+# ---------------------------------------------------------------- P4 sign preservation
+@pytest.mark.parametrize("opts", [0, FCT, TOT, FCT | TOT])
+@pytest.mark.parametrize("shape,cour", [((80,), 0.5), ((32, 28), 0.5), ((12, 10, 9), 0.5)])
+def test_sign_preserving(opts, shape, cour):
+    """Non-negative psi stays non-negative (Sect. 1 footnote; Sect. 3.1.4).
+    The advector is divergent; a Courant sum of 1/2 keeps every cell's total
+    outflow Courant number <= 1."""
+    gen = synth.rng(31)
+    c = synth.periodic_fix(synth.random_advector(shape, cour, gen))
+    psi = np.where(gen.uniform(size=shape) < 0.4, 0.0, gen.uniform(0, 1, size=shape))
+    out = oracle.step(psi, c, n_iters=3, opts=opts, n_steps=10)
+    assert out.min() >= -4 * np.finfo(float).eps * psi.max()
+
+
+# ---------------------------------------------------------------- P5 constant state
+@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("shape,bc", [((40,), 0), ((40,), 1), ((20, 18), 0), ((20, 18), 1),
+                                      ((10, 9, 8), 0), ((10, 9, 8), 1)])
+def test_constant_state_preserved(opts, shape, bc):
+    """psi = K with a non-divergent G-weighted advector stays K (eq. gte with
+    eq. gte_G): every difference in the pseudo-velocity vanishes."""
+    gen = synth.rng(41)
+    g = gen.uniform(0.5, 1.5, size=shape)
+    if len(shape) == 1:
+        c = [np.full(shape[0] + 1, 0.375)]
+    elif len(shape) == 2:
+        c = list(synth.stream_advector_2d(shape, 0.5, gen, n_modes=4, kmax=2))
+        c = [x * 0.5 for x in c]          # exact (power of two); keeps Courant/G <= 1
+    else:
+        c = list(synth.potential_advector_3d(shape, 0.5, gen, g=g, n_modes=3, kmax=2))
+    K = 0.7
+    psi = np.full(shape, K)
+    n_iters = 2 if opts & IGA else 3
+    out = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=4)
+    # K is not dyadic, so each flux product rounds: allow a few ulp per pass
+    np.testing.assert_allclose(out, K, rtol=32 * np.finfo(float).eps, atol=0)
+
+
+# ---------------------------------------------------------------- P6 exact shift
+@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("shape,axis,sgn", [((33,), 0, 1), ((33,), 0, -1), ((12, 11), 1, 1),
+                                           ((12, 11), 0, -1), ((6, 7, 8), 2, 1), ((6, 7, 8), 0, -1)])
+def test_unit_courant_shifts_one_cell(opts, shape, axis, sgn):
+    """|C| = 1 along one axis: every antidiffusive coefficient vanishes and the
+    step is an exact one-cell shift (eq. adf_vel at |GC| = G)."""
+    gen = synth.rng(51)
+    c = []
+    for d in range(len(shape)):
+        s = list(shape)
+        s[d] += 1
+        c.append(np.full(s, float(sgn) if d == axis else 0.0))
+    psi = gen.uniform(0.1, 1.0, size=shape)
+    if opts & IGA:
+        psi -= 0.5
+    n_iters = 2 if opts & IGA else 3
+    out = oracle.step(psi, c, n_iters=n_iters, opts=opts)
+    np.testing.assert_allclose(out, np.roll(psi, sgn, axis=axis), rtol=2 * np.finfo(float).eps,
+                               atol=2 * np.finfo(float).eps)
+
+
+# ---------------------------------------------------------------- P7 boundedness
+@pytest.mark.parametrize("opts", [FCT, FCT | TOT, FCT | IGA, FCT | IGA | TOT])
+@pytest.mark.parametrize("shape", [(120,), (40, 36), (14, 12, 10)])
+def test_fct_no_new_extrema(opts, shape):
+    """With the limiter (Sect. 3.1.4), and a non-divergent advector of Courant
+    sum <= 1, each new value lies within the range of the old values in the
+    domain of dependence (radius n_iters), and global extrema do not grow."""
+    gen = synth.rng(61)
+    c = synth.small_advector(shape, 0.5, gen) if len(shape) > 1 else [np.full(shape[0] + 1, 0.45)]
+    psi = np.where(gen.uniform(size=shape) < 0.5, 0.0, 1.0) + 0.1 * gen.uniform(size=shape)
+    if opts & IGA:
+        psi -= 0.6
+    n_iters = 2 if opts & IGA else 3
+    out = oracle.step(psi, c, n_iters=n_iters, opts=opts)
+    eps = 4 * np.finfo(float).eps * np.abs(psi).max()
+    hi = np.full(shape, -np.inf)
+    lo = np.full(shape, np.inf)
+    r = n_iters
+    for off in product(range(-r, r + 1), repeat=len(shape)):
+        if sum(abs(o) for o in off) > r:
+            continue
+        sh = np.roll(psi, off, axis=tuple(range(len(shape))))
+        hi, lo = np.maximum(hi, sh), np.minimum(lo, sh)
+    assert np.all(out <= hi + eps) and np.all(out >= lo - eps)
+    many = oracle.step(psi, c, n_iters=n_iters, opts=opts, n_steps=20)
+    assert many.max() <= psi.max() + eps and many.min() >= psi.min() - eps
+
+
+def test_fct_removes_overshoot_1d():
+    """The top-hat of the 1-D workload overshoots without the limiter and does
+    not with it (Sect. 3.1.4, Sect. 3.4 non-oscillatory option)."""
+    case = synth.case_1d(n_steps=100)
+    plain = oracle.step(case.psi, case.c, n_iters=2, n_steps=100)
+    lim = oracle.step(case.psi, case.c, n_iters=2, opts=FCT, n_steps=100)
+    assert plain.max() > case.psi.max() + 1e-3
+    assert lim.max() <= case.psi.max() + 1e-15 and lim.min() >= -1e-15
+
+
+# ---------------------------------------------------------------- P8 homogeneity
+@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("shape", [(50,), (16, 14), (8, 7, 6)])
+def test_power_of_two_homogeneity_bitwise(opts, shape):
+    """step(2^k psi) == 2^k step(psi) bit for bit: psi-fractions are ratios,
+    and no epsilon enters them."""
+    gen = synth.rng(71)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.6, gen))
+    psi = gen.uniform(0.0, 1.0, size=shape)
+    if opts & IGA:
+        psi -= 0.5
+    n_iters = 2 if opts & IGA else 3
+    a = oracle.step(psi, c, n_iters=n_iters, opts=opts, n_steps=3)
+    b = oracle.step(psi * 2.0 ** 7, c, n_iters=n_iters, opts=opts, n_steps=3)
+    np.testing.assert_array_equal(b, a * 2.0 ** 7)
+
+
+# ---------------------------------------------------------------- P9 linear infinite gauge
+@pytest.mark.parametrize("opts", [IGA, IGA | TOT])
+@pytest.mark.parametrize("shape", [(64,), (20, 18), (9, 8, 7)])
+def test_iga_is_linear(opts, shape):
+    """Without the limiter the infinite-gauge scheme is linear (Sect. 3.1.5)."""
+    gen = synth.rng(81)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.6, gen))
+    p, q = gen.normal(size=shape), gen.normal(size=shape)
+    a, b = 1.7, -0.3
+    lhs = oracle.step(a * p + b * q, c, n_iters=2, opts=opts, n_steps=2)
+    rhs = a * oracle.step(p, c, n_iters=2, opts=opts, n_steps=2) + \
+        b * oracle.step(q, c, n_iters=2, opts=opts, n_steps=2)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("opts", [IGA, IGA | TOT, IGA | FCT, IGA | FCT | TOT])
+def test_iga_background_independent(opts):
+    """Ripples of the infinite-gauge option do not depend on the constant
+    background (Sect. 3.4 variable-sign example); with the limiter too."""
+    gen = synth.rng(82)
+    shape = (30, 26)
+    c = synth.small_advector(shape, 0.5, gen)
+    psi = np.where(gen.uniform(size=shape) < 0.5, -1.0, 1.0)
+    K = 3.0
+    a = oracle.step(psi, c, n_iters=2, opts=opts, n_steps=5)
+    b = oracle.step(psi + K, c, n_iters=2, opts=opts, n_steps=5)
+    np.testing.assert_allclose(b - K, a, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- P10 gauge limit
+@pytest.mark.parametrize("tot", [0, TOT])
+@pytest.mark.parametrize("shape", [(48,), (16, 14), (8, 8, 6)])
+def test_gauge_limit(tot, shape):
+    """[step(psi + K) - K] of the standard scheme tends to the infinite-gauge
+    step with an error ~ 1/K (the gauge is the limit of infinite background)."""
+    gen = synth.rng(91)
+    # non-divergent, so a constant background is itself a steady solution
+    c = synth.small_advector(shape, 0.5, gen)
+    psi = gen.normal(size=shape)
+    ref = oracle.step(psi, c, n_iters=2, opts=IGA | tot)
+    errs = []
+    for K in (2.0 ** 12, 2.0 ** 14, 2.0 ** 16):
+        out = oracle.step(psi + K, c, n_iters=2, opts=tot) - K
+        errs.append(np.abs(out - ref).max())
+    assert errs[0] < 1e-2
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.0 < e0 / e1 < 5.5        # one factor 4 in K -> error / 4
+
+
+# ---------------------------------------------------------------- P11 Fourier
+def _amplification(shape, cvec, theta_idx, opts):
+    """Numerical amplification factor of one step on the Fourier mode with
+    integer wavenumber vector theta_idx (constant advector, G = 1)."""
+    nd = len(shape)
+    c = []
+    for d in range(nd):
+        s = list(shape)
+        s[d] += 1
+        c.append(np.full(s, cvec[d]))
+    grids = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    phase = sum(2 * math.pi * k * x / n for k, x, n in zip(theta_idx, grids, shape))
+    oc = oracle.step(np.cos(phase), c, n_iters=2, opts=opts)
+    os_ = oracle.step(np.sin(phase), c, n_iters=2, opts=opts)
+    g = (oc + 1j * os_) / np.exp(1j * phase)
+    return g.mean(), np.abs(g - g.mean()).max()
+
+
+def test_fourier_closed_form_1d():
+    """Infinite-gauge step on a Fourier mode, 1-D: the composition of the donor
+    factor and the corrective-flux factor (linear scheme, constant c)."""
+    for U in (0.3, -0.6):
+        for tot in (0, TOT):
+            n, k = 64, 5
+            th = 2 * math.pi * k / n
+            gnum, spread = _amplification((n,), [U], [k], IGA | tot)
+            assert spread < 1e-13
+            e = np.exp(1j * th)
+            if U >= 0:
+                g1 = 1 - U * (1 - 1 / e)
+            else:
+                g1 = 1 - U * (e - 1)
+            alpha = (3 * U * abs(U) - 2 * U ** 3 - U) / 3 if tot else 0.0
+            corr = (abs(U) - U * U) * (e - 1) / 2 + alpha * (e * e - e - 1 + 1 / e) / 4
+            gcf = g1 * (1 - (1 - 1 / e) * corr)
+            assert abs(gnum - gcf) < 1e-14
+
+
+@pytest.mark.parametrize("cvec", [(0.3,), (-0.55,), (0.3, 0.2), (-0.25, 0.35), (0.2, -0.15, 0.25),
+                                  (-0.3, -0.2, 0.1)])
+@pytest.mark.parametrize("tot", [0, TOT])
+def test_fourier_order_conditions(cvec, tot):
+    """Local error of one step on a mode is O(theta^3) (second order, Sect.
+    3.1.1) and O(theta^4) with the third-order terms (Sect. 3.1.2) for the
+    infinite-gauge scheme; checked by halving the wavenumber."""
+    nd = len(cvec)
+    n = 256 if nd == 1 else (128 if nd == 2 else 32)
+    shape = (n,) * nd
+    dirs = [(1,), (1, 1), (1, 1, 1)][nd - 1], [(1,), (1, -1), (1, -1, 1)][nd - 1]
+    want = 4.0 if tot else 3.0
+    for dvec in dirs:
+        errs = []
+        for m in (4, 2, 1):
+            kk = [m * v for v in dvec]
+            g, _ = _amplification(shape, cvec, kk, IGA | tot)
+            th = [2 * math.pi * k / n for k in kk]
+            exact = np.exp(-1j * sum(c * t for c, t in zip(cvec, th)))
+            errs.append(abs(g - exact))
+        orders = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+        assert orders[-1] > want - 0.25, (dvec, errs, orders)
+
+
+# ---------------------------------------------------------------- P12 convergence
+def _cell_gauss(x_lo, x_hi, x0, sigma):
+    from scipy.special import erf
+    s = sigma * math.sqrt(2.0)
+    return 0.5 * (erf((x_hi - x0) / s) - erf((x_lo - x0) / s)) / (x_hi - x_lo)
+
+
+def _conv_error(k, C, n_iters, opts):
+    """Truncation error (eq. trerr) of the 1-D convergence test (Sect. 3.5):
+    X = 44, T = 1, u = 1, sigma = 1.5, x0 = X/2, cell-integrated profiles,
+    periodic; NT = round(T / dt) and the exact solution at NT dt."""
+    X, sigma = 44.0, 1.5
+    dx = 2.0 ** -k
+    nx = int(round(X / dx))
+    dt = C * dx
+    nt = int(round(1.0 / dt))
+    t = nt * dt
+    edges = np.arange(nx + 1) * dx
+    psi0 = _cell_gauss(edges[:-1], edges[1:], X / 2, sigma)
+    ex = _cell_gauss(edges[:-1], edges[1:], X / 2 + t, sigma)
+    out = oracle.step(psi0, [np.full(nx + 1, C)], n_iters=n_iters, opts=opts, n_steps=nt)
+    return math.sqrt(np.mean((ex - out) ** 2)) / 1.0
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("label,n_iters,opts,lo,hi", [
+    ("donor", 1, 0, 0.8, 1.2),
+    ("basic", 2, 0, 1.8, 2.3),
+    ("three-pass", 3, 0, 1.8, 2.6),
+    ("tot three-pass", 3, TOT, 2.7, 3.4),
+    ("fct", 2, FCT, 1.5, 2.2),
+    ("iga", 2, IGA, 1.8, 2.3),
+    ("iga tot", 2, IGA | TOT, 2.7, 3.4),
+])
+@pytest.mark.parametrize("C", [0.25, 0.75])
+def test_convergence_orders(label, n_iters, opts, lo, hi, C):
+    """Orders of the convergence test of Sect. 3.5: donor-cell 1, MPDATA 2,
+    third-order variant 3, limiter about 1.8, infinite gauge 2 (3 with tot)."""
+    e5 = _conv_error(5, C, n_iters, opts)
+    e6 = _conv_error(6, C, n_iters, opts)
+    order = math.log2(e5 / e6)
+    assert lo < order < hi, (label, C, e5, e6, order)
+
+
+def test_iga_as_accurate_as_three_pass():
+    """Sect. 3.5: the infinite gauge is about as accurate as three-pass MPDATA."""
+    e_iga = _conv_error(5, 0.5 - 0.25, 2, IGA)
+    e_3 = _conv_error(5, 0.25, 3, 0)
+    e_2 = _conv_error(5, 0.25, 2, 0)
+    assert e_iga < e_2 and 0.3 < e_iga / e_3 < 3.0
+
+
+def test_variable_g_second_order():
+    """1-D, G = 1 + 0.3 sin(2 pi x / X), constant G-weighted advector: the
+    exact solution moves the mass coordinate m(x) = int G dx uniformly, and the
+    scheme (with the mean G at walls) converges at second order."""
+    X, a = 32.0, 0.3
+
+    def m_of(x):
+        return x + a * X / (2 * math.pi) * (1 - np.cos(2 * math.pi * x / X))
+
+    def x_of(m):
+        x = m.copy()
+        for _ in range(60):
+            x = x - (m_of(x) - m) / (1 + a * np.sin(2 * math.pi * x / X))
+        return x
+
+    def prof(x):
+        d = (x - X / 2 + X / 2) % X - X / 2
+        return np.exp(-d * d / (2 * 2.0 ** 2))
+
+    errs = []
+    for k in (4, 5, 6):
+        dx = 2.0 ** -k
+        nx = int(X / dx)
+        x = (np.arange(nx) + 0.5) * dx
+        g = 1 + a * np.sin(2 * math.pi * x / X)
+        Q = 0.4                      # G-weighted Courant number per step
+        nt = int(round(4.0 / (Q * dx)))
+        psi = oracle.step(prof(x), [np.full(nx + 1, Q)], g=g, n_iters=2, n_steps=nt)
+        shift = nt * Q * dx
+        ex = prof(x_of((m_of(x) - shift) % X))
+        errs.append(math.sqrt(np.mean((psi - ex) ** 2)))
+    orders = [math.log2(e0 / e1) for e0, e1 in zip(errs, errs[1:])]
+    assert 1.8 < orders[-1] < 2.3, (errs, orders)
+
+
+# ---------------------------------------------------------------- P13 symmetry
+@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("shape", [(30,), (12, 10), (7, 6, 5)])
+def test_translation_equivariance_bitwise(opts, shape):
+    gen = synth.rng(101)
+    g = gen.uniform(0.5, 1.5, size=shape)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.5, gen))
+    psi = gen.uniform(0.0, 1.0, size=shape) - (0.5 if opts & IGA else 0.0)
+    n_iters = 2 if opts & IGA else 3
+    shift = tuple(range(1, len(shape) + 1))
+    axes = tuple(range(len(shape)))
+    a = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, n_steps=2)
+
+    def roll_wall(x, d):
+        core = np.take(x, range(shape[d]), axis=d)
+        core = np.roll(core, shift, axis=axes)
+        first = np.take(core, [0], axis=d)
+        return np.concatenate([core, first], axis=d)
+
+    b = oracle.step(np.roll(psi, shift, axis=axes), [roll_wall(x, d) for d, x in enumerate(c)],
+                    g=np.roll(g, shift, axis=axes), n_iters=n_iters, opts=opts, n_steps=2)
+    np.testing.assert_array_equal(b, np.roll(a, shift, axis=axes))
+
+
+@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("shape,bc", [((30,), 1), ((12, 10), 0), ((12, 10), 1), ((7, 6, 5), 1)])
+def test_mirror_symmetry(opts, shape, bc):
+    """Reflecting the grid along an axis (and negating that velocity
+    component) reflects the result (Arakawa-C staggering, Sect. 2.3)."""
+    gen = synth.rng(111)
+    g = gen.uniform(0.5, 1.5, size=shape)
+    c = synth.random_advector(shape, 0.5, gen)
+    if bc == 0:
+        c = synth.periodic_fix(c)
+    psi = gen.uniform(0.0, 1.0, size=shape) - (0.5 if opts & IGA else 0.0)
+    n_iters = 2 if opts & IGA else 3
+    a = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=2)
+    for ax in range(len(shape)):
+        cm = [np.flip(x, axis=ax) * (-1.0 if d == ax else 1.0) for d, x in enumerate(c)]
+        b = oracle.step(np.flip(psi, axis=ax), cm, g=np.flip(g, axis=ax), n_iters=n_iters,
+                        opts=opts, bc=bc, n_steps=2)
+        np.testing.assert_allclose(np.flip(b, axis=ax), a, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("opts", ALL_OPTS)
+def test_transpose_symmetry(opts):
+    """Swapping the two axes of a 2-D problem swaps the result."""
+    gen = synth.rng(121)
+    shape = (11, 9)
+    g = gen.uniform(0.5, 1.5, size=shape)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.5, gen))
+    psi = gen.uniform(0.0, 1.0, size=shape) - (0.5 if opts & IGA else 0.0)
+    n_iters = 2 if opts & IGA else 3
+    a = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, n_steps=2)
+    b = oracle.step(psi.T.copy(), [c[1].T.copy(), c[0].T.copy()], g=g.T.copy(), n_iters=n_iters,
+                    opts=opts, n_steps=2)
+    np.testing.assert_allclose(b.T, a, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- workload sanity
+def test_1d_workload_one_period():
+    """1000 steps at C = 0.5 move the 1-D workload once round the 500-cell ring;
+    MPDATA keeps it close to the initial field (accuracy report, not parity)."""
+    case = synth.case_1d()
+    out = oracle.step(case.psi, case.c, n_iters=2, n_steps=1000)
+    err = math.sqrt(np.mean((out - case.psi) ** 2))
+    donor = oracle.step(case.psi, case.c, n_iters=1, n_steps=1000)
+    err_d = math.sqrt(np.mean((donor - case.psi) ** 2))
+    assert err < 0.6 * err_d
+
+
+def test_diag_and_courant():
+    psi = np.array([[1.0, -2.0], [np.nan, 4.0]])
+    g = np.array([[2.0, 1.0], [1.0, 0.5]])
+    s, mn, mx, bad = oracle.diag(psi, g)
+    assert (s, mn, mx, bad) == (2.0, -2.0, 4.0, 1)
+    c0 = np.array([[0.1, 0.2], [0.3, -0.4], [0.1, 0.2]])
+    c1 = np.array([[0.05, 0.0, 0.05], [-0.25, 0.1, -0.25]])
+    cm = oracle.courant_max((2, 2), [c0, c1], g=g)
+    # cell (1,1): max(0.4, 0.2) + max(0.1, 0.25) = 0.65, / 0.5
+    assert abs(cm - 1.3) < 1e-15
