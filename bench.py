@@ -1,0 +1,178 @@
+"""Benchmark of the MPDATA step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Default workload: 2-D periodic 2048x2048, FP64, n_iters=3 with the limiter
+(stream-function advector of Courant sum 0.5, 64 non-negative blobs).  Inputs
+are resident in HBM before the timed region; K steps are timed with HIP
+events on the stream the kernels run on, bracketed by device syncs.  One JSON
+line is printed: Mcell-steps/s, the roofline of the dominant kernel, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Other workloads (--workload): 2d-f32, 3d, 1d, batched, adjoint.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="2d",
+                    choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "staged", "fused"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
+    return ap.parse_args()
+
+
+def _traffic_entry(kernel_name, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, used
+    only while the kernel source still has the hash recorded with it."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data.get(f"{kernel_name}:{workload}")
+        if not ent:
+            return None
+        from paper_1407_1309_amd.build import source_hash
+        if ent.get("source_hash") != source_hash():
+            return None
+        return ent.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def _time_steps(run, steps, torch):
+    """Time `run(steps)` with HIP events on the current stream."""
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3      # seconds
+
+
+def bench_single(args, torch, mpdata, synth, oracle):
+    f32 = args.workload in ("2d-f32",)
+    if args.workload in ("2d", "2d-f32"):
+        case = synth.case_2d()
+        name = "2d_periodic_2048x2048_fct_iters3"
+    elif args.workload == "3d":
+        case = synth.case_3d()
+        name = "3d_open_384x384x256_tot_iga_iters2_gz"
+    else:
+        case = synth.case_1d()
+        name = "1d_periodic_500_iters2"
+    dtype = torch.float32 if f32 else torch.float64
+    es = 4 if f32 else 8
+    K = args.steps if args.steps is not None else case.n_steps
+    W = args.warmup
+    kernel = {"auto": mpdata.KERNEL_AUTO, "staged": mpdata.KERNEL_STAGED,
+              "fused": mpdata.KERNEL_FUSED}[args.kernel]
+    dev = torch.device("cuda:0")
+    plan = mpdata.Plan(case.psi.shape, dtype=dtype, n_iters=case.n_iters, opts=case.opts,
+                       bc=case.bc, has_g=case.g is not None, device=dev, kernel=kernel)
+    psi0 = torch.from_numpy(case.psi).to(dev, dtype)
+    c = [torch.from_numpy(x).to(dev, dtype).contiguous() for x in case.c]
+    g = torch.from_numpy(case.g).to(dev, dtype) if case.g is not None else None
+    N = int(np.prod(case.psi.shape))
+
+    # parity of the first two steps of this very configuration vs the oracle
+    chk = psi0.clone()
+    plan.step(chk, c, g=g, n_steps=2)
+    torch.cuda.synchronize()
+
+    psi = psi0.clone()
+    plan.step(psi, c, g=g, n_steps=W)
+    secs = _time_steps(lambda k: plan.step(psi, c, g=g, n_steps=k), K, torch)
+    ms = secs * 1e3 / max(K, 1)
+    value = N * K / secs / 1e6
+
+    # algorithmic bytes per step: read psi, every advector component, G; write psi
+    walls = 0
+    for d in range(len(case.psi.shape)):
+        s = list(case.psi.shape)
+        if case.bc == 1:
+            s[d] += 1                    # open: both edge walls are data
+        walls += int(np.prod(s))
+    alg_bytes = es * (2 * N + walls + (N if case.g is not None else 0))
+    achieved = alg_bytes / (ms / 1e3) / 1e9
+    fused = plan_uses_fused(plan, mpdata, kernel)
+    kname = "mpdata_fused2d" if fused else "mpdata_staged_step"
+    traffic = _traffic_entry(kname, name + ("_f32" if f32 else "_f64"))
+
+    out = {
+        "metric": "Mcell-steps/s", "value": round(value, 3), "unit": "Mcell-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if f32 else "f64", "data": "synthetic (seeded)",
+        "config": {"workload": name, "shape": list(case.psi.shape), "n_iters": case.n_iters,
+                   "opts": case.opts, "bc": "open" if case.bc else "periodic",
+                   "kernel": "fused" if fused else "staged", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
+                     "kernel": kname},
+    }
+    if not args.no_cpu:
+        psi_o = case.psi.astype(np.float32).astype(np.float64) if f32 else case.psi
+        c_o = [x.astype(np.float32).astype(np.float64) for x in case.c] if f32 else case.c
+        g_o = case.g
+        t0 = time.perf_counter()
+        ref = oracle.step(psi_o, c_o, g=g_o, n_iters=case.n_iters, opts=case.opts, bc=case.bc,
+                          n_steps=2)
+        dt = time.perf_counter() - t0
+        got = chk.double().cpu().numpy()
+        rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["cpu_baseline"] = {"value": round(N * 2 / dt / 1e6, 4), "unit": "Mcell-steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"2 steps of the full {name} grid, FP64, one thread"}
+        out["parity_rel_l2_vs_oracle_2steps"] = rel
+    return out
+
+
+def plan_uses_fused(plan, mpdata, requested):
+    """Which step kernel the plan runs for the requested selection."""
+    if requested == mpdata.KERNEL_STAGED:
+        return False
+    ok = mpdata.lib().mpdata_set_kernel(plan._handle, mpdata.KERNEL_FUSED) == 0
+    plan.set_kernel(requested)
+    return ok
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the MPDATA step "
+              "here is a single-GPU build and has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import oracle
+    from paper_1407_1309_amd import mpdata, synth
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    out = bench_single(args, torch, mpdata, synth, oracle)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * mpdata.h -- C ABI of libmpdata, the MI355X (gfx950) MPDATA time step.
+ *
+ * The step solves the homogeneous generalised transport equation in the form
+ *     d(psi)/dt + (1/G) div(G u psi) = 0              (paper eq. gte_final)
+ * with G constant in time, on the staggered Arakawa-C grid of Sect. 2.3:
+ * psi and G live at cell centres, the advector (G-weighted Courant number
+ * GC = G u dt/dx, Sect. 3.1.1) lives on the cell walls.
+ *
+ * One step is a donor-cell pass (eqs. upstream and F) followed by n_iters-1
+ * corrective passes that advect the previous pass's result with the
+ * antidiffusive pseudo-velocity (eq. adf_vel and its multi-dimensional
+ * form), optionally with the third-order terms (Sect. 3.1.2), the infinite-
+ * gauge variant (Sect. 3.1.5) and the non-oscillatory limiter (Sect. 3.1.4).
+ * Summation is the "straightforward" one of Sect. 3.1.1.
+ *
+ * Memory and ownership
+ *   - Every array argument is a DEVICE pointer to C-contiguous (row-major,
+ *     last dimension fastest, Sect. 3.2) data of the plan's dtype, owned by
+ *     the caller.  The library never allocates device memory: scratch space
+ *     comes from the caller's workspace (mpdata_workspace_bytes).
+ *   - psi and G have the plan's shape (n0[, n1[, n2]]).
+ *   - Advector component c_d has the plan's shape with n_d + 1 entries along
+ *     dimension d; entry f is the wall between cells f-1 and f.  With
+ *     periodic boundaries wall n_d is the same wall as wall 0 and is never
+ *     read; with open boundaries walls 0 and n_d are the domain edges.
+ *   - g == NULL means G == 1.
+ *
+ * Boundaries (Sect. 2.2): periodic wraps every array; open gives every cell
+ * array a zero-gradient halo and every wall array copies its edge wall.
+ *
+ * Execution and errors
+ *   - Calls enqueue work on the plan's HIP stream and return without
+ *     waiting, except mpdata_diag, mpdata_courant_max and mpdata_adv_adj,
+ *     which wait for their results.
+ *   - Every call returns MPDATA_OK or a negative status; nothing throws.
+ *     mpdata_last_error() gives the message of the calling thread's last
+ *     failure.  A device fault surfaces at the next synchronising call.
+ *   - A plan is not thread-safe; calls on one plan must be serialised.
+ */
+#ifndef MPDATA_H
+#define MPDATA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mpdata_status {
+    MPDATA_OK = 0,
+    MPDATA_EINVAL = -1,       /* bad argument (null pointer, shape, flag)   */
+    MPDATA_EWORKSPACE = -2,   /* workspace missing, too small or unaligned  */
+    MPDATA_EHIP = -3,         /* a HIP runtime call or launch failed        */
+    MPDATA_ENONFINITE = -4,   /* mpdata_diag found NaN or Inf values        */
+    MPDATA_EUNSUPPORTED = -6  /* valid but not provided (see mpdata_init)   */
+};
+
+/* option bits (Sect. 3.4) */
+enum {
+    MPDATA_OPT_FCT = 1u << 0, /* non-oscillatory limiter, Sect. 3.1.4       */
+    MPDATA_OPT_IGA = 1u << 1, /* infinite gauge, Sect. 3.1.5                */
+    MPDATA_OPT_TOT = 1u << 2  /* third-order terms, Sect. 3.1.2             */
+};
+
+enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 };
+enum { MPDATA_F32 = 0, MPDATA_F64 = 1 };
+
+/* kernel selection for mpdata_set_kernel */
+enum {
+    MPDATA_KERNEL_AUTO = 0,    /* fused kernel where one exists, else staged */
+    MPDATA_KERNEL_STAGED = 1,  /* one launch per stage (cross-check path)    */
+    MPDATA_KERNEL_FUSED = 2    /* all passes of a step in one launch         */
+};
+
+typedef struct mpdata_desc {
+    int n_dims;           /* 1, 2 or 3                                       */
+    int64_t shape[3];     /* cells per dimension; entries >= n_dims ignored  */
+    int dtype;            /* MPDATA_F32 or MPDATA_F64                         */
+    int n_iters;          /* passes per step incl. the donor pass, 1..8      */
+    uint32_t opts;        /* MPDATA_OPT_* bits                               */
+    int bc[3];            /* MPDATA_BC_* per dimension                       */
+    int has_g;            /* nonzero if steps will pass a G array            */
+} mpdata_desc;
+
+typedef struct mpdata_plan mpdata_plan; /* opaque host object */
+
+/* Bytes of device workspace a plan for *desc needs (0 on invalid desc). */
+size_t mpdata_workspace_bytes(const mpdata_desc *desc);
+
+/* Validate *desc and create a plan bound to `workspace` (device memory of at
+ * least mpdata_workspace_bytes(desc) bytes, 256-byte aligned, owned by the
+ * caller and kept alive until mpdata_destroy) and `hip_stream` (a
+ * hipStream_t; NULL = the default stream).
+ * Rejects: n_dims outside 1..3, a shape < 1 (< 3 along a periodic dimension),
+ * n_iters outside 1..8, unknown option bits, bc or dtype values
+ * (MPDATA_EINVAL); the infinite gauge with n_iters > 2 (MPDATA_EUNSUPPORTED:
+ * its pseudo-velocity is a flux, not a Courant number, so it cannot drive a
+ * third pass). */
+int mpdata_init(const mpdata_desc *desc, void *workspace, size_t ws_bytes,
+                void *hip_stream, mpdata_plan **out);
+
+/* Re-bind the plan to another HIP stream (NULL = the default stream). */
+int mpdata_set_stream(mpdata_plan *plan, void *hip_stream);
+
+/* Choose the step kernel (MPDATA_KERNEL_*).  FUSED returns
+ * MPDATA_EUNSUPPORTED when no fused kernel covers the plan. */
+int mpdata_set_kernel(mpdata_plan *plan, int kernel);
+
+/* Advance psi (in place) by n_steps steps (n_steps >= 0) with the advector
+ * c0..c2 held fixed over the call (the caller passes the advector at the
+ * intermediate time level n+1/2, Sect. 3.1.1).  c_d must be non-NULL for
+ * d < n_dims and NULL otherwise; g must be non-NULL iff the plan has_g.
+ * Successive calls continue the integration exactly (resumable like the
+ * paper's advance()). */
+int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0,
+                const void *c1, const void *c2, int n_steps);
+
+/* Diagnostics of psi (waits for the result): out[0] = sum of G*psi over the
+ * finite cells (FP64, compensated), out[1] = min, out[2] = max of the finite
+ * values, *n_nonfinite = number of NaN/Inf cells.  Returns MPDATA_ENONFINITE
+ * (after filling the outputs) when *n_nonfinite > 0.  g may be NULL. */
+int mpdata_diag(mpdata_plan *plan, const void *psi, const void *g,
+                double out_sum_min_max[3], int64_t *n_nonfinite);
+
+/* max over cells of sum_d max(|c_d| on the two d-walls of the cell) / G
+ * (waits for the result).  A value above 1 means the donor-cell pass can
+ * empty a cell, so sign preservation (Sect. 1) is no longer guaranteed. */
+int mpdata_courant_max(mpdata_plan *plan, const void *g, const void *c0,
+                       const void *c1, const void *c2, double *out);
+
+/* Gradient of a scalar J(psi_T), psi_T = n_steps steps from psi0, with
+ * respect to psi0 and the advector (reverse mode of the full nonlinear step:
+ * pseudo-velocity, cross/third-order terms and limiter included; G is held
+ * constant).  lambda_T = dJ/dpsi_T.  grad_psi0 and grad_c0..grad_c2
+ * (NULL for d >= n_dims) are overwritten.  The forward trajectory is kept
+ * only every ckpt_every steps (1 <= ckpt_every <= n_steps) and recomputed in
+ * between; memory for the checkpoints comes from the plan's workspace, sized
+ * by mpdata_adj_workspace_bytes.  Waits for completion.  Periodic walls:
+ * the gradient of the shared wall 0 / wall n_d is returned in entry 0, and
+ * entry n_d is zero.
+ * Derivatives at non-differentiable points: d[u]+/du = 1 only for u > 0,
+ * d[u]-/du = 1 only for u < 0; a max/min passes its derivative to the first
+ * argument attaining it in the order the method lists its arguments; the
+ * zero-denominator and no-flux branches of the fractions and limiter
+ * coefficients have zero derivative. */
+int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g,
+                   const void *c0, const void *c1, const void *c2,
+                   int n_steps, int ckpt_every, const void *lambda_T,
+                   void *grad_psi0, void *grad_c0, void *grad_c1,
+                   void *grad_c2);
+
+/* Workspace bytes mpdata_adv_adj needs for n_steps / ckpt_every (0 on bad
+ * arguments); a plan meant for the adjoint must be created with at least
+ * this much workspace. */
+size_t mpdata_adj_workspace_bytes(const mpdata_desc *desc, int n_steps,
+                                  int ckpt_every);
+
+/* ---------------------------------------------------------------------- */
+/* Batched step: many independent 2-D grids (ensemble members, tracers)    */
+/* advanced together, one launch per step over every tile of every grid.   */
+/* ---------------------------------------------------------------------- */
+
+/* shapes[2*i], shapes[2*i+1] = (n0, n1) of grid i.  Grids are packed one
+ * after another in three device buffers: psi (sum n0*n1 values), c0 (sum
+ * (n0+1)*n1) and c1 (sum n0*(n1+1)), each grid C-contiguous, in order.
+ * Every grid shares dtype, n_iters, opts and one boundary type for both
+ * dimensions.  The workspace must hold mpdata_batched_workspace_bytes. */
+size_t mpdata_batched_workspace_bytes(int n_grids, const int64_t *shapes,
+                                      int dtype, int n_iters, uint32_t opts,
+                                      int bc);
+int mpdata_batched_init(int n_grids, const int64_t *shapes, int dtype,
+                        int n_iters, uint32_t opts, int bc, void *workspace,
+                        size_t ws_bytes, void *hip_stream, mpdata_plan **out);
+
+/* Advance every grid by n_steps steps (in place).  With use_graph != 0 the
+ * n_steps launches are captured once into a HIP graph per (buffers,
+ * n_steps) and replayed; otherwise they are launched directly. */
+int mpdata_step_batched(mpdata_plan *plan, void *psi_packed,
+                        const void *c0_packed, const void *c1_packed,
+                        int n_steps, int use_graph);
+
+/* Same update, one ordinary launch sequence per grid (the baseline the
+ * batched launch is measured against). */
+int mpdata_step_per_grid(mpdata_plan *plan, void *psi_packed,
+                         const void *c0_packed, const void *c1_packed,
+                         int n_steps);
+
+void mpdata_destroy(mpdata_plan *plan);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *mpdata_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

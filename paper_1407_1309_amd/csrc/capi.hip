@@ -1,0 +1,649 @@
+// capi.hip -- the extern "C" boundary of libmpdata (declared in mpdata.h).
+//
+// Host-side validation, workspace carving, the step loop (ping-pong between
+// the caller's psi and a workspace buffer), kernel selection and the
+// synchronous diagnostics.  No exception crosses the boundary; failures set a
+// thread-local message and return a negative status.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mpdata.h"
+#include "adjoint.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(MPDATA_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Bump allocator over the caller's workspace (offsets only; no allocation).
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    void *take(size_t bytes)
+    {
+        void *p = base ? base + used : nullptr;
+        used += align_up(bytes);
+        return p;
+    }
+};
+
+int64_t cells_of(const mp::Geom &g) { return g.n[0] * g.n[1] * g.n[2]; }
+
+int64_t walls_of(const mp::Geom &g, int d)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    return e[0] * e[1] * e[2];
+}
+
+size_t dsize(int dtype) { return dtype == MPDATA_F64 ? 8 : 4; }
+
+int check_desc(const mpdata_desc *d, mp::Geom *g)
+{
+    if (!d) return fail(MPDATA_EINVAL, "desc is NULL");
+    if (d->n_dims < 1 || d->n_dims > 3) return fail(MPDATA_EINVAL, "n_dims %d not in 1..3", d->n_dims);
+    if (d->dtype != MPDATA_F32 && d->dtype != MPDATA_F64)
+        return fail(MPDATA_EINVAL, "unknown dtype %d", d->dtype);
+    if (d->n_iters < 1 || d->n_iters > 8)
+        return fail(MPDATA_EINVAL, "n_iters %d not in 1..8", d->n_iters);
+    if (d->opts & ~(uint32_t)(MPDATA_OPT_FCT | MPDATA_OPT_IGA | MPDATA_OPT_TOT))
+        return fail(MPDATA_EINVAL, "unknown option bits 0x%x", d->opts);
+    g->nd = d->n_dims;
+    for (int k = 0; k < 3; k++) {
+        if (k < d->n_dims) {
+            if (d->bc[k] != MPDATA_BC_PERIODIC && d->bc[k] != MPDATA_BC_OPEN)
+                return fail(MPDATA_EINVAL, "unknown bc %d in dimension %d", d->bc[k], k);
+            int64_t lo = d->bc[k] == MPDATA_BC_PERIODIC ? 3 : 1;
+            if (d->shape[k] < lo)
+                return fail(MPDATA_EINVAL, "shape[%d] = %lld below %lld", k,
+                            (long long)d->shape[k], (long long)lo);
+            if (d->shape[k] > (int64_t)1 << 31)
+                return fail(MPDATA_EINVAL, "shape[%d] too large", k);
+            g->n[k] = d->shape[k];
+            g->bc[k] = d->bc[k];
+        } else {
+            g->n[k] = 1;
+            g->bc[k] = MPDATA_BC_PERIODIC;
+        }
+    }
+    if (cells_of(*g) > ((int64_t)1 << 40)) return fail(MPDATA_EINVAL, "grid too large");
+    if ((d->opts & MPDATA_OPT_IGA) && d->n_iters > 2)
+        return fail(MPDATA_EUNSUPPORTED,
+                    "the infinite gauge is defined for n_iters <= 2 (got %d)", d->n_iters);
+    return MPDATA_OK;
+}
+
+// Workspace layout of a single-grid plan.
+struct Layout {
+    void *psi_alt;
+    void *tmp[2];
+    void *faces[2][3];
+    void *bup, *bdn;
+    double *part;   // diag partials (5 per block)
+    double *out;    // diag result (4) + courant result (1)
+    size_t bytes;
+};
+
+Layout carve(const mp::Geom &g, int dtype, void *base)
+{
+    Layout L;
+    memset(&L, 0, sizeof L);
+    Carver c(base);
+    size_t es = dsize(dtype);
+    int64_t N = cells_of(g);
+    L.part = (double *)c.take(sizeof(double) * 5 * mp::diag_max_blocks());
+    L.out = (double *)c.take(sizeof(double) * 8);
+    L.psi_alt = c.take(es * N);
+    L.tmp[0] = c.take(es * N);
+    L.tmp[1] = c.take(es * N);
+    for (int s = 0; s < 2; s++)
+        for (int d = 0; d < g.nd; d++) L.faces[s][d] = c.take(es * walls_of(g, d));
+    L.bup = c.take(es * N);
+    L.bdn = c.take(es * N);
+    L.bytes = c.used;
+    return L;
+}
+
+}  // namespace
+
+struct mpdata_plan {
+    mpdata_desc desc;
+    mp::Geom g;
+    void *ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    int kernel;
+    Layout L;
+    // batched plans
+    bool batched = false;
+    std::vector<mp::BatchGrid> grids;
+    mp::BatchGrid *grids_dev = nullptr;
+    void *batch_alt = nullptr;
+    int64_t batch_psi_total = 0, batch_c0_total = 0, batch_c1_total = 0;
+    int batch_tiles = 0;
+    // graph cache (batched)
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void *g_key[3] = {nullptr, nullptr, nullptr};
+    int g_steps = -1;
+};
+
+namespace {
+
+template <typename T>
+int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0, const T *c1,
+             const T *c2, bool fused)
+{
+    hipError_t e;
+    if (fused) {
+        mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1]};
+        e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, G,
+                                p->stream);
+    } else {
+        mp::StagedArgs<T> a;
+        a.g = p->g;
+        a.n_iters = p->desc.n_iters;
+        a.opts = p->desc.opts;
+        a.psi_n = psi_n;
+        a.psi_out = psi_out;
+        a.c[0] = c0;
+        a.c[1] = c1;
+        a.c[2] = c2;
+        a.G = G;
+        a.tmp[0] = (T *)p->L.tmp[0];
+        a.tmp[1] = (T *)p->L.tmp[1];
+        for (int s = 0; s < 2; s++)
+            for (int d = 0; d < 3; d++) a.faces[s][d] = (T *)p->L.faces[s][d];
+        a.bup = (T *)p->L.bup;
+        a.bdn = (T *)p->L.bdn;
+        e = mp::staged_step<T>(a, p->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return MPDATA_OK;
+}
+
+bool use_fused(const mpdata_plan *p)
+{
+    bool ok = mp::fused2d_supported(p->desc.n_dims, p->desc.n_iters, p->desc.opts,
+                                    p->desc.dtype == MPDATA_F64);
+    if (p->kernel == MPDATA_KERNEL_STAGED) return false;
+    return ok;
+}
+
+template <typename T>
+int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, const T *c2,
+              int n_steps)
+{
+    if (n_steps == 0) return MPDATA_OK;
+    bool fused = use_fused(p);
+    int64_t N = cells_of(p->g);
+    T *alt = (T *)p->L.psi_alt;
+    T *cur = psi, *nxt = alt;
+    if (n_steps & 1) {
+        hipError_t e = hipMemcpyAsync(alt, psi, sizeof(T) * N, hipMemcpyDeviceToDevice, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        cur = alt;
+        nxt = psi;
+    }
+    for (int s = 0; s < n_steps; s++) {
+        int rc = one_step<T>(p, cur, nxt, G, c0, c1, c2, fused);
+        if (rc) return rc;
+        T *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    return MPDATA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpdata_last_error(void) { return g_err.c_str(); }
+
+size_t mpdata_workspace_bytes(const mpdata_desc *desc)
+{
+    mp::Geom g;
+    if (check_desc(desc, &g) != MPDATA_OK) return 0;
+    return carve(g, desc->dtype, nullptr).bytes;
+}
+
+int mpdata_init(const mpdata_desc *desc, void *workspace, size_t ws_bytes, void *hip_stream,
+                mpdata_plan **out)
+{
+    if (!out) return fail(MPDATA_EINVAL, "out is NULL");
+    *out = nullptr;
+    mp::Geom g;
+    int rc = check_desc(desc, &g);
+    if (rc) return rc;
+    size_t need = carve(g, desc->dtype, nullptr).bytes;
+    if (!workspace) return fail(MPDATA_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+    if ((uintptr_t)workspace % ALIGN) return fail(MPDATA_EWORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(MPDATA_EWORKSPACE, "workspace has %zu bytes, need %zu", ws_bytes, need);
+    mpdata_plan *p = new (std::nothrow) mpdata_plan();
+    if (!p) return fail(MPDATA_EINVAL, "out of host memory");
+    p->desc = *desc;
+    p->g = g;
+    p->ws = workspace;
+    p->ws_bytes = ws_bytes;
+    p->stream = (hipStream_t)hip_stream;
+    p->kernel = MPDATA_KERNEL_AUTO;
+    p->L = carve(g, desc->dtype, workspace);
+    *out = p;
+    return MPDATA_OK;
+}
+
+int mpdata_set_kernel(mpdata_plan *plan, int kernel)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (kernel < MPDATA_KERNEL_AUTO || kernel > MPDATA_KERNEL_FUSED)
+        return fail(MPDATA_EINVAL, "unknown kernel %d", kernel);
+    if (kernel == MPDATA_KERNEL_FUSED &&
+        !mp::fused2d_supported(plan->desc.n_dims, plan->desc.n_iters, plan->desc.opts,
+                               plan->desc.dtype == MPDATA_F64))
+        return fail(MPDATA_EUNSUPPORTED, "no fused kernel for this plan");
+    plan->kernel = kernel;
+    return MPDATA_OK;
+}
+
+int mpdata_set_stream(mpdata_plan *plan, void *hip_stream)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    plan->stream = (hipStream_t)hip_stream;
+    return MPDATA_OK;
+}
+
+int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0, const void *c1,
+                const void *c2, int n_steps)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (plan->batched) return fail(MPDATA_EINVAL, "batched plan: use mpdata_step_batched");
+    if (!psi) return fail(MPDATA_EINVAL, "psi is NULL");
+    if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
+    const void *c[3] = {c0, c1, c2};
+    for (int d = 0; d < 3; d++) {
+        if (d < plan->desc.n_dims && !c[d]) return fail(MPDATA_EINVAL, "c%d is NULL", d);
+        if (d >= plan->desc.n_dims && c[d])
+            return fail(MPDATA_EINVAL, "c%d given for a %d-D plan", d, plan->desc.n_dims);
+    }
+    if ((g != nullptr) != (plan->desc.has_g != 0))
+        return fail(MPDATA_EINVAL, plan->desc.has_g ? "plan has_g but g is NULL"
+                                                    : "g given but plan was made without has_g");
+    if (plan->desc.dtype == MPDATA_F64)
+        return run_steps<double>(plan, (double *)psi, (const double *)g, (const double *)c0,
+                                 (const double *)c1, (const double *)c2, n_steps);
+    return run_steps<float>(plan, (float *)psi, (const float *)g, (const float *)c0,
+                            (const float *)c1, (const float *)c2, n_steps);
+}
+
+int mpdata_diag(mpdata_plan *plan, const void *psi, const void *g, double out[3],
+                int64_t *n_nonfinite)
+{
+    if (!plan || !psi || !out || !n_nonfinite) return fail(MPDATA_EINVAL, "NULL argument");
+    if (plan->batched) return fail(MPDATA_EINVAL, "diag needs a single-grid plan");
+    int64_t N = cells_of(plan->g);
+    hipError_t e;
+    if (plan->desc.dtype == MPDATA_F64)
+        e = mp::diag_launch<double>((const double *)psi, (const double *)g, N, plan->L.part,
+                                    plan->L.out, plan->stream);
+    else
+        e = mp::diag_launch<float>((const float *)psi, (const float *)g, N, plan->L.part,
+                                   plan->L.out, plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "diag launch");
+    double h[4];
+    e = hipMemcpyAsync(h, plan->L.out, sizeof h, hipMemcpyDeviceToHost, plan->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "diag copy");
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+    *n_nonfinite = (int64_t)h[3];
+    if (*n_nonfinite > 0)
+        return fail(MPDATA_ENONFINITE, "%lld non-finite values", (long long)*n_nonfinite);
+    return MPDATA_OK;
+}
+
+int mpdata_courant_max(mpdata_plan *plan, const void *g, const void *c0, const void *c1,
+                       const void *c2, double *out)
+{
+    if (!plan || !out) return fail(MPDATA_EINVAL, "NULL argument");
+    if (plan->batched) return fail(MPDATA_EINVAL, "courant check needs a single-grid plan");
+    const void *c[3] = {c0, c1, c2};
+    for (int d = 0; d < plan->desc.n_dims; d++)
+        if (!c[d]) return fail(MPDATA_EINVAL, "c%d is NULL", d);
+    hipError_t e;
+    if (plan->desc.dtype == MPDATA_F64)
+        e = mp::courant_launch<double>(plan->g, (const double *)c0, (const double *)c1,
+                                       (const double *)c2, (const double *)g, plan->L.part,
+                                       plan->L.out + 4, plan->stream);
+    else
+        e = mp::courant_launch<float>(plan->g, (const float *)c0, (const float *)c1,
+                                      (const float *)c2, (const float *)g, plan->L.part,
+                                      plan->L.out + 4, plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "courant launch");
+    double h;
+    e = hipMemcpyAsync(&h, plan->L.out + 4, sizeof h, hipMemcpyDeviceToHost, plan->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "courant copy");
+    *out = h;
+    return MPDATA_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+size_t mpdata_adj_workspace_bytes(const mpdata_desc *desc, int n_steps, int ckpt_every)
+{
+    mp::Geom g;
+    if (check_desc(desc, &g) != MPDATA_OK) return 0;
+    if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps) return 0;
+    size_t base = carve(g, desc->dtype, nullptr).bytes;
+    return base + mp::adj_extra_bytes(g, desc->dtype == MPDATA_F64 ? 8 : 4, desc->n_iters,
+                                      n_steps, ckpt_every);
+}
+
+int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const void *c0,
+                   const void *c1, const void *c2, int n_steps, int ckpt_every,
+                   const void *lambda_T, void *grad_psi0, void *grad_c0, void *grad_c1,
+                   void *grad_c2)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (plan->batched) return fail(MPDATA_EINVAL, "adjoint needs a single-grid plan");
+    if (!psi0 || !lambda_T || !grad_psi0) return fail(MPDATA_EINVAL, "NULL argument");
+    if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps)
+        return fail(MPDATA_EINVAL, "need 1 <= ckpt_every <= n_steps (got %d, %d)", ckpt_every,
+                    n_steps);
+    const void *c[3] = {c0, c1, c2};
+    void *gc[3] = {grad_c0, grad_c1, grad_c2};
+    for (int d = 0; d < 3; d++) {
+        bool want = d < plan->desc.n_dims;
+        if (want && (!c[d] || !gc[d])) return fail(MPDATA_EINVAL, "c%d / grad_c%d is NULL", d, d);
+        if (!want && (c[d] || gc[d])) return fail(MPDATA_EINVAL, "c%d given for a %d-D plan", d,
+                                                  plan->desc.n_dims);
+    }
+    if ((g != nullptr) != (plan->desc.has_g != 0)) return fail(MPDATA_EINVAL, "g / has_g mismatch");
+    size_t need = mpdata_adj_workspace_bytes(&plan->desc, n_steps, ckpt_every);
+    if (plan->ws_bytes < need)
+        return fail(MPDATA_EWORKSPACE, "adjoint needs %zu workspace bytes, plan has %zu", need,
+                    plan->ws_bytes);
+    char *extra = (char *)plan->ws + plan->L.bytes;
+    hipError_t e;
+    if (plan->desc.dtype == MPDATA_F64) {
+        mp::AdjArgs<double> a;
+        mp::adj_fill_args<double>(a, plan->g, plan->desc.n_iters, plan->desc.opts,
+                                  (const double *)psi0, (const double *)g,
+                                  (const double *const *)c, n_steps, ckpt_every,
+                                  (const double *)lambda_T, (double *)grad_psi0, (double **)gc,
+                                  extra);
+        e = mp::adjoint_run<double>(a, plan->stream);
+    } else {
+        mp::AdjArgs<float> a;
+        mp::adj_fill_args<float>(a, plan->g, plan->desc.n_iters, plan->desc.opts,
+                                 (const float *)psi0, (const float *)g, (const float *const *)c,
+                                 n_steps, ckpt_every, (const float *)lambda_T,
+                                 (float *)grad_psi0, (float **)gc, extra);
+        e = mp::adjoint_run<float>(a, plan->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint");
+    return MPDATA_OK;
+}
+
+// ------------------------------------------------------------------ batched
+size_t mpdata_batched_workspace_bytes(int n_grids, const int64_t *shapes, int dtype, int n_iters,
+                                      uint32_t opts, int bc)
+{
+    (void)n_iters;
+    (void)opts;
+    (void)bc;
+    if (n_grids < 1 || !shapes || (dtype != MPDATA_F32 && dtype != MPDATA_F64)) return 0;
+    int64_t tot = 0;
+    for (int i = 0; i < n_grids; i++) {
+        if (shapes[2 * i] < 3 || shapes[2 * i + 1] < 3) return 0;
+        tot += shapes[2 * i] * shapes[2 * i + 1];
+    }
+    return align_up(sizeof(mp::BatchGrid) * (size_t)n_grids) + align_up(dsize(dtype) * tot);
+}
+
+int mpdata_batched_init(int n_grids, const int64_t *shapes, int dtype, int n_iters, uint32_t opts,
+                        int bc, void *workspace, size_t ws_bytes, void *hip_stream,
+                        mpdata_plan **out)
+{
+    if (!out) return fail(MPDATA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_grids < 1 || !shapes) return fail(MPDATA_EINVAL, "need n_grids >= 1 and shapes");
+    mpdata_desc d;
+    memset(&d, 0, sizeof d);
+    d.n_dims = 2;
+    d.dtype = dtype;
+    d.n_iters = n_iters;
+    d.opts = opts;
+    d.bc[0] = d.bc[1] = bc;
+    mp::Geom g;
+    for (int i = 0; i < n_grids; i++) {
+        d.shape[0] = shapes[2 * i];
+        d.shape[1] = shapes[2 * i + 1];
+        int rc = check_desc(&d, &g);
+        if (rc) return fail(rc, "grid %d: %s", i, g_err.c_str());
+    }
+    if (!mp::fused2d_supported(2, n_iters, opts, dtype == MPDATA_F64))
+        return fail(MPDATA_EUNSUPPORTED, "no batched kernel for these options");
+    size_t need = mpdata_batched_workspace_bytes(n_grids, shapes, dtype, n_iters, opts, bc);
+    if (!workspace || ws_bytes < need || (uintptr_t)workspace % ALIGN)
+        return fail(MPDATA_EWORKSPACE, "batched workspace: need %zu aligned bytes", need);
+    mpdata_plan *p = new (std::nothrow) mpdata_plan();
+    if (!p) return fail(MPDATA_EINVAL, "out of host memory");
+    p->desc = d;
+    p->batched = true;
+    p->ws = workspace;
+    p->ws_bytes = ws_bytes;
+    p->stream = (hipStream_t)hip_stream;
+    p->kernel = MPDATA_KERNEL_FUSED;
+    memset(&p->L, 0, sizeof p->L);
+    int tr = mp::fused2d_tile_rows(), tc = mp::fused2d_tile_cols();
+    p->grids.resize(n_grids);
+    int64_t op = 0, o0 = 0, o1 = 0;
+    int64_t tiles = 0;
+    for (int i = 0; i < n_grids; i++) {
+        mp::BatchGrid &G = p->grids[i];
+        G.n0 = shapes[2 * i];
+        G.n1 = shapes[2 * i + 1];
+        G.off_psi = op;
+        G.off_c0 = o0;
+        G.off_c1 = o1;
+        G.tiles_w = (int)mp::cdiv(G.n1, tc);
+        G.tile_begin = (int)tiles;
+        tiles += (int64_t)G.tiles_w * mp::cdiv(G.n0, tr);
+        op += G.n0 * G.n1;
+        o0 += (G.n0 + 1) * G.n1;
+        o1 += G.n0 * (G.n1 + 1);
+    }
+    if (tiles > (int64_t)1 << 30) {
+        delete p;
+        return fail(MPDATA_EINVAL, "too many tiles");
+    }
+    p->batch_tiles = (int)tiles;
+    p->batch_psi_total = op;
+    p->batch_c0_total = o0;
+    p->batch_c1_total = o1;
+    Carver c(workspace);
+    p->grids_dev = (mp::BatchGrid *)c.take(sizeof(mp::BatchGrid) * n_grids);
+    p->batch_alt = c.take(dsize(dtype) * op);
+    hipError_t e = hipMemcpyAsync(p->grids_dev, p->grids.data(), sizeof(mp::BatchGrid) * n_grids,
+                                  hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "batched table upload");
+    }
+    *out = p;
+    return MPDATA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+hipError_t batched_launches(mpdata_plan *p, T *psi, const T *c0, const T *c1, int n_steps)
+{
+    T *alt = (T *)p->batch_alt;
+    T *cur = psi, *nxt = alt;
+    hipError_t e = hipSuccess;
+    if (n_steps & 1) {
+        e = hipMemcpyAsync(alt, psi, sizeof(T) * p->batch_psi_total, hipMemcpyDeviceToDevice,
+                           p->stream);
+        if (e != hipSuccess) return e;
+        cur = alt;
+        nxt = psi;
+    }
+    for (int s = 0; s < n_steps; s++) {
+        e = mp::fused2d_batched_step<T>(p->grids_dev, (int)p->grids.size(), p->batch_tiles,
+                                        p->desc.bc[0], p->desc.n_iters, p->desc.opts, cur, nxt,
+                                        c0, c1, p->stream);
+        if (e != hipSuccess) return e;
+        T *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t per_grid_launches(mpdata_plan *p, T *psi, const T *c0, const T *c1, int n_steps)
+{
+    T *alt = (T *)p->batch_alt;
+    hipError_t e = hipSuccess;
+    for (const mp::BatchGrid &G : p->grids) {
+        T *gp = psi + G.off_psi, *ga = alt + G.off_psi;
+        const T *g0 = c0 + G.off_c0, *g1 = c1 + G.off_c1;
+        T *cur = gp, *nxt = ga;
+        if (n_steps & 1) {
+            e = hipMemcpyAsync(ga, gp, sizeof(T) * G.n0 * G.n1, hipMemcpyDeviceToDevice, p->stream);
+            if (e != hipSuccess) return e;
+            cur = ga;
+            nxt = gp;
+        }
+        mp::Fused2DShape sh{G.n0, G.n1, p->desc.bc[0], p->desc.bc[1]};
+        for (int s = 0; s < n_steps; s++) {
+            e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, cur, nxt, g0, g1, nullptr,
+                                    p->stream);
+            if (e != hipSuccess) return e;
+            T *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpdata_step_batched(mpdata_plan *plan, void *psi, const void *c0, const void *c1,
+                        int n_steps, int use_graph)
+{
+    if (!plan || !plan->batched) return fail(MPDATA_EINVAL, "not a batched plan");
+    if (!psi || !c0 || !c1) return fail(MPDATA_EINVAL, "NULL buffer");
+    if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
+    if (n_steps == 0) return MPDATA_OK;
+    bool f64 = plan->desc.dtype == MPDATA_F64;
+    auto launch = [&]() -> hipError_t {
+        return f64 ? batched_launches<double>(plan, (double *)psi, (const double *)c0,
+                                              (const double *)c1, n_steps)
+                   : batched_launches<float>(plan, (float *)psi, (const float *)c0,
+                                             (const float *)c1, n_steps);
+    };
+    if (!use_graph) {
+        hipError_t e = launch();
+        return e == hipSuccess ? MPDATA_OK : hip_fail(e, "batched launch");
+    }
+    bool hit = plan->gexec && plan->g_key[0] == psi && plan->g_key[1] == c0 &&
+               plan->g_key[2] == c1 && plan->g_steps == n_steps;
+    if (!hit) {
+        if (plan->gexec) {
+            (void)hipGraphExecDestroy(plan->gexec);
+            plan->gexec = nullptr;
+        }
+        if (plan->graph) {
+            (void)hipGraphDestroy(plan->graph);
+            plan->graph = nullptr;
+        }
+        hipError_t e = hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = launch();
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(plan->stream, &gr);
+        if (le != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return hip_fail(le, "batched launch under capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&plan->gexec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        plan->graph = gr;
+        plan->g_key[0] = psi;
+        plan->g_key[1] = c0;
+        plan->g_key[2] = c1;
+        plan->g_steps = n_steps;
+    }
+    hipError_t e = hipGraphLaunch(plan->gexec, plan->stream);
+    return e == hipSuccess ? MPDATA_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int mpdata_step_per_grid(mpdata_plan *plan, void *psi, const void *c0, const void *c1,
+                         int n_steps)
+{
+    if (!plan || !plan->batched) return fail(MPDATA_EINVAL, "not a batched plan");
+    if (!psi || !c0 || !c1) return fail(MPDATA_EINVAL, "NULL buffer");
+    if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
+    if (n_steps == 0) return MPDATA_OK;
+    hipError_t e = plan->desc.dtype == MPDATA_F64
+                       ? per_grid_launches<double>(plan, (double *)psi, (const double *)c0,
+                                                   (const double *)c1, n_steps)
+                       : per_grid_launches<float>(plan, (float *)psi, (const float *)c0,
+                                                  (const float *)c1, n_steps);
+    return e == hipSuccess ? MPDATA_OK : hip_fail(e, "per-grid launch");
+}
+
+void mpdata_destroy(mpdata_plan *plan)
+{
+    if (!plan) return;
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+}
+
+}  // extern "C"

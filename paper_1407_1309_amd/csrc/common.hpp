@@ -1,0 +1,47 @@
+// common.hpp -- grid geometry, boundary map and small helpers shared by the
+// libmpdata kernels (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mp {
+
+enum { BC_PERIODIC = 0, BC_OPEN = 1 };
+enum { OPT_FCT = 1u, OPT_IGA = 2u, OPT_TOT = 4u };
+
+// Grid extents padded with 1 beyond n_dims; boundary type per dimension.
+struct Geom {
+    int nd;
+    int64_t n[3];
+    int bc[3];
+};
+
+// Boundary map (Sect. 2.2): periodic wraps, open clamps.  Cells live in
+// [0, n), walls of the dimension's own advector component in [0, n]; with
+// periodic boundaries wall n is wall 0.
+__host__ __device__ inline int64_t map_cell(int64_t q, int64_t n, int bc)
+{
+    if (bc == BC_PERIODIC) {
+        q %= n;
+        return q < 0 ? q + n : q;
+    }
+    return q < 0 ? 0 : (q >= n ? n - 1 : q);
+}
+
+__host__ __device__ inline int64_t map_wall(int64_t f, int64_t n, int bc)
+{
+    if (bc == BC_PERIODIC) {
+        f %= n;
+        return f < 0 ? f + n : f;
+    }
+    return f < 0 ? 0 : (f > n ? n : f);
+}
+
+template <typename T> __device__ inline T pos(T u) { return u > T(0) ? u : T(0); }
+template <typename T> __device__ inline T neg(T u) { return u < T(0) ? u : T(0); }
+
+// Round-up integer division.
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace mp

@@ -1,0 +1,70 @@
+// kernels.hpp -- internal launcher interfaces between the C ABI (capi.hip)
+// and the kernel translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace mp {
+
+// Arguments of one step through the staged (one launch per stage) path.
+template <typename T> struct StagedArgs {
+    Geom g;
+    int n_iters;
+    unsigned opts;
+    const T *psi_n;     // step input (read by every pass under the limiter)
+    T *psi_out;         // step output, distinct from psi_n
+    const T *c[3];      // advector components (NULL beyond nd)
+    const T *G;         // NULL: G == 1
+    T *tmp[2];          // pass results, cell arrays
+    T *faces[2][3];     // two sets of wall arrays
+    T *bup, *bdn;       // limiter coefficients, cell arrays
+};
+
+template <typename T> hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s);
+
+// Diagnostics: per-block partials into `part` (4 doubles per block, at most
+// diag_max_blocks blocks), then one finalising block writing out[0..3] =
+// (sum G psi, min, max, non-finite count as double).
+int diag_max_blocks();
+template <typename T>
+hipError_t diag_launch(const T *psi, const T *G, int64_t N, double *part, double *out,
+                       hipStream_t s);
+
+// out[0] = max over cells of sum_d max(|c_d| lo, |c_d| hi) / G.
+template <typename T>
+hipError_t courant_launch(const Geom &g, const T *c0, const T *c1, const T *c2, const T *G,
+                          double *part, double *out, hipStream_t s);
+
+// ---- fused 2-D kernel (all passes of a step in one launch) ---------------
+struct Fused2DShape {
+    int64_t n0, n1;      // rows (slow), columns (fast)
+    int bc0, bc1;
+};
+
+// true if a fused kernel exists for this configuration
+bool fused2d_supported(int nd, int n_iters, unsigned opts, int dtype_is_f64);
+
+template <typename T>
+hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
+                        T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s);
+
+// ---- batched fused 2-D: one launch over all tiles of all grids ---------
+struct BatchGrid {
+    int64_t n0, n1;
+    int64_t off_psi, off_c0, off_c1;   // element offsets into packed buffers
+    int tile_begin;                    // first tile of this grid in the work list
+    int tiles_w;                       // tiles along columns
+};
+
+template <typename T>
+hipError_t fused2d_batched_step(const BatchGrid *grids_dev, int n_grids, int n_tiles, int bc,
+                                int n_iters, unsigned opts, const T *psi_n, T *psi_out,
+                                const T *c0, const T *c1, hipStream_t s);
+
+int fused2d_tile_rows();
+int fused2d_tile_cols();
+
+}  // namespace mp

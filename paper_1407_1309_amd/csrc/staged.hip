@@ -1,0 +1,268 @@
+// staged.hip -- the MPDATA step as one kernel launch per stage.
+//
+// Every stage is a plain gather: one thread per output cell or wall, every
+// input read through the boundary map.  Intermediate fields (pass results,
+// pseudo-velocities, limiter coefficients) round-trip through the caller's
+// workspace.  This is the general path (1-3 D, every option, both boundary
+// types, FP32/FP64) and the cross-check for the fused kernels.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mp {
+namespace {
+
+struct Idx3 {
+    int64_t v[3];
+};
+
+__device__ inline Idx3 unflat(int64_t t, const int64_t e[3])
+{
+    Idx3 p;
+    p.v[2] = t % e[2];
+    t /= e[2];
+    p.v[1] = t % e[1];
+    p.v[0] = t / e[1];
+    return p;
+}
+
+__device__ inline Idx3 shifted(Idx3 p, int d, int64_t s)
+{
+    p.v[d] += s;
+    return p;
+}
+
+template <typename T>
+__device__ inline T cell(const Geom &g, const T *a, const Idx3 &p)
+{
+    int64_t i = map_cell(p.v[0], g.n[0], g.bc[0]);
+    int64_t j = map_cell(p.v[1], g.n[1], g.bc[1]);
+    int64_t k = map_cell(p.v[2], g.n[2], g.bc[2]);
+    return a[(i * g.n[1] + j) * g.n[2] + k];
+}
+
+template <typename T>
+__device__ inline T gcell(const Geom &g, const T *G, const Idx3 &p)
+{
+    return G ? cell(g, G, p) : T(1);
+}
+
+// wall value of the dimension-d advector component at p (p.v[d] = wall)
+template <typename T>
+__device__ inline T wall(const Geom &g, int d, const T *a, const Idx3 &p)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    int64_t q[3];
+    for (int t = 0; t < 3; t++)
+        q[t] = (t == d) ? map_wall(p.v[t], g.n[t], g.bc[t])
+                        : map_cell(p.v[t], g.n[t], g.bc[t]);
+    return a[(q[0] * e[1] + q[1]) * e[2] + q[2]];
+}
+
+template <typename T>
+__device__ inline T frac(bool iga, T num, T den, T m)
+{
+    if (iga) return num / m;
+    return den == T(0) ? T(0) : num / den;
+}
+
+// donor-cell pass (eqs. upstream, F); with flux_is_vel the wall flux is the
+// advector itself (infinite-gauge corrective pass)
+template <typename T>
+__global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
+                        const T *c2, const T *G, int flux_is_vel, T *__restrict__ out)
+{
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    Idx3 p = unflat(t, g.n);
+    const T *c[3] = {c0, c1, c2};
+    T acc = T(0);
+    for (int d = 0; d < g.nd; d++) {
+        T fl[2];
+        for (int s = 0; s < 2; s++) {
+            Idx3 w = shifted(p, d, s);
+            T u = wall(g, d, c[d], w);
+            if (flux_is_vel)
+                fl[s] = u;
+            else
+                fl[s] = pos(u) * cell(g, x, shifted(w, d, -1)) + neg(u) * cell(g, x, w);
+        }
+        acc += fl[1] - fl[0];
+    }
+    T r = G ? acc / G[t] : acc;
+    out[t] = x[t] - r;
+}
+
+// antidiffusive pseudo-velocity at every dimension-d wall (eq. adf_vel, its
+// cross terms and the third-order terms)
+template <typename T>
+__global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, const T *c0,
+                         const T *c1, const T *c2, const T *G, T *__restrict__ V)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    int64_t M = e[0] * e[1] * e[2];
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M) return;
+    const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
+    const T *c[3] = {c0, c1, c2};
+    Idx3 p = unflat(t, e);
+    Idx3 L = shifted(p, d, -1), R = p;
+    T u = wall(g, d, c[d], p);
+    T Gb = T(0.5) * (gcell(g, G, L) + gcell(g, G, R));
+    T xL = cell(g, x, L), xR = cell(g, x, R);
+    T V_ = (fabs(u) - u * u / Gb) * frac(iga, xR - xL, xR + xL, T(2));
+
+    T cb[3] = {T(0), T(0), T(0)};
+    for (int o = 0; o < g.nd; o++) {
+        if (o == d) continue;
+        cb[o] = T(0.25) * (wall(g, o, c[o], L) + wall(g, o, c[o], shifted(L, o, 1)) +
+                           wall(g, o, c[o], R) + wall(g, o, c[o], shifted(R, o, 1)));
+        T a = cell(g, x, shifted(R, o, 1)), b = cell(g, x, shifted(L, o, 1));
+        T e_ = cell(g, x, shifted(R, o, -1)), f = cell(g, x, shifted(L, o, -1));
+        V_ -= T(0.5) * u * cb[o] / Gb * frac(iga, a + b - e_ - f, a + b + e_ + f, T(4));
+    }
+    if (tot) {
+        T xR2 = cell(g, x, shifted(R, d, 1)), xL2 = cell(g, x, shifted(L, d, -1));
+        T D = frac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
+        V_ += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) * D;
+        for (int o = 0; o < g.nd; o++) {
+            if (o == d) continue;
+            T a = cell(g, x, shifted(R, o, 1)), b = cell(g, x, shifted(L, o, 1));
+            T e_ = cell(g, x, shifted(R, o, -1)), f = cell(g, x, shifted(L, o, -1));
+            T E = frac(iga, a - b - e_ + f, a + b + e_ + f, T(4));
+            V_ += (fabs(u) * cb[o] / Gb - T(2) * u * u * cb[o] / (Gb * Gb)) * E;
+        }
+        if (g.nd == 3) {
+            int o1 = (d == 0) ? 1 : 0;
+            int o2 = (d == 2) ? 1 : 2;
+            T num = T(0), den = T(0);
+            for (int s = 0; s < 2; s++) {
+                Idx3 S = s ? R : L;
+                T vpp = cell(g, x, shifted(shifted(S, o1, 1), o2, 1));
+                T vmp = cell(g, x, shifted(shifted(S, o1, -1), o2, 1));
+                T vpm = cell(g, x, shifted(shifted(S, o1, 1), o2, -1));
+                T vmm = cell(g, x, shifted(shifted(S, o1, -1), o2, -1));
+                num += vpp - vmp - vpm + vmm;
+                den += vpp + vmp + vpm + vmm;
+            }
+            V_ += -(T(2) / T(3)) * u * cb[o1] * cb[o2] / (Gb * Gb) * frac(iga, num, den, T(8));
+        }
+    }
+    V[t] = V_;
+}
+
+// limiter coefficients per cell (Sect. 3.1.4)
+template <typename T>
+__global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
+                           const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
+                           const T *G, T *__restrict__ bup, T *__restrict__ bdn)
+{
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const bool iga = opts & OPT_IGA;
+    const T *V[3] = {V0, V1, V2};
+    Idx3 p = unflat(t, g.n);
+    T xi = x[t];
+    T mx = psi_n[t], mn = mx;
+    mx = fmax(mx, xi);
+    mn = fmin(mn, xi);
+    for (int d = 0; d < g.nd; d++)
+        for (int s = -1; s <= 1; s += 2) {
+            Idx3 q = shifted(p, d, s);
+            T a = cell(g, psi_n, q), b = cell(g, x, q);
+            mx = fmax(fmax(mx, a), b);
+            mn = fmin(fmin(mn, a), b);
+        }
+    T fin = T(0), fout = T(0);
+    for (int d = 0; d < g.nd; d++) {
+        T vlo = wall(g, d, V[d], p), vhi = wall(g, d, V[d], shifted(p, d, 1));
+        T wm = iga ? T(1) : cell(g, x, shifted(p, d, -1));
+        T wp = iga ? T(1) : cell(g, x, shifted(p, d, 1));
+        T wi = iga ? T(1) : xi;
+        fin += pos(vlo) * wm - neg(vhi) * wp;
+        fout += pos(vhi) * wi - neg(vlo) * wi;
+    }
+    T Gi = G ? G[t] : T(1);
+    bup[t] = fin > T(0) ? Gi * (mx - xi) / fin : T(1);
+    bdn[t] = fout > T(0) ? Gi * (xi - mn) / fout : T(1);
+}
+
+// limited pseudo-velocity at every dimension-d wall
+template <typename T>
+__global__ void k_fct_limit(Geom g, int d, const T *__restrict__ V, const T *__restrict__ bup,
+                            const T *__restrict__ bdn, T *__restrict__ W)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    int64_t M = e[0] * e[1] * e[2];
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M) return;
+    Idx3 p = unflat(t, e);
+    Idx3 L = shifted(p, d, -1), R = p;
+    T v = V[t];
+    T up = fmin(fmin(T(1), cell(g, bdn, L)), cell(g, bup, R));
+    T dn = fmin(fmin(T(1), cell(g, bup, L)), cell(g, bdn, R));
+    W[t] = pos(v) * up + neg(v) * dn;
+}
+
+template <typename T>
+int64_t wall_count(const Geom &g, int d)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    return e[0] * e[1] * e[2];
+}
+
+}  // namespace
+
+// One full step psi_n -> psi_out through the staged kernels.
+template <typename T>
+hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s)
+{
+    const Geom &g = a.g;
+    const int B = 256;
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    unsigned cblocks = (unsigned)cdiv(N, B);
+    const bool fct = a.opts & OPT_FCT, iga = a.opts & OPT_IGA;
+
+    T *out1 = (a.n_iters == 1) ? a.psi_out : a.tmp[0];
+    k_donor<T><<<cblocks, B, 0, s>>>(g, a.psi_n, a.c[0], a.c[1], a.c[2], a.G, 0, out1);
+    const T *cprev[3] = {a.c[0], a.c[1], a.c[2]};
+    const T *x = out1;
+    int set = 0;
+    for (int it = 2; it <= a.n_iters; it++) {
+        // raw pseudo-velocity into the face set not holding cprev
+        T *const *raw = a.faces[set];
+        for (int d = 0; d < g.nd; d++) {
+            unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), B);
+            k_pseudo<T><<<wb, B, 0, s>>>(g, d, a.opts, x, cprev[0], cprev[1], cprev[2], a.G,
+                                         raw[d]);
+        }
+        T *const *adv = raw;
+        if (fct) {
+            T *const *lim = a.faces[set ^ 1];
+            k_fct_beta<T><<<cblocks, B, 0, s>>>(g, a.opts, a.psi_n, x, raw[0], raw[1], raw[2],
+                                                a.G, a.bup, a.bdn);
+            for (int d = 0; d < g.nd; d++) {
+                unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), B);
+                k_fct_limit<T><<<wb, B, 0, s>>>(g, d, raw[d], a.bup, a.bdn, lim[d]);
+            }
+            adv = lim;
+        } else {
+            set ^= 1;
+        }
+        T *y = (it == a.n_iters) ? a.psi_out : a.tmp[(it - 1) & 1];
+        k_donor<T><<<cblocks, B, 0, s>>>(g, x, adv[0], adv[1], adv[2], a.G, iga ? 1 : 0, y);
+        for (int d = 0; d < 3; d++) cprev[d] = adv[d];
+        x = y;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t staged_step<float>(const StagedArgs<float> &, hipStream_t);
+template hipError_t staged_step<double>(const StagedArgs<double> &, hipStream_t);
+
+}  // namespace mp

@@ -1,0 +1,310 @@
+"""Thin Python binding of libmpdata (the C ABI in include/mpdata.h).
+
+Argument marshalling only: shapes, dtypes and devices are checked, torch
+tensors are passed as raw device pointers together with torch's current HIP
+stream, and every step of the computation runs in the library's kernels.
+PyTorch supplies device memory (including the plan's workspace) and streams.
+
+The library is loaded on first use from this package directory; if it is
+missing the binding raises instead of computing anything another way.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpdata.so")
+
+OK, EINVAL, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+OPT_FCT, OPT_IGA, OPT_TOT = 1, 2, 4
+BC_PERIODIC, BC_OPEN = 0, 1
+F32, F64 = 0, 1
+KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2
+
+EXPORTS = [
+    "mpdata_workspace_bytes", "mpdata_init", "mpdata_set_stream", "mpdata_set_kernel",
+    "mpdata_step", "mpdata_diag", "mpdata_courant_max", "mpdata_adv_adj",
+    "mpdata_adj_workspace_bytes", "mpdata_batched_workspace_bytes", "mpdata_batched_init",
+    "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_destroy", "mpdata_last_error",
+]
+
+
+class MPDATAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmpdata status {code}: {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n_dims", ctypes.c_int), ("shape", ctypes.c_int64 * 3), ("dtype", ctypes.c_int),
+                ("n_iters", ctypes.c_int), ("opts", ctypes.c_uint32), ("bc", ctypes.c_int * 3),
+                ("has_g", ctypes.c_int)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """Load libmpdata.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the MPDATA step has no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        DP = ctypes.POINTER(Desc)
+        L.mpdata_workspace_bytes.argtypes = [DP]
+        L.mpdata_workspace_bytes.restype = ctypes.c_size_t
+        L.mpdata_init.argtypes = [DP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]
+        L.mpdata_set_stream.argtypes = [_VP, _VP]
+        L.mpdata_set_kernel.argtypes = [_VP, ctypes.c_int]
+        L.mpdata_step.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int]
+        L.mpdata_diag.argtypes = [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int64)]
+        L.mpdata_courant_max.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)]
+        L.mpdata_adv_adj.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int,
+                                     _VP, _VP, _VP, _VP, _VP]
+        L.mpdata_adj_workspace_bytes.argtypes = [DP, ctypes.c_int, ctypes.c_int]
+        L.mpdata_adj_workspace_bytes.restype = ctypes.c_size_t
+        I64P = ctypes.POINTER(ctypes.c_int64)
+        L.mpdata_batched_workspace_bytes.argtypes = [ctypes.c_int, I64P, ctypes.c_int, ctypes.c_int,
+                                                     ctypes.c_uint32, ctypes.c_int]
+        L.mpdata_batched_workspace_bytes.restype = ctypes.c_size_t
+        L.mpdata_batched_init.argtypes = [ctypes.c_int, I64P, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_uint32, ctypes.c_int, _VP, ctypes.c_size_t, _VP,
+                                          ctypes.POINTER(_VP)]
+        L.mpdata_step_batched.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int]
+        L.mpdata_step_per_grid.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int]
+        L.mpdata_destroy.argtypes = [_VP]
+        L.mpdata_destroy.restype = None
+        L.mpdata_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise MPDATAError(rc, lib().mpdata_last_error().decode())
+
+
+def _dtype_code(dtype):
+    if dtype == torch.float64:
+        return F64
+    if dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _wall_shape(shape, d):
+    s = list(shape)
+    s[d] += 1
+    return tuple(s)
+
+
+class Plan:
+    """A single-grid plan: validated descriptor + workspace + stream.
+
+    shape: cells per dimension (1-3 entries); bc: int or per-dimension list.
+    adj_steps / ckpt_every: size the workspace for mpdata_adv_adj as well."""
+
+    def __init__(self, shape, dtype=torch.float64, n_iters=2, opts=0, bc=BC_PERIODIC,
+                 has_g=False, device="cuda", kernel=KERNEL_AUTO, adj_steps=None, ckpt_every=None):
+        self.shape = tuple(int(s) for s in shape)
+        self.nd = len(self.shape)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        bcs = [bc] * self.nd if isinstance(bc, int) else list(bc)
+        d = Desc()
+        d.n_dims = self.nd
+        for k in range(3):
+            d.shape[k] = self.shape[k] if k < self.nd else 1
+            d.bc[k] = bcs[k] if k < self.nd else 0
+        d.dtype = _dtype_code(dtype)
+        d.n_iters = int(n_iters)
+        d.opts = int(opts)
+        d.has_g = 1 if has_g else 0
+        self.desc = d
+        L = lib()
+        need = L.mpdata_workspace_bytes(ctypes.byref(d))
+        if need == 0:
+            # let init report the reason
+            self._handle = _VP()
+            _check(L.mpdata_init(ctypes.byref(d), None, 0, None, ctypes.byref(self._handle)))
+        if adj_steps is not None:
+            adj = L.mpdata_adj_workspace_bytes(ctypes.byref(d), int(adj_steps), int(ckpt_every))
+            if adj == 0:
+                raise ValueError("bad adjoint sizing (need 1 <= ckpt_every <= adj_steps)")
+            need = max(need, adj)
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        self._ws_bytes = need
+        self._handle = _VP()
+        _check(L.mpdata_init(ctypes.byref(d), ctypes.c_void_p(self._ws_ptr), need,
+                             _stream(self.device), ctypes.byref(self._handle)))
+        if kernel != KERNEL_AUTO:
+            self.set_kernel(kernel)
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h and _lib is not None:
+            _lib.mpdata_destroy(h)
+            self._handle = None
+
+    def set_kernel(self, kernel):
+        _check(lib().mpdata_set_kernel(self._handle, int(kernel)))
+
+    def _bind_stream(self):
+        _check(lib().mpdata_set_stream(self._handle, _stream(self.device)))
+
+    def _check_cell(self, t, name):
+        if t is None:
+            return
+        if t.device != self.device and not (t.is_cuda and self.device.type == "cuda"):
+            raise ValueError(f"{name} must be on {self.device}")
+        if t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name}: need contiguous {self.dtype} of shape {self.shape}, got "
+                             f"{t.dtype} {tuple(t.shape)} contiguous={t.is_contiguous()}")
+
+    def _check_walls(self, c):
+        if len(c) != self.nd:
+            raise ValueError(f"need {self.nd} advector components")
+        for d, cd in enumerate(c):
+            want = _wall_shape(self.shape, d)
+            if cd.dtype != self.dtype or tuple(cd.shape) != want or not cd.is_contiguous() \
+                    or not cd.is_cuda:
+                raise ValueError(f"c[{d}]: need contiguous {self.dtype} of shape {want} on the GPU")
+        return [_ptr(x) for x in c] + [None] * (3 - self.nd)
+
+    def step(self, psi, c, g=None, n_steps=1):
+        """Advance psi in place by n_steps steps on torch's current stream."""
+        self._check_cell(psi, "psi")
+        self._check_cell(g, "g")
+        cp = self._check_walls(c)
+        self._bind_stream()
+        _check(lib().mpdata_step(self._handle, _ptr(psi), _ptr(g), cp[0], cp[1], cp[2],
+                                 int(n_steps)))
+        return psi
+
+    def diag(self, psi, g=None):
+        """(sum G psi, min, max, n_nonfinite); waits for the result."""
+        self._check_cell(psi, "psi")
+        self._check_cell(g, "g")
+        self._bind_stream()
+        out = (ctypes.c_double * 3)()
+        bad = ctypes.c_int64(0)
+        rc = lib().mpdata_diag(self._handle, _ptr(psi), _ptr(g), out, ctypes.byref(bad))
+        if rc not in (OK, ENONFINITE):
+            _check(rc)
+        return out[0], out[1], out[2], int(bad.value)
+
+    def courant_max(self, c, g=None):
+        self._check_cell(g, "g")
+        cp = self._check_walls(c)
+        self._bind_stream()
+        out = ctypes.c_double(0.0)
+        _check(lib().mpdata_courant_max(self._handle, _ptr(g), cp[0], cp[1], cp[2],
+                                        ctypes.byref(out)))
+        return out.value
+
+    def adv_adj(self, psi0, c, lambda_T, g=None, n_steps=1, ckpt_every=None):
+        """Gradient of J w.r.t. psi0 and c, given lambda_T = dJ/dpsi_T."""
+        ckpt_every = int(ckpt_every or n_steps)
+        self._check_cell(psi0, "psi0")
+        self._check_cell(lambda_T, "lambda_T")
+        self._check_cell(g, "g")
+        cp = self._check_walls(c)
+        gpsi = torch.empty_like(psi0)
+        gc = [torch.empty_like(x) for x in c]
+        gp = [_ptr(x) for x in gc] + [None] * (3 - self.nd)
+        self._bind_stream()
+        _check(lib().mpdata_adv_adj(self._handle, _ptr(psi0), _ptr(g), cp[0], cp[1], cp[2],
+                                    int(n_steps), ckpt_every, _ptr(lambda_T), _ptr(gpsi),
+                                    gp[0], gp[1], gp[2]))
+        return gpsi, gc
+
+
+class BatchedPlan:
+    """Many independent 2-D grids of uneven size in packed buffers."""
+
+    def __init__(self, shapes, dtype=torch.float32, n_iters=2, opts=OPT_FCT, bc=BC_PERIODIC,
+                 device="cuda"):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.n = len(self.shapes)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        flat = (ctypes.c_int64 * (2 * self.n))(*[v for s in self.shapes for v in s])
+        L = lib()
+        need = L.mpdata_batched_workspace_bytes(self.n, flat, _dtype_code(dtype), int(n_iters),
+                                                int(opts), int(bc))
+        if need == 0:
+            raise ValueError("invalid batched shapes (each side must be >= 3)")
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = base + (-base) % 256
+        self._handle = _VP()
+        _check(L.mpdata_batched_init(self.n, flat, _dtype_code(dtype), int(n_iters), int(opts),
+                                     int(bc), ctypes.c_void_p(self._ws_ptr), need,
+                                     _stream(self.device), ctypes.byref(self._handle)))
+        self.n_psi = sum(a * b for a, b in self.shapes)
+        self.n_c0 = sum((a + 1) * b for a, b in self.shapes)
+        self.n_c1 = sum(a * (b + 1) for a, b in self.shapes)
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h and _lib is not None:
+            _lib.mpdata_destroy(h)
+            self._handle = None
+
+    def _check(self, psi, c0, c1):
+        for t, n, name in ((psi, self.n_psi, "psi"), (c0, self.n_c0, "c0"), (c1, self.n_c1, "c1")):
+            if t.dtype != self.dtype or t.numel() != n or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name}: need {n} contiguous {self.dtype} values on the GPU")
+        _check(lib().mpdata_set_stream(self._handle, _stream(self.device)))
+
+    def step(self, psi, c0, c1, n_steps=1, use_graph=True):
+        self._check(psi, c0, c1)
+        _check(lib().mpdata_step_batched(self._handle, _ptr(psi), _ptr(c0), _ptr(c1),
+                                         int(n_steps), 1 if use_graph else 0))
+        return psi
+
+    def step_per_grid(self, psi, c0, c1, n_steps=1):
+        self._check(psi, c0, c1)
+        _check(lib().mpdata_step_per_grid(self._handle, _ptr(psi), _ptr(c0), _ptr(c1),
+                                          int(n_steps)))
+        return psi
+
+    def pack(self, arrays, which):
+        """Concatenate per-grid arrays (cells / c0 walls / c1 walls) into one
+        packed device tensor."""
+        return torch.cat([torch.as_tensor(a, dtype=self.dtype).reshape(-1) for a in arrays]) \
+            .to(self.device).contiguous()
+
+    def unpack(self, packed, which):
+        out, off = [], 0
+        for a, b in self.shapes:
+            shp = {"psi": (a, b), "c0": (a + 1, b), "c1": (a, b + 1)}[which]
+            n = shp[0] * shp[1]
+            out.append(packed[off:off + n].reshape(shp))
+            off += n
+        return out
+
+
+def step(psi, c, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1, kernel=KERNEL_AUTO):
+    """One-shot convenience: build a plan and advance psi in place."""
+    p = Plan(tuple(psi.shape), dtype=psi.dtype, n_iters=n_iters, opts=opts, bc=bc,
+             has_g=g is not None, device=psi.device, kernel=kernel)
+    return p.step(psi, c, g=g, n_steps=n_steps)

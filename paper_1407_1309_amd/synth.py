@@ -66,23 +66,32 @@ def blob_field(shape, n_blobs, sigma_range, amp, gen: np.random.Generator,
                periodic=True) -> np.ndarray:
     """Sum of Gaussian blobs exp(-r^2 / (2 s^2)); amp is 'uniform' (U(0,1)) or
     'normal' (N(0,1)).  Periodic fields use the minimum-image distance.  Each
-    blob is separable, so it is built as an outer product."""
+    blob is separable, so the sum over blobs is a product of per-axis profile
+    matrices (the last axis split off)."""
     shape = tuple(int(s) for s in shape)
-    out = np.zeros(shape)
+    nd = len(shape)
+    profs = [[] for _ in range(nd)]
+    amps = []
     for _ in range(n_blobs):
         centre = [gen.uniform(0, s) for s in shape]
         s = gen.uniform(*sigma_range)
         a = gen.uniform(0.0, 1.0) if amp == "uniform" else gen.normal()
-        prof = None
+        amps.append(a)
         for d, n in enumerate(shape):
             if periodic:
                 x = _periodic_offsets(n, centre[d])
             else:
                 x = np.arange(n, dtype=np.float64) - centre[d]
-            p = np.exp(-x * x / (2.0 * s * s))
-            prof = p if prof is None else np.multiply.outer(prof, p)
-        out += a * prof
-    return out
+            profs[d].append(np.exp(-x * x / (2.0 * s * s)))
+    amps = np.array(amps)
+    if nd == 1:
+        return np.array(profs[0]).T @ amps
+    lead = np.array(profs[0]).T * amps                     # (n0, B)
+    for d in range(1, nd - 1):
+        P = np.array(profs[d]).T                            # (nd, B)
+        lead = (lead[:, None, :] * P[None, :, :]).reshape(-1, n_blobs)
+    out = lead @ np.array(profs[nd - 1])                    # (prod lead, n_last)
+    return out.reshape(shape)
 
 
 # --------------------------------------------------------------------------
@@ -101,18 +110,26 @@ def _modes(gen, nd, n_modes, kmax):
 
 
 def _sum_of_sines(coords, lengths, ks, amps, phases):
-    """sum_m a_m sin(2 pi sum_d k_md x_d / L_d + phi_m), on the outer grid of
-    the 1-D coordinate vectors; built from separable cos/sin products."""
+    """sum_m a_m sin(2 pi sum_d k_md x_d / L_d + phi_m) on the outer grid of
+    the 1-D coordinate vectors.  With the last axis split off,
+    sin(P + Q) = sin P cos Q + cos P sin Q turns the sum over modes into one
+    matrix product."""
     shape = tuple(len(x) for x in coords)
-    out = np.zeros(shape)
+    nd = len(coords)
+    lead_cols_s, lead_cols_c, last_c, last_s = [], [], [], []
     for k, a, ph in zip(ks, amps, phases):
-        # complex exponential is separable: Im(e^{i phi} prod_d e^{i k_d x_d})
-        prod = None
-        for d, x in enumerate(coords):
-            e = np.exp(1j * 2.0 * math.pi * k[d] * x / lengths[d])
-            prod = e if prod is None else np.multiply.outer(prod, e)
-        out += a * np.imag(np.exp(1j * ph) * prod)
-    return out
+        P = np.full((1,), ph)
+        for d in range(nd - 1):
+            ang = 2.0 * math.pi * k[d] * coords[d] / lengths[d]
+            P = (P[:, None] + ang[None, :]).reshape(-1)
+        q = 2.0 * math.pi * k[nd - 1] * coords[nd - 1] / lengths[nd - 1]
+        lead_cols_s.append(a * np.sin(P))
+        lead_cols_c.append(a * np.cos(P))
+        last_c.append(np.cos(q))
+        last_s.append(np.sin(q))
+    lead = np.stack(lead_cols_s + lead_cols_c, axis=1)      # (prod lead, 2M)
+    last = np.stack(last_c + last_s, axis=0)                # (2M, n_last)
+    return (lead @ last).reshape(shape)
 
 
 def stream_advector_2d(shape, courant, gen, n_modes=8, kmax=4, mant_bits=23):

@@ -1,0 +1,215 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: relative L2 <= 1e-12 for the FP64 path and <= 1e-5 for the FP32 path
+(the oracle consumes the FP32-rounded inputs widened to FP64).  Sizes span
+several tiles with ragged tails; full workload sizes are checked on whole
+fields where the oracle is fast enough and on sampled sub-blocks otherwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1407_1309_amd import mpdata, synth
+from tests.gpu_util import TOL, as_dtype, dev, gpu_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FCT, IGA, TOT = 1, 2, 4
+OPTS = [0, FCT, TOT, FCT | TOT, IGA, IGA | FCT, IGA | TOT, IGA | TOT | FCT]
+KERNELS = [mpdata.KERNEL_STAGED, mpdata.KERNEL_AUTO]
+DTYPES = [torch.float64, torch.float32]
+
+
+def _inputs(shape, bc, opts, seed, with_g):
+    gen = synth.rng(seed)
+    nd = len(shape)
+    g = gen.uniform(0.6, 1.4, size=shape) if with_g else None
+    if bc == 0:
+        c = synth.small_advector(shape, 0.5, gen, g=g) if nd > 1 else [np.full(shape[0] + 1, 0.43)]
+    else:
+        c = synth.random_advector(shape, 0.45, gen)
+    m = min(shape)
+    psi = synth.blob_field(shape, 6, (m / 10, m / 4), "normal" if opts & IGA else "uniform", gen,
+                           periodic=(bc == 0))
+    return psi, c, g
+
+
+CASES = []
+for shape in [(1000,), (150, 197), (37, 29, 41)]:
+    for bc in (0, 1):
+        for opts in OPTS:
+            CASES.append((shape, bc, opts))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,bc,opts", CASES)
+def test_parity_small(shape, bc, opts, dtype):
+    n_iters = 2 if opts & IGA else 3
+    with_g = (opts % 2 == 0)
+    psi, c, g = _inputs(shape, bc, opts, seed=len(shape) * 100 + bc * 10 + opts, with_g=with_g)
+    psi, c, g = as_dtype(psi, dtype), [as_dtype(x, dtype) for x in c], as_dtype(g, dtype)
+    n_steps = 5
+    ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=n_steps)
+    for kernel in KERNELS:
+        out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, n_steps, kernel=kernel)
+        err = rel_l2(out, ref)
+        assert err <= TOL[dtype], (kernel, err)
+
+
+@pytest.mark.parametrize("n_iters", [1, 2, 3, 4])
+def test_parity_pass_counts(n_iters):
+    shape = (130, 70)
+    psi, c, g = _inputs(shape, 0, FCT, seed=7, with_g=True)
+    ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=FCT, n_steps=3)
+    for kernel in KERNELS:
+        out = gpu_run(psi, c, g, torch.float64, n_iters, FCT, 0, 3, kernel=kernel)
+        assert rel_l2(out, ref) <= 1e-12
+
+
+def test_parity_1d_workload_full():
+    """1-D periodic, nx=500, C=0.5, n_iters=2, 1000 steps: whole field."""
+    case = synth.case_1d()
+    ref = oracle.step(case.psi, case.c, n_iters=2, n_steps=case.n_steps)
+    out = gpu_run(case.psi, case.c, None, torch.float64, 2, 0, 0, case.n_steps)
+    assert rel_l2(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_parity_2d_workload_full(dtype):
+    """2-D periodic 2048^2, n_iters=3 with the limiter: whole field after 2
+    steps at full size, in the launch configuration the benchmark times."""
+    case = synth.case_2d()
+    psi = as_dtype(case.psi, dtype)
+    c = [as_dtype(x, dtype) for x in case.c]
+    ref = oracle.step(psi, c, n_iters=3, opts=FCT, n_steps=2)
+    out = gpu_run(psi, c, None, dtype, 3, FCT, 0, 2)
+    assert rel_l2(out, ref) <= TOL[dtype]
+
+
+def _subblock_check(case, out, dtype, n_steps, centres, half=6):
+    """Compare `out` with the oracle run on sub-blocks around `centres`; the
+    block margin exceeds the domain of dependence, so its own boundaries do
+    not reach the compared core (real boundaries are kept)."""
+    shape = case.psi.shape
+    nd = len(shape)
+    radius = 3 * n_steps + 2
+    errs = []
+    for ctr in centres:
+        lo = [max(0, ctr[d] - half - radius) if case.bc else ctr[d] - half - radius for d in range(nd)]
+        hi = [min(shape[d], ctr[d] + half + radius + 1) if case.bc else ctr[d] + half + radius + 1
+              for d in range(nd)]
+        idx = [np.arange(lo[d], hi[d]) % shape[d] for d in range(nd)]
+        ix = np.ix_(*idx)
+        sub_psi = as_dtype(case.psi[ix], dtype)
+        sub_g = as_dtype(case.g[ix], dtype) if case.g is not None else None
+        sub_c = []
+        for d in range(nd):
+            wi = list(idx)
+            wi[d] = np.arange(lo[d], hi[d] + 1) % (shape[d] + (1 if case.bc else 0))
+            sub_c.append(as_dtype(case.c[d][np.ix_(*wi)], dtype))
+        ref = oracle.step(sub_psi, sub_c, g=sub_g, n_iters=case.n_iters, opts=case.opts,
+                          bc=case.bc, n_steps=n_steps)
+        core = []
+        for d in range(nd):
+            a = max(lo[d], ctr[d] - half) - lo[d]
+            b = min(hi[d], ctr[d] + half + 1) - lo[d]
+            core.append(slice(a, b))
+        got = out[ix][tuple(core)]
+        errs.append(rel_l2(got, ref[tuple(core)]))
+    return max(errs)
+
+
+def test_parity_3d_workload_sampled():
+    """3-D open 384x384x256 (G(z), tot + iga, n_iters=2): full-size GPU run,
+    oracle on sub-blocks at corners, edges, faces and the interior."""
+    case = synth.case_3d()
+    n_steps = 2
+    out = gpu_run(case.psi, case.c, case.g, torch.float64, 2, case.opts, 1, n_steps)
+    s = case.psi.shape
+    centres = [(0, 0, 0), (s[0] - 1, s[1] - 1, s[2] - 1), (0, s[1] // 2, s[2] - 1),
+               (s[0] // 2, s[1] // 2, s[2] // 2), (s[0] - 3, 5, s[2] // 3), (100, 0, 128)]
+    assert _subblock_check(case, out, torch.float64, n_steps, centres) <= 1e-12
+
+
+def test_resume_is_bitwise():
+    """Resumability (the paper's advance()): 3 + 4 steps == 7 steps, bit for bit."""
+    case = synth.case_2d(n=192, n_steps=7)
+    for kernel in KERNELS:
+        plan = mpdata.Plan(case.psi.shape, n_iters=3, opts=FCT, kernel=kernel)
+        c = [dev(x, torch.float64) for x in case.c]
+        a = dev(case.psi, torch.float64)
+        b = a.clone()
+        plan.step(a, c, n_steps=7)
+        plan.step(b, c, n_steps=3)
+        plan.step(b, c, n_steps=4)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_gpu_invariants_conservation_and_bounds():
+    """On the GPU path itself: sum(G psi) conserved (periodic) and, with the
+    limiter, no new global extrema."""
+    case = synth.case_2d(n=512, seed=9)
+    plan = mpdata.Plan(case.psi.shape, n_iters=3, opts=FCT)
+    c = [dev(x, torch.float64) for x in case.c]
+    p = dev(case.psi, torch.float64)
+    s0, mn0, mx0, bad0 = plan.diag(p)
+    plan.step(p, c, n_steps=50)
+    s1, mn1, mx1, bad1 = plan.diag(p)
+    assert bad0 == bad1 == 0
+    assert abs(s1 - s0) <= 1e-13 * abs(s0)
+    assert mx1 <= mx0 and mn1 >= mn0 - 1e-15
+
+
+def test_diag_matches_oracle():
+    gen = synth.rng(5)
+    shape = (333, 257)
+    psi = gen.normal(size=shape)
+    g = gen.uniform(0.5, 2.0, size=shape)
+    plan = mpdata.Plan(shape, has_g=True)
+    s, mn, mx, bad = plan.diag(dev(psi, torch.float64), dev(g, torch.float64))
+    rs, rmn, rmx, rbad = oracle.diag(psi, g)
+    assert abs(s - rs) <= 1e-14 * np.sum(np.abs(g * psi)) and (mn, mx, bad) == (rmn, rmx, rbad)
+    psi[3, 5] = np.nan
+    psi[100, 7] = np.inf
+    s, mn, mx, bad = plan.diag(dev(psi, torch.float64), dev(g, torch.float64))
+    assert bad == 2
+
+
+def test_courant_max_matches_oracle():
+    case = synth.case_3d(shape=(40, 36, 28))
+    plan = mpdata.Plan(case.psi.shape, n_iters=2, opts=case.opts, bc=1, has_g=True)
+    got = plan.courant_max([dev(x, torch.float64) for x in case.c], g=dev(case.g, torch.float64))
+    ref = oracle.courant_max(case.psi.shape, case.c, g=case.g, bc=1)
+    assert abs(got - ref) <= 1e-15 * ref
+
+
+def test_step_argument_errors():
+    plan = mpdata.Plan((64, 64))
+    p = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
+    c0 = torch.zeros(65, 64, dtype=torch.float64, device="cuda")
+    c1 = torch.zeros(64, 65, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        plan.step(p, [c0])
+    with pytest.raises(ValueError):
+        plan.step(p, [c0, c1.float()])
+    L = mpdata.lib()
+    import ctypes
+    rc = L.mpdata_step(plan._handle, ctypes.c_void_p(p.data_ptr()), None,
+                       ctypes.c_void_p(c0.data_ptr()), None, None, 1)
+    assert rc == mpdata.EINVAL
+    rc = L.mpdata_step(plan._handle, ctypes.c_void_p(p.data_ptr()),
+                       ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(c0.data_ptr()),
+                       ctypes.c_void_p(c1.data_ptr()), None, 1)
+    assert rc == mpdata.EINVAL          # g given to a plan without has_g
+
+
+def test_zero_steps_is_identity():
+    case = synth.case_2d(n=64)
+    p = dev(case.psi, torch.float64)
+    q = p.clone()
+    mpdata.Plan(case.psi.shape, n_iters=3, opts=FCT).step(p, [dev(x, torch.float64) for x in case.c],
+                                                          n_steps=0)
+    torch.cuda.synchronize()
+    assert torch.equal(p, q)
