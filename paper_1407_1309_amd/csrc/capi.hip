@@ -194,7 +194,7 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
 bool use_fused(const mpdata_plan *p)
 {
     bool ok = mp::fused2d_supported(p->desc.n_dims, p->desc.n_iters, p->desc.opts,
-                                    p->desc.dtype == MPDATA_F64);
+                                    p->desc.has_g, p->g.bc[0], p->g.bc[1]);
     if (p->kernel == MPDATA_KERNEL_STAGED) return false;
     return ok;
 }
@@ -270,7 +270,7 @@ int mpdata_set_kernel(mpdata_plan *plan, int kernel)
         return fail(MPDATA_EINVAL, "unknown kernel %d", kernel);
     if (kernel == MPDATA_KERNEL_FUSED &&
         !mp::fused2d_supported(plan->desc.n_dims, plan->desc.n_iters, plan->desc.opts,
-                               plan->desc.dtype == MPDATA_F64))
+                               plan->desc.has_g, plan->g.bc[0], plan->g.bc[1]))
         return fail(MPDATA_EUNSUPPORTED, "no fused kernel for this plan");
     plan->kernel = kernel;
     return MPDATA_OK;
@@ -454,7 +454,7 @@ int mpdata_batched_init(int n_grids, const int64_t *shapes, int dtype, int n_ite
         int rc = check_desc(&d, &g);
         if (rc) return fail(rc, "grid %d: %s", i, g_err.c_str());
     }
-    if (!mp::fused2d_supported(2, n_iters, opts, dtype == MPDATA_F64))
+    if (!mp::fused2d_supported(2, n_iters, opts, 0, bc, bc))
         return fail(MPDATA_EUNSUPPORTED, "no batched kernel for these options");
     size_t need = mpdata_batched_workspace_bytes(n_grids, shapes, dtype, n_iters, opts, bc);
     if (!workspace || ws_bytes < need || (uintptr_t)workspace % ALIGN)
@@ -468,7 +468,7 @@ int mpdata_batched_init(int n_grids, const int64_t *shapes, int dtype, int n_ite
     p->stream = (hipStream_t)hip_stream;
     p->kernel = MPDATA_KERNEL_FUSED;
     memset(&p->L, 0, sizeof p->L);
-    int tr = mp::fused2d_tile_rows(), tc = mp::fused2d_tile_cols();
+    int tr = mp::fused2d_tile_rows(), tc = mp::fused2d_strip_cols(n_iters, opts);
     p->grids.resize(n_grids);
     int64_t op = 0, o0 = 0, o1 = 0;
     int64_t tiles = 0;

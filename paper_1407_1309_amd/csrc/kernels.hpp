@@ -45,7 +45,7 @@ struct Fused2DShape {
 };
 
 // true if a fused kernel exists for this configuration
-bool fused2d_supported(int nd, int n_iters, unsigned opts, int dtype_is_f64);
+bool fused2d_supported(int nd, int n_iters, unsigned opts, int has_g, int bc0, int bc1);
 
 template <typename T>
 hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
@@ -64,7 +64,7 @@ hipError_t fused2d_batched_step(const BatchGrid *grids_dev, int n_grids, int n_t
                                 int n_iters, unsigned opts, const T *psi_n, T *psi_out,
                                 const T *c0, const T *c1, hipStream_t s);
 
-int fused2d_tile_rows();
-int fused2d_tile_cols();
+int fused2d_tile_rows();                             // rows per batched tile
+int fused2d_strip_cols(int n_iters, unsigned opts);  // output columns per strip
 
 }  // namespace mp
