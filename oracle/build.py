@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["mpdata_oracle.c", "mpdata_oracle_adj.c"]
+SOURCES = ["mpdata_oracle.c"]
 OUT = os.path.join(HERE, "liboracle.so")
 
 
