@@ -1,13 +1,623 @@
-// adjoint.hip -- reverse-mode MPDATA step (placeholder until implemented).
+// adjoint.hip -- reverse mode of the MPDATA step on the GPU (an extension of
+// the method, not in the paper).
+//
+// Sweep: a forward pass keeps psi at the start of every segment of
+// ckpt_every steps; segments are then reversed last to first, recomputing
+// their states, and every step is reversed stage by stage.  The forward
+// recompute of a step runs the staged kernels and keeps each pass's input
+// field, raw and limited pseudo-velocities and limiter coefficients; the
+// reverse kernels are the transposes of those stages, one thread per
+// forward output (cell or wall), scattering into the adjoints of the values
+// that output read (through the boundary map) with hardware floating-point
+// atomics.
+//
+// Conventions at non-differentiable points: d[u]+/du = [u > 0],
+// d[u]-/du = [u < 0], d|u|/du = [u > 0] - [u < 0]; max/min pass the
+// derivative to the operand they returned, ties to the earliest operand in
+// the forward's scan order; zero-denominator fractions and the "no flux"
+// limiter branch have zero derivative.  G is a constant.
 #include "adjoint.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
 
 namespace mp {
+namespace {
 
-size_t adj_extra_bytes(const Geom &, size_t, int, int, int) { return 0; }
+constexpr int B = 256;
 
-template <typename T> hipError_t adjoint_run(const AdjArgs<T> &, hipStream_t)
+struct I3 {
+    int64_t v[3];
+};
+
+__device__ inline I3 unflat3(int64_t t, const int64_t e[3])
 {
-    return hipErrorNotSupported;
+    I3 p;
+    p.v[2] = t % e[2];
+    t /= e[2];
+    p.v[1] = t % e[1];
+    p.v[0] = t / e[1];
+    return p;
+}
+
+__device__ inline I3 sh1(I3 p, int d, int64_t s)
+{
+    p.v[d] += s;
+    return p;
+}
+
+__device__ inline I3 sh2(I3 p, int d, int64_t s, int e, int64_t t)
+{
+    p.v[d] += s;
+    p.v[e] += t;
+    return p;
+}
+
+__device__ inline int64_t ci(const Geom &g, const I3 &p)
+{
+    int64_t i = map_cell(p.v[0], g.n[0], g.bc[0]);
+    int64_t j = map_cell(p.v[1], g.n[1], g.bc[1]);
+    int64_t k = map_cell(p.v[2], g.n[2], g.bc[2]);
+    return (i * g.n[1] + j) * g.n[2] + k;
+}
+
+__device__ inline int64_t wi(const Geom &g, int d, const I3 &p)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    int64_t q[3];
+    for (int t = 0; t < 3; t++)
+        q[t] = (t == d) ? map_wall(p.v[t], g.n[t], g.bc[t]) : map_cell(p.v[t], g.n[t], g.bc[t]);
+    return (q[0] * e[1] + q[1]) * e[2] + q[2];
+}
+
+template <typename T> __device__ inline void aadd(T *a, int64_t k, T v)
+{
+    if (v != T(0)) unsafeAtomicAdd(a + k, v);
+}
+
+template <typename T> __device__ inline T sgnv(T u) { return T((u > T(0)) - (u < T(0))); }
+
+template <typename T> __device__ inline T fracv(bool iga, T num, T den, T m)
+{
+    if (iga) return num / m;
+    return den == T(0) ? T(0) : num / den;
+}
+
+// d frac / d num, d frac / d den
+template <typename T> __device__ inline void frac_d(bool iga, T num, T den, T m, T &dn, T &dd)
+{
+    if (iga) {
+        dn = T(1) / m;
+        dd = T(0);
+    } else if (den == T(0)) {
+        dn = dd = T(0);
+    } else {
+        dn = T(1) / den;
+        dd = -num / (den * den);
+    }
+}
+
+template <typename T> __global__ void k_fill(T *a, int64_t n, T v)
+{
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
+template <typename T> __global__ void k_add(T *a, const T *b, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t < n) a[t] += b[t];
+}
+
+template <typename T> __global__ void k_copy(T *a, const T *b, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t < n) a[t] = b[t];
+}
+
+// transpose of the donor-cell pass y = x - sum_d (F(hi) - F(lo)) / G
+template <typename T>
+__global__ void k_donor_adj(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
+                            const T *c2, const T *G, int flux_is_vel, const T *__restrict__ yb,
+                            T *xb, T *cb0, T *cb1, T *cb2)
+{
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= N) return;
+    const T *c[3] = {c0, c1, c2};
+    T *cb[3] = {cb0, cb1, cb2};
+    I3 p = unflat3(t, g.n);
+    T ob = yb[t];
+    aadd(xb, t, ob);
+    T accb = G ? -ob / G[t] : -ob;
+    for (int d = 0; d < g.nd; d++)
+        for (int s = 0; s < 2; s++) {
+            I3 w = sh1(p, d, s);
+            T fb = s ? accb : -accb;
+            int64_t kw = wi(g, d, w);
+            if (flux_is_vel) {
+                aadd(cb[d], kw, fb);
+                continue;
+            }
+            I3 L = sh1(w, d, -1);
+            int64_t kL = ci(g, L), kR = ci(g, w);
+            T u = c[d][kw];
+            T du = (u > T(0) ? x[kL] : T(0)) + (u < T(0) ? x[kR] : T(0));
+            aadd(cb[d], kw, du * fb);
+            aadd(xb, kL, pos(u) * fb);
+            aadd(xb, kR, neg(u) * fb);
+        }
+}
+
+// transpose of the pseudo-velocity at every dimension-d wall
+template <typename T>
+__global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__ x, const T *c0,
+                             const T *c1, const T *c2, const T *G, const T *__restrict__ Vb,
+                             T *xb, T *cb0, T *cb1, T *cb2)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    int64_t M = e[0] * e[1] * e[2];
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= M) return;
+    T vb = Vb[t];
+    if (vb == T(0)) return;
+    const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
+    const T *c[3] = {c0, c1, c2};
+    T *cb[3] = {cb0, cb1, cb2};
+    I3 p = unflat3(t, e);
+    I3 L = sh1(p, d, -1), R = p;
+    T u = c[d][wi(g, d, p)];
+    T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
+    T Gb = T(0.5) * (GL + GR);
+    int64_t kL = ci(g, L), kR = ci(g, R);
+    T xL = x[kL], xR = x[kR];
+    T ub = T(0), fn, fd;
+
+    T nA = xR - xL, dA = xR + xL;
+    T A = fracv(iga, nA, dA, T(2));
+    frac_d(iga, nA, dA, T(2), fn, fd);
+    ub += (sgnv(u) - T(2) * u / Gb) * A * vb;
+    T Ab = (fabs(u) - u * u / Gb) * vb;
+    aadd(xb, kR, (fn + fd) * Ab);
+    aadd(xb, kL, (-fn + fd) * Ab);
+
+    T cbar[3] = {T(0), T(0), T(0)}, cbar_b[3] = {T(0), T(0), T(0)};
+    for (int o = 0; o < g.nd; o++) {
+        if (o == d) continue;
+        cbar[o] = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, sh1(L, o, 1))] +
+                             c[o][wi(g, o, R)] + c[o][wi(g, o, sh1(R, o, 1))]);
+        int64_t kRp = ci(g, sh1(R, o, 1)), kLp = ci(g, sh1(L, o, 1));
+        int64_t kRm = ci(g, sh1(R, o, -1)), kLm = ci(g, sh1(L, o, -1));
+        T a = x[kRp], b = x[kLp], ee = x[kRm], f = x[kLm];
+        T nB = a + b - ee - f, dB = a + b + ee + f;
+        T Bv = fracv(iga, nB, dB, T(4));
+        frac_d(iga, nB, dB, T(4), fn, fd);
+        ub += T(-0.5) * cbar[o] / Gb * Bv * vb;
+        cbar_b[o] += T(-0.5) * u / Gb * Bv * vb;
+        T Bb = T(-0.5) * u * cbar[o] / Gb * vb;
+        aadd(xb, kRp, (fn + fd) * Bb);
+        aadd(xb, kLp, (fn + fd) * Bb);
+        aadd(xb, kRm, (-fn + fd) * Bb);
+        aadd(xb, kLm, (-fn + fd) * Bb);
+    }
+    if (tot) {
+        int64_t kR2 = ci(g, sh1(R, d, 1)), kL2 = ci(g, sh1(L, d, -1));
+        T xR2 = x[kR2], xL2 = x[kL2];
+        T nD = xR2 - xR - xL + xL2, dD = xR2 + xR + xL + xL2;
+        T Dv = fracv(iga, nD, dD, T(4));
+        frac_d(iga, nD, dD, T(4), fn, fd);
+        T cD = (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3);
+        ub += (T(6) * fabs(u) / Gb - T(6) * u * u / (Gb * Gb) - T(1)) / T(3) * Dv * vb;
+        T Db = cD * vb;
+        aadd(xb, kR2, (fn + fd) * Db);
+        aadd(xb, kR, (-fn + fd) * Db);
+        aadd(xb, kL, (-fn + fd) * Db);
+        aadd(xb, kL2, (fn + fd) * Db);
+        for (int o = 0; o < g.nd; o++) {
+            if (o == d) continue;
+            int64_t kRp = ci(g, sh1(R, o, 1)), kLp = ci(g, sh1(L, o, 1));
+            int64_t kRm = ci(g, sh1(R, o, -1)), kLm = ci(g, sh1(L, o, -1));
+            T a = x[kRp], b = x[kLp], ee = x[kRm], f = x[kLm];
+            T nE = a - b - ee + f, dE = a + b + ee + f;
+            T Ev = fracv(iga, nE, dE, T(4));
+            frac_d(iga, nE, dE, T(4), fn, fd);
+            T cE = fabs(u) * cbar[o] / Gb - T(2) * u * u * cbar[o] / (Gb * Gb);
+            ub += (sgnv(u) * cbar[o] / Gb - T(4) * u * cbar[o] / (Gb * Gb)) * Ev * vb;
+            cbar_b[o] += (fabs(u) / Gb - T(2) * u * u / (Gb * Gb)) * Ev * vb;
+            T Eb = cE * vb;
+            aadd(xb, kRp, (fn + fd) * Eb);
+            aadd(xb, kLp, (-fn + fd) * Eb);
+            aadd(xb, kRm, (-fn + fd) * Eb);
+            aadd(xb, kLm, (fn + fd) * Eb);
+        }
+        if (g.nd == 3) {
+            int o1 = (d == 0) ? 1 : 0;
+            int o2 = (d == 2) ? 1 : 2;
+            int64_t kp[2][4];
+            T num = T(0), den = T(0);
+            for (int s = 0; s < 2; s++) {
+                I3 S = s ? R : L;
+                kp[s][0] = ci(g, sh2(S, o1, 1, o2, 1));
+                kp[s][1] = ci(g, sh2(S, o1, -1, o2, 1));
+                kp[s][2] = ci(g, sh2(S, o1, 1, o2, -1));
+                kp[s][3] = ci(g, sh2(S, o1, -1, o2, -1));
+                T vpp = x[kp[s][0]], vmp = x[kp[s][1]], vpm = x[kp[s][2]], vmm = x[kp[s][3]];
+                num += vpp - vmp - vpm + vmm;
+                den += vpp + vmp + vpm + vmm;
+            }
+            T Tv = fracv(iga, num, den, T(8));
+            frac_d(iga, num, den, T(8), fn, fd);
+            T k = -(T(2) / T(3)) / (Gb * Gb);
+            ub += k * cbar[o1] * cbar[o2] * Tv * vb;
+            cbar_b[o1] += k * u * cbar[o2] * Tv * vb;
+            cbar_b[o2] += k * u * cbar[o1] * Tv * vb;
+            T Tb = k * u * cbar[o1] * cbar[o2] * vb;
+            const T sg[4] = {T(1), T(-1), T(-1), T(1)};
+            for (int s = 0; s < 2; s++)
+                for (int q = 0; q < 4; q++) aadd(xb, kp[s][q], (sg[q] * fn + fd) * Tb);
+        }
+    }
+    aadd(cb[d], wi(g, d, p), ub);
+    for (int o = 0; o < g.nd; o++) {
+        if (o == d || cbar_b[o] == T(0)) continue;
+        T q = T(0.25) * cbar_b[o];
+        aadd(cb[o], wi(g, o, L), q);
+        aadd(cb[o], wi(g, o, sh1(L, o, 1)), q);
+        aadd(cb[o], wi(g, o, R), q);
+        aadd(cb[o], wi(g, o, sh1(R, o, 1)), q);
+    }
+}
+
+// transpose of the limited velocity W = [V]+ up + [V]- dn at dimension-d walls
+template <typename T>
+__global__ void k_limit_adj(Geom g, int d, const T *__restrict__ V, const T *__restrict__ bup,
+                            const T *__restrict__ bdn, const T *__restrict__ Wb, T *Vb, T *bub,
+                            T *bdb)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    int64_t M = e[0] * e[1] * e[2];
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= M) return;
+    T wb = Wb[t];
+    if (wb == T(0)) return;
+    I3 p = unflat3(t, e);
+    I3 L = sh1(p, d, -1), R = p;
+    int64_t kL = ci(g, L), kR = ci(g, R);
+    T v = V[wi(g, d, p)];
+    T up = T(1), dn = T(1);
+    int wu = 0, wd = 0;
+    if (bdn[kL] < up) { up = bdn[kL]; wu = 1; }
+    if (bup[kR] < up) { up = bup[kR]; wu = 2; }
+    if (bup[kL] < dn) { dn = bup[kL]; wd = 1; }
+    if (bdn[kR] < dn) { dn = bdn[kR]; wd = 2; }
+    aadd(Vb, wi(g, d, p), ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb);
+    T upb = pos(v) * wb, dnb = neg(v) * wb;
+    if (wu == 1) aadd(bdb, kL, upb);
+    if (wu == 2) aadd(bub, kR, upb);
+    if (wd == 1) aadd(bub, kL, dnb);
+    if (wd == 2) aadd(bdb, kR, dnb);
+}
+
+// transpose of the limiter coefficients (bounds, in/out fluxes) per cell
+template <typename T>
+__global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
+                           const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
+                           const T *G, const T *__restrict__ bub, const T *__restrict__ bdb,
+                           T *xb, T *pnb, T *Vb0, T *Vb1, T *Vb2)
+{
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= N) return;
+    T bu_b = bub[t], bd_b = bdb[t];
+    if (bu_b == T(0) && bd_b == T(0)) return;
+    const bool iga = opts & OPT_IGA;
+    const T *V[3] = {V0, V1, V2};
+    T *Vb[3] = {Vb0, Vb1, Vb2};
+    I3 p = unflat3(t, g.n);
+    T mx = psi_n[t], mn = mx;
+    int64_t amx = t, amn = t;
+    int smx = 0, smn = 0;
+    T v = x[t];
+    if (v > mx) { mx = v; smx = 1; }
+    if (v < mn) { mn = v; smn = 1; }
+    for (int d = 0; d < g.nd; d++)
+        for (int s = -1; s <= 1; s += 2) {
+            int64_t kq = ci(g, sh1(p, d, s));
+            T a = psi_n[kq], b = x[kq];
+            if (a > mx) { mx = a; amx = kq; smx = 0; }
+            if (a < mn) { mn = a; amn = kq; smn = 0; }
+            if (b > mx) { mx = b; amx = kq; smx = 1; }
+            if (b < mn) { mn = b; amn = kq; smn = 1; }
+        }
+    T xi = v;
+    T fin = T(0), fout = T(0);
+    for (int d = 0; d < g.nd; d++) {
+        T vlo = V[d][wi(g, d, p)], vhi = V[d][wi(g, d, sh1(p, d, 1))];
+        T wm = iga ? T(1) : x[ci(g, sh1(p, d, -1))];
+        T wp = iga ? T(1) : x[ci(g, sh1(p, d, 1))];
+        T wc = iga ? T(1) : xi;
+        fin += pos(vlo) * wm - neg(vhi) * wp;
+        fout += pos(vhi) * wc - neg(vlo) * wc;
+    }
+    T Gi = G ? G[t] : T(1);
+    T finb = T(0), foutb = T(0), mxb = T(0), mnb = T(0), xib = T(0);
+    if (fin > T(0) && bu_b != T(0)) {
+        mxb += Gi / fin * bu_b;
+        xib -= Gi / fin * bu_b;
+        finb -= Gi * (mx - xi) / (fin * fin) * bu_b;
+    }
+    if (fout > T(0) && bd_b != T(0)) {
+        xib += Gi / fout * bd_b;
+        mnb -= Gi / fout * bd_b;
+        foutb -= Gi * (xi - mn) / (fout * fout) * bd_b;
+    }
+    aadd(smx ? xb : pnb, amx, mxb);
+    aadd(smn ? xb : pnb, amn, mnb);
+    for (int d = 0; d < g.nd; d++) {
+        int64_t wlo = wi(g, d, p), whi = wi(g, d, sh1(p, d, 1));
+        int64_t km = ci(g, sh1(p, d, -1)), kp = ci(g, sh1(p, d, 1));
+        T vlo = V[d][wlo], vhi = V[d][whi];
+        T wm = iga ? T(1) : x[km];
+        T wp = iga ? T(1) : x[kp];
+        T wc = iga ? T(1) : xi;
+        aadd(Vb[d], wlo, (vlo > T(0) ? wm : T(0)) * finb - (vlo < T(0) ? wc : T(0)) * foutb);
+        aadd(Vb[d], whi, (vhi > T(0) ? wc : T(0)) * foutb - (vhi < T(0) ? wp : T(0)) * finb);
+        if (!iga) {
+            aadd(xb, km, pos(vlo) * finb);
+            aadd(xb, kp, -neg(vhi) * finb);
+            xib += (pos(vhi) - neg(vlo)) * foutb;
+        }
+    }
+    aadd(xb, t, xib);
+}
+
+int64_t ncells(const Geom &g) { return g.n[0] * g.n[1] * g.n[2]; }
+
+int64_t nwalls(const Geom &g, int d)
+{
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    return e[0] * e[1] * e[2];
+}
+
+size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// workspace carving for the adjoint (shared by sizing and use)
+template <typename T> struct AdjWs {
+    T *ck;          // checkpoints
+    T *seg;         // states of one segment
+    T *X[8];        // pass inputs 1..n_iters-1 (X[0] is the state itself)
+    T *V[8][3];     // raw pseudo-velocities of passes 2..n
+    T *W[8][3];     // limited pseudo-velocities (== V without the limiter)
+    T *bu[8], *bd[8];
+    T *yb, *xb, *pnb, *bub, *bdb;
+    T *Ab[3], *Vb[3], *Cb[3];
+    T *tmp;         // output of a recomputed step
+    size_t bytes;
+};
+
+template <typename T>
+AdjWs<T> carve_adj(const Geom &g, int n_iters, bool fct, int n_steps, int ckpt, char *base)
+{
+    AdjWs<T> w;
+    size_t off = 0;
+    auto take = [&](size_t n) -> T * {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += up256(n * sizeof(T));
+        return p;
+    };
+    int64_t N = ncells(g);
+    int nck = (n_steps + ckpt - 1) / ckpt;
+    w.ck = take((size_t)N * nck);
+    w.seg = take((size_t)N * ckpt);
+    for (int p = 0; p < 8; p++) {
+        w.X[p] = nullptr;
+        w.bu[p] = w.bd[p] = nullptr;
+        for (int d = 0; d < 3; d++) w.V[p][d] = w.W[p][d] = nullptr;
+    }
+    for (int p = 1; p < n_iters; p++) {
+        w.X[p] = take(N);
+        for (int d = 0; d < g.nd; d++) {
+            w.V[p][d] = take(nwalls(g, d));
+            w.W[p][d] = fct ? take(nwalls(g, d)) : w.V[p][d];
+        }
+        if (fct) {
+            w.bu[p] = take(N);
+            w.bd[p] = take(N);
+        }
+    }
+    w.yb = take(N);
+    w.xb = take(N);
+    w.pnb = take(N);
+    w.bub = take(N);
+    w.bdb = take(N);
+    w.tmp = take(N);
+    for (int d = 0; d < 3; d++) w.Ab[d] = w.Vb[d] = w.Cb[d] = nullptr;
+    for (int d = 0; d < g.nd; d++) {
+        w.Ab[d] = take(nwalls(g, d));
+        w.Vb[d] = take(nwalls(g, d));
+        w.Cb[d] = take(nwalls(g, d));
+    }
+    w.bytes = off;
+    return w;
+}
+
+template <typename T> hipError_t fill(T *a, int64_t n, hipStream_t s)
+{
+    k_fill<T><<<(unsigned)cdiv(n, B), B, 0, s>>>(a, n, T(0));
+    return hipGetLastError();
+}
+
+// forward recompute of one step from psi_n, keeping the pass records;
+// writes the step's result to out when out != nullptr
+template <typename T>
+hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out, hipStream_t s)
+{
+    const Geom &g = a.g;
+    const bool fct = a.opts & OPT_FCT, iga = a.opts & OPT_IGA;
+    const int n = a.n_iters;
+    hipError_t e;
+    T *first = n > 1 ? w.X[1] : out;
+    if (first) {
+        e = launch_donor<T>(g, psi_n, a.c, a.G, 0, first, s);
+        if (e != hipSuccess) return e;
+    }
+    for (int it = 2; it <= n; it++) {
+        const T *x = w.X[it - 1];
+        // advector of the previous pass: the input one for pass 2
+        const T *cin[3];
+        for (int d = 0; d < 3; d++) cin[d] = (it == 2) ? a.c[d] : w.W[it - 2][d];
+        T *V[3] = {w.V[it - 1][0], w.V[it - 1][1], w.V[it - 1][2]};
+        T *W[3] = {w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2]};
+        e = launch_pseudo<T>(g, a.opts, x, cin, a.G, V, s);
+        if (e != hipSuccess) return e;
+        if (fct) {
+            e = launch_fct<T>(g, a.opts, psi_n, x, V, a.G, w.bu[it - 1], w.bd[it - 1], W, s);
+            if (e != hipSuccess) return e;
+        }
+        T *y = (it < n) ? w.X[it] : out;
+        if (y) {
+            e = launch_donor<T>(g, x, W, a.G, iga ? 1 : 0, y, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipGetLastError();
+}
+
+// reverse of one step: w.yb = dJ/dpsi_{n+1} on entry, dJ/dpsi_n on exit;
+// w.Cb accumulates dJ/dc
+template <typename T>
+hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStream_t s)
+{
+    const Geom &g = a.g;
+    const bool fct = a.opts & OPT_FCT, iga = a.opts & OPT_IGA;
+    const int n = a.n_iters;
+    const int64_t N = ncells(g);
+    const unsigned cb = (unsigned)cdiv(N, B);
+    hipError_t e = record_step<T>(a, w, psi_n, nullptr, s);
+    if (e != hipSuccess) return e;
+    e = fill<T>(w.pnb, N, s);
+    for (int d = 0; d < g.nd; d++) e = fill<T>(w.Ab[d], nwalls(g, d), s);
+    for (int it = n; it >= 2; it--) {
+        const T *x = w.X[it - 1];
+        e = fill<T>(w.xb, N, s);
+        // corrective donor-cell pass
+        k_donor_adj<T><<<cb, B, 0, s>>>(g, x, w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2], a.G,
+                                        iga ? 1 : 0, w.yb, w.xb, w.Ab[0], w.Ab[1], w.Ab[2]);
+        // limiter
+        for (int d = 0; d < g.nd; d++) e = fill<T>(w.Vb[d], nwalls(g, d), s);
+        if (fct) {
+            e = fill<T>(w.bub, N, s);
+            e = fill<T>(w.bdb, N, s);
+            for (int d = 0; d < g.nd; d++)
+                k_limit_adj<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
+                    g, d, w.V[it - 1][d], w.bu[it - 1], w.bd[it - 1], w.Ab[d], w.Vb[d], w.bub,
+                    w.bdb);
+            k_beta_adj<T><<<cb, B, 0, s>>>(g, a.opts, psi_n, x, w.V[it - 1][0], w.V[it - 1][1],
+                                           w.V[it - 1][2], a.G, w.bub, w.bdb, w.xb, w.pnb,
+                                           w.Vb[0], w.Vb[1], w.Vb[2]);
+        } else {
+            for (int d = 0; d < g.nd; d++)
+                k_copy<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(w.Vb[d], w.Ab[d],
+                                                                        nwalls(g, d));
+        }
+        // pseudo-velocity: to x and to the previous pass's advector
+        for (int d = 0; d < g.nd; d++) e = fill<T>(w.Ab[d], nwalls(g, d), s);
+        const T *cin[3];
+        for (int d = 0; d < 3; d++) cin[d] = (it == 2) ? a.c[d] : w.W[it - 2][d];
+        for (int d = 0; d < g.nd; d++)
+            k_pseudo_adj<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
+                g, d, a.opts, x, cin[0], cin[1], cin[2], a.G, w.Vb[d], w.xb, w.Ab[0], w.Ab[1],
+                w.Ab[2]);
+        if (it == 2)
+            for (int d = 0; d < g.nd; d++) {
+                k_add<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(w.Cb[d], w.Ab[d],
+                                                                       nwalls(g, d));
+                e = fill<T>(w.Ab[d], nwalls(g, d), s);
+            }
+        T *t = w.yb;
+        w.yb = w.xb;
+        w.xb = t;
+    }
+    // donor-cell pass of the input field with the input advector
+    e = fill<T>(w.xb, N, s);
+    k_donor_adj<T><<<cb, B, 0, s>>>(g, psi_n, a.c[0], a.c[1], a.c[2], a.G, 0, w.yb, w.xb, w.Cb[0],
+                                    w.Cb[1], w.Cb[2]);
+    k_add<T><<<cb, B, 0, s>>>(w.xb, w.pnb, N);
+    T *t = w.yb;
+    w.yb = w.xb;
+    w.xb = t;
+    (void)e;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t adj_extra_bytes(const Geom &g, size_t es, int n_iters, int n_steps, int ckpt_every)
+{
+    // FCT on/off changes the layout; size for the larger one
+    if (es == 8) return carve_adj<double>(g, n_iters, true, n_steps, ckpt_every, nullptr).bytes;
+    return carve_adj<float>(g, n_iters, true, n_steps, ckpt_every, nullptr).bytes;
+}
+
+template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
+{
+    const Geom &g = a.g;
+    const int64_t N = ncells(g);
+    const size_t nb = (size_t)N * sizeof(T);
+    AdjWs<T> w = carve_adj<T>(g, a.n_iters, (a.opts & OPT_FCT) != 0, a.n_steps, a.ckpt_every,
+                              a.ws);
+    hipError_t e;
+    // forward sweep: checkpoint at the start of every segment
+    const int ck = a.ckpt_every;
+    const int nck = (a.n_steps + ck - 1) / ck;
+    T *cur = w.seg, *nxt = w.tmp;
+    e = hipMemcpyAsync(cur, a.psi0, nb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    for (int st = 0; st < a.n_steps; st++) {
+        if (st % ck == 0) {
+            e = hipMemcpyAsync(w.ck + (size_t)(st / ck) * N, cur, nb, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        if (st == a.n_steps - 1) break;   // the final state is not needed
+        e = record_step<T>(a, w, cur, nxt, s);
+        if (e != hipSuccess) return e;
+        T *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    for (int d = 0; d < g.nd; d++) {
+        e = fill<T>(w.Cb[d], nwalls(g, d), s);
+        if (e != hipSuccess) return e;
+    }
+    e = hipMemcpyAsync(w.yb, a.lambda_T, nb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    // reverse sweep over segments
+    for (int sg = nck - 1; sg >= 0; sg--) {
+        int s0 = sg * ck;
+        int s1 = s0 + ck < a.n_steps ? s0 + ck : a.n_steps;
+        e = hipMemcpyAsync(w.seg, w.ck + (size_t)sg * N, nb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        for (int st = s0; st < s1 - 1; st++) {
+            e = record_step<T>(a, w, w.seg + (size_t)(st - s0) * N,
+                               w.seg + (size_t)(st - s0 + 1) * N, s);
+            if (e != hipSuccess) return e;
+        }
+        for (int st = s1 - 1; st >= s0; st--) {
+            e = reverse_step<T>(a, w, w.seg + (size_t)(st - s0) * N, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    e = hipMemcpyAsync(a.grad_psi0, w.yb, nb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    for (int d = 0; d < g.nd; d++) {
+        e = hipMemcpyAsync(a.grad_c[d], w.Cb[d], nwalls(g, d) * sizeof(T),
+                           hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
 }
 
 template hipError_t adjoint_run<float>(const AdjArgs<float> &, hipStream_t);

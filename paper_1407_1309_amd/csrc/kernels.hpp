@@ -25,6 +25,18 @@ template <typename T> struct StagedArgs {
 
 template <typename T> hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s);
 
+// single stages of the staged path (arrays as in StagedArgs)
+template <typename T>
+hipError_t launch_donor(const Geom &g, const T *x, const T *const c[3], const T *G,
+                        int flux_is_vel, T *out, hipStream_t s);
+template <typename T>
+hipError_t launch_pseudo(const Geom &g, unsigned opts, const T *x, const T *const c[3],
+                         const T *G, T *const V[3], hipStream_t s);
+template <typename T>
+hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
+                      const T *const V[3], const T *G, T *bup, T *bdn, T *const W[3],
+                      hipStream_t s);
+
 // Diagnostics: per-block partials into `part` (4 doubles per block, at most
 // diag_max_blocks blocks), then one finalising block writing out[0..3] =
 // (sum G psi, min, max, non-finite count as double).

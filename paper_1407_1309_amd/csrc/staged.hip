@@ -218,6 +218,55 @@ int64_t wall_count(const Geom &g, int d)
 
 }  // namespace
 
+// ---- single-stage launchers (used by the adjoint's forward recompute) ----
+template <typename T>
+hipError_t launch_donor(const Geom &g, const T *x, const T *const c[3], const T *G,
+                        int flux_is_vel, T *out, hipStream_t s)
+{
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    k_donor<T><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(g, x, c[0], c[1], c[2], G, flux_is_vel,
+                                                        out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pseudo(const Geom &g, unsigned opts, const T *x, const T *const c[3],
+                         const T *G, T *const V[3], hipStream_t s)
+{
+    for (int d = 0; d < g.nd; d++) {
+        unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), 256);
+        k_pseudo<T><<<wb, 256, 0, s>>>(g, d, opts, x, c[0], c[1], c[2], G, V[d]);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
+                      const T *const V[3], const T *G, T *bup, T *bdn, T *const W[3],
+                      hipStream_t s)
+{
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    k_fct_beta<T><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(g, opts, psi_n, x, V[0], V[1], V[2],
+                                                          G, bup, bdn);
+    for (int d = 0; d < g.nd; d++) {
+        unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), 256);
+        k_fct_limit<T><<<wb, 256, 0, s>>>(g, d, V[d], bup, bdn, W[d]);
+    }
+    return hipGetLastError();
+}
+
+#define MP_INST(T)                                                                            \
+    template hipError_t launch_donor<T>(const Geom &, const T *, const T *const[3], const T *, \
+                                        int, T *, hipStream_t);                               \
+    template hipError_t launch_pseudo<T>(const Geom &, unsigned, const T *, const T *const[3], \
+                                         const T *, T *const[3], hipStream_t);                \
+    template hipError_t launch_fct<T>(const Geom &, unsigned, const T *, const T *,            \
+                                      const T *const[3], const T *, T *, T *, T *const[3],    \
+                                      hipStream_t);
+MP_INST(float)
+MP_INST(double)
+#undef MP_INST
+
 // One full step psi_n -> psi_out through the staged kernels.
 template <typename T>
 hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s)

@@ -308,3 +308,32 @@ def step(psi, c, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1, kernel=KE
     p = Plan(tuple(psi.shape), dtype=psi.dtype, n_iters=n_iters, opts=opts, bc=bc,
              has_g=g is not None, device=psi.device, kernel=kernel)
     return p.step(psi, c, g=g, n_steps=n_steps)
+
+
+class MPDATAFunction(torch.autograd.Function):
+    """psi_T = n_steps MPDATA steps of psi0 with the advector c (G constant).
+
+    Backward runs mpdata_adv_adj (checkpointed reverse sweep in the library),
+    giving gradients with respect to psi0 and every advector component."""
+
+    @staticmethod
+    def forward(ctx, psi0, plan, n_steps, ckpt_every, g, *c):
+        psi = psi0.detach().clone().contiguous()
+        cs = [x.detach().contiguous() for x in c]
+        plan.step(psi, cs, g=g, n_steps=n_steps)
+        ctx.save_for_backward(psi0.detach(), *cs)
+        ctx.plan, ctx.n_steps, ctx.ckpt, ctx.g = plan, n_steps, ckpt_every, g
+        return psi
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        psi0, *c = ctx.saved_tensors
+        gpsi, gc = ctx.plan.adv_adj(psi0, c, grad_out.contiguous(), g=ctx.g,
+                                    n_steps=ctx.n_steps, ckpt_every=ctx.ckpt)
+        return (gpsi, None, None, None, None, *gc)
+
+
+def advance(psi0, c, plan, n_steps, ckpt_every=None, g=None):
+    """Differentiable n_steps advance (see MPDATAFunction); the plan must be
+    created with adj_steps >= n_steps and the same ckpt_every."""
+    return MPDATAFunction.apply(psi0, plan, int(n_steps), int(ckpt_every or n_steps), g, *c)
