@@ -148,6 +148,114 @@ def bench_single(args, torch, mpdata, synth, oracle):
     return out
 
 
+def bench_batched(args, torch, mpdata, synth, oracle):
+    """1024 independent 2-D periodic grids (sides 64..768), FP32, n_iters=2
+    with the limiter: one launch per step over every tile of every grid,
+    replayed from a HIP graph, against one launch per grid per step."""
+    K = args.steps if args.steps is not None else 100
+    W = args.warmup
+    shapes = synth.batch_shapes()
+    cases = synth.case_batch()
+    dev = torch.device("cuda:0")
+    bp = mpdata.BatchedPlan(shapes, dtype=torch.float32, n_iters=2, opts=mpdata.OPT_FCT,
+                            device=dev)
+    psi0 = bp.pack([c.psi for c in cases], "psi")
+    c0 = bp.pack([c.c[0] for c in cases], "c0")
+    c1 = bp.pack([c.c[1] for c in cases], "c1")
+    N = bp.n_psi
+    psi = psi0.clone()
+    bp.step(psi, c0, c1, n_steps=K, use_graph=True)       # capture + warm-up replay
+    secs = _time_steps(lambda k: bp.step(psi, c0, c1, n_steps=k, use_graph=True), K, torch)
+    pg = psi0.clone()
+    bp.step_per_grid(pg, c0, c1, n_steps=max(W, 1))
+    secs_pg = _time_steps(lambda k: bp.step_per_grid(pg, c0, c1, n_steps=k), K, torch)
+    ms = secs * 1e3 / K
+    alg = 4 * (2 * N + bp.n_c0 - sum(b for a, b in shapes) + bp.n_c1 - sum(a for a, b in shapes))
+    achieved = alg / (ms / 1e3) / 1e9
+    out = {
+        "metric": "Mcell-steps/s", "value": round(N * K / secs / 1e6, 3), "unit": "Mcell-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "batched_1024x2d_periodic_64to768_fct_iters2", "grids": len(shapes),
+                   "cells": N, "launch": "one launch per step, HIP graph", "parallelism": "single GPU"},
+        "per_grid_launches": {"value": round(N * K / secs_pg / 1e6, 3), "unit": "Mcell-steps/s",
+                              "ms_per_step": round(secs_pg * 1e3 / K, 6)},
+        "speedup_vs_per_grid": round(secs_pg / secs, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": _traffic_entry("mpdata_fused2d_batched", "batched_f32"),
+                     "alg_bytes_per_launch": alg, "kernel": "mpdata_fused2d_batched"},
+    }
+    if not args.no_cpu:
+        order = np.argsort([a * b for a, b in shapes])[:4]
+        t0 = time.perf_counter()
+        cells = 0
+        for i in order:
+            cs = cases[int(i)]
+            oracle.step(cs.psi.astype(np.float32).astype(np.float64),
+                        [x.astype(np.float32).astype(np.float64) for x in cs.c], n_iters=2,
+                        opts=1, n_steps=20)
+            cells += cs.psi.size * 20
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(cells / dt / 1e6, 4), "unit": "Mcell-steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "20 steps of the 4 smallest grids, FP64, one thread"}
+    return out
+
+
+def bench_adjoint(args, torch, mpdata, synth, oracle):
+    """Gradient of J = 1/2 ||psi_T - psi_obs||^2 w.r.t. psi0 and the advector
+    through 200 steps of 2-D periodic 1024^2 FP64, n_iters=2 with the limiter,
+    checkpoint every 20 steps."""
+    w = synth.case_adjoint()
+    case = w["case"]
+    K = args.steps if args.steps is not None else case.n_steps
+    ck = min(20, K)
+    dev = torch.device("cuda:0")
+    plan = mpdata.Plan(case.psi.shape, n_iters=2, opts=mpdata.OPT_FCT,
+                       kernel=mpdata.KERNEL_STAGED, adj_steps=K, ckpt_every=ck, device=dev)
+    psi = torch.from_numpy(case.psi).to(dev)
+    c = [torch.from_numpy(x).to(dev) for x in case.c]
+    obs = torch.from_numpy(w["psi_perturbed"]).to(dev)
+    plan.step(obs, [torch.from_numpy(x).to(dev) for x in w["c_perturbed"]], n_steps=K)
+    out = psi.clone()
+    plan.step(out, c, n_steps=K)
+    lam = (out - obs).contiguous()
+    plan.adv_adj(psi, c, lam, n_steps=min(K, 2 * ck), ckpt_every=ck)     # warm-up
+    t = {}
+
+    def run(k):
+        t["g"] = plan.adv_adj(psi, c, lam, n_steps=k, ckpt_every=ck)
+
+    secs = _time_steps(run, K, torch)
+    N = psi.numel()
+    ms = secs * 1e3 / K
+    alg = 8 * 16 * N      # bytes per cell-step of the gradient (see DESIGN.md)
+    achieved = alg / (ms / 1e3) / 1e9
+    res = {
+        "metric": "Mcell-steps/s", "value": round(N * K / secs / 1e6, 3), "unit": "Mcell-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": 1, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "adjoint_2d_periodic_1024x1024_fct_iters2_ckpt20",
+                   "checkpoint_every": ck, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": alg, "kernel": "whole reverse step"},
+    }
+    if not args.no_cpu:
+        sub = synth.case_2d(n=128, seed=5, sigma=(2.0, 8.0), n_iters=2, n_steps=10)
+        lam_s = np.random.default_rng(0).normal(size=sub.psi.shape)
+        t0 = time.perf_counter()
+        oracle.adjoint(sub.psi, sub.c, lam_s, n_iters=2, opts=1, n_steps=10, ckpt_every=5)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(sub.psi.size * 10 / dt / 1e6, 4),
+                               "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": "gradient through 10 steps of a 128^2 grid, FP64, one thread"}
+    return res
+
+
 def plan_uses_fused(plan, mpdata, requested):
     """Which step kernel the plan runs for the requested selection."""
     if requested == mpdata.KERNEL_STAGED:
@@ -170,7 +278,12 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
-    out = bench_single(args, torch, mpdata, synth, oracle)
+    if args.workload == "batched":
+        out = bench_batched(args, torch, mpdata, synth, oracle)
+    elif args.workload == "adjoint":
+        out = bench_adjoint(args, torch, mpdata, synth, oracle)
+    else:
+        out = bench_single(args, torch, mpdata, synth, oracle)
     print(json.dumps(out), flush=True)
 
 
