@@ -108,6 +108,18 @@ int mpdata_set_stream(mpdata_plan *plan, void *hip_stream);
  * MPDATA_EUNSUPPORTED when no fused kernel covers the plan. */
 int mpdata_set_kernel(mpdata_plan *plan, int kernel);
 
+/* Rows per wavefront chunk of the fused 2-D kernel (0 = built-in default).
+ * Results do not depend on it (bit for bit); only the speed does. */
+int mpdata_set_tile_rows(mpdata_plan *plan, int rows);
+
+/* Autotuner: time the fused step on the caller's inputs for a set of chunk
+ * lengths (psi is read, not modified; results go to workspace) and keep the
+ * fastest in the plan.  *out_tile_rows receives the choice (0 when the plan
+ * runs the staged path, which has nothing to tune).  Waits for completion. */
+int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g,
+                    const void *c0, const void *c1, const void *c2,
+                    int *out_tile_rows);
+
 /* Advance psi (in place) by n_steps steps (n_steps >= 0) with the advector
  * c0..c2 held fixed over the call (the caller passes the advector at the
  * intermediate time level n+1/2, Sect. 3.1.1).  c_d must be non-NULL for

@@ -142,6 +142,7 @@ struct mpdata_plan {
     size_t ws_bytes;
     hipStream_t stream;
     int kernel;
+    int tile_rows = 0;   // fused kernel rows per wavefront chunk (0 = default)
     Layout L;
     // batched plans
     bool batched = false;
@@ -165,7 +166,7 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
 {
     hipError_t e;
     if (fused) {
-        mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1]};
+        mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1], p->tile_rows};
         e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, G,
                                 p->stream);
     } else {
@@ -281,6 +282,71 @@ int mpdata_set_stream(mpdata_plan *plan, void *hip_stream)
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     plan->stream = (hipStream_t)hip_stream;
     return MPDATA_OK;
+}
+
+int mpdata_set_tile_rows(mpdata_plan *plan, int rows)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (rows < 0 || rows > (1 << 20)) return fail(MPDATA_EINVAL, "tile rows %d out of range", rows);
+    plan->tile_rows = rows;
+    return MPDATA_OK;
+}
+
+int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g, const void *c0,
+                    const void *c1, const void *c2, int *out_tile_rows)
+{
+    if (!plan || !psi || !out_tile_rows) return fail(MPDATA_EINVAL, "NULL argument");
+    if (plan->batched) return fail(MPDATA_EINVAL, "autotune needs a single-grid plan");
+    *out_tile_rows = plan->tile_rows;
+    if (!use_fused(plan)) return MPDATA_OK;   // staged path: nothing to tune
+    const void *c[3] = {c0, c1, c2};
+    for (int d = 0; d < plan->desc.n_dims; d++)
+        if (!c[d]) return fail(MPDATA_EINVAL, "c%d is NULL", d);
+    static const int cand[] = {16, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(MPDATA_EHIP, "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(MPDATA_EHIP, "hipEventCreate");
+    }
+    int saved = plan->tile_rows, best = 0;
+    float best_ms = 0.0f;
+    int rc = MPDATA_OK;
+    for (int k = 0; k < (int)(sizeof cand / sizeof cand[0]); k++) {
+        int th = cand[k];
+        if (th > plan->g.n[0] && k > 0) break;
+        plan->tile_rows = th;
+        const int reps = 5;
+        for (int r = 0; r <= reps && rc == MPDATA_OK; r++) {
+            if (r == 1) (void)hipEventRecord(e0, plan->stream);
+            if (plan->desc.dtype == MPDATA_F64)
+                rc = one_step<double>(plan, (const double *)psi, (double *)plan->L.psi_alt,
+                                      (const double *)g, (const double *)c0, (const double *)c1,
+                                      (const double *)c2, true);
+            else
+                rc = one_step<float>(plan, (const float *)psi, (float *)plan->L.psi_alt,
+                                     (const float *)g, (const float *)c0, (const float *)c1,
+                                     (const float *)c2, true);
+        }
+        if (rc) break;
+        (void)hipEventRecord(e1, plan->stream);
+        hipError_t e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune timing");
+            break;
+        }
+        if (best == 0 || ms < best_ms) {
+            best = th;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->tile_rows = rc == MPDATA_OK ? best : saved;
+    *out_tile_rows = plan->tile_rows;
+    return rc;
 }
 
 int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0, const void *c1,
@@ -552,7 +618,7 @@ hipError_t per_grid_launches(mpdata_plan *p, T *psi, const T *c0, const T *c1, i
             cur = ga;
             nxt = gp;
         }
-        mp::Fused2DShape sh{G.n0, G.n1, p->desc.bc[0], p->desc.bc[1]};
+        mp::Fused2DShape sh{G.n0, G.n1, p->desc.bc[0], p->desc.bc[1], 0};
         for (int s = 0; s < n_steps; s++) {
             e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, cur, nxt, g0, g1, nullptr,
                                     p->stream);

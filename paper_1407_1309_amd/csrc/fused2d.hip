@@ -201,18 +201,16 @@ template <int NI, bool FCT> struct Cfg {
 constexpr int PF = 2;
 
 template <typename T, int NI, bool FCT>
-__device__ __forceinline__ void strip_body(int64_t n0, int64_t n1, const T *__restrict__ psi_n,
+__device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__ psi_n,
                                            T *__restrict__ psi_out, const T *__restrict__ c0,
-                                           const T *__restrict__ c1, int64_t jstrip0, int64_t i0,
-                                           int64_t i1)
+                                           const T *__restrict__ c1, int jstrip0, int i0, int i1)
 {
     using C = Cfg<NI, FCT>;
     const int lane = threadIdx.x & (WAVE - 1);
     // global column of this lane (may lie outside [0, n1) in the halo)
-    int64_t col = jstrip0 - C::H + lane;
-    int64_t jj = col % n1;
+    const int col = jstrip0 - C::H + lane;
+    int jj = col % n1;
     if (jj < 0) jj += n1;
-    const int64_t ld1 = n1 + 1;
 
     T pq[C::QP];
 #pragma unroll
@@ -222,26 +220,39 @@ __device__ __forceinline__ void strip_body(int64_t n0, int64_t n1, const T *__re
 #pragma unroll
     for (int k = 0; k < C::NP; k++) ps[k].init();
 
-    const int64_t t_begin = i0 - C::LAG - 1;
-    const int64_t t_end = i1 - 1 + C::LAG;    // inclusive
-    // row index (mod n0) of the row loaded at iteration t
-    int64_t r = t_begin % n0;
-    if (r < 0) r += n0;
+    const int t_begin = i0 - C::LAG - 1;
+    const int t_end = i1 - 1 + C::LAG;    // inclusive
+    // row (mod n0) of the next row to load, and its row pointers
+    int rr = t_begin % n0;
+    if (rr < 0) rr += n0;
+    const int64_t ld1 = (int64_t)n1 + 1;
+    const T *prow = psi_n + (int64_t)rr * n1;
+    const T *c0row = c0 + (int64_t)rr * n1;
+    const T *c1row = c1 + (int64_t)rr * ld1;
 
     // prefetch queue: rows t .. t+PF-1
     T fp[PF], f0[PF], f1[PF];
-    int64_t rr = r;
 #pragma unroll
     for (int k = 0; k < PF; k++) {
-        fp[k] = psi_n[rr * n1 + jj];
-        f0[k] = c0[rr * n1 + jj];
-        f1[k] = c1[rr * ld1 + jj];
-        rr = (rr + 1 == n0) ? 0 : rr + 1;
+        fp[k] = prow[jj];
+        f0[k] = c0row[jj];
+        f1[k] = c1row[jj];
+        if (++rr == n0) {
+            rr = 0;
+            prow = psi_n;
+            c0row = c0;
+            c1row = c1;
+        } else {
+            prow += n1;
+            c0row += n1;
+            c1row += ld1;
+        }
     }
 
     const bool out_lane = lane >= C::H && lane < WAVE - C::H && col < n1;
+    T *orow = psi_out + (int64_t)i0 * n1 + (out_lane ? col : 0);
 
-    for (int64_t t = t_begin; t <= t_end; t++) {
+    for (int t = t_begin; t <= t_end; t++) {
         T p_new = fp[0], c0_new = f0[0], c1_new = f1[0];
 #pragma unroll
         for (int k = 0; k < PF - 1; k++) {
@@ -249,10 +260,19 @@ __device__ __forceinline__ void strip_body(int64_t n0, int64_t n1, const T *__re
             f0[k] = f0[k + 1];
             f1[k] = f1[k + 1];
         }
-        fp[PF - 1] = psi_n[rr * n1 + jj];
-        f0[PF - 1] = c0[rr * n1 + jj];
-        f1[PF - 1] = c1[rr * ld1 + jj];
-        rr = (rr + 1 == n0) ? 0 : rr + 1;
+        fp[PF - 1] = prow[jj];
+        f0[PF - 1] = c0row[jj];
+        f1[PF - 1] = c1row[jj];
+        if (++rr == n0) {
+            rr = 0;
+            prow = psi_n;
+            c0row = c0;
+            c1row = c1;
+        } else {
+            prow += n1;
+            c0row += n1;
+            c1row += ld1;
+        }
 
 #pragma unroll
         for (int k = 0; k < C::QP - 1; k++) pq[k] = pq[k + 1];
@@ -281,17 +301,16 @@ __device__ __forceinline__ void strip_body(int64_t n0, int64_t n1, const T *__re
             y = yk;
         }
 
-        int64_t orow = t - C::LAG;
-        if (orow >= i0 && out_lane) {
-            int64_t ro = orow % n0;
-            psi_out[ro * n1 + col] = y;
+        if (t - C::LAG >= i0) {
+            if (out_lane) *orow = y;
+            orow += n1;
         }
     }
 }
 
 template <typename T, int NI, bool FCT>
-__global__ void __launch_bounds__(WAVE) k_fused2d(int64_t n0, int64_t n1, int64_t th,
-                                                  int strips, const T *__restrict__ psi_n,
+__global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int strips,
+                                                  const T *__restrict__ psi_n,
                                                   T *__restrict__ psi_out,
                                                   const T *__restrict__ c0,
                                                   const T *__restrict__ c1)
@@ -299,14 +318,14 @@ __global__ void __launch_bounds__(WAVE) k_fused2d(int64_t n0, int64_t n1, int64_
     using C = Cfg<NI, FCT>;
     int b = blockIdx.x;
     int strip = b % strips, chunk = b / strips;
-    int64_t i0 = (int64_t)chunk * th;
-    int64_t i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT>(n0, n1, psi_n, psi_out, c0, c1, (int64_t)strip * C::OW, i0, i1);
+    int i0 = chunk * th;
+    int i1 = i0 + th < n0 ? i0 + th : n0;
+    strip_body<T, NI, FCT>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1);
 }
 
 template <typename T, int NI, bool FCT>
 __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__restrict__ grids,
-                                                          int n_grids, int64_t th,
+                                                          int n_grids, int th,
                                                           const T *__restrict__ psi_n,
                                                           T *__restrict__ psi_out,
                                                           const T *__restrict__ c0,
@@ -326,14 +345,15 @@ __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__res
     const BatchGrid g = grids[lo];
     int local = b - g.tile_begin;
     int strip = local % g.tiles_w, chunk = local / g.tiles_w;
-    int64_t i0 = (int64_t)chunk * th;
-    int64_t i1 = i0 + th < g.n0 ? i0 + th : g.n0;
-    strip_body<T, NI, FCT>(g.n0, g.n1, psi_n + g.off_psi, psi_out + g.off_psi, c0 + g.off_c0,
-                           c1 + g.off_c1, (int64_t)strip * C::OW, i0, i1);
+    int n0 = (int)g.n0, n1 = (int)g.n1;
+    int i0 = chunk * th;
+    int i1 = i0 + th < n0 ? i0 + th : n0;
+    strip_body<T, NI, FCT>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi, c0 + g.off_c0,
+                           c1 + g.off_c1, strip * C::OW, i0, i1);
 }
 
-// rows per chunk: enough waves to fill the chip (about 4 per SIMD for the
-// 2048^2 grid) while keeping the warm-up rows a small fraction
+// default rows per chunk (when not tuned): about two waves per SIMD, so the
+// chip is full while the warm-up rows stay a modest fraction
 int64_t rows_per_chunk(int64_t n0, int64_t strips)
 {
     int64_t target_waves = 2048;
@@ -350,11 +370,12 @@ hipError_t launch(const Fused2DShape &sh, const T *psi_n, T *psi_out, const T *c
 {
     using C = Cfg<NI, FCT>;
     int64_t strips = cdiv(sh.n1, C::OW);
-    int64_t th = rows_per_chunk(sh.n0, strips);
+    int64_t th = sh.tile_rows > 0 ? sh.tile_rows : rows_per_chunk(sh.n0, strips);
+    if (th > sh.n0) th = sh.n0;
     int64_t chunks = cdiv(sh.n0, th);
     int64_t blocks = strips * chunks;
-    k_fused2d<T, NI, FCT><<<(unsigned)blocks, WAVE, 0, s>>>(sh.n0, sh.n1, th, (int)strips,
-                                                           psi_n, psi_out, c0, c1);
+    k_fused2d<T, NI, FCT><<<(unsigned)blocks, WAVE, 0, s>>>((int)sh.n0, (int)sh.n1, (int)th,
+                                                           (int)strips, psi_n, psi_out, c0, c1);
     return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ hipError_t courant_launch(const Geom &g, const T *c0, const T *c1, const T *c2, 
 struct Fused2DShape {
     int64_t n0, n1;      // rows (slow), columns (fast)
     int bc0, bc1;
+    int tile_rows;       // rows per wavefront chunk; 0 = built-in default
 };
 
 // true if a fused kernel exists for this configuration

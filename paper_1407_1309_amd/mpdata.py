@@ -26,6 +26,7 @@ KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2
 
 EXPORTS = [
     "mpdata_workspace_bytes", "mpdata_init", "mpdata_set_stream", "mpdata_set_kernel",
+    "mpdata_set_tile_rows", "mpdata_autotune",
     "mpdata_step", "mpdata_diag", "mpdata_courant_max", "mpdata_adv_adj",
     "mpdata_adj_workspace_bytes", "mpdata_batched_workspace_bytes", "mpdata_batched_init",
     "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_destroy", "mpdata_last_error",
@@ -62,6 +63,8 @@ def lib():
         L.mpdata_init.argtypes = [DP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]
         L.mpdata_set_stream.argtypes = [_VP, _VP]
         L.mpdata_set_kernel.argtypes = [_VP, ctypes.c_int]
+        L.mpdata_set_tile_rows.argtypes = [_VP, ctypes.c_int]
+        L.mpdata_autotune.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int)]
         L.mpdata_step.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int]
         L.mpdata_diag.argtypes = [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -166,6 +169,21 @@ class Plan:
 
     def set_kernel(self, kernel):
         _check(lib().mpdata_set_kernel(self._handle, int(kernel)))
+
+    def set_tile_rows(self, rows):
+        _check(lib().mpdata_set_tile_rows(self._handle, int(rows)))
+
+    def autotune(self, psi, c, g=None):
+        """Pick the fused kernel's chunk length by timing candidates on these
+        inputs (psi is not modified); returns the chosen rows per chunk."""
+        self._check_cell(psi, "psi")
+        self._check_cell(g, "g")
+        cp = self._check_walls(c)
+        self._bind_stream()
+        out = ctypes.c_int(0)
+        _check(lib().mpdata_autotune(self._handle, _ptr(psi), _ptr(g), cp[0], cp[1], cp[2],
+                                     ctypes.byref(out)))
+        return out.value
 
     def _bind_stream(self):
         _check(lib().mpdata_set_stream(self._handle, _stream(self.device)))

@@ -213,3 +213,27 @@ def test_zero_steps_is_identity():
                                                           n_steps=0)
     torch.cuda.synchronize()
     assert torch.equal(p, q)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_fused_tile_rows_bitwise_independent(dtype):
+    """The fused kernel's chunk length changes only the speed: every setting
+    gives the same bits (and the staged path agrees to round-off)."""
+    case = synth.case_2d(shape=(300, 211), seed=4, sigma=(8.0, 30.0))
+    c = [dev(x, dtype) for x in case.c]
+    plan = mpdata.Plan(case.psi.shape, dtype=dtype, n_iters=3, opts=FCT)
+    ref = None
+    for rows in (0, 1, 7, 16, 33, 64, 299, 300, 1000):
+        plan.set_tile_rows(rows)
+        p = dev(case.psi, dtype)
+        plan.step(p, c, n_steps=3)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = p
+        assert torch.equal(p, ref), rows
+    tuned = plan.autotune(dev(case.psi, dtype), c)
+    assert tuned > 0
+    p = dev(case.psi, dtype)
+    plan.step(p, c, n_steps=3)
+    torch.cuda.synchronize()
+    assert torch.equal(p, ref)
