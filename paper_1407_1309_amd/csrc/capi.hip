@@ -192,12 +192,26 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
     return MPDATA_OK;
 }
 
+bool fused_available(const mpdata_plan *p)
+{
+    return mp::fused2d_supported(p->desc.n_dims, p->desc.n_iters, p->desc.opts, p->desc.has_g,
+                                 p->g.bc[0], p->g.bc[1]);
+}
+
+bool resident_available(const mpdata_plan *p)
+{
+    return mp::resident1d_supported(p->desc.n_dims, p->g.n[0], p->desc.dtype == MPDATA_F64,
+                                    p->desc.has_g);
+}
+
 bool use_fused(const mpdata_plan *p)
 {
-    bool ok = mp::fused2d_supported(p->desc.n_dims, p->desc.n_iters, p->desc.opts,
-                                    p->desc.has_g, p->g.bc[0], p->g.bc[1]);
-    if (p->kernel == MPDATA_KERNEL_STAGED) return false;
-    return ok;
+    return p->kernel != MPDATA_KERNEL_STAGED && fused_available(p);
+}
+
+bool use_resident(const mpdata_plan *p)
+{
+    return p->kernel != MPDATA_KERNEL_STAGED && resident_available(p);
 }
 
 template <typename T>
@@ -205,6 +219,11 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
               int n_steps)
 {
     if (n_steps == 0) return MPDATA_OK;
+    if (use_resident(p)) {
+        hipError_t e = mp::resident1d_steps<T>(p->g.n[0], p->g.bc[0], p->desc.n_iters,
+                                               p->desc.opts, psi, c0, G, n_steps, p->stream);
+        return e == hipSuccess ? MPDATA_OK : hip_fail(e, "resident 1-D launch");
+    }
     bool fused = use_fused(p);
     int64_t N = cells_of(p->g);
     T *alt = (T *)p->L.psi_alt;
@@ -269,9 +288,7 @@ int mpdata_set_kernel(mpdata_plan *plan, int kernel)
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     if (kernel < MPDATA_KERNEL_AUTO || kernel > MPDATA_KERNEL_FUSED)
         return fail(MPDATA_EINVAL, "unknown kernel %d", kernel);
-    if (kernel == MPDATA_KERNEL_FUSED &&
-        !mp::fused2d_supported(plan->desc.n_dims, plan->desc.n_iters, plan->desc.opts,
-                               plan->desc.has_g, plan->g.bc[0], plan->g.bc[1]))
+    if (kernel == MPDATA_KERNEL_FUSED && !fused_available(plan) && !resident_available(plan))
         return fail(MPDATA_EUNSUPPORTED, "no fused kernel for this plan");
     plan->kernel = kernel;
     return MPDATA_OK;

@@ -64,6 +64,12 @@ template <typename T>
 hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
                         T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s);
 
+// ---- 1-D grid resident in LDS: all steps of a call in one launch --------
+bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g);
+template <typename T>
+hipError_t resident1d_steps(int64_t n, int bc, int n_iters, unsigned opts, T *psi, const T *c,
+                            const T *G, int n_steps, hipStream_t s);
+
 // ---- batched fused 2-D: one launch over all tiles of all grids ---------
 struct BatchGrid {
     int64_t n0, n1;

@@ -1,0 +1,188 @@
+// resident1d.hip -- 1-D MPDATA steps with the whole grid resident in LDS.
+//
+// A 1-D grid of up to a few hundred cells is far too small to fill the chip,
+// so its cost is launch latency.  One workgroup keeps psi, the advector, G
+// and every intermediate field in LDS and runs all n_steps of a call in a
+// single launch, stage by stage with workgroup barriers in between.  Every
+// option (tot, iga, fct, G, periodic / open) is supported.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mp {
+namespace {
+
+constexpr int RB = 512;            // threads
+constexpr size_t LDS_BYTES = 64 * 1024;
+
+__device__ inline int mc(int q, int n, int bc)
+{
+    if (bc == BC_PERIODIC) {
+        q %= n;
+        return q < 0 ? q + n : q;
+    }
+    return q < 0 ? 0 : (q >= n ? n - 1 : q);
+}
+
+__device__ inline int mw(int f, int n, int bc)
+{
+    if (bc == BC_PERIODIC) {
+        f %= n;
+        return f < 0 ? f + n : f;
+    }
+    return f < 0 ? 0 : (f > n ? n : f);
+}
+
+template <typename T> __device__ inline T rfrac(bool iga, T num, T den, T m)
+{
+    if (iga) return num / m;
+    return den == T(0) ? T(0) : num / den;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, unsigned opts,
+                                                   T *psi, const T *__restrict__ cin,
+                                                   const T *__restrict__ Gin, int n_steps)
+{
+    extern __shared__ char lds_raw[];
+    T *P = (T *)lds_raw;          // psi at the start of the step
+    T *X = P + n;                 // pass input
+    T *Y = X + n;                 // pass output
+    T *BU = Y + n;
+    T *BD = BU + n;
+    T *GG = BD + n;               // G (n values, only with Gin)
+    T *C = GG + (Gin ? n : 0);    // input advector (n+1)
+    T *W0 = C + (n + 1);          // three wall buffers
+    T *W1 = W0 + (n + 1);
+    T *W2 = W1 + (n + 1);
+    const bool fct = opts & OPT_FCT, iga = opts & OPT_IGA, tot = opts & OPT_TOT;
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < n; i += RB) {
+        P[i] = psi[i];
+        if (Gin) GG[i] = Gin[i];
+    }
+    for (int f = tid; f <= n; f += RB) C[f] = cin[f];
+    __syncthreads();
+
+    auto gv = [&](int i) -> T { return Gin ? GG[mc(i, n, bc)] : T(1); };
+
+    for (int step = 0; step < n_steps; step++) {
+        // donor-cell pass: P -> Y
+        for (int i = tid; i < n; i += RB) {
+            T ul = C[mw(i, n, bc)], uh = C[mw(i + 1, n, bc)];
+            T flo = pos(ul) * P[mc(i - 1, n, bc)] + neg(ul) * P[i];
+            T fhi = pos(uh) * P[i] + neg(uh) * P[mc(i + 1, n, bc)];
+            T acc = fhi - flo;
+            Y[i] = P[i] - (Gin ? acc / GG[i] : acc);
+        }
+        __syncthreads();
+        const T *cprev = C;
+        for (int it = 2; it <= n_iters; it++) {
+            // move Y into X; raw and limited velocities go to the two wall
+            // buffers that do not hold the previous pass's advector
+            for (int i = tid; i < n; i += RB) X[i] = Y[i];
+            T *cand[3] = {W0, W1, W2};
+            T *V = nullptr, *Wl = nullptr;
+            for (int k = 0; k < 3; k++) {
+                if (cand[k] == cprev) continue;
+                if (!V)
+                    V = cand[k];
+                else if (!Wl)
+                    Wl = cand[k];
+            }
+            __syncthreads();
+            // pseudo-velocity at every wall
+            for (int f = tid; f <= n; f += RB) {
+                int L = f - 1, R = f;
+                T u = cprev[mw(f, n, bc)];
+                T Gb = T(0.5) * (gv(L) + gv(R));
+                T xL = X[mc(L, n, bc)], xR = X[mc(R, n, bc)];
+                T v = (fabs(u) - u * u / Gb) * rfrac(iga, xR - xL, xR + xL, T(2));
+                if (tot) {
+                    T xR2 = X[mc(R + 1, n, bc)], xL2 = X[mc(L - 1, n, bc)];
+                    T D = rfrac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
+                    v += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) * D;
+                }
+                V[f] = v;
+            }
+            __syncthreads();
+            const T *adv = V;
+            if (fct) {
+                for (int i = tid; i < n; i += RB) {
+                    T xi = X[i];
+                    T mx = fmax(P[i], xi), mn = fmin(P[i], xi);
+                    for (int s = -1; s <= 1; s += 2) {
+                        int q = mc(i + s, n, bc);
+                        mx = fmax(fmax(mx, P[q]), X[q]);
+                        mn = fmin(fmin(mn, P[q]), X[q]);
+                    }
+                    T vlo = V[mw(i, n, bc)], vhi = V[mw(i + 1, n, bc)];
+                    T wm = iga ? T(1) : X[mc(i - 1, n, bc)];
+                    T wp = iga ? T(1) : X[mc(i + 1, n, bc)];
+                    T wc = iga ? T(1) : xi;
+                    T fin = pos(vlo) * wm - neg(vhi) * wp;
+                    T fout = pos(vhi) * wc - neg(vlo) * wc;
+                    T Gi = Gin ? GG[i] : T(1);
+                    BU[i] = fin > T(0) ? Gi * (mx - xi) / fin : T(1);
+                    BD[i] = fout > T(0) ? Gi * (xi - mn) / fout : T(1);
+                }
+                __syncthreads();
+                for (int f = tid; f <= n; f += RB) {
+                    int L = mc(f - 1, n, bc), R = mc(f, n, bc);
+                    T v = V[f];
+                    T up = fmin(fmin(T(1), BD[L]), BU[R]);
+                    T dn = fmin(fmin(T(1), BU[L]), BD[R]);
+                    Wl[f] = pos(v) * up + neg(v) * dn;
+                }
+                __syncthreads();
+                adv = Wl;
+            }
+            // corrective donor-cell pass: X -> Y
+            for (int i = tid; i < n; i += RB) {
+                T ul = adv[mw(i, n, bc)], uh = adv[mw(i + 1, n, bc)];
+                T flo, fhi;
+                if (iga) {
+                    flo = ul;
+                    fhi = uh;
+                } else {
+                    flo = pos(ul) * X[mc(i - 1, n, bc)] + neg(ul) * X[i];
+                    fhi = pos(uh) * X[i] + neg(uh) * X[mc(i + 1, n, bc)];
+                }
+                T acc = fhi - flo;
+                Y[i] = X[i] - (Gin ? acc / GG[i] : acc);
+            }
+            cprev = adv;
+            __syncthreads();
+        }
+        for (int i = tid; i < n; i += RB) P[i] = Y[i];
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += RB) psi[i] = P[i];
+}
+
+size_t lds_need(int n, size_t es, bool has_g) { return es * ((5 + (has_g ? 1 : 0)) * (size_t)n + 4 * ((size_t)n + 1)); }
+
+}  // namespace
+
+bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g)
+{
+    if (nd != 1 || n < 1 || n > (1 << 20)) return false;
+    return lds_need((int)n, dtype_is_f64 ? 8 : 4, has_g != 0) <= LDS_BYTES;
+}
+
+template <typename T>
+hipError_t resident1d_steps(int64_t n, int bc, int n_iters, unsigned opts, T *psi, const T *c,
+                            const T *G, int n_steps, hipStream_t s)
+{
+    size_t lds = lds_need((int)n, sizeof(T), G != nullptr);
+    if (lds > LDS_BYTES) return hipErrorInvalidValue;
+    k_resident1d<T><<<1, RB, lds, s>>>((int)n, bc, n_iters, opts, psi, c, G, n_steps);
+    return hipGetLastError();
+}
+
+template hipError_t resident1d_steps<float>(int64_t, int, int, unsigned, float *, const float *,
+                                            const float *, int, hipStream_t);
+template hipError_t resident1d_steps<double>(int64_t, int, int, unsigned, double *,
+                                             const double *, const double *, int, hipStream_t);
+
+}  // namespace mp

@@ -237,3 +237,20 @@ def test_fused_tile_rows_bitwise_independent(dtype):
     plan.step(p, c, n_steps=3)
     torch.cuda.synchronize()
     assert torch.equal(p, ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("opts", OPTS)
+def test_parity_1d_resident(opts, bc, dtype):
+    """1-D grids small enough for the LDS-resident kernel (all steps of a
+    call in one launch), every option, with and without G."""
+    n_iters = 2 if opts & IGA else 3
+    for with_g in (False, True):
+        psi, c, g = _inputs((300,), bc, opts, seed=40 + opts + bc, with_g=with_g)
+        if bc == 0:
+            c = [np.full(301, -0.37)]
+        psi, c, g = as_dtype(psi, dtype), [as_dtype(x, dtype) for x in c], as_dtype(g, dtype)
+        ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=25)
+        out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 25, kernel=mpdata.KERNEL_FUSED)
+        assert rel_l2(out, ref) <= TOL[dtype], with_g
