@@ -31,7 +31,7 @@ def _parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="2d",
-                    choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint"])
+                    choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint", "copy"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     return ap.parse_args()
@@ -258,6 +258,22 @@ def bench_adjoint(args, torch, mpdata, synth, oracle):
     return res
 
 
+def bench_copy(args, torch):
+    """Calibration for the HBM byte counters: a plain device copy of a known
+    size (256 MiB read + 256 MiB written per launch)."""
+    K = args.steps if args.steps is not None else 20
+    n = 256 * 1024 * 1024 // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    secs = _time_steps(lambda k: [b.copy_(a) for _ in range(k)], K, torch)
+    gbs = 2 * a.numel() * 8 * K / secs / 1e9
+    return {"metric": "copy GB/s", "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1,
+            "steps": K, "warmup": 1, "ms_per_step": round(secs * 1e3 / K, 6),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "copy_256MiB"}}
+
+
 def plan_uses_fused(plan, mpdata, requested):
     """Which step kernel the plan runs for the requested selection."""
     if requested == mpdata.KERNEL_STAGED:
@@ -280,7 +296,9 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
-    if args.workload == "batched":
+    if args.workload == "copy":
+        out = bench_copy(args, torch)
+    elif args.workload == "batched":
         out = bench_batched(args, torch, mpdata, synth, oracle)
     elif args.workload == "adjoint":
         out = bench_adjoint(args, torch, mpdata, synth, oracle)

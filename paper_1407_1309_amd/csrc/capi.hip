@@ -36,6 +36,9 @@ int fail(int code, const char *fmt, ...)
 
 int hip_fail(hipError_t e, const char *what)
 {
+    // the status code carries the failure; clear HIP's sticky last error so
+    // the caller's next runtime call does not report it again
+    (void)hipGetLastError();
     return fail(MPDATA_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -151,7 +154,10 @@ struct mpdata_plan {
     void *batch_alt = nullptr;
     int64_t batch_psi_total = 0, batch_c0_total = 0, batch_c1_total = 0;
     int batch_tiles = 0;
-    // graph cache (batched)
+    // graph cache (batched); graphs are captured on a library-owned stream
+    // (capture is not allowed on the legacy default stream) and launched on
+    // the plan's stream
+    hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     const void *g_key[3] = {nullptr, nullptr, nullptr};
@@ -681,11 +687,24 @@ int mpdata_step_batched(mpdata_plan *plan, void *psi, const void *c0, const void
             (void)hipGraphDestroy(plan->graph);
             plan->graph = nullptr;
         }
+        if (!plan->cap_stream) {
+            hipError_t e = hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                plan->cap_stream = nullptr;
+                return hip_fail(e, "hipStreamCreateWithFlags");
+            }
+        }
+        hipStream_t user = plan->stream;
+        plan->stream = plan->cap_stream;
         hipError_t e = hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        if (e != hipSuccess) {
+            plan->stream = user;
+            return hip_fail(e, "hipStreamBeginCapture");
+        }
         hipError_t le = launch();
         hipGraph_t gr = nullptr;
         e = hipStreamEndCapture(plan->stream, &gr);
+        plan->stream = user;
         if (le != hipSuccess) {
             if (gr) (void)hipGraphDestroy(gr);
             return hip_fail(le, "batched launch under capture");
@@ -726,6 +745,7 @@ void mpdata_destroy(mpdata_plan *plan)
     if (!plan) return;
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
 }
 
