@@ -26,26 +26,23 @@ namespace {
 constexpr int B = 256;
 
 struct I3 {
-    int64_t v[3];
+    int v[3];
 };
 
-__device__ inline I3 unflat3(int64_t t, const int64_t e[3])
+__device__ inline I3 unflat_i3(int64_t t, const int64_t e[3])
 {
     I3 p;
-    p.v[2] = t % e[2];
-    t /= e[2];
-    p.v[1] = t % e[1];
-    p.v[0] = t / e[1];
+    unflat3(t, e, p.v);
     return p;
 }
 
-__device__ inline I3 sh1(I3 p, int d, int64_t s)
+__device__ inline I3 sh1(I3 p, int d, int s)
 {
     p.v[d] += s;
     return p;
 }
 
-__device__ inline I3 sh2(I3 p, int d, int64_t s, int e, int64_t t)
+__device__ inline I3 sh2(I3 p, int d, int s, int e, int t)
 {
     p.v[d] += s;
     p.v[e] += t;
@@ -54,20 +51,21 @@ __device__ inline I3 sh2(I3 p, int d, int64_t s, int e, int64_t t)
 
 __device__ inline int64_t ci(const Geom &g, const I3 &p)
 {
-    int64_t i = map_cell(p.v[0], g.n[0], g.bc[0]);
-    int64_t j = map_cell(p.v[1], g.n[1], g.bc[1]);
-    int64_t k = map_cell(p.v[2], g.n[2], g.bc[2]);
-    return (i * g.n[1] + j) * g.n[2] + k;
+    int i = wrap_cell(p.v[0], (int)g.n[0], g.bc[0]);
+    int j = wrap_cell(p.v[1], (int)g.n[1], g.bc[1]);
+    int k = wrap_cell(p.v[2], (int)g.n[2], g.bc[2]);
+    return ((int64_t)i * g.n[1] + j) * g.n[2] + k;
 }
 
 __device__ inline int64_t wi(const Geom &g, int d, const I3 &p)
 {
     int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
     e[d] += 1;
-    int64_t q[3];
+    int q[3];
     for (int t = 0; t < 3; t++)
-        q[t] = (t == d) ? map_wall(p.v[t], g.n[t], g.bc[t]) : map_cell(p.v[t], g.n[t], g.bc[t]);
-    return (q[0] * e[1] + q[1]) * e[2] + q[2];
+        q[t] = (t == d) ? wrap_wall(p.v[t], (int)g.n[t], g.bc[t])
+                        : wrap_cell(p.v[t], (int)g.n[t], g.bc[t]);
+    return ((int64_t)q[0] * e[1] + q[1]) * e[2] + q[2];
 }
 
 template <typename T> __device__ inline void aadd(T *a, int64_t k, T v)
@@ -126,7 +124,7 @@ __global__ void k_donor_adj(Geom g, const T *__restrict__ x, const T *c0, const 
     if (t >= N) return;
     const T *c[3] = {c0, c1, c2};
     T *cb[3] = {cb0, cb1, cb2};
-    I3 p = unflat3(t, g.n);
+    I3 p = unflat_i3(t, g.n);
     T ob = yb[t];
     aadd(xb, t, ob);
     T accb = G ? -ob / G[t] : -ob;
@@ -165,7 +163,7 @@ __global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__
     const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
     const T *c[3] = {c0, c1, c2};
     T *cb[3] = {cb0, cb1, cb2};
-    I3 p = unflat3(t, e);
+    I3 p = unflat_i3(t, e);
     I3 L = sh1(p, d, -1), R = p;
     T u = c[d][wi(g, d, p)];
     T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
@@ -282,7 +280,7 @@ __global__ void k_limit_adj(Geom g, int d, const T *__restrict__ V, const T *__r
     if (t >= M) return;
     T wb = Wb[t];
     if (wb == T(0)) return;
-    I3 p = unflat3(t, e);
+    I3 p = unflat_i3(t, e);
     I3 L = sh1(p, d, -1), R = p;
     int64_t kL = ci(g, L), kR = ci(g, R);
     T v = V[wi(g, d, p)];
@@ -315,7 +313,7 @@ __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
     const bool iga = opts & OPT_IGA;
     const T *V[3] = {V0, V1, V2};
     T *Vb[3] = {Vb0, Vb1, Vb2};
-    I3 p = unflat3(t, g.n);
+    I3 p = unflat_i3(t, g.n);
     T mx = psi_n[t], mn = mx;
     int64_t amx = t, amn = t;
     int smx = 0, smn = 0;

@@ -38,6 +38,38 @@ __host__ __device__ inline int64_t map_wall(int64_t f, int64_t n, int bc)
     return f < 0 ? 0 : (f > n ? n : f);
 }
 
+// Single-wrap variants for coordinates at most one period outside the range
+// (q in (-n, 2n)), which is all the stencils need: 32-bit, no division.
+__host__ __device__ inline int wrap_cell(int q, int n, int bc)
+{
+    if (bc == BC_PERIODIC) return q < 0 ? q + n : (q >= n ? q - n : q);
+    return q < 0 ? 0 : (q >= n ? n - 1 : q);
+}
+
+__host__ __device__ inline int wrap_wall(int f, int n, int bc)
+{
+    if (bc == BC_PERIODIC) return f < 0 ? f + n : (f >= n ? f - n : f);
+    return f < 0 ? 0 : (f > n ? n : f);
+}
+
+// Coordinates of flat index t in a row-major box of extents e (32-bit
+// arithmetic when the box has fewer than 2^31 entries).
+__device__ inline void unflat3(int64_t t, const int64_t e[3], int v[3])
+{
+    if (e[0] * e[1] * e[2] < ((int64_t)1 << 31)) {
+        unsigned u = (unsigned)t, e2 = (unsigned)e[2], e1 = (unsigned)e[1];
+        v[2] = (int)(u % e2);
+        u /= e2;
+        v[1] = (int)(u % e1);
+        v[0] = (int)(u / e1);
+    } else {
+        v[2] = (int)(t % e[2]);
+        t /= e[2];
+        v[1] = (int)(t % e[1]);
+        v[0] = (int)(t / e[1]);
+    }
+}
+
 template <typename T> __device__ inline T pos(T u) { return u > T(0) ? u : T(0); }
 template <typename T> __device__ inline T neg(T u) { return u < T(0) ? u : T(0); }
 

@@ -302,8 +302,12 @@ __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__
 
 #pragma unroll
         for (int k = 0; k < C::NP; k++) {
-            // pass k+2: newest input row a = t - 1 - 2k; psi^n row a sits at
-            // pq index QP - 2 - 2k
+            // pass m = k+2 takes input row a = t - 1 - 2k (psi^n row a sits at
+            // pq index QP - 2 - 2k).  Its first input row inside the dependency
+            // cone of output row i0 is i0 - 2(NI - m + 1), reached at iteration
+            // i0 - 2 NI + 4 m - 5; earlier iterations of this pass are skipped
+            // (the queues then hold only rows outside the cone).
+            if (t < i0 - 2 * NI + 4 * (k + 2) - 5) break;
             T yk = ps[k].template advance<FCT>(y, cn0, cn1, pq[C::QP - 2 - 2 * k]);
             cn0 = ps[k].aq0[1];
             cn1 = ps[k].aq1[1];

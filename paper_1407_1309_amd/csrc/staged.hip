@@ -12,20 +12,17 @@ namespace mp {
 namespace {
 
 struct Idx3 {
-    int64_t v[3];
+    int v[3];
 };
 
 __device__ inline Idx3 unflat(int64_t t, const int64_t e[3])
 {
     Idx3 p;
-    p.v[2] = t % e[2];
-    t /= e[2];
-    p.v[1] = t % e[1];
-    p.v[0] = t / e[1];
+    unflat3(t, e, p.v);
     return p;
 }
 
-__device__ inline Idx3 shifted(Idx3 p, int d, int64_t s)
+__device__ inline Idx3 shifted(Idx3 p, int d, int s)
 {
     p.v[d] += s;
     return p;
@@ -34,10 +31,10 @@ __device__ inline Idx3 shifted(Idx3 p, int d, int64_t s)
 template <typename T>
 __device__ inline T cell(const Geom &g, const T *a, const Idx3 &p)
 {
-    int64_t i = map_cell(p.v[0], g.n[0], g.bc[0]);
-    int64_t j = map_cell(p.v[1], g.n[1], g.bc[1]);
-    int64_t k = map_cell(p.v[2], g.n[2], g.bc[2]);
-    return a[(i * g.n[1] + j) * g.n[2] + k];
+    int i = wrap_cell(p.v[0], (int)g.n[0], g.bc[0]);
+    int j = wrap_cell(p.v[1], (int)g.n[1], g.bc[1]);
+    int k = wrap_cell(p.v[2], (int)g.n[2], g.bc[2]);
+    return a[((int64_t)i * g.n[1] + j) * g.n[2] + k];
 }
 
 template <typename T>
@@ -52,11 +49,11 @@ __device__ inline T wall(const Geom &g, int d, const T *a, const Idx3 &p)
 {
     int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
     e[d] += 1;
-    int64_t q[3];
+    int q[3];
     for (int t = 0; t < 3; t++)
-        q[t] = (t == d) ? map_wall(p.v[t], g.n[t], g.bc[t])
-                        : map_cell(p.v[t], g.n[t], g.bc[t]);
-    return a[(q[0] * e[1] + q[1]) * e[2] + q[2]];
+        q[t] = (t == d) ? wrap_wall(p.v[t], (int)g.n[t], g.bc[t])
+                        : wrap_cell(p.v[t], (int)g.n[t], g.bc[t]);
+    return a[((int64_t)q[0] * e[1] + q[1]) * e[2] + q[2]];
 }
 
 template <typename T>
