@@ -335,9 +335,12 @@ int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g, const voi
     int saved = plan->tile_rows, best = 0;
     float best_ms = 0.0f;
     int rc = MPDATA_OK;
-    for (int k = 0; k < (int)(sizeof cand / sizeof cand[0]); k++) {
+    const int ncand = (int)(sizeof cand / sizeof cand[0]);
+    // two sweeps over the candidates; the minimum time of each counts
+    for (int kk = 0; kk < 2 * ncand && rc == MPDATA_OK; kk++) {
+        int k = kk % ncand;
         int th = cand[k];
-        if (th > plan->g.n[0] && k > 0) break;
+        if (th > plan->g.n[0] && k > 0) continue;
         plan->tile_rows = th;
         const int reps = 5;
         for (int r = 0; r <= reps && rc == MPDATA_OK; r++) {
