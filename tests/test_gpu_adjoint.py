@@ -125,10 +125,11 @@ def test_adjoint_workload_point_checks_vs_fd():
             return _J(plan, p, cc, obs, n_steps)[0]
         ad = float(gp[idx]) if what == "psi" else float(gc[int(what[1])][idx])
         h = 1e-5
-        fd = (J_at(h) - J_at(-h)) / (2 * h)
+        fd1 = (J_at(h) - J_at(-h)) / (2 * h)
         fd2 = (J_at(h / 2) - J_at(-h / 2)) / h
-        if abs(fd - fd2) > 1e-6 * abs(fd):
+        if abs(fd1 - fd2) > 1e-5 * abs(fd2):
             continue                                   # a limiter switch within +-h
+        fd = (4.0 * fd2 - fd1) / 3.0                  # Richardson: removes the h^2 term
         assert abs(fd - ad) <= 1e-6 * abs(ad), (what, idx, ad, fd)
         n_ok += 1
     assert n_ok >= 12, n_ok
@@ -136,15 +137,17 @@ def test_adjoint_workload_point_checks_vs_fd():
 
 def test_adjoint_directions_vs_fd():
     """Whole-field directions (psi only, advector only, joint) on the adjoint
-    workload's inputs at 128^2 over 10 steps, checkpoint every 4: the
+    workload's recipe at 64^2 over 6 steps, checkpoint every 2: the
     directional derivative from the adjoint equals the central difference to
-    1e-6 relative (directions are zero on exactly-zero walls)."""
-    n_steps, ck = 10, 4
-    plan, psi, c, obs, gp, gc = _workload(128, n_steps, ck)
+    1e-6 relative (directions are zero on exactly-zero walls; a direction
+    whose difference quotient does not converge straddles a limiter switch
+    and is redrawn)."""
+    n_steps, ck = 6, 2
+    plan, psi, c, obs, gp, gc = _workload(64, n_steps, ck)
     gen = torch.Generator(device="cuda").manual_seed(7)
     passed = 0
     for which in ("psi", "c", "joint"):
-        for attempt in range(3):
+        for attempt in range(6):
             dpsi = torch.randn(psi.shape, generator=gen, device="cuda", dtype=torch.float64) \
                 if which != "c" else torch.zeros_like(psi)
             dc = [torch.randn(x.shape, generator=gen, device="cuda", dtype=torch.float64)
@@ -157,9 +160,10 @@ def test_adjoint_directions_vs_fd():
                 Jm, _ = _J(plan, psi - h * dpsi, [a - h * b for a, b in zip(c, dc)], obs, n_steps)
                 return (Jp - Jm) / (2 * h)
 
-            fd, fd2 = central(1e-7), central(5e-8)
-            if abs(fd - fd2) > 1e-6 * abs(fd):
+            fd1, fd2 = central(1e-6), central(5e-7)
+            if abs(fd1 - fd2) > 1e-5 * abs(fd2):
                 continue
+            fd = (4.0 * fd2 - fd1) / 3.0
             ad = float(torch.sum(gp * dpsi) + sum(torch.sum(a * b) for a, b in zip(gc, dc)))
             assert abs(ad - fd) <= 1e-6 * abs(fd), (which, ad, fd)
             passed += 1
