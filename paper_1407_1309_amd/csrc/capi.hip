@@ -171,7 +171,10 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
              const T *c2, bool fused)
 {
     hipError_t e;
-    if (fused) {
+    if (fused && p->desc.n_dims == 3) {
+        e = mp::fused3d_step<T>(p->g, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, c2,
+                                G, (T *)p->L.tmp[0], p->tile_rows, p->stream);
+    } else if (fused) {
         mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1], p->tile_rows};
         e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, G,
                                 p->stream);
@@ -201,7 +204,8 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
 bool fused_available(const mpdata_plan *p)
 {
     return mp::fused2d_supported(p->desc.n_dims, p->desc.n_iters, p->desc.opts, p->desc.has_g,
-                                 p->g.bc[0], p->g.bc[1]);
+                                 p->g.bc[0], p->g.bc[1]) ||
+           mp::fused3d_supported(p->desc.n_dims, p->desc.n_iters, p->desc.opts, p->g.n, p->g.bc);
 }
 
 bool resident_available(const mpdata_plan *p)

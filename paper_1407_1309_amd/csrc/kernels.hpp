@@ -64,6 +64,13 @@ template <typename T>
 hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
                         T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s);
 
+// ---- 3-D, two passes without the limiter: donor kernel + corrective kernel
+bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], const int bc[3]);
+template <typename T>
+hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_n, T *psi_out,
+                        const T *c0, const T *c1, const T *c2, const T *G, T *y1buf,
+                        int tile_planes, hipStream_t s);
+
 // ---- 1-D grid resident in LDS: all steps of a call in one launch --------
 bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g);
 template <typename T>
