@@ -142,13 +142,21 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
     T v1_keep = T(0), v2_keep = T(0);    // V1, V2 at plane t-1 (to LDS next plane)
 
     const int t_begin = i0 - 2, t_end = i1 + 1;
+    // plane t+1 is loaded while plane t is processed
+    T y_nx = y1[cix(g, t_begin, jj, kk)];
+    T g_nx = HAS_G ? G[cix(g, t_begin, jj, kk)] : T(1);
+    T c0_nx = c0[w0ix(g, t_begin, jj, kk)];
+    T c1_nx = c1[w1ix(g, t_begin, jj, kk)];
+    T c2_nx = c2[w2ix(g, t_begin, jj, kk)];
     for (int t = t_begin; t <= t_end; t++) {
-        // ---- loads of plane t (mapped) ----
-        T y_new = y1[cix(g, t, jj, kk)];
-        T g_new = HAS_G ? G[cix(g, t, jj, kk)] : T(1);
-        T c0_new = c0[w0ix(g, t, jj, kk)];
-        T c1_new = c1[w1ix(g, t, jj, kk)];
-        T c2_new = c2[w2ix(g, t, jj, kk)];
+        T y_new = y_nx, g_new = g_nx, c0_new = c0_nx, c1_new = c1_nx, c2_new = c2_nx;
+        if (t < t_end) {
+            y_nx = y1[cix(g, t + 1, jj, kk)];
+            if (HAS_G) g_nx = G[cix(g, t + 1, jj, kk)];
+            c0_nx = c0[w0ix(g, t + 1, jj, kk)];
+            c1_nx = c1[w1ix(g, t + 1, jj, kk)];
+            c2_nx = c2[w2ix(g, t + 1, jj, kk)];
+        }
         yq[0] = yq[1]; yq[1] = yq[2]; yq[2] = yq[3]; yq[3] = y_new;
         gq[0] = gq[1]; gq[1] = gq[2]; gq[2] = g_new;
         c0q[0] = c0q[1]; c0q[1] = c0q[2]; c0q[2] = c0_new;
@@ -178,25 +186,25 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
         T v0;
         {
             T xL = yq[1], xR = yq[2];
-            T Gb = T(0.5) * (gq[0] + gq[1]);
+            T ig = T(1) / (T(0.5) * (gq[0] + gq[1]));   // 1 / mean G at the wall
             T u = c0q[1];
             T A = fr<T, IGA>(xR - xL, xR + xL, T(2));
-            T v = (fabs(u) - u * u / Gb) * A;
+            T v = (fabs(u) - u * u * ig) * A;
             T cb1 = T(0.25) * (S1[r][l] + S1[rp1][l]);
             T cb2 = T(0.25) * (S2[r][l] + S2[r][lp1]);
             // o = 1 (j)
             T a1 = Y[sm1][rp1][l], b1 = Y[sm2][rp1][l], e1 = Y[sm1][rm1][l], f1 = Y[sm2][rm1][l];
-            v -= T(0.5) * u * cb1 / Gb * fr<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
+            v -= T(0.5) * u * cb1 * ig * fr<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
             // o = 2 (k)
             T a2 = Y[sm1][r][lp1], b2 = Y[sm2][r][lp1], e2 = Y[sm1][r][lm1], f2 = Y[sm2][r][lm1];
-            v -= T(0.5) * u * cb2 / Gb * fr<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
+            v -= T(0.5) * u * cb2 * ig * fr<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
             if (TOT) {
                 T xR2 = yq[3], xL2 = yq[0];
-                v += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) *
+                v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
                      fr<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
-                v += (fabs(u) * cb1 / Gb - T(2) * u * u * cb1 / (Gb * Gb)) *
+                v += (fabs(u) * cb1 * ig - T(2) * u * u * cb1 * (ig * ig)) *
                      fr<T, IGA>(a1 - b1 - e1 + f1, a1 + b1 + e1 + f1, T(4));
-                v += (fabs(u) * cb2 / Gb - T(2) * u * u * cb2 / (Gb * Gb)) *
+                v += (fabs(u) * cb2 * ig - T(2) * u * u * cb2 * (ig * ig)) *
                      fr<T, IGA>(a2 - b2 - e2 + f2, a2 + b2 + e2 + f2, T(4));
                 // o1 = j, o2 = k, sides L = plane t-2, R = plane t-1
                 T num = T(0), den = T(0);
@@ -207,7 +215,7 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
                     num += pp - mp_ - pm + mm;
                     den += pp + mp_ + pm + mm;
                 }
-                v += -(T(2) / T(3)) * u * cb1 * cb2 / (Gb * Gb) * fr<T, IGA>(num, den, T(8));
+                v += -(T(2) / T(3)) * u * cb1 * cb2 * (ig * ig) * fr<T, IGA>(num, den, T(8));
             }
             v0 = v;
         }
@@ -215,26 +223,26 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
         T v1;
         {
             T xL = Y[sm1][rm1][l], xR = Y[sm1][r][l];
-            T Gb = T(0.5) * (GP[rm1][l] + GP[r][l]);
+            T ig = T(1) / (T(0.5) * (GP[rm1][l] + GP[r][l]));
             T u = C1P[r][l];
             T A = fr<T, IGA>(xR - xL, xR + xL, T(2));
-            T v = (fabs(u) - u * u / Gb) * A;
+            T v = (fabs(u) - u * u * ig) * A;
             T cb0 = T(0.25) * (Q0[rm1][l] + Q0[r][l]);
             T cb2 = T(0.25) * ((C2P[rm1][l] + C2P[rm1][lp1]) + (C2P[r][l] + C2P[r][lp1]));
             // o = 0 (i): R+e0 = plane t at r, L+e0 = plane t at r-1, minus plane t-2
             T a0 = Y[s0][r][l], b0 = Y[s0][rm1][l], e0 = Y[sm2][r][l], f0 = Y[sm2][rm1][l];
-            v -= T(0.5) * u * cb0 / Gb * fr<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
+            v -= T(0.5) * u * cb0 * ig * fr<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
             // o = 2 (k)
             T a2 = Y[sm1][r][lp1], b2 = Y[sm1][rm1][lp1], e2 = Y[sm1][r][lm1],
               f2 = Y[sm1][rm1][lm1];
-            v -= T(0.5) * u * cb2 / Gb * fr<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
+            v -= T(0.5) * u * cb2 * ig * fr<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
             if (TOT) {
                 T xR2 = Y[sm1][rp1][l], xL2 = Y[sm1][rm2][l];
-                v += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) *
+                v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
                      fr<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
-                v += (fabs(u) * cb0 / Gb - T(2) * u * u * cb0 / (Gb * Gb)) *
+                v += (fabs(u) * cb0 * ig - T(2) * u * u * cb0 * (ig * ig)) *
                      fr<T, IGA>(a0 - b0 - e0 + f0, a0 + b0 + e0 + f0, T(4));
-                v += (fabs(u) * cb2 / Gb - T(2) * u * u * cb2 / (Gb * Gb)) *
+                v += (fabs(u) * cb2 * ig - T(2) * u * u * cb2 * (ig * ig)) *
                      fr<T, IGA>(a2 - b2 - e2 + f2, a2 + b2 + e2 + f2, T(4));
                 // o1 = i, o2 = k, sides L = row r-1, R = row r
                 T num = T(0), den = T(0);
@@ -245,7 +253,7 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
                     num += pp - mp_ - pm + mm;
                     den += pp + mp_ + pm + mm;
                 }
-                v += -(T(2) / T(3)) * u * cb0 * cb2 / (Gb * Gb) * fr<T, IGA>(num, den, T(8));
+                v += -(T(2) / T(3)) * u * cb0 * cb2 * (ig * ig) * fr<T, IGA>(num, den, T(8));
             }
             v1 = v;
         }
@@ -253,26 +261,26 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
         T v2;
         {
             T xL = Y[sm1][r][lm1], xR = Y[sm1][r][l];
-            T Gb = T(0.5) * (GP[r][lm1] + GP[r][l]);
+            T ig = T(1) / (T(0.5) * (GP[r][lm1] + GP[r][l]));
             T u = C2P[r][l];
             T A = fr<T, IGA>(xR - xL, xR + xL, T(2));
-            T v = (fabs(u) - u * u / Gb) * A;
+            T v = (fabs(u) - u * u * ig) * A;
             T cb0 = T(0.25) * (Q0[r][lm1] + Q0[r][l]);
             T cb1 = T(0.25) * ((C1P[r][lm1] + C1P[rp1][lm1]) + (C1P[r][l] + C1P[rp1][l]));
             // o = 0 (i)
             T a0 = Y[s0][r][l], b0 = Y[s0][r][lm1], e0 = Y[sm2][r][l], f0 = Y[sm2][r][lm1];
-            v -= T(0.5) * u * cb0 / Gb * fr<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
+            v -= T(0.5) * u * cb0 * ig * fr<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
             // o = 1 (j)
             T a1 = Y[sm1][rp1][l], b1 = Y[sm1][rp1][lm1], e1 = Y[sm1][rm1][l],
               f1 = Y[sm1][rm1][lm1];
-            v -= T(0.5) * u * cb1 / Gb * fr<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
+            v -= T(0.5) * u * cb1 * ig * fr<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
             if (TOT) {
                 T xR2 = Y[sm1][r][lp1], xL2 = Y[sm1][r][lm2];
-                v += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) *
+                v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
                      fr<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
-                v += (fabs(u) * cb0 / Gb - T(2) * u * u * cb0 / (Gb * Gb)) *
+                v += (fabs(u) * cb0 * ig - T(2) * u * u * cb0 * (ig * ig)) *
                      fr<T, IGA>(a0 - b0 - e0 + f0, a0 + b0 + e0 + f0, T(4));
-                v += (fabs(u) * cb1 / Gb - T(2) * u * u * cb1 / (Gb * Gb)) *
+                v += (fabs(u) * cb1 * ig - T(2) * u * u * cb1 * (ig * ig)) *
                      fr<T, IGA>(a1 - b1 - e1 + f1, a1 + b1 + e1 + f1, T(4));
                 // o1 = i, o2 = j, sides L = lane l-1, R = lane l
                 T num = T(0), den = T(0);
@@ -283,7 +291,7 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
                     num += pp - mp_ - pm + mm;
                     den += pp + mp_ + pm + mm;
                 }
-                v += -(T(2) / T(3)) * u * cb0 * cb1 / (Gb * Gb) * fr<T, IGA>(num, den, T(8));
+                v += -(T(2) / T(3)) * u * cb0 * cb1 * (ig * ig) * fr<T, IGA>(num, den, T(8));
             }
             v2 = v;
         }

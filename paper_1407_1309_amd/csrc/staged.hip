@@ -107,9 +107,9 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
     Idx3 p = unflat(t, e);
     Idx3 L = shifted(p, d, -1), R = p;
     T u = wall(g, d, c[d], p);
-    T Gb = T(0.5) * (gcell(g, G, L) + gcell(g, G, R));
+    T ig = T(1) / (T(0.5) * (gcell(g, G, L) + gcell(g, G, R)));   // 1 / mean G
     T xL = cell(g, x, L), xR = cell(g, x, R);
-    T V_ = (fabs(u) - u * u / Gb) * frac(iga, xR - xL, xR + xL, T(2));
+    T V_ = (fabs(u) - u * u * ig) * frac(iga, xR - xL, xR + xL, T(2));
 
     T cb[3] = {T(0), T(0), T(0)};
     for (int o = 0; o < g.nd; o++) {
@@ -118,18 +118,18 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
                            wall(g, o, c[o], R) + wall(g, o, c[o], shifted(R, o, 1)));
         T a = cell(g, x, shifted(R, o, 1)), b = cell(g, x, shifted(L, o, 1));
         T e_ = cell(g, x, shifted(R, o, -1)), f = cell(g, x, shifted(L, o, -1));
-        V_ -= T(0.5) * u * cb[o] / Gb * frac(iga, a + b - e_ - f, a + b + e_ + f, T(4));
+        V_ -= T(0.5) * u * cb[o] * ig * frac(iga, a + b - e_ - f, a + b + e_ + f, T(4));
     }
     if (tot) {
         T xR2 = cell(g, x, shifted(R, d, 1)), xL2 = cell(g, x, shifted(L, d, -1));
         T D = frac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
-        V_ += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) * D;
+        V_ += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) * D;
         for (int o = 0; o < g.nd; o++) {
             if (o == d) continue;
             T a = cell(g, x, shifted(R, o, 1)), b = cell(g, x, shifted(L, o, 1));
             T e_ = cell(g, x, shifted(R, o, -1)), f = cell(g, x, shifted(L, o, -1));
             T E = frac(iga, a - b - e_ + f, a + b + e_ + f, T(4));
-            V_ += (fabs(u) * cb[o] / Gb - T(2) * u * u * cb[o] / (Gb * Gb)) * E;
+            V_ += (fabs(u) * cb[o] * ig - T(2) * u * u * cb[o] * (ig * ig)) * E;
         }
         if (g.nd == 3) {
             int o1 = (d == 0) ? 1 : 0;
@@ -144,7 +144,7 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
                 num += vpp - vmp - vpm + vmm;
                 den += vpp + vmp + vpm + vmm;
             }
-            V_ += -(T(2) / T(3)) * u * cb[o1] * cb[o2] / (Gb * Gb) * frac(iga, num, den, T(8));
+            V_ += -(T(2) / T(3)) * u * cb[o1] * cb[o2] * (ig * ig) * frac(iga, num, den, T(8));
         }
     }
     V[t] = V_;
