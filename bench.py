@@ -23,6 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+# algorithmic floating-point operations per cell-step of the dominant kernel
+# (add, subtract, multiply, divide, min, max, compare each count one)
+ALG_FLOPS = {"2d_periodic_2048x2048_fct_iters3": 281}
 
 
 def _parse():
@@ -51,7 +56,7 @@ def _traffic_entry(kernel_name, workload):
         if not ent:
             return None
         from paper_1407_1309_amd.build import source_hash
-        if ent.get("source_hash") != source_hash():
+        if ent.get("source_hash") != source_hash(kernel_name):
             return None
         return ent.get("bytes_per_launch")
     except Exception:
@@ -112,7 +117,17 @@ def bench_single(args, torch, mpdata, synth, oracle):
     ms = secs * 1e3 / max(K, 1)
     value = N * K / secs / 1e6
 
-    # algorithmic bytes per step: read psi, every advector component, G; write psi
+    # launch durations of the dominant kernel, HIP events on the plan's stream
+    psi_t = psi0.clone()
+    plan.timing(K)
+    plan.step(psi_t, c, g=g, n_steps=K)
+    kern_ms, n_launch, kname = plan.timing_read()
+    plan.timing(0)
+    if kname == "k_resident1d":         # one launch runs all K steps
+        kern_ms /= max(K, 1)
+
+    # algorithmic bytes per launch of that kernel: read psi (the donor output
+    # in 3-D), every advector component, G; write psi
     walls = 0
     for d in range(len(case.psi.shape)):
         s = list(case.psi.shape)
@@ -120,9 +135,8 @@ def bench_single(args, torch, mpdata, synth, oracle):
             s[d] += 1                    # open: both edge walls are data
         walls += int(np.prod(s))
     alg_bytes = es * (2 * N + walls + (N if case.g is not None else 0))
-    achieved = alg_bytes / (ms / 1e3) / 1e9
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9
     fused = plan_uses_fused(plan, mpdata, kernel)
-    kname = "mpdata_fused2d" if fused else "mpdata_staged_step"
     traffic = _traffic_entry(kname, name + ("_f32" if f32 else "_f64"))
 
     out = {
@@ -137,8 +151,14 @@ def bench_single(args, torch, mpdata, synth, oracle):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
-                     "kernel": kname},
+                     "kernel": kname, "launch_ms": round(kern_ms, 6), "launches": n_launch},
     }
+    flops = ALG_FLOPS.get(name)
+    if flops is not None:
+        peak = FP32_PEAK_TFLOPS if f32 else FP64_PEAK_TFLOPS
+        tf = flops * N / (kern_ms / 1e3) / 1e12
+        out["roofline"]["alu"] = {"achieved": round(tf, 3), "peak": peak, "unit": "TFLOP/s",
+                                  "frac": round(tf / peak, 4), "flops_per_cell": flops}
     if not args.no_cpu:
         psi_o = case.psi.astype(np.float32).astype(np.float64) if f32 else case.psi
         c_o = [x.astype(np.float32).astype(np.float64) for x in case.c] if f32 else case.c

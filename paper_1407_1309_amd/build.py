@@ -26,12 +26,21 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def source_hash():
+KERNEL_SOURCE = {"k_fused2d": "fused2d.hip", "k_fused2d_batched": "fused2d.hip",
+                 "k_corr3d": "fused3d.hip", "k_donor3d": "fused3d.hip",
+                 "k_resident1d": "resident1d.hip"}
+
+
+def source_hash(kernel=None):
     """SHA-256 over the kernel sources (used to tie stored counter readings to
-    the code they were taken from)."""
+    the code they were taken from): the file that defines `kernel` plus the
+    shared header, or every source when kernel is None or unknown."""
     import hashlib
     h = hashlib.sha256()
+    own = KERNEL_SOURCE.get(kernel)
     for f in sorted(os.listdir(CSRC)):
+        if own is not None and f not in (own, "common.hpp"):
+            continue
         if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
             h.update(open(os.path.join(CSRC, f), "rb").read())

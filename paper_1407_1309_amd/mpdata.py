@@ -29,7 +29,8 @@ EXPORTS = [
     "mpdata_set_tile_rows", "mpdata_autotune",
     "mpdata_step", "mpdata_diag", "mpdata_courant_max", "mpdata_adv_adj",
     "mpdata_adj_workspace_bytes", "mpdata_batched_workspace_bytes", "mpdata_batched_init",
-    "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_destroy", "mpdata_last_error",
+    "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_timing", "mpdata_timing_read",
+    "mpdata_destroy", "mpdata_last_error",
 ]
 
 
@@ -82,6 +83,10 @@ def lib():
                                           ctypes.POINTER(_VP)]
         L.mpdata_step_batched.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int]
         L.mpdata_step_per_grid.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int]
+        L.mpdata_timing.argtypes = [_VP, ctypes.c_int]
+        L.mpdata_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_char_p)]
         L.mpdata_destroy.argtypes = [_VP]
         L.mpdata_destroy.restype = None
         L.mpdata_last_error.restype = ctypes.c_char_p
@@ -172,6 +177,22 @@ class Plan:
 
     def set_tile_rows(self, rows):
         _check(lib().mpdata_set_tile_rows(self._handle, int(rows)))
+
+    def timing(self, max_launches):
+        """Bracket each of the next max_launches launches of the step's
+        dominant kernel with HIP events (0 switches timing off)."""
+        _check(lib().mpdata_timing(self._handle, int(max_launches)))
+
+    def timing_read(self):
+        """(mean launch milliseconds, launches, kernel name) of the timed
+        launches; waits for them."""
+        tot = ctypes.c_double(0.0)
+        n = ctypes.c_int(0)
+        name = ctypes.c_char_p()
+        _check(lib().mpdata_timing_read(self._handle, ctypes.byref(tot), ctypes.byref(n),
+                                        ctypes.byref(name)))
+        return (tot.value / n.value if n.value else float("nan"), n.value,
+                (name.value or b"").decode())
 
     def autotune(self, psi, c, g=None):
         """Pick the fused kernel's chunk length by timing candidates on these
