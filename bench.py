@@ -34,7 +34,7 @@ def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="2d",
                     choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint", "copy"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "staged", "fused"])

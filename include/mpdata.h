@@ -199,16 +199,17 @@ int mpdata_step_per_grid(mpdata_plan *plan, void *psi_packed,
                          const void *c0_packed, const void *c1_packed,
                          int n_steps);
 
-/* Per-launch timing of the kernel that dominates a step (the fused 2-D
- * kernel, the 3-D corrective kernel, the resident 1-D kernel, or the whole
- * staged step), for roofline accounting.  mpdata_timing(plan, m) with m > 0
- * clears earlier records and brackets each of the next m such launches made
- * by mpdata_step with a pair of HIP events on the plan's stream (launches
- * beyond m are not timed); m = 0 switches timing off and frees the events.
+/* Timing of the step kernels, for roofline accounting.  mpdata_timing(plan,
+ * m) with m > 0 clears earlier records and times the next m step launches
+ * made by mpdata_step (the fused 2-D kernel, the 3-D donor + corrective
+ * pair, the resident 1-D kernel -- one launch for all steps of a call -- or
+ * the staged kernel sequence): a HIP event on the plan's stream before the
+ * first of them and one after the latest, so time between the launches of
+ * separate mpdata_step calls is included.  m = 0 switches timing off.
  * Timing does not change results.  mpdata_timing_read waits for the
- * recorded launches and returns their summed duration in milliseconds, their
- * count and the kernel's name (a static string; may be NULL).  Single-grid
- * plans only. */
+ * recorded launches and returns the elapsed milliseconds of the window,
+ * the number of launches in it and the name of what was launched (a static
+ * string; kernel may be NULL).  Single-grid plans only. */
 int mpdata_timing(mpdata_plan *plan, int max_launches);
 int mpdata_timing_read(mpdata_plan *plan, double *total_ms, int *launches,
                        const char **kernel);

@@ -162,22 +162,31 @@ struct mpdata_plan {
     hipGraph_t graph = nullptr;
     const void *g_key[3] = {nullptr, nullptr, nullptr};
     int g_steps = -1;
-    // per-launch timing of the dominant kernel (mpdata_timing): event pairs
+    // timing window of the step kernels (mpdata_timing): an event before the
+    // first timed launch, one after the latest, and the launch count
     bool timing = false;
-    std::vector<hipEvent_t> tev;
-    int tev_used = 0;
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    int t_launches = 0, t_limit = 0;
     const char *tname = "";
 };
 
 namespace {
 
-// Next free event pair of an active timer (nullptr when timing is off or
-// the pool is exhausted; launches beyond the pool are not timed).
-hipEvent_t *timer_slot(mpdata_plan *p, const char *name)
+// Brackets of a timed launch: timer_begin records the window's start event
+// before the first timed launch; timer_end moves the stop event after the
+// launch.  Launches beyond the limit are not timed.
+bool timer_begin(mpdata_plan *p, const char *name)
 {
-    if (!p->timing || 2 * (size_t)(p->tev_used + 1) > p->tev.size()) return nullptr;
+    if (!p->timing || p->t_launches >= p->t_limit) return false;
+    if (p->t_launches == 0) (void)hipEventRecord(p->tev[0], p->stream);
     p->tname = name;
-    return &p->tev[2 * (size_t)p->tev_used++];
+    return true;
+}
+
+void timer_end(mpdata_plan *p)
+{
+    (void)hipEventRecord(p->tev[1], p->stream);
+    p->t_launches++;
 }
 
 template <typename T>
@@ -185,15 +194,14 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
              const T *c2, bool fused, bool timed = false)
 {
     hipError_t e;
-    hipEvent_t *ev = nullptr;
-    if (timed && fused && p->desc.n_dims == 3)
-        ev = timer_slot(p, p->desc.n_iters == 1 ? "k_donor3d" : "k_corr3d");
-    else if (timed)
-        ev = timer_slot(p, fused ? "k_fused2d" : "staged step");
-    if (ev && !(fused && p->desc.n_dims == 3)) (void)hipEventRecord(ev[0], p->stream);
+    const char *name = !fused ? "staged step"
+                       : p->desc.n_dims == 3
+                           ? (p->desc.n_iters == 1 ? "k_donor3d" : "k_donor3d+k_corr3d")
+                           : "k_fused2d";
+    bool tm = timed && timer_begin(p, name);
     if (fused && p->desc.n_dims == 3) {
         e = mp::fused3d_step<T>(p->g, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, c2,
-                                G, (T *)p->L.tmp[0], p->tile_rows, p->stream, ev);
+                                G, (T *)p->L.tmp[0], p->tile_rows, p->stream);
     } else if (fused) {
         mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1], p->tile_rows};
         e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, G,
@@ -217,7 +225,7 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
         a.bdn = (T *)p->L.bdn;
         e = mp::staged_step<T>(a, p->stream);
     }
-    if (ev && !(fused && p->desc.n_dims == 3)) (void)hipEventRecord(ev[1], p->stream);
+    if (tm) timer_end(p);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     return MPDATA_OK;
 }
@@ -251,11 +259,10 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
 {
     if (n_steps == 0) return MPDATA_OK;
     if (use_resident(p)) {
-        hipEvent_t *ev = timer_slot(p, "k_resident1d");
-        if (ev) (void)hipEventRecord(ev[0], p->stream);
+        bool tm = timer_begin(p, "k_resident1d");
         hipError_t e = mp::resident1d_steps<T>(p->g.n[0], p->g.bc[0], p->desc.n_iters,
                                                p->desc.opts, psi, c0, G, n_steps, p->stream);
-        if (ev) (void)hipEventRecord(ev[1], p->stream);
+        if (tm) timer_end(p);
         return e == hipSuccess ? MPDATA_OK : hip_fail(e, "resident 1-D launch");
     }
     bool fused = use_fused(p);
@@ -774,23 +781,19 @@ int mpdata_step_per_grid(mpdata_plan *plan, void *psi, const void *c0, const voi
 int mpdata_timing(mpdata_plan *plan, int max_launches)
 {
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
-    if (max_launches < 0 || max_launches > (1 << 20))
-        return fail(MPDATA_EINVAL, "max_launches %d out of range", max_launches);
+    if (max_launches < 0) return fail(MPDATA_EINVAL, "max_launches %d < 0", max_launches);
     if (plan->batched) return fail(MPDATA_EINVAL, "timing needs a single-grid plan");
-    for (hipEvent_t ev : plan->tev) (void)hipEventDestroy(ev);
-    plan->tev.clear();
-    plan->tev_used = 0;
+    plan->t_launches = 0;
+    plan->t_limit = max_launches;
     plan->tname = "";
-    plan->timing = max_launches > 0;
-    for (int i = 0; i < 2 * max_launches; i++) {
-        hipEvent_t ev;
-        hipError_t e = hipEventCreate(&ev);
-        if (e != hipSuccess) {
-            plan->timing = false;
-            return hip_fail(e, "hipEventCreate");
-        }
-        plan->tev.push_back(ev);
+    plan->timing = false;
+    if (max_launches == 0) return MPDATA_OK;
+    for (int i = 0; i < 2; i++) {
+        if (plan->tev[i]) continue;
+        hipError_t e = hipEventCreate(&plan->tev[i]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
+    plan->timing = true;
     return MPDATA_OK;
 }
 
@@ -798,23 +801,23 @@ int mpdata_timing_read(mpdata_plan *plan, double *total_ms, int *launches, const
 {
     if (!plan || !total_ms || !launches) return fail(MPDATA_EINVAL, "NULL argument");
     *total_ms = 0.0;
-    *launches = plan->tev_used;
+    *launches = plan->t_launches;
     if (kernel) *kernel = plan->tname;
-    for (int i = 0; i < plan->tev_used; i++) {
-        hipError_t e = hipEventSynchronize(plan->tev[2 * (size_t)i + 1]);
-        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-        float ms = 0.0f;
-        e = hipEventElapsedTime(&ms, plan->tev[2 * (size_t)i], plan->tev[2 * (size_t)i + 1]);
-        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-        *total_ms += ms;
-    }
+    if (plan->t_launches == 0) return MPDATA_OK;
+    hipError_t e = hipEventSynchronize(plan->tev[1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, plan->tev[0], plan->tev[1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    *total_ms = ms;
     return MPDATA_OK;
 }
 
 void mpdata_destroy(mpdata_plan *plan)
 {
     if (!plan) return;
-    for (hipEvent_t ev : plan->tev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : plan->tev)
+        if (ev) (void)hipEventDestroy(ev);
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);

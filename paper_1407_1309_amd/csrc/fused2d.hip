@@ -58,13 +58,51 @@ __device__ inline double from_right(double v)
     return __hiloint2double(lane_from_right(__double2hiint(v)), lane_from_right(__double2loint(v)));
 }
 
-template <typename T> __device__ inline T frac(T num, T den)
+// Quotients.  FP32: the hardware reciprocal refined by one Newton step
+// (within an ulp or two of the rounded quotient) when the divisor is normal
+// or zero -- a zero divisor's quotient is discarded by every caller -- and
+// the IEEE division for subnormal or non-finite divisors.  The guarded fast
+// path is cheaper than the IEEE sequence in FP32; in FP64 (two Newton steps)
+// its branch costs more than it saves, so FP64 keeps the IEEE division.
+__device__ inline double qdiv(double n, double d) { return n / d; }
+__device__ inline float qdiv(float n, float d)
 {
-    return den == T(0) ? T(0) : num / den;
+    if (__builtin_amdgcn_classf(d, 0x168)) {      // +-normal or +-zero
+        float r = __builtin_amdgcn_rcpf(d);
+        float q = n * r;
+        return fmaf(fmaf(-d, q, n), r, q);
+    }
+    return n / d;
 }
 
+template <typename T> __device__ inline T frac(T num, T den)
+{
+    return den == T(0) ? T(0) : qdiv(num, den);
+}
+
+// ---- register row-queues ------------------------------------------------
+// The row loop is unrolled by U iterations and every queue is a ring whose
+// depth divides U, so the slot holding "the row pushed `age` iterations ago"
+// is a compile-time index for each unrolled iteration (phase P): queues
+// advance by renaming registers instead of moving them.
+template <int D> __host__ __device__ constexpr int slot(int phase, int age)
+{
+    return ((phase - age) % D + D) % D;
+}
+
+template <typename T, int D> struct Ring {
+    T v[D];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k < D; k++) v[k] = T(0);
+    }
+};
+#define AT(ring, depth, age) (ring).v[slot<depth>(P, (age))]
+
 // ---- one corrective pass --------------------------------------------------
-// Row bookkeeping for a pass whose newest input row is a:
+// Row bookkeeping for a pass whose newest input row is a (ages count rows
+// back from a):
 //   x rows a-3..a, x(j-1) rows a-2..a, x(j+1) rows a-1..a,
 //   input advector walls a-1, a (dimension 0) and rows a-1, a (dimension 1),
 //   raw V0 at walls a-1, a, limiter bounds rows a-2..a,
@@ -74,50 +112,34 @@ template <typename T> __device__ inline T frac(T num, T den)
 // row a-1, the limited velocities at wall a-1 / row a-1, and the corrected
 // field at row a-2.
 template <typename T> struct Pass {
-    T xq[4], xl[3], xr[2];
-    T c0q[2], c1q[2];
-    T v0q[2];
-    T mxq[3], mnq[3];
-    T buq[2], bdq[2];
-    T aq0[3], aq1[3];
+    Ring<T, 4> xq, xl, mxq, mnq, aq0, aq1;
+    Ring<T, 2> xr, c0q, c1q, v0q, buq, bdq;
 
-    __device__ void init()
+    __device__ __forceinline__ void init()
     {
-#pragma unroll
-        for (int k = 0; k < 4; k++) xq[k] = T(0);
-#pragma unroll
-        for (int k = 0; k < 3; k++) xl[k] = mxq[k] = mnq[k] = aq0[k] = aq1[k] = T(0);
-#pragma unroll
-        for (int k = 0; k < 2; k++) xr[k] = c0q[k] = c1q[k] = v0q[k] = buq[k] = bdq[k] = T(0);
+        xq.zero(); xl.zero(); mxq.zero(); mnq.zero(); aq0.zero(); aq1.zero();
+        xr.zero(); c0q.zero(); c1q.zero(); v0q.zero(); buq.zero(); bdq.zero();
     }
 
     // x_new: row a of the previous pass's result; c0_new / c1_new: the
     // previous pass's advector at wall a / row a; pn_a: psi^n at row a.
-    template <bool FCT> __device__ T advance(T x_new, T c0_new, T c1_new, T pn_a)
+    template <bool FCT, int P> __device__ __forceinline__ T advance(T x_new, T c0_new, T c1_new, T pn_a)
     {
-        xq[0] = xq[1];
-        xq[1] = xq[2];
-        xq[2] = xq[3];
-        xq[3] = x_new;
-        xl[0] = xl[1];
-        xl[1] = xl[2];
-        xl[2] = from_left(x_new);
-        xr[0] = xr[1];
-        xr[1] = from_right(x_new);
-        c0q[0] = c0q[1];
-        c0q[1] = c0_new;
-        c1q[0] = c1q[1];
-        c1q[1] = c1_new;
+        AT(xq, 4, 0) = x_new;
+        AT(xl, 4, 0) = from_left(x_new);
+        AT(xr, 2, 0) = from_right(x_new);
+        AT(c0q, 2, 0) = c0_new;
+        AT(c1q, 2, 0) = c1_new;
 
         // V0 at wall a (rows a-1 | a), column j
         T v0;
         {
-            T xL = xq[2], xR = xq[3];
-            T u = c0q[1];
+            T xL = AT(xq, 4, 1), xR = AT(xq, 4, 0);
+            T u = AT(c0q, 2, 0);
             T A = frac(xR - xL, xR + xL);
-            T s1 = c1q[0] + c1q[1];
+            T s1 = AT(c1q, 2, 1) + AT(c1q, 2, 0);
             T cb = T(0.25) * (s1 + from_right(s1));
-            T a = xr[1], b = xr[0], e = xl[2], f = xl[1];
+            T a = AT(xr, 2, 0), b = AT(xr, 2, 1), e = AT(xl, 4, 0), f = AT(xl, 4, 1);
             T B = frac(a + b - e - f, a + b + e + f);
             v0 = (fabs(u) - u * u) * A;
             v0 -= T(0.5) * u * cb * B;
@@ -125,45 +147,39 @@ template <typename T> struct Pass {
         // V1 at row a-1, wall j (columns j-1 | j)
         T v1;
         {
-            T xL = xl[1], xR = xq[2];
-            T u = c1q[0];
+            T xL = AT(xl, 4, 1), xR = AT(xq, 4, 1);
+            T u = AT(c1q, 2, 1);
             T A = frac(xR - xL, xR + xL);
-            T s0 = c0q[0] + c0q[1];
+            T s0 = AT(c0q, 2, 1) + AT(c0q, 2, 0);
             T cb = T(0.25) * (from_left(s0) + s0);
-            T a = xq[3], b = xl[2], e = xq[1], f = xl[0];
+            T a = AT(xq, 4, 0), b = AT(xl, 4, 0), e = AT(xq, 4, 2), f = AT(xl, 4, 2);
             T B = frac(a + b - e - f, a + b + e + f);
             v1 = (fabs(u) - u * u) * A;
             v1 -= T(0.5) * u * cb * B;
         }
-        v0q[0] = v0q[1];
-        v0q[1] = v0;
+        AT(v0q, 2, 0) = v0;
 
         T lim0, lim1;
         if (FCT) {
             // local bounds over {psi^n, x} at the cell and its face neighbours
-            mxq[0] = mxq[1];
-            mxq[1] = mxq[2];
-            mxq[2] = fmax(pn_a, xq[3]);
-            mnq[0] = mnq[1];
-            mnq[1] = mnq[2];
-            mnq[2] = fmin(pn_a, xq[3]);
-            T mx = fmax(fmax(mxq[1], fmax(mxq[0], mxq[2])),
-                        fmax(from_left(mxq[1]), from_right(mxq[1])));
-            T mn = fmin(fmin(mnq[1], fmin(mnq[0], mnq[2])),
-                        fmin(from_left(mnq[1]), from_right(mnq[1])));
+            AT(mxq, 4, 0) = fmax(pn_a, AT(xq, 4, 0));
+            AT(mnq, 4, 0) = fmin(pn_a, AT(xq, 4, 0));
+            T m1 = AT(mxq, 4, 1), n1 = AT(mnq, 4, 1);
+            T mx = fmax(fmax(m1, fmax(AT(mxq, 4, 2), AT(mxq, 4, 0))),
+                        fmax(from_left(m1), from_right(m1)));
+            T mn = fmin(fmin(n1, fmin(AT(mnq, 4, 2), AT(mnq, 4, 0))),
+                        fmin(from_left(n1), from_right(n1)));
             // in/out fluxes of cell (a-1, j)
-            T xc = xq[2];
-            T v0lo = v0q[0], v0hi = v0q[1];
+            T xc = AT(xq, 4, 1);
+            T v0lo = AT(v0q, 2, 1), v0hi = AT(v0q, 2, 0);
             T v1lo = v1, v1hi = from_right(v1);
-            T fin = (pos(v0lo) * xq[1] - neg(v0hi) * xq[3]) +
-                    (pos(v1lo) * xl[1] - neg(v1hi) * xr[0]);
+            T fin = (pos(v0lo) * AT(xq, 4, 2) - neg(v0hi) * AT(xq, 4, 0)) +
+                    (pos(v1lo) * AT(xl, 4, 1) - neg(v1hi) * AT(xr, 2, 1));
             T fout = (pos(v0hi) * xc - neg(v0lo) * xc) + (pos(v1hi) * xc - neg(v1lo) * xc);
-            T bu = fin > T(0) ? (mx - xc) / fin : T(1);
-            T bd = fout > T(0) ? (xc - mn) / fout : T(1);
-            buq[0] = buq[1];
-            buq[1] = bu;
-            bdq[0] = bdq[1];
-            bdq[1] = bd;
+            T bu = fin > T(0) ? qdiv(mx - xc, fin) : T(1);
+            T bd = fout > T(0) ? qdiv(xc - mn, fout) : T(1);
+            AT(buq, 2, 0) = bu;
+            AT(bdq, 2, 0) = bd;
             // limited V1 at row a-1, wall j: L = (a-1, j-1), R = (a-1, j)
             {
                 T up = fmin(fmin(T(1), from_left(bd)), bu);
@@ -172,27 +188,23 @@ template <typename T> struct Pass {
             }
             // limited V0 at wall a-1: L = (a-2, j), R = (a-1, j)
             {
-                T v = v0q[0];
-                T up = fmin(fmin(T(1), bdq[0]), buq[1]);
-                T dn = fmin(fmin(T(1), buq[0]), bdq[1]);
+                T v = AT(v0q, 2, 1);
+                T up = fmin(fmin(T(1), AT(bdq, 2, 1)), AT(buq, 2, 0));
+                T dn = fmin(fmin(T(1), AT(buq, 2, 1)), AT(bdq, 2, 0));
                 lim0 = pos(v) * up + neg(v) * dn;
             }
         } else {
-            lim0 = v0q[0];
+            lim0 = AT(v0q, 2, 1);
             lim1 = v1;
         }
-        aq0[0] = aq0[1];
-        aq0[1] = aq0[2];
-        aq0[2] = lim0;
-        aq1[0] = aq1[1];
-        aq1[1] = aq1[2];
-        aq1[2] = lim1;
+        AT(aq0, 4, 0) = lim0;
+        AT(aq1, 4, 0) = lim1;
 
         // corrective donor-cell pass at row a-2
-        T x = xq[1];
-        T f0lo = pos(aq0[1]) * xq[0] + neg(aq0[1]) * x;
-        T f0hi = pos(aq0[2]) * x + neg(aq0[2]) * xq[2];
-        T f1lo = pos(aq1[1]) * xl[0] + neg(aq1[1]) * x;
+        T x = AT(xq, 4, 2);
+        T f0lo = pos(AT(aq0, 4, 1)) * AT(xq, 4, 3) + neg(AT(aq0, 4, 1)) * x;
+        T f0hi = pos(AT(aq0, 4, 0)) * x + neg(AT(aq0, 4, 0)) * AT(xq, 4, 1);
+        T f1lo = pos(AT(aq1, 4, 1)) * AT(xl, 4, 2) + neg(AT(aq1, 4, 1)) * x;
         T f1hi = from_right(f1lo);
         return x - ((f0hi - f0lo) + (f1hi - f1lo));
     }
@@ -202,12 +214,94 @@ template <int NI, bool FCT> struct Cfg {
     static constexpr int NP = NI - 1;                 // corrective passes
     static constexpr int H = 1 + (FCT ? 2 : 1) * NP;  // horizontal halo (lanes)
     static constexpr int LAG = 1 + 2 * NP;            // output row = t - LAG
-    static constexpr int QP = (2 * NI > 3) ? 2 * NI : 3;  // psi^n rows kept
+    static constexpr int QP = NI <= 3 ? 4 : 8;        // psi^n ring (ages 0..2NI-3 used)
+    static constexpr int U = QP;                      // row-loop unroll
     static constexpr int OW = WAVE - 2 * H;           // output columns per strip
 };
 
 // Prefetch distance (rows in flight ahead of the one being consumed).
 constexpr int PF = 2;
+
+// State of one wavefront marching down rows i0..i1-1 of a 64-column strip.
+template <typename T, int NI, bool FCT> struct Strip {
+    using C = Cfg<NI, FCT>;
+    int n0, n1, i0, i1, jj, rr;
+    int64_t ld1;
+    bool out_lane;
+    const T *psi_n, *c0, *c1;
+    const T *prow, *c0row, *c1row;
+    T *orow;
+    Ring<T, C::QP> pq;
+    Ring<T, 2> dc0, dc1;
+    T fp[PF], f0[PF], f1[PF];
+    Pass<T> ps[C::NP > 0 ? C::NP : 1];
+
+    __device__ __forceinline__ void next_row()
+    {
+        if (++rr == n0) {
+            rr = 0;
+            prow = psi_n;
+            c0row = c0;
+            c1row = c1;
+        } else {
+            prow += n1;
+            c0row += n1;
+            c1row += ld1;
+        }
+    }
+
+    // one row of the pipeline at loop position t (phase P = t - t_begin mod U)
+    template <int P> __device__ __forceinline__ void iter(int t)
+    {
+        constexpr int S = P % PF;
+        T p_new = fp[S], c0_new = f0[S], c1_new = f1[S];
+        fp[S] = prow[jj];
+        f0[S] = c0row[jj];
+        f1[S] = c1row[jj];
+        next_row();
+
+        AT(pq, C::QP, 0) = p_new;
+        AT(dc0, 2, 0) = c0_new;
+        AT(dc1, 2, 0) = c1_new;
+
+        // donor-cell pass at row t-1
+        T x = AT(pq, C::QP, 1);
+        T f0lo = pos(AT(dc0, 2, 1)) * AT(pq, C::QP, 2) + neg(AT(dc0, 2, 1)) * x;
+        T f0hi = pos(AT(dc0, 2, 0)) * x + neg(AT(dc0, 2, 0)) * AT(pq, C::QP, 0);
+        T f1lo = pos(AT(dc1, 2, 1)) * from_left(x) + neg(AT(dc1, 2, 1)) * x;
+        T f1hi = from_right(f1lo);
+        T y = x - ((f0hi - f0lo) + (f1hi - f1lo));
+        T cn0 = AT(dc0, 2, 1), cn1 = AT(dc1, 2, 1);
+
+#pragma unroll
+        for (int k = 0; k < C::NP; k++) {
+            // pass m = k+2 takes input row a = t - 1 - 2k (psi^n row a is
+            // 1 + 2k rows old).  Its first input row inside the dependency
+            // cone of output row i0 is i0 - 2(NI - m + 1), reached at iteration
+            // i0 - 2 NI + 4 m - 5; earlier iterations of this pass are skipped
+            // (the queues then hold only rows outside the cone).
+            if (t < i0 - 2 * NI + 4 * (k + 2) - 5) break;
+            T yk = ps[k].template advance<FCT, P>(y, cn0, cn1, pq.v[slot<C::QP>(P, 1 + 2 * k)]);
+            cn0 = ps[k].aq0.v[slot<4>(P, 1)];
+            cn1 = ps[k].aq1.v[slot<4>(P, 1)];
+            y = yk;
+        }
+
+        if (t - C::LAG >= i0 && t - C::LAG < i1) {
+            if (out_lane) *orow = y;
+            orow += n1;
+        }
+    }
+};
+
+template <typename T, int NI, bool FCT, int P = 0>
+__device__ __forceinline__ void iter_block(Strip<T, NI, FCT> &st, int t)
+{
+    if constexpr (P < Cfg<NI, FCT>::U) {
+        st.template iter<P>(t + P);
+        iter_block<T, NI, FCT, P + 1>(st, t);
+    }
+}
 
 template <typename T, int NI, bool FCT>
 __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__ psi_n,
@@ -215,110 +309,52 @@ __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__
                                            const T *__restrict__ c1, int jstrip0, int i0, int i1)
 {
     using C = Cfg<NI, FCT>;
+    Strip<T, NI, FCT> st;
     const int lane = threadIdx.x & (WAVE - 1);
     // global column of this lane (may lie outside [0, n1) in the halo)
     const int col = jstrip0 - C::H + lane;
     int jj = col % n1;
     if (jj < 0) jj += n1;
-
-    T pq[C::QP];
+    st.n0 = n0;
+    st.n1 = n1;
+    st.i0 = i0;
+    st.i1 = i1;
+    st.jj = jj;
+    st.psi_n = psi_n;
+    st.c0 = c0;
+    st.c1 = c1;
+    st.pq.zero();
+    st.dc0.zero();
+    st.dc1.zero();
 #pragma unroll
-    for (int k = 0; k < C::QP; k++) pq[k] = T(0);
-    T dc0[2] = {T(0), T(0)}, dc1[2] = {T(0), T(0)};
-    Pass<T> ps[C::NP > 0 ? C::NP : 1];
-#pragma unroll
-    for (int k = 0; k < C::NP; k++) ps[k].init();
+    for (int k = 0; k < C::NP; k++) st.ps[k].init();
 
+    // iterations t_begin .. t_end; the loop runs whole blocks of U, so up to
+    // U-1 extra iterations at the end compute rows that are not stored
     const int t_begin = i0 - C::LAG - 1;
     const int t_end = i1 - 1 + C::LAG;    // inclusive
     // row (mod n0) of the next row to load, and its row pointers
     int rr = t_begin % n0;
     if (rr < 0) rr += n0;
-    const int64_t ld1 = (int64_t)n1 + 1;
-    const T *prow = psi_n + (int64_t)rr * n1;
-    const T *c0row = c0 + (int64_t)rr * n1;
-    const T *c1row = c1 + (int64_t)rr * ld1;
+    st.rr = rr;
+    st.ld1 = (int64_t)n1 + 1;
+    st.prow = psi_n + (int64_t)rr * n1;
+    st.c0row = c0 + (int64_t)rr * n1;
+    st.c1row = c1 + (int64_t)rr * st.ld1;
 
-    // prefetch queue: rows t .. t+PF-1
-    T fp[PF], f0[PF], f1[PF];
+    // prefetch: rows t_begin .. t_begin+PF-1 (slot k holds row t_begin+k)
 #pragma unroll
     for (int k = 0; k < PF; k++) {
-        fp[k] = prow[jj];
-        f0[k] = c0row[jj];
-        f1[k] = c1row[jj];
-        if (++rr == n0) {
-            rr = 0;
-            prow = psi_n;
-            c0row = c0;
-            c1row = c1;
-        } else {
-            prow += n1;
-            c0row += n1;
-            c1row += ld1;
-        }
+        st.fp[k] = st.prow[jj];
+        st.f0[k] = st.c0row[jj];
+        st.f1[k] = st.c1row[jj];
+        st.next_row();
     }
 
-    const bool out_lane = lane >= C::H && lane < WAVE - C::H && col < n1;
-    T *orow = psi_out + (int64_t)i0 * n1 + (out_lane ? col : 0);
+    st.out_lane = lane >= C::H && lane < WAVE - C::H && col < n1;
+    st.orow = psi_out + (int64_t)i0 * n1 + (st.out_lane ? col : 0);
 
-    for (int t = t_begin; t <= t_end; t++) {
-        T p_new = fp[0], c0_new = f0[0], c1_new = f1[0];
-#pragma unroll
-        for (int k = 0; k < PF - 1; k++) {
-            fp[k] = fp[k + 1];
-            f0[k] = f0[k + 1];
-            f1[k] = f1[k + 1];
-        }
-        fp[PF - 1] = prow[jj];
-        f0[PF - 1] = c0row[jj];
-        f1[PF - 1] = c1row[jj];
-        if (++rr == n0) {
-            rr = 0;
-            prow = psi_n;
-            c0row = c0;
-            c1row = c1;
-        } else {
-            prow += n1;
-            c0row += n1;
-            c1row += ld1;
-        }
-
-#pragma unroll
-        for (int k = 0; k < C::QP - 1; k++) pq[k] = pq[k + 1];
-        pq[C::QP - 1] = p_new;
-        dc0[0] = dc0[1];
-        dc0[1] = c0_new;
-        dc1[0] = dc1[1];
-        dc1[1] = c1_new;
-
-        // donor-cell pass at row t-1
-        T x = pq[C::QP - 2];
-        T f0lo = pos(dc0[0]) * pq[C::QP - 3] + neg(dc0[0]) * x;
-        T f0hi = pos(dc0[1]) * x + neg(dc0[1]) * pq[C::QP - 1];
-        T f1lo = pos(dc1[0]) * from_left(x) + neg(dc1[0]) * x;
-        T f1hi = from_right(f1lo);
-        T y = x - ((f0hi - f0lo) + (f1hi - f1lo));
-        T cn0 = dc0[0], cn1 = dc1[0];
-
-#pragma unroll
-        for (int k = 0; k < C::NP; k++) {
-            // pass m = k+2 takes input row a = t - 1 - 2k (psi^n row a sits at
-            // pq index QP - 2 - 2k).  Its first input row inside the dependency
-            // cone of output row i0 is i0 - 2(NI - m + 1), reached at iteration
-            // i0 - 2 NI + 4 m - 5; earlier iterations of this pass are skipped
-            // (the queues then hold only rows outside the cone).
-            if (t < i0 - 2 * NI + 4 * (k + 2) - 5) break;
-            T yk = ps[k].template advance<FCT>(y, cn0, cn1, pq[C::QP - 2 - 2 * k]);
-            cn0 = ps[k].aq0[1];
-            cn1 = ps[k].aq1[1];
-            y = yk;
-        }
-
-        if (t - C::LAG >= i0) {
-            if (out_lane) *orow = y;
-            orow += n1;
-        }
-    }
+    for (int t = t_begin; t <= t_end; t += C::U) iter_block<T, NI, FCT>(st, t);
 }
 
 template <typename T, int NI, bool FCT>

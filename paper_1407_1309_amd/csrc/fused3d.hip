@@ -343,22 +343,16 @@ bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], c
 template <typename T>
 hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *psi_n, T *psi_out,
                         const T *c0, const T *c1, const T *c2, const T *G, T *y1buf, int tile_planes,
-                        hipStream_t s, hipEvent_t *timer)
+                        hipStream_t s)
 {
     G3 g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
     dim3 gd((unsigned)cdiv(g.n2, 64), (unsigned)cdiv(g.n1, 4), (unsigned)g.n0);
     T *y1 = (n_iters == 1) ? psi_out : y1buf;
-    // the timer brackets the kernel that dominates the step: the corrective
-    // kernel, or the donor kernel when it is the only one
-    if (timer && n_iters == 1) (void)hipEventRecord(timer[0], s);
     if (G)
         k_donor3d<T, true><<<gd, 256, 0, s>>>(g, psi_n, c0, c1, c2, G, y1);
     else
         k_donor3d<T, false><<<gd, 256, 0, s>>>(g, psi_n, c0, c1, c2, G, y1);
-    if (n_iters == 1) {
-        if (timer) (void)hipEventRecord(timer[1], s);
-        return hipGetLastError();
-    }
+    if (n_iters == 1) return hipGetLastError();
     constexpr int TL = TileL<T>::v;
     int tiles_k = (g.n2 + TL - 2 * HALO - 1) / (TL - 2 * HALO);
     int tiles_j = (g.n1 + TR - 2 * HALO - 1) / (TR - 2 * HALO);
@@ -367,7 +361,6 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
     int chunks = (g.n0 + th - 1) / th;
     unsigned blocks = (unsigned)tiles_k * tiles_j * chunks;
     const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
-    if (timer) (void)hipEventRecord(timer[0], s);
 #define MP_CORR(HG, IG, TO) \
     k_corr3d<T, HG, IG, TO><<<blocks, TR * TL, 0, s>>>(g, th, y1, c0, c1, c2, G, psi_out)
     if (G) {
@@ -378,17 +371,14 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
         else { if (tot) MP_CORR(false, false, true); else MP_CORR(false, false, false); }
     }
 #undef MP_CORR
-    if (timer) (void)hipEventRecord(timer[1], s);
     return hipGetLastError();
 }
 
 template hipError_t fused3d_step<float>(const Geom &, int, unsigned, const float *, float *,
                                         const float *, const float *, const float *,
-                                        const float *, float *, int, hipStream_t,
-                                        hipEvent_t *);
+                                        const float *, float *, int, hipStream_t);
 template hipError_t fused3d_step<double>(const Geom &, int, unsigned, const double *, double *,
                                          const double *, const double *, const double *,
-                                         const double *, double *, int, hipStream_t,
-                                         hipEvent_t *);
+                                         const double *, double *, int, hipStream_t);
 
 }  // namespace mp

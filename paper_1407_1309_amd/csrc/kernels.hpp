@@ -69,7 +69,7 @@ bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], c
 template <typename T>
 hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_n, T *psi_out,
                         const T *c0, const T *c1, const T *c2, const T *G, T *y1buf,
-                        int tile_planes, hipStream_t s, hipEvent_t *timer = nullptr);
+                        int tile_planes, hipStream_t s);
 
 // ---- 1-D grid resident in LDS: all steps of a call in one launch --------
 bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g);

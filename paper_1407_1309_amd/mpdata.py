@@ -179,12 +179,12 @@ class Plan:
         _check(lib().mpdata_set_tile_rows(self._handle, int(rows)))
 
     def timing(self, max_launches):
-        """Bracket each of the next max_launches launches of the step's
-        dominant kernel with HIP events (0 switches timing off)."""
+        """Time the next max_launches step launches with a pair of HIP events
+        around them (0 switches timing off)."""
         _check(lib().mpdata_timing(self._handle, int(max_launches)))
 
     def timing_read(self):
-        """(mean launch milliseconds, launches, kernel name) of the timed
+        """(mean milliseconds per launch, launches, kernel name) of the timed
         launches; waits for them."""
         tot = ctypes.c_double(0.0)
         n = ctypes.c_int(0)

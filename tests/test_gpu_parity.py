@@ -215,6 +215,32 @@ def test_zero_steps_is_identity():
     assert torch.equal(p, q)
 
 
+@pytest.mark.parametrize("shape", [(96, 80), (24, 20, 70), (300,)], ids=["2d", "3d", "1d"])
+def test_timing_window(shape):
+    """mpdata_timing brackets the next m step launches without changing the
+    result; launches beyond m are not counted."""
+    nd = len(shape)
+    rng = np.random.default_rng(11)
+    psi = rng.uniform(0.0, 1.0, size=shape)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.3, rng))
+    opts = 0 if nd == 3 else FCT
+    plan = mpdata.Plan(shape, n_iters=2, opts=opts, bc=mpdata.BC_PERIODIC)
+    cd = [dev(x, torch.float64) for x in c]
+    a = dev(psi, torch.float64)
+    plan.step(a, cd, n_steps=4)
+    b = dev(psi, torch.float64)
+    plan.timing(3)
+    plan.step(b, cd, n_steps=4)
+    ms, n, name = plan.timing_read()
+    plan.timing(0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert n == (1 if nd == 1 else 3)
+    assert ms > 0.0 and name
+    plan.timing(0)
+    assert plan.timing_read()[1] == 0
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 def test_fused_tile_rows_bitwise_independent(dtype):
     """The fused kernel's chunk length changes only the speed: every setting
