@@ -242,7 +242,7 @@ def bench_adjoint(args, torch, mpdata, synth, oracle):
     ck = min(20, K)
     dev = torch.device("cuda:0")
     plan = mpdata.Plan(case.psi.shape, n_iters=2, opts=mpdata.OPT_FCT,
-                       kernel=mpdata.KERNEL_STAGED, adj_steps=K, ckpt_every=ck, device=dev)
+                       adj_steps=K, ckpt_every=ck, device=dev)
     psi = torch.from_numpy(case.psi).to(dev)
     c = [torch.from_numpy(x).to(dev) for x in case.c]
     obs = torch.from_numpy(w["psi_perturbed"]).to(dev)

@@ -580,7 +580,7 @@ template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
             if (e != hipSuccess) return e;
         }
         if (st == a.n_steps - 1) break;   // the final state is not needed
-        e = record_step<T>(a, w, cur, nxt, s);
+        e = a.plain_step ? a.plain_step(a.plain_ctx, cur, nxt) : record_step<T>(a, w, cur, nxt, s);
         if (e != hipSuccess) return e;
         T *t = cur;
         cur = nxt;
@@ -599,8 +599,9 @@ template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
         e = hipMemcpyAsync(w.seg, w.ck + (size_t)sg * N, nb, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
         for (int st = s0; st < s1 - 1; st++) {
-            e = record_step<T>(a, w, w.seg + (size_t)(st - s0) * N,
-                               w.seg + (size_t)(st - s0 + 1) * N, s);
+            const T *in = w.seg + (size_t)(st - s0) * N;
+            T *out = w.seg + (size_t)(st - s0 + 1) * N;
+            e = a.plain_step ? a.plain_step(a.plain_ctx, in, out) : record_step<T>(a, w, in, out, s);
             if (e != hipSuccess) return e;
         }
         for (int st = s1 - 1; st >= s0; st--) {

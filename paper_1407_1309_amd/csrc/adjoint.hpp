@@ -20,6 +20,11 @@ template <typename T> struct AdjArgs {
     T *grad_psi0;
     T *grad_c[3];
     char *ws;   // adjoint scratch (adj_extra_bytes)
+    // Optional forward step psi_in -> psi_out without records (the caller's
+    // fastest kernel for this configuration), used wherever the sweep only
+    // needs states: the checkpointing pass and the segment recomputation.
+    hipError_t (*plain_step)(void *ctx, const T *in, T *out) = nullptr;
+    void *plain_ctx = nullptr;
 };
 
 size_t adj_extra_bytes(const Geom &g, size_t es, int n_iters, int n_steps, int ckpt_every);

@@ -497,6 +497,28 @@ size_t mpdata_adj_workspace_bytes(const mpdata_desc *desc, int n_steps, int ckpt
                                       n_steps, ckpt_every);
 }
 
+}  // extern "C"
+
+namespace {
+
+// forward step without records for the adjoint's state sweeps
+struct AdjStepCtx {
+    mpdata_plan *p;
+    const void *G, *c[3];
+};
+
+template <typename T> hipError_t adj_plain_step(void *ctx, const T *in, T *out)
+{
+    const AdjStepCtx *x = (const AdjStepCtx *)ctx;
+    int rc = one_step<T>(x->p, in, out, (const T *)x->G, (const T *)x->c[0], (const T *)x->c[1],
+                         (const T *)x->c[2], use_fused(x->p));
+    return rc == MPDATA_OK ? hipSuccess : hipErrorLaunchFailure;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const void *c0,
                    const void *c1, const void *c2, int n_steps, int ckpt_every,
                    const void *lambda_T, void *grad_psi0, void *grad_c0, void *grad_c1,
@@ -522,6 +544,7 @@ int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const voi
         return fail(MPDATA_EWORKSPACE, "adjoint needs %zu workspace bytes, plan has %zu", need,
                     plan->ws_bytes);
     char *extra = (char *)plan->ws + plan->L.bytes;
+    AdjStepCtx sc{plan, g, {c0, c1, c2}};
     hipError_t e;
     if (plan->desc.dtype == MPDATA_F64) {
         mp::AdjArgs<double> a;
@@ -530,6 +553,8 @@ int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const voi
                                   (const double *const *)c, n_steps, ckpt_every,
                                   (const double *)lambda_T, (double *)grad_psi0, (double **)gc,
                                   extra);
+        a.plain_step = adj_plain_step<double>;
+        a.plain_ctx = &sc;
         e = mp::adjoint_run<double>(a, plan->stream);
     } else {
         mp::AdjArgs<float> a;
@@ -537,6 +562,8 @@ int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const voi
                                  (const float *)psi0, (const float *)g, (const float *const *)c,
                                  n_steps, ckpt_every, (const float *)lambda_T,
                                  (float *)grad_psi0, (float **)gc, extra);
+        a.plain_step = adj_plain_step<float>;
+        a.plain_ctx = &sc;
         e = mp::adjoint_run<float>(a, plan->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
