@@ -107,6 +107,41 @@ template <typename T> __global__ void k_add(T *a, const T *b, int64_t n)
     if (t < n) a[t] += b[t];
 }
 
+// several buffers per launch: clear a[i] (b == nullptr) or add b[i] into
+// a[i] and clear b[i]
+template <typename T> struct Bufs {
+    T *a[8];
+    T *b[8];
+    int64_t n[8];
+    int k = 0;
+    int64_t nmax = 0;
+    void push(T *x, int64_t m, T *y = nullptr)
+    {
+        a[k] = x;
+        b[k] = y;
+        n[k] = m;
+        k++;
+        if (m > nmax) nmax = m;
+    }
+};
+
+template <typename T> __global__ void k_clear_n(Bufs<T> f)
+{
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    for (int i = 0; i < f.k; i++)
+        if (t < f.n[i]) f.a[i][t] = T(0);
+}
+
+template <typename T> __global__ void k_add_clear_n(Bufs<T> f)
+{
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    for (int i = 0; i < f.k; i++)
+        if (t < f.n[i]) {
+            f.a[i][t] += f.b[i][t];
+            f.b[i][t] = T(0);
+        }
+}
+
 template <typename T> __global__ void k_copy(T *a, const T *b, int64_t n)
 {
     int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
@@ -448,6 +483,11 @@ template <typename T> hipError_t fill(T *a, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T> void clear_n(const Bufs<T> &f, hipStream_t s)
+{
+    if (f.k) k_clear_n<T><<<(unsigned)cdiv(f.nmax, B), B, 0, s>>>(f);
+}
+
 // forward recompute of one step from psi_n, keeping the pass records;
 // writes the step's result to out when out != nullptr
 template <typename T>
@@ -496,19 +536,29 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
     const unsigned cb = (unsigned)cdiv(N, B);
     hipError_t e = record_step<T>(a, w, psi_n, nullptr, s);
     if (e != hipSuccess) return e;
-    e = fill<T>(w.pnb, N, s);
-    for (int d = 0; d < g.nd; d++) e = fill<T>(w.Ab[d], nwalls(g, d), s);
+    {
+        Bufs<T> f;
+        f.push(w.pnb, N);
+        for (int d = 0; d < g.nd; d++) f.push(w.Ab[d], nwalls(g, d));
+        clear_n<T>(f, s);
+    }
     for (int it = n; it >= 2; it--) {
         const T *x = w.X[it - 1];
-        e = fill<T>(w.xb, N, s);
+        {
+            Bufs<T> f;
+            f.push(w.xb, N);
+            for (int d = 0; d < g.nd; d++) f.push(w.Vb[d], nwalls(g, d));
+            if (fct) {
+                f.push(w.bub, N);
+                f.push(w.bdb, N);
+            }
+            clear_n<T>(f, s);
+        }
         // corrective donor-cell pass
         k_donor_adj<T><<<cb, B, 0, s>>>(g, x, w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2], a.G,
                                         iga ? 1 : 0, w.yb, w.xb, w.Ab[0], w.Ab[1], w.Ab[2]);
         // limiter
-        for (int d = 0; d < g.nd; d++) e = fill<T>(w.Vb[d], nwalls(g, d), s);
         if (fct) {
-            e = fill<T>(w.bub, N, s);
-            e = fill<T>(w.bdb, N, s);
             for (int d = 0; d < g.nd; d++)
                 k_limit_adj<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
                     g, d, w.V[it - 1][d], w.bu[it - 1], w.bd[it - 1], w.Ab[d], w.Vb[d], w.bub,
@@ -522,19 +572,28 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
                                                                         nwalls(g, d));
         }
         // pseudo-velocity: to x and to the previous pass's advector
-        for (int d = 0; d < g.nd; d++) e = fill<T>(w.Ab[d], nwalls(g, d), s);
+        {
+            Bufs<T> f;
+            for (int d = 0; d < g.nd; d++) f.push(w.Ab[d], nwalls(g, d));
+            clear_n<T>(f, s);
+        }
         const T *cin[3];
         for (int d = 0; d < 3; d++) cin[d] = (it == 2) ? a.c[d] : w.W[it - 2][d];
         for (int d = 0; d < g.nd; d++)
             k_pseudo_adj<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
                 g, d, a.opts, x, cin[0], cin[1], cin[2], a.G, w.Vb[d], w.xb, w.Ab[0], w.Ab[1],
                 w.Ab[2]);
-        if (it == 2)
+        if (it == 2) {
+            // the first corrective pass reads the input advector: move its
+            // adjoint into the result and clear the buffer
+            Bufs<T> f;
+            int64_t m = 0;
             for (int d = 0; d < g.nd; d++) {
-                k_add<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(w.Cb[d], w.Ab[d],
-                                                                       nwalls(g, d));
-                e = fill<T>(w.Ab[d], nwalls(g, d), s);
+                f.push(w.Cb[d], nwalls(g, d), w.Ab[d]);
+                m = nwalls(g, d) > m ? nwalls(g, d) : m;
             }
+            k_add_clear_n<T><<<(unsigned)cdiv(m, B), B, 0, s>>>(f);
+        }
         T *t = w.yb;
         w.yb = w.xb;
         w.xb = t;

@@ -409,7 +409,7 @@ int64_t rows_per_chunk(int64_t n0, int64_t strips)
     int64_t chunks = target_waves / (strips > 0 ? strips : 1);
     if (chunks < 1) chunks = 1;
     int64_t th = cdiv(n0, chunks);
-    if (th < 32) th = 32;
+    if (th < 16) th = 16;
     return th;
 }
 

@@ -2,19 +2,28 @@
 // launches (the three-dimensional workload: third-order terms, infinite
 // gauge, variable G, open boundaries).
 //
-//   k_donor3d : donor-cell pass, one thread per cell, psi^n -> y1 (workspace)
+//   k_donor3d : donor-cell pass, psi^n -> y1 (workspace).  Each thread owns a
+//               (j, k) column and marches along i over a chunk of planes,
+//               keeping psi at i-1, i, i+1 and the dimension-0 walls in
+//               registers; in-plane neighbours are read through L1/L2.
 //   k_corr3d  : pseudo-velocity on every wall and the corrective pass,
-//               y1 -> psi^{n+1}.  A workgroup of 16 x 64 threads owns a
-//               (j, k) tile with a halo of two cells and marches along i.
-//               Each thread keeps its own column's planes in registers; the
-//               in-plane neighbours it needs come through LDS (two barriers
-//               per plane).  The pseudo-velocity of each wall is computed
-//               once: V0 by the cell above it, V1 / V2 by the cell after it.
+//               y1 -> psi^{n+1}.  A workgroup of 16 x 32 (FP64) or 16 x 64
+//               (FP32) threads owns a (j, k) tile with a halo of two cells and
+//               marches along i.  Each thread keeps its own column's planes in
+//               registers; the in-plane neighbours it needs come through LDS
+//               (two barriers per plane).  The pseudo-velocity of each wall is
+//               computed once: V0 by the cell above it, V1 / V2 by the cell
+//               after it.
 // Every global read goes through the boundary map (periodic wrap / open
 // clamp), so halo positions hold mapped values and the computed walls equal
-// the staged path's walls.
+// the staged path's walls.  A thread's (j, k) part of every address is fixed,
+// so the per-plane part is uniform scalar arithmetic.  Tiles are numbered so
+// that neighbouring tiles run on the same XCD and share its L2 for their
+// overlapping halo reads.
 #include "common.hpp"
 #include "kernels.hpp"
+
+#include <type_traits>
 
 namespace mp {
 namespace {
@@ -32,30 +41,9 @@ struct G3 {
     int bc0, bc1, bc2;
 };
 
-__device__ inline int64_t cix(const G3 &g, int i, int j, int k)
-{
-    return ((int64_t)wrap_cell(i, g.n0, g.bc0) * g.n1 + wrap_cell(j, g.n1, g.bc1)) * g.n2 +
-           wrap_cell(k, g.n2, g.bc2);
-}
-// wall arrays: c0 (n0+1, n1, n2), c1 (n0, n1+1, n2), c2 (n0, n1, n2+1)
-__device__ inline int64_t w0ix(const G3 &g, int f, int j, int k)
-{
-    return ((int64_t)wrap_wall(f, g.n0, g.bc0) * g.n1 + wrap_cell(j, g.n1, g.bc1)) * g.n2 +
-           wrap_cell(k, g.n2, g.bc2);
-}
-__device__ inline int64_t w1ix(const G3 &g, int i, int f, int k)
-{
-    return ((int64_t)wrap_cell(i, g.n0, g.bc0) * (g.n1 + 1) + wrap_wall(f, g.n1, g.bc1)) * g.n2 +
-           wrap_cell(k, g.n2, g.bc2);
-}
-__device__ inline int64_t w2ix(const G3 &g, int i, int j, int f)
-{
-    return ((int64_t)wrap_cell(i, g.n0, g.bc0) * g.n1 + wrap_cell(j, g.n1, g.bc1)) *
-               (g.n2 + 1) +
-           wrap_wall(f, g.n2, g.bc2);
-}
-
 // ---- donor-cell pass ----------------------------------------------------
+constexpr int DONOR_PLANES = 16;   // planes per thread column
+
 template <typename T, bool HAS_G>
 __global__ void __launch_bounds__(256) k_donor3d(G3 g, const T *__restrict__ x,
                                                  const T *__restrict__ c0,
@@ -63,32 +51,55 @@ __global__ void __launch_bounds__(256) k_donor3d(G3 g, const T *__restrict__ x,
                                                  const T *__restrict__ c2,
                                                  const T *__restrict__ G, T *__restrict__ y)
 {
-    int k = blockIdx.x * 64 + (threadIdx.x & 63);
-    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    int i = blockIdx.z;
+    const int k = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int i0 = blockIdx.z * DONOR_PLANES;
+    const int i1 = min(i0 + DONOR_PLANES, g.n0);
     if (k >= g.n2 || j >= g.n1) return;
-    int64_t o = ((int64_t)i * g.n1 + j) * g.n2 + k;
-    T xc = x[o];
-    T acc = T(0);
-    {
-        T ul = c0[w0ix(g, i, j, k)], uh = c0[w0ix(g, i + 1, j, k)];
-        T flo = pos(ul) * x[cix(g, i - 1, j, k)] + neg(ul) * xc;
-        T fhi = pos(uh) * xc + neg(uh) * x[cix(g, i + 1, j, k)];
-        acc += fhi - flo;
+    const int64_t pl = (int64_t)g.n1 * g.n2;                 // cell / c0 plane
+    const int64_t pl1 = (int64_t)(g.n1 + 1) * g.n2;          // c1 plane
+    const int64_t pl2 = (int64_t)g.n1 * (g.n2 + 1);          // c2 plane
+    // in-plane offsets (fixed for the column)
+    const int64_t o = (int64_t)j * g.n2 + k;
+    const int64_t ojm = (int64_t)wrap_cell(j - 1, g.n1, g.bc1) * g.n2 + k;
+    const int64_t ojp = (int64_t)wrap_cell(j + 1, g.n1, g.bc1) * g.n2 + k;
+    const int64_t okm = (int64_t)j * g.n2 + wrap_cell(k - 1, g.n2, g.bc2);
+    const int64_t okp = (int64_t)j * g.n2 + wrap_cell(k + 1, g.n2, g.bc2);
+    const int64_t w1lo = (int64_t)j * g.n2 + k;
+    const int64_t w1hi = (int64_t)wrap_wall(j + 1, g.n1, g.bc1) * g.n2 + k;
+    const int64_t w2lo = (int64_t)j * (g.n2 + 1) + k;
+    const int64_t w2hi = (int64_t)j * (g.n2 + 1) + wrap_wall(k + 1, g.n2, g.bc2);
+
+    T xm = x[wrap_cell(i0 - 1, g.n0, g.bc0) * pl + o];
+    T xc = x[i0 * pl + o];
+    T ulo = c0[i0 * pl + o];
+    for (int i = i0; i < i1; i++) {
+        const int64_t pc = i * pl;
+        T xp = x[wrap_cell(i + 1, g.n0, g.bc0) * pl + o];
+        T uhi = c0[wrap_wall(i + 1, g.n0, g.bc0) * pl + o];
+        T acc = T(0);
+        {
+            T flo = pos(ulo) * xm + neg(ulo) * xc;
+            T fhi = pos(uhi) * xc + neg(uhi) * xp;
+            acc += fhi - flo;
+        }
+        {
+            T ul = c1[i * pl1 + w1lo], uh = c1[i * pl1 + w1hi];
+            T flo = pos(ul) * x[pc + ojm] + neg(ul) * xc;
+            T fhi = pos(uh) * xc + neg(uh) * x[pc + ojp];
+            acc += fhi - flo;
+        }
+        {
+            T ul = c2[i * pl2 + w2lo], uh = c2[i * pl2 + w2hi];
+            T flo = pos(ul) * x[pc + okm] + neg(ul) * xc;
+            T fhi = pos(uh) * xc + neg(uh) * x[pc + okp];
+            acc += fhi - flo;
+        }
+        y[pc + o] = xc - (HAS_G ? acc / G[pc + o] : acc);
+        xm = xc;
+        xc = xp;
+        ulo = uhi;
     }
-    {
-        T ul = c1[w1ix(g, i, j, k)], uh = c1[w1ix(g, i, j + 1, k)];
-        T flo = pos(ul) * x[cix(g, i, j - 1, k)] + neg(ul) * xc;
-        T fhi = pos(uh) * xc + neg(uh) * x[cix(g, i, j + 1, k)];
-        acc += fhi - flo;
-    }
-    {
-        T ul = c2[w2ix(g, i, j, k)], uh = c2[w2ix(g, i, j, k + 1)];
-        T flo = pos(ul) * x[cix(g, i, j, k - 1)] + neg(ul) * xc;
-        T fhi = pos(uh) * xc + neg(uh) * x[cix(g, i, j, k + 1)];
-        acc += fhi - flo;
-    }
-    y[o] = xc - (HAS_G ? acc / G[o] : acc);
 }
 
 template <typename T, bool IGA> __device__ inline T fr(T num, T den, T m)
@@ -99,7 +110,8 @@ template <typename T, bool IGA> __device__ inline T fr(T num, T den, T m)
 
 // ---- pseudo-velocity + corrective pass ---------------------------------
 template <typename T, bool HAS_G, bool IGA, bool TOT>
-__global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const T *__restrict__ y1,
+__global__ void __launch_bounds__(TR * TileL<T>::v)
+k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__ y1,
                                                     const T *__restrict__ c0,
                                                     const T *__restrict__ c1,
                                                     const T *__restrict__ c2,
@@ -119,9 +131,13 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
     __shared__ T V2B[TR][TL];      // V2 at plane t-2
 
     const int l = threadIdx.x % TL, r = threadIdx.x / TL;
-    const int tiles_k = (g.n2 + TL - 2 * HALO - 1) / (TL - 2 * HALO);
-    const int tiles_j = (g.n1 + TR - 2 * HALO - 1) / (TR - 2 * HALO);
-    int b = blockIdx.x;
+    // The hardware deals workgroup b to XCD b % 8; tile q is numbered so
+    // that consecutive tiles (which share halo cells) land on one XCD.
+    int b;
+    {
+        const int x = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
+        b = x * per + (x < rem ? x : rem) + (blockIdx.x >> 3);
+    }
     const int tk = b % tiles_k;
     b /= tiles_k;
     const int tj = b % tiles_j;
@@ -131,6 +147,15 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
     const int i0 = ch * th, i1 = min(i0 + th, g.n0);
     const bool out_pos = r >= HALO && r < TR - HALO && l >= HALO && l < TL - HALO &&
                          jj < g.n1 && kk < g.n2;
+    // the (j, k) part of this thread's addresses; planes add a uniform part
+    const int jw = wrap_cell(jj, g.n1, g.bc1), kw = wrap_cell(kk, g.n2, g.bc2);
+    const int64_t pl = (int64_t)g.n1 * g.n2, pl1 = (int64_t)(g.n1 + 1) * g.n2,
+                  pl2 = (int64_t)g.n1 * (g.n2 + 1);
+    const T *y1p = y1 + ((int64_t)jw * g.n2 + kw);
+    const T *Gp = HAS_G ? G + ((int64_t)jw * g.n2 + kw) : nullptr;
+    const T *c0p = c0 + ((int64_t)jw * g.n2 + kw);
+    const T *c1p = c1 + ((int64_t)wrap_wall(jj, g.n1, g.bc1) * g.n2 + kw);
+    const T *c2p = c2 + ((int64_t)jw * (g.n2 + 1) + wrap_wall(kk, g.n2, g.bc2));
 
     // own-column queues (index 0 = oldest)
     T yq[4] = {T(0), T(0), T(0), T(0)};  // y1 planes t-3..t
@@ -143,27 +168,28 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
 
     const int t_begin = i0 - 2, t_end = i1 + 1;
     // plane t+1 is loaded while plane t is processed
-    T y_nx = y1[cix(g, t_begin, jj, kk)];
-    T g_nx = HAS_G ? G[cix(g, t_begin, jj, kk)] : T(1);
-    T c0_nx = c0[w0ix(g, t_begin, jj, kk)];
-    T c1_nx = c1[w1ix(g, t_begin, jj, kk)];
-    T c2_nx = c2[w2ix(g, t_begin, jj, kk)];
-    for (int t = t_begin; t <= t_end; t++) {
+    T y_nx, g_nx = T(1), c0_nx, c1_nx, c2_nx;
+    auto load = [&](int t) {
+        const int ic = wrap_cell(t, g.n0, g.bc0), iw = wrap_wall(t, g.n0, g.bc0);
+        y_nx = y1p[ic * pl];
+        if (HAS_G) g_nx = Gp[ic * pl];
+        c0_nx = c0p[iw * pl];
+        c1_nx = c1p[ic * pl1];
+        c2_nx = c2p[ic * pl2];
+    };
+    load(t_begin);
+    // one plane; the LDS ring slot of plane t is its phase (t - t_begin) mod 3,
+    // a compile-time constant in each of the three unrolled copies
+    auto plane = [&](auto phase, int t) {
+        constexpr int s0 = decltype(phase)::value;
+        constexpr int sm1 = (s0 + 2) % 3, sm2 = (s0 + 1) % 3;
         T y_new = y_nx, g_new = g_nx, c0_new = c0_nx, c1_new = c1_nx, c2_new = c2_nx;
-        if (t < t_end) {
-            y_nx = y1[cix(g, t + 1, jj, kk)];
-            if (HAS_G) g_nx = G[cix(g, t + 1, jj, kk)];
-            c0_nx = c0[w0ix(g, t + 1, jj, kk)];
-            c1_nx = c1[w1ix(g, t + 1, jj, kk)];
-            c2_nx = c2[w2ix(g, t + 1, jj, kk)];
-        }
+        load(t + 1);   // wrapped: past the chunk it reads valid, unused planes
         yq[0] = yq[1]; yq[1] = yq[2]; yq[2] = yq[3]; yq[3] = y_new;
         gq[0] = gq[1]; gq[1] = gq[2]; gq[2] = g_new;
         c0q[0] = c0q[1]; c0q[1] = c0q[2]; c0q[2] = c0_new;
         c1q[0] = c1q[1]; c1q[1] = c1q[2]; c1q[2] = c1_new;
         c2q[0] = c2q[1]; c2q[1] = c2q[2]; c2q[2] = c2_new;
-        const int s0 = ((t % 3) + 3) % 3;          // slot of plane t
-        const int sm1 = (s0 + 2) % 3, sm2 = (s0 + 1) % 3;
 
         // ---- write phase ----
         Y[s0][r][l] = y_new;
@@ -325,6 +351,12 @@ __global__ void __launch_bounds__(TR * TileL<T>::v) k_corr3d(G3 g, int th, const
         v1_keep = v1;
         v2_keep = v2;
         __syncthreads();
+    };
+    // whole blocks of three planes; iterations past t_end store nothing
+    for (int t = t_begin; t <= t_end; t += 3) {
+        plane(std::integral_constant<int, 0>{}, t);
+        plane(std::integral_constant<int, 1>{}, t + 1);
+        plane(std::integral_constant<int, 2>{}, t + 2);
     }
 }
 
@@ -334,7 +366,9 @@ bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], c
 {
     if (nd != 3 || !(n_iters == 1 || n_iters == 2) || (opts & OPT_FCT)) return false;
     if (n[0] >= 65536 || n[1] >= (1 << 30) || n[2] >= (1 << 30)) return false;
-    // halo coordinates must stay within one period of a periodic dimension
+    // halo coordinates (and the planes read past a chunk) must stay within
+    // one period of a periodic dimension
+    if (bc[0] == BC_PERIODIC && n[0] < 5) return false;
     if (bc[1] == BC_PERIODIC && n[1] < TR) return false;
     if (bc[2] == BC_PERIODIC && n[2] < 64) return false;
     return true;
@@ -346,7 +380,7 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
                         hipStream_t s)
 {
     G3 g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
-    dim3 gd((unsigned)cdiv(g.n2, 64), (unsigned)cdiv(g.n1, 4), (unsigned)g.n0);
+    dim3 gd((unsigned)cdiv(g.n2, 64), (unsigned)cdiv(g.n1, 4), (unsigned)cdiv(g.n0, DONOR_PLANES));
     T *y1 = (n_iters == 1) ? psi_out : y1buf;
     if (G)
         k_donor3d<T, true><<<gd, 256, 0, s>>>(g, psi_n, c0, c1, c2, G, y1);
@@ -362,7 +396,8 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
     unsigned blocks = (unsigned)tiles_k * tiles_j * chunks;
     const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
 #define MP_CORR(HG, IG, TO) \
-    k_corr3d<T, HG, IG, TO><<<blocks, TR * TL, 0, s>>>(g, th, y1, c0, c1, c2, G, psi_out)
+    k_corr3d<T, HG, IG, TO><<<blocks, TR * TL, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, y1, \
+                                                      c0, c1, c2, G, psi_out)
     if (G) {
         if (iga) { if (tot) MP_CORR(true, true, true); else MP_CORR(true, true, false); }
         else { if (tot) MP_CORR(true, false, true); else MP_CORR(true, false, false); }
