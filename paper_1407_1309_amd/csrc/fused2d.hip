@@ -58,54 +58,6 @@ __device__ inline double from_right(double v)
     return __hiloint2double(lane_from_right(__double2hiint(v)), lane_from_right(__double2loint(v)));
 }
 
-// Quotients.
-// FP64: the quotients of a stage are formed together.  When every lane's
-// divisors are zero or normal and below 2^1000 in magnitude (a wave-uniform
-// test), each quotient is n * r with r the hardware reciprocal (about 2^-23
-// accurate) refined by one Newton step: within 18 ulp of the rounded
-// quotient (measured over 2^20 random operands), four instructions instead
-// of the eleven of the IEEE sequence.  Otherwise the whole wave takes the
-// IEEE division.  A zero divisor's quotient is discarded by every caller.
-// FP32: the hardware reciprocal refined by one Newton step when the divisor
-// is normal or zero (a per-lane branch, cheap in FP32), else the IEEE
-// division.
-template <int K> __device__ __forceinline__ void quotients(const double (&n)[K],
-                                                          const double (&d)[K], double (&q)[K])
-{
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < K; k++)
-        ok = ok && __builtin_amdgcn_class(d[k], 0x168) && fabs(d[k]) < 0x1p1000;
-    if (__builtin_amdgcn_ballot_w64(!ok) == 0) {
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            double r = __builtin_amdgcn_rcp(d[k]);
-            r = fma(fma(-d[k], r, 1.0), r, r);
-            q[k] = n[k] * r;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < K; k++) q[k] = n[k] / d[k];
-    }
-}
-
-__device__ inline float qdiv(float n, float d)
-{
-    if (__builtin_amdgcn_classf(d, 0x168)) {      // +-normal or +-zero
-        float r = __builtin_amdgcn_rcpf(d);
-        float q = n * r;
-        return fmaf(fmaf(-d, q, n), r, q);
-    }
-    return n / d;
-}
-
-template <int K> __device__ __forceinline__ void quotients(const float (&n)[K],
-                                                         const float (&d)[K], float (&q)[K])
-{
-#pragma unroll
-    for (int k = 0; k < K; k++) q[k] = qdiv(n[k], d[k]);
-}
-
 // ---- register row-queues ------------------------------------------------
 // The row loop is unrolled by U iterations and every queue is a ring whose
 // depth divides U, so the slot holding "the row pushed `age` iterations ago"

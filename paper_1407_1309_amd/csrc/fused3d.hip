@@ -120,15 +120,15 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
 {
     constexpr int TL = TileL<T>::v;
     // LDS planes [TR][TL]
-    __shared__ T Y[3][TR][TL];     // y1 planes (ring of three)
-    __shared__ T S1[TR][TL];       // c1(t-2) + c1(t-1)        (V0 cross mean)
-    __shared__ T S2[TR][TL];       // c2(t-2) + c2(t-1)
-    __shared__ T Q0[TR][TL];       // c0(wall t-1) + c0(wall t)  (V1, V2 cross mean)
-    __shared__ T C1P[TR][TL];      // c1(t-1)
-    __shared__ T C2P[TR][TL];      // c2(t-1)
-    __shared__ T GP[TR][TL];       // G(t-1)
-    __shared__ T V1B[TR][TL];      // V1 at plane t-2
-    __shared__ T V2B[TR][TL];      // V2 at plane t-2
+    __shared__ T Y[4][TR][TL];     // y1 planes (ring of four)
+    __shared__ T S1[2][TR][TL];       // c1(t-2) + c1(t-1)        (V0 cross mean)
+    __shared__ T S2[2][TR][TL];       // c2(t-2) + c2(t-1)
+    __shared__ T Q0[2][TR][TL];       // c0(wall t-1) + c0(wall t)  (V1, V2 cross mean)
+    __shared__ T C1P[2][TR][TL];      // c1(t-1)
+    __shared__ T C2P[2][TR][TL];      // c2(t-1)
+    __shared__ T GP[2][TR][TL];       // G(t-1)
+    __shared__ T V1B[2][TR][TL];      // V1 at plane t-2
+    __shared__ T V2B[2][TR][TL];      // V2 at plane t-2
 
     const int l = threadIdx.x % TL, r = threadIdx.x / TL;
     // The hardware deals workgroup b to XCD b % 8; tile q is numbered so
@@ -178,11 +178,15 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
         c2_nx = c2p[ic * pl2];
     };
     load(t_begin);
-    // one plane; the LDS ring slot of plane t is its phase (t - t_begin) mod 3,
-    // a compile-time constant in each of the three unrolled copies
+    // One plane.  The LDS ring slot of plane t is its phase (t - t_begin)
+    // mod 4 and the other per-plane arrays alternate between two sets, both
+    // compile-time constants in each of the four unrolled copies.  With four
+    // y1 slots and two sets, one barrier per plane suffices: a thread writing
+    // plane t+2 has passed the barrier of plane t+1, which every thread
+    // reaches only after it has finished reading plane t's arrays.
     auto plane = [&](auto phase, int t) {
         constexpr int s0 = decltype(phase)::value;
-        constexpr int sm1 = (s0 + 2) % 3, sm2 = (s0 + 1) % 3;
+        constexpr int sm1 = (s0 + 3) % 4, sm2 = (s0 + 2) % 4, bs = s0 & 1;
         T y_new = y_nx, g_new = g_nx, c0_new = c0_nx, c1_new = c1_nx, c2_new = c2_nx;
         load(t + 1);   // wrapped: past the chunk it reads valid, unused planes
         yq[0] = yq[1]; yq[1] = yq[2]; yq[2] = yq[3]; yq[3] = y_new;
@@ -193,14 +197,14 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
 
         // ---- write phase ----
         Y[s0][r][l] = y_new;
-        S1[r][l] = c1q[0] + c1q[1];
-        S2[r][l] = c2q[0] + c2q[1];
-        Q0[r][l] = c0q[1] + c0q[2];
-        C1P[r][l] = c1q[1];
-        C2P[r][l] = c2q[1];
-        GP[r][l] = gq[1];
-        V1B[r][l] = v1_keep;
-        V2B[r][l] = v2_keep;
+        S1[bs][r][l] = c1q[0] + c1q[1];
+        S2[bs][r][l] = c2q[0] + c2q[1];
+        Q0[bs][r][l] = c0q[1] + c0q[2];
+        C1P[bs][r][l] = c1q[1];
+        C2P[bs][r][l] = c2q[1];
+        GP[bs][r][l] = gq[1];
+        V1B[bs][r][l] = v1_keep;
+        V2B[bs][r][l] = v2_keep;
         __syncthreads();
 
         // neighbour accessors (clamped to the tile; only halo lanes / rows
@@ -208,16 +212,25 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
         const int rm1 = max(r - 1, 0), rm2 = max(r - 2, 0), rp1 = min(r + 1, TR - 1);
         const int lm1 = max(l - 1, 0), lm2 = max(l - 2, 0), lp1 = min(l + 1, TL - 1);
 
+        // 1 / mean G at the three walls this thread owns (V0 at wall t-1,
+        // V1 at wall jj and V2 at wall kk of plane t-1)
+        T igw[3] = {T(1), T(1), T(1)};
+        if (HAS_G) {
+            T one[3] = {T(1), T(1), T(1)};
+            T gb[3] = {T(0.5) * (gq[0] + gq[1]), T(0.5) * (GP[bs][rm1][l] + GP[bs][r][l]),
+                       T(0.5) * (GP[bs][r][lm1] + GP[bs][r][l])};
+            quotients<3>(one, gb, igw);
+        }
         // ---- V0 at wall t-1 (planes t-2 | t-1), own (j, k) ----
         T v0;
         {
             T xL = yq[1], xR = yq[2];
-            T ig = T(1) / (T(0.5) * (gq[0] + gq[1]));   // 1 / mean G at the wall
+            T ig = igw[0];
             T u = c0q[1];
             T A = fr<T, IGA>(xR - xL, xR + xL, T(2));
             T v = (fabs(u) - u * u * ig) * A;
-            T cb1 = T(0.25) * (S1[r][l] + S1[rp1][l]);
-            T cb2 = T(0.25) * (S2[r][l] + S2[r][lp1]);
+            T cb1 = T(0.25) * (S1[bs][r][l] + S1[bs][rp1][l]);
+            T cb2 = T(0.25) * (S2[bs][r][l] + S2[bs][r][lp1]);
             // o = 1 (j)
             T a1 = Y[sm1][rp1][l], b1 = Y[sm2][rp1][l], e1 = Y[sm1][rm1][l], f1 = Y[sm2][rm1][l];
             v -= T(0.5) * u * cb1 * ig * fr<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
@@ -249,12 +262,12 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
         T v1;
         {
             T xL = Y[sm1][rm1][l], xR = Y[sm1][r][l];
-            T ig = T(1) / (T(0.5) * (GP[rm1][l] + GP[r][l]));
-            T u = C1P[r][l];
+            T ig = igw[1];
+            T u = C1P[bs][r][l];
             T A = fr<T, IGA>(xR - xL, xR + xL, T(2));
             T v = (fabs(u) - u * u * ig) * A;
-            T cb0 = T(0.25) * (Q0[rm1][l] + Q0[r][l]);
-            T cb2 = T(0.25) * ((C2P[rm1][l] + C2P[rm1][lp1]) + (C2P[r][l] + C2P[r][lp1]));
+            T cb0 = T(0.25) * (Q0[bs][rm1][l] + Q0[bs][r][l]);
+            T cb2 = T(0.25) * ((C2P[bs][rm1][l] + C2P[bs][rm1][lp1]) + (C2P[bs][r][l] + C2P[bs][r][lp1]));
             // o = 0 (i): R+e0 = plane t at r, L+e0 = plane t at r-1, minus plane t-2
             T a0 = Y[s0][r][l], b0 = Y[s0][rm1][l], e0 = Y[sm2][r][l], f0 = Y[sm2][rm1][l];
             v -= T(0.5) * u * cb0 * ig * fr<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
@@ -287,12 +300,12 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
         T v2;
         {
             T xL = Y[sm1][r][lm1], xR = Y[sm1][r][l];
-            T ig = T(1) / (T(0.5) * (GP[r][lm1] + GP[r][l]));
-            T u = C2P[r][l];
+            T ig = igw[2];
+            T u = C2P[bs][r][l];
             T A = fr<T, IGA>(xR - xL, xR + xL, T(2));
             T v = (fabs(u) - u * u * ig) * A;
-            T cb0 = T(0.25) * (Q0[r][lm1] + Q0[r][l]);
-            T cb1 = T(0.25) * ((C1P[r][lm1] + C1P[rp1][lm1]) + (C1P[r][l] + C1P[rp1][l]));
+            T cb0 = T(0.25) * (Q0[bs][r][lm1] + Q0[bs][r][l]);
+            T cb1 = T(0.25) * ((C1P[bs][r][lm1] + C1P[bs][rp1][lm1]) + (C1P[bs][r][l] + C1P[bs][rp1][l]));
             // o = 0 (i)
             T a0 = Y[s0][r][l], b0 = Y[s0][r][lm1], e0 = Y[sm2][r][l], f0 = Y[sm2][r][lm1];
             v -= T(0.5) * u * cb0 * ig * fr<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
@@ -329,8 +342,8 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
         if (p >= i0 && p < i1 && out_pos) {
             T x = yq[1];
             T V0lo = v0q[0], V0hi = v0q[1];
-            T V1lo = V1B[r][l], V1hi = V1B[rp1][l];
-            T V2lo = V2B[r][l], V2hi = V2B[r][lp1];
+            T V1lo = V1B[bs][r][l], V1hi = V1B[bs][rp1][l];
+            T V2lo = V2B[bs][r][l], V2hi = V2B[bs][r][lp1];
             T f0lo, f0hi, f1lo, f1hi, f2lo, f2hi;
             if (IGA) {
                 f0lo = V0lo; f0hi = V0hi; f1lo = V1lo; f1hi = V1hi; f2lo = V2lo; f2hi = V2hi;
@@ -346,17 +359,22 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
             acc += f0hi - f0lo;
             acc += f1hi - f1lo;
             acc += f2hi - f2lo;
-            out[((int64_t)p * g.n1 + jj) * g.n2 + kk] = x - (HAS_G ? acc / gq[0] : acc);
+            if (HAS_G) {
+                T nn[1] = {acc}, dd[1] = {gq[0]}, qq[1];
+                quotients<1>(nn, dd, qq);
+                acc = qq[0];
+            }
+            out[((int64_t)p * g.n1 + jj) * g.n2 + kk] = x - acc;
         }
         v1_keep = v1;
         v2_keep = v2;
-        __syncthreads();
     };
-    // whole blocks of three planes; iterations past t_end store nothing
-    for (int t = t_begin; t <= t_end; t += 3) {
+    // whole blocks of four planes; iterations past t_end store nothing
+    for (int t = t_begin; t <= t_end; t += 4) {
         plane(std::integral_constant<int, 0>{}, t);
         plane(std::integral_constant<int, 1>{}, t + 1);
         plane(std::integral_constant<int, 2>{}, t + 2);
+        plane(std::integral_constant<int, 3>{}, t + 3);
     }
 }
 
@@ -368,7 +386,7 @@ bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], c
     if (n[0] >= 65536 || n[1] >= (1 << 30) || n[2] >= (1 << 30)) return false;
     // halo coordinates (and the planes read past a chunk) must stay within
     // one period of a periodic dimension
-    if (bc[0] == BC_PERIODIC && n[0] < 5) return false;
+    if (bc[0] == BC_PERIODIC && n[0] < 6) return false;
     if (bc[1] == BC_PERIODIC && n[1] < TR) return false;
     if (bc[2] == BC_PERIODIC && n[2] < 64) return false;
     return true;
