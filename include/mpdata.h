@@ -193,6 +193,21 @@ int mpdata_step_batched(mpdata_plan *plan, void *psi_packed,
                         const void *c0_packed, const void *c1_packed,
                         int n_steps, int use_graph);
 
+/* Tiling of the batched launch: chunks of tile_rows rows (0 = the default,
+ * 64) and the tile order (xcd_order = 0: grid by grid; 1: numbered so that
+ * consecutive tiles, which share halo columns, run on the same XCD).
+ * Results do not depend on either (bit for bit).  Rebuilds the work list in
+ * the workspace (waits for the plan's stream) and drops cached graphs. */
+int mpdata_set_batched_tiling(mpdata_plan *plan, int tile_rows, int xcd_order);
+
+/* Batched autotuner: times one batched step on the caller's buffers for
+ * every candidate chunk length (16..256 rows) and both tile orders (psi is
+ * read, not modified; the result goes to workspace), keeps the fastest and
+ * returns it.  Waits for completion. */
+int mpdata_autotune_batched(mpdata_plan *plan, const void *psi_packed,
+                            const void *c0_packed, const void *c1_packed,
+                            int *out_tile_rows, int *out_xcd_order);
+
 /* Same update, one ordinary launch sequence per grid (the baseline the
  * batched launch is measured against). */
 int mpdata_step_per_grid(mpdata_plan *plan, void *psi_packed,

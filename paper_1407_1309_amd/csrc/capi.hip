@@ -154,6 +154,7 @@ struct mpdata_plan {
     void *batch_alt = nullptr;
     int64_t batch_psi_total = 0, batch_c0_total = 0, batch_c1_total = 0;
     int batch_tiles = 0;
+    int batch_xcd = 0;   // tile order: 0 grid by grid, 1 grouped per XCD
     // graph cache (batched); graphs are captured on a library-owned stream
     // (capture is not allowed on the legacy default stream) and launched on
     // the plan's stream
@@ -571,6 +572,49 @@ int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const voi
     return MPDATA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+void drop_graph(mpdata_plan *p)
+{
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+    p->g_steps = -1;
+}
+
+// (Re)build the batched work list for chunks of `rows` rows and upload it to
+// the workspace (waits for the upload).  Cached graphs refer to the old list
+// and are dropped.
+int batched_table(mpdata_plan *p, int rows)
+{
+    if (rows < 1 || rows > (1 << 20)) return fail(MPDATA_EINVAL, "tile rows %d out of range", rows);
+    int tc = mp::fused2d_strip_cols(p->desc.n_iters, p->desc.opts);
+    int64_t tiles = 0;
+    for (mp::BatchGrid &G : p->grids) {
+        G.tiles_w = (int)mp::cdiv(G.n1, tc);
+        G.tile_begin = (int)tiles;
+        tiles += (int64_t)G.tiles_w * mp::cdiv(G.n0, rows);
+        if (tiles > (int64_t)1 << 30) return fail(MPDATA_EINVAL, "too many tiles");
+    }
+    hipError_t e = hipStreamSynchronize(p->stream);   // no launch may still read the old list
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->grids_dev, p->grids.data(), sizeof(mp::BatchGrid) * p->grids.size(),
+                           hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "batched table upload");
+    p->batch_tiles = (int)tiles;
+    p->tile_rows = rows;
+    drop_graph(p);
+    return MPDATA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 // ------------------------------------------------------------------ batched
 size_t mpdata_batched_workspace_bytes(int n_grids, const int64_t *shapes, int dtype, int n_iters,
                                       uint32_t opts, int bc)
@@ -622,10 +666,8 @@ int mpdata_batched_init(int n_grids, const int64_t *shapes, int dtype, int n_ite
     p->stream = (hipStream_t)hip_stream;
     p->kernel = MPDATA_KERNEL_FUSED;
     memset(&p->L, 0, sizeof p->L);
-    int tr = mp::fused2d_tile_rows(), tc = mp::fused2d_strip_cols(n_iters, opts);
     p->grids.resize(n_grids);
     int64_t op = 0, o0 = 0, o1 = 0;
-    int64_t tiles = 0;
     for (int i = 0; i < n_grids; i++) {
         mp::BatchGrid &G = p->grids[i];
         G.n0 = shapes[2 * i];
@@ -633,30 +675,20 @@ int mpdata_batched_init(int n_grids, const int64_t *shapes, int dtype, int n_ite
         G.off_psi = op;
         G.off_c0 = o0;
         G.off_c1 = o1;
-        G.tiles_w = (int)mp::cdiv(G.n1, tc);
-        G.tile_begin = (int)tiles;
-        tiles += (int64_t)G.tiles_w * mp::cdiv(G.n0, tr);
         op += G.n0 * G.n1;
         o0 += (G.n0 + 1) * G.n1;
         o1 += G.n0 * (G.n1 + 1);
     }
-    if (tiles > (int64_t)1 << 30) {
-        delete p;
-        return fail(MPDATA_EINVAL, "too many tiles");
-    }
-    p->batch_tiles = (int)tiles;
     p->batch_psi_total = op;
     p->batch_c0_total = o0;
     p->batch_c1_total = o1;
     Carver c(workspace);
     p->grids_dev = (mp::BatchGrid *)c.take(sizeof(mp::BatchGrid) * n_grids);
     p->batch_alt = c.take(dsize(dtype) * op);
-    hipError_t e = hipMemcpyAsync(p->grids_dev, p->grids.data(), sizeof(mp::BatchGrid) * n_grids,
-                                  hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) {
+    int rc = batched_table(p, mp::fused2d_tile_rows());
+    if (rc) {
         delete p;
-        return hip_fail(e, "batched table upload");
+        return rc;
     }
     *out = p;
     return MPDATA_OK;
@@ -681,8 +713,8 @@ hipError_t batched_launches(mpdata_plan *p, T *psi, const T *c0, const T *c1, in
     }
     for (int s = 0; s < n_steps; s++) {
         e = mp::fused2d_batched_step<T>(p->grids_dev, (int)p->grids.size(), p->batch_tiles,
-                                        p->desc.bc[0], p->desc.n_iters, p->desc.opts, cur, nxt,
-                                        c0, c1, p->stream);
+                                        p->desc.bc[0], p->desc.n_iters, p->desc.opts,
+                                        p->tile_rows, p->batch_xcd, cur, nxt, c0, c1, p->stream);
         if (e != hipSuccess) return e;
         T *t = cur;
         cur = nxt;
@@ -744,14 +776,7 @@ int mpdata_step_batched(mpdata_plan *plan, void *psi, const void *c0, const void
     bool hit = plan->gexec && plan->g_key[0] == psi && plan->g_key[1] == c0 &&
                plan->g_key[2] == c1 && plan->g_steps == n_steps;
     if (!hit) {
-        if (plan->gexec) {
-            (void)hipGraphExecDestroy(plan->gexec);
-            plan->gexec = nullptr;
-        }
-        if (plan->graph) {
-            (void)hipGraphDestroy(plan->graph);
-            plan->graph = nullptr;
-        }
+        drop_graph(plan);
         if (!plan->cap_stream) {
             hipError_t e = hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking);
             if (e != hipSuccess) {
@@ -788,6 +813,71 @@ int mpdata_step_batched(mpdata_plan *plan, void *psi, const void *c0, const void
     }
     hipError_t e = hipGraphLaunch(plan->gexec, plan->stream);
     return e == hipSuccess ? MPDATA_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int mpdata_set_batched_tiling(mpdata_plan *plan, int tile_rows, int xcd_order)
+{
+    if (!plan || !plan->batched) return fail(MPDATA_EINVAL, "not a batched plan");
+    if (tile_rows < 0) return fail(MPDATA_EINVAL, "tile rows %d < 0", tile_rows);
+    plan->batch_xcd = xcd_order ? 1 : 0;
+    drop_graph(plan);
+    return batched_table(plan, tile_rows ? tile_rows : mp::fused2d_tile_rows());
+}
+
+int mpdata_autotune_batched(mpdata_plan *plan, const void *psi, const void *c0, const void *c1,
+                            int *out_tile_rows, int *out_xcd_order)
+{
+    if (!plan || !plan->batched) return fail(MPDATA_EINVAL, "not a batched plan");
+    if (!psi || !c0 || !c1 || !out_tile_rows || !out_xcd_order)
+        return fail(MPDATA_EINVAL, "NULL argument");
+    static const int cand[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+    const bool f64 = plan->desc.dtype == MPDATA_F64;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best_rows = plan->tile_rows, best_x = plan->batch_xcd, rc = MPDATA_OK;
+    float best = 0.0f;
+    // one step from psi into the workspace buffer (psi itself is not written)
+    auto one = [&]() -> hipError_t {
+        return f64 ? mp::fused2d_batched_step<double>(
+                         plan->grids_dev, (int)plan->grids.size(), plan->batch_tiles,
+                         plan->desc.bc[0], plan->desc.n_iters, plan->desc.opts, plan->tile_rows,
+                         plan->batch_xcd, (const double *)psi, (double *)plan->batch_alt,
+                         (const double *)c0, (const double *)c1, plan->stream)
+                   : mp::fused2d_batched_step<float>(
+                         plan->grids_dev, (int)plan->grids.size(), plan->batch_tiles,
+                         plan->desc.bc[0], plan->desc.n_iters, plan->desc.opts, plan->tile_rows,
+                         plan->batch_xcd, (const float *)psi, (float *)plan->batch_alt,
+                         (const float *)c0, (const float *)c1, plan->stream);
+    };
+    for (int x = 0; x < 2 && e == hipSuccess && rc == MPDATA_OK; x++)
+        for (int rows : cand) {
+            plan->batch_xcd = x;
+            rc = batched_table(plan, rows);
+            if (rc) break;
+            e = one();                                   // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, plan->stream);
+            for (int r = 0; r < 3 && e == hipSuccess; r++) e = one();
+            if (e == hipSuccess) e = hipEventRecord(e1, plan->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (best == 0.0f || ms < best) {
+                best = ms;
+                best_rows = rows;
+                best_x = x;
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) rc = hip_fail(e, "batched autotune");
+    plan->batch_xcd = best_x;
+    int rc2 = batched_table(plan, best_rows);
+    if (rc == MPDATA_OK) rc = rc2;
+    *out_tile_rows = plan->tile_rows;
+    *out_xcd_order = plan->batch_xcd;
+    return rc;
 }
 
 int mpdata_step_per_grid(mpdata_plan *plan, void *psi, const void *c0, const void *c1,

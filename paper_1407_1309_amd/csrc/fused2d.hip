@@ -366,7 +366,8 @@ __global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int st
 
 template <typename T, int NI, bool FCT>
 __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__restrict__ grids,
-                                                          int n_grids, int th,
+                                                          int n_grids, int th, int n_tiles,
+                                                          int xcd_order,
                                                           const T *__restrict__ psi_n,
                                                           T *__restrict__ psi_out,
                                                           const T *__restrict__ c0,
@@ -374,6 +375,13 @@ __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__res
 {
     using C = Cfg<NI, FCT>;
     int b = blockIdx.x;
+    if (xcd_order) {
+        // the hardware deals workgroup b to XCD b % 8: number the tiles so
+        // that consecutive tiles (neighbouring strips of one grid, sharing
+        // halo columns) run on the same XCD and its L2
+        const int x = b & 7, per = n_tiles >> 3, rem = n_tiles & 7;
+        b = x * per + (x < rem ? x : rem) + (b >> 3);
+    }
     // grid owning tile b: last grid with tile_begin <= b
     int lo = 0, hi = n_grids - 1;
     while (lo < hi) {
@@ -421,11 +429,11 @@ hipError_t launch(const Fused2DShape &sh, const T *psi_n, T *psi_out, const T *c
 }
 
 template <typename T, int NI, bool FCT>
-hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, const T *psi_n,
-                          T *psi_out, const T *c0, const T *c1, hipStream_t s)
+hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, int xcd,
+                          const T *psi_n, T *psi_out, const T *c0, const T *c1, hipStream_t s)
 {
     k_fused2d_batched<T, NI, FCT><<<(unsigned)n_tiles, WAVE, 0, s>>>(
-        g, n_grids, fused2d_tile_rows(), psi_n, psi_out, c0, c1);
+        g, n_grids, th, n_tiles, xcd, psi_n, psi_out, c0, c1);
     return hipGetLastError();
 }
 
@@ -467,21 +475,23 @@ hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, cons
 
 template <typename T>
 hipError_t fused2d_batched_step(const BatchGrid *g, int n_grids, int n_tiles, int bc,
-                                int n_iters, unsigned opts, const T *psi_n, T *psi_out,
-                                const T *c0, const T *c1, hipStream_t s)
+                                int n_iters, unsigned opts, int th, int xcd, const T *psi_n,
+                                T *psi_out, const T *c0, const T *c1, hipStream_t s)
 {
-    if (bc != BC_PERIODIC) return hipErrorNotSupported;
+    if (bc != BC_PERIODIC || th < 1) return hipErrorNotSupported;
     bool fct = opts & OPT_FCT;
+#define MP_B(NI, F) launch_batched<T, NI, F>(g, n_grids, n_tiles, th, xcd, psi_n, psi_out, c0, c1, s)
     switch (n_iters * 2 + (fct ? 1 : 0)) {
-    case 2: case 3: return launch_batched<T, 1, false>(g, n_grids, n_tiles, psi_n, psi_out, c0, c1, s);
-    case 4: return launch_batched<T, 2, false>(g, n_grids, n_tiles, psi_n, psi_out, c0, c1, s);
-    case 5: return launch_batched<T, 2, true>(g, n_grids, n_tiles, psi_n, psi_out, c0, c1, s);
-    case 6: return launch_batched<T, 3, false>(g, n_grids, n_tiles, psi_n, psi_out, c0, c1, s);
-    case 7: return launch_batched<T, 3, true>(g, n_grids, n_tiles, psi_n, psi_out, c0, c1, s);
-    case 8: return launch_batched<T, 4, false>(g, n_grids, n_tiles, psi_n, psi_out, c0, c1, s);
-    case 9: return launch_batched<T, 4, true>(g, n_grids, n_tiles, psi_n, psi_out, c0, c1, s);
+    case 2: case 3: return MP_B(1, false);
+    case 4: return MP_B(2, false);
+    case 5: return MP_B(2, true);
+    case 6: return MP_B(3, false);
+    case 7: return MP_B(3, true);
+    case 8: return MP_B(4, false);
+    case 9: return MP_B(4, true);
     default: return hipErrorNotSupported;
     }
+#undef MP_B
 }
 
 template hipError_t fused2d_step<float>(const Fused2DShape &, int, unsigned, const float *, float *,
@@ -490,10 +500,10 @@ template hipError_t fused2d_step<double>(const Fused2DShape &, int, unsigned, co
                                          double *, const double *, const double *, const double *,
                                          hipStream_t);
 template hipError_t fused2d_batched_step<float>(const BatchGrid *, int, int, int, int, unsigned,
-                                                const float *, float *, const float *,
+                                                int, int, const float *, float *, const float *,
                                                 const float *, hipStream_t);
 template hipError_t fused2d_batched_step<double>(const BatchGrid *, int, int, int, int, unsigned,
-                                                 const double *, double *, const double *,
-                                                 const double *, hipStream_t);
+                                                 int, int, const double *, double *,
+                                                 const double *, const double *, hipStream_t);
 
 }  // namespace mp

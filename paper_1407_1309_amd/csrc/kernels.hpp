@@ -85,12 +85,15 @@ struct BatchGrid {
     int tiles_w;                       // tiles along columns
 };
 
+// tile_rows: rows per tile (the chunk length the table was built with);
+// xcd_order != 0 numbers the tiles so that consecutive ones run on one XCD
 template <typename T>
 hipError_t fused2d_batched_step(const BatchGrid *grids_dev, int n_grids, int n_tiles, int bc,
-                                int n_iters, unsigned opts, const T *psi_n, T *psi_out,
-                                const T *c0, const T *c1, hipStream_t s);
+                                int n_iters, unsigned opts, int tile_rows, int xcd_order,
+                                const T *psi_n, T *psi_out, const T *c0, const T *c1,
+                                hipStream_t s);
 
-int fused2d_tile_rows();                             // rows per batched tile
+int fused2d_tile_rows();                             // default rows per batched tile
 int fused2d_strip_cols(int n_iters, unsigned opts);  // output columns per strip
 
 }  // namespace mp

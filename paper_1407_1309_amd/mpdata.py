@@ -29,7 +29,8 @@ EXPORTS = [
     "mpdata_set_tile_rows", "mpdata_autotune",
     "mpdata_step", "mpdata_diag", "mpdata_courant_max", "mpdata_adv_adj",
     "mpdata_adj_workspace_bytes", "mpdata_batched_workspace_bytes", "mpdata_batched_init",
-    "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_timing", "mpdata_timing_read",
+    "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_set_batched_tiling",
+    "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read",
     "mpdata_destroy", "mpdata_last_error",
 ]
 
@@ -83,6 +84,9 @@ def lib():
                                           ctypes.POINTER(_VP)]
         L.mpdata_step_batched.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int]
         L.mpdata_step_per_grid.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int]
+        L.mpdata_set_batched_tiling.argtypes = [_VP, ctypes.c_int, ctypes.c_int]
+        L.mpdata_autotune_batched.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]
         L.mpdata_timing.argtypes = [_VP, ctypes.c_int]
         L.mpdata_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int),
@@ -319,6 +323,20 @@ class BatchedPlan:
         _check(lib().mpdata_step_batched(self._handle, _ptr(psi), _ptr(c0), _ptr(c1),
                                          int(n_steps), 1 if use_graph else 0))
         return psi
+
+    def set_tiling(self, tile_rows=0, xcd_order=False):
+        """Chunk length (0 = default) and tile order of the batched launch."""
+        _check(lib().mpdata_set_stream(self._handle, _stream(self.device)))
+        _check(lib().mpdata_set_batched_tiling(self._handle, int(tile_rows), 1 if xcd_order else 0))
+
+    def autotune(self, psi, c0, c1):
+        """Pick chunk length and tile order by timing one batched step per
+        candidate on these buffers (psi is not modified); returns both."""
+        self._check(psi, c0, c1)
+        rows, xcd = ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().mpdata_autotune_batched(self._handle, _ptr(psi), _ptr(c0), _ptr(c1),
+                                             ctypes.byref(rows), ctypes.byref(xcd)))
+        return rows.value, bool(xcd.value)
 
     def step_per_grid(self, psi, c0, c1, n_steps=1):
         self._check(psi, c0, c1)

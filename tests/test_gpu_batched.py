@@ -73,6 +73,33 @@ def test_batched_graph_replays_match_eager():
     assert torch.equal(pg, graph)
 
 
+def test_batched_tiling_and_autotune_bitwise():
+    """Chunk length and tile order change only the speed: every tiling, and
+    the autotuner's choice (also replayed from a graph), gives the same bits."""
+    grids = _grids(SHAPES, seed=13)
+    dtype = torch.float32
+    bp = mpdata.BatchedPlan(SHAPES, dtype=dtype, n_iters=2, opts=FCT)
+    psi0 = bp.pack([g[0] for g in grids], "psi")
+    c0 = bp.pack([g[1] for g in grids], "c0")
+    c1 = bp.pack([g[2] for g in grids], "c1")
+    ref = None
+    for rows, xcd in [(0, False), (1, True), (7, False), (16, True), (100, True), (1000, False)]:
+        bp.set_tiling(rows, xcd)
+        p = psi0.clone()
+        bp.step(p, c0, c1, n_steps=4, use_graph=False)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = p
+        assert torch.equal(p, ref), (rows, xcd)
+    rows, xcd = bp.autotune(psi0, c0, c1)
+    assert rows > 0
+    for use_graph in (False, True, True):
+        p = psi0.clone()
+        bp.step(p, c0, c1, n_steps=4, use_graph=use_graph)
+        torch.cuda.synchronize()
+        assert torch.equal(p, ref), (rows, xcd, use_graph)
+
+
 def test_batched_workload_sampled():
     """1024 grids, sides uniform in [64, 768], FP32, n_iters=2 with the
     limiter, 100 steps, graph-captured: the smallest grids against the oracle
