@@ -33,7 +33,7 @@ typedef struct {
     int ndims;
     long n[3];
     int bc[3];
-    int iga, tot, fct;
+    int iga, tot, fct, kahan;
 } grid_t;
 
 /* ------------------------------------------------------------------------ */
@@ -155,7 +155,10 @@ static double donor_flux(const grid_t *g, int d, const double *x,
 
 /* out(i) = x(i) - [sum_d (F_d(i+1/2) - F_d(i-1/2))] / G(i), dimensions summed
  * in increasing order.  When iga_flux is set the corrective-pass flux is the
- * pseudo-velocity itself (infinite-gauge limit, F = V). */
+ * pseudo-velocity itself (infinite-gauge limit, F = V).
+ * With the Kahan option (Sect. 3.1.1) the update is the compensated sum of
+ * x(i) and the terms -(F_d(i+1/2) - F_d(i-1/2)) / G(i), d increasing:
+ * s = x(i), c = 0; per term t: y = t - c, u = s + y, c = (u - s) - y, s = u. */
 static void donor_pass(const grid_t *g, const double *x, double *const c[3],
                        const double *G, int iga_flux, double *out)
 {
@@ -164,6 +167,7 @@ static void donor_pass(const grid_t *g, const double *x, double *const c[3],
         for (p[1] = 0; p[1] < g->n[1]; p[1]++)
             for (p[2] = 0; p[2] < g->n[2]; p[2]++) {
                 double acc = 0.0;
+                double ks = at(g, x, p), kc = 0.0;   /* Kahan sum and compensation */
                 for (int d = 0; d < g->ndims; d++) {
                     long lo[3], hi[3];
                     sh(lo, p, d, 0);
@@ -177,9 +181,21 @@ static void donor_pass(const grid_t *g, const double *x, double *const c[3],
                         fhi = donor_flux(g, d, x, c[d], hi);
                     }
                     acc += fhi - flo;
+                    if (g->kahan) {
+                        double t = fhi - flo;
+                        if (G) t = t / at(g, G, p);
+                        double y = -t - kc;
+                        double u = ks + y;
+                        kc = (u - ks) - y;
+                        ks = u;
+                    }
                 }
-                double r = G ? acc / at(g, G, p) : acc;
-                out[cidx(g, p)] = at(g, x, p) - r;
+                if (g->kahan) {
+                    out[cidx(g, p)] = ks;
+                } else {
+                    double r = G ? acc / at(g, G, p) : acc;
+                    out[cidx(g, p)] = at(g, x, p) - r;
+                }
             }
 }
 
@@ -457,7 +473,7 @@ static int make_grid(grid_t *g, int ndims, const long n[3], const int bc[3],
                      unsigned opts)
 {
     if (ndims < 1 || ndims > 3) return -1;
-    if (opts & ~(unsigned)(ORC_OPT_FCT | ORC_OPT_IGA | ORC_OPT_TOT)) return -1;
+    if (opts & ~(unsigned)(ORC_OPT_FCT | ORC_OPT_IGA | ORC_OPT_TOT | ORC_OPT_KAHAN)) return -1;
     g->ndims = ndims;
     for (int d = 0; d < 3; d++) {
         g->n[d] = d < ndims ? n[d] : 1;
@@ -468,6 +484,7 @@ static int make_grid(grid_t *g, int ndims, const long n[3], const int bc[3],
     g->fct = (opts & ORC_OPT_FCT) != 0;
     g->iga = (opts & ORC_OPT_IGA) != 0;
     g->tot = (opts & ORC_OPT_TOT) != 0;
+    g->kahan = (opts & ORC_OPT_KAHAN) != 0;
     return 0;
 }
 

@@ -24,6 +24,8 @@ from tests.bruteforce import mpdata_exact
 FCT, IGA, TOT = oracle.OPT_FCT, oracle.OPT_IGA, oracle.OPT_TOT
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 ALL_OPTS = [0, FCT, TOT, FCT | TOT, IGA, IGA | FCT, IGA | TOT, IGA | TOT | FCT]
+KAHAN = oracle.OPT_KAHAN
+KAHAN_OPTS = [KAHAN, FCT | KAHAN, IGA | TOT | KAHAN, FCT | TOT | KAHAN]
 
 
 def _fr(s):
@@ -103,7 +105,7 @@ BF_CASES = [((8,), 0), ((8,), 1), ((5, 4), 0), ((5, 4), 1), ((4, 3, 3), 0), ((3,
 
 
 @pytest.mark.parametrize("shape,bc", BF_CASES)
-@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("opts", ALL_OPTS + KAHAN_OPTS)
 def test_bruteforce_exact(shape, bc, opts):
     """Oracle == exact-rational second coding, every option, 1/2/3-D, both BCs."""
     iga = bool(opts & IGA)
@@ -122,8 +124,73 @@ def test_bruteforce_exact(shape, bc, opts):
     np.testing.assert_allclose(out, ref, rtol=0, atol=1e-13 * scale)
 
 
+# ------------------------------------------------- compensated donor summation
+@pytest.mark.parametrize("shape", [(24, 20), (10, 9, 8)])
+def test_kahan_donor_update_is_compensated(shape):
+    """With the Kahan option the donor-cell update is Kahan's compensated sum
+    of psi and the per-dimension terms -(F(i+1/2) - F(i-1/2)) (Sect. 3.1.1).
+    Check against the exact rational sum of those terms (recomputed from
+    eq. F in plain floats: one product per flux, one difference per
+    dimension), correctly rounded: a compensated sum of three or four terms
+    of very different size is within one ulp of it everywhere and equal to
+    it almost everywhere.  The uncompensated left-to-right sum, as a foil,
+    misses the rounded value in far more cells, so a lost or mis-signed
+    compensation fails the test."""
+    gen = synth.rng(41)
+    nd = len(shape)
+    psi = gen.uniform(1.0, 2.0, size=shape)
+    c = synth.periodic_fix([gen.uniform(-0.2 / nd, 0.2 / nd, size=tuple(
+        s + (1 if d == e else 0) for e, s in enumerate(shape))) for d in range(nd)])
+    k = oracle.step(psi, c, n_iters=1, opts=KAHAN, n_steps=1)
+
+    def flux(u, xl, xr):
+        return (u if u > 0 else 0.0) * xl + (u if u < 0 else 0.0) * xr
+
+    hit = hit_naive = 0
+    worst = 0.0
+    for idx in np.ndindex(shape):
+        x = psi[idx]
+        terms = []
+        for d in range(nd):
+            lo = list(idx)
+            hi = list(idx)
+            hi[d] += 1
+            m = list(idx)
+            m[d] = (idx[d] - 1) % shape[d]
+            p = list(idx)
+            p[d] = (idx[d] + 1) % shape[d]
+            fhi = flux(c[d][tuple(hi)], x, psi[tuple(p)])
+            flo = flux(c[d][tuple(lo)], psi[tuple(m)], x)
+            terms.append(-(fhi - flo))
+        exact = float(Fraction(x) + sum(Fraction(t) for t in terms))
+        naive = x
+        for t in terms:
+            naive = naive + t
+        hit += k[idx] == exact
+        hit_naive += naive == exact
+        worst = max(worst, abs(k[idx] - exact) / np.spacing(exact))
+    n = np.prod(shape)
+    assert worst <= 1.0
+    assert hit >= 0.95 * n
+    assert hit_naive <= 0.9 * n          # the foil shows the test discriminates
+
+
+def test_kahan_changes_only_rounding():
+    """Kahan summation changes results by round-off only, for every option."""
+    gen = synth.rng(42)
+    shape = (20, 18)
+    psi = gen.uniform(0.0, 1.0, size=shape)
+    c = synth.periodic_fix(synth.random_advector(shape, 0.4, gen))
+    g = gen.uniform(0.5, 1.5, size=shape)
+    for opts in ALL_OPTS:
+        n_iters = 2 if opts & IGA else 3
+        a = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, n_steps=4)
+        b = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts | KAHAN, n_steps=4)
+        assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a)), opts
+
+
 # ---------------------------------------------------------------- P3 conservation
-@pytest.mark.parametrize("opts", ALL_OPTS)
+@pytest.mark.parametrize("opts", ALL_OPTS + [KAHAN, FCT | KAHAN])
 @pytest.mark.parametrize("shape", [(64,), (24, 20), (10, 9, 8)])
 def test_conservation_periodic(opts, shape):
     """Flux form conserves sum(G psi) to round-off (Sect. 1; eq. gte)."""
