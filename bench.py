@@ -39,6 +39,8 @@ def _parse():
                     choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint", "copy"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
+    ap.add_argument("--kahan", action="store_true",
+                    help="Kahan-compensated donor-cell updates (the library-default summation)")
     ap.add_argument("--tile-rows", type=int, default=None,
                     help="fused kernel rows per wavefront chunk (default: autotune)")
     return ap.parse_args()
@@ -87,6 +89,9 @@ def bench_single(args, torch, mpdata, synth, oracle):
     else:
         case = synth.case_1d()
         name = "1d_periodic_500_iters2"
+    if args.kahan:
+        case.opts |= mpdata.OPT_KAHAN
+        name += "_kahan"
     dtype = torch.float32 if f32 else torch.float64
     es = 4 if f32 else 8
     K = args.steps if args.steps is not None else case.n_steps
@@ -185,7 +190,8 @@ def bench_batched(args, torch, mpdata, synth, oracle):
     shapes = synth.batch_shapes()
     cases = synth.case_batch()
     dev = torch.device("cuda:0")
-    bp = mpdata.BatchedPlan(shapes, dtype=torch.float32, n_iters=2, opts=mpdata.OPT_FCT,
+    bopts = mpdata.OPT_FCT | (mpdata.OPT_KAHAN if args.kahan else 0)
+    bp = mpdata.BatchedPlan(shapes, dtype=torch.float32, n_iters=2, opts=bopts,
                             device=dev)
     psi0 = bp.pack([c.psi for c in cases], "psi")
     c0 = bp.pack([c.c[0] for c in cases], "c0")
@@ -206,7 +212,8 @@ def bench_batched(args, torch, mpdata, synth, oracle):
         "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms, 6),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded)",
-        "config": {"workload": "batched_1024x2d_periodic_64to768_fct_iters2", "grids": len(shapes),
+        "config": {"workload": "batched_1024x2d_periodic_64to768_fct_iters2"
+                   + ("_kahan" if args.kahan else ""), "grids": len(shapes),
                    "cells": N, "launch": "one launch per step, HIP graph", "tile_rows": tile_rows,
                    "xcd_order": xcd, "parallelism": "single GPU"},
         "per_grid_launches": {"value": round(N * K / secs_pg / 1e6, 3), "unit": "Mcell-steps/s",
@@ -225,7 +232,7 @@ def bench_batched(args, torch, mpdata, synth, oracle):
             cs = cases[int(i)]
             oracle.step(cs.psi.astype(np.float32).astype(np.float64),
                         [x.astype(np.float32).astype(np.float64) for x in cs.c], n_iters=2,
-                        opts=1, n_steps=20)
+                        opts=bopts, n_steps=20)
             cells += cs.psi.size * 20
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(cells / dt / 1e6, 4), "unit": "Mcell-steps/s",

@@ -61,7 +61,13 @@ enum mpdata_status {
 enum {
     MPDATA_OPT_FCT = 1u << 0, /* non-oscillatory limiter, Sect. 3.1.4       */
     MPDATA_OPT_IGA = 1u << 1, /* infinite gauge, Sect. 3.1.5                */
-    MPDATA_OPT_TOT = 1u << 2  /* third-order terms, Sect. 3.1.2             */
+    MPDATA_OPT_TOT = 1u << 2, /* third-order terms, Sect. 3.1.2             */
+    /* Kahan-compensated donor-cell update (Sect. 3.1.1): every donor-cell pass
+     * forms psi + sum_d -(F_d(i+1/2) - F_d(i-1/2)) / G with Kahan's
+     * compensated summation, dimensions in increasing order, instead of
+     * psi - [sum_d (F_d(i+1/2) - F_d(i-1/2))] / G.  Round-off only; the
+     * adjoint differentiates the exact sum. */
+    MPDATA_OPT_KAHAN = 1u << 5
 };
 
 enum { MPDATA_BC_PERIODIC = 0, MPDATA_BC_OPEN = 1 };

@@ -497,9 +497,10 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
     const bool fct = a.opts & OPT_FCT, iga = a.opts & OPT_IGA;
     const int n = a.n_iters;
     hipError_t e;
+    const int km = (a.opts & OPT_KAHAN) ? 2 : 0;   // Kahan-compensated donor update
     T *first = n > 1 ? w.X[1] : out;
     if (first) {
-        e = launch_donor<T>(g, psi_n, a.c, a.G, 0, first, s);
+        e = launch_donor<T>(g, psi_n, a.c, a.G, km, first, s);
         if (e != hipSuccess) return e;
     }
     for (int it = 2; it <= n; it++) {
@@ -517,7 +518,7 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
         }
         T *y = (it < n) ? w.X[it] : out;
         if (y) {
-            e = launch_donor<T>(g, x, W, a.G, iga ? 1 : 0, y, s);
+            e = launch_donor<T>(g, x, W, a.G, (iga ? 1 : 0) | km, y, s);
             if (e != hipSuccess) return e;
         }
     }

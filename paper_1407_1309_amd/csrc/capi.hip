@@ -78,7 +78,7 @@ int check_desc(const mpdata_desc *d, mp::Geom *g)
         return fail(MPDATA_EINVAL, "unknown dtype %d", d->dtype);
     if (d->n_iters < 1 || d->n_iters > 8)
         return fail(MPDATA_EINVAL, "n_iters %d not in 1..8", d->n_iters);
-    if (d->opts & ~(uint32_t)(MPDATA_OPT_FCT | MPDATA_OPT_IGA | MPDATA_OPT_TOT))
+    if (d->opts & ~(uint32_t)(MPDATA_OPT_FCT | MPDATA_OPT_IGA | MPDATA_OPT_TOT | MPDATA_OPT_KAHAN))
         return fail(MPDATA_EINVAL, "unknown option bits 0x%x", d->opts);
     g->nd = d->n_dims;
     for (int k = 0; k < 3; k++) {

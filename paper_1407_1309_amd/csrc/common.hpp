@@ -8,7 +8,7 @@
 namespace mp {
 
 enum { BC_PERIODIC = 0, BC_OPEN = 1 };
-enum { OPT_FCT = 1u, OPT_IGA = 2u, OPT_TOT = 4u };
+enum { OPT_FCT = 1u, OPT_IGA = 2u, OPT_TOT = 4u, OPT_KAHAN = 32u };
 
 // Grid extents padded with 1 beyond n_dims; boundary type per dimension.
 struct Geom {
@@ -119,6 +119,17 @@ template <int K> __device__ __forceinline__ void quotients(const float (&n)[K],
 {
 #pragma unroll
     for (int k = 0; k < K; k++) q[k] = qdiv(n[k], d[k]);
+}
+
+// s += t with Kahan's compensated summation (compensation c starts at 0):
+// y = t - c, u = s + y, c = (u - s) - y, s = u.  No contraction into FMAs.
+template <typename T> __device__ __forceinline__ void kahan_add(T &s, T &c, T t)
+{
+#pragma clang fp contract(off)
+    T y = t - c;
+    T u = s + y;
+    c = (u - s) - y;
+    s = u;
 }
 
 // Round-up integer division.

@@ -58,6 +58,17 @@ __device__ inline double from_right(double v)
     return __hiloint2double(lane_from_right(__double2hiint(v)), lane_from_right(__double2loint(v)));
 }
 
+// Donor-cell update of one cell from the flux differences of the two
+// dimensions (G = 1): straightforward x - (d0 + d1), or Kahan-compensated.
+template <typename T> __device__ __forceinline__ T donor_update(bool kahan, T x, T d0, T d1)
+{
+    if (!kahan) return x - (d0 + d1);
+    T s = x, c = T(0);
+    kahan_add(s, c, -d0);
+    kahan_add(s, c, -d1);
+    return s;
+}
+
 // ---- register row-queues ------------------------------------------------
 // The row loop is unrolled by U iterations and every queue is a ring whose
 // depth divides U, so the slot holding "the row pushed `age` iterations ago"
@@ -101,7 +112,8 @@ template <typename T> struct Pass {
 
     // x_new: row a of the previous pass's result; c0_new / c1_new: the
     // previous pass's advector at wall a / row a; pn_a: psi^n at row a.
-    template <bool FCT, int P> __device__ __forceinline__ T advance(T x_new, T c0_new, T c1_new, T pn_a)
+    template <bool FCT, int P>
+    __device__ __forceinline__ T advance(T x_new, T c0_new, T c1_new, T pn_a, bool kahan)
     {
         AT(xq, 4, 0) = x_new;
         AT(xl, 4, 0) = from_left(x_new);
@@ -198,7 +210,7 @@ template <typename T> struct Pass {
         T f0hi = pos(AT(aq0, 4, 0)) * x + neg(AT(aq0, 4, 0)) * AT(xq, 4, 1);
         T f1lo = pos(AT(aq1, 4, 1)) * AT(xl, 4, 2) + neg(AT(aq1, 4, 1)) * x;
         T f1hi = from_right(f1lo);
-        return x - ((f0hi - f0lo) + (f1hi - f1lo));
+        return donor_update(kahan, x, f0hi - f0lo, f1hi - f1lo);
     }
 };
 
@@ -219,7 +231,7 @@ template <typename T, int NI, bool FCT> struct Strip {
     using C = Cfg<NI, FCT>;
     int n0, n1, i0, i1, jj, rr;
     int64_t ld1;
-    bool out_lane;
+    bool out_lane, kahan;
     const T *psi_n, *c0, *c1;
     const T *prow, *c0row, *c1row;
     T *orow;
@@ -262,7 +274,7 @@ template <typename T, int NI, bool FCT> struct Strip {
         T f0hi = pos(AT(dc0, 2, 0)) * x + neg(AT(dc0, 2, 0)) * AT(pq, C::QP, 0);
         T f1lo = pos(AT(dc1, 2, 1)) * from_left(x) + neg(AT(dc1, 2, 1)) * x;
         T f1hi = from_right(f1lo);
-        T y = x - ((f0hi - f0lo) + (f1hi - f1lo));
+        T y = donor_update(kahan, x, f0hi - f0lo, f1hi - f1lo);
         T cn0 = AT(dc0, 2, 1), cn1 = AT(dc1, 2, 1);
 
 #pragma unroll
@@ -273,7 +285,8 @@ template <typename T, int NI, bool FCT> struct Strip {
             // i0 - 2 NI + 4 m - 5; earlier iterations of this pass are skipped
             // (the queues then hold only rows outside the cone).
             if (t < i0 - 2 * NI + 4 * (k + 2) - 5) break;
-            T yk = ps[k].template advance<FCT, P>(y, cn0, cn1, pq.v[slot<C::QP>(P, 1 + 2 * k)]);
+            T yk = ps[k].template advance<FCT, P>(y, cn0, cn1, pq.v[slot<C::QP>(P, 1 + 2 * k)],
+                                                  kahan);
             cn0 = ps[k].aq0.v[slot<4>(P, 1)];
             cn1 = ps[k].aq1.v[slot<4>(P, 1)];
             y = yk;
@@ -298,10 +311,12 @@ __device__ __forceinline__ void iter_block(Strip<T, NI, FCT> &st, int t)
 template <typename T, int NI, bool FCT>
 __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__ psi_n,
                                            T *__restrict__ psi_out, const T *__restrict__ c0,
-                                           const T *__restrict__ c1, int jstrip0, int i0, int i1)
+                                           const T *__restrict__ c1, int jstrip0, int i0, int i1,
+                                           bool kahan)
 {
     using C = Cfg<NI, FCT>;
     Strip<T, NI, FCT> st;
+    st.kahan = kahan;
     const int lane = threadIdx.x & (WAVE - 1);
     // global column of this lane (may lie outside [0, n1) in the halo)
     const int col = jstrip0 - C::H + lane;
@@ -350,7 +365,7 @@ __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__
 }
 
 template <typename T, int NI, bool FCT>
-__global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int strips,
+__global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int strips, int kahan,
                                                   const T *__restrict__ psi_n,
                                                   T *__restrict__ psi_out,
                                                   const T *__restrict__ c0,
@@ -361,13 +376,13 @@ __global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int st
     int strip = b % strips, chunk = b / strips;
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1);
+    strip_body<T, NI, FCT>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1, kahan != 0);
 }
 
 template <typename T, int NI, bool FCT>
 __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__restrict__ grids,
                                                           int n_grids, int th, int n_tiles,
-                                                          int xcd_order,
+                                                          int xcd_order, int kahan,
                                                           const T *__restrict__ psi_n,
                                                           T *__restrict__ psi_out,
                                                           const T *__restrict__ c0,
@@ -398,7 +413,7 @@ __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__res
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
     strip_body<T, NI, FCT>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi, c0 + g.off_c0,
-                           c1 + g.off_c1, strip * C::OW, i0, i1);
+                           c1 + g.off_c1, strip * C::OW, i0, i1, kahan != 0);
 }
 
 // default rows per chunk (when not tuned): about two waves per SIMD, so the
@@ -414,8 +429,8 @@ int64_t rows_per_chunk(int64_t n0, int64_t strips)
 }
 
 template <typename T, int NI, bool FCT>
-hipError_t launch(const Fused2DShape &sh, const T *psi_n, T *psi_out, const T *c0, const T *c1,
-                  hipStream_t s)
+hipError_t launch(const Fused2DShape &sh, int kahan, const T *psi_n, T *psi_out, const T *c0,
+                  const T *c1, hipStream_t s)
 {
     using C = Cfg<NI, FCT>;
     int64_t strips = cdiv(sh.n1, C::OW);
@@ -424,16 +439,18 @@ hipError_t launch(const Fused2DShape &sh, const T *psi_n, T *psi_out, const T *c
     int64_t chunks = cdiv(sh.n0, th);
     int64_t blocks = strips * chunks;
     k_fused2d<T, NI, FCT><<<(unsigned)blocks, WAVE, 0, s>>>((int)sh.n0, (int)sh.n1, (int)th,
-                                                           (int)strips, psi_n, psi_out, c0, c1);
+                                                           (int)strips, kahan, psi_n, psi_out,
+                                                           c0, c1);
     return hipGetLastError();
 }
 
 template <typename T, int NI, bool FCT>
 hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, int xcd,
-                          const T *psi_n, T *psi_out, const T *c0, const T *c1, hipStream_t s)
+                          int kahan, const T *psi_n, T *psi_out, const T *c0, const T *c1,
+                          hipStream_t s)
 {
     k_fused2d_batched<T, NI, FCT><<<(unsigned)n_tiles, WAVE, 0, s>>>(
-        g, n_grids, th, n_tiles, xcd, psi_n, psi_out, c0, c1);
+        g, n_grids, th, n_tiles, xcd, kahan, psi_n, psi_out, c0, c1);
     return hipGetLastError();
 }
 
@@ -442,7 +459,7 @@ hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, 
 bool fused2d_supported(int nd, int n_iters, unsigned opts, int has_g, int bc0, int bc1)
 {
     if (nd != 2 || has_g || bc0 != BC_PERIODIC || bc1 != BC_PERIODIC) return false;
-    if (opts & ~OPT_FCT) return false;          // tot / iga: staged path
+    if (opts & ~(OPT_FCT | OPT_KAHAN)) return false;   // tot / iga: staged path
     return n_iters >= 1 && n_iters <= 4;
 }
 
@@ -461,16 +478,19 @@ hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, cons
 {
     if (G || sh.bc0 != BC_PERIODIC || sh.bc1 != BC_PERIODIC) return hipErrorNotSupported;
     bool fct = opts & OPT_FCT;
+    const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
+#define MP_L(NI, F) launch<T, NI, F>(sh, kahan, psi_n, psi_out, c0, c1, s)
     switch (n_iters * 2 + (fct ? 1 : 0)) {
-    case 2: case 3: return launch<T, 1, false>(sh, psi_n, psi_out, c0, c1, s);
-    case 4: return launch<T, 2, false>(sh, psi_n, psi_out, c0, c1, s);
-    case 5: return launch<T, 2, true>(sh, psi_n, psi_out, c0, c1, s);
-    case 6: return launch<T, 3, false>(sh, psi_n, psi_out, c0, c1, s);
-    case 7: return launch<T, 3, true>(sh, psi_n, psi_out, c0, c1, s);
-    case 8: return launch<T, 4, false>(sh, psi_n, psi_out, c0, c1, s);
-    case 9: return launch<T, 4, true>(sh, psi_n, psi_out, c0, c1, s);
+    case 2: case 3: return MP_L(1, false);
+    case 4: return MP_L(2, false);
+    case 5: return MP_L(2, true);
+    case 6: return MP_L(3, false);
+    case 7: return MP_L(3, true);
+    case 8: return MP_L(4, false);
+    case 9: return MP_L(4, true);
     default: return hipErrorNotSupported;
     }
+#undef MP_L
 }
 
 template <typename T>
@@ -480,7 +500,9 @@ hipError_t fused2d_batched_step(const BatchGrid *g, int n_grids, int n_tiles, in
 {
     if (bc != BC_PERIODIC || th < 1) return hipErrorNotSupported;
     bool fct = opts & OPT_FCT;
-#define MP_B(NI, F) launch_batched<T, NI, F>(g, n_grids, n_tiles, th, xcd, psi_n, psi_out, c0, c1, s)
+    const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
+#define MP_B(NI, F) \
+    launch_batched<T, NI, F>(g, n_grids, n_tiles, th, xcd, kahan, psi_n, psi_out, c0, c1, s)
     switch (n_iters * 2 + (fct ? 1 : 0)) {
     case 2: case 3: return MP_B(1, false);
     case 4: return MP_B(2, false);

@@ -45,7 +45,7 @@ struct G3 {
 constexpr int DONOR_PLANES = 16;   // planes per thread column
 
 template <typename T, bool HAS_G>
-__global__ void __launch_bounds__(256) k_donor3d(G3 g, const T *__restrict__ x,
+__global__ void __launch_bounds__(256) k_donor3d(G3 g, int kahan, const T *__restrict__ x,
                                                  const T *__restrict__ c0,
                                                  const T *__restrict__ c1,
                                                  const T *__restrict__ c2,
@@ -77,25 +77,36 @@ __global__ void __launch_bounds__(256) k_donor3d(G3 g, const T *__restrict__ x,
         const int64_t pc = i * pl;
         T xp = x[wrap_cell(i + 1, g.n0, g.bc0) * pl + o];
         T uhi = c0[wrap_wall(i + 1, g.n0, g.bc0) * pl + o];
-        T acc = T(0);
+        T dv[3];
         {
             T flo = pos(ulo) * xm + neg(ulo) * xc;
             T fhi = pos(uhi) * xc + neg(uhi) * xp;
-            acc += fhi - flo;
+            dv[0] = fhi - flo;
         }
         {
             T ul = c1[i * pl1 + w1lo], uh = c1[i * pl1 + w1hi];
             T flo = pos(ul) * x[pc + ojm] + neg(ul) * xc;
             T fhi = pos(uh) * xc + neg(uh) * x[pc + ojp];
-            acc += fhi - flo;
+            dv[1] = fhi - flo;
         }
         {
             T ul = c2[i * pl2 + w2lo], uh = c2[i * pl2 + w2hi];
             T flo = pos(ul) * x[pc + okm] + neg(ul) * xc;
             T fhi = pos(uh) * xc + neg(uh) * x[pc + okp];
-            acc += fhi - flo;
+            dv[2] = fhi - flo;
         }
-        y[pc + o] = xc - (HAS_G ? acc / G[pc + o] : acc);
+        if (kahan) {
+            T ks = xc, kc = T(0);
+#pragma unroll
+            for (int d = 0; d < 3; d++) kahan_add(ks, kc, -(HAS_G ? dv[d] / G[pc + o] : dv[d]));
+            y[pc + o] = ks;
+        } else {
+            T acc = T(0);
+            acc += dv[0];
+            acc += dv[1];
+            acc += dv[2];
+            y[pc + o] = xc - (HAS_G ? acc / G[pc + o] : acc);
+        }
         xm = xc;
         xc = xp;
         ulo = uhi;
@@ -111,7 +122,7 @@ template <typename T, bool IGA> __device__ inline T fr(T num, T den, T m)
 // ---- pseudo-velocity + corrective pass ---------------------------------
 template <typename T, bool HAS_G, bool IGA, bool TOT>
 __global__ void __launch_bounds__(TR * TileL<T>::v)
-k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__ y1,
+k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, int kahan, const T *__restrict__ y1,
                                                     const T *__restrict__ c0,
                                                     const T *__restrict__ c1,
                                                     const T *__restrict__ c2,
@@ -355,16 +366,33 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, const T *__restrict__
                 f2lo = pos(V2lo) * Y[sm2][r][lm1] + neg(V2lo) * x;
                 f2hi = pos(V2hi) * x + neg(V2hi) * Y[sm2][r][lp1];
             }
-            T acc = T(0);
-            acc += f0hi - f0lo;
-            acc += f1hi - f1lo;
-            acc += f2hi - f2lo;
-            if (HAS_G) {
-                T nn[1] = {acc}, dd[1] = {gq[0]}, qq[1];
-                quotients<1>(nn, dd, qq);
-                acc = qq[0];
+            T res;
+            if (kahan) {
+                T dv[3] = {f0hi - f0lo, f1hi - f1lo, f2hi - f2lo};
+                if (HAS_G) {
+                    T gg[3] = {gq[0], gq[0], gq[0]}, qq[3];
+                    quotients<3>(dv, gg, qq);
+                    dv[0] = qq[0];
+                    dv[1] = qq[1];
+                    dv[2] = qq[2];
+                }
+                T ks = x, kc = T(0);
+#pragma unroll
+                for (int d = 0; d < 3; d++) kahan_add(ks, kc, -dv[d]);
+                res = ks;
+            } else {
+                T acc = T(0);
+                acc += f0hi - f0lo;
+                acc += f1hi - f1lo;
+                acc += f2hi - f2lo;
+                if (HAS_G) {
+                    T nn[1] = {acc}, dd[1] = {gq[0]}, qq[1];
+                    quotients<1>(nn, dd, qq);
+                    acc = qq[0];
+                }
+                res = x - acc;
             }
-            out[((int64_t)p * g.n1 + jj) * g.n2 + kk] = x - acc;
+            out[((int64_t)p * g.n1 + jj) * g.n2 + kk] = res;
         }
         v1_keep = v1;
         v2_keep = v2;
@@ -400,10 +428,11 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
     G3 g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
     dim3 gd((unsigned)cdiv(g.n2, 64), (unsigned)cdiv(g.n1, 4), (unsigned)cdiv(g.n0, DONOR_PLANES));
     T *y1 = (n_iters == 1) ? psi_out : y1buf;
+    const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
     if (G)
-        k_donor3d<T, true><<<gd, 256, 0, s>>>(g, psi_n, c0, c1, c2, G, y1);
+        k_donor3d<T, true><<<gd, 256, 0, s>>>(g, kahan, psi_n, c0, c1, c2, G, y1);
     else
-        k_donor3d<T, false><<<gd, 256, 0, s>>>(g, psi_n, c0, c1, c2, G, y1);
+        k_donor3d<T, false><<<gd, 256, 0, s>>>(g, kahan, psi_n, c0, c1, c2, G, y1);
     if (n_iters == 1) return hipGetLastError();
     constexpr int TL = TileL<T>::v;
     int tiles_k = (g.n2 + TL - 2 * HALO - 1) / (TL - 2 * HALO);
@@ -414,7 +443,8 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
     unsigned blocks = (unsigned)tiles_k * tiles_j * chunks;
     const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
 #define MP_CORR(HG, IG, TO) \
-    k_corr3d<T, HG, IG, TO><<<blocks, TR * TL, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, y1, \
+    k_corr3d<T, HG, IG, TO><<<blocks, TR * TL, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, \
+                                                      kahan, y1, \
                                                       c0, c1, c2, G, psi_out)
     if (G) {
         if (iga) { if (tot) MP_CORR(true, true, true); else MP_CORR(true, true, false); }

@@ -28,7 +28,7 @@ template <typename T> hipError_t staged_step(const StagedArgs<T> &a, hipStream_t
 // single stages of the staged path (arrays as in StagedArgs)
 template <typename T>
 hipError_t launch_donor(const Geom &g, const T *x, const T *const c[3], const T *G,
-                        int flux_is_vel, T *out, hipStream_t s);
+                        int mode, T *out, hipStream_t s);   // mode: 1 flux = advector, 2 Kahan
 template <typename T>
 hipError_t launch_pseudo(const Geom &g, unsigned opts, const T *x, const T *const c[3],
                          const T *G, T *const V[3], hipStream_t s);

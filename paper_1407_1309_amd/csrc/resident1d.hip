@@ -55,6 +55,17 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
     T *W1 = W0 + (n + 1);
     T *W2 = W1 + (n + 1);
     const bool fct = opts & OPT_FCT, iga = opts & OPT_IGA, tot = opts & OPT_TOT;
+    const bool kahan = opts & OPT_KAHAN;
+    // donor-cell update from the flux difference acc (straightforward, or
+    // Kahan-compensated: psi + (-acc / G) as a compensated sum)
+    auto upd = [&](T x, T acc, int i) -> T {
+        if (kahan) {
+            T s = x, c = T(0);
+            kahan_add(s, c, -(Gin ? acc / GG[i] : acc));
+            return s;
+        }
+        return x - (Gin ? acc / GG[i] : acc);
+    };
     const int tid = threadIdx.x;
 
     for (int i = tid; i < n; i += RB) {
@@ -73,7 +84,7 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
             T flo = pos(ul) * P[mc(i - 1, n, bc)] + neg(ul) * P[i];
             T fhi = pos(uh) * P[i] + neg(uh) * P[mc(i + 1, n, bc)];
             T acc = fhi - flo;
-            Y[i] = P[i] - (Gin ? acc / GG[i] : acc);
+            Y[i] = upd(P[i], acc, i);
         }
         __syncthreads();
         const T *cprev = C;
@@ -149,7 +160,7 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
                     fhi = pos(uh) * X[i] + neg(uh) * X[mc(i + 1, n, bc)];
                 }
                 T acc = fhi - flo;
-                Y[i] = X[i] - (Gin ? acc / GG[i] : acc);
+                Y[i] = upd(X[i], acc, i);
             }
             cprev = adv;
             __syncthreads();

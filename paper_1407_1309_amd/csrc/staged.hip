@@ -63,18 +63,21 @@ __device__ inline T frac(bool iga, T num, T den, T m)
     return den == T(0) ? T(0) : num / den;
 }
 
-// donor-cell pass (eqs. upstream, F); with flux_is_vel the wall flux is the
-// advector itself (infinite-gauge corrective pass)
+// donor-cell pass (eqs. upstream, F).  mode bit 0: the wall flux is the
+// advector itself (infinite-gauge corrective pass); bit 1: Kahan-compensated
+// update (terms -(F(hi) - F(lo)) / G, dimensions in increasing order)
 template <typename T>
 __global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
-                        const T *c2, const T *G, int flux_is_vel, T *__restrict__ out)
+                        const T *c2, const T *G, int mode, T *__restrict__ out)
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
+    const bool flux_is_vel = mode & 1, kahan = mode & 2;
     Idx3 p = unflat(t, g.n);
     const T *c[3] = {c0, c1, c2};
     T acc = T(0);
+    T ks = x[t], kc = T(0);
     for (int d = 0; d < g.nd; d++) {
         T fl[2];
         for (int s = 0; s < 2; s++) {
@@ -86,6 +89,15 @@ __global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c
                 fl[s] = pos(u) * cell(g, x, shifted(w, d, -1)) + neg(u) * cell(g, x, w);
         }
         acc += fl[1] - fl[0];
+        if (kahan) {
+            T term = fl[1] - fl[0];
+            if (G) term = term / G[t];
+            kahan_add(ks, kc, -term);
+        }
+    }
+    if (kahan) {
+        out[t] = ks;
+        return;
     }
     T r = G ? acc / G[t] : acc;
     out[t] = x[t] - r;
@@ -218,10 +230,10 @@ int64_t wall_count(const Geom &g, int d)
 // ---- single-stage launchers (used by the adjoint's forward recompute) ----
 template <typename T>
 hipError_t launch_donor(const Geom &g, const T *x, const T *const c[3], const T *G,
-                        int flux_is_vel, T *out, hipStream_t s)
+                        int mode, T *out, hipStream_t s)
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
-    k_donor<T><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(g, x, c[0], c[1], c[2], G, flux_is_vel,
+    k_donor<T><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(g, x, c[0], c[1], c[2], G, mode,
                                                         out);
     return hipGetLastError();
 }
@@ -275,7 +287,8 @@ hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s)
     const bool fct = a.opts & OPT_FCT, iga = a.opts & OPT_IGA;
 
     T *out1 = (a.n_iters == 1) ? a.psi_out : a.tmp[0];
-    k_donor<T><<<cblocks, B, 0, s>>>(g, a.psi_n, a.c[0], a.c[1], a.c[2], a.G, 0, out1);
+    const int km = (a.opts & OPT_KAHAN) ? 2 : 0;
+    k_donor<T><<<cblocks, B, 0, s>>>(g, a.psi_n, a.c[0], a.c[1], a.c[2], a.G, km, out1);
     const T *cprev[3] = {a.c[0], a.c[1], a.c[2]};
     const T *x = out1;
     int set = 0;
@@ -301,7 +314,7 @@ hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s)
             set ^= 1;
         }
         T *y = (it == a.n_iters) ? a.psi_out : a.tmp[(it - 1) & 1];
-        k_donor<T><<<cblocks, B, 0, s>>>(g, x, adv[0], adv[1], adv[2], a.G, iga ? 1 : 0, y);
+        k_donor<T><<<cblocks, B, 0, s>>>(g, x, adv[0], adv[1], adv[2], a.G, (iga ? 1 : 0) | km, y);
         for (int d = 0; d < 3; d++) cprev[d] = adv[d];
         x = y;
     }

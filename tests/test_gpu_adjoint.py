@@ -53,8 +53,8 @@ def test_adjoint_vs_oracle(shape, bc, n_iters, opts, dtype):
         assert rel_l2(a.double().cpu().numpy(), b) <= tol
 
 
-@pytest.mark.parametrize("n_iters", [2, 3])
-def test_adjoint_fused_state_sweeps_vs_oracle(n_iters):
+@pytest.mark.parametrize("n_iters,opts", [(2, FCT), (3, FCT), (2, FCT | mpdata.OPT_KAHAN)])
+def test_adjoint_fused_state_sweeps_vs_oracle(n_iters, opts):
     """Periodic, no G, FCT: the checkpointing and segment sweeps run the fused
     2-D kernel; the gradient still matches the oracle's reverse mode."""
     shape = (96, 80)
@@ -62,9 +62,9 @@ def test_adjoint_fused_state_sweeps_vs_oracle(n_iters):
     case = synth.case_2d(shape=shape, seed=31 + n_iters, sigma=(4.0, 16.0), n_iters=n_iters)
     lam = gen.normal(size=shape)
     n_steps, ck = 7, 3
-    ref_psi, ref_c = oracle.adjoint(case.psi, case.c, lam, n_iters=n_iters, opts=FCT,
+    ref_psi, ref_c = oracle.adjoint(case.psi, case.c, lam, n_iters=n_iters, opts=opts,
                                     n_steps=n_steps, ckpt_every=ck)
-    plan = mpdata.Plan(shape, n_iters=n_iters, opts=FCT, adj_steps=n_steps, ckpt_every=ck)
+    plan = mpdata.Plan(shape, n_iters=n_iters, opts=opts, adj_steps=n_steps, ckpt_every=ck)
     gp, gc = plan.adv_adj(dev(case.psi, torch.float64), [dev(x, torch.float64) for x in case.c],
                           dev(lam, torch.float64), n_steps=n_steps, ckpt_every=ck)
     assert rel_l2(gp.double().cpu().numpy(), ref_psi) <= 1e-10

@@ -30,10 +30,10 @@ SHAPES = [(3, 3), (64, 64), (768, 64), (7, 300), (131, 97), (64, 768), (200, 5),
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("n_iters", [2, 3])
-def test_batched_matches_oracle_and_single(dtype, n_iters):
+@pytest.mark.parametrize("n_iters,opts", [(2, FCT), (3, FCT), (2, FCT | mpdata.OPT_KAHAN)])
+def test_batched_matches_oracle_and_single(dtype, n_iters, opts):
     grids = _grids(SHAPES, seed=11)
-    bp = mpdata.BatchedPlan(SHAPES, dtype=dtype, n_iters=n_iters, opts=FCT)
+    bp = mpdata.BatchedPlan(SHAPES, dtype=dtype, n_iters=n_iters, opts=opts)
     psi = bp.pack([as_dtype(g[0], dtype) for g in grids], "psi")
     c0 = bp.pack([g[1] for g in grids], "c0")
     c1 = bp.pack([g[2] for g in grids], "c1")
@@ -43,10 +43,10 @@ def test_batched_matches_oracle_and_single(dtype, n_iters):
     outs = bp.unpack(psi, "psi")
     for (p0, a, b), shp, got in zip(grids, SHAPES, outs):
         ref = oracle.step(as_dtype(p0, dtype), [as_dtype(a, dtype), as_dtype(b, dtype)],
-                          n_iters=n_iters, opts=FCT, n_steps=n_steps)
+                          n_iters=n_iters, opts=opts, n_steps=n_steps)
         assert rel_l2(got.double().cpu().numpy(), ref) <= TOL[dtype], shp
         single = dev(as_dtype(p0, dtype), dtype)
-        plan = mpdata.Plan(shp, dtype=dtype, n_iters=n_iters, opts=FCT)
+        plan = mpdata.Plan(shp, dtype=dtype, n_iters=n_iters, opts=opts)
         plan.step(single, [dev(a, dtype), dev(b, dtype)], n_steps=n_steps)
         torch.cuda.synchronize()
         assert torch.equal(single, got), shp        # tile-size independent, bit for bit

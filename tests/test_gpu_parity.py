@@ -57,6 +57,30 @@ def test_parity_small(shape, bc, opts, dtype):
         assert err <= TOL[dtype], (kernel, err)
 
 
+KAHAN = mpdata.OPT_KAHAN
+KAHAN_CASES = []
+for shape in [(300,), (150, 197), (37, 29, 41)]:
+    for bc in (0, 1):
+        for opts in (KAHAN, FCT | KAHAN, TOT | KAHAN, IGA | TOT | KAHAN):
+            KAHAN_CASES.append((shape, bc, opts))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,bc,opts", KAHAN_CASES)
+def test_parity_kahan(shape, bc, opts, dtype):
+    """Kahan-compensated donor updates through every kernel family (staged,
+    fused 2-D, resident 1-D), with and without G."""
+    n_iters = 2 if opts & IGA else 3
+    for with_g in (False, True):
+        psi, c, g = _inputs(shape, bc, opts, seed=len(shape) * 100 + bc * 10 + opts + with_g,
+                            with_g=with_g)
+        psi, c, g = as_dtype(psi, dtype), [as_dtype(x, dtype) for x in c], as_dtype(g, dtype)
+        ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=5)
+        for kernel in KERNELS:
+            out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 5, kernel=kernel)
+            assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
+
+
 @pytest.mark.parametrize("n_iters", [1, 2, 3, 4])
 def test_parity_pass_counts(n_iters):
     shape = (130, 70)
@@ -284,7 +308,7 @@ def test_parity_1d_resident(opts, bc, dtype):
 
 F3_CASES = []
 for shape, bc in [((9, 37, 130), 1), ((10, 16, 64), 0), ((7, 45, 70), 0), ((12, 20, 67), 1)]:
-    for n_iters, opts in [(1, 0), (2, 0), (2, TOT), (2, IGA), (2, IGA | TOT)]:
+    for n_iters, opts in [(1, 0), (2, 0), (2, TOT), (2, IGA), (2, IGA | TOT), (2, IGA | TOT | 32)]:
         F3_CASES.append((shape, bc, n_iters, opts))
 
 
