@@ -33,7 +33,7 @@ typedef struct {
     int ndims;
     long n[3];
     int bc[3];
-    int iga, tot, fct, kahan;
+    int iga, tot, fct, kahan, abs;
 } grid_t;
 
 /* ------------------------------------------------------------------------ */
@@ -138,6 +138,14 @@ static double frac(const grid_t *g, double num, double den, double m)
     return den == 0.0 ? 0.0 : num / den;
 }
 
+/* psi value entering a psi-fraction: |psi| under the abs option (Sect. 3.1.5,
+ * variable-sign fields), psi otherwise */
+static double xat(const grid_t *g, const double *x, const long p[3])
+{
+    double v = at(g, x, p);
+    return g->abs ? fabs(v) : v;
+}
+
 /* ------------------------------------------------------------------------ */
 /* donor-cell pass, eq. (upstream) with the flux function eq. (F)            */
 /* ------------------------------------------------------------------------ */
@@ -238,7 +246,7 @@ static double pseudo_velocity(const grid_t *g, int d, const double *x,
     sh(R, p, d, 0);
     double u = wat(g, d, c[d], p);
     double Gb = 0.5 * (gat(g, G, L) + gat(g, G, R));
-    double xL = at(g, x, L), xR = at(g, x, R);
+    double xL = xat(g, x, L), xR = xat(g, x, R);
 
     double A = frac(g, xR - xL, xR + xL, 2.0);
     double V = (fabs(u) - u * u / Gb) * A;
@@ -252,8 +260,8 @@ static double pseudo_velocity(const grid_t *g, int d, const double *x,
         sh(Lp, L, o, 1);
         sh(Rm, R, o, -1);
         sh(Lm, L, o, -1);
-        double a = at(g, x, Rp), b = at(g, x, Lp), e = at(g, x, Rm),
-               f = at(g, x, Lm);
+        double a = xat(g, x, Rp), b = xat(g, x, Lp), e = xat(g, x, Rm),
+               f = xat(g, x, Lm);
         double B = frac(g, a + b - e - f, a + b + e + f, 4.0);
         V -= 0.5 * u * cb[o] / Gb * B;
     }
@@ -262,7 +270,7 @@ static double pseudo_velocity(const grid_t *g, int d, const double *x,
         long R2[3], L2[3];
         sh(R2, R, d, 1);
         sh(L2, L, d, -1);
-        double xR2 = at(g, x, R2), xL2 = at(g, x, L2);
+        double xR2 = xat(g, x, R2), xL2 = xat(g, x, L2);
         double D = frac(g, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, 4.0);
         V += (3.0 * u * fabs(u) / Gb - 2.0 * u * u * u / (Gb * Gb) - u) /
              3.0 * D;
@@ -274,8 +282,8 @@ static double pseudo_velocity(const grid_t *g, int d, const double *x,
             sh(Lp, L, o, 1);
             sh(Rm, R, o, -1);
             sh(Lm, L, o, -1);
-            double a = at(g, x, Rp), b = at(g, x, Lp), e = at(g, x, Rm),
-                   f = at(g, x, Lm);
+            double a = xat(g, x, Rp), b = xat(g, x, Lp), e = xat(g, x, Rm),
+                   f = xat(g, x, Lm);
             double E = frac(g, a - b - e + f, a + b + e + f, 4.0);
             V += (fabs(u) * cb[o] / Gb - 2.0 * u * u * cb[o] / (Gb * Gb)) * E;
         }
@@ -291,8 +299,8 @@ static double pseudo_velocity(const grid_t *g, int d, const double *x,
                 sh2(mp, side[s], o1, -1, o2, 1);
                 sh2(pm, side[s], o1, 1, o2, -1);
                 sh2(mm, side[s], o1, -1, o2, -1);
-                double vpp = at(g, x, pp), vmp = at(g, x, mp),
-                       vpm = at(g, x, pm), vmm = at(g, x, mm);
+                double vpp = xat(g, x, pp), vmp = xat(g, x, mp),
+                       vpm = xat(g, x, pm), vmm = xat(g, x, mm);
                 num += vpp - vmp - vpm + vmm;
                 den += vpp + vmp + vpm + vmm;
             }
@@ -473,7 +481,10 @@ static int make_grid(grid_t *g, int ndims, const long n[3], const int bc[3],
                      unsigned opts)
 {
     if (ndims < 1 || ndims > 3) return -1;
-    if (opts & ~(unsigned)(ORC_OPT_FCT | ORC_OPT_IGA | ORC_OPT_TOT | ORC_OPT_KAHAN)) return -1;
+    if (opts & ~(unsigned)(ORC_OPT_FCT | ORC_OPT_IGA | ORC_OPT_TOT | ORC_OPT_KAHAN | ORC_OPT_ABS))
+        return -1;
+    /* abs and iga are the two alternative variable-sign options */
+    if ((opts & ORC_OPT_ABS) && (opts & ORC_OPT_IGA)) return -1;
     g->ndims = ndims;
     for (int d = 0; d < 3; d++) {
         g->n[d] = d < ndims ? n[d] : 1;
@@ -485,6 +496,7 @@ static int make_grid(grid_t *g, int ndims, const long n[3], const int bc[3],
     g->iga = (opts & ORC_OPT_IGA) != 0;
     g->tot = (opts & ORC_OPT_TOT) != 0;
     g->kahan = (opts & ORC_OPT_KAHAN) != 0;
+    g->abs = (opts & ORC_OPT_ABS) != 0;
     return 0;
 }
 
@@ -1104,6 +1116,7 @@ int orc_adjoint(int ndims, const long n[3], const int bc[3], int n_iters,
     if (make_grid(&g, ndims, n, bc, opts)) return -1;
     if (n_iters < 1 || n_iters > 8 || n_steps < 1 || ckpt_every < 1) return -1;
     if (g.iga && n_iters > 2) return -1;
+    if (g.abs) return -1;   /* reverse mode covers the signed fractions only */
     if (!psi0 || !lambda_T || !grad_psi0) return -1;
     double *c[3] = {(double *)c0, (double *)c1, (double *)c2};
     double *gc[3] = {grad_c0, grad_c1, grad_c2};

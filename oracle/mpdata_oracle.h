@@ -28,8 +28,11 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_OPEN = 1 };
 /* KAHAN: every donor-cell pass sums its update terms with Kahan's
  * compensated summation (the library default the paper describes in
  * Sect. 3.1.1) instead of straightforwardly. */
+/* ABS: |psi| replaces psi in every psi-fraction of the pseudo-velocity
+ * (variable-sign fields, Sect. 3.1.5); not combinable with IGA, forward
+ * only (orc_adjoint rejects it). */
 enum { ORC_OPT_FCT = 1u << 0, ORC_OPT_IGA = 1u << 1, ORC_OPT_TOT = 1u << 2,
-       ORC_OPT_KAHAN = 1u << 5 };
+       ORC_OPT_ABS = 1u << 3, ORC_OPT_KAHAN = 1u << 5 };
 
 /* Advance psi (in place) by n_steps MPDATA steps.  g may be NULL (G = 1).
  * c[d] must be non-NULL for d < ndims.  Returns 0, or -1 on bad arguments. */

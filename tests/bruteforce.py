@@ -52,7 +52,7 @@ def _fr(num, den, iga, m):
     return Fraction(0) if den == 0 else num / den
 
 
-def mpdata_exact(psi, c, g, shape, bc, n_iters, fct, iga, tot, n_steps):
+def mpdata_exact(psi, c, g, shape, bc, n_iters, fct, iga, tot, n_steps, absf=False):
     """psi: dict cell->Fraction; c: list of dict wall->Fraction; g: dict or None."""
     G = Grid(shape, bc)
     one = Fraction(1)
@@ -84,6 +84,8 @@ def mpdata_exact(psi, c, g, shape, bc, n_iters, fct, iga, tot, n_steps):
         return out
 
     def pseudo(x, cp):
+        if absf:                  # |psi| in every psi-fraction
+            x = {k: abs(v) for k, v in x.items()}
         V = []
         for d in range(G.nd):
             Vd = {}

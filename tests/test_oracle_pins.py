@@ -26,6 +26,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 ALL_OPTS = [0, FCT, TOT, FCT | TOT, IGA, IGA | FCT, IGA | TOT, IGA | TOT | FCT]
 KAHAN = oracle.OPT_KAHAN
 KAHAN_OPTS = [KAHAN, FCT | KAHAN, IGA | TOT | KAHAN, FCT | TOT | KAHAN]
+ABS = oracle.OPT_ABS
+ABS_OPTS = [ABS, ABS | FCT, ABS | TOT, ABS | TOT | FCT]
 
 
 def _fr(s):
@@ -105,17 +107,19 @@ BF_CASES = [((8,), 0), ((8,), 1), ((5, 4), 0), ((5, 4), 1), ((4, 3, 3), 0), ((3,
 
 
 @pytest.mark.parametrize("shape,bc", BF_CASES)
-@pytest.mark.parametrize("opts", ALL_OPTS + KAHAN_OPTS)
+@pytest.mark.parametrize("opts", ALL_OPTS + KAHAN_OPTS + ABS_OPTS)
 def test_bruteforce_exact(shape, bc, opts):
-    """Oracle == exact-rational second coding, every option, 1/2/3-D, both BCs."""
+    """Oracle == exact-rational second coding, every option, 1/2/3-D, both BCs
+    (variable-sign psi for the two variable-sign options, iga and abs)."""
     iga = bool(opts & IGA)
     n_iters = 2 if (iga or len(shape) == 3) else 3
     with_g = len(shape) != 1 or bc == 1
     psi, c, g = _to_frac_case(shape, bc, seed=hash((shape, bc, opts)) % 1000, with_g=with_g,
-                              sign=iga)
+                              sign=iga or bool(opts & ABS))
     n_steps = 2 if len(shape) == 1 else 1
     exact = mpdata_exact(_dict(psi), [_dict(x) for x in c], _dict(g) if g is not None else None,
-                         shape, bc, n_iters, bool(opts & FCT), iga, bool(opts & TOT), n_steps)
+                         shape, bc, n_iters, bool(opts & FCT), iga, bool(opts & TOT), n_steps,
+                         absf=bool(opts & ABS))
     ref = np.zeros(shape)
     for k, v in exact.items():
         ref[k] = float(v)
@@ -189,8 +193,48 @@ def test_kahan_changes_only_rounding():
         assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a)), opts
 
 
+# ------------------------------------------------------------- abs option
+@pytest.mark.parametrize("opts", [0, FCT, TOT, FCT | TOT])
+@pytest.mark.parametrize("shape,bc", [((60,), 0), ((20, 18), 1), ((9, 8, 7), 0)])
+def test_abs_equals_basic_for_nonnegative_psi(opts, shape, bc):
+    """With psi >= 0 everywhere |psi| = psi, so the abs option reduces to the
+    basic scheme bit for bit (Sect. 3.1.5)."""
+    gen = synth.rng(51)
+    c = synth.random_advector(shape, 0.4, gen)
+    if bc == 0:
+        c = synth.periodic_fix(c)
+    psi = gen.uniform(0.0, 1.0, size=shape)
+    a = oracle.step(psi, c, n_iters=3, opts=opts, bc=bc, n_steps=4)
+    b = oracle.step(psi, c, n_iters=3, opts=opts | ABS, bc=bc, n_steps=4)
+    assert np.array_equal(a, b)
+
+
+def test_abs_bounded_fractions_variable_sign():
+    """For a variable-sign field the basic psi-fraction (x_R - x_L)/(x_R + x_L)
+    is unbounded where psi changes sign; with |psi| it is at most 1.  A
+    one-pass-plus-correction step of a field that crosses zero between
+    neighbouring cells therefore stays within the donor-cell bounds scaled by
+    the Courant number under abs, while the basic scheme overshoots."""
+    n = 64
+    psi = np.where(np.arange(n) % 2 == 0, 1.0, -0.999)
+    c = [np.full(n + 1, 0.25)]
+    basic = oracle.step(psi, c, n_iters=2, opts=0, n_steps=1)
+    absr = oracle.step(psi, c, n_iters=2, opts=ABS, n_steps=1)
+    assert np.max(np.abs(absr)) <= 1.0 + 1e-12
+    assert np.max(np.abs(basic)) > 1.5
+
+
+def test_abs_rejected_with_iga_and_in_reverse_mode():
+    psi = np.ones(16)
+    c = [np.full(17, 0.2)]
+    with pytest.raises(ValueError):
+        oracle.step(psi, c, n_iters=2, opts=ABS | IGA)
+    with pytest.raises(ValueError):
+        oracle.adjoint(psi, c, np.ones(16), n_iters=2, opts=ABS, n_steps=1)
+
+
 # ---------------------------------------------------------------- P3 conservation
-@pytest.mark.parametrize("opts", ALL_OPTS + [KAHAN, FCT | KAHAN])
+@pytest.mark.parametrize("opts", ALL_OPTS + [KAHAN, FCT | KAHAN, ABS, ABS | TOT | FCT])
 @pytest.mark.parametrize("shape", [(64,), (24, 20), (10, 9, 8)])
 def test_conservation_periodic(opts, shape):
     """Flux form conserves sum(G psi) to round-off (Sect. 1; eq. gte)."""
@@ -198,7 +242,7 @@ def test_conservation_periodic(opts, shape):
     g = gen.uniform(0.5, 1.5, size=shape)
     c = synth.periodic_fix(synth.random_advector(shape, 0.5, gen))
     psi = gen.uniform(0.0, 1.0, size=shape)
-    if opts & IGA:
+    if opts & (IGA | ABS):
         psi -= 0.5
     n_iters = 2 if opts & IGA else 3
     out = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, n_steps=5)
