@@ -62,6 +62,11 @@ enum {
     MPDATA_OPT_FCT = 1u << 0, /* non-oscillatory limiter, Sect. 3.1.4       */
     MPDATA_OPT_IGA = 1u << 1, /* infinite gauge, Sect. 3.1.5                */
     MPDATA_OPT_TOT = 1u << 2, /* third-order terms, Sect. 3.1.2             */
+    /* |psi| replaces psi in every psi-fraction of the pseudo-velocity, for
+     * variable-sign fields (Sect. 3.1.5).  Not combinable with IGA (the other
+     * variable-sign option: MPDATA_EINVAL); mpdata_adv_adj rejects it
+     * (MPDATA_EUNSUPPORTED). */
+    MPDATA_OPT_ABS = 1u << 3,
     /* Kahan-compensated donor-cell update (Sect. 3.1.1): every donor-cell pass
      * forms psi + sum_d -(F_d(i+1/2) - F_d(i-1/2)) / G with Kahan's
      * compensated summation, dimensions in increasing order, instead of

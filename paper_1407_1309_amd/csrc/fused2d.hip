@@ -112,7 +112,7 @@ template <typename T> struct Pass {
 
     // x_new: row a of the previous pass's result; c0_new / c1_new: the
     // previous pass's advector at wall a / row a; pn_a: psi^n at row a.
-    template <bool FCT, int P>
+    template <bool FCT, bool ABS, int P>
     __device__ __forceinline__ T advance(T x_new, T c0_new, T c1_new, T pn_a, bool kahan)
     {
         AT(xq, 4, 0) = x_new;
@@ -123,20 +123,22 @@ template <typename T> struct Pass {
 
         // psi-fractions of V0 at wall a (rows a-1 | a), column j, and of V1 at
         // row a-1, wall j (columns j-1 | j): A terms and cross (B) terms
+        // (|psi| in every fraction under the abs option)
+        auto fa = [](T v) -> T { return ABS ? fabs(v) : v; };
         T num[4], den[4], fr[4];
         {
-            T xL = AT(xq, 4, 1), xR = AT(xq, 4, 0);
+            T xL = fa(AT(xq, 4, 1)), xR = fa(AT(xq, 4, 0));
             num[0] = xR - xL;
             den[0] = xR + xL;
-            T a = AT(xr, 2, 0), b = AT(xr, 2, 1), e = AT(xl, 4, 0), f = AT(xl, 4, 1);
+            T a = fa(AT(xr, 2, 0)), b = fa(AT(xr, 2, 1)), e = fa(AT(xl, 4, 0)), f = fa(AT(xl, 4, 1));
             num[1] = a + b - e - f;
             den[1] = a + b + e + f;
         }
         {
-            T xL = AT(xl, 4, 1), xR = AT(xq, 4, 1);
+            T xL = fa(AT(xl, 4, 1)), xR = fa(AT(xq, 4, 1));
             num[2] = xR - xL;
             den[2] = xR + xL;
-            T a = AT(xq, 4, 0), b = AT(xl, 4, 0), e = AT(xq, 4, 2), f = AT(xl, 4, 2);
+            T a = fa(AT(xq, 4, 0)), b = fa(AT(xl, 4, 0)), e = fa(AT(xq, 4, 2)), f = fa(AT(xl, 4, 2));
             num[3] = a + b - e - f;
             den[3] = a + b + e + f;
         }
@@ -227,7 +229,7 @@ template <int NI, bool FCT> struct Cfg {
 constexpr int PF = 2;
 
 // State of one wavefront marching down rows i0..i1-1 of a 64-column strip.
-template <typename T, int NI, bool FCT> struct Strip {
+template <typename T, int NI, bool FCT, bool ABS> struct Strip {
     using C = Cfg<NI, FCT>;
     int n0, n1, i0, i1, jj, rr;
     int64_t ld1;
@@ -285,8 +287,8 @@ template <typename T, int NI, bool FCT> struct Strip {
             // i0 - 2 NI + 4 m - 5; earlier iterations of this pass are skipped
             // (the queues then hold only rows outside the cone).
             if (t < i0 - 2 * NI + 4 * (k + 2) - 5) break;
-            T yk = ps[k].template advance<FCT, P>(y, cn0, cn1, pq.v[slot<C::QP>(P, 1 + 2 * k)],
-                                                  kahan);
+            T yk = ps[k].template advance<FCT, ABS, P>(y, cn0, cn1,
+                                                       pq.v[slot<C::QP>(P, 1 + 2 * k)], kahan);
             cn0 = ps[k].aq0.v[slot<4>(P, 1)];
             cn1 = ps[k].aq1.v[slot<4>(P, 1)];
             y = yk;
@@ -299,23 +301,23 @@ template <typename T, int NI, bool FCT> struct Strip {
     }
 };
 
-template <typename T, int NI, bool FCT, int P = 0>
-__device__ __forceinline__ void iter_block(Strip<T, NI, FCT> &st, int t)
+template <typename T, int NI, bool FCT, bool ABS, int P = 0>
+__device__ __forceinline__ void iter_block(Strip<T, NI, FCT, ABS> &st, int t)
 {
     if constexpr (P < Cfg<NI, FCT>::U) {
         st.template iter<P>(t + P);
-        iter_block<T, NI, FCT, P + 1>(st, t);
+        iter_block<T, NI, FCT, ABS, P + 1>(st, t);
     }
 }
 
-template <typename T, int NI, bool FCT>
+template <typename T, int NI, bool FCT, bool ABS>
 __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__ psi_n,
                                            T *__restrict__ psi_out, const T *__restrict__ c0,
                                            const T *__restrict__ c1, int jstrip0, int i0, int i1,
                                            bool kahan)
 {
     using C = Cfg<NI, FCT>;
-    Strip<T, NI, FCT> st;
+    Strip<T, NI, FCT, ABS> st;
     st.kahan = kahan;
     const int lane = threadIdx.x & (WAVE - 1);
     // global column of this lane (may lie outside [0, n1) in the halo)
@@ -361,10 +363,10 @@ __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__
     st.out_lane = lane >= C::H && lane < WAVE - C::H && col < n1;
     st.orow = psi_out + (int64_t)i0 * n1 + (st.out_lane ? col : 0);
 
-    for (int t = t_begin; t <= t_end; t += C::U) iter_block<T, NI, FCT>(st, t);
+    for (int t = t_begin; t <= t_end; t += C::U) iter_block<T, NI, FCT, ABS>(st, t);
 }
 
-template <typename T, int NI, bool FCT>
+template <typename T, int NI, bool FCT, bool ABS>
 __global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int strips, int kahan,
                                                   const T *__restrict__ psi_n,
                                                   T *__restrict__ psi_out,
@@ -376,10 +378,11 @@ __global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int st
     int strip = b % strips, chunk = b / strips;
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1, kahan != 0);
+    strip_body<T, NI, FCT, ABS>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1,
+                                kahan != 0);
 }
 
-template <typename T, int NI, bool FCT>
+template <typename T, int NI, bool FCT, bool ABS>
 __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__restrict__ grids,
                                                           int n_grids, int th, int n_tiles,
                                                           int xcd_order, int kahan,
@@ -412,8 +415,8 @@ __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__res
     int n0 = (int)g.n0, n1 = (int)g.n1;
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi, c0 + g.off_c0,
-                           c1 + g.off_c1, strip * C::OW, i0, i1, kahan != 0);
+    strip_body<T, NI, FCT, ABS>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi, c0 + g.off_c0,
+                                c1 + g.off_c1, strip * C::OW, i0, i1, kahan != 0);
 }
 
 // default rows per chunk (when not tuned): about two waves per SIMD, so the
@@ -428,7 +431,7 @@ int64_t rows_per_chunk(int64_t n0, int64_t strips)
     return th;
 }
 
-template <typename T, int NI, bool FCT>
+template <typename T, int NI, bool FCT, bool ABS>
 hipError_t launch(const Fused2DShape &sh, int kahan, const T *psi_n, T *psi_out, const T *c0,
                   const T *c1, hipStream_t s)
 {
@@ -438,18 +441,18 @@ hipError_t launch(const Fused2DShape &sh, int kahan, const T *psi_n, T *psi_out,
     if (th > sh.n0) th = sh.n0;
     int64_t chunks = cdiv(sh.n0, th);
     int64_t blocks = strips * chunks;
-    k_fused2d<T, NI, FCT><<<(unsigned)blocks, WAVE, 0, s>>>((int)sh.n0, (int)sh.n1, (int)th,
+    k_fused2d<T, NI, FCT, ABS><<<(unsigned)blocks, WAVE, 0, s>>>((int)sh.n0, (int)sh.n1, (int)th,
                                                            (int)strips, kahan, psi_n, psi_out,
                                                            c0, c1);
     return hipGetLastError();
 }
 
-template <typename T, int NI, bool FCT>
+template <typename T, int NI, bool FCT, bool ABS>
 hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, int xcd,
                           int kahan, const T *psi_n, T *psi_out, const T *c0, const T *c1,
                           hipStream_t s)
 {
-    k_fused2d_batched<T, NI, FCT><<<(unsigned)n_tiles, WAVE, 0, s>>>(
+    k_fused2d_batched<T, NI, FCT, ABS><<<(unsigned)n_tiles, WAVE, 0, s>>>(
         g, n_grids, th, n_tiles, xcd, kahan, psi_n, psi_out, c0, c1);
     return hipGetLastError();
 }
@@ -459,7 +462,8 @@ hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, 
 bool fused2d_supported(int nd, int n_iters, unsigned opts, int has_g, int bc0, int bc1)
 {
     if (nd != 2 || has_g || bc0 != BC_PERIODIC || bc1 != BC_PERIODIC) return false;
-    if (opts & ~(OPT_FCT | OPT_KAHAN)) return false;   // tot / iga: staged path
+    if (opts & ~(OPT_FCT | OPT_KAHAN | OPT_ABS)) return false;   // tot / iga: staged path
+    if ((opts & OPT_ABS) && n_iters > 3) return false;
     return n_iters >= 1 && n_iters <= 4;
 }
 
@@ -479,15 +483,25 @@ hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, cons
     if (G || sh.bc0 != BC_PERIODIC || sh.bc1 != BC_PERIODIC) return hipErrorNotSupported;
     bool fct = opts & OPT_FCT;
     const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
-#define MP_L(NI, F) launch<T, NI, F>(sh, kahan, psi_n, psi_out, c0, c1, s)
+    const bool absf = (opts & OPT_ABS) && n_iters > 1;
+#define MP_L(NI, F, A) launch<T, NI, F, A>(sh, kahan, psi_n, psi_out, c0, c1, s)
+    if (absf) {
+        switch (n_iters * 2 + (fct ? 1 : 0)) {
+        case 4: return MP_L(2, false, true);
+        case 5: return MP_L(2, true, true);
+        case 6: return MP_L(3, false, true);
+        case 7: return MP_L(3, true, true);
+        default: return hipErrorNotSupported;
+        }
+    }
     switch (n_iters * 2 + (fct ? 1 : 0)) {
-    case 2: case 3: return MP_L(1, false);
-    case 4: return MP_L(2, false);
-    case 5: return MP_L(2, true);
-    case 6: return MP_L(3, false);
-    case 7: return MP_L(3, true);
-    case 8: return MP_L(4, false);
-    case 9: return MP_L(4, true);
+    case 2: case 3: return MP_L(1, false, false);
+    case 4: return MP_L(2, false, false);
+    case 5: return MP_L(2, true, false);
+    case 6: return MP_L(3, false, false);
+    case 7: return MP_L(3, true, false);
+    case 8: return MP_L(4, false, false);
+    case 9: return MP_L(4, true, false);
     default: return hipErrorNotSupported;
     }
 #undef MP_L
@@ -501,16 +515,26 @@ hipError_t fused2d_batched_step(const BatchGrid *g, int n_grids, int n_tiles, in
     if (bc != BC_PERIODIC || th < 1) return hipErrorNotSupported;
     bool fct = opts & OPT_FCT;
     const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
-#define MP_B(NI, F) \
-    launch_batched<T, NI, F>(g, n_grids, n_tiles, th, xcd, kahan, psi_n, psi_out, c0, c1, s)
+    const bool absf = (opts & OPT_ABS) && n_iters > 1;
+#define MP_B(NI, F, A) \
+    launch_batched<T, NI, F, A>(g, n_grids, n_tiles, th, xcd, kahan, psi_n, psi_out, c0, c1, s)
+    if (absf) {
+        switch (n_iters * 2 + (fct ? 1 : 0)) {
+        case 4: return MP_B(2, false, true);
+        case 5: return MP_B(2, true, true);
+        case 6: return MP_B(3, false, true);
+        case 7: return MP_B(3, true, true);
+        default: return hipErrorNotSupported;
+        }
+    }
     switch (n_iters * 2 + (fct ? 1 : 0)) {
-    case 2: case 3: return MP_B(1, false);
-    case 4: return MP_B(2, false);
-    case 5: return MP_B(2, true);
-    case 6: return MP_B(3, false);
-    case 7: return MP_B(3, true);
-    case 8: return MP_B(4, false);
-    case 9: return MP_B(4, true);
+    case 2: case 3: return MP_B(1, false, false);
+    case 4: return MP_B(2, false, false);
+    case 5: return MP_B(2, true, false);
+    case 6: return MP_B(3, false, false);
+    case 7: return MP_B(3, true, false);
+    case 8: return MP_B(4, false, false);
+    case 9: return MP_B(4, true, false);
     default: return hipErrorNotSupported;
     }
 #undef MP_B

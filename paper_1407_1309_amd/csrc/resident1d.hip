@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
     T *W1 = W0 + (n + 1);
     T *W2 = W1 + (n + 1);
     const bool fct = opts & OPT_FCT, iga = opts & OPT_IGA, tot = opts & OPT_TOT;
-    const bool kahan = opts & OPT_KAHAN;
+    const bool kahan = opts & OPT_KAHAN, absf = opts & OPT_ABS;
     // donor-cell update from the flux difference acc (straightforward, or
     // Kahan-compensated: psi + (-acc / G) as a compensated sum)
     auto upd = [&](T x, T acc, int i) -> T {
@@ -107,10 +107,19 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
                 int L = f - 1, R = f;
                 T u = cprev[mw(f, n, bc)];
                 T Gb = T(0.5) * (gv(L) + gv(R));
+                // |psi| in the psi-fractions under the abs option
                 T xL = X[mc(L, n, bc)], xR = X[mc(R, n, bc)];
+                if (absf) {
+                    xL = fabs(xL);
+                    xR = fabs(xR);
+                }
                 T v = (fabs(u) - u * u / Gb) * rfrac(iga, xR - xL, xR + xL, T(2));
                 if (tot) {
                     T xR2 = X[mc(R + 1, n, bc)], xL2 = X[mc(L - 1, n, bc)];
+                    if (absf) {
+                        xR2 = fabs(xR2);
+                        xL2 = fabs(xL2);
+                    }
                     T D = rfrac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
                     v += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) * D;
                 }

@@ -114,13 +114,18 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
     int64_t M = e[0] * e[1] * e[2];
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= M) return;
-    const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
+    const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT, absf = opts & OPT_ABS;
+    // psi value entering a psi-fraction: |psi| under the abs option
+    auto xv = [&](const Idx3 &q) -> T {
+        T v = cell(g, x, q);
+        return absf ? fabs(v) : v;
+    };
     const T *c[3] = {c0, c1, c2};
     Idx3 p = unflat(t, e);
     Idx3 L = shifted(p, d, -1), R = p;
     T u = wall(g, d, c[d], p);
     T ig = T(1) / (T(0.5) * (gcell(g, G, L) + gcell(g, G, R)));   // 1 / mean G
-    T xL = cell(g, x, L), xR = cell(g, x, R);
+    T xL = xv(L), xR = xv(R);
     T V_ = (fabs(u) - u * u * ig) * frac(iga, xR - xL, xR + xL, T(2));
 
     T cb[3] = {T(0), T(0), T(0)};
@@ -128,18 +133,18 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
         if (o == d) continue;
         cb[o] = T(0.25) * (wall(g, o, c[o], L) + wall(g, o, c[o], shifted(L, o, 1)) +
                            wall(g, o, c[o], R) + wall(g, o, c[o], shifted(R, o, 1)));
-        T a = cell(g, x, shifted(R, o, 1)), b = cell(g, x, shifted(L, o, 1));
-        T e_ = cell(g, x, shifted(R, o, -1)), f = cell(g, x, shifted(L, o, -1));
+        T a = xv(shifted(R, o, 1)), b = xv(shifted(L, o, 1));
+        T e_ = xv(shifted(R, o, -1)), f = xv(shifted(L, o, -1));
         V_ -= T(0.5) * u * cb[o] * ig * frac(iga, a + b - e_ - f, a + b + e_ + f, T(4));
     }
     if (tot) {
-        T xR2 = cell(g, x, shifted(R, d, 1)), xL2 = cell(g, x, shifted(L, d, -1));
+        T xR2 = xv(shifted(R, d, 1)), xL2 = xv(shifted(L, d, -1));
         T D = frac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
         V_ += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) * D;
         for (int o = 0; o < g.nd; o++) {
             if (o == d) continue;
-            T a = cell(g, x, shifted(R, o, 1)), b = cell(g, x, shifted(L, o, 1));
-            T e_ = cell(g, x, shifted(R, o, -1)), f = cell(g, x, shifted(L, o, -1));
+            T a = xv(shifted(R, o, 1)), b = xv(shifted(L, o, 1));
+            T e_ = xv(shifted(R, o, -1)), f = xv(shifted(L, o, -1));
             T E = frac(iga, a - b - e_ + f, a + b + e_ + f, T(4));
             V_ += (fabs(u) * cb[o] * ig - T(2) * u * u * cb[o] * (ig * ig)) * E;
         }
@@ -149,10 +154,10 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
             T num = T(0), den = T(0);
             for (int s = 0; s < 2; s++) {
                 Idx3 S = s ? R : L;
-                T vpp = cell(g, x, shifted(shifted(S, o1, 1), o2, 1));
-                T vmp = cell(g, x, shifted(shifted(S, o1, -1), o2, 1));
-                T vpm = cell(g, x, shifted(shifted(S, o1, 1), o2, -1));
-                T vmm = cell(g, x, shifted(shifted(S, o1, -1), o2, -1));
+                T vpp = xv(shifted(shifted(S, o1, 1), o2, 1));
+                T vmp = xv(shifted(shifted(S, o1, -1), o2, 1));
+                T vpm = xv(shifted(shifted(S, o1, 1), o2, -1));
+                T vmm = xv(shifted(shifted(S, o1, -1), o2, -1));
                 num += vpp - vmp - vpm + vmm;
                 den += vpp + vmp + vpm + vmm;
             }

@@ -44,7 +44,8 @@ def _desc(shape, dtype=mpdata.F64, n_iters=2, opts=0, bc=0, has_g=0):
     (dict(shape=(2,)), mpdata.EINVAL),                    # periodic needs >= 3
     (dict(shape=(4, 4, 4, 4)[:3], n_iters=0), mpdata.EINVAL),
     (dict(shape=(8,), n_iters=9), mpdata.EINVAL),
-    (dict(shape=(8,), opts=8), mpdata.EINVAL),
+    (dict(shape=(8,), opts=64), mpdata.EINVAL),           # unknown option bit
+    (dict(shape=(8,), opts=mpdata.OPT_ABS | mpdata.OPT_IGA), mpdata.EINVAL),
     (dict(shape=(8,), bc=5), mpdata.EINVAL),
     (dict(shape=(8,), dtype=7), mpdata.EINVAL),
     (dict(shape=(8,), opts=mpdata.OPT_IGA, n_iters=3), mpdata.EUNSUPPORTED),

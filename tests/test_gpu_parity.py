@@ -30,8 +30,8 @@ def _inputs(shape, bc, opts, seed, with_g):
     else:
         c = synth.random_advector(shape, 0.45, gen)
     m = min(shape)
-    psi = synth.blob_field(shape, 6, (m / 10, m / 4), "normal" if opts & IGA else "uniform", gen,
-                           periodic=(bc == 0))
+    psi = synth.blob_field(shape, 6, (m / 10, m / 4), "normal" if opts & (IGA | 8) else "uniform",
+                           gen, periodic=(bc == 0))
     return psi, c, g
 
 
@@ -79,6 +79,42 @@ def test_parity_kahan(shape, bc, opts, dtype):
         for kernel in KERNELS:
             out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 5, kernel=kernel)
             assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
+
+
+ABS = mpdata.OPT_ABS
+ABS_CASES = []
+for shape in [(300,), (150, 197), (37, 29, 41)]:
+    for bc in (0, 1):
+        for opts in (ABS, ABS | FCT, ABS | TOT, ABS | TOT | FCT | KAHAN):
+            ABS_CASES.append((shape, bc, opts))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,bc,opts", ABS_CASES)
+def test_parity_abs(shape, bc, opts, dtype):
+    """abs option (|psi| in the psi-fractions) on variable-sign fields through
+    the staged, fused 2-D and resident 1-D kernels, with and without G."""
+    for with_g in (False, True):
+        psi, c, g = _inputs(shape, bc, opts, seed=len(shape) * 100 + bc * 10 + opts + with_g,
+                            with_g=with_g)
+        psi, c, g = as_dtype(psi, dtype), [as_dtype(x, dtype) for x in c], as_dtype(g, dtype)
+        ref = oracle.step(psi, c, g=g, n_iters=3, opts=opts, bc=bc, n_steps=5)
+        for kernel in KERNELS:
+            out = gpu_run(psi, c, g, dtype, 3, opts, bc, 5, kernel=kernel)
+            assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
+
+
+def test_abs_option_errors():
+    with pytest.raises(mpdata.MPDATAError) as ei:
+        mpdata.Plan((32, 32), n_iters=2, opts=ABS | IGA)
+    assert ei.value.code == mpdata.EINVAL
+    plan = mpdata.Plan((32, 32), n_iters=2, opts=ABS, adj_steps=2, ckpt_every=1)
+    x = torch.zeros((32, 32), dtype=torch.float64, device="cuda")
+    c = [torch.zeros((33, 32), dtype=torch.float64, device="cuda"),
+         torch.zeros((32, 33), dtype=torch.float64, device="cuda")]
+    with pytest.raises(mpdata.MPDATAError) as ei:
+        plan.adv_adj(x, c, x, n_steps=2, ckpt_every=1)
+    assert ei.value.code == mpdata.EUNSUPPORTED
 
 
 @pytest.mark.parametrize("n_iters", [1, 2, 3, 4])
