@@ -16,7 +16,7 @@ import numpy as np
 from . import build as _build
 
 BC_PERIODIC, BC_OPEN = 0, 1
-OPT_FCT, OPT_IGA, OPT_TOT, OPT_ABS, OPT_KAHAN = 1, 2, 4, 8, 32
+OPT_FCT, OPT_IGA, OPT_TOT, OPT_ABS, OPT_DFL, OPT_KAHAN = 1, 2, 4, 8, 16, 32
 
 _LIB = None
 _DP = ctypes.POINTER(ctypes.c_double)

@@ -33,7 +33,7 @@ typedef struct {
     int ndims;
     long n[3];
     int bc[3];
-    int iga, tot, fct, kahan, abs;
+    int iga, tot, fct, kahan, abs, dfl;
 } grid_t;
 
 /* ------------------------------------------------------------------------ */
@@ -266,6 +266,21 @@ static double pseudo_velocity(const grid_t *g, int d, const double *x,
         V -= 0.5 * u * cb[o] / Gb * B;
     }
 
+    if (g->dfl) {
+        /* divergent-flow term (Sect. 3.1.3): -c/(2 Gb) times the advector's
+         * divergence at the wall, the mean of the two cells' divergences
+         * sum_o (c_o(hi) - c_o(lo)) */
+        double dv = 0.0;
+        for (int o = 0; o < g->ndims; o++) {
+            long Lh[3], Rh[3];
+            sh(Lh, L, o, 1);
+            sh(Rh, R, o, 1);
+            dv += (wat(g, o, c[o], Lh) - wat(g, o, c[o], L)) +
+                  (wat(g, o, c[o], Rh) - wat(g, o, c[o], R));
+        }
+        V -= 0.25 * u / Gb * dv;
+    }
+
     if (g->tot) {
         long R2[3], L2[3];
         sh(R2, R, d, 1);
@@ -481,7 +496,8 @@ static int make_grid(grid_t *g, int ndims, const long n[3], const int bc[3],
                      unsigned opts)
 {
     if (ndims < 1 || ndims > 3) return -1;
-    if (opts & ~(unsigned)(ORC_OPT_FCT | ORC_OPT_IGA | ORC_OPT_TOT | ORC_OPT_KAHAN | ORC_OPT_ABS))
+    if (opts & ~(unsigned)(ORC_OPT_FCT | ORC_OPT_IGA | ORC_OPT_TOT | ORC_OPT_KAHAN | ORC_OPT_ABS |
+                           ORC_OPT_DFL))
         return -1;
     /* abs and iga are the two alternative variable-sign options */
     if ((opts & ORC_OPT_ABS) && (opts & ORC_OPT_IGA)) return -1;
@@ -497,6 +513,7 @@ static int make_grid(grid_t *g, int ndims, const long n[3], const int bc[3],
     g->tot = (opts & ORC_OPT_TOT) != 0;
     g->kahan = (opts & ORC_OPT_KAHAN) != 0;
     g->abs = (opts & ORC_OPT_ABS) != 0;
+    g->dfl = (opts & ORC_OPT_DFL) != 0;
     return 0;
 }
 
@@ -1116,7 +1133,7 @@ int orc_adjoint(int ndims, const long n[3], const int bc[3], int n_iters,
     if (make_grid(&g, ndims, n, bc, opts)) return -1;
     if (n_iters < 1 || n_iters > 8 || n_steps < 1 || ckpt_every < 1) return -1;
     if (g.iga && n_iters > 2) return -1;
-    if (g.abs) return -1;   /* reverse mode covers the signed fractions only */
+    if (g.abs || g.dfl) return -1;   /* reverse mode: not for the abs and dfl options */
     if (!psi0 || !lambda_T || !grad_psi0) return -1;
     double *c[3] = {(double *)c0, (double *)c1, (double *)c2};
     double *gc[3] = {grad_c0, grad_c1, grad_c2};

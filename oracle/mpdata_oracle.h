@@ -31,8 +31,11 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_OPEN = 1 };
 /* ABS: |psi| replaces psi in every psi-fraction of the pseudo-velocity
  * (variable-sign fields, Sect. 3.1.5); not combinable with IGA, forward
  * only (orc_adjoint rejects it). */
+/* DFL: the pseudo-velocity gains the divergent-flow term -c/(2 Gb) * div,
+ * div the mean over the wall's two cells of sum_o (c_o(hi) - c_o(lo)) of
+ * the pass's advector (Sect. 3.1.3).  Forward only (orc_adjoint rejects it). */
 enum { ORC_OPT_FCT = 1u << 0, ORC_OPT_IGA = 1u << 1, ORC_OPT_TOT = 1u << 2,
-       ORC_OPT_ABS = 1u << 3, ORC_OPT_KAHAN = 1u << 5 };
+       ORC_OPT_ABS = 1u << 3, ORC_OPT_DFL = 1u << 4, ORC_OPT_KAHAN = 1u << 5 };
 
 /* Advance psi (in place) by n_steps MPDATA steps.  g may be NULL (G = 1).
  * c[d] must be non-NULL for d < ndims.  Returns 0, or -1 on bad arguments. */

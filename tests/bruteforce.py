@@ -52,7 +52,7 @@ def _fr(num, den, iga, m):
     return Fraction(0) if den == 0 else num / den
 
 
-def mpdata_exact(psi, c, g, shape, bc, n_iters, fct, iga, tot, n_steps, absf=False):
+def mpdata_exact(psi, c, g, shape, bc, n_iters, fct, iga, tot, n_steps, absf=False, dfl=False):
     """psi: dict cell->Fraction; c: list of dict wall->Fraction; g: dict or None."""
     G = Grid(shape, bc)
     one = Fraction(1)
@@ -104,6 +104,12 @@ def mpdata_exact(psi, c, g, shape, bc, n_iters, fct, iga, tot, n_steps, absf=Fal
                     a, b = X(x, _add(R, o, 1)), X(x, _add(L, o, 1))
                     e, f = X(x, _add(R, o, -1)), X(x, _add(L, o, -1))
                     v -= u * cb[o] / (2 * gb) * _fr(a + b - e - f, a + b + e + f, iga, 4)
+                if dfl:                # divergent-flow term
+                    dv = Fraction(0)
+                    for o in range(G.nd):
+                        for S in (L, R):
+                            dv += W(cp, o, _add(S, o, 1)) - W(cp, o, S)
+                    v -= u / (2 * gb) * dv / 2
                 if tot:
                     x2, x_1 = X(x, _add(R, d, 1)), X(x, _add(L, d, -1))
                     Dq = _fr(x2 - xr - xl + x_1, x2 + xr + xl + x_1, iga, 4)

@@ -28,6 +28,8 @@ KAHAN = oracle.OPT_KAHAN
 KAHAN_OPTS = [KAHAN, FCT | KAHAN, IGA | TOT | KAHAN, FCT | TOT | KAHAN]
 ABS = oracle.OPT_ABS
 ABS_OPTS = [ABS, ABS | FCT, ABS | TOT, ABS | TOT | FCT]
+DFL = oracle.OPT_DFL
+DFL_OPTS = [DFL, DFL | FCT, DFL | TOT, DFL | IGA | TOT | FCT]
 
 
 def _fr(s):
@@ -107,7 +109,7 @@ BF_CASES = [((8,), 0), ((8,), 1), ((5, 4), 0), ((5, 4), 1), ((4, 3, 3), 0), ((3,
 
 
 @pytest.mark.parametrize("shape,bc", BF_CASES)
-@pytest.mark.parametrize("opts", ALL_OPTS + KAHAN_OPTS + ABS_OPTS)
+@pytest.mark.parametrize("opts", ALL_OPTS + KAHAN_OPTS + ABS_OPTS + DFL_OPTS)
 def test_bruteforce_exact(shape, bc, opts):
     """Oracle == exact-rational second coding, every option, 1/2/3-D, both BCs
     (variable-sign psi for the two variable-sign options, iga and abs)."""
@@ -119,7 +121,7 @@ def test_bruteforce_exact(shape, bc, opts):
     n_steps = 2 if len(shape) == 1 else 1
     exact = mpdata_exact(_dict(psi), [_dict(x) for x in c], _dict(g) if g is not None else None,
                          shape, bc, n_iters, bool(opts & FCT), iga, bool(opts & TOT), n_steps,
-                         absf=bool(opts & ABS))
+                         absf=bool(opts & ABS), dfl=bool(opts & DFL))
     ref = np.zeros(shape)
     for k, v in exact.items():
         ref[k] = float(v)
@@ -231,10 +233,65 @@ def test_abs_rejected_with_iga_and_in_reverse_mode():
         oracle.step(psi, c, n_iters=2, opts=ABS | IGA)
     with pytest.raises(ValueError):
         oracle.adjoint(psi, c, np.ones(16), n_iters=2, opts=ABS, n_steps=1)
+    with pytest.raises(ValueError):
+        oracle.adjoint(psi, c, np.ones(16), n_iters=2, opts=DFL, n_steps=1)
+
+
+# ------------------------------------------------------------ dfl option
+def _divergent_1d(N, opts, with_g=False, T=0.5, cour=0.4):
+    """Periodic 1-D run with the divergent advector c = (0.5 + 0.3 sin(2 pi x))
+    dt/dx at fixed Courant number, optionally with G = 1 + 0.4 cos(2 pi x);
+    cell averages of a smooth positive profile."""
+    dx = 1.0 / N
+    dt = cour * dx / 0.8
+    nt = int(round(T / dt))
+    dt = T / nt
+    u = 0.5 + 0.3 * np.sin(2 * np.pi * np.arange(N + 1) * dx)
+    C = u * dt / dx
+    C[-1] = C[0]
+    xs = (np.arange(N * 16) + 0.5) * dx / 16
+    prof = 1.0 + 0.5 * np.sin(2 * np.pi * xs) ** 2 + np.exp(-((xs - 0.5) / 0.1) ** 2)
+    G = (1.0 + 0.4 * np.cos(2 * np.pi * xs)).reshape(N, 16).mean(1) if with_g else None
+    return oracle.step(prof.reshape(N, 16).mean(1), [C], g=G, n_iters=2, opts=opts, n_steps=nt)
+
+
+@pytest.mark.parametrize("with_g", [False, True])
+def test_dfl_restores_second_order_in_divergent_flow(with_g):
+    """In a divergent flow the donor-cell truncation error has a term in the
+    velocity divergence that the basic pseudo-velocity does not remove, so
+    MPDATA drops towards first order; the divergent-flow term (Sect. 3.1.3)
+    restores second order, also with variable G (products of two advector
+    factors divided by the wall mean of G).  Self-convergence against a
+    4096-cell run."""
+    for opts, lo, hi in [(DFL, 1.85, 2.2), (0, 0.9, 1.55)]:
+        ref = _divergent_1d(4096, opts, with_g)
+        errs = []
+        for N in (128, 256, 512):
+            r = ref.reshape(N, 4096 // N).mean(1)
+            errs.append(np.sqrt(np.mean((_divergent_1d(N, opts, with_g) - r) ** 2)))
+        order = np.log2(errs[1] / errs[2])
+        assert lo <= order <= hi, (opts, order)
+
+
+@pytest.mark.parametrize("opts", [0, FCT, TOT, IGA])
+def test_dfl_vanishes_for_nondivergent_advector(opts):
+    """With two passes the corrective pass uses the input advector; for an
+    exactly non-divergent one the divergent-flow term is zero and the result
+    equals the basic scheme bit for bit."""
+    gen = synth.rng(61)
+    shape = (24, 20)
+    c = synth.small_advector(shape, 0.5, gen)
+    psi = gen.uniform(0.0, 1.0, size=shape)
+    if opts & IGA:
+        psi -= 0.5
+    a = oracle.step(psi, c, n_iters=2, opts=opts, n_steps=3)
+    b = oracle.step(psi, c, n_iters=2, opts=opts | DFL, n_steps=3)
+    assert np.array_equal(a, b)
 
 
 # ---------------------------------------------------------------- P3 conservation
-@pytest.mark.parametrize("opts", ALL_OPTS + [KAHAN, FCT | KAHAN, ABS, ABS | TOT | FCT])
+@pytest.mark.parametrize("opts", ALL_OPTS + [KAHAN, FCT | KAHAN, ABS, ABS | TOT | FCT, DFL,
+                                              DFL | TOT | FCT])
 @pytest.mark.parametrize("shape", [(64,), (24, 20), (10, 9, 8)])
 def test_conservation_periodic(opts, shape):
     """Flux form conserves sum(G psi) to round-off (Sect. 1; eq. gte)."""
