@@ -41,6 +41,8 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--kahan", action="store_true",
                     help="Kahan-compensated donor-cell updates (the library-default summation)")
+    ap.add_argument("--abs", action="store_true", help="|psi| in the psi-fractions")
+    ap.add_argument("--dfl", action="store_true", help="divergent-flow pseudo-velocity term")
     ap.add_argument("--tile-rows", type=int, default=None,
                     help="fused kernel rows per wavefront chunk (default: autotune)")
     return ap.parse_args()
@@ -89,9 +91,10 @@ def bench_single(args, torch, mpdata, synth, oracle):
     else:
         case = synth.case_1d()
         name = "1d_periodic_500_iters2"
-    if args.kahan:
-        case.opts |= mpdata.OPT_KAHAN
-        name += "_kahan"
+    for flag, bit in (("kahan", mpdata.OPT_KAHAN), ("abs", mpdata.OPT_ABS), ("dfl", mpdata.OPT_DFL)):
+        if getattr(args, flag):
+            case.opts |= bit
+            name += "_" + flag
     dtype = torch.float32 if f32 else torch.float64
     es = 4 if f32 else 8
     K = args.steps if args.steps is not None else case.n_steps

@@ -67,6 +67,11 @@ enum {
      * variable-sign option: MPDATA_EINVAL); mpdata_adv_adj rejects it
      * (MPDATA_EUNSUPPORTED). */
     MPDATA_OPT_ABS = 1u << 3,
+    /* divergent-flow term (Sect. 3.1.3): the pseudo-velocity at a wall gains
+     * -c/(2 Gb) times the mean over the wall's two cells of the pass
+     * advector's divergence sum_o (c_o(hi) - c_o(lo)).  Staged and resident
+     * 1-D kernels; mpdata_adv_adj rejects it (MPDATA_EUNSUPPORTED). */
+    MPDATA_OPT_DFL = 1u << 4,
     /* Kahan-compensated donor-cell update (Sect. 3.1.1): every donor-cell pass
      * forms psi + sum_d -(F_d(i+1/2) - F_d(i-1/2)) / G with Kahan's
      * compensated summation, dimensions in increasing order, instead of

@@ -81,7 +81,7 @@ int check_desc(const mpdata_desc *d, mp::Geom *g)
     if ((d->opts & MPDATA_OPT_ABS) && (d->opts & MPDATA_OPT_IGA))
         return fail(MPDATA_EINVAL, "abs and iga are alternative variable-sign options");
     if (d->opts & ~(uint32_t)(MPDATA_OPT_FCT | MPDATA_OPT_IGA | MPDATA_OPT_TOT | MPDATA_OPT_ABS |
-                              MPDATA_OPT_KAHAN))
+                              MPDATA_OPT_DFL | MPDATA_OPT_KAHAN))
         return fail(MPDATA_EINVAL, "unknown option bits 0x%x", d->opts);
     g->nd = d->n_dims;
     for (int k = 0; k < 3; k++) {
@@ -530,8 +530,8 @@ int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const voi
 {
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     if (plan->batched) return fail(MPDATA_EINVAL, "adjoint needs a single-grid plan");
-    if (plan->desc.opts & MPDATA_OPT_ABS)
-        return fail(MPDATA_EUNSUPPORTED, "the reverse mode does not cover the abs option");
+    if (plan->desc.opts & (MPDATA_OPT_ABS | MPDATA_OPT_DFL))
+        return fail(MPDATA_EUNSUPPORTED, "the reverse mode does not cover the abs / dfl options");
     if (!psi0 || !lambda_T || !grad_psi0) return fail(MPDATA_EINVAL, "NULL argument");
     if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps)
         return fail(MPDATA_EINVAL, "need 1 <= ckpt_every <= n_steps (got %d, %d)", ckpt_every,

@@ -8,7 +8,7 @@
 namespace mp {
 
 enum { BC_PERIODIC = 0, BC_OPEN = 1 };
-enum { OPT_FCT = 1u, OPT_IGA = 2u, OPT_TOT = 4u, OPT_ABS = 8u, OPT_KAHAN = 32u };
+enum { OPT_FCT = 1u, OPT_IGA = 2u, OPT_TOT = 4u, OPT_ABS = 8u, OPT_DFL = 16u, OPT_KAHAN = 32u };
 
 // Grid extents padded with 1 beyond n_dims; boundary type per dimension.
 struct Geom {

@@ -462,7 +462,7 @@ hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, 
 bool fused2d_supported(int nd, int n_iters, unsigned opts, int has_g, int bc0, int bc1)
 {
     if (nd != 2 || has_g || bc0 != BC_PERIODIC || bc1 != BC_PERIODIC) return false;
-    if (opts & ~(OPT_FCT | OPT_KAHAN | OPT_ABS)) return false;   // tot / iga: staged path
+    if (opts & ~(OPT_FCT | OPT_KAHAN | OPT_ABS)) return false;   // tot / iga / dfl: staged path
     if ((opts & OPT_ABS) && n_iters > 3) return false;
     return n_iters >= 1 && n_iters <= 4;
 }

@@ -410,7 +410,7 @@ k_corr3d(G3 g, int th, int tiles_k, int tiles_j, int nblk, int kahan, const T *_
 
 bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], const int bc[3])
 {
-    if (nd != 3 || !(n_iters == 1 || n_iters == 2) || (opts & (OPT_FCT | OPT_ABS))) return false;
+    if (nd != 3 || !(n_iters == 1 || n_iters == 2) || (opts & (OPT_FCT | OPT_ABS | OPT_DFL))) return false;
     if (n[0] >= 65536 || n[1] >= (1 << 30) || n[2] >= (1 << 30)) return false;
     // halo coordinates (and the planes read past a chunk) must stay within
     // one period of a periodic dimension

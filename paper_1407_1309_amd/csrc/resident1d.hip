@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
     T *W1 = W0 + (n + 1);
     T *W2 = W1 + (n + 1);
     const bool fct = opts & OPT_FCT, iga = opts & OPT_IGA, tot = opts & OPT_TOT;
-    const bool kahan = opts & OPT_KAHAN, absf = opts & OPT_ABS;
+    const bool kahan = opts & OPT_KAHAN, absf = opts & OPT_ABS, dfl = opts & OPT_DFL;
     // donor-cell update from the flux difference acc (straightforward, or
     // Kahan-compensated: psi + (-acc / G) as a compensated sum)
     auto upd = [&](T x, T acc, int i) -> T {
@@ -122,6 +122,13 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
                     }
                     T D = rfrac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
                     v += (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3) * D;
+                }
+                if (dfl) {
+                    // divergent-flow term: -c/(2 Gb) times the mean divergence
+                    // (c(f+1) - c(f)) + (c(f) - c(f-1)) of the two cells
+                    T dv = (cprev[mw(f + 1, n, bc)] - cprev[mw(f, n, bc)]) +
+                           (cprev[mw(f, n, bc)] - cprev[mw(f - 1, n, bc)]);
+                    v -= T(0.25) * u / Gb * dv;
                 }
                 V[f] = v;
             }

@@ -137,6 +137,15 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
         T e_ = xv(shifted(R, o, -1)), f = xv(shifted(L, o, -1));
         V_ -= T(0.5) * u * cb[o] * ig * frac(iga, a + b - e_ - f, a + b + e_ + f, T(4));
     }
+    if (opts & OPT_DFL) {
+        // divergent-flow term: -c / (2 Gb) times the mean of the two cells'
+        // advector divergences sum_o (c_o(hi) - c_o(lo))
+        T dv = T(0);
+        for (int o = 0; o < g.nd; o++)
+            dv += (wall(g, o, c[o], shifted(L, o, 1)) - wall(g, o, c[o], L)) +
+                  (wall(g, o, c[o], shifted(R, o, 1)) - wall(g, o, c[o], R));
+        V_ -= T(0.25) * u * ig * dv;
+    }
     if (tot) {
         T xR2 = xv(shifted(R, d, 1)), xL2 = xv(shifted(L, d, -1));
         T D = frac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));

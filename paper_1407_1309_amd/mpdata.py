@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpdata.so")
 
 OK, EINVAL, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -6
-OPT_FCT, OPT_IGA, OPT_TOT, OPT_ABS, OPT_KAHAN = 1, 2, 4, 8, 32
+OPT_FCT, OPT_IGA, OPT_TOT, OPT_ABS, OPT_DFL, OPT_KAHAN = 1, 2, 4, 8, 16, 32
 BC_PERIODIC, BC_OPEN = 0, 1
 F32, F64 = 0, 1
 KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2

@@ -104,17 +104,43 @@ def test_parity_abs(shape, bc, opts, dtype):
             assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
 
 
+DFL = mpdata.OPT_DFL
+DFL_CASES = []
+for shape in [(300,), (150, 197), (37, 29, 41)]:
+    for bc in (0, 1):
+        for opts in (DFL, DFL | FCT, DFL | TOT | IGA, DFL | TOT | FCT | KAHAN):
+            DFL_CASES.append((shape, bc, opts))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,bc,opts", DFL_CASES)
+def test_parity_dfl(shape, bc, opts, dtype):
+    """Divergent-flow term through the staged and resident 1-D kernels, on
+    divergent (open) and non-divergent (periodic) advectors, with and
+    without G."""
+    n_iters = 2 if opts & IGA else 3
+    for with_g in (False, True):
+        psi, c, g = _inputs(shape, bc, opts, seed=len(shape) * 100 + bc * 10 + opts + with_g,
+                            with_g=with_g)
+        psi, c, g = as_dtype(psi, dtype), [as_dtype(x, dtype) for x in c], as_dtype(g, dtype)
+        ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=5)
+        for kernel in KERNELS:
+            out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 5, kernel=kernel)
+            assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
+
+
 def test_abs_option_errors():
     with pytest.raises(mpdata.MPDATAError) as ei:
         mpdata.Plan((32, 32), n_iters=2, opts=ABS | IGA)
     assert ei.value.code == mpdata.EINVAL
-    plan = mpdata.Plan((32, 32), n_iters=2, opts=ABS, adj_steps=2, ckpt_every=1)
     x = torch.zeros((32, 32), dtype=torch.float64, device="cuda")
     c = [torch.zeros((33, 32), dtype=torch.float64, device="cuda"),
          torch.zeros((32, 33), dtype=torch.float64, device="cuda")]
-    with pytest.raises(mpdata.MPDATAError) as ei:
-        plan.adv_adj(x, c, x, n_steps=2, ckpt_every=1)
-    assert ei.value.code == mpdata.EUNSUPPORTED
+    for opts in (ABS, mpdata.OPT_DFL):
+        plan = mpdata.Plan((32, 32), n_iters=2, opts=opts, adj_steps=2, ckpt_every=1)
+        with pytest.raises(mpdata.MPDATAError) as ei:
+            plan.adv_adj(x, c, x, n_steps=2, ckpt_every=1)
+        assert ei.value.code == mpdata.EUNSUPPORTED
 
 
 @pytest.mark.parametrize("n_iters", [1, 2, 3, 4])
