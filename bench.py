@@ -262,6 +262,7 @@ def bench_adjoint(args, torch, mpdata, synth, oracle):
     out = psi.clone()
     plan.step(out, c, n_steps=K)
     lam = (out - obs).contiguous()
+    plan.autotune(psi, c)                   # chunk length of the fused state sweeps
     plan.adv_adj(psi, c, lam, n_steps=min(K, 2 * ck), ckpt_every=ck)     # warm-up
     t = {}
 

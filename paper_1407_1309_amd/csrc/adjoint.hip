@@ -20,6 +20,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace mp {
 namespace {
 
@@ -148,46 +150,97 @@ template <typename T> __global__ void k_copy(T *a, const T *b, int64_t n)
     if (t < n) a[t] = b[t];
 }
 
-// transpose of the donor-cell pass y = x - sum_d (F(hi) - F(lo)) / G
-template <typename T>
-__global__ void k_donor_adj(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
-                            const T *c2, const T *G, int flux_is_vel, const T *__restrict__ yb,
-                            T *xb, T *cb0, T *cb1, T *cb2)
+// Gather form of the donor-cell transpose (no atomics).  Cell i's adjoint
+// collects, from every cell q in {i - e_d, i, i + e_d} and each of q's two
+// dimension-d walls, the derivative of q's update with respect to x_i
+// through that wall's flux (whose left / right cells are read through the
+// boundary map, exactly as the forward pass reads them); the advector
+// adjoint of a wall collects the same from the cells that read the wall.
+template <typename T, int ND>
+__global__ void k_donor_adj_cells(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
+                                  const T *c2, const T *G, int flux_is_vel,
+                                  const T *__restrict__ yb, T *xb)
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
     int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
     if (t >= N) return;
-    const T *c[3] = {c0, c1, c2};
-    T *cb[3] = {cb0, cb1, cb2};
-    I3 p = unflat_i3(t, g.n);
-    T ob = yb[t];
-    aadd(xb, t, ob);
-    T accb = G ? -ob / G[t] : -ob;
-    for (int d = 0; d < g.nd; d++)
-        for (int s = 0; s < 2; s++) {
-            I3 w = sh1(p, d, s);
-            T fb = s ? accb : -accb;
-            int64_t kw = wi(g, d, w);
-            if (flux_is_vel) {
-                aadd(cb[d], kw, fb);
-                continue;
+    T acc = yb[t];
+    if (!flux_is_vel) {
+        const T *c[3] = {c0, c1, c2};
+        I3 p = unflat_i3(t, g.n);
+#pragma unroll
+        for (int d = 0; d < ND; d++) {
+            const int n = (int)g.n[d], bc = g.bc[d], pd = p.v[d];
+#pragma unroll
+            for (int off = -1; off <= 1; off++) {
+                int qd = pd + off;
+                if (bc == BC_OPEN && (qd < 0 || qd >= n)) continue;
+                I3 q = p;
+                q.v[d] = qd;
+                int64_t kq = ci(g, q);
+                T ybg = G ? yb[kq] / G[kq] : yb[kq];
+#pragma unroll
+                for (int sd = 0; sd < 2; sd++) {
+                    int wd = qd + sd;                  // wall of q (before the map)
+                    int Ld = wrap_cell(wd - 1, n, bc), Rd = wrap_cell(wd, n, bc);
+                    if (Ld != pd && Rd != pd) continue;
+                    I3 w = q;
+                    w.v[d] = wd;
+                    T u = c[d][wi(g, d, w)];
+                    T fb = sd ? -ybg : ybg;            // d y_q / d F (times yb_q)
+                    if (Ld == pd) acc += pos(u) * fb;
+                    if (Rd == pd) acc += neg(u) * fb;
+                }
             }
-            I3 L = sh1(w, d, -1);
-            int64_t kL = ci(g, L), kR = ci(g, w);
-            T u = c[d][kw];
-            T du = (u > T(0) ? x[kL] : T(0)) + (u < T(0) ? x[kR] : T(0));
-            aadd(cb[d], kw, du * fb);
-            aadd(xb, kL, pos(u) * fb);
-            aadd(xb, kR, neg(u) * fb);
         }
+    }
+    xb[t] += acc;
+}
+
+template <typename T, int ND, int WD>
+__global__ void k_donor_adj_walls(Geom g, const T *__restrict__ x, const T *cd, const T *G,
+                                  int flux_is_vel, const T *__restrict__ yb, T *cbd)
+{
+    constexpr int d = WD;
+    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    e[d] += 1;
+    int64_t M = e[0] * e[1] * e[2];
+    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= M) return;
+    I3 w = unflat_i3(t, e);
+    const int n = (int)g.n[d], bc = g.bc[d], wdv = w.v[d];
+    T acc = T(0);
+#pragma unroll
+    for (int sd = 0; sd < 2; sd++) {
+        int qd = wdv - sd;                         // cell whose side sd is this wall
+        if (bc == BC_OPEN && (qd < 0 || qd >= n)) continue;
+        if (wrap_wall(qd + sd, n, bc) != wdv) continue;   // periodic wall n is never read
+        I3 q = w;
+        q.v[d] = qd;
+        int64_t kq = ci(g, q);
+        T ybg = G ? yb[kq] / G[kq] : yb[kq];
+        T fb = sd ? -ybg : ybg;
+        if (flux_is_vel) {
+            acc += fb;
+        } else {
+            T u = cd[wi(g, d, w)];
+            I3 L = q, R = q;
+            L.v[d] = qd + sd - 1;
+            R.v[d] = qd + sd;
+            T du = (u > T(0) ? x[ci(g, L)] : T(0)) + (u < T(0) ? x[ci(g, R)] : T(0));
+            acc += du * fb;
+        }
+    }
+    if (acc != T(0)) cbd[t] += acc;
 }
 
 // transpose of the pseudo-velocity at every dimension-d wall
-template <typename T>
-__global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__ x, const T *c0,
+template <typename T, int ND, int WD>
+__global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, const T *c0,
                              const T *c1, const T *c2, const T *G, const T *__restrict__ Vb,
                              T *xb, T *cb0, T *cb1, T *cb2)
 {
+    constexpr int d = WD;   // wall dimension (compile time: no dynamic indexing)
     int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
     e[d] += 1;
     int64_t M = e[0] * e[1] * e[2];
@@ -216,7 +269,7 @@ __global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__
     aadd(xb, kL, (-fn + fd) * Ab);
 
     T cbar[3] = {T(0), T(0), T(0)}, cbar_b[3] = {T(0), T(0), T(0)};
-    for (int o = 0; o < g.nd; o++) {
+    for (int o = 0; o < ND; o++) {
         if (o == d) continue;
         cbar[o] = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, sh1(L, o, 1))] +
                              c[o][wi(g, o, R)] + c[o][wi(g, o, sh1(R, o, 1))]);
@@ -247,7 +300,7 @@ __global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__
         aadd(xb, kR, (-fn + fd) * Db);
         aadd(xb, kL, (-fn + fd) * Db);
         aadd(xb, kL2, (fn + fd) * Db);
-        for (int o = 0; o < g.nd; o++) {
+        for (int o = 0; o < ND; o++) {
             if (o == d) continue;
             int64_t kRp = ci(g, sh1(R, o, 1)), kLp = ci(g, sh1(L, o, 1));
             int64_t kRm = ci(g, sh1(R, o, -1)), kLm = ci(g, sh1(L, o, -1));
@@ -264,7 +317,7 @@ __global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__
             aadd(xb, kRm, (-fn + fd) * Eb);
             aadd(xb, kLm, (fn + fd) * Eb);
         }
-        if (g.nd == 3) {
+        if (ND == 3) {
             int o1 = (d == 0) ? 1 : 0;
             int o2 = (d == 2) ? 1 : 2;
             int64_t kp[2][4];
@@ -292,7 +345,7 @@ __global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__
         }
     }
     aadd(cb[d], wi(g, d, p), ub);
-    for (int o = 0; o < g.nd; o++) {
+    for (int o = 0; o < ND; o++) {
         if (o == d || cbar_b[o] == T(0)) continue;
         T q = T(0.25) * cbar_b[o];
         aadd(cb[o], wi(g, o, L), q);
@@ -303,11 +356,12 @@ __global__ void k_pseudo_adj(Geom g, int d, unsigned opts, const T *__restrict__
 }
 
 // transpose of the limited velocity W = [V]+ up + [V]- dn at dimension-d walls
-template <typename T>
-__global__ void k_limit_adj(Geom g, int d, const T *__restrict__ V, const T *__restrict__ bup,
+template <typename T, int ND, int WD>
+__global__ void k_limit_adj(Geom g, const T *__restrict__ V, const T *__restrict__ bup,
                             const T *__restrict__ bdn, const T *__restrict__ Wb, T *Vb, T *bub,
                             T *bdb)
 {
+    constexpr int d = WD;   // wall dimension (compile time)
     int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
     e[d] += 1;
     int64_t M = e[0] * e[1] * e[2];
@@ -334,7 +388,7 @@ __global__ void k_limit_adj(Geom g, int d, const T *__restrict__ V, const T *__r
 }
 
 // transpose of the limiter coefficients (bounds, in/out fluxes) per cell
-template <typename T>
+template <typename T, int ND>
 __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
                            const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
                            const T *G, const T *__restrict__ bub, const T *__restrict__ bdb,
@@ -355,7 +409,7 @@ __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
     T v = x[t];
     if (v > mx) { mx = v; smx = 1; }
     if (v < mn) { mn = v; smn = 1; }
-    for (int d = 0; d < g.nd; d++)
+    for (int d = 0; d < ND; d++)
         for (int s = -1; s <= 1; s += 2) {
             int64_t kq = ci(g, sh1(p, d, s));
             T a = psi_n[kq], b = x[kq];
@@ -366,7 +420,7 @@ __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
         }
     T xi = v;
     T fin = T(0), fout = T(0);
-    for (int d = 0; d < g.nd; d++) {
+    for (int d = 0; d < ND; d++) {
         T vlo = V[d][wi(g, d, p)], vhi = V[d][wi(g, d, sh1(p, d, 1))];
         T wm = iga ? T(1) : x[ci(g, sh1(p, d, -1))];
         T wp = iga ? T(1) : x[ci(g, sh1(p, d, 1))];
@@ -388,7 +442,7 @@ __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
     }
     aadd(smx ? xb : pnb, amx, mxb);
     aadd(smn ? xb : pnb, amn, mnb);
-    for (int d = 0; d < g.nd; d++) {
+    for (int d = 0; d < ND; d++) {
         int64_t wlo = wi(g, d, p), whi = wi(g, d, sh1(p, d, 1));
         int64_t km = ci(g, sh1(p, d, -1)), kp = ci(g, sh1(p, d, 1));
         T vlo = V[d][wlo], vhi = V[d][whi];
@@ -404,6 +458,86 @@ __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
         }
     }
     aadd(xb, t, xib);
+}
+
+// Run f with the dimension count (and a wall dimension) as compile-time
+// constants.
+template <typename F> void with_nd(int nd, F f)
+{
+    if (nd == 1)
+        f(std::integral_constant<int, 1>{});
+    else if (nd == 2)
+        f(std::integral_constant<int, 2>{});
+    else
+        f(std::integral_constant<int, 3>{});
+}
+
+template <typename F> void with_nd_d(int nd, int d, F f)
+{
+    using N1 = std::integral_constant<int, 1>;
+    using N2 = std::integral_constant<int, 2>;
+    using N3 = std::integral_constant<int, 3>;
+    using D0 = std::integral_constant<int, 0>;
+    using D1 = std::integral_constant<int, 1>;
+    using D2 = std::integral_constant<int, 2>;
+    if (nd == 1)
+        f(N1{}, D0{});
+    else if (nd == 2) {
+        if (d == 0) f(N2{}, D0{}); else f(N2{}, D1{});
+    } else {
+        if (d == 0) f(N3{}, D0{}); else if (d == 1) f(N3{}, D1{}); else f(N3{}, D2{});
+    }
+}
+
+// transpose of a donor-cell pass: xb += (dy/dx)^T yb, cb_d += (dy/dc_d)^T yb
+template <typename T>
+void donor_adj(const Geom &g, const T *x, const T *const c[3], const T *G, int flux_is_vel,
+               const T *yb, T *xb, T *const cb[3], hipStream_t s)
+{
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    with_nd(g.nd, [&](auto ND) {
+        k_donor_adj_cells<T, decltype(ND)::value><<<(unsigned)cdiv(N, B), B, 0, s>>>(
+            g, x, c[0], c[1], c[2], G, flux_is_vel, yb, xb);
+    });
+    for (int d = 0; d < g.nd; d++) {
+        int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+        e[d] += 1;
+        const int64_t M = e[0] * e[1] * e[2];
+        with_nd_d(g.nd, d, [&](auto ND, auto WD) {
+            k_donor_adj_walls<T, decltype(ND)::value, decltype(WD)::value>
+                <<<(unsigned)cdiv(M, B), B, 0, s>>>(g, x, c[d], G, flux_is_vel, yb, cb[d]);
+        });
+    }
+}
+
+// launches with the dimension count (and wall dimension) as template
+// parameters, so the stencil indices are static
+template <typename T>
+void pseudo_adj_dispatch(const Geom &g, int d, unsigned blocks, hipStream_t s, unsigned opts,
+                         const T *x, const T *c0, const T *c1, const T *c2, const T *G,
+                         const T *Vb, T *xb, T *cb0, T *cb1, T *cb2)
+{
+#define MP_P(ND, D) \
+    k_pseudo_adj<T, ND, D><<<blocks, B, 0, s>>>(g, opts, x, c0, c1, c2, G, Vb, xb, cb0, cb1, cb2)
+    if (g.nd == 1) MP_P(1, 0);
+    else if (g.nd == 2) { if (d == 0) MP_P(2, 0); else MP_P(2, 1); }
+    else { if (d == 0) MP_P(3, 0); else if (d == 1) MP_P(3, 1); else MP_P(3, 2); }
+#undef MP_P
+}
+
+template <typename T>
+void beta_adj_dispatch(const Geom &g, unsigned blocks, hipStream_t s, unsigned opts,
+                       const T *psi_n, const T *x, const T *V0, const T *V1, const T *V2,
+                       const T *G, const T *bub, const T *bdb, T *xb, T *pnb, T *Vb0, T *Vb1,
+                       T *Vb2)
+{
+#define MP_B(ND) \
+    k_beta_adj<T, ND><<<blocks, B, 0, s>>>(g, opts, psi_n, x, V0, V1, V2, G, bub, bdb, xb, pnb, \
+                                          Vb0, Vb1, Vb2)
+    if (g.nd == 1) MP_B(1);
+    else if (g.nd == 2) MP_B(2);
+    else MP_B(3);
+#undef MP_B
 }
 
 int64_t ncells(const Geom &g) { return g.n[0] * g.n[1] * g.n[2]; }
@@ -556,17 +690,22 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
             clear_n<T>(f, s);
         }
         // corrective donor-cell pass
-        k_donor_adj<T><<<cb, B, 0, s>>>(g, x, w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2], a.G,
-                                        iga ? 1 : 0, w.yb, w.xb, w.Ab[0], w.Ab[1], w.Ab[2]);
+        {
+            const T *Wc[3] = {w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2]};
+            donor_adj<T>(g, x, Wc, a.G, iga ? 1 : 0, w.yb, w.xb, w.Ab, s);
+        }
         // limiter
         if (fct) {
             for (int d = 0; d < g.nd; d++)
-                k_limit_adj<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
-                    g, d, w.V[it - 1][d], w.bu[it - 1], w.bd[it - 1], w.Ab[d], w.Vb[d], w.bub,
-                    w.bdb);
-            k_beta_adj<T><<<cb, B, 0, s>>>(g, a.opts, psi_n, x, w.V[it - 1][0], w.V[it - 1][1],
-                                           w.V[it - 1][2], a.G, w.bub, w.bdb, w.xb, w.pnb,
-                                           w.Vb[0], w.Vb[1], w.Vb[2]);
+                with_nd_d(g.nd, d, [&](auto ND, auto WD) {
+                    k_limit_adj<T, decltype(ND)::value, decltype(WD)::value>
+                        <<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
+                            g, w.V[it - 1][d], w.bu[it - 1], w.bd[it - 1], w.Ab[d], w.Vb[d],
+                            w.bub, w.bdb);
+                });
+            beta_adj_dispatch<T>(g, cb, s, a.opts, psi_n, x, w.V[it - 1][0], w.V[it - 1][1],
+                                 w.V[it - 1][2], a.G, w.bub, w.bdb, w.xb, w.pnb, w.Vb[0],
+                                 w.Vb[1], w.Vb[2]);
         } else {
             for (int d = 0; d < g.nd; d++)
                 k_copy<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(w.Vb[d], w.Ab[d],
@@ -581,9 +720,9 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
         const T *cin[3];
         for (int d = 0; d < 3; d++) cin[d] = (it == 2) ? a.c[d] : w.W[it - 2][d];
         for (int d = 0; d < g.nd; d++)
-            k_pseudo_adj<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
-                g, d, a.opts, x, cin[0], cin[1], cin[2], a.G, w.Vb[d], w.xb, w.Ab[0], w.Ab[1],
-                w.Ab[2]);
+            pseudo_adj_dispatch<T>(g, d, (unsigned)cdiv(nwalls(g, d), B), s, a.opts, x, cin[0],
+                                   cin[1], cin[2], a.G, w.Vb[d], w.xb, w.Ab[0], w.Ab[1],
+                                   w.Ab[2]);
         if (it == 2) {
             // the first corrective pass reads the input advector: move its
             // adjoint into the result and clear the buffer
@@ -601,8 +740,7 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
     }
     // donor-cell pass of the input field with the input advector
     e = fill<T>(w.xb, N, s);
-    k_donor_adj<T><<<cb, B, 0, s>>>(g, psi_n, a.c[0], a.c[1], a.c[2], a.G, 0, w.yb, w.xb, w.Cb[0],
-                                    w.Cb[1], w.Cb[2]);
+    donor_adj<T>(g, psi_n, a.c, a.G, 0, w.yb, w.xb, w.Cb, s);
     k_add<T><<<cb, B, 0, s>>>(w.xb, w.pnb, N);
     T *t = w.yb;
     w.yb = w.xb;

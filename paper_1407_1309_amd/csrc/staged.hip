@@ -8,6 +8,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace mp {
 namespace {
 
@@ -66,7 +68,7 @@ __device__ inline T frac(bool iga, T num, T den, T m)
 // donor-cell pass (eqs. upstream, F).  mode bit 0: the wall flux is the
 // advector itself (infinite-gauge corrective pass); bit 1: Kahan-compensated
 // update (terms -(F(hi) - F(lo)) / G, dimensions in increasing order)
-template <typename T>
+template <typename T, int ND>
 __global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
                         const T *c2, const T *G, int mode, T *__restrict__ out)
 {
@@ -78,7 +80,7 @@ __global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c
     const T *c[3] = {c0, c1, c2};
     T acc = T(0);
     T ks = x[t], kc = T(0);
-    for (int d = 0; d < g.nd; d++) {
+    for (int d = 0; d < ND; d++) {
         T fl[2];
         for (int s = 0; s < 2; s++) {
             Idx3 w = shifted(p, d, s);
@@ -105,10 +107,11 @@ __global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c
 
 // antidiffusive pseudo-velocity at every dimension-d wall (eq. adf_vel, its
 // cross terms and the third-order terms)
-template <typename T>
-__global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, const T *c0,
+template <typename T, int ND, int WD>
+__global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T *c0,
                          const T *c1, const T *c2, const T *G, T *__restrict__ V)
 {
+    constexpr int d = WD;   // wall dimension (compile time: no dynamic indexing)
     int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
     e[d] += 1;
     int64_t M = e[0] * e[1] * e[2];
@@ -129,7 +132,7 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
     T V_ = (fabs(u) - u * u * ig) * frac(iga, xR - xL, xR + xL, T(2));
 
     T cb[3] = {T(0), T(0), T(0)};
-    for (int o = 0; o < g.nd; o++) {
+    for (int o = 0; o < ND; o++) {
         if (o == d) continue;
         cb[o] = T(0.25) * (wall(g, o, c[o], L) + wall(g, o, c[o], shifted(L, o, 1)) +
                            wall(g, o, c[o], R) + wall(g, o, c[o], shifted(R, o, 1)));
@@ -141,7 +144,7 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
         // divergent-flow term: -c / (2 Gb) times the mean of the two cells'
         // advector divergences sum_o (c_o(hi) - c_o(lo))
         T dv = T(0);
-        for (int o = 0; o < g.nd; o++)
+        for (int o = 0; o < ND; o++)
             dv += (wall(g, o, c[o], shifted(L, o, 1)) - wall(g, o, c[o], L)) +
                   (wall(g, o, c[o], shifted(R, o, 1)) - wall(g, o, c[o], R));
         V_ -= T(0.25) * u * ig * dv;
@@ -150,14 +153,14 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
         T xR2 = xv(shifted(R, d, 1)), xL2 = xv(shifted(L, d, -1));
         T D = frac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
         V_ += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) * D;
-        for (int o = 0; o < g.nd; o++) {
+        for (int o = 0; o < ND; o++) {
             if (o == d) continue;
             T a = xv(shifted(R, o, 1)), b = xv(shifted(L, o, 1));
             T e_ = xv(shifted(R, o, -1)), f = xv(shifted(L, o, -1));
             T E = frac(iga, a - b - e_ + f, a + b + e_ + f, T(4));
             V_ += (fabs(u) * cb[o] * ig - T(2) * u * u * cb[o] * (ig * ig)) * E;
         }
-        if (g.nd == 3) {
+        if (ND == 3) {
             int o1 = (d == 0) ? 1 : 0;
             int o2 = (d == 2) ? 1 : 2;
             T num = T(0), den = T(0);
@@ -177,7 +180,7 @@ __global__ void k_pseudo(Geom g, int d, unsigned opts, const T *__restrict__ x, 
 }
 
 // limiter coefficients per cell (Sect. 3.1.4)
-template <typename T>
+template <typename T, int ND>
 __global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
                            const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
                            const T *G, T *__restrict__ bup, T *__restrict__ bdn)
@@ -192,7 +195,7 @@ __global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
     T mx = psi_n[t], mn = mx;
     mx = fmax(mx, xi);
     mn = fmin(mn, xi);
-    for (int d = 0; d < g.nd; d++)
+    for (int d = 0; d < ND; d++)
         for (int s = -1; s <= 1; s += 2) {
             Idx3 q = shifted(p, d, s);
             T a = cell(g, psi_n, q), b = cell(g, x, q);
@@ -200,7 +203,7 @@ __global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
             mn = fmin(fmin(mn, a), b);
         }
     T fin = T(0), fout = T(0);
-    for (int d = 0; d < g.nd; d++) {
+    for (int d = 0; d < ND; d++) {
         T vlo = wall(g, d, V[d], p), vhi = wall(g, d, V[d], shifted(p, d, 1));
         T wm = iga ? T(1) : cell(g, x, shifted(p, d, -1));
         T wp = iga ? T(1) : cell(g, x, shifted(p, d, 1));
@@ -214,10 +217,11 @@ __global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
 }
 
 // limited pseudo-velocity at every dimension-d wall
-template <typename T>
-__global__ void k_fct_limit(Geom g, int d, const T *__restrict__ V, const T *__restrict__ bup,
+template <typename T, int ND, int WD>
+__global__ void k_fct_limit(Geom g, const T *__restrict__ V, const T *__restrict__ bup,
                             const T *__restrict__ bdn, T *__restrict__ W)
 {
+    constexpr int d = WD;   // wall dimension (compile time)
     int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
     e[d] += 1;
     int64_t M = e[0] * e[1] * e[2];
@@ -247,9 +251,53 @@ hipError_t launch_donor(const Geom &g, const T *x, const T *const c[3], const T 
                         int mode, T *out, hipStream_t s)
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
-    k_donor<T><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(g, x, c[0], c[1], c[2], G, mode,
-                                                        out);
+    with_nd(g.nd, [&](auto ND) {
+        k_donor<T, decltype(ND)::value><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(
+            g, x, c[0], c[1], c[2], G, mode, out);
+    });
     return hipGetLastError();
+}
+
+// Run f with the dimension count as a compile-time constant.
+template <typename F> void with_nd(int nd, F f)
+{
+    if (nd == 1)
+        f(std::integral_constant<int, 1>{});
+    else if (nd == 2)
+        f(std::integral_constant<int, 2>{});
+    else
+        f(std::integral_constant<int, 3>{});
+}
+
+// ... and with a wall dimension d < nd as a second one.
+template <typename F> void with_nd_d(int nd, int d, F f)
+{
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3c = std::integral_constant<int, 3>;
+    using D0 = std::integral_constant<int, 0>;
+    using D1 = std::integral_constant<int, 1>;
+    using D2 = std::integral_constant<int, 2>;
+    if (nd == 1)
+        f(I1{}, D0{});
+    else if (nd == 2) {
+        if (d == 0) f(I2{}, D0{}); else f(I2{}, D1{});
+    } else {
+        if (d == 0) f(I3c{}, D0{}); else if (d == 1) f(I3c{}, D1{}); else f(I3c{}, D2{});
+    }
+}
+
+// k_pseudo for the runtime (n_dims, d): the dimension count and the wall
+// dimension are template parameters so every stencil index is static
+template <typename T>
+void pseudo_dispatch(const Geom &g, int d, unsigned wb, unsigned tb, hipStream_t s, unsigned opts,
+                     const T *x, const T *c0, const T *c1, const T *c2, const T *G, T *V)
+{
+#define MP_P(ND, D) k_pseudo<T, ND, D><<<wb, tb, 0, s>>>(g, opts, x, c0, c1, c2, G, V)
+    if (g.nd == 1) MP_P(1, 0);
+    else if (g.nd == 2) { if (d == 0) MP_P(2, 0); else MP_P(2, 1); }
+    else { if (d == 0) MP_P(3, 0); else if (d == 1) MP_P(3, 1); else MP_P(3, 2); }
+#undef MP_P
 }
 
 template <typename T>
@@ -258,7 +306,7 @@ hipError_t launch_pseudo(const Geom &g, unsigned opts, const T *x, const T *cons
 {
     for (int d = 0; d < g.nd; d++) {
         unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), 256);
-        k_pseudo<T><<<wb, 256, 0, s>>>(g, d, opts, x, c[0], c[1], c[2], G, V[d]);
+        pseudo_dispatch<T>(g, d, wb, 256, s, opts, x, c[0], c[1], c[2], G, V[d]);
     }
     return hipGetLastError();
 }
@@ -269,11 +317,16 @@ hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
                       hipStream_t s)
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
-    k_fct_beta<T><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(g, opts, psi_n, x, V[0], V[1], V[2],
-                                                          G, bup, bdn);
+    with_nd(g.nd, [&](auto ND) {
+        k_fct_beta<T, decltype(ND)::value><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(
+            g, opts, psi_n, x, V[0], V[1], V[2], G, bup, bdn);
+    });
     for (int d = 0; d < g.nd; d++) {
         unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), 256);
-        k_fct_limit<T><<<wb, 256, 0, s>>>(g, d, V[d], bup, bdn, W[d]);
+        with_nd_d(g.nd, d, [&](auto ND, auto WD) {
+            k_fct_limit<T, decltype(ND)::value, decltype(WD)::value><<<wb, 256, 0, s>>>(
+                g, V[d], bup, bdn, W[d]);
+        });
     }
     return hipGetLastError();
 }
@@ -302,7 +355,10 @@ hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s)
 
     T *out1 = (a.n_iters == 1) ? a.psi_out : a.tmp[0];
     const int km = (a.opts & OPT_KAHAN) ? 2 : 0;
-    k_donor<T><<<cblocks, B, 0, s>>>(g, a.psi_n, a.c[0], a.c[1], a.c[2], a.G, km, out1);
+    with_nd(g.nd, [&](auto ND) {
+        k_donor<T, decltype(ND)::value><<<cblocks, B, 0, s>>>(g, a.psi_n, a.c[0], a.c[1], a.c[2],
+                                                              a.G, km, out1);
+    });
     const T *cprev[3] = {a.c[0], a.c[1], a.c[2]};
     const T *x = out1;
     int set = 0;
@@ -311,24 +367,32 @@ hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s)
         T *const *raw = a.faces[set];
         for (int d = 0; d < g.nd; d++) {
             unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), B);
-            k_pseudo<T><<<wb, B, 0, s>>>(g, d, a.opts, x, cprev[0], cprev[1], cprev[2], a.G,
+            pseudo_dispatch<T>(g, d, wb, B, s, a.opts, x, cprev[0], cprev[1], cprev[2], a.G,
                                          raw[d]);
         }
         T *const *adv = raw;
         if (fct) {
             T *const *lim = a.faces[set ^ 1];
-            k_fct_beta<T><<<cblocks, B, 0, s>>>(g, a.opts, a.psi_n, x, raw[0], raw[1], raw[2],
-                                                a.G, a.bup, a.bdn);
+            with_nd(g.nd, [&](auto ND) {
+                k_fct_beta<T, decltype(ND)::value><<<cblocks, B, 0, s>>>(
+                    g, a.opts, a.psi_n, x, raw[0], raw[1], raw[2], a.G, a.bup, a.bdn);
+            });
             for (int d = 0; d < g.nd; d++) {
                 unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), B);
-                k_fct_limit<T><<<wb, B, 0, s>>>(g, d, raw[d], a.bup, a.bdn, lim[d]);
+                with_nd_d(g.nd, d, [&](auto ND, auto WD) {
+                    k_fct_limit<T, decltype(ND)::value, decltype(WD)::value><<<wb, B, 0, s>>>(
+                        g, raw[d], a.bup, a.bdn, lim[d]);
+                });
             }
             adv = lim;
         } else {
             set ^= 1;
         }
         T *y = (it == a.n_iters) ? a.psi_out : a.tmp[(it - 1) & 1];
-        k_donor<T><<<cblocks, B, 0, s>>>(g, x, adv[0], adv[1], adv[2], a.G, (iga ? 1 : 0) | km, y);
+        with_nd(g.nd, [&](auto ND) {
+            k_donor<T, decltype(ND)::value><<<cblocks, B, 0, s>>>(g, x, adv[0], adv[1], adv[2],
+                                                                  a.G, (iga ? 1 : 0) | km, y);
+        });
         for (int d = 0; d < 3; d++) cprev[d] = adv[d];
         x = y;
     }
