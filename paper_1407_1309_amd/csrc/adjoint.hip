@@ -355,6 +355,91 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
     }
 }
 
+// 2-D transpose of the pseudo-velocity (no third-order terms) with the
+// scatter staged in LDS: a workgroup owns a tile of TPR x TPC walls and
+// accumulates its contributions to the cell adjoint and to the other
+// dimension's advector adjoint in two LDS boxes (the tile plus a one-cell
+// rim, in coordinates before the boundary map), then adds each non-zero box
+// entry to the mapped global entry with one atomic -- about one global
+// atomic per target instead of one per contribution.
+constexpr int TPR = 4, TPC = 64;                  // tile rows x columns (walls)
+constexpr int BXR = TPR + 2, BXC = TPC + 2;       // LDS box: rows / columns
+
+template <typename T, int WD>
+__global__ void __launch_bounds__(TPR * TPC)
+k_pseudo_adj2t(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
+               const T *G, const T *__restrict__ Vb, T *xb, T *cb0, T *cb1)
+{
+    constexpr int d = WD, o = 1 - WD;
+    __shared__ T XB[BXR * BXC];
+    __shared__ T CB[BXR * BXC];
+    const int e0 = (int)g.n[0] + (d == 0), e1 = (int)g.n[1] + (d == 1);
+    const int tiles_c = (e1 + TPC - 1) / TPC;
+    const int i0 = (blockIdx.x / tiles_c) * TPR, j0 = (blockIdx.x % tiles_c) * TPC;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < BXR * BXC; k += TPR * TPC) {
+        XB[k] = T(0);
+        CB[k] = T(0);
+    }
+    __syncthreads();
+    // box entry of unmapped coordinates (i, j)
+    auto bx = [&](int i, int j) { return (i - i0 + 1) * BXC + (j - j0 + 1); };
+    const int i = i0 + tid / TPC, j = j0 + tid % TPC;
+    const T *c[2] = {c0, c1};
+    T *cbp[2] = {cb0, cb1};
+    if (i < e0 && j < e1) {
+        const int64_t t = (int64_t)i * e1 + j;
+        const T vb = Vb[t];
+        if (vb != T(0)) {
+            const bool iga = opts & OPT_IGA;
+            I3 p{{i, j, 0}};
+            I3 L = sh1(p, d, -1), R = p;
+            T u = c[d][wi(g, d, p)];
+            T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
+            T Gb = T(0.5) * (GL + GR);
+            T xL = x[ci(g, L)], xR = x[ci(g, R)];
+            T ub = T(0), fn, fd;
+            T nA = xR - xL, dA = xR + xL;
+            T A = fracv(iga, nA, dA, T(2));
+            frac_d(iga, nA, dA, T(2), fn, fd);
+            ub += (sgnv(u) - T(2) * u / Gb) * A * vb;
+            T Ab = (fabs(u) - u * u / Gb) * vb;
+            atomicAdd(&XB[bx(R.v[0], R.v[1])], (fn + fd) * Ab);
+            atomicAdd(&XB[bx(L.v[0], L.v[1])], (-fn + fd) * Ab);
+            I3 Lo = sh1(L, o, 1), Ro = sh1(R, o, 1);
+            T cbar = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, Lo)] + c[o][wi(g, o, R)] +
+                                c[o][wi(g, o, Ro)]);
+            I3 Rp = sh1(R, o, 1), Lp = sh1(L, o, 1), Rm = sh1(R, o, -1), Lm = sh1(L, o, -1);
+            T a = x[ci(g, Rp)], b = x[ci(g, Lp)], ee = x[ci(g, Rm)], f = x[ci(g, Lm)];
+            T nB = a + b - ee - f, dB = a + b + ee + f;
+            T Bv = fracv(iga, nB, dB, T(4));
+            frac_d(iga, nB, dB, T(4), fn, fd);
+            ub += T(-0.5) * cbar / Gb * Bv * vb;
+            T cbar_b = T(-0.5) * u / Gb * Bv * vb;
+            T Bb = T(-0.5) * u * cbar / Gb * vb;
+            atomicAdd(&XB[bx(Rp.v[0], Rp.v[1])], (fn + fd) * Bb);
+            atomicAdd(&XB[bx(Lp.v[0], Lp.v[1])], (fn + fd) * Bb);
+            atomicAdd(&XB[bx(Rm.v[0], Rm.v[1])], (-fn + fd) * Bb);
+            atomicAdd(&XB[bx(Lm.v[0], Lm.v[1])], (-fn + fd) * Bb);
+            if (cbar_b != T(0)) {
+                T q = T(0.25) * cbar_b;
+                atomicAdd(&CB[bx(L.v[0], L.v[1])], q);
+                atomicAdd(&CB[bx(Lo.v[0], Lo.v[1])], q);
+                atomicAdd(&CB[bx(R.v[0], R.v[1])], q);
+                atomicAdd(&CB[bx(Ro.v[0], Ro.v[1])], q);
+            }
+            aadd(cbp[d], wi(g, d, p), ub);
+        }
+    }
+    __syncthreads();
+    // flush: box entries to the mapped global entries
+    for (int k = tid; k < BXR * BXC; k += TPR * TPC) {
+        I3 q{{i0 - 1 + k / BXC, j0 - 1 + k % BXC, 0}};
+        if (XB[k] != T(0)) aadd(xb, ci(g, q), XB[k]);
+        if (CB[k] != T(0)) aadd(cbp[o], wi(g, o, q), CB[k]);
+    }
+}
+
 // transpose of the limited velocity W = [V]+ up + [V]- dn at dimension-d walls
 template <typename T, int ND, int WD>
 __global__ void k_limit_adj(Geom g, const T *__restrict__ V, const T *__restrict__ bup,
@@ -517,6 +602,15 @@ void pseudo_adj_dispatch(const Geom &g, int d, unsigned blocks, hipStream_t s, u
                          const T *x, const T *c0, const T *c1, const T *c2, const T *G,
                          const T *Vb, T *xb, T *cb0, T *cb1, T *cb2)
 {
+    if (g.nd == 2 && !(opts & OPT_TOT)) {
+        const int64_t e0 = g.n[0] + (d == 0), e1 = g.n[1] + (d == 1);
+        const unsigned tb = (unsigned)(cdiv(e0, TPR) * cdiv(e1, TPC));
+        if (d == 0)
+            k_pseudo_adj2t<T, 0><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb, xb, cb0, cb1);
+        else
+            k_pseudo_adj2t<T, 1><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb, xb, cb0, cb1);
+        return;
+    }
 #define MP_P(ND, D) \
     k_pseudo_adj<T, ND, D><<<blocks, B, 0, s>>>(g, opts, x, c0, c1, c2, G, Vb, xb, cb0, cb1, cb2)
     if (g.nd == 1) MP_P(1, 0);
