@@ -43,6 +43,8 @@ def _parse():
                     help="Kahan-compensated donor-cell updates (the library-default summation)")
     ap.add_argument("--abs", action="store_true", help="|psi| in the psi-fractions")
     ap.add_argument("--dfl", action="store_true", help="divergent-flow pseudo-velocity term")
+    ap.add_argument("--xcd-order", type=int, default=1,
+                    help="batched tile order with --tile-rows: 1 grouped per XCD, 0 grid by grid")
     ap.add_argument("--tile-rows", type=int, default=None,
                     help="fused kernel rows per wavefront chunk (default: autotune)")
     return ap.parse_args()
@@ -208,7 +210,11 @@ def bench_batched(args, torch, mpdata, synth, oracle):
     c0 = bp.pack([c.c[0] for c in cases], "c0")
     c1 = bp.pack([c.c[1] for c in cases], "c1")
     N = bp.n_psi
-    tile_rows, xcd = bp.autotune(psi0, c0, c1)          # outside the timed region
+    if args.tile_rows is None:
+        tile_rows, xcd = bp.autotune(psi0, c0, c1)      # outside the timed region
+    else:
+        tile_rows, xcd = args.tile_rows, bool(args.xcd_order)
+        bp.set_tiling(tile_rows, xcd)
     psi = psi0.clone()
     bp.step(psi, c0, c1, n_steps=K, use_graph=True)       # capture + warm-up replay
     secs = _time_steps(lambda k: bp.step(psi, c0, c1, n_steps=k, use_graph=True), K, torch)
