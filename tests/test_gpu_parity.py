@@ -5,6 +5,8 @@ Bar: relative L2 <= 1e-12 for the FP64 path and <= 1e-5 for the FP32 path
 several tiles with ragged tails; full workload sizes are checked on whole
 fields where the oracle is fast enough and on sampled sub-blocks otherwise.
 """
+import types
+
 import numpy as np
 import pytest
 import torch
@@ -173,13 +175,14 @@ def test_parity_2d_workload_full(dtype):
     assert rel_l2(out, ref) <= TOL[dtype]
 
 
-def _subblock_check(case, out, dtype, n_steps, centres, half=6):
+def _subblock_check(case, out, dtype, n_steps, centres, half=6, step_radius=3):
     """Compare `out` with the oracle run on sub-blocks around `centres`; the
-    block margin exceeds the domain of dependence, so its own boundaries do
-    not reach the compared core (real boundaries are kept)."""
+    block margin exceeds the domain of dependence (step_radius cells per
+    step), so its own boundaries do not reach the compared core (real
+    boundaries are kept)."""
     shape = case.psi.shape
     nd = len(shape)
-    radius = 3 * n_steps + 2
+    radius = step_radius * n_steps + 2
     errs = []
     for ctr in centres:
         lo = [max(0, ctr[d] - half - radius) if case.bc else ctr[d] - half - radius for d in range(nd)]
@@ -216,6 +219,64 @@ def test_parity_3d_workload_sampled():
     centres = [(0, 0, 0), (s[0] - 1, s[1] - 1, s[2] - 1), (0, s[1] // 2, s[2] - 1),
                (s[0] // 2, s[1] // 2, s[2] // 2), (s[0] - 3, 5, s[2] // 3), (100, 0, 128)]
     assert _subblock_check(case, out, torch.float64, n_steps, centres) <= 1e-12
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_parity_2d_large_sampled(kernel):
+    """Maximum-size check: a 16384 x 16390 periodic FP64 grid (2.1 GB per
+    field, byte offsets far past 2^31, ragged last strip), n_iters=3 with the
+    limiter, 2 steps; oracle on sub-blocks at the corners, edges and
+    interior (dependence radius 5 cells per step)."""
+    shape = (16384, 16390)
+    gen = synth.rng(71)
+    c = list(synth.stream_advector_2d(shape, 0.5, gen, n_modes=4, kmax=3))
+    x0 = np.sin(2 * np.pi * 3 * (np.arange(shape[0]) + 0.5) / shape[0])
+    x1 = np.cos(2 * np.pi * 5 * (np.arange(shape[1]) + 0.5) / shape[1])
+    psi = 1.0 + 0.5 * np.outer(x0, x1)
+    psi[1000:3000, 5000:9000] += 1.0          # sharp edges for the limiter
+    case = types.SimpleNamespace(psi=psi, c=c, g=None, n_iters=3, opts=FCT, bc=0)
+    n_steps = 2
+    out = gpu_run(psi, c, None, torch.float64, 3, FCT, 0, n_steps, kernel=kernel)
+    s = shape
+    centres = [(0, 0), (s[0] - 1, s[1] - 1), (0, s[1] - 1), (s[0] - 1, 0), (1000, 5000),
+               (2999, 8999), (s[0] // 2, s[1] // 2), (12345, 16389)]
+    assert _subblock_check(case, out, torch.float64, n_steps, centres, step_radius=5) <= 1e-12
+
+
+@pytest.mark.parametrize("shape,bc", [((3,), 0), ((1,), 1), ((3, 3), 0), ((1, 1), 1), ((2, 7), 1),
+                                      ((3, 3, 3), 0), ((1, 2, 1), 1), ((6, 16, 64), 0)])
+def test_degenerate_cases(shape, bc):
+    """Degenerate inputs through every kernel family: the smallest grids each
+    boundary type allows, psi == 0 (every psi-fraction is 0/0), a zero
+    advector (identity), and a constant field in a non-divergent flow."""
+    nd = len(shape)
+    gen = synth.rng(81)
+    walls = [tuple(n + (1 if e == d else 0) for e, n in enumerate(shape)) for d in range(nd)]
+    for opts in (0, FCT, TOT | FCT, IGA | TOT, mpdata.OPT_KAHAN | FCT):
+        n_iters = 2 if opts & IGA else 3
+        # psi == 0 stays 0 exactly
+        c = [gen.uniform(-0.2 / nd, 0.2 / nd, size=w) for w in walls]
+        if bc == 0:
+            c = synth.periodic_fix(c)
+        z = np.zeros(shape)
+        for kernel in KERNELS:
+            out = gpu_run(z, c, None, torch.float64, n_iters, opts, bc, 3, kernel=kernel)
+            assert np.all(out == 0.0), (opts, kernel)
+        # zero advector: identity
+        psi = gen.uniform(0.1, 1.0, size=shape)
+        c0 = [np.zeros(w) for w in walls]
+        for kernel in KERNELS:
+            out = gpu_run(psi, c0, None, torch.float64, n_iters, opts, bc, 3, kernel=kernel)
+            assert np.array_equal(out, psi), (opts, kernel)
+        # constant field, non-divergent advector, against the oracle
+        if bc == 0 and min(shape) >= 3:
+            cn = synth.small_advector(shape, 0.4, gen)
+            k = np.full(shape, 0.75)
+            ref = oracle.step(k, cn, n_iters=n_iters, opts=opts, bc=0, n_steps=3)
+            for kernel in KERNELS:
+                out = gpu_run(k, cn, None, torch.float64, n_iters, opts, 0, 3, kernel=kernel)
+                assert rel_l2(out, ref) <= 1e-12, (opts, kernel)
+                assert np.max(np.abs(out - 0.75)) <= 1e-13, (opts, kernel)
 
 
 def test_resume_is_bitwise():
