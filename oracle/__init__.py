@@ -93,6 +93,41 @@ def step(psi, c, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1):
     return psi
 
 
+def step_rhs(psi, c, r_pre=None, a_pre=0.0, r_post=None, a_post=0.0, g=None, n_iters=2,
+             opts=0, bc=BC_PERIODIC):
+    """One step of the inhomogeneous transport equation (Sect. 4.1, eq.
+    gte_final_rhs): psi <- ADV(psi + a_pre r_pre) + a_post r_post, ADV one
+    MPDATA step.  The paper's schemes: euler_a (eq. euler_a) r_post = R^n,
+    a_post = dt; euler_b (eq. euler_b) r_pre = R^n, a_pre = dt; trapez (eq.
+    trapez) r_pre = R^n, a_pre = dt/2, r_post = R^{n+1}, a_post = dt/2."""
+    x = np.array(psi, dtype=np.float64, copy=True)
+    if r_pre is not None:
+        x = x + a_pre * _f64(r_pre)
+    x = step(x, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=1)
+    if r_post is not None:
+        x = x + a_post * _f64(r_post)
+    return x
+
+
+def osc_step(psi, phi, c, a, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1):
+    """Translating oscillator d(psi)/dt + div(u psi) = omega phi,
+    d(phi)/dt + div(u phi) = -omega psi under the trapezoidal rule (Sect. 4.3,
+    eqs. osc_disc, trapez_osc, final_osc) with a = dt omega / 2:
+    psi* = ADV(psi + a phi), phi* = ADV(phi - a psi), then
+    psi = (psi* + a phi*) / (1 + a^2), phi = (phi* - a psi*) / (1 + a^2).
+    The printed trapez_osc has phi^n where psi^n belongs in the second
+    argument (the explicit half of -omega psi); psi^n is used here."""
+    x = np.array(psi, dtype=np.float64, copy=True)
+    y = np.array(phi, dtype=np.float64, copy=True)
+    for _ in range(int(n_steps)):
+        xs = step(x + a * y, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=1)
+        ys = step(y - a * x, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=1)
+        den = 1.0 + a * a
+        x = (xs + a * ys) / den
+        y = (ys - a * xs) / den
+    return x, y
+
+
 def diag(psi, g=None):
     """(sum of G*psi, min, max, count of non-finite values)."""
     psi = _f64(psi)

@@ -289,6 +289,72 @@ def test_dfl_vanishes_for_nondivergent_advector(opts):
     assert np.array_equal(a, b)
 
 
+# ------------------------------------------------------------ source terms
+def test_rhs_schemes_without_advection_are_axpy():
+    """With a zero advector ADV is the identity, so euler_a and euler_b both
+    give psi + dt R and trapez psi + dt/2 (R^n + R^{n+1}) (Sect. 4.1)."""
+    gen = synth.rng(91)
+    shape = (30, 20)
+    psi = gen.uniform(0.0, 1.0, size=shape)
+    r0, r1 = gen.normal(size=shape), gen.normal(size=shape)
+    c = [np.zeros((31, 20)), np.zeros((30, 21))]
+    dt = 0.3
+    ea = oracle.step_rhs(psi, c, r_post=r0, a_post=dt, n_iters=3, opts=FCT)
+    eb = oracle.step_rhs(psi, c, r_pre=r0, a_pre=dt, n_iters=3, opts=FCT)
+    tz = oracle.step_rhs(psi, c, r_pre=r0, a_pre=dt / 2, r_post=r1, a_post=dt / 2, n_iters=3,
+                         opts=FCT)
+    assert np.allclose(ea, psi + dt * r0, rtol=0, atol=1e-15)
+    assert np.allclose(eb, psi + dt * r0, rtol=0, atol=1e-15)
+    assert np.allclose(tz, psi + dt / 2 * (r0 + r1), rtol=0, atol=1e-15)
+
+
+def test_rhs_constant_source_commutes_with_donor_cell():
+    """For a spatially constant source and a non-divergent advector the
+    donor-cell pass maps psi + k to ADV(psi) + k, so euler_a == euler_b."""
+    gen = synth.rng(92)
+    shape = (24, 20)
+    c = synth.small_advector(shape, 0.5, gen)
+    psi = gen.uniform(0.0, 1.0, size=shape)
+    R = np.full(shape, 0.37)
+    ea = oracle.step_rhs(psi, c, r_post=R, a_post=0.5, n_iters=1)
+    eb = oracle.step_rhs(psi, c, r_pre=R, a_pre=0.5, n_iters=1)
+    assert np.max(np.abs(ea - eb)) <= 1e-14
+
+
+def _rotation(psi0, phi0, ang):
+    return (psi0 * np.cos(ang) + phi0 * np.sin(ang), phi0 * np.cos(ang) - psi0 * np.sin(ang))
+
+
+def test_oscillator_at_rest_is_cayley_rotation():
+    """With no advection the trapezoidal oscillator step is the Cayley
+    transform of the rotation generator: after N steps (psi, phi) is rotated
+    by N * 2 atan(dt omega / 2) with the amplitude preserved exactly (eq.
+    final_osc).  Using phi^n in place of psi^n in the second argument of
+    eq. trapez_osc (as printed) breaks this."""
+    gen = synth.rng(93)
+    shape = (40,)
+    psi0, phi0 = gen.normal(size=shape), gen.normal(size=shape)
+    c = [np.zeros(41)]
+    a, N = 0.5 * 1.0 * (2 * np.pi / 400), 120
+    x, y = oracle.osc_step(psi0, phi0, c, a, n_iters=2, opts=IGA | FCT, n_steps=N)
+    ex, ey = _rotation(psi0, phi0, N * 2 * np.arctan(a))
+    assert np.max(np.abs(x - ex)) <= 1e-12 and np.max(np.abs(y - ey)) <= 1e-12
+    assert np.allclose(x ** 2 + y ** 2, psi0 ** 2 + phi0 ** 2, rtol=1e-12, atol=0)
+
+
+def test_oscillator_with_unit_courant_translates_and_rotates():
+    """At C = 1 every MPDATA step is an exact one-cell shift (Sect. 3), so the
+    oscillator's solution is the rotated initial state shifted by N cells."""
+    gen = synth.rng(94)
+    n = 64
+    psi0, phi0 = gen.normal(size=n), gen.normal(size=n)
+    c = [np.ones(n + 1)]
+    a, N = 0.05, 37
+    x, y = oracle.osc_step(psi0, phi0, c, a, n_iters=2, opts=IGA, n_steps=N)
+    ex, ey = _rotation(np.roll(psi0, N), np.roll(phi0, N), N * 2 * np.arctan(a))
+    assert np.max(np.abs(x - ex)) <= 1e-12 and np.max(np.abs(y - ey)) <= 1e-12
+
+
 # ---------------------------------------------------------------- P3 conservation
 @pytest.mark.parametrize("opts", ALL_OPTS + [KAHAN, FCT | KAHAN, ABS, ABS | TOT | FCT, DFL,
                                               DFL | TOT | FCT])
