@@ -9,7 +9,8 @@ events on the stream the kernels run on, bracketed by device syncs.  One JSON
 line is printed: Mcell-steps/s, the roofline of the dominant kernel, and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 
-Other workloads (--workload): 2d-f32, 3d, 1d, batched, adjoint.
+Other workloads (--workload): 2d-f32, 3d, 1d, batched, adjoint, osc (the
+translating oscillator with source terms), copy (counter calibration).
 """
 import argparse
 import json
@@ -36,7 +37,7 @@ def _parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="2d",
-                    choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint", "copy"])
+                    choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint", "osc", "copy"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--kahan", action="store_true",
@@ -312,6 +313,53 @@ def bench_adjoint(args, torch, mpdata, synth, oracle):
     return res
 
 
+def bench_osc(args, torch, mpdata, synth, oracle):
+    """Translating oscillator: 1-D periodic 1001 cells, C = 0.5,
+    omega = 2 pi / 400, dt = 1, trapezoidal coupling, iga + fct, 1400 steps;
+    each step advects both fields."""
+    case = synth.case_osc()
+    K = args.steps if args.steps is not None else case.n_steps
+    W = args.warmup
+    a = case.extra["a"]
+    dev = torch.device("cuda:0")
+    plan = mpdata.Plan(case.psi.shape, n_iters=case.n_iters, opts=case.opts, device=dev)
+    c = [torch.from_numpy(x).to(dev) for x in case.c]
+    psi0 = torch.from_numpy(case.psi).to(dev)
+    phi0 = torch.from_numpy(case.extra["phi"]).to(dev)
+    p, q = psi0.clone(), phi0.clone()
+    plan.osc_step(p, q, c, a, n_steps=W)
+    p, q = psi0.clone(), phi0.clone()
+    secs = _time_steps(lambda k: plan.osc_step(p, q, c, a, n_steps=k), K, torch)
+    N = 2 * case.psi.size                 # both fields advance every step
+    ms = secs * 1e3 / K
+    alg = 8 * 2 * (2 * case.psi.size + case.psi.size)   # psi, phi: read, write, + advector
+    out = {
+        "metric": "Mcell-steps/s", "value": round(N * K / secs / 1e6, 3), "unit": "Mcell-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "osc_1d_periodic_1001_iga_fct_iters2_trapez", "cells": N,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (ms / 1e3) / 1e9, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 6), "traffic": None,
+                     "alg_bytes_per_launch": alg, "kernel": "whole oscillator step (4 launches)"},
+    }
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        rx, ry = oracle.osc_step(case.psi, case.extra["phi"], case.c, a, n_iters=case.n_iters,
+                                 opts=case.opts, n_steps=K)
+        dt = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        got = np.concatenate([p.cpu().numpy(), q.cpu().numpy()])
+        ref = np.concatenate([rx, ry])
+        out["cpu_baseline"] = {"value": round(N * K / dt / 1e6, 4), "unit": "Mcell-steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"the whole {K}-step oscillator run, FP64, one thread"}
+        out["parity_rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return out
+
+
 def bench_copy(args, torch):
     """Calibration for the HBM byte counters: kernels of known traffic on a
     256 MiB buffer -- an elementwise in-place scale (reads and writes 256 MiB)
@@ -360,6 +408,8 @@ def main():
         out = bench_batched(args, torch, mpdata, synth, oracle)
     elif args.workload == "adjoint":
         out = bench_adjoint(args, torch, mpdata, synth, oracle)
+    elif args.workload == "osc":
+        out = bench_osc(args, torch, mpdata, synth, oracle)
     else:
         out = bench_single(args, torch, mpdata, synth, oracle)
     print(json.dumps(out), flush=True)

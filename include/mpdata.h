@@ -145,6 +145,28 @@ int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g,
 int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0,
                 const void *c1, const void *c2, int n_steps);
 
+/* One step of the inhomogeneous transport equation (Sect. 4.1):
+ * psi <- ADV(psi + a_pre * r_pre) + a_post * r_post, ADV one mpdata_step.
+ * r_pre / r_post are cell fields of the plan's dtype (either may be NULL:
+ * that term is skipped).  The paper's schemes: euler_a (r_post = R^n,
+ * a_post = dt), euler_b (r_pre = R^n, a_pre = dt), trapez (r_pre = R^n,
+ * a_pre = dt/2, r_post = R^{n+1}, a_post = dt/2; a forcing that depends on
+ * psi^{n+1} is applied by the caller after the call instead). */
+int mpdata_step_rhs(mpdata_plan *plan, void *psi, const void *g, const void *c0,
+                    const void *c1, const void *c2, const void *r_pre, double a_pre,
+                    const void *r_post, double a_post);
+
+/* n_steps steps of the translating oscillator (Sect. 4.3):
+ * d psi/dt + div(u psi) = omega phi, d phi/dt + div(u phi) = -omega psi with
+ * the trapezoidal rule, a = dt * omega / 2 (eqs. osc_disc, trapez_osc,
+ * final_osc): psi* = ADV(psi + a phi), phi* = ADV(phi - a psi), then
+ * psi = (psi* + a phi*) / (1 + a^2), phi = (phi* - a psi*) / (1 + a^2).
+ * psi and phi are distinct cell buffers, updated in place.  (The printed
+ * trapez_osc has phi^n in the second argument where psi^n belongs.) */
+int mpdata_osc_step(mpdata_plan *plan, void *psi, void *phi, const void *g,
+                    const void *c0, const void *c1, const void *c2, double a,
+                    int n_steps);
+
 /* Diagnostics of psi (waits for the result): out[0] = sum of G*psi over the
  * finite cells (FP64, compensated), out[1] = min, out[2] = max of the finite
  * values, *n_nonfinite = number of NaN/Inf cells.  Returns MPDATA_ENONFINITE

@@ -437,6 +437,77 @@ int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0, con
                             (const float *)c1, (const float *)c2, n_steps);
 }
 
+int mpdata_step_rhs(mpdata_plan *plan, void *psi, const void *g, const void *c0,
+                    const void *c1, const void *c2, const void *r_pre, double a_pre,
+                    const void *r_post, double a_post)
+{
+    if (!plan || !psi) return fail(MPDATA_EINVAL, "NULL argument");
+    if (plan->batched) return fail(MPDATA_EINVAL, "source terms need a single-grid plan");
+    const int64_t N = cells_of(plan->g);
+    const bool f64 = plan->desc.dtype == MPDATA_F64;
+    hipError_t e = hipSuccess;
+    if (r_pre)
+        e = f64 ? mp::axpy_launch<double>((double *)psi, (const double *)r_pre, a_pre, N,
+                                          plan->stream)
+                : mp::axpy_launch<float>((float *)psi, (const float *)r_pre, a_pre, N,
+                                         plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "source term launch");
+    int rc = mpdata_step(plan, psi, g, c0, c1, c2, 1);
+    if (rc) return rc;
+    if (r_post)
+        e = f64 ? mp::axpy_launch<double>((double *)psi, (const double *)r_post, a_post, N,
+                                          plan->stream)
+                : mp::axpy_launch<float>((float *)psi, (const float *)r_post, a_post, N,
+                                         plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "source term launch");
+    return MPDATA_OK;
+}
+
+int mpdata_osc_step(mpdata_plan *plan, void *psi, void *phi, const void *g, const void *c0,
+                    const void *c1, const void *c2, double a, int n_steps)
+{
+    if (!plan || !psi || !phi) return fail(MPDATA_EINVAL, "NULL argument");
+    if (psi == phi) return fail(MPDATA_EINVAL, "psi and phi must be distinct buffers");
+    if (plan->batched) return fail(MPDATA_EINVAL, "the oscillator needs a single-grid plan");
+    if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
+    const int64_t N = cells_of(plan->g);
+    const bool f64 = plan->desc.dtype == MPDATA_F64;
+    if (n_steps == 0) return MPDATA_OK;
+    if (plan->kernel != MPDATA_KERNEL_STAGED &&
+        mp::resident1d_supported(plan->desc.n_dims, plan->g.n[0], f64, plan->desc.has_g, 1)) {
+        // 1-D pair resident in LDS: every step of the call in one launch
+        bool tm = timer_begin(plan, "k_resident1d");
+        hipError_t e =
+            f64 ? mp::resident1d_osc<double>(plan->g.n[0], plan->g.bc[0], plan->desc.n_iters,
+                                             plan->desc.opts, (double *)psi, (double *)phi,
+                                             (const double *)c0, (const double *)g, a, n_steps,
+                                             plan->stream)
+                : mp::resident1d_osc<float>(plan->g.n[0], plan->g.bc[0], plan->desc.n_iters,
+                                            plan->desc.opts, (float *)psi, (float *)phi,
+                                            (const float *)c0, (const float *)g, a, n_steps,
+                                            plan->stream);
+        if (tm) timer_end(plan);
+        return e == hipSuccess ? MPDATA_OK : hip_fail(e, "resident oscillator launch");
+    }
+    for (int st = 0; st < n_steps; st++) {
+        hipError_t e = f64 ? mp::osc_couple_launch<double>((double *)psi, (double *)phi, a, 0,
+                                                           N, plan->stream)
+                           : mp::osc_couple_launch<float>((float *)psi, (float *)phi, a, 0, N,
+                                                          plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "oscillator coupling launch");
+        int rc = mpdata_step(plan, psi, g, c0, c1, c2, 1);
+        if (rc) return rc;
+        rc = mpdata_step(plan, phi, g, c0, c1, c2, 1);
+        if (rc) return rc;
+        e = f64 ? mp::osc_couple_launch<double>((double *)psi, (double *)phi, a, 1, N,
+                                                plan->stream)
+                : mp::osc_couple_launch<float>((float *)psi, (float *)phi, a, 1, N,
+                                               plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "oscillator coupling launch");
+    }
+    return MPDATA_OK;
+}
+
 int mpdata_diag(mpdata_plan *plan, const void *psi, const void *g, double out[3],
                 int64_t *n_nonfinite)
 {

@@ -72,10 +72,15 @@ hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_
                         int tile_planes, hipStream_t s);
 
 // ---- 1-D grid resident in LDS: all steps of a call in one launch --------
-bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g);
+// two_fields: room for the oscillator pair (resident1d_osc)
+bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g, int two_fields = 0);
 template <typename T>
 hipError_t resident1d_steps(int64_t n, int bc, int n_iters, unsigned opts, T *psi, const T *c,
                             const T *G, int n_steps, hipStream_t s);
+// n_steps trapezoidal steps of the translating oscillator pair (psi, phi)
+template <typename T>
+hipError_t resident1d_osc(int64_t n, int bc, int n_iters, unsigned opts, T *psi, T *phi,
+                          const T *c, const T *G, double a, int n_steps, hipStream_t s);
 
 // ---- batched fused 2-D: one launch over all tiles of all grids ---------
 struct BatchGrid {
@@ -95,5 +100,10 @@ hipError_t fused2d_batched_step(const BatchGrid *grids_dev, int n_grids, int n_t
 
 int fused2d_tile_rows();                             // default rows per batched tile
 int fused2d_strip_cols(int n_iters, unsigned opts);  // output columns per strip
+
+// ---- source terms and the oscillator coupling (rhs.hip) ----------------
+template <typename T> hipError_t axpy_launch(T *y, const T *x, double a, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t osc_couple_launch(T *psi, T *phi, double a, int implicit, int64_t n, hipStream_t s);
 
 }  // namespace mp

@@ -12,7 +12,7 @@ namespace mp {
 namespace {
 
 constexpr int RB = 512;            // threads
-constexpr size_t LDS_BYTES = 64 * 1024;
+constexpr size_t LDS_BYTES = 160 * 1024;   // upper bound; the device's limit applies
 
 __device__ inline int mc(int q, int n, int bc)
 {
@@ -38,14 +38,19 @@ template <typename T> __device__ inline T rfrac(bool iga, T num, T den, T m)
     return den == T(0) ? T(0) : num / den;
 }
 
+// With phi != nullptr the kernel advances the translating oscillator pair
+// (psi, phi) with the trapezoidal coupling of strength osc_a (= dt omega / 2):
+// explicit half, one MPDATA step of each field, implicit half in closed form.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, unsigned opts,
                                                    T *psi, const T *__restrict__ cin,
-                                                   const T *__restrict__ Gin, int n_steps)
+                                                   const T *__restrict__ Gin, int n_steps,
+                                                   T *phi, T osc_a)
 {
     extern __shared__ char lds_raw[];
     T *P = (T *)lds_raw;          // psi at the start of the step
-    T *X = P + n;                 // pass input
+    T *Q = P + n;                 // phi (oscillator only)
+    T *X = Q + (phi ? n : 0);     // pass input
     T *Y = X + n;                 // pass output
     T *BU = Y + n;
     T *BD = BU + n;
@@ -70,6 +75,7 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
 
     for (int i = tid; i < n; i += RB) {
         P[i] = psi[i];
+        if (phi) Q[i] = phi[i];
         if (Gin) GG[i] = Gin[i];
     }
     for (int f = tid; f <= n; f += RB) C[f] = cin[f];
@@ -77,14 +83,15 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
 
     auto gv = [&](int i) -> T { return Gin ? GG[mc(i, n, bc)] : T(1); };
 
-    for (int step = 0; step < n_steps; step++) {
-        // donor-cell pass: P -> Y
+    // one MPDATA step of the field F in place (F -> Y -> F)
+    auto advect = [&](T *F) {
+        // donor-cell pass: F -> Y
         for (int i = tid; i < n; i += RB) {
             T ul = C[mw(i, n, bc)], uh = C[mw(i + 1, n, bc)];
-            T flo = pos(ul) * P[mc(i - 1, n, bc)] + neg(ul) * P[i];
-            T fhi = pos(uh) * P[i] + neg(uh) * P[mc(i + 1, n, bc)];
+            T flo = pos(ul) * F[mc(i - 1, n, bc)] + neg(ul) * F[i];
+            T fhi = pos(uh) * F[i] + neg(uh) * F[mc(i + 1, n, bc)];
             T acc = fhi - flo;
-            Y[i] = upd(P[i], acc, i);
+            Y[i] = upd(F[i], acc, i);
         }
         __syncthreads();
         const T *cprev = C;
@@ -137,11 +144,11 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
             if (fct) {
                 for (int i = tid; i < n; i += RB) {
                     T xi = X[i];
-                    T mx = fmax(P[i], xi), mn = fmin(P[i], xi);
+                    T mx = fmax(F[i], xi), mn = fmin(F[i], xi);
                     for (int s = -1; s <= 1; s += 2) {
                         int q = mc(i + s, n, bc);
-                        mx = fmax(fmax(mx, P[q]), X[q]);
-                        mn = fmin(fmin(mn, P[q]), X[q]);
+                        mx = fmax(fmax(mx, F[q]), X[q]);
+                        mn = fmin(fmin(mn, F[q]), X[q]);
                     }
                     T vlo = V[mw(i, n, bc)], vhi = V[mw(i + 1, n, bc)];
                     T wm = iga ? T(1) : X[mc(i - 1, n, bc)];
@@ -181,35 +188,101 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
             cprev = adv;
             __syncthreads();
         }
-        for (int i = tid; i < n; i += RB) P[i] = Y[i];
+        for (int i = tid; i < n; i += RB) F[i] = Y[i];
         __syncthreads();
+    };
+
+    for (int step = 0; step < n_steps; step++) {
+        if (phi) {
+            // explicit half of the coupling: (psi, phi) += a (phi, -psi)
+            for (int i = tid; i < n; i += RB) {
+                T x = P[i], y = Q[i];
+                P[i] = x + osc_a * y;
+                Q[i] = y - osc_a * x;
+            }
+            __syncthreads();
+            advect(P);
+            advect(Q);
+            // implicit half in closed form
+            const T den = T(1) + osc_a * osc_a;
+            for (int i = tid; i < n; i += RB) {
+                T x = P[i], y = Q[i];
+                P[i] = (x + osc_a * y) / den;
+                Q[i] = (y - osc_a * x) / den;
+            }
+            __syncthreads();
+        } else {
+            advect(P);
+        }
     }
-    for (int i = tid; i < n; i += RB) psi[i] = P[i];
+    for (int i = tid; i < n; i += RB) {
+        psi[i] = P[i];
+        if (phi) phi[i] = Q[i];
+    }
 }
 
-size_t lds_need(int n, size_t es, bool has_g) { return es * ((5 + (has_g ? 1 : 0)) * (size_t)n + 4 * ((size_t)n + 1)); }
+size_t lds_need(int n, size_t es, bool has_g, bool two)
+{
+    return es * ((5 + (has_g ? 1 : 0) + (two ? 1 : 0)) * (size_t)n + 4 * ((size_t)n + 1));
+}
+
+// LDS a workgroup may use on the current device (160 KB on gfx950)
+size_t lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 64 * 1024;
+    }
+    return (size_t)v < LDS_BYTES ? (size_t)v : LDS_BYTES;
+}
+
+template <typename T>
+hipError_t launch_resident(int64_t n, int bc, int n_iters, unsigned opts, T *psi, const T *c,
+                           const T *G, int n_steps, T *phi, double a, hipStream_t s)
+{
+    size_t lds = lds_need((int)n, sizeof(T), G != nullptr, phi != nullptr);
+    if (lds > lds_limit()) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_resident1d<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_resident1d<T><<<1, RB, lds, s>>>((int)n, bc, n_iters, opts, psi, c, G, n_steps, phi, (T)a);
+    return hipGetLastError();
+}
 
 }  // namespace
 
-bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g)
+bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g, int two_fields)
 {
     if (nd != 1 || n < 1 || n > (1 << 20)) return false;
-    return lds_need((int)n, dtype_is_f64 ? 8 : 4, has_g != 0) <= LDS_BYTES;
+    return lds_need((int)n, dtype_is_f64 ? 8 : 4, has_g != 0, two_fields != 0) <= lds_limit();
 }
 
 template <typename T>
 hipError_t resident1d_steps(int64_t n, int bc, int n_iters, unsigned opts, T *psi, const T *c,
                             const T *G, int n_steps, hipStream_t s)
 {
-    size_t lds = lds_need((int)n, sizeof(T), G != nullptr);
-    if (lds > LDS_BYTES) return hipErrorInvalidValue;
-    k_resident1d<T><<<1, RB, lds, s>>>((int)n, bc, n_iters, opts, psi, c, G, n_steps);
-    return hipGetLastError();
+    return launch_resident<T>(n, bc, n_iters, opts, psi, c, G, n_steps, nullptr, 0.0, s);
+}
+
+template <typename T>
+hipError_t resident1d_osc(int64_t n, int bc, int n_iters, unsigned opts, T *psi, T *phi,
+                          const T *c, const T *G, double a, int n_steps, hipStream_t s)
+{
+    return launch_resident<T>(n, bc, n_iters, opts, psi, c, G, n_steps, phi, a, s);
 }
 
 template hipError_t resident1d_steps<float>(int64_t, int, int, unsigned, float *, const float *,
                                             const float *, int, hipStream_t);
 template hipError_t resident1d_steps<double>(int64_t, int, int, unsigned, double *,
                                              const double *, const double *, int, hipStream_t);
+template hipError_t resident1d_osc<float>(int64_t, int, int, unsigned, float *, float *,
+                                          const float *, const float *, double, int, hipStream_t);
+template hipError_t resident1d_osc<double>(int64_t, int, int, unsigned, double *, double *,
+                                           const double *, const double *, double, int,
+                                           hipStream_t);
 
 }  // namespace mp

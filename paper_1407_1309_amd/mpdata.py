@@ -30,7 +30,8 @@ EXPORTS = [
     "mpdata_step", "mpdata_diag", "mpdata_courant_max", "mpdata_adv_adj",
     "mpdata_adj_workspace_bytes", "mpdata_batched_workspace_bytes", "mpdata_batched_init",
     "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_set_batched_tiling",
-    "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read",
+    "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read", "mpdata_step_rhs",
+    "mpdata_osc_step",
     "mpdata_destroy", "mpdata_last_error",
 ]
 
@@ -87,6 +88,10 @@ def lib():
         L.mpdata_set_batched_tiling.argtypes = [_VP, ctypes.c_int, ctypes.c_int]
         L.mpdata_autotune_batched.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_int)]
+        L.mpdata_step_rhs.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP,
+                                      ctypes.c_double]
+        L.mpdata_osc_step.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double,
+                                      ctypes.c_int]
         L.mpdata_timing.argtypes = [_VP, ctypes.c_int]
         L.mpdata_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int),
@@ -241,6 +246,31 @@ class Plan:
         _check(lib().mpdata_step(self._handle, _ptr(psi), _ptr(g), cp[0], cp[1], cp[2],
                                  int(n_steps)))
         return psi
+
+    def step_rhs(self, psi, c, r_pre=None, a_pre=0.0, r_post=None, a_post=0.0, g=None):
+        """One step of the inhomogeneous transport equation in place:
+        psi <- ADV(psi + a_pre r_pre) + a_post r_post."""
+        self._check_cell(psi, "psi")
+        self._check_cell(g, "g")
+        self._check_cell(r_pre, "r_pre")
+        self._check_cell(r_post, "r_post")
+        cp = self._check_walls(c)
+        self._bind_stream()
+        _check(lib().mpdata_step_rhs(self._handle, _ptr(psi), _ptr(g), cp[0], cp[1], cp[2],
+                                     _ptr(r_pre), float(a_pre), _ptr(r_post), float(a_post)))
+        return psi
+
+    def osc_step(self, psi, phi, c, a, n_steps=1, g=None):
+        """n_steps trapezoidal steps of the translating oscillator (in place),
+        a = dt * omega / 2."""
+        self._check_cell(psi, "psi")
+        self._check_cell(phi, "phi")
+        self._check_cell(g, "g")
+        cp = self._check_walls(c)
+        self._bind_stream()
+        _check(lib().mpdata_osc_step(self._handle, _ptr(psi), _ptr(phi), _ptr(g), cp[0], cp[1],
+                                     cp[2], float(a), int(n_steps)))
+        return psi, phi
 
     def diag(self, psi, g=None):
         """(sum G psi, min, max, n_nonfinite); waits for the result."""

@@ -217,6 +217,19 @@ def case_1d(nx=500, n_steps=1000) -> Case:
     return Case("1d_periodic", psi, [c0], None, 2, 0, 0, n_steps)
 
 
+def case_osc(nx=1001, n_steps=1400, courant=0.5, omega=2 * np.pi / 400, dt=1.0) -> Case:
+    """Translating oscillator (the paper's inhomogeneous example): 1-D
+    periodic, psi = 0.5 (1 + cos(2 pi x / 100)) for 50 < x < 150 and 0
+    elsewhere (x = cell index), phi = 0, constant Courant number 0.5,
+    omega = 2 pi / 400, dt = 1; iga with the limiter, n_iters = 2 (the
+    library's default options for a variable-sign pair)."""
+    x = np.arange(nx, dtype=np.float64)
+    psi = np.where((x > 50) & (x < 150), 0.5 * (1.0 + np.cos(2 * np.pi * x / 100.0)), 0.0)
+    c0 = np.full(nx + 1, float(courant))
+    return Case("osc_1d_periodic", psi, [c0], None, 2, OPT_FCT | OPT_IGA, 0, n_steps,
+                extra={"phi": np.zeros(nx), "a": 0.5 * dt * omega})
+
+
 def case_2d(n=2048, seed=2, courant=0.5, sigma=(32.0, 128.0), n_blobs=64,
             n_iters=3, opts=OPT_FCT, n_steps=200, shape=None) -> Case:
     """2-D periodic: stream-function advector (8 modes, wavenumbers -4..4),
