@@ -157,9 +157,8 @@ template <typename T> __global__ void k_copy(T *a, const T *b, int64_t n)
 // boundary map, exactly as the forward pass reads them); the advector
 // adjoint of a wall collects the same from the cells that read the wall.
 template <typename T, int ND>
-__global__ void k_donor_adj_cells(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
-                                  const T *c2, const T *G, int flux_is_vel,
-                                  const T *__restrict__ yb, T *xb)
+__global__ void k_donor_adj_cells(Geom g, const T *c0, const T *c1, const T *c2, const T *G,
+                                  int flux_is_vel, const T *__restrict__ yb, T *xb)
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
     int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
@@ -582,7 +581,7 @@ void donor_adj(const Geom &g, const T *x, const T *const c[3], const T *G, int f
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
     with_nd(g.nd, [&](auto ND) {
         k_donor_adj_cells<T, decltype(ND)::value><<<(unsigned)cdiv(N, B), B, 0, s>>>(
-            g, x, c[0], c[1], c[2], G, flux_is_vel, yb, xb);
+            g, c[0], c[1], c[2], G, flux_is_vel, yb, xb);
     });
     for (int d = 0; d < g.nd; d++) {
         int64_t e[3] = {g.n[0], g.n[1], g.n[2]};

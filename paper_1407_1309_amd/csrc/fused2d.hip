@@ -27,26 +27,10 @@ constexpr int WAVE = 64;
 // ---- wave-wide lane shifts --------------------------------------------
 // from_left(v): lane l receives lane l-1's v (the value at column j-1);
 // from_right(v): lane l receives lane l+1's v (column j+1).  Lanes with no
-// source receive 0 (they are halo lanes).  Default: DPP wave shifts
-// (wave_shr:1 / wave_shl:1, VALU only); MP_SHIFT_BPERMUTE selects the
-// ds_bpermute crossbar instead.
-#ifndef MP_SHIFT_BPERMUTE
+// source receive 0 (they are halo lanes).  DPP wave shifts (wave_shr:1 /
+// wave_shl:1): VALU only, no LDS traffic.
 __device__ inline int lane_from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 __device__ inline int lane_from_right(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
-#else
-__device__ inline int lane_from_left(int v)
-{
-    int l = (int)(threadIdx.x & (WAVE - 1));
-    int r = __builtin_amdgcn_ds_bpermute(((l + WAVE - 1) & (WAVE - 1)) << 2, v);
-    return l == 0 ? 0 : r;
-}
-__device__ inline int lane_from_right(int v)
-{
-    int l = (int)(threadIdx.x & (WAVE - 1));
-    int r = __builtin_amdgcn_ds_bpermute(((l + 1) & (WAVE - 1)) << 2, v);
-    return l == WAVE - 1 ? 0 : r;
-}
-#endif
 __device__ inline float from_left(float v) { return __int_as_float(lane_from_left(__float_as_int(v))); }
 __device__ inline float from_right(float v) { return __int_as_float(lane_from_right(__float_as_int(v))); }
 __device__ inline double from_left(double v)
