@@ -288,7 +288,10 @@ def bench_adjoint(args, torch, mpdata, synth, oracle):
     secs = _time_steps(run, K, torch)
     N = psi.numel()
     ms = secs * 1e3 / K
-    alg = 8 * 16 * N      # bytes per cell-step of the gradient
+    # bytes per cell-step of the gradient: 16 FP64 values per cell (state, pass
+    # field, advector, raw and limited pseudo-velocities, limiter coefficients,
+    # adjoint in and out, advector adjoint read and written)
+    alg = 8 * 16 * N
     achieved = alg / (ms / 1e3) / 1e9
     res = {
         "metric": "Mcell-steps/s", "value": round(N * K / secs / 1e6, 3), "unit": "Mcell-steps/s",

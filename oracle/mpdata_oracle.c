@@ -423,7 +423,7 @@ static void fct_limit(const grid_t *g, const double *psi_n, const double *x,
 }
 
 /* ------------------------------------------------------------------------ */
-/* one step and the driver                                                   */
+/* one step and the step loop                                                */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
