@@ -5,7 +5,9 @@ may import this package.  The product path (the HIP library and its Python
 binding) never imports it.
 
 Thin ctypes wrapper over liboracle.so (built from mpdata_oracle*.c by
-oracle/build.py).  Arrays are numpy float64, C-contiguous, last dimension
+oracle/build.py); the source-term schemes and the translating oscillator
+(step_rhs, osc_step) are plain compositions of its step with numpy
+arithmetic.  Arrays are numpy float64, C-contiguous, last dimension
 fastest.  The advector component c[d] has n[d]+1 entries along dimension d.
 """
 import ctypes

@@ -21,7 +21,11 @@
  *   - psi-fractions n/d are 0 when d == 0, with no epsilon; under the infinite
  *     gauge they become n/m with m the number of values summed in d;
  *   - multi-dimensional cross terms, third-order terms and the limiter follow
- *     the forms written next to each function below.
+ *     the forms written next to each function below;
+ *   - options beyond the basic scheme: Kahan-compensated donor-cell updates
+ *     (Sect. 3.1.1), the divergent-flow term (Sect. 3.1.3, its form derived
+ *     from the donor-cell truncation error, see pseudo_velocity) and |psi| in
+ *     the psi-fractions (abs, Sect. 3.1.5).
  */
 #include "mpdata_oracle.h"
 
