@@ -282,7 +282,11 @@ static double pseudo_velocity(const grid_t *g, int d, const double *x,
             dv += (wat(g, o, c[o], Lh) - wat(g, o, c[o], L)) +
                   (wat(g, o, c[o], Rh) - wat(g, o, c[o], R));
         }
-        V -= 0.25 * u / Gb * dv;
+        /* under iga the pseudo-velocity is the flux of a unit field (the
+         * psi-fractions become halved differences), so this psi-free term
+         * takes the wall mean of psi to stay the same flux */
+        double w = g->iga ? 0.5 * (xL + xR) : 1.0;
+        V -= 0.25 * u / Gb * dv * w;
     }
 
     if (g->tot) {

@@ -135,6 +135,8 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
                     // (c(f+1) - c(f)) + (c(f) - c(f-1)) of the two cells
                     T dv = (cprev[mw(f + 1, n, bc)] - cprev[mw(f, n, bc)]) +
                            (cprev[mw(f, n, bc)] - cprev[mw(f - 1, n, bc)]);
+                    // under iga: times the wall mean of psi (unit-field flux)
+                    if (iga) dv *= T(0.5) * (xL + xR);
                     v -= T(0.25) * u / Gb * dv;
                 }
                 V[f] = v;

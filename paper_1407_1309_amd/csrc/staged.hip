@@ -147,6 +147,9 @@ __global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T
         for (int o = 0; o < ND; o++)
             dv += (wall(g, o, c[o], shifted(L, o, 1)) - wall(g, o, c[o], L)) +
                   (wall(g, o, c[o], shifted(R, o, 1)) - wall(g, o, c[o], R));
+        // under iga the pseudo-velocity is a unit-field flux, so this
+        // psi-free term carries the wall mean of psi
+        if (iga) dv *= T(0.5) * (xL + xR);
         V_ -= T(0.25) * u * ig * dv;
     }
     if (tot) {

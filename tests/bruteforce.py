@@ -109,6 +109,8 @@ def mpdata_exact(psi, c, g, shape, bc, n_iters, fct, iga, tot, n_steps, absf=Fal
                     for o in range(G.nd):
                         for S in (L, R):
                             dv += W(cp, o, _add(S, o, 1)) - W(cp, o, S)
+                    if iga:            # unit-field flux: times the wall mean of psi
+                        dv = dv * (xl + xr) / 2
                     v -= u / (2 * gb) * dv / 2
                 if tot:
                     x2, x_1 = X(x, _add(R, d, 1)), X(x, _add(L, d, -1))

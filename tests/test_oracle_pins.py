@@ -256,14 +256,16 @@ def _divergent_1d(N, opts, with_g=False, T=0.5, cour=0.4):
 
 
 @pytest.mark.parametrize("with_g", [False, True])
-def test_dfl_restores_second_order_in_divergent_flow(with_g):
+@pytest.mark.parametrize("base", [0, IGA])
+def test_dfl_restores_second_order_in_divergent_flow(with_g, base):
     """In a divergent flow the donor-cell truncation error has a term in the
     velocity divergence that the basic pseudo-velocity does not remove, so
     MPDATA drops towards first order; the divergent-flow term (Sect. 3.1.3)
     restores second order, also with variable G (products of two advector
-    factors divided by the wall mean of G).  Self-convergence against a
-    4096-cell run."""
-    for opts, lo, hi in [(DFL, 1.85, 2.2), (0, 0.9, 1.55)]:
+    factors divided by the wall mean of G) and under iga (where the term is
+    a unit-field flux and so carries the wall mean of psi).  Self-convergence
+    against a 4096-cell run."""
+    for opts, lo, hi in [(base | DFL, 1.85, 2.2), (base, 0.9, 1.6)]:
         ref = _divergent_1d(4096, opts, with_g)
         errs = []
         for N in (128, 256, 512):
@@ -489,10 +491,11 @@ def test_power_of_two_homogeneity_bitwise(opts, shape):
 
 
 # ---------------------------------------------------------------- P9 linear infinite gauge
-@pytest.mark.parametrize("opts", [IGA, IGA | TOT])
+@pytest.mark.parametrize("opts", [IGA, IGA | TOT, IGA | DFL, IGA | TOT | DFL])
 @pytest.mark.parametrize("shape", [(64,), (20, 18), (9, 8, 7)])
 def test_iga_is_linear(opts, shape):
-    """Without the limiter the infinite-gauge scheme is linear (Sect. 3.1.5)."""
+    """Without the limiter the infinite-gauge scheme is linear (Sect. 3.1.5),
+    also with the divergent-flow term (random, divergent advectors)."""
     gen = synth.rng(81)
     c = synth.periodic_fix(synth.random_advector(shape, 0.6, gen))
     p, q = gen.normal(size=shape), gen.normal(size=shape)
