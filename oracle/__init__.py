@@ -5,8 +5,9 @@ may import this package.  The product path (the HIP library and its Python
 binding) never imports it.
 
 Thin ctypes wrapper over liboracle.so (built from mpdata_oracle*.c by
-oracle/build.py); the source-term schemes and the translating oscillator
-(step_rhs, osc_step) are plain compositions of its step with numpy
+oracle/build.py); the source-term schemes, the translating oscillator, the
+prognosed-velocity advector and the shallow-water step (step_rhs, osc_step,
+vip_advector, sw_step) are plain compositions of its step with numpy
 arithmetic.  Arrays are numpy float64, C-contiguous, last dimension
 fastest.  The advector component c[d] has n[d]+1 entries along dimension d.
 """
@@ -128,6 +129,91 @@ def osc_step(psi, phi, c, a, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=
         x = (xs + a * ys) / den
         y = (ys - a * xs) / den
     return x, y
+
+
+def _cell_shift(a, d, s, bc):
+    """a at cell i + s along d through the boundary map (open: clamp)."""
+    n = a.shape[d]
+    idx = np.arange(n) + s
+    idx = np.clip(idx, 0, n - 1) if bc == BC_OPEN else idx % n
+    return np.take(a, idx, axis=d)
+
+
+def _spacing(dx, nd):
+    return [float(dx)] * nd if np.isscalar(dx) else [float(v) for v in dx]
+
+
+def vip_advector(num, den, num_prev, den_prev, dt, dx, eps, bc=BC_OPEN):
+    """Advector at n+1/2 from prognosed velocity (Sect. 5.1-5.2).
+
+    Velocity component d at a cell is num[d] / den (den None: num[d] is the
+    velocity itself), set to 0 where den <= eps; it is extrapolated linearly
+    in time, u^{n+1/2} = 1.5 u^n - 0.5 u^{n-1}, interpolated linearly to the
+    walls (mean of the wall's two cells through the boundary map: open
+    clamps, so an edge wall takes its cell's value) and multiplied by
+    dt / dx_d.  Returns the advector components (n_d + 1 walls along d)."""
+    nd = len(num)
+    sp = _spacing(dx, nd)
+
+    def vel(nm, dn):
+        nm = _f64(nm)
+        if dn is None:
+            return nm
+        dn = _f64(dn)
+        ok = dn > eps
+        return np.where(ok, nm / np.where(ok, dn, 1.0), 0.0)
+    out = []
+    for d in range(nd):
+        ue = 1.5 * vel(num[d], den) - 0.5 * vel(num_prev[d], den_prev)
+        n = ue.shape[d]
+        f = np.arange(n + 1)
+        left = np.clip(f - 1, 0, n - 1) if bc == BC_OPEN else (f - 1) % n
+        right = np.clip(f, 0, n - 1) if bc == BC_OPEN else f % n
+        out.append(dt / sp[d] * (0.5 * (np.take(ue, left, axis=d) +
+                                         np.take(ue, right, axis=d))))
+    return out
+
+
+def sw_forcing(h, d, dx_d, grav=1.0, bc=BC_OPEN):
+    """Pressure-gradient forcing of momentum component d in the shallow-water
+    equations (eqs. shw1d, shw2d): -g h dh/dx_d, the derivative as a centred
+    difference through the boundary map."""
+    return -grav * h * (_cell_shift(h, d, 1, bc) - _cell_shift(h, d, -1, bc)) / (2.0 * dx_d)
+
+
+def sw_step(h, q, h_prev, q_prev, dt, dx, eps=1e-8, grav=1.0, n_iters=2,
+            opts=OPT_IGA | OPT_FCT | OPT_DFL, bc=BC_OPEN):
+    """One step of the shallow-water system (Sect. 5.3-5.4): depth h and
+    momenta q_d = u_d h, advector from vip_advector (den = h), then with the
+    trapezoidal source-term scheme (Sect. 4.1)
+        h^{n+1}   = ADV(h^n)                       (no source term)
+        q_d^{n+1} = ADV(q_d^n + dt/2 R_d(h^n)) + dt/2 R_d(h^{n+1})
+    where R_d = sw_forcing: the equation for h has no source, so the forcing
+    at n+1 is known once h is advected.  Returns (h^{n+1}, [q_d^{n+1}]); the
+    caller keeps (h^n, q^n) as the next step's previous level (before the
+    first step the previous level equals the current one)."""
+    nd = h.ndim
+    sp = _spacing(dx, nd)
+    C = vip_advector(q, h, q_prev, h_prev, dt, sp, eps, bc)
+    hn = step(h, C, n_iters=n_iters, opts=opts, bc=bc, n_steps=1)
+    qn = []
+    for d in range(nd):
+        x = q[d] + 0.5 * dt * sw_forcing(h, d, sp[d], grav, bc)
+        x = step(x, C, n_iters=n_iters, opts=opts, bc=bc, n_steps=1)
+        qn.append(x + 0.5 * dt * sw_forcing(hn, d, sp[d], grav, bc))
+    return hn, qn
+
+
+def sw_run(h, q, n_steps, dt, dx, **kw):
+    """n_steps of sw_step from a state at rest in time (previous level =
+    current level).  Returns (h, [q_d])."""
+    h = _f64(h)
+    q = [_f64(x) for x in q]
+    hp, qp = h, q
+    for _ in range(n_steps):
+        hn, qn = sw_step(h, q, hp, qp, dt, dx, **kw)
+        hp, qp, h, q = h, q, hn, qn
+    return h, q
 
 
 def diag(psi, g=None):
