@@ -10,7 +10,8 @@ line is printed: Mcell-steps/s, the roofline of the dominant kernel, and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 
 Other workloads (--workload): 2d-f32, 3d, 1d, batched, adjoint, osc (the
-translating oscillator with source terms), copy (counter calibration).
+translating oscillator with source terms), sw (the 2-D shallow-water drop with
+prognosed velocity), copy (counter calibration).
 """
 import argparse
 import json
@@ -37,7 +38,8 @@ def _parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="2d",
-                    choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint", "osc", "copy"])
+                    choices=["2d", "2d-f32", "3d", "1d", "batched", "adjoint", "osc", "sw",
+                             "copy"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--kahan", action="store_true",
@@ -363,6 +365,64 @@ def bench_osc(args, torch, mpdata, synth, oracle):
     return out
 
 
+def bench_sw(args, torch, mpdata, synth, oracle):
+    """Shallow-water drop with prognosed velocity: 2-D open 2048 x 2048 over
+    [-6, 6]^2, dt = dx / 5, g = 1, eps = 1e-8, iga + fct + dfl, n_iters = 2,
+    FP64, from the drop at rest.  Each step computes the advector from two
+    time levels, applies the trapezoidal forcing and advects the depth and
+    both momenta."""
+    case = synth.case_sw(n=2048)
+    e = case.extra
+    K = args.steps if args.steps is not None else 40
+    W = args.warmup
+    dev = torch.device("cuda:0")
+    shape = case.psi.shape
+    plan = mpdata.Plan(shape, n_iters=case.n_iters, opts=case.opts, bc=case.bc, device=dev)
+    h0 = torch.from_numpy(case.psi).to(dev)
+    q0 = [torch.from_numpy(x).to(dev) for x in e["q"]]
+    c = [torch.empty((shape[0] + 1, shape[1]), dtype=torch.float64, device=dev),
+         torch.empty((shape[0], shape[1] + 1), dtype=torch.float64, device=dev)]
+
+    def fresh():
+        return h0.clone(), [x.clone() for x in q0], h0.clone(), [x.clone() for x in q0]
+
+    h, q, hp, qp = fresh()
+    plan.sw_step(h, q, hp, qp, c, e["dt"], e["dx"], grav=e["grav"], eps=e["eps"], n_steps=W)
+    h, q, hp, qp = fresh()
+    secs = _time_steps(lambda k: plan.sw_step(h, q, hp, qp, c, e["dt"], e["dx"], grav=e["grav"],
+                                              eps=e["eps"], n_steps=k), K, torch)
+    cells = case.psi.size
+    ms = secs * 1e3 / K
+    # algorithmic bytes of a step: levels n and n-1 of h, q_x, q_y read, level
+    # n+1 written (the old level n becomes the previous level)
+    alg = 8 * 9 * cells
+    out = {
+        "metric": "Mcell-steps/s", "value": round(cells * K / secs / 1e6, 3),
+        "unit": "Mcell-steps/s", "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": case.name + "_iga_fct_dfl_iters2_vip_trapez", "cells": cells,
+                   "advected_fields": 3, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (ms / 1e3) / 1e9, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 6), "traffic": None,
+                     "alg_bytes_per_launch": alg, "kernel": "whole shallow-water step"},
+    }
+    if not args.no_cpu:
+        sub = synth.case_sw(n=512)
+        se = sub.extra
+        n_sub = 24
+        t0 = time.perf_counter()
+        oracle.sw_run(sub.psi, se["q"], n_sub, se["dt"], se["dx"], eps=se["eps"],
+                      grav=se["grav"], n_iters=sub.n_iters, opts=sub.opts, bc=sub.bc)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(sub.psi.size * n_sub / dt / 1e6, 4),
+                               "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{n_sub} steps of the same drop on 512 x 512 cells, "
+                                         "FP64, one thread"}
+    return out
+
+
 def bench_copy(args, torch):
     """Calibration for the HBM byte counters: kernels of known traffic on a
     256 MiB buffer -- an elementwise in-place scale (reads and writes 256 MiB)
@@ -413,6 +473,8 @@ def main():
         out = bench_adjoint(args, torch, mpdata, synth, oracle)
     elif args.workload == "osc":
         out = bench_osc(args, torch, mpdata, synth, oracle)
+    elif args.workload == "sw":
+        out = bench_sw(args, torch, mpdata, synth, oracle)
     else:
         out = bench_single(args, torch, mpdata, synth, oracle)
     print(json.dumps(out), flush=True)

@@ -167,6 +167,42 @@ int mpdata_osc_step(mpdata_plan *plan, void *psi, void *phi, const void *g,
                     const void *c0, const void *c1, const void *c2, double a,
                     int n_steps);
 
+/* Advector at n+1/2 from prognosed velocity (Sect. 5.1-5.2).  The cell
+ * velocity component d is num[d] / den, set to 0 where den <= eps (den ==
+ * NULL: num[d] is the velocity itself; den and den_prev are both given or
+ * both NULL).  It is extrapolated in time from levels n (num, den) and n-1
+ * (num_prev, den_prev) as 1.5 u^n - 0.5 u^(n-1), averaged over the two
+ * cells of each dimension-d wall through the boundary map (open: an edge
+ * wall takes its cell's value), and multiplied by dt / dx[d].
+ * num, num_prev: arrays of n_dims cell-array pointers; c: n_dims wall-array
+ * pointers (written, distinct from every input).  dt > 0, dx[d] > 0 for
+ * d < n_dims, eps >= 0, all finite (else MPDATA_EINVAL).  The infinite
+ * gauge of the advected fields does not enter here; G is not used. */
+int mpdata_vip_advector(mpdata_plan *plan, const void *const num[3], const void *den,
+                        const void *const num_prev[3], const void *den_prev, double dt,
+                        const double dx[3], double eps, void *const c[3]);
+
+/* n_steps steps of the shallow-water system (eqs. shw1d, shw2d; Sect.
+ * 5.3-5.4): depth h and momenta q[d] = u_d h, gravity grav.  Each step
+ *   c = mpdata_vip_advector(q, h, q_prev, h_prev)        (den = h)
+ *   q_prev = q, h_prev = h
+ *   q[d] += dt/2 R_d(h),  R_d(h) = -grav h dh/dx_d (centred difference
+ *                                   through the boundary map)
+ *   h = ADV(h),  q[d] = ADV(q[d])   (the plan's step, advector c)
+ *   q[d] += dt/2 R_d(h)             (forcing at n+1 from the new depth)
+ * i.e. the trapezoidal source-term scheme with h advected first.  h, q,
+ * h_prev, q_prev hold levels n and n-1 on entry and n + n_steps and
+ * n + n_steps - 1 on return; before the first step of a run the previous
+ * level is a copy of the current one.  c (n_dims wall arrays) is scratch
+ * that holds the last step's advector on return.  All buffers distinct
+ * (else MPDATA_EINVAL).  The plan must be made without G
+ * (MPDATA_EUNSUPPORTED: prognosed velocity is defined for G = 1); its
+ * options and n_iters apply to every advection (the paper's example uses
+ * iga + fct + dfl or abs + fct, two passes). */
+int mpdata_sw_step(mpdata_plan *plan, void *h, void *const q[3], void *h_prev,
+                   void *const q_prev[3], void *const c[3], double dt, const double dx[3],
+                   double grav, double eps, int n_steps);
+
 /* Diagnostics of psi (waits for the result): out[0] = sum of G*psi over the
  * finite cells (FP64, compensated), out[1] = min, out[2] = max of the finite
  * values, *n_nonfinite = number of NaN/Inf cells.  Returns MPDATA_ENONFINITE

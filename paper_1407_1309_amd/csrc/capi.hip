@@ -6,10 +6,12 @@
 // thread-local message and return a negative status.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
 #include <new>
 #include <string>
 #include <vector>
@@ -506,6 +508,165 @@ int mpdata_osc_step(mpdata_plan *plan, void *psi, void *phi, const void *g, cons
         if (e != hipSuccess) return hip_fail(e, "oscillator coupling launch");
     }
     return MPDATA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// checks shared by the prognosed-velocity entry points: spacing, eps, the
+// per-dimension pointers of a plan of n_dims dimensions
+int vip_args(const mpdata_plan *plan, double dt, const double dx[3], double eps)
+{
+    if (!dx) return fail(MPDATA_EINVAL, "dx is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MPDATA_EINVAL, "dt must be finite and > 0");
+    for (int d = 0; d < plan->desc.n_dims; d++)
+        if (!(dx[d] > 0.0) || !std::isfinite(dx[d]))
+            return fail(MPDATA_EINVAL, "dx[%d] must be finite and > 0", d);
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(MPDATA_EINVAL, "eps must be finite and >= 0");
+    return MPDATA_OK;
+}
+
+int ptr_set(const mpdata_plan *plan, const void *const a[3], const char *name)
+{
+    if (!a) return fail(MPDATA_EINVAL, "%s is NULL", name);
+    for (int d = 0; d < plan->desc.n_dims; d++)
+        if (!a[d]) return fail(MPDATA_EINVAL, "%s[%d] is NULL", name, d);
+    return MPDATA_OK;
+}
+
+// true if two of the n non-NULL pointers are equal
+bool any_alias(const void *const *p, int n)
+{
+    for (int i = 0; i < n; i++)
+        for (int j = i + 1; j < n; j++)
+            if (p[i] && p[i] == p[j]) return true;
+    return false;
+}
+
+template <typename T> const T *const *cpp(const void *const a[3], const T *out[3], int nd)
+{
+    for (int d = 0; d < 3; d++) out[d] = d < nd ? (const T *)a[d] : nullptr;
+    return out;
+}
+
+template <typename T> T *const *mpp(void *const a[3], T *out[3], int nd)
+{
+    for (int d = 0; d < 3; d++) out[d] = d < nd ? (T *)a[d] : nullptr;
+    return out;
+}
+
+template <typename T>
+hipError_t vip_run(mpdata_plan *plan, const void *const num[3], const void *den,
+                   const void *const nump[3], const void *denp, double dt, const double dx[3],
+                   double eps, void *const c[3])
+{
+    const int nd = plan->desc.n_dims;
+    const T *a[3], *b[3];
+    T *o[3];
+    double k[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < nd; d++) k[d] = dt / dx[d];
+    return mp::vip_launch<T>(plan->g, cpp<T>(num, a, nd), (const T *)den, cpp<T>(nump, b, nd),
+                             (const T *)denp, eps, k, mpp<T>(c, o, nd), plan->stream);
+}
+
+template <typename T>
+int sw_run(mpdata_plan *plan, void *h, void *const q[3], void *h_prev, void *const q_prev[3],
+           void *const c[3], double dt, const double dx[3], double grav, double eps, int n_steps)
+{
+    const int nd = plan->desc.n_dims;
+    T *qq[3], *qp[3], *cc[3];
+    mpp<T>(q, qq, nd);
+    mpp<T>(q_prev, qp, nd);
+    mpp<T>(c, cc, nd);
+    const void *qc[3] = {qq[0], qq[1], qq[2]}, *qpc[3] = {qp[0], qp[1], qp[2]};
+    double sp[3] = {1.0, 1.0, 1.0};
+    for (int d = 0; d < nd; d++) sp[d] = dx[d];
+    for (int st = 0; st < n_steps; st++) {
+        // advector at n+1/2 from levels n and n-1
+        hipError_t e = vip_run<T>(plan, qc, h, qpc, h_prev, dt, sp, eps, c);
+        if (e != hipSuccess) return hip_fail(e, "prognosed-velocity launch");
+        // level n becomes the previous level; explicit half of the forcing
+        e = mp::sw_force_launch<T>(plan->g, (const T *)h, (T *)h_prev, qq, qp, grav, sp, dt, 1,
+                                   plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "shallow-water forcing launch");
+        int rc = mpdata_step(plan, h, nullptr, cc[0], cc[1], cc[2], 1);
+        if (rc) return rc;
+        for (int d = 0; d < nd; d++) {
+            rc = mpdata_step(plan, qq[d], nullptr, cc[0], cc[1], cc[2], 1);
+            if (rc) return rc;
+        }
+        // forcing at n+1 from the advected depth
+        e = mp::sw_force_launch<T>(plan->g, (const T *)h, (T *)h_prev, qq, qp, grav, sp, dt, 0,
+                                   plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "shallow-water forcing launch");
+    }
+    return MPDATA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpdata_vip_advector(mpdata_plan *plan, const void *const num[3], const void *den,
+                        const void *const num_prev[3], const void *den_prev, double dt,
+                        const double dx[3], double eps, void *const c[3])
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (plan->batched) return fail(MPDATA_EINVAL, "prognosed velocity needs a single-grid plan");
+    int rc = vip_args(plan, dt, dx, eps);
+    if (!rc) rc = ptr_set(plan, num, "num");
+    if (!rc) rc = ptr_set(plan, num_prev, "num_prev");
+    if (!rc) rc = ptr_set(plan, (const void *const *)c, "c");
+    if (rc) return rc;
+    if ((den != nullptr) != (den_prev != nullptr))
+        return fail(MPDATA_EINVAL, "den and den_prev must both be given or both be NULL");
+    const int nd = plan->desc.n_dims;
+    const void *all[11] = {den, den_prev};
+    int k = 2;
+    for (int d = 0; d < nd; d++) {
+        all[k++] = num[d];
+        all[k++] = num_prev[d];
+    }
+    for (int d = 0; d < nd; d++)
+        for (int j = 0; j < k; j++)
+            if (all[j] == c[d]) return fail(MPDATA_EINVAL, "c[%d] aliases an input", d);
+    if (any_alias((const void *const *)c, nd)) return fail(MPDATA_EINVAL, "c components alias");
+    hipError_t e = plan->desc.dtype == MPDATA_F64
+                       ? vip_run<double>(plan, num, den, num_prev, den_prev, dt, dx, eps, c)
+                       : vip_run<float>(plan, num, den, num_prev, den_prev, dt, dx, eps, c);
+    return e == hipSuccess ? MPDATA_OK : hip_fail(e, "prognosed-velocity launch");
+}
+
+int mpdata_sw_step(mpdata_plan *plan, void *h, void *const q[3], void *h_prev,
+                   void *const q_prev[3], void *const c[3], double dt, const double dx[3],
+                   double grav, double eps, int n_steps)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (plan->batched) return fail(MPDATA_EINVAL, "shallow water needs a single-grid plan");
+    if (plan->desc.has_g)
+        return fail(MPDATA_EUNSUPPORTED, "prognosed velocity is defined for G = 1 only");
+    if (!h || !h_prev) return fail(MPDATA_EINVAL, "h or h_prev is NULL");
+    if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
+    if (!std::isfinite(grav)) return fail(MPDATA_EINVAL, "grav must be finite");
+    int rc = vip_args(plan, dt, dx, eps);
+    if (!rc) rc = ptr_set(plan, (const void *const *)q, "q");
+    if (!rc) rc = ptr_set(plan, (const void *const *)q_prev, "q_prev");
+    if (!rc) rc = ptr_set(plan, (const void *const *)c, "c");
+    if (rc) return rc;
+    const int nd = plan->desc.n_dims;
+    const void *all[11] = {h, h_prev};
+    int k = 2;
+    for (int d = 0; d < nd; d++) {
+        all[k++] = q[d];
+        all[k++] = q_prev[d];
+        all[k++] = c[d];
+    }
+    if (any_alias(all, k)) return fail(MPDATA_EINVAL, "state and advector buffers must be distinct");
+    if (n_steps == 0) return MPDATA_OK;
+    return plan->desc.dtype == MPDATA_F64
+               ? sw_run<double>(plan, h, q, h_prev, q_prev, c, dt, dx, grav, eps, n_steps)
+               : sw_run<float>(plan, h, q, h_prev, q_prev, c, dt, dx, grav, eps, n_steps);
 }
 
 int mpdata_diag(mpdata_plan *plan, const void *psi, const void *g, double out[3],

@@ -106,4 +106,16 @@ template <typename T> hipError_t axpy_launch(T *y, const T *x, double a, int64_t
 template <typename T>
 hipError_t osc_couple_launch(T *psi, T *phi, double a, int implicit, int64_t n, hipStream_t s);
 
+// ---- prognosed velocity and the shallow-water forcing (sw.hip) ----------
+// c[d] = k[d] * wall mean of (1.5 u^n - 0.5 u^(n-1)), u = num / den (0 where
+// den <= eps; num itself when den is NULL), for d < g.nd
+template <typename T>
+hipError_t vip_launch(const Geom &g, const T *const num[3], const T *den, const T *const nump[3],
+                      const T *denp, double eps, const double k[3], T *const c[3], hipStream_t s);
+// q[d] += dt/2 * (-grav h dh/dx_d); with save, first q_prev[d] = q[d], h_prev = h
+template <typename T>
+hipError_t sw_force_launch(const Geom &g, const T *h, T *h_prev, T *const q[3],
+                           T *const q_prev[3], double grav, const double dx[3], double dt,
+                           int save, hipStream_t s);
+
 }  // namespace mp

@@ -31,7 +31,7 @@ EXPORTS = [
     "mpdata_adj_workspace_bytes", "mpdata_batched_workspace_bytes", "mpdata_batched_init",
     "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_set_batched_tiling",
     "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read", "mpdata_step_rhs",
-    "mpdata_osc_step",
+    "mpdata_osc_step", "mpdata_vip_advector", "mpdata_sw_step",
     "mpdata_destroy", "mpdata_last_error",
 ]
 
@@ -92,6 +92,12 @@ def lib():
                                       ctypes.c_double]
         L.mpdata_osc_step.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double,
                                       ctypes.c_int]
+        _P3 = _VP * 3
+        _D3 = ctypes.c_double * 3
+        L.mpdata_vip_advector.argtypes = [_VP, _P3, _VP, _P3, _VP, ctypes.c_double, _D3,
+                                          ctypes.c_double, _P3]
+        L.mpdata_sw_step.argtypes = [_VP, _VP, _P3, _VP, _P3, _P3, ctypes.c_double, _D3,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.mpdata_timing.argtypes = [_VP, ctypes.c_int]
         L.mpdata_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int),
@@ -271,6 +277,47 @@ class Plan:
         _check(lib().mpdata_osc_step(self._handle, _ptr(psi), _ptr(phi), _ptr(g), cp[0], cp[1],
                                      cp[2], float(a), int(n_steps)))
         return psi, phi
+
+    def _cells3(self, ts, name):
+        if len(ts) != self.nd:
+            raise ValueError(f"{name}: need {self.nd} cell arrays")
+        for d, t in enumerate(ts):
+            if t is None:
+                raise ValueError(f"{name}[{d}] is None")
+            self._check_cell(t, f"{name}[{d}]")
+        return (_VP * 3)(*([x.data_ptr() for x in ts] + [None] * (3 - self.nd)))
+
+    def _spacing(self, dx):
+        sp = [float(dx)] * self.nd if isinstance(dx, (int, float)) else [float(v) for v in dx]
+        if len(sp) != self.nd:
+            raise ValueError(f"need {self.nd} grid spacings")
+        return (ctypes.c_double * 3)(*(sp + [1.0] * (3 - self.nd)))
+
+    def vip_advector(self, num, den, num_prev, den_prev, dt, dx, eps, c):
+        """Advector at n+1/2 from prognosed velocity num[d] / den (den None:
+        num[d] is the velocity) at levels n and n-1, written into c."""
+        self._check_cell(den, "den")
+        self._check_cell(den_prev, "den_prev")
+        self._check_walls(c)
+        cp = (_VP * 3)(*([x.data_ptr() for x in c] + [None] * (3 - self.nd)))
+        self._bind_stream()
+        _check(lib().mpdata_vip_advector(self._handle, self._cells3(num, "num"), _ptr(den),
+                                         self._cells3(num_prev, "num_prev"), _ptr(den_prev),
+                                         float(dt), self._spacing(dx), float(eps), cp))
+        return c
+
+    def sw_step(self, h, q, h_prev, q_prev, c, dt, dx, grav=1.0, eps=1e-8, n_steps=1):
+        """n_steps shallow-water steps in place (depth h, momenta q, previous
+        level h_prev, q_prev; c receives the last step's advector)."""
+        self._check_cell(h, "h")
+        self._check_cell(h_prev, "h_prev")
+        self._check_walls(c)
+        cp = (_VP * 3)(*([x.data_ptr() for x in c] + [None] * (3 - self.nd)))
+        self._bind_stream()
+        _check(lib().mpdata_sw_step(self._handle, _ptr(h), self._cells3(q, "q"), _ptr(h_prev),
+                                    self._cells3(q_prev, "q_prev"), cp, float(dt),
+                                    self._spacing(dx), float(grav), float(eps), int(n_steps)))
+        return h, q
 
     def diag(self, psi, g=None):
         """(sum G psi, min, max, n_nonfinite); waits for the result."""

@@ -205,7 +205,7 @@ class Case:
     extra: dict = field(default_factory=dict)
 
 
-OPT_FCT, OPT_IGA, OPT_TOT = 1, 2, 4
+OPT_FCT, OPT_IGA, OPT_TOT, OPT_DFL = 1, 2, 4, 16
 
 
 def case_1d(nx=500, n_steps=1000) -> Case:
@@ -228,6 +228,48 @@ def case_osc(nx=1001, n_steps=1400, courant=0.5, omega=2 * np.pi / 400, dt=1.0) 
     c0 = np.full(nx + 1, float(courant))
     return Case("osc_1d_periodic", psi, [c0], None, 2, OPT_FCT | OPT_IGA, 0, n_steps,
                 extra={"phi": np.zeros(nx), "a": 0.5 * dt * omega})
+
+
+def drop_coords(shape, half):
+    """Cell-centre coordinates of a box [-half, half]^nd split into `shape`
+    cells, and the spacing per dimension."""
+    dx = [2.0 * half / n for n in shape]
+    axes = [(np.arange(n) + 0.5) * d - half for n, d in zip(shape, dx)]
+    return np.meshgrid(*axes, indexing="ij"), dx
+
+
+def case_sw(n=2048, half=6.0, n_steps=100) -> Case:
+    """Shallow-water drop (the paper's 2-D prognosed-velocity example): an
+    n x n box [-6, 6]^2, open boundaries, depth 1 - r^2 inside r < 1 and 0
+    outside, at rest; dt = dx / 5, g = 1, eps = 1e-8; iga + fct + dfl with
+    n_iters = 2.  extra: q (momenta), dt, dx, grav, eps."""
+    shape = (n, n)
+    X, dx = drop_coords(shape, half)
+    h = np.maximum(1.0 - X[0] ** 2 - X[1] ** 2, 0.0)
+    return Case(f"sw_2d_open_{n}x{n}", h, [], None, 2, OPT_FCT | OPT_IGA | OPT_DFL, 1, n_steps,
+                extra={"q": [np.zeros(shape), np.zeros(shape)], "dt": dx[0] / 5.0, "dx": dx,
+                       "grav": 1.0, "eps": 1e-8})
+
+
+def sw_state(shape, seed, half=2.0, ring=True):
+    """A perturbed shallow-water state in motion at two time levels:
+    depth (R^2 - r^2)+ (R = 0.8 half) times (1 + 5% noise), with `ring` a
+    ring of cells outside the drop with depths in [0, 2e-8) (around the
+    usual cut-off), outward velocity 0.4 x_d / half plus 5% noise, momenta
+    = velocity x depth; the previous level is the same with 2%
+    multiplicative noise.  Returns (h, q, h_prev, q_prev, dx)."""
+    gen = rng(seed)
+    X, dx = drop_coords(shape, half)
+    r2 = sum(x * x for x in X)
+    R2 = (0.8 * half) ** 2
+    h = np.maximum(R2 - r2, 0.0) / R2 * (1.0 + 0.05 * gen.uniform(-1, 1, size=shape))
+    band = (r2 >= R2) & (r2 < 1.2 * R2) & ring
+    h = np.where(band, gen.uniform(0.0, 2e-8, size=shape), h)
+    u = [0.4 * x / half + 0.05 * gen.uniform(-1, 1, size=shape) for x in X]
+    q = [ud * h for ud in u]
+    h_prev = h * (1.0 + 0.02 * gen.uniform(-1, 1, size=shape))
+    q_prev = [qd * (1.0 + 0.02 * gen.uniform(-1, 1, size=shape)) for qd in q]
+    return h, q, h_prev, q_prev, dx
 
 
 def case_2d(n=2048, seed=2, courant=0.5, sigma=(32.0, 128.0), n_blobs=64,
