@@ -195,17 +195,42 @@ void timer_end(mpdata_plan *p)
     p->t_launches++;
 }
 
+// kernels of one step: stage by stage, the whole-step fused kernels, or the
+// donor pass plus one launch per corrective pass (2-D)
+enum { PATH_STAGED = 0, PATH_FUSED = 1, PATH_PASS2D = 2 };
+
 template <typename T>
 int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0, const T *c1,
-             const T *c2, bool fused, bool timed = false)
+             const T *c2, int path, bool timed = false)
 {
-    hipError_t e;
-    const char *name = !fused ? "staged step"
+    hipError_t e = hipSuccess;
+    const bool fused = path == PATH_FUSED;
+    const char *name = path == PATH_PASS2D ? "k_donor+k_pass2d"
+                       : !fused            ? "staged step"
                        : p->desc.n_dims == 3
                            ? (p->desc.n_iters == 1 ? "k_donor3d" : "k_donor3d+k_corr3d")
                            : "k_fused2d";
     bool tm = timed && timer_begin(p, name);
-    if (fused && p->desc.n_dims == 3) {
+    if (path == PATH_PASS2D) {
+        // donor-cell pass, then one launch per corrective pass
+        T *x = (T *)p->L.tmp[0];
+        const T *c[3] = {c0, c1, nullptr};
+        const int km = (p->desc.opts & MPDATA_OPT_KAHAN) ? 2 : 0;
+        e = mp::launch_donor<T>(p->g, psi_n, c, nullptr, km, x, p->stream);
+        int set = 0;
+        for (int it = 2; it <= p->desc.n_iters && e == hipSuccess; it++) {
+            const bool last = it == p->desc.n_iters;
+            T *y = last ? psi_out : (T *)p->L.tmp[(it - 1) & 1];
+            T *w0 = last ? nullptr : (T *)p->L.faces[set][0];
+            T *w1 = last ? nullptr : (T *)p->L.faces[set][1];
+            e = mp::pass2d_launch<T>(p->g, p->desc.opts, x, c[0], c[1], psi_n, y, w0, w1,
+                                     p->stream);
+            c[0] = w0;
+            c[1] = w1;
+            set ^= 1;
+            x = y;
+        }
+    } else if (fused && p->desc.n_dims == 3) {
         e = mp::fused3d_step<T>(p->g, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, c2,
                                 G, (T *)p->L.tmp[0], p->tile_rows, p->stream);
     } else if (fused) {
@@ -254,6 +279,18 @@ bool use_fused(const mpdata_plan *p)
     return p->kernel != MPDATA_KERNEL_STAGED && fused_available(p);
 }
 
+bool use_pass2d(const mpdata_plan *p)
+{
+    return p->kernel != MPDATA_KERNEL_STAGED && !use_fused(p) &&
+           mp::pass2d_supported(p->desc.n_dims, p->desc.n_iters, p->desc.opts, p->desc.has_g,
+                                p->g.n);
+}
+
+int step_path(const mpdata_plan *p)
+{
+    return use_fused(p) ? PATH_FUSED : use_pass2d(p) ? PATH_PASS2D : PATH_STAGED;
+}
+
 bool use_resident(const mpdata_plan *p)
 {
     return p->kernel != MPDATA_KERNEL_STAGED && resident_available(p);
@@ -271,7 +308,17 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
         if (tm) timer_end(p);
         return e == hipSuccess ? MPDATA_OK : hip_fail(e, "resident 1-D launch");
     }
-    bool fused = use_fused(p);
+    const int path = step_path(p);
+    if (path == PATH_STAGED && p->desc.n_iters >= 2) {
+        // staged passes: psi^n is last read before the final corrective pass,
+        // which reads only the previous pass's result, so the step may
+        // overwrite psi in place (no ping-pong, no copy)
+        for (int s = 0; s < n_steps; s++) {
+            int rc = one_step<T>(p, psi, psi, G, c0, c1, c2, PATH_STAGED, true);
+            if (rc) return rc;
+        }
+        return MPDATA_OK;
+    }
     int64_t N = cells_of(p->g);
     T *alt = (T *)p->L.psi_alt;
     T *cur = psi, *nxt = alt;
@@ -282,7 +329,7 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
         nxt = psi;
     }
     for (int s = 0; s < n_steps; s++) {
-        int rc = one_step<T>(p, cur, nxt, G, c0, c1, c2, fused, true);
+        int rc = one_step<T>(p, cur, nxt, G, c0, c1, c2, path, true);
         if (rc) return rc;
         T *t = cur;
         cur = nxt;
@@ -389,11 +436,11 @@ int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g, const voi
             if (plan->desc.dtype == MPDATA_F64)
                 rc = one_step<double>(plan, (const double *)psi, (double *)plan->L.psi_alt,
                                       (const double *)g, (const double *)c0, (const double *)c1,
-                                      (const double *)c2, true);
+                                      (const double *)c2, PATH_FUSED);
             else
                 rc = one_step<float>(plan, (const float *)psi, (float *)plan->L.psi_alt,
                                      (const float *)g, (const float *)c0, (const float *)c1,
-                                     (const float *)c2, true);
+                                     (const float *)c2, PATH_FUSED);
         }
         if (rc) break;
         (void)hipEventRecord(e1, plan->stream);
@@ -747,7 +794,7 @@ template <typename T> hipError_t adj_plain_step(void *ctx, const T *in, T *out)
 {
     const AdjStepCtx *x = (const AdjStepCtx *)ctx;
     int rc = one_step<T>(x->p, in, out, (const T *)x->G, (const T *)x->c[0], (const T *)x->c[1],
-                         (const T *)x->c[2], use_fused(x->p));
+                         (const T *)x->c[2], step_path(x->p));
     return rc == MPDATA_OK ? hipSuccess : hipErrorLaunchFailure;
 }
 

@@ -71,6 +71,15 @@ hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_
                         const T *c0, const T *c1, const T *c2, const T *G, T *y1buf,
                         int tile_planes, hipStream_t s);
 
+// ---- one corrective pass of a 2-D step in one launch (pass2d.hip) --------
+// G = 1, no third-order terms, any boundaries; x: previous pass's result,
+// c0/c1: previous pass's advector, y (distinct from x and psi_n): result;
+// w0/w1 (both or neither): limited velocities for a following pass
+bool pass2d_supported(int nd, int n_iters, unsigned opts, int has_g, const int64_t n[3]);
+template <typename T>
+hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
+                         const T *psi_n, T *y, T *w0, T *w1, hipStream_t s);
+
 // ---- 1-D grid resident in LDS: all steps of a call in one launch --------
 // two_fields: room for the oscillator pair (resident1d_osc)
 bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g, int two_fields = 0);

@@ -1,0 +1,436 @@
+// pass2d.hip -- one corrective MPDATA pass on a 2-D grid in one launch.
+//
+// For the 2-D configurations the whole-step fused kernel does not take (open
+// boundaries, iga, dfl; G = 1, no third-order terms): the pseudo-velocities of
+// both dimensions (eq. adf_vel with its cross terms and the divergent-flow
+// term), the limiter bounds and coefficients, the limited velocities and the
+// corrective donor-cell update are computed in one sweep.
+//
+// Design (gfx950, wave64), the row march of the fused step kernel applied to
+// a single pass whose input lives in HBM:
+//   * one wavefront owns a strip of 64 columns and marches down a chunk of
+//     rows; every stage is kept in per-lane register rings (one row per
+//     iteration), column neighbours come from DPP lane shifts;
+//   * the halo is 2 lanes on the left and 3 on the right (the divergent-flow
+//     term reaches one wall further right), so a strip emits 59 columns;
+//   * every load goes through the boundary map of its array (cells: wrap or
+//     clamp; walls of the dimension's own advector: wrap, or clamp to the
+//     edge wall), so the halo lanes and warm-up rows see exactly what the
+//     stage-by-stage path reads.  The one quantity a halo cell may not
+//     recompute is the limiter coefficient pair: with open boundaries the
+//     coefficient of a cell outside the domain is that of the edge cell (the
+//     boundary map applied to the coefficient array), so those lanes and rows
+//     take it from the edge lane (readlane) or the edge row (ring slot).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mp {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int HL = 2, HR = 3;            // halo lanes left / right
+constexpr int OW = WAVE - HL - HR;       // output columns per strip
+constexpr int PF = 2;                    // rows in flight ahead of use
+
+// ---- wave-wide lane shifts (DPP wave_shr:1 / wave_shl:1) -------------------
+__device__ inline int lane_from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ inline int lane_from_right(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ inline float from_left(float v) { return __int_as_float(lane_from_left(__float_as_int(v))); }
+__device__ inline float from_right(float v) { return __int_as_float(lane_from_right(__float_as_int(v))); }
+__device__ inline double from_left(double v)
+{
+    return __hiloint2double(lane_from_left(__double2hiint(v)), lane_from_left(__double2loint(v)));
+}
+__device__ inline double from_right(double v)
+{
+    return __hiloint2double(lane_from_right(__double2hiint(v)), lane_from_right(__double2loint(v)));
+}
+// value of v in lane l (l wave-uniform)
+__device__ inline float lane_value(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double lane_value(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+template <typename T> __device__ __forceinline__ T donor_update(bool kahan, T x, T d0, T d1)
+{
+    if (!kahan) return x - (d0 + d1);
+    T s = x, c = T(0);
+    kahan_add(s, c, -d0);
+    kahan_add(s, c, -d1);
+    return s;
+}
+
+// ---- register rings (slot of the row pushed `age` iterations ago is a
+// compile-time index for each unrolled phase P) ------------------------------
+template <int D> __host__ __device__ constexpr int slot(int phase, int age)
+{
+    return ((phase - age) % D + D) % D;
+}
+
+template <typename T, int D> struct Ring {
+    T v[D];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k < D; k++) v[k] = T(0);
+    }
+};
+#define AT(ring, depth, age) (ring).v[slot<depth>(P, (age))]
+
+constexpr int U = 4;    // row-loop unroll; every ring depth divides it
+
+// State of one wavefront.  At iteration a (the newest row) it holds
+//   x rows a..a-3 (and their left / right neighbours), psi^n row a,
+//   dimension-0 walls a+1..a-1, dimension-1 walls of rows a, a-1,
+//   raw V0 at walls a, a-1, bounds rows a..a-2, coefficients rows a-1, a-2,
+//   limited V0 at walls a-1, a-2 and limited V1 of rows a-1, a-2;
+// it computes V0 at wall a, V1 of row a-1, the coefficients of row a-1, the
+// limited velocities at wall a-1 / row a-1 and the corrected row a-2.
+template <typename T, bool FCT, bool IGA, bool ABS> struct March {
+    int n0, n1, i0, i1, bc0, rr, rw;   // rr: next cell row to load, rw: next wall row
+    int lane_lo, lane_hi;              // lanes of columns 0 and n1-1 (edge strips)
+    bool dfl, kahan, out_lane, w1_lane, fix_lo, fix_hi;
+    int64_t ocol, ccol, wcol;          // per-lane column offsets
+    const T *x, *pn, *c0, *c1;
+    T *y, *w0, *w1;
+    T fx[PF], fp[PF], f0[PF], f1[PF];
+    Ring<T, 4> xq, xl, c0q, mxq, mnq;
+    Ring<T, 2> xr, c1q, v0q, buq, bdq, aq0, aq1;
+
+    __device__ __forceinline__ void load(int k)
+    {
+        const int64_t r = map_cell(rr, n0, bc0), w = map_wall(rw, n0, bc0);
+        fx[k] = x[r * n1 + ccol];
+        if (FCT) fp[k] = pn[r * n1 + ccol];
+        f1[k] = c1[r * (n1 + 1) + wcol];
+        f0[k] = c0[w * n1 + ccol];
+        rr++;
+        rw++;
+    }
+
+    template <int P> __device__ __forceinline__ void iter(int a)
+    {
+        constexpr int S = P % PF;
+        const T x_a = fx[S], pn_a = fp[S], c1_a = f1[S], c0_n = f0[S];
+        load(S);
+        AT(xq, 4, 0) = x_a;
+        AT(xl, 4, 0) = from_left(x_a);
+        AT(xr, 2, 0) = from_right(x_a);
+        AT(c0q, 4, 0) = c0_n;     // wall a+1
+        AT(c1q, 2, 0) = c1_a;     // row a
+
+        // psi-fractions: V0 at wall a (rows a-1 | a), V1 of row a-1 at wall j
+        // (columns j-1 | j); A terms and cross terms
+        auto fa = [](T v) -> T { return ABS ? fabs(v) : v; };
+        T num[4], den[4], fr[4];
+        {
+            T xL = fa(AT(xq, 4, 1)), xR = fa(AT(xq, 4, 0));
+            num[0] = xR - xL;
+            den[0] = xR + xL;
+            T p = fa(AT(xr, 2, 0)), q = fa(AT(xr, 2, 1)), e = fa(AT(xl, 4, 0)), f = fa(AT(xl, 4, 1));
+            num[1] = p + q - e - f;
+            den[1] = p + q + e + f;
+        }
+        {
+            T xL = fa(AT(xl, 4, 1)), xR = fa(AT(xq, 4, 1));
+            num[2] = xR - xL;
+            den[2] = xR + xL;
+            T p = fa(AT(xq, 4, 0)), q = fa(AT(xl, 4, 0)), e = fa(AT(xq, 4, 2)), f = fa(AT(xl, 4, 2));
+            num[3] = p + q - e - f;
+            den[3] = p + q + e + f;
+        }
+        if (IGA) {
+            fr[0] = num[0] / T(2);
+            fr[1] = num[1] / T(4);
+            fr[2] = num[2] / T(2);
+            fr[3] = num[3] / T(4);
+        } else {
+            quotients<4>(num, den, fr);
+#pragma unroll
+            for (int k = 0; k < 4; k++) fr[k] = den[k] == T(0) ? T(0) : fr[k];
+        }
+        T v0, v1;
+        {
+            T u = AT(c0q, 4, 1);                         // wall a
+            T s1 = AT(c1q, 2, 1) + AT(c1q, 2, 0);
+            T cb = T(0.25) * (s1 + from_right(s1));
+            v0 = (fabs(u) - u * u) * fr[0];
+            v0 -= T(0.5) * u * cb * fr[1];
+            if (dfl) {
+                // mean of the divergences of cells (a-1, j) and (a, j)
+                T c1a = AT(c1q, 2, 0), c1b = AT(c1q, 2, 1);
+                T dv = (AT(c0q, 4, 1) - AT(c0q, 4, 2)) + (AT(c0q, 4, 0) - AT(c0q, 4, 1));
+                dv += (from_right(c1b) - c1b) + (from_right(c1a) - c1a);
+                if (IGA) dv *= T(0.5) * (AT(xq, 4, 1) + AT(xq, 4, 0));
+                v0 -= T(0.25) * u * dv;
+            }
+        }
+        {
+            T u = AT(c1q, 2, 1);                         // row a-1, wall j
+            T s0 = AT(c0q, 4, 2) + AT(c0q, 4, 1);
+            T cb = T(0.25) * (from_left(s0) + s0);
+            v1 = (fabs(u) - u * u) * fr[2];
+            v1 -= T(0.5) * u * cb * fr[3];
+            if (dfl) {
+                // mean of the divergences of cells (a-1, j-1) and (a-1, j)
+                T d0 = AT(c0q, 4, 1) - AT(c0q, 4, 2);
+                T dv = from_left(d0) + d0;
+                T c = AT(c1q, 2, 1);
+                dv += (c - from_left(c)) + (from_right(c) - c);
+                if (IGA) dv *= T(0.5) * (AT(xl, 4, 1) + AT(xq, 4, 1));
+                v1 -= T(0.25) * u * dv;
+            }
+        }
+        AT(v0q, 2, 0) = v0;
+
+        T lim0, lim1;
+        if (FCT) {
+            // bounds over {psi^n, x} at the cell and its face neighbours
+            AT(mxq, 4, 0) = fmax(pn_a, x_a);
+            AT(mnq, 4, 0) = fmin(pn_a, x_a);
+            T m1 = AT(mxq, 4, 1), n1v = AT(mnq, 4, 1);
+            T mx = fmax(fmax(m1, fmax(AT(mxq, 4, 2), AT(mxq, 4, 0))),
+                        fmax(from_left(m1), from_right(m1)));
+            T mn = fmin(fmin(n1v, fmin(AT(mnq, 4, 2), AT(mnq, 4, 0))),
+                        fmin(from_left(n1v), from_right(n1v)));
+            // in / out fluxes of cell (a-1, j); unit field under iga
+            T xc = AT(xq, 4, 1);
+            T v0lo = AT(v0q, 2, 1), v0hi = v0;
+            T v1lo = v1, v1hi = from_right(v1);
+            T fin, fout;
+            if (IGA) {
+                fin = (pos(v0lo) - neg(v0hi)) + (pos(v1lo) - neg(v1hi));
+                fout = (pos(v0hi) - neg(v0lo)) + (pos(v1hi) - neg(v1lo));
+            } else {
+                fin = (pos(v0lo) * AT(xq, 4, 2) - neg(v0hi) * AT(xq, 4, 0)) +
+                      (pos(v1lo) * AT(xl, 4, 1) - neg(v1hi) * AT(xr, 2, 1));
+                fout = (pos(v0hi) * xc - neg(v0lo) * xc) + (pos(v1hi) * xc - neg(v1lo) * xc);
+            }
+            T bn[2] = {mx - xc, xc - mn}, bdv[2] = {fin, fout}, bq[2];
+            quotients<2>(bn, bdv, bq);
+            T bu = fin > T(0) ? bq[0] : T(1);
+            T bd = fout > T(0) ? bq[1] : T(1);
+            // open columns: a cell left of column 0 / right of column n1-1
+            // has the edge cell's coefficients
+            if (fix_lo) {
+                T eu = lane_value(bu, lane_lo), ed = lane_value(bd, lane_lo);
+                if (lane < lane_lo) {
+                    bu = eu;
+                    bd = ed;
+                }
+            }
+            if (fix_hi) {
+                T eu = lane_value(bu, lane_hi), ed = lane_value(bd, lane_hi);
+                if (lane > lane_hi) {
+                    bu = eu;
+                    bd = ed;
+                }
+            }
+            AT(buq, 2, 0) = bu;
+            AT(bdq, 2, 0) = bd;
+            // limited V1 of row a-1 at wall j: L = (a-1, j-1), R = (a-1, j)
+            {
+                T up = fmin(fmin(T(1), from_left(bd)), bu);
+                T dn = fmin(fmin(T(1), from_left(bu)), bd);
+                lim1 = pos(v1) * up + neg(v1) * dn;
+            }
+            // limited V0 at wall a-1: L = row a-2, R = row a-1; with open rows
+            // the row outside the domain takes the edge row's coefficients
+            {
+                T bu_l = AT(buq, 2, 1), bd_l = AT(bdq, 2, 1);
+                T bu_r = AT(buq, 2, 0), bd_r = AT(bdq, 2, 0);
+                if (bc0 == BC_OPEN) {
+                    if (a - 1 == 0) {
+                        bu_l = bu_r;
+                        bd_l = bd_r;
+                    } else if (a - 1 == n0) {
+                        bu_r = bu_l;
+                        bd_r = bd_l;
+                    }
+                }
+                T v = AT(v0q, 2, 1);
+                T up = fmin(fmin(T(1), bd_l), bu_r);
+                T dn = fmin(fmin(T(1), bu_l), bd_r);
+                lim0 = pos(v) * up + neg(v) * dn;
+            }
+        } else {
+            lim0 = AT(v0q, 2, 1);
+            lim1 = v1;
+        }
+        AT(aq0, 2, 0) = lim0;
+        AT(aq1, 2, 0) = lim1;
+
+        // limited velocities for a following pass: wall a-1 and row a-1
+        if (w0) {
+            const int w = a - 1;
+            if (w >= i0 && (w < i1 || (w == n0 && i1 == n0 && bc0 == BC_OPEN))) {
+                if (out_lane) w0[(int64_t)w * n1 + ocol] = lim0;
+                if (w < i1 && w1_lane) w1[(int64_t)w * (n1 + 1) + ocol] = lim1;
+            }
+        }
+
+        // corrective donor-cell pass at row a-2 (flux = limited velocity
+        // under iga)
+        const T xc = AT(xq, 4, 2);
+        T f0lo, f0hi, f1lo;
+        if (IGA) {
+            f0lo = AT(aq0, 2, 1);
+            f0hi = AT(aq0, 2, 0);
+            f1lo = AT(aq1, 2, 1);
+        } else {
+            f0lo = pos(AT(aq0, 2, 1)) * AT(xq, 4, 3) + neg(AT(aq0, 2, 1)) * xc;
+            f0hi = pos(AT(aq0, 2, 0)) * xc + neg(AT(aq0, 2, 0)) * AT(xq, 4, 1);
+            f1lo = pos(AT(aq1, 2, 1)) * AT(xl, 4, 2) + neg(AT(aq1, 2, 1)) * xc;
+        }
+        const T f1hi = from_right(f1lo);
+        const T res = donor_update(kahan, xc, f0hi - f0lo, f1hi - f1lo);
+        const int r = a - 2;
+        if (r >= i0 && r < i1 && out_lane) y[(int64_t)r * n1 + ocol] = res;
+    }
+    int lane;
+};
+
+template <typename T, bool FCT, bool IGA, bool ABS, int P = 0>
+__device__ __forceinline__ void iter_block(March<T, FCT, IGA, ABS> &m, int a)
+{
+    if constexpr (P < U) {
+        m.template iter<P>(a + P);
+        iter_block<T, FCT, IGA, ABS, P + 1>(m, a);
+    }
+}
+
+template <typename T, bool FCT, bool IGA, bool ABS>
+__global__ void __launch_bounds__(WAVE)
+    k_pass2d(int n0, int n1, int bc0, int bc1, int th, int strips, int dfl, int kahan,
+             const T *__restrict__ x, const T *__restrict__ c0, const T *__restrict__ c1,
+             const T *__restrict__ psi_n, T *__restrict__ y, T *__restrict__ w0,
+             T *__restrict__ w1)
+{
+    const int b = blockIdx.x;
+    const int strip = b % strips, chunk = b / strips;
+    const int i0 = chunk * th;
+    const int i1 = i0 + th < n0 ? i0 + th : n0;
+    const int jstrip0 = strip * OW;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int col = jstrip0 - HL + lane;
+
+    March<T, FCT, IGA, ABS> m;
+    m.n0 = n0;
+    m.n1 = n1;
+    m.i0 = i0;
+    m.i1 = i1;
+    m.bc0 = bc0;
+    m.lane = lane;
+    m.dfl = dfl != 0;
+    m.kahan = kahan != 0;
+    m.x = x;
+    m.pn = psi_n;
+    m.c0 = c0;
+    m.c1 = c1;
+    m.y = y;
+    m.w0 = w0;
+    m.w1 = w1;
+    m.ccol = map_cell(col, n1, bc1);
+    m.wcol = map_wall(col, n1, bc1);
+    m.ocol = col;
+    m.out_lane = lane >= HL && lane < WAVE - HR && col >= 0 && col < n1;
+    // walls of dimension 1 written for a following pass: the strip's output
+    // columns, plus the edge wall n1 (open) by the last strip
+    m.w1_lane = (lane >= HL && lane < WAVE - HR && col >= 0 && col < n1) ||
+                (bc1 == BC_OPEN && col == n1 && strip == strips - 1);
+    m.lane_lo = HL - jstrip0;
+    m.lane_hi = n1 - 1 - jstrip0 + HL;
+    m.fix_lo = bc1 == BC_OPEN && jstrip0 - HL < 0;
+    m.fix_hi = bc1 == BC_OPEN && jstrip0 - HL + WAVE > n1;
+    m.xq.zero();
+    m.xl.zero();
+    m.c0q.zero();
+    m.mxq.zero();
+    m.mnq.zero();
+    m.xr.zero();
+    m.c1q.zero();
+    m.v0q.zero();
+    m.buq.zero();
+    m.bdq.zero();
+    m.aq0.zero();
+    m.aq1.zero();
+#pragma unroll
+    for (int k = 0; k < PF; k++) m.fp[k] = T(0);
+
+    // iterations a = i0-3 .. i1+1 (whole blocks of U; extra rows are not
+    // stored); cell rows are loaded from a, dimension-0 walls one row ahead.
+    // The first output row i0 needs the limiter coefficients of row i0-1,
+    // hence V0 at wall i0-1, whose divergent-flow term reads wall i0-2:
+    // loaded as the newest wall at iteration i0-3.
+    const int a_begin = i0 - 3;
+    const int a_end = i1 + 1;
+    m.rr = a_begin;
+    m.rw = a_begin + 1;
+#pragma unroll
+    for (int k = 0; k < PF; k++) m.load(k);
+    for (int a = a_begin; a <= a_end; a += U) iter_block<T, FCT, IGA, ABS>(m, a);
+}
+
+int64_t chunk_rows(int64_t n0, int64_t strips)
+{
+    int64_t chunks = 2048 / (strips > 0 ? strips : 1);
+    if (chunks < 1) chunks = 1;
+    int64_t th = cdiv(n0, chunks);
+    if (th < 32) th = 32;
+    return th > n0 ? n0 : th;
+}
+
+template <typename T, bool FCT, bool IGA, bool ABS>
+hipError_t launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
+                  const T *psi_n, T *y, T *w0, T *w1, hipStream_t s)
+{
+    const int64_t n0 = g.n[0], n1 = g.n[1];
+    const int64_t strips = cdiv(n1, OW);
+    const int64_t th = chunk_rows(n0, strips);
+    const int64_t blocks = strips * cdiv(n0, th);
+    k_pass2d<T, FCT, IGA, ABS><<<(unsigned)blocks, WAVE, 0, s>>>(
+        (int)n0, (int)n1, g.bc[0], g.bc[1], (int)th, (int)strips, (opts & OPT_DFL) ? 1 : 0,
+        (opts & OPT_KAHAN) ? 1 : 0, x, c0, c1, psi_n, y, w0, w1);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool pass2d_supported(int nd, int n_iters, unsigned opts, int has_g, const int64_t n[3])
+{
+    if (nd != 2 || has_g || n_iters < 2 || (opts & OPT_TOT)) return false;
+    if ((opts & OPT_ABS) && (opts & OPT_IGA)) return false;
+    // 32-bit row / column arithmetic
+    return n[0] < (1 << 30) && n[1] < (1 << 30) && n[0] * (n[1] + 1) < ((int64_t)1 << 31);
+}
+
+template <typename T>
+hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
+                         const T *psi_n, T *y, T *w0, T *w1, hipStream_t s)
+{
+    const bool fct = opts & OPT_FCT, iga = opts & OPT_IGA, absf = opts & OPT_ABS;
+    if (iga) {
+        return fct ? launch<T, true, true, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s)
+                   : launch<T, false, true, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s);
+    }
+    if (absf) {
+        return fct ? launch<T, true, false, true>(g, opts, x, c0, c1, psi_n, y, w0, w1, s)
+                   : launch<T, false, false, true>(g, opts, x, c0, c1, psi_n, y, w0, w1, s);
+    }
+    return fct ? launch<T, true, false, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s)
+               : launch<T, false, false, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s);
+}
+
+template hipError_t pass2d_launch<float>(const Geom &, unsigned, const float *, const float *,
+                                         const float *, const float *, float *, float *, float *,
+                                         hipStream_t);
+template hipError_t pass2d_launch<double>(const Geom &, unsigned, const double *, const double *,
+                                          const double *, const double *, double *, double *,
+                                          double *, hipStream_t);
+
+}  // namespace mp
