@@ -212,11 +212,14 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
                            : "k_fused2d";
     bool tm = timed && timer_begin(p, name);
     if (path == PATH_PASS2D) {
-        // donor-cell pass, then one launch per corrective pass
+        // donor-cell pass, then one launch per corrective pass; in place
+        // (psi_out == psi_n) the donor pass keeps a copy of psi^n for the
+        // limiter of the corrective passes
         T *x = (T *)p->L.tmp[0];
         const T *c[3] = {c0, c1, nullptr};
-        const int km = (p->desc.opts & MPDATA_OPT_KAHAN) ? 2 : 0;
-        e = mp::launch_donor<T>(p->g, psi_n, c, nullptr, km, x, p->stream);
+        T *keep = psi_out == psi_n ? (T *)p->L.psi_alt : nullptr;
+        e = mp::donor2d_launch<T>(p->g, p->desc.opts, psi_n, c0, c1, x, keep, p->stream);
+        if (keep) psi_n = keep;
         int set = 0;
         for (int it = 2; it <= p->desc.n_iters && e == hipSuccess; it++) {
             const bool last = it == p->desc.n_iters;
@@ -309,6 +312,12 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
         return e == hipSuccess ? MPDATA_OK : hip_fail(e, "resident 1-D launch");
     }
     const int path = step_path(p);
+    if (path == PATH_PASS2D && (n_steps & 1)) {
+        // odd count: one step in place, the rest ping-pong and end in psi
+        int rc = one_step<T>(p, psi, psi, G, c0, c1, c2, PATH_PASS2D, true);
+        if (rc || n_steps == 1) return rc;
+        n_steps -= 1;
+    }
     if (path == PATH_STAGED && p->desc.n_iters >= 2) {
         // staged passes: psi^n is last read before the final corrective pass,
         // which reads only the previous pass's result, so the step may

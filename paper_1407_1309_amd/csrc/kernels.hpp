@@ -79,6 +79,11 @@ bool pass2d_supported(int nd, int n_iters, unsigned opts, int has_g, const int64
 template <typename T>
 hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
                          const T *psi_n, T *y, T *w0, T *w1, hipStream_t s);
+// donor-cell pass of a 2-D grid, G = 1 (Kahan per opts); copy (optional)
+// receives x unchanged
+template <typename T>
+hipError_t donor2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
+                          T *out, T *copy, hipStream_t s);
 
 // ---- 1-D grid resident in LDS: all steps of a call in one launch --------
 // two_fields: room for the oscillator pair (resident1d_osc)

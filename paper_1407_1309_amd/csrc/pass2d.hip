@@ -1,4 +1,5 @@
-// pass2d.hip -- one corrective MPDATA pass on a 2-D grid in one launch.
+// pass2d.hip -- one corrective MPDATA pass on a 2-D grid in one launch, and
+// the 2-D donor-cell pass that precedes it.
 //
 // For the 2-D configurations the whole-step fused kernel does not take (open
 // boundaries, iga, dfl; G = 1, no third-order terms): the pseudo-velocities of
@@ -376,6 +377,39 @@ __global__ void __launch_bounds__(WAVE)
     for (int a = a_begin; a <= a_end; a += U) iter_block<T, FCT, IGA, ABS>(m, a);
 }
 
+// Donor-cell pass of a 2-D grid (eqs. upstream, F; G = 1): one thread per
+// cell, a block of 256 threads per row segment (the row is wave-uniform, so
+// no division per thread).  With `copy`, psi^n is also written there (for
+// an in-place step whose corrective passes still need psi^n).
+constexpr int DB = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(DB)
+    k_donor2d(int n0, int n1, int bc0, int bc1, int bpr, int kahan, const T *__restrict__ x,
+              const T *__restrict__ c0, const T *__restrict__ c1, T *__restrict__ out,
+              T *__restrict__ copy)
+{
+    const int row = blockIdx.x / bpr;
+    const int j = (blockIdx.x - row * bpr) * DB + threadIdx.x;
+    if (j >= n1) return;
+    const int64_t r = (int64_t)row * n1;
+    const int64_t rm = (int64_t)wrap_cell(row - 1, n0, bc0) * n1;
+    const int64_t rp = (int64_t)wrap_cell(row + 1, n0, bc0) * n1;
+    const int jm = wrap_cell(j - 1, n1, bc1), jp = wrap_cell(j + 1, n1, bc1);
+    const T xc = x[r + j];
+    const T u0lo = c0[r + j];
+    const T u0hi = c0[(int64_t)wrap_wall(row + 1, n0, bc0) * n1 + j];
+    const int64_t r1 = (int64_t)row * (n1 + 1);
+    const T u1lo = c1[r1 + j];
+    const T u1hi = c1[r1 + wrap_wall(j + 1, n1, bc1)];
+    const T f0lo = pos(u0lo) * x[rm + j] + neg(u0lo) * xc;
+    const T f0hi = pos(u0hi) * xc + neg(u0hi) * x[rp + j];
+    const T f1lo = pos(u1lo) * x[r + jm] + neg(u1lo) * xc;
+    const T f1hi = pos(u1hi) * xc + neg(u1hi) * x[r + jp];
+    out[r + j] = donor_update(kahan != 0, xc, f0hi - f0lo, f1hi - f1lo);
+    if (copy) copy[r + j] = xc;
+}
+
 int64_t chunk_rows(int64_t n0, int64_t strips)
 {
     int64_t chunks = 2048 / (strips > 0 ? strips : 1);
@@ -426,6 +460,23 @@ hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, 
                : launch<T, false, false, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s);
 }
 
+template <typename T>
+hipError_t donor2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
+                          T *out, T *copy, hipStream_t s)
+{
+    const int bpr = (int)cdiv(g.n[1], DB);
+    k_donor2d<T><<<(unsigned)(bpr * g.n[0]), DB, 0, s>>>((int)g.n[0], (int)g.n[1], g.bc[0],
+                                                         g.bc[1], bpr,
+                                                         (opts & OPT_KAHAN) ? 1 : 0, x, c0, c1,
+                                                         out, copy);
+    return hipGetLastError();
+}
+
+template hipError_t donor2d_launch<float>(const Geom &, unsigned, const float *, const float *,
+                                          const float *, float *, float *, hipStream_t);
+template hipError_t donor2d_launch<double>(const Geom &, unsigned, const double *,
+                                           const double *, const double *, double *, double *,
+                                           hipStream_t);
 template hipError_t pass2d_launch<float>(const Geom &, unsigned, const float *, const float *,
                                          const float *, const float *, float *, float *, float *,
                                          hipStream_t);
