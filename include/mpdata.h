@@ -124,7 +124,8 @@ int mpdata_set_stream(mpdata_plan *plan, void *hip_stream);
  * MPDATA_EUNSUPPORTED when no fused kernel covers the plan. */
 int mpdata_set_kernel(mpdata_plan *plan, int kernel);
 
-/* Rows per wavefront chunk of the fused 2-D kernel (0 = built-in default).
+/* Rows per wavefront chunk of the fused 2-D kernel and of the 2-D
+ * single-pass kernel (0 = built-in default).
  * Results do not depend on it (bit for bit); only the speed does. */
 int mpdata_set_tile_rows(mpdata_plan *plan, int rows);
 

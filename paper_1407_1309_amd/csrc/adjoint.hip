@@ -233,6 +233,62 @@ __global__ void k_donor_adj_walls(Geom g, const T *__restrict__ x, const T *cd, 
     if (acc != T(0)) cbd[t] += acc;
 }
 
+// Both transposes of a 2-D donor-cell pass (G = 1) in one gather: the
+// thread of cell (i, j) owns xb(i, j) and the adjoints of the cell's low
+// walls, plus the far edge wall of an open dimension.  The flux adjoint of
+// a wall is yb of the cell above it minus yb of the cell below (cells
+// outside an open domain read no wall); a cell is the left cell of its high
+// wall and the right cell of its low wall, and at an open edge also the
+// mapped outside neighbour of the edge wall.  The row is wave-uniform (one
+// block per row segment), so no index division per thread.
+template <typename T>
+__global__ void __launch_bounds__(B)
+    k_donor_adj2d(int n0, int n1, int bc0, int bc1, int bpr, int flux_is_vel,
+                  const T *__restrict__ x, const T *__restrict__ c0, const T *__restrict__ c1,
+                  const T *__restrict__ yb, T *__restrict__ xb, T *__restrict__ cb0,
+                  T *__restrict__ cb1)
+{
+    const int i = blockIdx.x / bpr;
+    const int j = (blockIdx.x - i * bpr) * B + threadIdx.x;
+    if (j >= n1) return;
+    const bool o0 = bc0 == BC_OPEN, o1 = bc1 == BC_OPEN;
+    const bool top = o0 && i == 0, bot = o0 && i == n0 - 1;
+    const bool lft = o1 && j == 0, rgt = o1 && j == n1 - 1;
+    const int64_t r = (int64_t)i * n1;
+    const int64_t rm = (int64_t)wrap_cell(i - 1, n0, bc0) * n1;
+    const int64_t rp = (int64_t)wrap_cell(i + 1, n0, bc0) * n1;
+    const int jm = wrap_cell(j - 1, n1, bc1), jp = wrap_cell(j + 1, n1, bc1);
+    const T y = yb[r + j];
+    const T yim = top ? T(0) : yb[rm + j], yip = bot ? T(0) : yb[rp + j];
+    const T yjm = lft ? T(0) : yb[r + jm], yjp = rgt ? T(0) : yb[r + jp];
+    const T F0lo = y - yim, F0hi = yip - y, F1lo = y - yjm, F1hi = yjp - y;
+    const int64_t w0lo = r + j, w0hi = (int64_t)n0 * n1 + j;          // edge wall n0
+    const int64_t r1 = (int64_t)i * (n1 + 1);
+    const int64_t w1lo = r1 + j, w1hi = r1 + n1;                       // edge wall n1
+    if (flux_is_vel) {
+        xb[r + j] += y;
+        cb0[w0lo] += F0lo;
+        cb1[w1lo] += F1lo;
+        if (bot) cb0[w0hi] += F0hi;
+        if (rgt) cb1[w1hi] += F1hi;
+        return;
+    }
+    const T u0lo = c0[w0lo], u0hi = c0[(int64_t)wrap_wall(i + 1, n0, bc0) * n1 + j];
+    const T u1lo = c1[w1lo], u1hi = c1[r1 + wrap_wall(j + 1, n1, bc1)];
+    T acc = y + (pos(u0hi) * F0hi + neg(u0lo) * F0lo) + (pos(u1hi) * F1hi + neg(u1lo) * F1lo);
+    if (top) acc += pos(u0lo) * F0lo;
+    if (bot) acc += neg(u0hi) * F0hi;
+    if (lft) acc += pos(u1lo) * F1lo;
+    if (rgt) acc += neg(u1hi) * F1hi;
+    xb[r + j] += acc;
+    const T xc = x[r + j];
+    const T xi = x[rm + j], xj = x[r + jm];
+    cb0[w0lo] += ((u0lo > T(0) ? xi : T(0)) + (u0lo < T(0) ? xc : T(0))) * F0lo;
+    cb1[w1lo] += ((u1lo > T(0) ? xj : T(0)) + (u1lo < T(0) ? xc : T(0))) * F1lo;
+    if (bot) cb0[w0hi] += ((u0hi > T(0) ? xc : T(0)) + (u0hi < T(0) ? xc : T(0))) * F0hi;
+    if (rgt) cb1[w1hi] += ((u1hi > T(0) ? xc : T(0)) + (u1hi < T(0) ? xc : T(0))) * F1hi;
+}
+
 // transpose of the pseudo-velocity at every dimension-d wall
 template <typename T, int ND, int WD>
 __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, const T *c0,
@@ -579,6 +635,13 @@ void donor_adj(const Geom &g, const T *x, const T *const c[3], const T *G, int f
                const T *yb, T *xb, T *const cb[3], hipStream_t s)
 {
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    if (g.nd == 2 && !G && N < ((int64_t)1 << 31)) {
+        const int bpr = (int)cdiv(g.n[1], B);
+        k_donor_adj2d<T><<<(unsigned)(bpr * g.n[0]), B, 0, s>>>(
+            (int)g.n[0], (int)g.n[1], g.bc[0], g.bc[1], bpr, flux_is_vel, x, c[0], c[1], yb, xb,
+            cb[0], cb[1]);
+        return;
+    }
     with_nd(g.nd, [&](auto ND) {
         k_donor_adj_cells<T, decltype(ND)::value><<<(unsigned)cdiv(N, B), B, 0, s>>>(
             g, c[0], c[1], c[2], G, flux_is_vel, yb, xb);
@@ -726,6 +789,31 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
     hipError_t e;
     const int km = (a.opts & OPT_KAHAN) ? 2 : 0;   // Kahan-compensated donor update
     T *first = n > 1 ? w.X[1] : out;
+    if (!a.G && pass2d_supported(g.nd, n > 1 ? n : 2, a.opts, 0, g.n)) {
+        // 2-D: donor kernel, then one launch per corrective pass that also
+        // writes the records (raw and limited velocities, coefficients)
+        if (first) {
+            e = donor2d_launch<T>(g, a.opts, psi_n, a.c[0], a.c[1], first, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
+        for (int it = 2; it <= n; it++) {
+            const T *x = w.X[it - 1];
+            const T *c0 = it == 2 ? a.c[0] : w.W[it - 2][0];
+            const T *c1 = it == 2 ? a.c[1] : w.W[it - 2][1];
+            PassRecord<T> rec;
+            if (fct) {
+                rec.v0 = w.V[it - 1][0];
+                rec.v1 = w.V[it - 1][1];
+                rec.bu = w.bu[it - 1];
+                rec.bd = w.bd[it - 1];
+            }
+            T *y = (it < n) ? w.X[it] : out;
+            e = pass2d_launch<T>(g, a.opts, x, c0, c1, psi_n, y, w.W[it - 1][0], w.W[it - 1][1],
+                                 s, rec);
+            if (e != hipSuccess) return e;
+        }
+        return hipGetLastError();
+    }
     if (first) {
         e = launch_donor<T>(g, psi_n, a.c, a.G, km, first, s);
         if (e != hipSuccess) return e;

@@ -227,7 +227,7 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
             T *w0 = last ? nullptr : (T *)p->L.faces[set][0];
             T *w1 = last ? nullptr : (T *)p->L.faces[set][1];
             e = mp::pass2d_launch<T>(p->g, p->desc.opts, x, c[0], c[1], psi_n, y, w0, w1,
-                                     p->stream);
+                                     p->stream, mp::PassRecord<T>(), p->tile_rows);
             c[0] = w0;
             c[1] = w1;
             set ^= 1;

@@ -99,6 +99,7 @@ template <typename T, bool FCT, bool IGA, bool ABS> struct March {
     int64_t ocol, ccol, wcol;          // per-lane column offsets
     const T *x, *pn, *c0, *c1;
     T *y, *w0, *w1;
+    T *v0r, *v1r, *bur, *bdr;          // records: raw velocities, coefficients
     T fx[PF], fp[PF], f0[PF], f1[PF];
     Ring<T, 4> xq, xl, c0q, mxq, mnq;
     Ring<T, 2> xr, c1q, v0q, buq, bdq, aq0, aq1;
@@ -266,12 +267,24 @@ template <typename T, bool FCT, bool IGA, bool ABS> struct March {
         AT(aq0, 2, 0) = lim0;
         AT(aq1, 2, 0) = lim1;
 
-        // limited velocities for a following pass: wall a-1 and row a-1
+        // limited velocities for a following pass (and, when asked, the raw
+        // velocities and the coefficients): wall a-1 and row a-1
         if (w0) {
             const int w = a - 1;
             if (w >= i0 && (w < i1 || (w == n0 && i1 == n0 && bc0 == BC_OPEN))) {
-                if (out_lane) w0[(int64_t)w * n1 + ocol] = lim0;
-                if (w < i1 && w1_lane) w1[(int64_t)w * (n1 + 1) + ocol] = lim1;
+                const int64_t k0 = (int64_t)w * n1 + ocol, k1 = (int64_t)w * (n1 + 1) + ocol;
+                if (out_lane) {
+                    w0[k0] = lim0;
+                    if (v0r) v0r[k0] = AT(v0q, 2, 1);
+                }
+                if (w < i1 && w1_lane) {
+                    w1[k1] = lim1;
+                    if (v1r) v1r[k1] = v1;
+                }
+                if (FCT && bur && w < i1 && out_lane) {
+                    bur[k0] = AT(buq, 2, 0);
+                    bdr[k0] = AT(bdq, 2, 0);
+                }
             }
         }
 
@@ -291,7 +304,7 @@ template <typename T, bool FCT, bool IGA, bool ABS> struct March {
         const T f1hi = from_right(f1lo);
         const T res = donor_update(kahan, xc, f0hi - f0lo, f1hi - f1lo);
         const int r = a - 2;
-        if (r >= i0 && r < i1 && out_lane) y[(int64_t)r * n1 + ocol] = res;
+        if (y && r >= i0 && r < i1 && out_lane) y[(int64_t)r * n1 + ocol] = res;
     }
     int lane;
 };
@@ -310,7 +323,8 @@ __global__ void __launch_bounds__(WAVE)
     k_pass2d(int n0, int n1, int bc0, int bc1, int th, int strips, int dfl, int kahan,
              const T *__restrict__ x, const T *__restrict__ c0, const T *__restrict__ c1,
              const T *__restrict__ psi_n, T *__restrict__ y, T *__restrict__ w0,
-             T *__restrict__ w1)
+             T *__restrict__ w1, T *__restrict__ v0r, T *__restrict__ v1r,
+             T *__restrict__ bur, T *__restrict__ bdr)
 {
     const int b = blockIdx.x;
     const int strip = b % strips, chunk = b / strips;
@@ -336,6 +350,10 @@ __global__ void __launch_bounds__(WAVE)
     m.y = y;
     m.w0 = w0;
     m.w1 = w1;
+    m.v0r = v0r;
+    m.v1r = v1r;
+    m.bur = bur;
+    m.bdr = bdr;
     m.ccol = map_cell(col, n1, bc1);
     m.wcol = map_wall(col, n1, bc1);
     m.ocol = col;
@@ -410,26 +428,34 @@ __global__ void __launch_bounds__(DB)
     if (copy) copy[r + j] = xc;
 }
 
-int64_t chunk_rows(int64_t n0, int64_t strips)
+// Default rows per chunk: about four waves per SIMD (the FP64 kernels hold
+// 4-5 waves per SIMD), at least 11 rows, and a chunk length whose iteration
+// count (rows + 5) is a whole number of unrolled blocks of U = 4.
+int64_t chunk_rows(int64_t n0, int64_t strips, int tile_rows)
 {
-    int64_t chunks = 2048 / (strips > 0 ? strips : 1);
-    if (chunks < 1) chunks = 1;
-    int64_t th = cdiv(n0, chunks);
-    if (th < 32) th = 32;
+    int64_t th = tile_rows;
+    if (th <= 0) {
+        int64_t chunks = 4096 / (strips > 0 ? strips : 1);
+        if (chunks < 1) chunks = 1;
+        th = cdiv(n0, chunks);
+        if (th < 11) th = 11;
+        th = cdiv(th + 5, U) * U - 5;
+    }
     return th > n0 ? n0 : th;
 }
 
 template <typename T, bool FCT, bool IGA, bool ABS>
 hipError_t launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
-                  const T *psi_n, T *y, T *w0, T *w1, hipStream_t s)
+                  const T *psi_n, T *y, T *w0, T *w1, const PassRecord<T> &rec, int tile_rows,
+                  hipStream_t s)
 {
     const int64_t n0 = g.n[0], n1 = g.n[1];
     const int64_t strips = cdiv(n1, OW);
-    const int64_t th = chunk_rows(n0, strips);
+    const int64_t th = chunk_rows(n0, strips, tile_rows);
     const int64_t blocks = strips * cdiv(n0, th);
     k_pass2d<T, FCT, IGA, ABS><<<(unsigned)blocks, WAVE, 0, s>>>(
         (int)n0, (int)n1, g.bc[0], g.bc[1], (int)th, (int)strips, (opts & OPT_DFL) ? 1 : 0,
-        (opts & OPT_KAHAN) ? 1 : 0, x, c0, c1, psi_n, y, w0, w1);
+        (opts & OPT_KAHAN) ? 1 : 0, x, c0, c1, psi_n, y, w0, w1, rec.v0, rec.v1, rec.bu, rec.bd);
     return hipGetLastError();
 }
 
@@ -445,19 +471,15 @@ bool pass2d_supported(int nd, int n_iters, unsigned opts, int has_g, const int64
 
 template <typename T>
 hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
-                         const T *psi_n, T *y, T *w0, T *w1, hipStream_t s)
+                         const T *psi_n, T *y, T *w0, T *w1, hipStream_t s,
+                         const PassRecord<T> &rec, int tile_rows)
 {
     const bool fct = opts & OPT_FCT, iga = opts & OPT_IGA, absf = opts & OPT_ABS;
-    if (iga) {
-        return fct ? launch<T, true, true, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s)
-                   : launch<T, false, true, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s);
-    }
-    if (absf) {
-        return fct ? launch<T, true, false, true>(g, opts, x, c0, c1, psi_n, y, w0, w1, s)
-                   : launch<T, false, false, true>(g, opts, x, c0, c1, psi_n, y, w0, w1, s);
-    }
-    return fct ? launch<T, true, false, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s)
-               : launch<T, false, false, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, s);
+#define MP_P(F, I, A) launch<T, F, I, A>(g, opts, x, c0, c1, psi_n, y, w0, w1, rec, tile_rows, s)
+    if (iga) return fct ? MP_P(true, true, false) : MP_P(false, true, false);
+    if (absf) return fct ? MP_P(true, false, true) : MP_P(false, false, true);
+    return fct ? MP_P(true, false, false) : MP_P(false, false, false);
+#undef MP_P
 }
 
 template <typename T>
@@ -479,9 +501,9 @@ template hipError_t donor2d_launch<double>(const Geom &, unsigned, const double 
                                            hipStream_t);
 template hipError_t pass2d_launch<float>(const Geom &, unsigned, const float *, const float *,
                                          const float *, const float *, float *, float *, float *,
-                                         hipStream_t);
+                                         hipStream_t, const PassRecord<float> &, int);
 template hipError_t pass2d_launch<double>(const Geom &, unsigned, const double *, const double *,
                                           const double *, const double *, double *, double *,
-                                          double *, hipStream_t);
+                                          double *, hipStream_t, const PassRecord<double> &, int);
 
 }  // namespace mp
