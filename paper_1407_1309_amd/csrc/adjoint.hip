@@ -241,12 +241,15 @@ __global__ void k_donor_adj_walls(Geom g, const T *__restrict__ x, const T *cd, 
 // wall and the right cell of its low wall, and at an open edge also the
 // mapped outside neighbour of the edge wall.  The row is wave-uniform (one
 // block per row segment), so no index division per thread.
+// mode bit 0: write xb (instead of adding to it), plus xadd when given;
+// bit 1: write the wall adjoints (the periodic wall n of a dimension is
+// never written).
 template <typename T>
 __global__ void __launch_bounds__(B)
-    k_donor_adj2d(int n0, int n1, int bc0, int bc1, int bpr, int flux_is_vel,
+    k_donor_adj2d(int n0, int n1, int bc0, int bc1, int bpr, int flux_is_vel, int mode,
                   const T *__restrict__ x, const T *__restrict__ c0, const T *__restrict__ c1,
-                  const T *__restrict__ yb, T *__restrict__ xb, T *__restrict__ cb0,
-                  T *__restrict__ cb1)
+                  const T *__restrict__ yb, const T *__restrict__ xadd, T *__restrict__ xb,
+                  T *__restrict__ cb0, T *__restrict__ cb1)
 {
     const int i = blockIdx.x / bpr;
     const int j = (blockIdx.x - i * bpr) * B + threadIdx.x;
@@ -265,12 +268,19 @@ __global__ void __launch_bounds__(B)
     const int64_t w0lo = r + j, w0hi = (int64_t)n0 * n1 + j;          // edge wall n0
     const int64_t r1 = (int64_t)i * (n1 + 1);
     const int64_t w1lo = r1 + j, w1hi = r1 + n1;                       // edge wall n1
+    const bool ax = mode & 1, ac = mode & 2;
+    auto put = [](bool assign, T *a, int64_t k, T v) {
+        if (assign)
+            a[k] = v;
+        else
+            a[k] += v;
+    };
     if (flux_is_vel) {
-        xb[r + j] += y;
-        cb0[w0lo] += F0lo;
-        cb1[w1lo] += F1lo;
-        if (bot) cb0[w0hi] += F0hi;
-        if (rgt) cb1[w1hi] += F1hi;
+        put(ax, xb, r + j, xadd ? y + xadd[r + j] : y);
+        put(ac, cb0, w0lo, F0lo);
+        put(ac, cb1, w1lo, F1lo);
+        if (bot) put(ac, cb0, w0hi, F0hi);
+        if (rgt) put(ac, cb1, w1hi, F1hi);
         return;
     }
     const T u0lo = c0[w0lo], u0hi = c0[(int64_t)wrap_wall(i + 1, n0, bc0) * n1 + j];
@@ -280,13 +290,14 @@ __global__ void __launch_bounds__(B)
     if (bot) acc += neg(u0hi) * F0hi;
     if (lft) acc += pos(u1lo) * F1lo;
     if (rgt) acc += neg(u1hi) * F1hi;
-    xb[r + j] += acc;
+    if (xadd) acc += xadd[r + j];
+    put(ax, xb, r + j, acc);
     const T xc = x[r + j];
     const T xi = x[rm + j], xj = x[r + jm];
-    cb0[w0lo] += ((u0lo > T(0) ? xi : T(0)) + (u0lo < T(0) ? xc : T(0))) * F0lo;
-    cb1[w1lo] += ((u1lo > T(0) ? xj : T(0)) + (u1lo < T(0) ? xc : T(0))) * F1lo;
-    if (bot) cb0[w0hi] += ((u0hi > T(0) ? xc : T(0)) + (u0hi < T(0) ? xc : T(0))) * F0hi;
-    if (rgt) cb1[w1hi] += ((u1hi > T(0) ? xc : T(0)) + (u1hi < T(0) ? xc : T(0))) * F1hi;
+    put(ac, cb0, w0lo, ((u0lo > T(0) ? xi : T(0)) + (u0lo < T(0) ? xc : T(0))) * F0lo);
+    put(ac, cb1, w1lo, ((u1lo > T(0) ? xj : T(0)) + (u1lo < T(0) ? xc : T(0))) * F1lo);
+    if (bot) put(ac, cb0, w0hi, ((u0hi > T(0) ? xc : T(0)) + (u0hi < T(0) ? xc : T(0))) * F0hi);
+    if (rgt) put(ac, cb1, w1hi, ((u1hi > T(0) ? xc : T(0)) + (u1hi < T(0) ? xc : T(0))) * F1hi);
 }
 
 // transpose of the pseudo-velocity at every dimension-d wall
@@ -507,9 +518,14 @@ __global__ void k_limit_adj(Geom g, const T *__restrict__ V, const T *__restrict
     int64_t M = e[0] * e[1] * e[2];
     int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
     if (t >= M) return;
-    T wb = Wb[t];
-    if (wb == T(0)) return;
     I3 p = unflat_i3(t, e);
+    // periodic: wall n is wall 0 (its own thread); nothing reads entry n
+    if (g.bc[d] == BC_PERIODIC && p.v[d] == (int)g.n[d]) return;
+    T wb = Wb[t];
+    if (wb == T(0)) {
+        Vb[t] = T(0);
+        return;
+    }
     I3 L = sh1(p, d, -1), R = p;
     int64_t kL = ci(g, L), kR = ci(g, R);
     T v = V[wi(g, d, p)];
@@ -519,7 +535,7 @@ __global__ void k_limit_adj(Geom g, const T *__restrict__ V, const T *__restrict
     if (bup[kR] < up) { up = bup[kR]; wu = 2; }
     if (bup[kL] < dn) { dn = bup[kL]; wd = 1; }
     if (bdn[kR] < dn) { dn = bdn[kR]; wd = 2; }
-    aadd(Vb, wi(g, d, p), ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb);
+    Vb[t] = ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb;   // first writer
     T upb = pos(v) * wb, dnb = neg(v) * wb;
     if (wu == 1) aadd(bdb, kL, upb);
     if (wu == 2) aadd(bub, kR, upb);
@@ -629,17 +645,26 @@ template <typename F> void with_nd_d(int nd, int d, F f)
     }
 }
 
-// transpose of a donor-cell pass: xb += (dy/dx)^T yb, cb_d += (dy/dc_d)^T yb
+// true if the 2-D donor transpose (with its write modes) applies
+bool fast_donor_adj(const Geom &g, const void *G)
+{
+    return g.nd == 2 && !G && g.n[0] * g.n[1] < ((int64_t)1 << 31);
+}
+
+// transpose of a donor-cell pass: xb += (dy/dx)^T yb, cb_d += (dy/dc_d)^T yb;
+// with the 2-D kernel, mode bit 0 writes xb (= ... + xadd) and bit 1 writes
+// the wall adjoints instead of adding (other paths: mode must be 0)
 template <typename T>
 void donor_adj(const Geom &g, const T *x, const T *const c[3], const T *G, int flux_is_vel,
-               const T *yb, T *xb, T *const cb[3], hipStream_t s)
+               const T *yb, T *xb, T *const cb[3], hipStream_t s, int mode = 0,
+               const T *xadd = nullptr)
 {
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
-    if (g.nd == 2 && !G && N < ((int64_t)1 << 31)) {
+    if (fast_donor_adj(g, G)) {
         const int bpr = (int)cdiv(g.n[1], B);
         k_donor_adj2d<T><<<(unsigned)(bpr * g.n[0]), B, 0, s>>>(
-            (int)g.n[0], (int)g.n[1], g.bc[0], g.bc[1], bpr, flux_is_vel, x, c[0], c[1], yb, xb,
-            cb[0], cb[1]);
+            (int)g.n[0], (int)g.n[1], g.bc[0], g.bc[1], bpr, flux_is_vel, mode, x, c[0], c[1],
+            yb, xadd, xb, cb[0], cb[1]);
         return;
     }
     with_nd(g.nd, [&](auto ND) {
@@ -852,18 +877,23 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
     const unsigned cb = (unsigned)cdiv(N, B);
     hipError_t e = record_step<T>(a, w, psi_n, nullptr, s);
     if (e != hipSuccess) return e;
+    // Buffers whose first writer in a pass assigns need no clearing: the
+    // 2-D donor transpose writes xb (and, in the last pass, the advector
+    // adjoint); the limiter transpose writes Vb.  The entries of a periodic
+    // dimension's wall n are never written and stay zero from adjoint_run.
+    const bool fast = fast_donor_adj(g, a.G);
     {
         Bufs<T> f;
         f.push(w.pnb, N);
-        for (int d = 0; d < g.nd; d++) f.push(w.Ab[d], nwalls(g, d));
+        if (!fast)
+            for (int d = 0; d < g.nd; d++) f.push(w.Ab[d], nwalls(g, d));
         clear_n<T>(f, s);
     }
     for (int it = n; it >= 2; it--) {
         const T *x = w.X[it - 1];
         {
             Bufs<T> f;
-            f.push(w.xb, N);
-            for (int d = 0; d < g.nd; d++) f.push(w.Vb[d], nwalls(g, d));
+            if (!fast) f.push(w.xb, N);
             if (fct) {
                 f.push(w.bub, N);
                 f.push(w.bdb, N);
@@ -873,7 +903,8 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
         // corrective donor-cell pass
         {
             const T *Wc[3] = {w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2]};
-            donor_adj<T>(g, x, Wc, a.G, iga ? 1 : 0, w.yb, w.xb, w.Ab, s);
+            const int mode = fast ? (1 | (it == n ? 2 : 0)) : 0;
+            donor_adj<T>(g, x, Wc, a.G, iga ? 1 : 0, w.yb, w.xb, w.Ab, s, mode);
         }
         // limiter
         if (fct) {
@@ -892,8 +923,11 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
                 k_copy<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(w.Vb[d], w.Ab[d],
                                                                         nwalls(g, d));
         }
-        // pseudo-velocity: to x and to the previous pass's advector
-        {
+        // pseudo-velocity: to x and to the previous pass's advector (the
+        // first corrective pass reads the input advector: straight into
+        // its gradient)
+        T *const *tgt = (it == 2) ? w.Cb : w.Ab;
+        if (it > 2) {
             Bufs<T> f;
             for (int d = 0; d < g.nd; d++) f.push(w.Ab[d], nwalls(g, d));
             clear_n<T>(f, s);
@@ -902,27 +936,20 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
         for (int d = 0; d < 3; d++) cin[d] = (it == 2) ? a.c[d] : w.W[it - 2][d];
         for (int d = 0; d < g.nd; d++)
             pseudo_adj_dispatch<T>(g, d, (unsigned)cdiv(nwalls(g, d), B), s, a.opts, x, cin[0],
-                                   cin[1], cin[2], a.G, w.Vb[d], w.xb, w.Ab[0], w.Ab[1],
-                                   w.Ab[2]);
-        if (it == 2) {
-            // the first corrective pass reads the input advector: move its
-            // adjoint into the result and clear the buffer
-            Bufs<T> f;
-            int64_t m = 0;
-            for (int d = 0; d < g.nd; d++) {
-                f.push(w.Cb[d], nwalls(g, d), w.Ab[d]);
-                m = nwalls(g, d) > m ? nwalls(g, d) : m;
-            }
-            k_add_clear_n<T><<<(unsigned)cdiv(m, B), B, 0, s>>>(f);
-        }
+                                   cin[1], cin[2], a.G, w.Vb[d], w.xb, tgt[0], tgt[1], tgt[2]);
         T *t = w.yb;
         w.yb = w.xb;
         w.xb = t;
     }
-    // donor-cell pass of the input field with the input advector
-    e = fill<T>(w.xb, N, s);
-    donor_adj<T>(g, psi_n, a.c, a.G, 0, w.yb, w.xb, w.Cb, s);
-    k_add<T><<<cb, B, 0, s>>>(w.xb, w.pnb, N);
+    // donor-cell pass of the input field with the input advector, plus the
+    // limiter's direct dependence on psi^n
+    if (fast) {
+        donor_adj<T>(g, psi_n, a.c, a.G, 0, w.yb, w.xb, w.Cb, s, 1, w.pnb);
+    } else {
+        e = fill<T>(w.xb, N, s);
+        donor_adj<T>(g, psi_n, a.c, a.G, 0, w.yb, w.xb, w.Cb, s);
+        k_add<T><<<cb, B, 0, s>>>(w.xb, w.pnb, N);
+    }
     T *t = w.yb;
     w.yb = w.xb;
     w.xb = t;
@@ -967,6 +994,8 @@ template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
     }
     for (int d = 0; d < g.nd; d++) {
         e = fill<T>(w.Cb[d], nwalls(g, d), s);
+        if (e == hipSuccess) e = fill<T>(w.Ab[d], nwalls(g, d), s);
+        if (e == hipSuccess) e = fill<T>(w.Vb[d], nwalls(g, d), s);
         if (e != hipSuccess) return e;
     }
     e = hipMemcpyAsync(w.yb, a.lambda_T, nb, hipMemcpyDeviceToDevice, s);

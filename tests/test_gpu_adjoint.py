@@ -53,6 +53,60 @@ def test_adjoint_vs_oracle(shape, bc, n_iters, opts, dtype):
         assert rel_l2(a.double().cpu().numpy(), b) <= tol
 
 
+NOG_CASES = []
+for shape, bc in [((33, 29), 0), ((33, 29), 1), ((70, 131), 1), ((40, 64), 0)]:
+    for n_iters, opts in [(2, FCT), (3, FCT), (2, 0), (3, 0), (2, IGA | FCT), (2, IGA),
+                          (3, TOT | FCT), (2, FCT | mpdata.OPT_KAHAN)]:
+        NOG_CASES.append((shape, bc, n_iters, opts))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,bc,n_iters,opts", NOG_CASES)
+def test_adjoint_without_g_vs_oracle(shape, bc, n_iters, opts, dtype):
+    """G = 1 in 2-D: the recompute through the single-pass kernel with its
+    records and the 2-D donor transpose with its write modes (no clearing of
+    the buffers it writes first), for each pass count and option set.
+
+    FP32 with the limiter: the GPU takes the limiter's decisions (which
+    coefficient is the minimum, sign tests) on FP32 values, the oracle on
+    FP64 values of the same rounded inputs; where the two differ the
+    derivative of that cell changes by O(1) (e.g. 5 of 957 cells for the
+    33 x 29 open case with three passes, the same with the stage-by-stage
+    recompute).  There the bar applies to all but the 1 % largest
+    deviations, and the whole field is held to 2e-2."""
+    gen, psi, c, _ = _setup(shape, bc, opts, seed=3 * len(shape) + 5 * bc + opts + n_iters,
+                            with_g=False)
+    if dtype == torch.float32:
+        psi = psi.astype(np.float32).astype(np.float64)
+        c = [x.astype(np.float32).astype(np.float64) for x in c]
+    lam = gen.normal(size=shape)
+    n_steps, ck = 5, 2
+    ref_psi, ref_c = oracle.adjoint(psi, c, lam, n_iters=n_iters, opts=opts, bc=bc,
+                                    n_steps=n_steps, ckpt_every=ck)
+    plan = mpdata.Plan(shape, dtype=dtype, n_iters=n_iters, opts=opts, bc=bc,
+                       adj_steps=n_steps, ckpt_every=ck)
+    gp, gc = plan.adv_adj(dev(psi, dtype), [dev(x, dtype) for x in c], dev(lam, dtype),
+                          n_steps=n_steps, ckpt_every=ck)
+    tol = 1e-10 if dtype == torch.float64 else 1e-3
+    flips = dtype == torch.float32 and bool(opts & FCT)
+
+    def check(got, ref):
+        got = got.double().cpu().numpy()
+        if not flips:
+            assert rel_l2(got, ref) <= tol
+            return
+        assert rel_l2(got, ref) <= 2e-2
+        dev_ = np.abs(got - ref).ravel()
+        keep = np.argsort(dev_)[: dev_.size - max(1, dev_.size // 100)]
+        assert rel_l2(got.ravel()[keep], ref.ravel()[keep]) <= tol
+
+    check(gp, ref_psi)
+    for d, (a, b) in enumerate(zip(gc, ref_c)):
+        check(a, b)
+        if bc == 0:      # periodic: the shared wall's gradient is in entry 0, entry n is 0
+            assert not bool(a.select(d, -1).any())
+
+
 @pytest.mark.parametrize("n_iters,opts", [(2, FCT), (3, FCT), (2, FCT | mpdata.OPT_KAHAN)])
 def test_adjoint_fused_state_sweeps_vs_oracle(n_iters, opts):
     """Periodic, no G, FCT: the checkpointing and segment sweeps run the fused
