@@ -205,29 +205,25 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
 {
     hipError_t e = hipSuccess;
     const bool fused = path == PATH_FUSED;
-    const char *name = path == PATH_PASS2D ? "k_donor+k_pass2d"
+    const char *name = path == PATH_PASS2D ? "k_pass2d"
                        : !fused            ? "staged step"
                        : p->desc.n_dims == 3
                            ? (p->desc.n_iters == 1 ? "k_donor3d" : "k_donor3d+k_corr3d")
                            : "k_fused2d";
     bool tm = timed && timer_begin(p, name);
     if (path == PATH_PASS2D) {
-        // donor-cell pass, then one launch per corrective pass; in place
-        // (psi_out == psi_n) the donor pass keeps a copy of psi^n for the
-        // limiter of the corrective passes
-        T *x = (T *)p->L.tmp[0];
+        // one launch per corrective pass, the first with the donor pass
+        // folded in (psi_out != psi_n: the passes read psi^n)
+        const T *x = psi_n;
         const T *c[3] = {c0, c1, nullptr};
-        T *keep = psi_out == psi_n ? (T *)p->L.psi_alt : nullptr;
-        e = mp::donor2d_launch<T>(p->g, p->desc.opts, psi_n, c0, c1, x, keep, p->stream);
-        if (keep) psi_n = keep;
         int set = 0;
         for (int it = 2; it <= p->desc.n_iters && e == hipSuccess; it++) {
             const bool last = it == p->desc.n_iters;
             T *y = last ? psi_out : (T *)p->L.tmp[(it - 1) & 1];
             T *w0 = last ? nullptr : (T *)p->L.faces[set][0];
             T *w1 = last ? nullptr : (T *)p->L.faces[set][1];
-            e = mp::pass2d_launch<T>(p->g, p->desc.opts, x, c[0], c[1], psi_n, y, w0, w1,
-                                     p->stream, mp::PassRecord<T>(), p->tile_rows);
+            e = mp::pass2d_launch<T>(p->g, p->desc.opts, x, c[0], c[1], it == 2 ? nullptr : psi_n,
+                                     y, w0, w1, p->stream, mp::PassRecord<T>(), p->tile_rows);
             c[0] = w0;
             c[1] = w1;
             set ^= 1;
@@ -312,12 +308,6 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
         return e == hipSuccess ? MPDATA_OK : hip_fail(e, "resident 1-D launch");
     }
     const int path = step_path(p);
-    if (path == PATH_PASS2D && (n_steps & 1)) {
-        // odd count: one step in place, the rest ping-pong and end in psi
-        int rc = one_step<T>(p, psi, psi, G, c0, c1, c2, PATH_PASS2D, true);
-        if (rc || n_steps == 1) return rc;
-        n_steps -= 1;
-    }
     if (path == PATH_STAGED && p->desc.n_iters >= 2) {
         // staged passes: psi^n is last read before the final corrective pass,
         // which reads only the previous pass's result, so the step may

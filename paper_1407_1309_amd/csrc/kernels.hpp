@@ -81,8 +81,9 @@ template <typename T> struct PassRecord {
     T *v0 = nullptr, *v1 = nullptr, *bu = nullptr, *bd = nullptr;
 };
 bool pass2d_supported(int nd, int n_iters, unsigned opts, int has_g, const int64_t n[3]);
-// y may be NULL (no result needed); tile_rows: rows per wavefront chunk
-// (0 = built-in default)
+// y may be NULL (no result needed); psi_n NULL: x is psi^n and the donor
+// pass is folded in (the first corrective pass; no records); tile_rows:
+// rows per wavefront chunk (0 = built-in default)
 template <typename T>
 hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
                          const T *psi_n, T *y, T *w0, T *w1, hipStream_t s,

@@ -29,9 +29,15 @@ namespace mp {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int HL = 2, HR = 3;            // halo lanes left / right
-constexpr int OW = WAVE - HL - HR;       // output columns per strip
 constexpr int PF = 2;                    // rows in flight ahead of use
+
+// Halo lanes left / right and output columns per strip.  With the donor
+// pass computed in the kernel its result is valid one lane less on each
+// side, so the strip needs one more halo lane on the left.
+template <bool DONOR> struct Lanes {
+    static constexpr int HL = DONOR ? 3 : 2, HR = 3;
+    static constexpr int OW = WAVE - HL - HR;
+};
 
 // ---- wave-wide lane shifts (DPP wave_shr:1 / wave_shl:1) -------------------
 __device__ inline int lane_from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
@@ -92,39 +98,100 @@ constexpr int U = 4;    // row-loop unroll; every ring depth divides it
 //   limited V0 at walls a-1, a-2 and limited V1 of rows a-1, a-2;
 // it computes V0 at wall a, V1 of row a-1, the coefficients of row a-1, the
 // limited velocities at wall a-1 / row a-1 and the corrected row a-2.
-template <typename T, bool FCT, bool IGA, bool ABS> struct March {
+//
+// DONOR: the pass input x is the donor-cell pass of psi^n, computed here
+// (row a from psi^n rows a-1..a+1, which are loaded one row ahead like the
+// dimension-0 walls); otherwise x is loaded.  With open boundaries the donor
+// result of a cell outside the domain is the edge cell's: edge lanes are
+// copied across (readlane), rows past the end repeat the last row, and the
+// first chunk starts at row 0 with the rows above filled with row 0.
+template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR> struct March {
+    static constexpr int CO = DONOR ? 1 : 0;   // age of row a in the c1 ring
     int n0, n1, i0, i1, bc0, rr, rw;   // rr: next cell row to load, rw: next wall row
     int lane_lo, lane_hi;              // lanes of columns 0 and n1-1 (edge strips)
-    bool dfl, kahan, out_lane, w1_lane, fix_lo, fix_hi;
+    bool dfl, kahan, out_lane, w1_lane, fix_lo, fix_hi, prefill;
     int64_t ocol, ccol, wcol;          // per-lane column offsets
     const T *x, *pn, *c0, *c1;
     T *y, *w0, *w1;
     T *v0r, *v1r, *bur, *bdr;          // records: raw velocities, coefficients
     T fx[PF], fp[PF], f0[PF], f1[PF];
-    Ring<T, 4> xq, xl, c0q, mxq, mnq;
-    Ring<T, 2> xr, c1q, v0q, buq, bdq, aq0, aq1;
+    Ring<T, 4> xq, xl, c0q, c1q, mxq, mnq, pq;
+    Ring<T, 2> xr, v0q, buq, bdq, aq0, aq1;
+
+    // x (or psi^n), psi^n, c1 of cell row rr and the dimension-0 wall rw
+    __device__ __forceinline__ void fetch(int r_cell, int r_wall, T &vx, T &vp, T &v1, T &v0)
+    {
+        const int64_t r = map_cell(r_cell, n0, bc0), w = map_wall(r_wall, n0, bc0);
+        vx = x[r * n1 + ccol];
+        if (FCT && !DONOR) vp = pn[r * n1 + ccol];
+        v1 = c1[r * (n1 + 1) + wcol];
+        v0 = c0[w * n1 + ccol];
+    }
 
     __device__ __forceinline__ void load(int k)
     {
-        const int64_t r = map_cell(rr, n0, bc0), w = map_wall(rw, n0, bc0);
-        fx[k] = x[r * n1 + ccol];
-        if (FCT) fp[k] = pn[r * n1 + ccol];
-        f1[k] = c1[r * (n1 + 1) + wcol];
-        f0[k] = c0[w * n1 + ccol];
+        fetch(rr, rw, fx[k], fp[k], f1[k], f0[k]);
         rr++;
         rw++;
+    }
+
+    // donor result at a lane outside an open domain: the edge lane's
+    __device__ __forceinline__ T edge_cols(T v)
+    {
+        if (fix_lo) {
+            T e = lane_value(v, lane_lo);
+            if (lane < lane_lo) v = e;
+        }
+        if (fix_hi) {
+            T e = lane_value(v, lane_hi);
+            if (lane > lane_hi) v = e;
+        }
+        return v;
     }
 
     template <int P> __device__ __forceinline__ void iter(int a)
     {
         constexpr int S = P % PF;
-        const T x_a = fx[S], pn_a = fp[S], c1_a = f1[S], c0_n = f0[S];
-        load(S);
+        T x_a, pn_a;
+        if (DONOR) {
+            // psi^n, c1 of row a+1 and wall a+1 arrive; donor pass of row a
+            AT(pq, 4, 0) = fx[S];
+            AT(c1q, 4, 0) = f1[S];
+            AT(c0q, 4, 0) = f0[S];
+            load(S);
+            const T pc = AT(pq, 4, 1), pm = AT(pq, 4, 2), pp = AT(pq, 4, 0);
+            const T u0lo = AT(c0q, 4, 1), u0hi = AT(c0q, 4, 0), u1 = AT(c1q, 4, 1);
+            const T f0lo = pos(u0lo) * pm + neg(u0lo) * pc;
+            const T f0hi = pos(u0hi) * pc + neg(u0hi) * pp;
+            const T f1lo = pos(u1) * from_left(pc) + neg(u1) * pc;
+            const T f1hi = from_right(f1lo);
+            x_a = edge_cols(donor_update(kahan, pc, f0hi - f0lo, f1hi - f1lo));
+            if (bc0 == BC_OPEN && a >= n0) x_a = AT(xq, 4, 1);   // rows past the end
+            pn_a = pc;
+        } else {
+            x_a = fx[S];
+            pn_a = fp[S];
+            AT(c1q, 4, 0) = f1[S];   // row a
+            AT(c0q, 4, 0) = f0[S];   // wall a+1
+            load(S);
+        }
         AT(xq, 4, 0) = x_a;
         AT(xl, 4, 0) = from_left(x_a);
         AT(xr, 2, 0) = from_right(x_a);
-        AT(c0q, 4, 0) = c0_n;     // wall a+1
-        AT(c1q, 2, 0) = c1_a;     // row a
+        if (DONOR && prefill) {
+            // first row of an open domain: the rows above are copies of it
+            prefill = false;
+            AT(xq, 4, 1) = x_a;
+            AT(xq, 4, 2) = x_a;
+            AT(xq, 4, 3) = x_a;
+            AT(xl, 4, 1) = AT(xl, 4, 0);
+            AT(xl, 4, 2) = AT(xl, 4, 0);
+            AT(xr, 2, 1) = AT(xr, 2, 0);
+            if (FCT) {
+                AT(mxq, 4, 1) = AT(mxq, 4, 2) = fmax(pn_a, x_a);
+                AT(mnq, 4, 1) = AT(mnq, 4, 2) = fmin(pn_a, x_a);
+            }
+        }
 
         // psi-fractions: V0 at wall a (rows a-1 | a), V1 of row a-1 at wall j
         // (columns j-1 | j); A terms and cross terms
@@ -159,13 +226,13 @@ template <typename T, bool FCT, bool IGA, bool ABS> struct March {
         T v0, v1;
         {
             T u = AT(c0q, 4, 1);                         // wall a
-            T s1 = AT(c1q, 2, 1) + AT(c1q, 2, 0);
+            T s1 = AT(c1q, 4, CO + 1) + AT(c1q, 4, CO);
             T cb = T(0.25) * (s1 + from_right(s1));
             v0 = (fabs(u) - u * u) * fr[0];
             v0 -= T(0.5) * u * cb * fr[1];
             if (dfl) {
                 // mean of the divergences of cells (a-1, j) and (a, j)
-                T c1a = AT(c1q, 2, 0), c1b = AT(c1q, 2, 1);
+                T c1a = AT(c1q, 4, CO), c1b = AT(c1q, 4, CO + 1);
                 T dv = (AT(c0q, 4, 1) - AT(c0q, 4, 2)) + (AT(c0q, 4, 0) - AT(c0q, 4, 1));
                 dv += (from_right(c1b) - c1b) + (from_right(c1a) - c1a);
                 if (IGA) dv *= T(0.5) * (AT(xq, 4, 1) + AT(xq, 4, 0));
@@ -173,7 +240,7 @@ template <typename T, bool FCT, bool IGA, bool ABS> struct March {
             }
         }
         {
-            T u = AT(c1q, 2, 1);                         // row a-1, wall j
+            T u = AT(c1q, 4, CO + 1);                    // row a-1, wall j
             T s0 = AT(c0q, 4, 2) + AT(c0q, 4, 1);
             T cb = T(0.25) * (from_left(s0) + s0);
             v1 = (fabs(u) - u * u) * fr[2];
@@ -182,7 +249,7 @@ template <typename T, bool FCT, bool IGA, bool ABS> struct March {
                 // mean of the divergences of cells (a-1, j-1) and (a-1, j)
                 T d0 = AT(c0q, 4, 1) - AT(c0q, 4, 2);
                 T dv = from_left(d0) + d0;
-                T c = AT(c1q, 2, 1);
+                T c = AT(c1q, 4, CO + 1);
                 dv += (c - from_left(c)) + (from_right(c) - c);
                 if (IGA) dv *= T(0.5) * (AT(xl, 4, 1) + AT(xq, 4, 1));
                 v1 -= T(0.25) * u * dv;
@@ -309,16 +376,18 @@ template <typename T, bool FCT, bool IGA, bool ABS> struct March {
     int lane;
 };
 
-template <typename T, bool FCT, bool IGA, bool ABS, int P = 0>
-__device__ __forceinline__ void iter_block(March<T, FCT, IGA, ABS> &m, int a)
+template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR, int P = 0>
+__device__ __forceinline__ void iter_block(March<T, FCT, IGA, ABS, DONOR> &m, int a)
 {
     if constexpr (P < U) {
         m.template iter<P>(a + P);
-        iter_block<T, FCT, IGA, ABS, P + 1>(m, a);
+        iter_block<T, FCT, IGA, ABS, DONOR, P + 1>(m, a);
     }
 }
 
-template <typename T, bool FCT, bool IGA, bool ABS>
+// DONOR: x is psi^n (the donor pass is done here); otherwise x is the
+// previous pass's result and psi_n is psi^n.
+template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR>
 __global__ void __launch_bounds__(WAVE)
     k_pass2d(int n0, int n1, int bc0, int bc1, int th, int strips, int dfl, int kahan,
              const T *__restrict__ x, const T *__restrict__ c0, const T *__restrict__ c1,
@@ -326,6 +395,7 @@ __global__ void __launch_bounds__(WAVE)
              T *__restrict__ w1, T *__restrict__ v0r, T *__restrict__ v1r,
              T *__restrict__ bur, T *__restrict__ bdr)
 {
+    constexpr int HL = Lanes<DONOR>::HL, HR = Lanes<DONOR>::HR, OW = Lanes<DONOR>::OW;
     const int b = blockIdx.x;
     const int strip = b % strips, chunk = b / strips;
     const int i0 = chunk * th;
@@ -334,7 +404,7 @@ __global__ void __launch_bounds__(WAVE)
     const int lane = threadIdx.x & (WAVE - 1);
     const int col = jstrip0 - HL + lane;
 
-    March<T, FCT, IGA, ABS> m;
+    March<T, FCT, IGA, ABS, DONOR> m;
     m.n0 = n0;
     m.n1 = n1;
     m.i0 = i0;
@@ -369,6 +439,7 @@ __global__ void __launch_bounds__(WAVE)
     m.xq.zero();
     m.xl.zero();
     m.c0q.zero();
+    m.pq.zero();
     m.mxq.zero();
     m.mnq.zero();
     m.xr.zero();
@@ -382,17 +453,31 @@ __global__ void __launch_bounds__(WAVE)
     for (int k = 0; k < PF; k++) m.fp[k] = T(0);
 
     // iterations a = i0-3 .. i1+1 (whole blocks of U; extra rows are not
-    // stored); cell rows are loaded from a, dimension-0 walls one row ahead.
-    // The first output row i0 needs the limiter coefficients of row i0-1,
-    // hence V0 at wall i0-1, whose divergent-flow term reads wall i0-2:
-    // loaded as the newest wall at iteration i0-3.
-    const int a_begin = i0 - 3;
+    // stored).  The first output row i0 needs the limiter coefficients of
+    // row i0-1, hence V0 at wall i0-1, whose divergent-flow term reads wall
+    // i0-2: loaded as the newest wall at iteration i0-3.  Without the donor
+    // pass, cell rows are loaded from a and dimension-0 walls one row
+    // ahead; with it, psi^n, c1 and the walls all one row ahead, and the
+    // rings start with rows a-1 and a.  The first chunk of an open domain
+    // starts at row 0 (the rows above are copies of row 0).
+    m.prefill = DONOR && bc0 == BC_OPEN && i0 == 0;
+    const int a_begin = m.prefill ? 0 : i0 - 3;
     const int a_end = i1 + 1;
-    m.rr = a_begin;
-    m.rw = a_begin + 1;
+    if (DONOR) {
+        T vp;
+        m.fetch(a_begin - 1, a_begin - 1, m.pq.v[slot<4>(0, 2)], vp, m.c1q.v[slot<4>(0, 2)],
+                m.c0q.v[slot<4>(0, 2)]);
+        m.fetch(a_begin, a_begin, m.pq.v[slot<4>(0, 1)], vp, m.c1q.v[slot<4>(0, 1)],
+                m.c0q.v[slot<4>(0, 1)]);
+        m.rr = a_begin + 1;
+        m.rw = a_begin + 1;
+    } else {
+        m.rr = a_begin;
+        m.rw = a_begin + 1;
+    }
 #pragma unroll
     for (int k = 0; k < PF; k++) m.load(k);
-    for (int a = a_begin; a <= a_end; a += U) iter_block<T, FCT, IGA, ABS>(m, a);
+    for (int a = a_begin; a <= a_end; a += U) iter_block<T, FCT, IGA, ABS, DONOR>(m, a);
 }
 
 // Donor-cell pass of a 2-D grid (eqs. upstream, F; G = 1): one thread per
@@ -444,16 +529,16 @@ int64_t chunk_rows(int64_t n0, int64_t strips, int tile_rows)
     return th > n0 ? n0 : th;
 }
 
-template <typename T, bool FCT, bool IGA, bool ABS>
+template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR>
 hipError_t launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
                   const T *psi_n, T *y, T *w0, T *w1, const PassRecord<T> &rec, int tile_rows,
                   hipStream_t s)
 {
     const int64_t n0 = g.n[0], n1 = g.n[1];
-    const int64_t strips = cdiv(n1, OW);
+    const int64_t strips = cdiv(n1, Lanes<DONOR>::OW);
     const int64_t th = chunk_rows(n0, strips, tile_rows);
     const int64_t blocks = strips * cdiv(n0, th);
-    k_pass2d<T, FCT, IGA, ABS><<<(unsigned)blocks, WAVE, 0, s>>>(
+    k_pass2d<T, FCT, IGA, ABS, DONOR><<<(unsigned)blocks, WAVE, 0, s>>>(
         (int)n0, (int)n1, g.bc[0], g.bc[1], (int)th, (int)strips, (opts & OPT_DFL) ? 1 : 0,
         (opts & OPT_KAHAN) ? 1 : 0, x, c0, c1, psi_n, y, w0, w1, rec.v0, rec.v1, rec.bu, rec.bd);
     return hipGetLastError();
@@ -475,7 +560,16 @@ hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, 
                          const PassRecord<T> &rec, int tile_rows)
 {
     const bool fct = opts & OPT_FCT, iga = opts & OPT_IGA, absf = opts & OPT_ABS;
-#define MP_P(F, I, A) launch<T, F, I, A>(g, opts, x, c0, c1, psi_n, y, w0, w1, rec, tile_rows, s)
+    if (!psi_n) {
+        // first corrective pass with the donor pass folded in (x = psi^n)
+#define MP_P(F, I, A) launch<T, F, I, A, true>(g, opts, x, c0, c1, x, y, w0, w1, rec, tile_rows, s)
+        if (iga) return fct ? MP_P(true, true, false) : MP_P(false, true, false);
+        if (absf) return fct ? MP_P(true, false, true) : MP_P(false, false, true);
+        return fct ? MP_P(true, false, false) : MP_P(false, false, false);
+#undef MP_P
+    }
+#define MP_P(F, I, A) \
+    launch<T, F, I, A, false>(g, opts, x, c0, c1, psi_n, y, w0, w1, rec, tile_rows, s)
     if (iga) return fct ? MP_P(true, true, false) : MP_P(false, true, false);
     if (absf) return fct ? MP_P(true, false, true) : MP_P(false, false, true);
     return fct ? MP_P(true, false, false) : MP_P(false, false, false);

@@ -53,7 +53,7 @@ def test_pass2d_shapes_open(shape, opts):
     psi, c = _inputs(shape, (OPEN, OPEN), opts, seed=shape[0] * 1000 + shape[1] + opts)
     ref = oracle.step(psi, c, n_iters=2, opts=opts, bc=OPEN, n_steps=4)
     out, name = _run(psi, c, (OPEN, OPEN), opts, 2, 4, torch.float64)
-    assert name == "k_donor+k_pass2d"
+    assert name == "k_pass2d"
     assert rel_l2(out, ref) <= TOL[torch.float64]
     assert np.abs(out - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
 
@@ -75,7 +75,7 @@ def test_pass2d_options_and_boundaries(shape, opts, bcs, dtype):
         ref = oracle.step(psi, c, n_iters=n_iters, opts=opts, bc=list(bcs), n_steps=3)
         out, name = _run(psi, c, bcs, opts, n_iters, 3, dtype)
         fused = bcs == (PER, PER) and not (opts & (IGA | DFL))
-        assert name == ("k_fused2d" if fused else "k_donor+k_pass2d"), name
+        assert name == ("k_fused2d" if fused else "k_pass2d"), name
         assert rel_l2(out, ref) <= TOL[dtype], (n_iters, name)
 
 
@@ -87,7 +87,7 @@ def test_pass2d_matches_staged_bitwise_zero_and_identity():
         gen = synth.rng(3)
         c = synth.random_advector(shape, 0.4, gen)
         out, name = _run(z, c, (OPEN, OPEN), opts, 2, 3, torch.float64)
-        assert name == "k_donor+k_pass2d" and not out.any()
+        assert name == "k_pass2d" and not out.any()
         psi = gen.uniform(0.1, 1.0, size=shape)
         c0 = [np.zeros_like(x) for x in c]
         out, _ = _run(psi, c0, (OPEN, OPEN), opts, 2, 3, torch.float64)
