@@ -54,6 +54,7 @@ enum mpdata_status {
     MPDATA_EWORKSPACE = -2,   /* workspace missing, too small or unaligned  */
     MPDATA_EHIP = -3,         /* a HIP runtime call or launch failed        */
     MPDATA_ENONFINITE = -4,   /* mpdata_diag found NaN or Inf values        */
+    MPDATA_ECANCELLED = -5,   /* stopped by the plan's cancel flag          */
     MPDATA_EUNSUPPORTED = -6  /* valid but not provided (see mpdata_init)   */
 };
 
@@ -145,6 +146,22 @@ int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g,
  * paper's advance()). */
 int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0,
                 const void *c1, const void *c2, int n_steps);
+
+/* Stop flag for the step loop of mpdata_step (the paper's solvers stop
+ * after the current step when a flag is raised: Sect. 3.2, public
+ * methods).  flag is a host address (plain or pinned memory, owned by the
+ * caller, read with volatile loads; NULL removes it).  While a flag is set
+ * on the plan, mpdata_step waits for each step to finish before it reads
+ * the flag and launches the next one, so a flag raised from another thread
+ * or a signal handler stops the run after the step in progress: the call
+ * then returns MPDATA_ECANCELLED with psi holding the last completed step.
+ * The 1-D kernel that runs every step of a call in one launch reads the
+ * flag only before that launch. */
+int mpdata_set_cancel_flag(mpdata_plan *plan, const volatile int *flag);
+
+/* Number of steps the last mpdata_step call on this plan completed
+ * (n_steps unless it was cancelled or failed). */
+int mpdata_steps_done(const mpdata_plan *plan, int64_t *out);
 
 /* One step of the inhomogeneous transport equation (Sect. 4.1):
  * psi <- ADV(psi + a_pre * r_pre) + a_post * r_post, ADV one mpdata_step.

@@ -174,6 +174,9 @@ struct mpdata_plan {
     hipEvent_t tev[2] = {nullptr, nullptr};
     int t_launches = 0, t_limit = 0;
     const char *tname = "";
+    // stop flag (host memory, caller-owned) and the last call's step count
+    const volatile int *cancel = nullptr;
+    int64_t steps_done = 0;
 };
 
 namespace {
@@ -295,17 +298,69 @@ bool use_resident(const mpdata_plan *p)
     return p->kernel != MPDATA_KERNEL_STAGED && resident_available(p);
 }
 
+// Step loop with a stop flag: every step runs to completion (stream
+// synchronisation) before the flag is read and the next step launched; the
+// state alternates between psi and the workspace buffer and is copied back
+// to psi if the run stops on the workspace side.
+template <typename T>
+int run_steps_polled(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1,
+                     const T *c2, int n_steps)
+{
+    const bool resident = use_resident(p);
+    const int path = step_path(p);
+    T *cur = psi, *nxt = (T *)p->L.psi_alt;
+    int done = 0, rc = MPDATA_OK;
+    while (done < n_steps) {
+        if (*p->cancel) {
+            rc = fail(MPDATA_ECANCELLED, "cancelled after %d of %d steps", done, n_steps);
+            break;
+        }
+        hipError_t e;
+        if (resident) {
+            e = mp::resident1d_steps<T>(p->g.n[0], p->g.bc[0], p->desc.n_iters, p->desc.opts,
+                                        cur, c0, G, n_steps, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "resident 1-D launch");
+            done = n_steps;
+        } else if (path == PATH_STAGED && p->desc.n_iters >= 2) {
+            int r = one_step<T>(p, cur, cur, G, c0, c1, c2, PATH_STAGED, true);
+            if (r) return r;
+            done++;
+        } else {
+            int r = one_step<T>(p, cur, nxt, G, c0, c1, c2, path, true);
+            if (r) return r;
+            T *t = cur;
+            cur = nxt;
+            nxt = t;
+            done++;
+        }
+        e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return hip_fail(e, "step synchronisation");
+        p->steps_done = done;
+    }
+    if (cur != psi) {
+        hipError_t e = hipMemcpyAsync(psi, cur, sizeof(T) * cells_of(p->g),
+                                      hipMemcpyDeviceToDevice, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return hip_fail(e, "copy of the last completed step");
+    }
+    return rc;
+}
+
 template <typename T>
 int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, const T *c2,
               int n_steps)
 {
+    p->steps_done = 0;
     if (n_steps == 0) return MPDATA_OK;
+    if (p->cancel) return run_steps_polled<T>(p, psi, G, c0, c1, c2, n_steps);
     if (use_resident(p)) {
         bool tm = timer_begin(p, "k_resident1d");
         hipError_t e = mp::resident1d_steps<T>(p->g.n[0], p->g.bc[0], p->desc.n_iters,
                                                p->desc.opts, psi, c0, G, n_steps, p->stream);
         if (tm) timer_end(p);
-        return e == hipSuccess ? MPDATA_OK : hip_fail(e, "resident 1-D launch");
+        if (e != hipSuccess) return hip_fail(e, "resident 1-D launch");
+        p->steps_done = n_steps;
+        return MPDATA_OK;
     }
     const int path = step_path(p);
     if (path == PATH_STAGED && p->desc.n_iters >= 2) {
@@ -316,6 +371,7 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
             int rc = one_step<T>(p, psi, psi, G, c0, c1, c2, PATH_STAGED, true);
             if (rc) return rc;
         }
+        p->steps_done = n_steps;
         return MPDATA_OK;
     }
     int64_t N = cells_of(p->g);
@@ -334,6 +390,7 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
         cur = nxt;
         nxt = t;
     }
+    p->steps_done = n_steps;
     return MPDATA_OK;
 }
 
@@ -391,6 +448,20 @@ int mpdata_set_stream(mpdata_plan *plan, void *hip_stream)
 {
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     plan->stream = (hipStream_t)hip_stream;
+    return MPDATA_OK;
+}
+
+int mpdata_set_cancel_flag(mpdata_plan *plan, const volatile int *flag)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    plan->cancel = flag;
+    return MPDATA_OK;
+}
+
+int mpdata_steps_done(const mpdata_plan *plan, int64_t *out)
+{
+    if (!plan || !out) return fail(MPDATA_EINVAL, "NULL argument");
+    *out = plan->steps_done;
     return MPDATA_OK;
 }
 

@@ -13,12 +13,13 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpdata.so")
 
-OK, EINVAL, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+OK, EINVAL, EWORKSPACE, EHIP, ENONFINITE, ECANCELLED, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 OPT_FCT, OPT_IGA, OPT_TOT, OPT_ABS, OPT_DFL, OPT_KAHAN = 1, 2, 4, 8, 16, 32
 BC_PERIODIC, BC_OPEN = 0, 1
 F32, F64 = 0, 1
@@ -31,7 +32,8 @@ EXPORTS = [
     "mpdata_adj_workspace_bytes", "mpdata_batched_workspace_bytes", "mpdata_batched_init",
     "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_set_batched_tiling",
     "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read", "mpdata_step_rhs",
-    "mpdata_osc_step", "mpdata_vip_advector", "mpdata_sw_step",
+    "mpdata_osc_step", "mpdata_vip_advector", "mpdata_sw_step", "mpdata_set_cancel_flag",
+    "mpdata_steps_done",
     "mpdata_destroy", "mpdata_last_error",
 ]
 
@@ -98,6 +100,8 @@ def lib():
                                           ctypes.c_double, _P3]
         L.mpdata_sw_step.argtypes = [_VP, _VP, _P3, _VP, _P3, _P3, ctypes.c_double, _D3,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.mpdata_set_cancel_flag.argtypes = [_VP, _VP]
+        L.mpdata_steps_done.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64)]
         L.mpdata_timing.argtypes = [_VP, ctypes.c_int]
         L.mpdata_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int),
@@ -189,6 +193,26 @@ class Plan:
 
     def set_kernel(self, kernel):
         _check(lib().mpdata_set_kernel(self._handle, int(kernel)))
+
+    def set_cancel_flag(self, flag):
+        """Stop flag for step(): a host numpy int32 array of one element (kept
+        referenced here), or None to remove it.  While set, step() waits for
+        each step before launching the next and returns early, raising
+        MPDATAError with code ECANCELLED, once flag[0] != 0."""
+        if flag is None:
+            self._cancel = None
+            _check(lib().mpdata_set_cancel_flag(self._handle, None))
+            return
+        if flag.dtype != np.int32 or flag.size != 1 or not flag.flags["C_CONTIGUOUS"]:
+            raise ValueError("flag: need a contiguous numpy int32 array of one element")
+        self._cancel = flag
+        _check(lib().mpdata_set_cancel_flag(self._handle, ctypes.c_void_p(flag.ctypes.data)))
+
+    def steps_done(self):
+        """Steps completed by the last step() call."""
+        out = ctypes.c_int64(0)
+        _check(lib().mpdata_steps_done(self._handle, ctypes.byref(out)))
+        return int(out.value)
 
     def set_tile_rows(self, rows):
         _check(lib().mpdata_set_tile_rows(self._handle, int(rows)))
