@@ -20,12 +20,22 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <type_traits>
 
 namespace mp {
 namespace {
 
 constexpr int B = 256;
+
+// Named range in rocprofv3's marker trace (--marker-trace), scoped.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 struct I3 {
     int v[3];
@@ -981,6 +991,7 @@ template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
     e = hipMemcpyAsync(cur, a.psi0, nb, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     for (int st = 0; st < a.n_steps; st++) {
+        TraceRange tr("adjoint forward step");
         if (st % ck == 0) {
             e = hipMemcpyAsync(w.ck + (size_t)(st / ck) * N, cur, nb, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return e;
@@ -1002,6 +1013,7 @@ template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
     if (e != hipSuccess) return e;
     // reverse sweep over segments
     for (int sg = nck - 1; sg >= 0; sg--) {
+        TraceRange tr("adjoint reverse segment");
         int s0 = sg * ck;
         int s1 = s0 + ck < a.n_steps ? s0 + ck : a.n_steps;
         e = hipMemcpyAsync(w.seg, w.ck + (size_t)sg * N, nb, hipMemcpyDeviceToDevice, s);

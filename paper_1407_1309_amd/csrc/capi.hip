@@ -16,6 +16,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/mpdata.h"
 #include "adjoint.hpp"
 #include "common.hpp"
@@ -24,6 +26,15 @@
 namespace {
 
 thread_local std::string g_err;
+
+// Named range around an entry point's work in rocprofv3's marker trace
+// (--marker-trace): pushed on entry, popped on return.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 int fail(int code, const char *fmt, ...)
 {
@@ -476,6 +487,7 @@ int mpdata_set_tile_rows(mpdata_plan *plan, int rows)
 int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g, const void *c0,
                     const void *c1, const void *c2, int *out_tile_rows)
 {
+    TraceRange trace_range("mpdata_autotune");
     if (!plan || !psi || !out_tile_rows) return fail(MPDATA_EINVAL, "NULL argument");
     if (plan->batched) return fail(MPDATA_EINVAL, "autotune needs a single-grid plan");
     *out_tile_rows = plan->tile_rows;
@@ -536,6 +548,7 @@ int mpdata_autotune(mpdata_plan *plan, const void *psi, const void *g, const voi
 int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0, const void *c1,
                 const void *c2, int n_steps)
 {
+    TraceRange trace_range("mpdata_step");
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     if (plan->batched) return fail(MPDATA_EINVAL, "batched plan: use mpdata_step_batched");
     if (!psi) return fail(MPDATA_EINVAL, "psi is NULL");
@@ -560,6 +573,7 @@ int mpdata_step_rhs(mpdata_plan *plan, void *psi, const void *g, const void *c0,
                     const void *c1, const void *c2, const void *r_pre, double a_pre,
                     const void *r_post, double a_post)
 {
+    TraceRange trace_range("mpdata_step_rhs");
     if (!plan || !psi) return fail(MPDATA_EINVAL, "NULL argument");
     if (plan->batched) return fail(MPDATA_EINVAL, "source terms need a single-grid plan");
     const int64_t N = cells_of(plan->g);
@@ -585,6 +599,7 @@ int mpdata_step_rhs(mpdata_plan *plan, void *psi, const void *g, const void *c0,
 int mpdata_osc_step(mpdata_plan *plan, void *psi, void *phi, const void *g, const void *c0,
                     const void *c1, const void *c2, double a, int n_steps)
 {
+    TraceRange trace_range("mpdata_osc_step");
     if (!plan || !psi || !phi) return fail(MPDATA_EINVAL, "NULL argument");
     if (psi == phi) return fail(MPDATA_EINVAL, "psi and phi must be distinct buffers");
     if (plan->batched) return fail(MPDATA_EINVAL, "the oscillator needs a single-grid plan");
@@ -729,6 +744,7 @@ int mpdata_vip_advector(mpdata_plan *plan, const void *const num[3], const void 
                         const void *const num_prev[3], const void *den_prev, double dt,
                         const double dx[3], double eps, void *const c[3])
 {
+    TraceRange trace_range("mpdata_vip_advector");
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     if (plan->batched) return fail(MPDATA_EINVAL, "prognosed velocity needs a single-grid plan");
     int rc = vip_args(plan, dt, dx, eps);
@@ -759,6 +775,7 @@ int mpdata_sw_step(mpdata_plan *plan, void *h, void *const q[3], void *h_prev,
                    void *const q_prev[3], void *const c[3], double dt, const double dx[3],
                    double grav, double eps, int n_steps)
 {
+    TraceRange trace_range("mpdata_sw_step");
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     if (plan->batched) return fail(MPDATA_EINVAL, "shallow water needs a single-grid plan");
     if (plan->desc.has_g)
@@ -789,6 +806,7 @@ int mpdata_sw_step(mpdata_plan *plan, void *h, void *const q[3], void *h_prev,
 int mpdata_diag(mpdata_plan *plan, const void *psi, const void *g, double out[3],
                 int64_t *n_nonfinite)
 {
+    TraceRange trace_range("mpdata_diag");
     if (!plan || !psi || !out || !n_nonfinite) return fail(MPDATA_EINVAL, "NULL argument");
     if (plan->batched) return fail(MPDATA_EINVAL, "diag needs a single-grid plan");
     int64_t N = cells_of(plan->g);
@@ -877,6 +895,7 @@ int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g, const voi
                    const void *lambda_T, void *grad_psi0, void *grad_c0, void *grad_c1,
                    void *grad_c2)
 {
+    TraceRange trace_range("mpdata_adv_adj");
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
     if (plan->batched) return fail(MPDATA_EINVAL, "adjoint needs a single-grid plan");
     if (plan->desc.opts & (MPDATA_OPT_ABS | MPDATA_OPT_DFL))
@@ -1112,6 +1131,7 @@ extern "C" {
 int mpdata_step_batched(mpdata_plan *plan, void *psi, const void *c0, const void *c1,
                         int n_steps, int use_graph)
 {
+    TraceRange trace_range("mpdata_step_batched");
     if (!plan || !plan->batched) return fail(MPDATA_EINVAL, "not a batched plan");
     if (!psi || !c0 || !c1) return fail(MPDATA_EINVAL, "NULL buffer");
     if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
@@ -1181,6 +1201,7 @@ int mpdata_set_batched_tiling(mpdata_plan *plan, int tile_rows, int xcd_order)
 int mpdata_autotune_batched(mpdata_plan *plan, const void *psi, const void *c0, const void *c1,
                             int *out_tile_rows, int *out_xcd_order)
 {
+    TraceRange trace_range("mpdata_autotune_batched");
     if (!plan || !plan->batched) return fail(MPDATA_EINVAL, "not a batched plan");
     if (!psi || !c0 || !c1 || !out_tile_rows || !out_xcd_order)
         return fail(MPDATA_EINVAL, "NULL argument");
@@ -1237,6 +1258,7 @@ int mpdata_autotune_batched(mpdata_plan *plan, const void *psi, const void *c0, 
 int mpdata_step_per_grid(mpdata_plan *plan, void *psi, const void *c0, const void *c1,
                          int n_steps)
 {
+    TraceRange trace_range("mpdata_step_per_grid");
     if (!plan || !plan->batched) return fail(MPDATA_EINVAL, "not a batched plan");
     if (!psi || !c0 || !c1) return fail(MPDATA_EINVAL, "NULL buffer");
     if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
