@@ -11,6 +11,7 @@ missing the binding raises instead of computing anything another way.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -140,6 +141,37 @@ def _wall_shape(shape, d):
     return tuple(s)
 
 
+def _tune_key(device, kind, dtype, shape, opts, n_iters, bc, has_g):
+    """Autotune cache key: device architecture and everything that selects
+    a kernel and its launch shape."""
+    arch = torch.cuda.get_device_properties(device).gcnArchName
+    return json.dumps([arch, kind, str(dtype), shape, int(opts), int(n_iters), bc, bool(has_g)],
+                      default=list)
+
+
+def _cache_get(path, key):
+    try:
+        with open(path) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def _cache_put(path, key, value):
+    """Add one entry (read-modify-write through a temporary file and an
+    atomic rename, so a concurrent reader never sees a partial file)."""
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {}
+    data[key] = value
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 class Plan:
     """A single-grid plan: validated descriptor + workspace + stream.
 
@@ -233,16 +265,30 @@ class Plan:
         return (tot.value / n.value if n.value else float("nan"), n.value,
                 (name.value or b"").decode())
 
-    def autotune(self, psi, c, g=None):
+    def autotune(self, psi, c, g=None, cache=None):
         """Pick the fused kernel's chunk length by timing candidates on these
-        inputs (psi is not modified); returns the chosen rows per chunk."""
+        inputs (psi is not modified); returns the chosen rows per chunk.
+        cache: path of a JSON file of earlier choices keyed by device
+        architecture, dtype, shape, options, pass count and boundaries; a
+        hit sets the stored chunk length without timing, a miss times and
+        stores."""
         self._check_cell(psi, "psi")
         self._check_cell(g, "g")
         cp = self._check_walls(c)
+        key = None
+        if cache is not None:
+            key = _tune_key(self.device, "single", self.dtype, self.shape, self.desc.opts,
+                            self.desc.n_iters, list(self.desc.bc)[: self.nd], self.desc.has_g)
+            hit = _cache_get(cache, key)
+            if hit is not None:
+                self.set_tile_rows(int(hit["tile_rows"]))
+                return int(hit["tile_rows"])
         self._bind_stream()
         out = ctypes.c_int(0)
         _check(lib().mpdata_autotune(self._handle, _ptr(psi), _ptr(g), cp[0], cp[1], cp[2],
                                      ctypes.byref(out)))
+        if key is not None:
+            _cache_put(cache, key, {"tile_rows": int(out.value)})
         return out.value
 
     def _bind_stream(self):
@@ -390,6 +436,7 @@ class BatchedPlan:
         self.n = len(self.shapes)
         self.dtype = dtype
         self.device = torch.device(device)
+        self.n_iters, self.opts, self.bc = int(n_iters), int(opts), int(bc)
         flat = (ctypes.c_int64 * (2 * self.n))(*[v for s in self.shapes for v in s])
         L = lib()
         need = L.mpdata_batched_workspace_bytes(self.n, flat, _dtype_code(dtype), int(n_iters),
@@ -430,13 +477,25 @@ class BatchedPlan:
         _check(lib().mpdata_set_stream(self._handle, _stream(self.device)))
         _check(lib().mpdata_set_batched_tiling(self._handle, int(tile_rows), 1 if xcd_order else 0))
 
-    def autotune(self, psi, c0, c1):
+    def autotune(self, psi, c0, c1, cache=None):
         """Pick chunk length and tile order by timing one batched step per
-        candidate on these buffers (psi is not modified); returns both."""
+        candidate on these buffers (psi is not modified); returns both.
+        cache: JSON file of earlier choices (see Plan.autotune), keyed here
+        by the list of grid shapes as well."""
         self._check(psi, c0, c1)
+        key = None
+        if cache is not None:
+            key = _tune_key(self.device, "batched", self.dtype, self.shapes, self.opts,
+                            self.n_iters, self.bc, False)
+            hit = _cache_get(cache, key)
+            if hit is not None:
+                self.set_tiling(int(hit["tile_rows"]), bool(hit["xcd_order"]))
+                return int(hit["tile_rows"]), bool(hit["xcd_order"])
         rows, xcd = ctypes.c_int(0), ctypes.c_int(0)
         _check(lib().mpdata_autotune_batched(self._handle, _ptr(psi), _ptr(c0), _ptr(c1),
                                              ctypes.byref(rows), ctypes.byref(xcd)))
+        if key is not None:
+            _cache_put(cache, key, {"tile_rows": int(rows.value), "xcd_order": bool(xcd.value)})
         return rows.value, bool(xcd.value)
 
     def step_per_grid(self, psi, c0, c1, n_steps=1):

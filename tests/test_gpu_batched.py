@@ -129,3 +129,41 @@ def test_batched_workload_sampled():
 def test_batched_rejects_bad_shapes():
     with pytest.raises(ValueError):
         mpdata.BatchedPlan([(64, 64), (2, 64)])
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    """The autotune cache stores a choice on a miss and restores it on a hit
+    without timing, for a single grid and for a batch; each plan kind and
+    shape has its own key, and a restored choice gives the same bits."""
+    import json
+    cache = str(tmp_path / "tune.json")
+    case = synth.case_2d(n=192, n_iters=2, n_steps=1)
+    plan = mpdata.Plan(case.psi.shape, n_iters=2, opts=FCT)
+    psi = torch.from_numpy(case.psi).cuda()
+    c = [torch.from_numpy(x).cuda() for x in case.c]
+    th = plan.autotune(psi, c, cache=cache)
+    data = json.load(open(cache))
+    assert len(data) == 1 and list(data.values())[0] == {"tile_rows": th}
+    plan2 = mpdata.Plan(case.psi.shape, n_iters=2, opts=FCT)
+    assert plan2.autotune(psi, c, cache=cache) == th
+    a, b = psi.clone(), psi.clone()
+    plan.step(a, c, n_steps=3)
+    plan2.step(b, c, n_steps=3)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+    shapes = SHAPES[:6]
+    grids = _grids(shapes, seed=21)
+    bp = mpdata.BatchedPlan(shapes, n_iters=2, opts=FCT)
+    psi0 = bp.pack([g[0] for g in grids], "psi")
+    c0 = bp.pack([g[1] for g in grids], "c0")
+    c1 = bp.pack([g[2] for g in grids], "c1")
+    rows, xcd = bp.autotune(psi0, c0, c1, cache=cache)
+    assert len(json.load(open(cache))) == 2
+    bp2 = mpdata.BatchedPlan(shapes, n_iters=2, opts=FCT)
+    assert bp2.autotune(psi0, c0, c1, cache=cache) == (rows, xcd)
+    p, q = psi0.clone(), psi0.clone()
+    bp.step(p, c0, c1, n_steps=2, use_graph=False)
+    bp2.step(q, c0, c1, n_steps=2, use_graph=False)
+    torch.cuda.synchronize()
+    assert torch.equal(p, q)
