@@ -72,6 +72,20 @@ def _traffic_entry(kernel_name, workload):
         return None
 
 
+def _host():
+    """CPU model and logical CPU count of the host the oracle is timed on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count()}
+
+
 def _time_steps(run, steps, torch):
     """Time `run(steps)` with HIP events on the current stream."""
     stream = torch.cuda.current_stream()
@@ -496,6 +510,8 @@ def main():
         out = bench_sw(args, torch, mpdata, synth, oracle)
     else:
         out = bench_single(args, torch, mpdata, synth, oracle)
+    if "cpu_baseline" in out:
+        out["cpu_baseline"]["host"] = _host()
     print(json.dumps(out), flush=True)
 
 
