@@ -91,6 +91,18 @@ def test_null_plan_calls_fail_cleanly():
     L = mpdata.lib()
     assert L.mpdata_step(None, None, None, None, None, None, 1) == mpdata.EINVAL
     assert L.mpdata_set_kernel(None, 0) == mpdata.EINVAL
+    P3, D3 = ctypes.c_void_p * 3, ctypes.c_double * 3
+    assert L.mpdata_vip_advector(None, P3(), None, P3(), None, 0.1, D3(1, 1, 1), 0.0,
+                                 P3()) == mpdata.EINVAL
+    assert L.mpdata_sw_step(None, None, P3(), None, P3(), P3(), 0.1, D3(1, 1, 1), 1.0, 0.0,
+                            1) == mpdata.EINVAL
+    assert L.mpdata_set_cancel_flag(None, None) == mpdata.EINVAL
+    out = ctypes.c_int64(7)
+    assert L.mpdata_steps_done(None, ctypes.byref(out)) == mpdata.EINVAL
+    assert L.mpdata_osc_step(None, None, None, None, None, None, None, 0.1, 1) == mpdata.EINVAL
+    assert L.mpdata_step_rhs(None, None, None, None, None, None, None, 0.0, None,
+                             0.0) == mpdata.EINVAL
+    assert L.mpdata_last_error()  # the message of the last failure
     L.mpdata_destroy(None)
 
 
