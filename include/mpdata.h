@@ -255,6 +255,24 @@ int mpdata_adv_adj(mpdata_plan *plan, const void *psi0, const void *g,
                    void *grad_psi0, void *grad_c0, void *grad_c1,
                    void *grad_c2);
 
+/* Tangent-linear steps (forward-mode derivative of the full nonlinear step,
+ * the directional counterpart of mpdata_adv_adj): psi advances by n_steps
+ * steps as in mpdata_step and dpsi becomes the derivative of the result
+ * along the direction (dpsi, dc0..dc2) of (psi0, c0..c2); G is constant.
+ * psi and dpsi are distinct cell buffers updated in place; dc_d may be
+ * NULL (zero tangent), else it has c_d's layout.  Derivatives at
+ * non-differentiable points follow the conventions of mpdata_adv_adj, so
+ * <tangent(v), w> = <v, adjoint(w)> holds to rounding.  Runs the
+ * stage-by-stage kernels on (value, derivative) pairs held in the plan's
+ * workspace, which must have mpdata_tlm_workspace_bytes bytes
+ * (MPDATA_EWORKSPACE otherwise). */
+int mpdata_tlm_step(mpdata_plan *plan, void *psi, void *dpsi, const void *g,
+                    const void *c0, const void *c1, const void *c2, const void *dc0,
+                    const void *dc1, const void *dc2, int n_steps);
+
+/* Workspace bytes mpdata_tlm_step needs (0 on an invalid desc). */
+size_t mpdata_tlm_workspace_bytes(const mpdata_desc *desc);
+
 /* Workspace bytes mpdata_adv_adj needs for n_steps / ckpt_every (0 on bad
  * arguments); a plan meant for the adjoint must be created with at least
  * this much workspace. */

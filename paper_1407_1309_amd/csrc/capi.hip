@@ -462,6 +462,60 @@ int mpdata_set_stream(mpdata_plan *plan, void *hip_stream)
     return MPDATA_OK;
 }
 
+size_t mpdata_tlm_workspace_bytes(const mpdata_desc *desc)
+{
+    mp::Geom g;
+    if (check_desc(desc, &g) != MPDATA_OK) return 0;
+    return mp::tlm_workspace_bytes(g, desc->dtype == MPDATA_F64, desc->has_g);
+}
+
+int mpdata_tlm_step(mpdata_plan *plan, void *psi, void *dpsi, const void *g, const void *c0,
+                    const void *c1, const void *c2, const void *dc0, const void *dc1,
+                    const void *dc2, int n_steps)
+{
+    TraceRange trace_range("mpdata_tlm_step");
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (plan->batched) return fail(MPDATA_EINVAL, "the tangent-linear step needs a single-grid plan");
+    if (!psi || !dpsi) return fail(MPDATA_EINVAL, "psi or dpsi is NULL");
+    if (psi == dpsi) return fail(MPDATA_EINVAL, "psi and dpsi must be distinct buffers");
+    if (n_steps < 0) return fail(MPDATA_EINVAL, "n_steps < 0");
+    const void *c[3] = {c0, c1, c2}, *dc[3] = {dc0, dc1, dc2};
+    for (int d = 0; d < 3; d++) {
+        if (d < plan->desc.n_dims && !c[d]) return fail(MPDATA_EINVAL, "c%d is NULL", d);
+        if (d >= plan->desc.n_dims && (c[d] || dc[d]))
+            return fail(MPDATA_EINVAL, "c%d / dc%d given for a %d-D plan", d, d,
+                        plan->desc.n_dims);
+    }
+    if ((g != nullptr) != (plan->desc.has_g != 0)) return fail(MPDATA_EINVAL, "g / has_g mismatch");
+    const bool f64 = plan->desc.dtype == MPDATA_F64;
+    const size_t need = mp::tlm_workspace_bytes(plan->g, f64, plan->desc.has_g);
+    if (plan->ws_bytes < need)
+        return fail(MPDATA_EWORKSPACE, "workspace has %zu bytes, the tangent-linear step needs %zu",
+                    plan->ws_bytes, need);
+    if (n_steps == 0) return MPDATA_OK;
+    hipError_t e;
+    if (f64) {
+        const double *cc[3], *dd[3];
+        for (int d = 0; d < 3; d++) {
+            cc[d] = (const double *)c[d];
+            dd[d] = (const double *)dc[d];
+        }
+        e = mp::tlm_steps<double>(plan->g, plan->desc.n_iters, plan->desc.opts, (double *)psi,
+                                  (double *)dpsi, (const double *)g, cc, dd, n_steps, plan->ws,
+                                  plan->stream);
+    } else {
+        const float *cc[3], *dd[3];
+        for (int d = 0; d < 3; d++) {
+            cc[d] = (const float *)c[d];
+            dd[d] = (const float *)dc[d];
+        }
+        e = mp::tlm_steps<float>(plan->g, plan->desc.n_iters, plan->desc.opts, (float *)psi,
+                                 (float *)dpsi, (const float *)g, cc, dd, n_steps, plan->ws,
+                                 plan->stream);
+    }
+    return e == hipSuccess ? MPDATA_OK : hip_fail(e, "tangent-linear launch");
+}
+
 int mpdata_set_cancel_flag(mpdata_plan *plan, const volatile int *flag)
 {
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");

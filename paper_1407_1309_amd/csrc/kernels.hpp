@@ -94,6 +94,17 @@ template <typename T>
 hipError_t donor2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
                           T *out, T *copy, hipStream_t s);
 
+// ---- tangent-linear step (tlm.hip) ----------------------------------------
+// workspace bytes of tlm_steps for the geometry and dtype
+size_t tlm_workspace_bytes(const Geom &g, int f64, int has_g);
+// n_steps steps of psi and its tangent dpsi (in place) along the advector
+// tangent dc (entries NULL: zero); G constant; stage-by-stage kernels on
+// dual numbers
+template <typename T>
+hipError_t tlm_steps(const Geom &g, int n_iters, unsigned opts, T *psi, T *dpsi, const T *G,
+                     const T *const c[3], const T *const dc[3], int n_steps, void *ws,
+                     hipStream_t s);
+
 // ---- 1-D grid resident in LDS: all steps of a call in one launch --------
 // two_fields: room for the oscillator pair (resident1d_osc)
 bool resident1d_supported(int nd, int64_t n, int dtype_is_f64, int has_g, int two_fields = 0);

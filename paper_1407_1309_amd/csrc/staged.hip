@@ -6,6 +6,7 @@
 // workspace.  This is the general path (1-3 D, every option, both boundary
 // types, FP32/FP64) and the cross-check for the fused kernels.
 #include "common.hpp"
+#include "dual.hpp"
 #include "kernels.hpp"
 
 #include <type_traits>
@@ -404,5 +405,8 @@ hipError_t staged_step(const StagedArgs<T> &a, hipStream_t s)
 
 template hipError_t staged_step<float>(const StagedArgs<float> &, hipStream_t);
 template hipError_t staged_step<double>(const StagedArgs<double> &, hipStream_t);
+// the tangent-linear step: value and derivative through the same stages
+template hipError_t staged_step<Dual<float>>(const StagedArgs<Dual<float>> &, hipStream_t);
+template hipError_t staged_step<Dual<double>>(const StagedArgs<Dual<double>> &, hipStream_t);
 
 }  // namespace mp

@@ -34,7 +34,7 @@ EXPORTS = [
     "mpdata_step_batched", "mpdata_step_per_grid", "mpdata_set_batched_tiling",
     "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read", "mpdata_step_rhs",
     "mpdata_osc_step", "mpdata_vip_advector", "mpdata_sw_step", "mpdata_set_cancel_flag",
-    "mpdata_steps_done",
+    "mpdata_steps_done", "mpdata_tlm_step", "mpdata_tlm_workspace_bytes",
     "mpdata_destroy", "mpdata_last_error",
 ]
 
@@ -102,6 +102,9 @@ def lib():
         L.mpdata_sw_step.argtypes = [_VP, _VP, _P3, _VP, _P3, _P3, ctypes.c_double, _D3,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.mpdata_set_cancel_flag.argtypes = [_VP, _VP]
+        L.mpdata_tlm_step.argtypes = [_VP] + [_VP] * 9 + [ctypes.c_int]
+        L.mpdata_tlm_workspace_bytes.argtypes = [DP]
+        L.mpdata_tlm_workspace_bytes.restype = ctypes.c_size_t
         L.mpdata_steps_done.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64)]
         L.mpdata_timing.argtypes = [_VP, ctypes.c_int]
         L.mpdata_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double),
@@ -176,10 +179,12 @@ class Plan:
     """A single-grid plan: validated descriptor + workspace + stream.
 
     shape: cells per dimension (1-3 entries); bc: int or per-dimension list.
-    adj_steps / ckpt_every: size the workspace for mpdata_adv_adj as well."""
+    adj_steps / ckpt_every: size the workspace for mpdata_adv_adj as well;
+    tlm: size it for mpdata_tlm_step as well."""
 
     def __init__(self, shape, dtype=torch.float64, n_iters=2, opts=0, bc=BC_PERIODIC,
-                 has_g=False, device="cuda", kernel=KERNEL_AUTO, adj_steps=None, ckpt_every=None):
+                 has_g=False, device="cuda", kernel=KERNEL_AUTO, adj_steps=None, ckpt_every=None,
+                 tlm=False):
         self.shape = tuple(int(s) for s in shape)
         self.nd = len(self.shape)
         self.dtype = dtype
@@ -206,6 +211,8 @@ class Plan:
             if adj == 0:
                 raise ValueError("bad adjoint sizing (need 1 <= ckpt_every <= adj_steps)")
             need = max(need, adj)
+        if tlm:
+            need = max(need, L.mpdata_tlm_workspace_bytes(ctypes.byref(d)))
         self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         off = (-base) % 256
@@ -410,6 +417,19 @@ class Plan:
                                         ctypes.byref(out)))
         return out.value
 
+    def tlm_step(self, psi, dpsi, c, dc=None, g=None, n_steps=1):
+        """n_steps tangent-linear steps in place: psi advances, dpsi becomes
+        the derivative of the result along (dpsi, dc) (dc None: zero)."""
+        self._check_cell(psi, "psi")
+        self._check_cell(dpsi, "dpsi")
+        self._check_cell(g, "g")
+        cp = self._check_walls(c)
+        dp = [None] * 3 if dc is None else self._check_walls(dc)
+        self._bind_stream()
+        _check(lib().mpdata_tlm_step(self._handle, _ptr(psi), _ptr(dpsi), _ptr(g), cp[0], cp[1],
+                                     cp[2], dp[0], dp[1], dp[2], int(n_steps)))
+        return psi, dpsi
+
     def adv_adj(self, psi0, c, lambda_T, g=None, n_steps=1, ckpt_every=None):
         """Gradient of J w.r.t. psi0 and c, given lambda_T = dJ/dpsi_T."""
         ckpt_every = int(ckpt_every or n_steps)
@@ -531,7 +551,8 @@ class MPDATAFunction(torch.autograd.Function):
     """psi_T = n_steps MPDATA steps of psi0 with the advector c (G constant).
 
     Backward runs mpdata_adv_adj (checkpointed reverse sweep in the library),
-    giving gradients with respect to psi0 and every advector component."""
+    giving gradients with respect to psi0 and every advector component;
+    forward mode (torch.func.jvp, forward-mode AD) runs mpdata_tlm_step."""
 
     @staticmethod
     def forward(ctx, psi0, plan, n_steps, ckpt_every, g, *c):
@@ -539,8 +560,23 @@ class MPDATAFunction(torch.autograd.Function):
         cs = [x.detach().contiguous() for x in c]
         plan.step(psi, cs, g=g, n_steps=n_steps)
         ctx.save_for_backward(psi0.detach(), *cs)
+        ctx.save_for_forward(psi0.detach(), *cs)
         ctx.plan, ctx.n_steps, ctx.ckpt, ctx.g = plan, n_steps, ckpt_every, g
         return psi
+
+    @staticmethod
+    def jvp(ctx, dpsi0, _plan, _n, _ck, _g, *dc):
+        """Forward mode: mpdata_tlm_step along (dpsi0, dc) (the plan needs
+        tlm=True)."""
+        psi0, *c = ctx.saved_tensors
+        psi = psi0.clone()
+        dpsi = (torch.zeros_like(psi0) if dpsi0 is None else dpsi0.detach().clone()).contiguous()
+        dcs = None
+        if any(x is not None for x in dc):
+            dcs = [torch.zeros_like(cd) if x is None else x.detach().contiguous()
+                   for x, cd in zip(dc, c)]
+        ctx.plan.tlm_step(psi, dpsi, c, dc=dcs, g=ctx.g, n_steps=ctx.n_steps)
+        return dpsi
 
     @staticmethod
     def backward(ctx, grad_out):
