@@ -25,14 +25,14 @@ CFLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
 # Per-file device flags.  The fused 2-D kernel assumes NaN-free data, so its
 # min/max need no operand quieting (IEEE-mode fmax/fmin otherwise cost an
 # extra instruction per operand).
-FILE_FLAGS = {"fused2d.hip": ["-fno-honor-nans"]}
+FILE_FLAGS = {"fused2d_f32.hip": ["-fno-honor-nans"], "fused2d_f64.hip": ["-fno-honor-nans"]}
 
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-KERNEL_SOURCE = {"k_fused2d": "fused2d.hip", "k_fused2d_batched": "fused2d.hip",
+KERNEL_SOURCE = {"k_fused2d": "fused2d.hpp", "k_fused2d_batched": "fused2d.hpp",
                  "k_corr3d": "fused3d.hip", "k_donor3d": "fused3d.hip",
                  "k_donor3d+k_corr3d": "fused3d.hip", "k_resident1d": "resident1d.hip",
                  "k_pass2d": "pass2d.hip", "k_donor2d": "pass2d.hip"}

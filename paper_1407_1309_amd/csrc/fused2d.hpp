@@ -1,4 +1,6 @@
-// fused2d.hip -- all passes of a 2-D MPDATA step in one launch.
+// fused2d.hpp -- all passes of a 2-D MPDATA step in one launch (kernel
+// templates; fused2d_f32.hip and fused2d_f64.hip instantiate them, so the two
+// element types compile in parallel).
 //
 // Design (gfx950, wave64):
 //   * one wavefront owns a strip of 64 consecutive columns (the contiguous
@@ -16,8 +18,18 @@
 // Periodic boundaries are handled by wrapping row and column indices of the
 // loads; the halo lanes and warm-up rows recompute wrapped cells, which is
 // exact because the step is translation-equivariant.
+#pragma once
+
 #include "common.hpp"
 #include "kernels.hpp"
+
+// Multiply-add contraction only within one source expression (decided by the
+// front end from the source alone).  The kernel body is instantiated twice
+// (fast and safe quotient modes, see qset); with contraction left to the
+// back end, the two instantiations could fuse different multiply-add pairs
+// and round a value differently, and a chunk's bits would depend on whether
+// it was recomputed.
+#pragma clang fp contract(on)
 
 namespace mp {
 namespace {
@@ -44,13 +56,66 @@ __device__ inline double from_right(double v)
 
 // Donor-cell update of one cell from the flux differences of the two
 // dimensions (G = 1): straightforward x - (d0 + d1), or Kahan-compensated.
-template <typename T> __device__ __forceinline__ T donor_update(bool kahan, T x, T d0, T d1)
+template <bool KAHAN, typename T> __device__ __forceinline__ T donor_update(T x, T d0, T d1)
 {
-    if (!kahan) return x - (d0 + d1);
+    if constexpr (!KAHAN) return x - (d0 + d1);
     T s = x, c = T(0);
     kahan_add(s, c, -d0);
     kahan_add(s, c, -d1);
     return s;
+}
+
+// ---- quotient sets ---------------------------------------------------------
+// A wave first runs its whole chunk in fast mode: every quotient is n * r
+// with r the hardware reciprocal refined by one Newton step (FP64: within 18
+// ulp of the rounded quotient; FP32: the residual-corrected form), for every
+// lane and with no branch, so each row stays one long straight-line region
+// for the instruction scheduler.  That is accurate only for divisors that are
+// zero (whose quotients every caller discards) or normal, and in FP64 below
+// 2^1000 in magnitude; fast mode records, wave-uniformly, whether any
+// divisor fell outside that range.  A wave with such a record recomputes its
+// chunk in safe mode, rewriting every row it stored (the kernel reads only
+// psi^n and the advector, so the redo sees the same inputs).  Safe mode
+// decides lane by lane: the fast quotient where the divisor is in range, the
+// IEEE quotient elsewhere.  A quotient's value therefore depends only on its
+// operands, never on which lanes share its wave or where its chunk begins, so
+// every tiling (and the batched kernel) gives the same bits.
+__device__ __forceinline__ bool q_in_range(double d)
+{
+    return __builtin_amdgcn_class(d, 0x168) && fabs(d) < 0x1p1000;   // +-normal or +-zero
+}
+__device__ __forceinline__ bool q_in_range(float d)
+{
+    return __builtin_amdgcn_classf(d, 0x168);
+}
+__device__ __forceinline__ double q_fast(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return n * r;
+}
+__device__ __forceinline__ float q_fast(float n, float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float q0 = n * r;
+    return fmaf(fmaf(-d, q0, n), r, q0);
+}
+
+template <bool SAFE, int K, typename T>
+__device__ __forceinline__ void qset(const T (&n)[K], const T (&d)[K], T (&q)[K], uint64_t &bad)
+{
+    if constexpr (SAFE) {
+#pragma unroll
+        for (int k = 0; k < K; k++) q[k] = q_in_range(d[k]) ? q_fast(n[k], d[k]) : n[k] / d[k];
+    } else {
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            ok = ok && q_in_range(d[k]);
+            q[k] = q_fast(n[k], d[k]);
+        }
+        bad |= __builtin_amdgcn_ballot_w64(!ok);
+    }
 }
 
 // ---- register row-queues ------------------------------------------------
@@ -96,8 +161,8 @@ template <typename T> struct Pass {
 
     // x_new: row a of the previous pass's result; c0_new / c1_new: the
     // previous pass's advector at wall a / row a; pn_a: psi^n at row a.
-    template <bool FCT, bool ABS, int P>
-    __device__ __forceinline__ T advance(T x_new, T c0_new, T c1_new, T pn_a, bool kahan)
+    template <bool FCT, bool ABS, bool KH, bool SAFE, int P>
+    __device__ __forceinline__ T advance(T x_new, T c0_new, T c1_new, T pn_a, uint64_t &bad)
     {
         AT(xq, 4, 0) = x_new;
         AT(xl, 4, 0) = from_left(x_new);
@@ -126,7 +191,7 @@ template <typename T> struct Pass {
             num[3] = a + b - e - f;
             den[3] = a + b + e + f;
         }
-        quotients<4>(num, den, fr);
+        qset<SAFE, 4>(num, den, fr, bad);
 #pragma unroll
         for (int k = 0; k < 4; k++) fr[k] = den[k] == T(0) ? T(0) : fr[k];
         T v0;
@@ -165,7 +230,7 @@ template <typename T> struct Pass {
                     (pos(v1lo) * AT(xl, 4, 1) - neg(v1hi) * AT(xr, 2, 1));
             T fout = (pos(v0hi) * xc - neg(v0lo) * xc) + (pos(v1hi) * xc - neg(v1lo) * xc);
             T bn[2] = {mx - xc, xc - mn}, bdv[2] = {fin, fout}, bq[2];
-            quotients<2>(bn, bdv, bq);
+            qset<SAFE, 2>(bn, bdv, bq, bad);
             T bu = fin > T(0) ? bq[0] : T(1);
             T bd = fout > T(0) ? bq[1] : T(1);
             AT(buq, 2, 0) = bu;
@@ -196,28 +261,38 @@ template <typename T> struct Pass {
         T f0hi = pos(AT(aq0, 4, 0)) * x + neg(AT(aq0, 4, 0)) * AT(xq, 4, 1);
         T f1lo = pos(AT(aq1, 4, 1)) * AT(xl, 4, 2) + neg(AT(aq1, 4, 1)) * x;
         T f1hi = from_right(f1lo);
-        return donor_update(kahan, x, f0hi - f0lo, f1hi - f1lo);
+        return donor_update<KH>(x, f0hi - f0lo, f1hi - f1lo);
     }
 };
 
+// Row-loop unroll: U = 8 rows per loop trip.  With 4 the register copies
+// of the loop-carried prefetch at the back edge made the compiler wait for
+// the newest loads (s_waitcnt vmcnt(0)) once per trip, draining the
+// two-row prefetch; with 8 the waits stay two rows behind the loads.  The
+// rows left over after the last whole trip run in blocks of UT = 4 (every
+// ring depth divides 4 when the psi^n ring has depth 4), so a chunk is
+// rounded up to a multiple of 4 iterations, not 8.
 template <int NI, bool FCT> struct Cfg {
     static constexpr int NP = NI - 1;                 // corrective passes
     static constexpr int H = 1 + (FCT ? 2 : 1) * NP;  // horizontal halo (lanes)
     static constexpr int LAG = 1 + 2 * NP;            // output row = t - LAG
     static constexpr int QP = NI <= 3 ? 4 : 8;        // psi^n ring (ages 0..2NI-3 used)
-    static constexpr int U = QP;                      // row-loop unroll
+    static constexpr int U = 8;                       // row-loop unroll
+    static constexpr int UT = QP;                     // tail block (divides U)
     static constexpr int OW = WAVE - 2 * H;           // output columns per strip
 };
 
 // Prefetch distance (rows in flight ahead of the one being consumed).
 constexpr int PF = 2;
 
-// State of one wavefront marching down rows i0..i1-1 of a 64-column strip.
-template <typename T, int NI, bool FCT, bool ABS> struct Strip {
+// State of one wavefront marching down rows i0..i1-1 of a 64-column strip
+// (quotients in fast or safe mode, see qset).
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Strip {
     using C = Cfg<NI, FCT>;
     int n0, n1, i0, i1, jj, rr;
     int64_t ld1;
-    bool out_lane, kahan;
+    bool out_lane;
+    uint64_t bad;      // fast mode: lanes whose divisors left the fast range
     const T *psi_n, *c0, *c1;
     const T *prow, *c0row, *c1row;
     T *orow;
@@ -226,18 +301,15 @@ template <typename T, int NI, bool FCT, bool ABS> struct Strip {
     T fp[PF], f0[PF], f1[PF];
     Pass<T> ps[C::NP > 0 ? C::NP : 1];
 
+    // advance the load pointers one row, wrapping at n0 (selects, not a
+    // branch, so that a row of the unrolled loop stays one basic block)
     __device__ __forceinline__ void next_row()
     {
-        if (++rr == n0) {
-            rr = 0;
-            prow = psi_n;
-            c0row = c0;
-            c1row = c1;
-        } else {
-            prow += n1;
-            c0row += n1;
-            c1row += ld1;
-        }
+        const bool wrap = ++rr == n0;
+        rr = wrap ? 0 : rr;
+        prow = wrap ? psi_n : prow + n1;
+        c0row = wrap ? c0 : c0row + n1;
+        c1row = wrap ? c1 : c1row + ld1;
     }
 
     // one row of the pipeline at loop position t (phase P = t - t_begin mod U)
@@ -260,49 +332,49 @@ template <typename T, int NI, bool FCT, bool ABS> struct Strip {
         T f0hi = pos(AT(dc0, 2, 0)) * x + neg(AT(dc0, 2, 0)) * AT(pq, C::QP, 0);
         T f1lo = pos(AT(dc1, 2, 1)) * from_left(x) + neg(AT(dc1, 2, 1)) * x;
         T f1hi = from_right(f1lo);
-        T y = donor_update(kahan, x, f0hi - f0lo, f1hi - f1lo);
+        T y = donor_update<KH>(x, f0hi - f0lo, f1hi - f1lo);
         T cn0 = AT(dc0, 2, 1), cn1 = AT(dc1, 2, 1);
 
+        // pass m = k+2 takes input row a = t - 1 - 2k (psi^n row a is 1 + 2k
+        // rows old).  On the first warm-up rows a pass works on rows outside
+        // the dependency cone of the chunk's first output row (from the
+        // zero-initialised queues); no row inside the cone reads them, and
+        // running every pass on every row keeps the row one basic block.
 #pragma unroll
         for (int k = 0; k < C::NP; k++) {
-            // pass m = k+2 takes input row a = t - 1 - 2k (psi^n row a is
-            // 1 + 2k rows old).  Its first input row inside the dependency
-            // cone of output row i0 is i0 - 2(NI - m + 1), reached at iteration
-            // i0 - 2 NI + 4 m - 5; earlier iterations of this pass are skipped
-            // (the queues then hold only rows outside the cone).
-            if (t < i0 - 2 * NI + 4 * (k + 2) - 5) break;
-            T yk = ps[k].template advance<FCT, ABS, P>(y, cn0, cn1,
-                                                       pq.v[slot<C::QP>(P, 1 + 2 * k)], kahan);
+            T yk = ps[k].template advance<FCT, ABS, KH, SAFE, P>(
+                y, cn0, cn1, pq.v[slot<C::QP>(P, 1 + 2 * k)], bad);
             cn0 = ps[k].aq0.v[slot<4>(P, 1)];
             cn1 = ps[k].aq1.v[slot<4>(P, 1)];
             y = yk;
         }
 
-        if (t - C::LAG >= i0 && t - C::LAG < i1) {
-            if (out_lane) *orow = y;
-            orow += n1;
-        }
+        const bool row_out = t - C::LAG >= i0 && t - C::LAG < i1;
+        if (out_lane && row_out) *orow = y;
+        orow += row_out ? n1 : 0;
     }
 };
 
-template <typename T, int NI, bool FCT, bool ABS, int P = 0>
-__device__ __forceinline__ void iter_block(Strip<T, NI, FCT, ABS> &st, int t)
+// iterations t .. t+N-1 (phases 0 .. N-1)
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE, int N, int P = 0>
+__device__ __forceinline__ void iter_block(Strip<T, NI, FCT, ABS, KH, SAFE> &st, int t)
 {
-    if constexpr (P < Cfg<NI, FCT>::U) {
+    if constexpr (P < N) {
         st.template iter<P>(t + P);
-        iter_block<T, NI, FCT, ABS, P + 1>(st, t);
+        iter_block<T, NI, FCT, ABS, KH, SAFE, N, P + 1>(st, t);
     }
 }
 
-template <typename T, int NI, bool FCT, bool ABS>
-__device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__ psi_n,
+// One chunk of one strip; returns true when fast mode met a divisor outside
+// its range (the rows stored are then not to be kept).
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE>
+__device__ __forceinline__ bool strip_pass(int n0, int n1, const T *__restrict__ psi_n,
                                            T *__restrict__ psi_out, const T *__restrict__ c0,
-                                           const T *__restrict__ c1, int jstrip0, int i0, int i1,
-                                           bool kahan)
+                                           const T *__restrict__ c1, int jstrip0, int i0, int i1)
 {
     using C = Cfg<NI, FCT>;
-    Strip<T, NI, FCT, ABS> st;
-    st.kahan = kahan;
+    Strip<T, NI, FCT, ABS, KH, SAFE> st;
+    st.bad = 0;
     const int lane = threadIdx.x & (WAVE - 1);
     // global column of this lane (may lie outside [0, n1) in the halo)
     const int col = jstrip0 - C::H + lane;
@@ -322,8 +394,9 @@ __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__
 #pragma unroll
     for (int k = 0; k < C::NP; k++) st.ps[k].init();
 
-    // iterations t_begin .. t_end; the loop runs whole blocks of U, so up to
-    // U-1 extra iterations at the end compute rows that are not stored
+    // iterations t_begin .. t_end; the loop runs whole blocks of U and then
+    // of UT, so up to UT-1 extra iterations at the end compute rows that are
+    // not stored (their loads wrap like every other row index)
     const int t_begin = i0 - C::LAG - 1;
     const int t_end = i1 - 1 + C::LAG;    // inclusive
     // row (mod n0) of the next row to load, and its row pointers
@@ -347,11 +420,28 @@ __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__
     st.out_lane = lane >= C::H && lane < WAVE - C::H && col < n1;
     st.orow = psi_out + (int64_t)i0 * n1 + (st.out_lane ? col : 0);
 
-    for (int t = t_begin; t <= t_end; t += C::U) iter_block<T, NI, FCT, ABS>(st, t);
+    int t = t_begin;
+    for (; t + C::U - 1 <= t_end; t += C::U) iter_block<T, NI, FCT, ABS, KH, SAFE, C::U>(st, t);
+    if constexpr (C::UT < C::U) {
+        for (; t <= t_end; t += C::UT) iter_block<T, NI, FCT, ABS, KH, SAFE, C::UT>(st, t);
+    } else {
+        if (t <= t_end) iter_block<T, NI, FCT, ABS, KH, SAFE, C::U>(st, t);
+    }
+    return st.bad != 0;
 }
 
-template <typename T, int NI, bool FCT, bool ABS>
-__global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int strips, int kahan,
+// Fast mode, then (rarely, wave-uniformly) the same chunk again in safe mode.
+template <typename T, int NI, bool FCT, bool ABS, bool KH>
+__device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__ psi_n,
+                                           T *__restrict__ psi_out, const T *__restrict__ c0,
+                                           const T *__restrict__ c1, int jstrip0, int i0, int i1)
+{
+    if (strip_pass<T, NI, FCT, ABS, KH, false>(n0, n1, psi_n, psi_out, c0, c1, jstrip0, i0, i1))
+        strip_pass<T, NI, FCT, ABS, KH, true>(n0, n1, psi_n, psi_out, c0, c1, jstrip0, i0, i1);
+}
+
+template <typename T, int NI, bool FCT, bool ABS, bool KH>
+__global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int strips,
                                                   const T *__restrict__ psi_n,
                                                   T *__restrict__ psi_out,
                                                   const T *__restrict__ c0,
@@ -362,14 +452,13 @@ __global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int st
     int strip = b % strips, chunk = b / strips;
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT, ABS>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1,
-                                kahan != 0);
+    strip_body<T, NI, FCT, ABS, KH>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1);
 }
 
-template <typename T, int NI, bool FCT, bool ABS>
+template <typename T, int NI, bool FCT, bool ABS, bool KH>
 __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__restrict__ grids,
                                                           int n_grids, int th, int n_tiles,
-                                                          int xcd_order, int kahan,
+                                                          int xcd_order,
                                                           const T *__restrict__ psi_n,
                                                           T *__restrict__ psi_out,
                                                           const T *__restrict__ c0,
@@ -399,8 +488,8 @@ __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__res
     int n0 = (int)g.n0, n1 = (int)g.n1;
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT, ABS>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi, c0 + g.off_c0,
-                                c1 + g.off_c1, strip * C::OW, i0, i1, kahan != 0);
+    strip_body<T, NI, FCT, ABS, KH>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi,
+                                    c0 + g.off_c0, c1 + g.off_c1, strip * C::OW, i0, i1);
 }
 
 // default rows per chunk (when not tuned): about two waves per SIMD, so the
@@ -415,8 +504,8 @@ int64_t rows_per_chunk(int64_t n0, int64_t strips)
     return th;
 }
 
-template <typename T, int NI, bool FCT, bool ABS>
-hipError_t launch(const Fused2DShape &sh, int kahan, const T *psi_n, T *psi_out, const T *c0,
+template <typename T, int NI, bool FCT, bool ABS, bool KH>
+hipError_t launch(const Fused2DShape &sh, const T *psi_n, T *psi_out, const T *c0,
                   const T *c1, hipStream_t s)
 {
     using C = Cfg<NI, FCT>;
@@ -425,50 +514,35 @@ hipError_t launch(const Fused2DShape &sh, int kahan, const T *psi_n, T *psi_out,
     if (th > sh.n0) th = sh.n0;
     int64_t chunks = cdiv(sh.n0, th);
     int64_t blocks = strips * chunks;
-    k_fused2d<T, NI, FCT, ABS><<<(unsigned)blocks, WAVE, 0, s>>>((int)sh.n0, (int)sh.n1, (int)th,
-                                                           (int)strips, kahan, psi_n, psi_out,
-                                                           c0, c1);
+    k_fused2d<T, NI, FCT, ABS, KH><<<(unsigned)blocks, WAVE, 0, s>>>(
+        (int)sh.n0, (int)sh.n1, (int)th, (int)strips, psi_n, psi_out, c0, c1);
     return hipGetLastError();
 }
 
-template <typename T, int NI, bool FCT, bool ABS>
+template <typename T, int NI, bool FCT, bool ABS, bool KH>
 hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, int xcd,
-                          int kahan, const T *psi_n, T *psi_out, const T *c0, const T *c1,
+                          const T *psi_n, T *psi_out, const T *c0, const T *c1,
                           hipStream_t s)
 {
-    k_fused2d_batched<T, NI, FCT, ABS><<<(unsigned)n_tiles, WAVE, 0, s>>>(
-        g, n_grids, th, n_tiles, xcd, kahan, psi_n, psi_out, c0, c1);
+    k_fused2d_batched<T, NI, FCT, ABS, KH><<<(unsigned)n_tiles, WAVE, 0, s>>>(
+        g, n_grids, th, n_tiles, xcd, psi_n, psi_out, c0, c1);
     return hipGetLastError();
 }
 
 }  // namespace
-
-bool fused2d_supported(int nd, int n_iters, unsigned opts, int has_g, int bc0, int bc1)
-{
-    if (nd != 2 || has_g || bc0 != BC_PERIODIC || bc1 != BC_PERIODIC) return false;
-    if (opts & ~(OPT_FCT | OPT_KAHAN | OPT_ABS)) return false;   // tot / iga / dfl: staged path
-    if ((opts & OPT_ABS) && n_iters > 3) return false;
-    return n_iters >= 1 && n_iters <= 4;
-}
-
-int fused2d_tile_rows() { return 64; }
-
-int fused2d_strip_cols(int n_iters, unsigned opts)
-{
-    int np = n_iters - 1;
-    int h = 1 + ((opts & OPT_FCT) ? 2 : 1) * np;
-    return WAVE - 2 * h;
-}
 
 template <typename T>
 hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
                         T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s)
 {
     if (G || sh.bc0 != BC_PERIODIC || sh.bc1 != BC_PERIODIC) return hipErrorNotSupported;
+    if (psi_n == psi_out) return hipErrorInvalidValue;   // a chunk may be recomputed (qset)
     bool fct = opts & OPT_FCT;
-    const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
+    const bool kahan = opts & OPT_KAHAN;
     const bool absf = (opts & OPT_ABS) && n_iters > 1;
-#define MP_L(NI, F, A) launch<T, NI, F, A>(sh, kahan, psi_n, psi_out, c0, c1, s)
+#define MP_L(NI, F, A)                                                                   \
+    (kahan ? launch<T, NI, F, A, true>(sh, psi_n, psi_out, c0, c1, s)                    \
+           : launch<T, NI, F, A, false>(sh, psi_n, psi_out, c0, c1, s))
     if (absf) {
         switch (n_iters * 2 + (fct ? 1 : 0)) {
         case 4: return MP_L(2, false, true);
@@ -497,11 +571,15 @@ hipError_t fused2d_batched_step(const BatchGrid *g, int n_grids, int n_tiles, in
                                 T *psi_out, const T *c0, const T *c1, hipStream_t s)
 {
     if (bc != BC_PERIODIC || th < 1) return hipErrorNotSupported;
+    if (psi_n == psi_out) return hipErrorInvalidValue;   // a chunk may be recomputed (qset)
     bool fct = opts & OPT_FCT;
-    const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
+    const bool kahan = opts & OPT_KAHAN;
     const bool absf = (opts & OPT_ABS) && n_iters > 1;
-#define MP_B(NI, F, A) \
-    launch_batched<T, NI, F, A>(g, n_grids, n_tiles, th, xcd, kahan, psi_n, psi_out, c0, c1, s)
+#define MP_B(NI, F, A)                                                                       \
+    (kahan ? launch_batched<T, NI, F, A, true>(g, n_grids, n_tiles, th, xcd, psi_n, psi_out, \
+                                               c0, c1, s)                                    \
+           : launch_batched<T, NI, F, A, false>(g, n_grids, n_tiles, th, xcd, psi_n,         \
+                                                psi_out, c0, c1, s))
     if (absf) {
         switch (n_iters * 2 + (fct ? 1 : 0)) {
         case 4: return MP_B(2, false, true);
@@ -523,17 +601,5 @@ hipError_t fused2d_batched_step(const BatchGrid *g, int n_grids, int n_tiles, in
     }
 #undef MP_B
 }
-
-template hipError_t fused2d_step<float>(const Fused2DShape &, int, unsigned, const float *, float *,
-                                        const float *, const float *, const float *, hipStream_t);
-template hipError_t fused2d_step<double>(const Fused2DShape &, int, unsigned, const double *,
-                                         double *, const double *, const double *, const double *,
-                                         hipStream_t);
-template hipError_t fused2d_batched_step<float>(const BatchGrid *, int, int, int, int, unsigned,
-                                                int, int, const float *, float *, const float *,
-                                                const float *, hipStream_t);
-template hipError_t fused2d_batched_step<double>(const BatchGrid *, int, int, int, int, unsigned,
-                                                 int, int, const double *, double *,
-                                                 const double *, const double *, hipStream_t);
 
 }  // namespace mp
