@@ -313,7 +313,9 @@ template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Str
     }
 
     // one row of the pipeline at loop position t (phase P = t - t_begin mod U)
-    template <int P> __device__ __forceinline__ void iter(int t)
+    // NPASS: corrective passes run on this row (fewer on the first warm-up
+    // rows, whose later passes would work outside the dependency cone)
+    template <int P, int NPASS> __device__ __forceinline__ void iter(int t)
     {
         constexpr int S = P % PF;
         T p_new = fp[S], c0_new = f0[S], c1_new = f1[S];
@@ -336,12 +338,9 @@ template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Str
         T cn0 = AT(dc0, 2, 1), cn1 = AT(dc1, 2, 1);
 
         // pass m = k+2 takes input row a = t - 1 - 2k (psi^n row a is 1 + 2k
-        // rows old).  On the first warm-up rows a pass works on rows outside
-        // the dependency cone of the chunk's first output row (from the
-        // zero-initialised queues); no row inside the cone reads them, and
-        // running every pass on every row keeps the row one basic block.
+        // rows old)
 #pragma unroll
-        for (int k = 0; k < C::NP; k++) {
+        for (int k = 0; k < NPASS; k++) {
             T yk = ps[k].template advance<FCT, ABS, KH, SAFE, P>(
                 y, cn0, cn1, pq.v[slot<C::QP>(P, 1 + 2 * k)], bad);
             cn0 = ps[k].aq0.v[slot<4>(P, 1)];
@@ -349,19 +348,40 @@ template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Str
             y = yk;
         }
 
-        const bool row_out = t - C::LAG >= i0 && t - C::LAG < i1;
-        if (out_lane && row_out) *orow = y;
-        orow += row_out ? n1 : 0;
+        if constexpr (NPASS == C::NP) {     // warm-up rows store nothing
+            const bool row_out = t - C::LAG >= i0 && t - C::LAG < i1;
+            if (out_lane && row_out) *orow = y;
+            orow += row_out ? n1 : 0;
+        }
     }
 };
 
-// iterations t .. t+N-1 (phases 0 .. N-1)
-template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE, int N, int P = 0>
+// iterations t .. t+N-1 with phases P0 .. P0+N-1, NPASS corrective passes
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE, int N, int P0, int NPASS,
+          int I = 0>
 __device__ __forceinline__ void iter_block(Strip<T, NI, FCT, ABS, KH, SAFE> &st, int t)
 {
-    if constexpr (P < N) {
-        st.template iter<P>(t + P);
-        iter_block<T, NI, FCT, ABS, KH, SAFE, N, P + 1>(st, t);
+    if constexpr (I < N) {
+        st.template iter<P0 + I, NPASS>(t + I);
+        iter_block<T, NI, FCT, ABS, KH, SAFE, N, P0, NPASS, I + 1>(st, t);
+    }
+}
+
+// Warm-up of a chunk (iterations relative to t_begin).  Pass k's first input
+// row inside the dependency cone of the chunk's first output row i0 is
+// i0 - 2(NI - k - 1), reached at relative iteration 4k + 3; before that the
+// pass would work on rows no output reads.  So relative iterations 0..2 run
+// the donor pass only, and each following group of four runs one corrective
+// pass more (stage K: iterations 4K-1 .. 4K+2, K passes), all in straight
+// code; from relative iteration 4 NP - 1 on every pass runs.
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE, int K = 0>
+__device__ __forceinline__ void warm_up(Strip<T, NI, FCT, ABS, KH, SAFE> &st, int t_begin)
+{
+    constexpr int NP = Cfg<NI, FCT>::NP;
+    if constexpr (K < NP) {
+        constexpr int start = K == 0 ? 0 : 4 * K - 1, len = K == 0 ? 3 : 4;
+        iter_block<T, NI, FCT, ABS, KH, SAFE, len, start, K>(st, t_begin + start);
+        warm_up<T, NI, FCT, ABS, KH, SAFE, K + 1>(st, t_begin);
     }
 }
 
@@ -420,12 +440,17 @@ __device__ __forceinline__ bool strip_pass(int n0, int n1, const T *__restrict__
     st.out_lane = lane >= C::H && lane < WAVE - C::H && col < n1;
     st.orow = psi_out + (int64_t)i0 * n1 + (st.out_lane ? col : 0);
 
-    int t = t_begin;
-    for (; t + C::U - 1 <= t_end; t += C::U) iter_block<T, NI, FCT, ABS, KH, SAFE, C::U>(st, t);
+    // warm-up (W iterations; a chunk has th + 4 NI - 1 > W), then the full
+    // rows in blocks of U and UT whose phases continue from W
+    constexpr int W = C::NP == 0 ? 0 : 4 * C::NP - 1;
+    warm_up<T, NI, FCT, ABS, KH, SAFE>(st, t_begin);
+    int t = t_begin + W;
+    for (; t + C::U - 1 <= t_end; t += C::U)
+        iter_block<T, NI, FCT, ABS, KH, SAFE, C::U, W, C::NP>(st, t);
     if constexpr (C::UT < C::U) {
-        for (; t <= t_end; t += C::UT) iter_block<T, NI, FCT, ABS, KH, SAFE, C::UT>(st, t);
+        for (; t <= t_end; t += C::UT) iter_block<T, NI, FCT, ABS, KH, SAFE, C::UT, W, C::NP>(st, t);
     } else {
-        if (t <= t_end) iter_block<T, NI, FCT, ABS, KH, SAFE, C::U>(st, t);
+        if (t <= t_end) iter_block<T, NI, FCT, ABS, KH, SAFE, C::U, W, C::NP>(st, t);
     }
     return st.bad != 0;
 }
