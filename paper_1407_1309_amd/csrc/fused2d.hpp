@@ -70,52 +70,66 @@ template <bool KAHAN, typename T> __device__ __forceinline__ T donor_update(T x,
 // with r the hardware reciprocal refined by one Newton step (FP64: within 18
 // ulp of the rounded quotient; FP32: the residual-corrected form), for every
 // lane and with no branch, so each row stays one long straight-line region
-// for the instruction scheduler.  That is accurate only for divisors that are
-// zero (whose quotients every caller discards) or normal, and in FP64 below
-// 2^1000 in magnitude; fast mode records, wave-uniformly, whether any
-// divisor fell outside that range.  A wave with such a record recomputes its
-// chunk in safe mode, rewriting every row it stored (the kernel reads only
-// psi^n and the advector, so the redo sees the same inputs).  Safe mode
-// decides lane by lane: the fast quotient where the divisor is in range, the
-// IEEE quotient elsewhere.  A quotient's value therefore depends only on its
-// operands, never on which lanes share its wave or where its chunk begins, so
-// every tiling (and the batched kernel) gives the same bits.
-__device__ __forceinline__ bool q_in_range(double d)
+// for the instruction scheduler.  `keep` marks the quotients the caller uses
+// (a zero divisor's, or a limiter coefficient's with no in- or out-flux, is
+// replaced by a constant).  A kept quotient is in range when
+//   FP64: the hardware reciprocal of the divisor is a normal number (so the
+//         divisor is neither 2^1022 or more in magnitude, whose reciprocal
+//         is subnormal, nor a subnormal the reciprocal cannot invert;
+//         one class test of r replaces tests of the divisor's class and
+//         magnitude),
+//   FP32: the divisor is normal or zero (one class test of the divisor, for
+//         kept and discarded quotients alike, which is cheaper there than
+//         combining it with the caller's test).
+// Fast mode records, wave-uniformly, whether any kept quotient was out of
+// range.  A wave with such a record recomputes its chunk in safe mode,
+// rewriting every row it stored (the kernel reads only psi^n and the
+// advector, so the redo sees the same inputs).  Safe mode decides lane by
+// lane with the same test: the fast quotient in range, the IEEE quotient
+// elsewhere.  A kept quotient's value therefore depends only on its
+// operands, never on which lanes share its wave or where its chunk begins,
+// so every tiling (and the batched kernel) gives the same bits.
+__device__ __forceinline__ double q_rcp(double d) { return __builtin_amdgcn_rcp(d); }
+__device__ __forceinline__ float q_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ bool q_in_range(double d, double r)
 {
-    return __builtin_amdgcn_class(d, 0x168) && fabs(d) < 0x1p1000;   // +-normal or +-zero
+    return __builtin_amdgcn_class(r, 0x108);     // r is +-normal
 }
-__device__ __forceinline__ bool q_in_range(float d)
+__device__ __forceinline__ bool q_in_range(float d, float)
 {
-    return __builtin_amdgcn_classf(d, 0x168);
+    return __builtin_amdgcn_classf(d, 0x168);    // d is +-normal or +-zero
 }
-__device__ __forceinline__ double q_fast(double n, double d)
+__device__ __forceinline__ double q_fast(double n, double d, double r)
 {
-    double r = __builtin_amdgcn_rcp(d);
     r = fma(fma(-d, r, 1.0), r, r);
     return n * r;
 }
-__device__ __forceinline__ float q_fast(float n, float d)
+__device__ __forceinline__ float q_fast(float n, float d, float r)
 {
-    const float r = __builtin_amdgcn_rcpf(d);
     const float q0 = n * r;
     return fmaf(fmaf(-d, q0, n), r, q0);
 }
 
 template <bool SAFE, int K, typename T>
-__device__ __forceinline__ void qset(const T (&n)[K], const T (&d)[K], T (&q)[K], uint64_t &bad)
+__device__ __forceinline__ void qset(const T (&n)[K], const T (&d)[K], const bool (&keep)[K],
+                                     T (&q)[K], uint64_t &bad)
 {
-    if constexpr (SAFE) {
+    bool ok = true;
 #pragma unroll
-        for (int k = 0; k < K; k++) q[k] = q_in_range(d[k]) ? q_fast(n[k], d[k]) : n[k] / d[k];
-    } else {
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            ok = ok && q_in_range(d[k]);
-            q[k] = q_fast(n[k], d[k]);
+    for (int k = 0; k < K; k++) {
+        const T r = q_rcp(d[k]);
+        const bool in = q_in_range(d[k], r);
+        if constexpr (SAFE) {
+            q[k] = in ? q_fast(n[k], d[k], r) : n[k] / d[k];
+        } else {
+            if constexpr (sizeof(T) == 8)
+                ok = ok & (in | !keep[k]);     // bitwise: lane masks, no short circuit
+            else
+                ok = ok && in;
+            q[k] = q_fast(n[k], d[k], r);
         }
-        bad |= __builtin_amdgcn_ballot_w64(!ok);
     }
+    if constexpr (!SAFE) bad |= __builtin_amdgcn_ballot_w64(!ok);
 }
 
 // ---- register row-queues ------------------------------------------------
@@ -191,9 +205,10 @@ template <typename T> struct Pass {
             num[3] = a + b - e - f;
             den[3] = a + b + e + f;
         }
-        qset<SAFE, 4>(num, den, fr, bad);
+        const bool keep[4] = {den[0] != T(0), den[1] != T(0), den[2] != T(0), den[3] != T(0)};
+        qset<SAFE, 4>(num, den, keep, fr, bad);
 #pragma unroll
-        for (int k = 0; k < 4; k++) fr[k] = den[k] == T(0) ? T(0) : fr[k];
+        for (int k = 0; k < 4; k++) fr[k] = keep[k] ? fr[k] : T(0);
         T v0;
         {
             T u = AT(c0q, 2, 0);
@@ -230,9 +245,10 @@ template <typename T> struct Pass {
                     (pos(v1lo) * AT(xl, 4, 1) - neg(v1hi) * AT(xr, 2, 1));
             T fout = (pos(v0hi) * xc - neg(v0lo) * xc) + (pos(v1hi) * xc - neg(v1lo) * xc);
             T bn[2] = {mx - xc, xc - mn}, bdv[2] = {fin, fout}, bq[2];
-            qset<SAFE, 2>(bn, bdv, bq, bad);
-            T bu = fin > T(0) ? bq[0] : T(1);
-            T bd = fout > T(0) ? bq[1] : T(1);
+            const bool keep[2] = {fin > T(0), fout > T(0)};
+            qset<SAFE, 2>(bn, bdv, keep, bq, bad);
+            T bu = keep[0] ? bq[0] : T(1);
+            T bd = keep[1] ? bq[1] : T(1);
             AT(buq, 2, 0) = bu;
             AT(bdq, 2, 0) = bd;
             // limited V1 at row a-1, wall j: L = (a-1, j-1), R = (a-1, j)
