@@ -87,23 +87,22 @@ template <typename T> __device__ inline void aadd(T *a, int64_t k, T v)
 
 template <typename T> __device__ inline T sgnv(T u) { return T((u > T(0)) - (u < T(0))); }
 
-template <typename T> __device__ inline T fracv(bool iga, T num, T den, T m)
-{
-    if (iga) return num / m;
-    return den == T(0) ? T(0) : num / den;
-}
-
-// d frac / d num, d frac / d den
-template <typename T> __device__ inline void frac_d(bool iga, T num, T den, T m, T &dn, T &dd)
+// psi-fraction num / den (num / m under iga; 0 for a zero den) and its
+// derivatives d/d num and d/d den, from one reciprocal of den
+template <typename T>
+__device__ inline void frac_vd(bool iga, T num, T den, T m, T &v, T &dn, T &dd)
 {
     if (iga) {
+        v = num / m;
         dn = T(1) / m;
         dd = T(0);
     } else if (den == T(0)) {
-        dn = dd = T(0);
+        v = dn = dd = T(0);
     } else {
-        dn = T(1) / den;
-        dd = -num / (den * den);
+        const T r = T(1) / den;
+        v = num * r;
+        dn = r;
+        dd = -v * r;
     }
 }
 
@@ -332,15 +331,16 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
     T u = c[d][wi(g, d, p)];
     T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
     T Gb = T(0.5) * (GL + GR);
+    const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
     int64_t kL = ci(g, L), kR = ci(g, R);
     T xL = x[kL], xR = x[kR];
     T ub = T(0), fn, fd;
 
     T nA = xR - xL, dA = xR + xL;
-    T A = fracv(iga, nA, dA, T(2));
-    frac_d(iga, nA, dA, T(2), fn, fd);
-    ub += (sgnv(u) - T(2) * u / Gb) * A * vb;
-    T Ab = (fabs(u) - u * u / Gb) * vb;
+    T A;
+    frac_vd(iga, nA, dA, T(2), A, fn, fd);
+    ub += (sgnv(u) - T(2) * u * iGb) * A * vb;
+    T Ab = (fabs(u) - u * u * iGb) * vb;
     aadd(xb, kR, (fn + fd) * Ab);
     aadd(xb, kL, (-fn + fd) * Ab);
 
@@ -353,11 +353,11 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
         int64_t kRm = ci(g, sh1(R, o, -1)), kLm = ci(g, sh1(L, o, -1));
         T a = x[kRp], b = x[kLp], ee = x[kRm], f = x[kLm];
         T nB = a + b - ee - f, dB = a + b + ee + f;
-        T Bv = fracv(iga, nB, dB, T(4));
-        frac_d(iga, nB, dB, T(4), fn, fd);
-        ub += T(-0.5) * cbar[o] / Gb * Bv * vb;
-        cbar_b[o] += T(-0.5) * u / Gb * Bv * vb;
-        T Bb = T(-0.5) * u * cbar[o] / Gb * vb;
+        T Bv;
+        frac_vd(iga, nB, dB, T(4), Bv, fn, fd);
+        ub += T(-0.5) * cbar[o] * iGb * Bv * vb;
+        cbar_b[o] += T(-0.5) * u * iGb * Bv * vb;
+        T Bb = T(-0.5) * u * cbar[o] * iGb * vb;
         aadd(xb, kRp, (fn + fd) * Bb);
         aadd(xb, kLp, (fn + fd) * Bb);
         aadd(xb, kRm, (-fn + fd) * Bb);
@@ -367,10 +367,10 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
         int64_t kR2 = ci(g, sh1(R, d, 1)), kL2 = ci(g, sh1(L, d, -1));
         T xR2 = x[kR2], xL2 = x[kL2];
         T nD = xR2 - xR - xL + xL2, dD = xR2 + xR + xL + xL2;
-        T Dv = fracv(iga, nD, dD, T(4));
-        frac_d(iga, nD, dD, T(4), fn, fd);
-        T cD = (T(3) * u * fabs(u) / Gb - T(2) * u * u * u / (Gb * Gb) - u) / T(3);
-        ub += (T(6) * fabs(u) / Gb - T(6) * u * u / (Gb * Gb) - T(1)) / T(3) * Dv * vb;
+        T Dv;
+        frac_vd(iga, nD, dD, T(4), Dv, fn, fd);
+        T cD = (T(3) * u * fabs(u) * iGb - T(2) * u * u * u * iGb2 - u) / T(3);
+        ub += (T(6) * fabs(u) * iGb - T(6) * u * u * iGb2 - T(1)) / T(3) * Dv * vb;
         T Db = cD * vb;
         aadd(xb, kR2, (fn + fd) * Db);
         aadd(xb, kR, (-fn + fd) * Db);
@@ -382,11 +382,11 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
             int64_t kRm = ci(g, sh1(R, o, -1)), kLm = ci(g, sh1(L, o, -1));
             T a = x[kRp], b = x[kLp], ee = x[kRm], f = x[kLm];
             T nE = a - b - ee + f, dE = a + b + ee + f;
-            T Ev = fracv(iga, nE, dE, T(4));
-            frac_d(iga, nE, dE, T(4), fn, fd);
-            T cE = fabs(u) * cbar[o] / Gb - T(2) * u * u * cbar[o] / (Gb * Gb);
-            ub += (sgnv(u) * cbar[o] / Gb - T(4) * u * cbar[o] / (Gb * Gb)) * Ev * vb;
-            cbar_b[o] += (fabs(u) / Gb - T(2) * u * u / (Gb * Gb)) * Ev * vb;
+            T Ev;
+            frac_vd(iga, nE, dE, T(4), Ev, fn, fd);
+            T cE = fabs(u) * cbar[o] * iGb - T(2) * u * u * cbar[o] * iGb2;
+            ub += (sgnv(u) * cbar[o] * iGb - T(4) * u * cbar[o] * iGb2) * Ev * vb;
+            cbar_b[o] += (fabs(u) * iGb - T(2) * u * u * iGb2) * Ev * vb;
             T Eb = cE * vb;
             aadd(xb, kRp, (fn + fd) * Eb);
             aadd(xb, kLp, (-fn + fd) * Eb);
@@ -408,9 +408,9 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
                 num += vpp - vmp - vpm + vmm;
                 den += vpp + vmp + vpm + vmm;
             }
-            T Tv = fracv(iga, num, den, T(8));
-            frac_d(iga, num, den, T(8), fn, fd);
-            T k = -(T(2) / T(3)) / (Gb * Gb);
+            T Tv;
+            frac_vd(iga, num, den, T(8), Tv, fn, fd);
+            T k = -(T(2) / T(3)) * iGb2;
             ub += k * cbar[o1] * cbar[o2] * Tv * vb;
             cbar_b[o1] += k * u * cbar[o2] * Tv * vb;
             cbar_b[o2] += k * u * cbar[o1] * Tv * vb;
@@ -473,13 +473,14 @@ k_pseudo_adj2t(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, cons
             T u = c[d][wi(g, d, p)];
             T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
             T Gb = T(0.5) * (GL + GR);
+            const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
             T xL = x[ci(g, L)], xR = x[ci(g, R)];
             T ub = T(0), fn, fd;
             T nA = xR - xL, dA = xR + xL;
-            T A = fracv(iga, nA, dA, T(2));
-            frac_d(iga, nA, dA, T(2), fn, fd);
-            ub += (sgnv(u) - T(2) * u / Gb) * A * vb;
-            T Ab = (fabs(u) - u * u / Gb) * vb;
+            T A;
+            frac_vd(iga, nA, dA, T(2), A, fn, fd);
+            ub += (sgnv(u) - T(2) * u * iGb) * A * vb;
+            T Ab = (fabs(u) - u * u * iGb) * vb;
             atomicAdd(&XB[bx(R.v[0], R.v[1])], (fn + fd) * Ab);
             atomicAdd(&XB[bx(L.v[0], L.v[1])], (-fn + fd) * Ab);
             I3 Lo = sh1(L, o, 1), Ro = sh1(R, o, 1);
@@ -488,11 +489,11 @@ k_pseudo_adj2t(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, cons
             I3 Rp = sh1(R, o, 1), Lp = sh1(L, o, 1), Rm = sh1(R, o, -1), Lm = sh1(L, o, -1);
             T a = x[ci(g, Rp)], b = x[ci(g, Lp)], ee = x[ci(g, Rm)], f = x[ci(g, Lm)];
             T nB = a + b - ee - f, dB = a + b + ee + f;
-            T Bv = fracv(iga, nB, dB, T(4));
-            frac_d(iga, nB, dB, T(4), fn, fd);
-            ub += T(-0.5) * cbar / Gb * Bv * vb;
-            T cbar_b = T(-0.5) * u / Gb * Bv * vb;
-            T Bb = T(-0.5) * u * cbar / Gb * vb;
+            T Bv;
+            frac_vd(iga, nB, dB, T(4), Bv, fn, fd);
+            ub += T(-0.5) * cbar * iGb * Bv * vb;
+            T cbar_b = T(-0.5) * u * iGb * Bv * vb;
+            T Bb = T(-0.5) * u * cbar * iGb * vb;
             atomicAdd(&XB[bx(Rp.v[0], Rp.v[1])], (fn + fd) * Bb);
             atomicAdd(&XB[bx(Lp.v[0], Lp.v[1])], (fn + fd) * Bb);
             atomicAdd(&XB[bx(Rm.v[0], Rm.v[1])], (-fn + fd) * Bb);
@@ -597,14 +598,16 @@ __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
     T Gi = G ? G[t] : T(1);
     T finb = T(0), foutb = T(0), mxb = T(0), mnb = T(0), xib = T(0);
     if (fin > T(0) && bu_b != T(0)) {
-        mxb += Gi / fin * bu_b;
-        xib -= Gi / fin * bu_b;
-        finb -= Gi * (mx - xi) / (fin * fin) * bu_b;
+        const T r = T(1) / fin, gq = Gi * r * bu_b;
+        mxb += gq;
+        xib -= gq;
+        finb -= (mx - xi) * r * gq;
     }
     if (fout > T(0) && bd_b != T(0)) {
-        xib += Gi / fout * bd_b;
-        mnb -= Gi / fout * bd_b;
-        foutb -= Gi * (xi - mn) / (fout * fout) * bd_b;
+        const T r = T(1) / fout, gq = Gi * r * bd_b;
+        xib += gq;
+        mnb -= gq;
+        foutb -= (xi - mn) * r * gq;
     }
     aadd(smx ? xb : pnb, amx, mxb);
     aadd(smn ? xb : pnb, amn, mnb);
