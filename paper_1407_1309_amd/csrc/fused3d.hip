@@ -44,16 +44,32 @@ struct G3 {
 // ---- donor-cell pass ----------------------------------------------------
 constexpr int DONOR_PLANES = 16;   // planes per thread column
 
+// Blocks of 64 (k) x 4 (j) columns over DONOR_PLANES planes; a 1-D grid of
+// nblk blocks.  The hardware deals block b to XCD b % 8: block b takes tile
+// number x * (nblk / 8) + ... (x = b % 8), so each XCD runs a contiguous
+// range of tiles, k fastest, then j, and the rows a tile reads above and
+// below its own (the in-plane neighbours) are mostly read by tiles on the
+// same XCD, through its L2.
 template <typename T, bool HAS_G>
-__global__ void __launch_bounds__(256) k_donor3d(G3 g, int kahan, const T *__restrict__ x,
+__global__ void __launch_bounds__(256) k_donor3d(G3 g, int kahan, int tiles_k, int tiles_j,
+                                                 int nblk, const T *__restrict__ x,
                                                  const T *__restrict__ c0,
                                                  const T *__restrict__ c1,
                                                  const T *__restrict__ c2,
                                                  const T *__restrict__ G, T *__restrict__ y)
 {
-    const int k = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int i0 = blockIdx.z * DONOR_PLANES;
+    int b;
+    {
+        const int xcd = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
+        b = xcd * per + (xcd < rem ? xcd : rem) + (blockIdx.x >> 3);
+    }
+    const int tk = b % tiles_k;
+    b /= tiles_k;
+    const int tj = b % tiles_j;
+    const int ch = b / tiles_j;
+    const int k = tk * 64 + (threadIdx.x & 63);
+    const int j = tj * 4 + (threadIdx.x >> 6);
+    const int i0 = ch * DONOR_PLANES;
     const int i1 = min(i0 + DONOR_PLANES, g.n0);
     if (k >= g.n2 || j >= g.n1) return;
     const int64_t pl = (int64_t)g.n1 * g.n2;                 // cell / c0 plane
@@ -426,13 +442,17 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
                         hipStream_t s)
 {
     G3 g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
-    dim3 gd((unsigned)cdiv(g.n2, 64), (unsigned)cdiv(g.n1, 4), (unsigned)cdiv(g.n0, DONOR_PLANES));
+    const int dk = (int)cdiv(g.n2, 64), dj = (int)cdiv(g.n1, 4);
+    const int64_t dblk = (int64_t)dk * dj * cdiv(g.n0, DONOR_PLANES);
+    if (dblk > INT32_MAX) return hipErrorInvalidValue;
     T *y1 = (n_iters == 1) ? psi_out : y1buf;
     const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
     if (G)
-        k_donor3d<T, true><<<gd, 256, 0, s>>>(g, kahan, psi_n, c0, c1, c2, G, y1);
+        k_donor3d<T, true><<<(unsigned)dblk, 256, 0, s>>>(g, kahan, dk, dj, (int)dblk, psi_n, c0,
+                                                          c1, c2, G, y1);
     else
-        k_donor3d<T, false><<<gd, 256, 0, s>>>(g, kahan, psi_n, c0, c1, c2, G, y1);
+        k_donor3d<T, false><<<(unsigned)dblk, 256, 0, s>>>(g, kahan, dk, dj, (int)dblk, psi_n, c0,
+                                                           c1, c2, G, y1);
     if (n_iters == 1) return hipGetLastError();
     constexpr int TL = TileL<T>::v;
     int tiles_k = (g.n2 + TL - 2 * HALO - 1) / (TL - 2 * HALO);
