@@ -776,7 +776,14 @@ int sw_run(mpdata_plan *plan, void *h, void *const q[3], void *h_prev, void *con
         e = mp::sw_force_launch<T>(plan->g, (const T *)h, (T *)h_prev, qq, qp, grav, sp, dt, 1,
                                    plan->stream);
         if (e != hipSuccess) return hip_fail(e, "shallow-water forcing launch");
-        int rc = mpdata_step(plan, h, nullptr, cc[0], cc[1], cc[2], 1);
+        // the depth: the forcing launch above copied level n into h_prev
+        // and left h unchanged, so the step reads h_prev and writes h (no
+        // copy into the workspace and back); the LDS-resident 1-D kernel
+        // steps in place through mpdata_step
+        int rc = use_resident(plan)
+                     ? mpdata_step(plan, h, nullptr, cc[0], cc[1], cc[2], 1)
+                     : one_step<T>(plan, (const T *)h_prev, (T *)h, nullptr, cc[0], cc[1], cc[2],
+                                   step_path(plan), false);
         if (rc) return rc;
         for (int d = 0; d < nd; d++) {
             rc = mpdata_step(plan, qq[d], nullptr, cc[0], cc[1], cc[2], 1);
