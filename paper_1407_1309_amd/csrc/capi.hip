@@ -772,21 +772,35 @@ int sw_run(mpdata_plan *plan, void *h, void *const q[3], void *h_prev, void *con
         // advector at n+1/2 from levels n and n-1
         hipError_t e = vip_run<T>(plan, qc, h, qpc, h_prev, dt, sp, eps, c);
         if (e != hipSuccess) return hip_fail(e, "prognosed-velocity launch");
-        // level n becomes the previous level; explicit half of the forcing
-        e = mp::sw_force_launch<T>(plan->g, (const T *)h, (T *)h_prev, qq, qp, grav, sp, dt, 1,
-                                   plan->stream);
-        if (e != hipSuccess) return hip_fail(e, "shallow-water forcing launch");
-        // the depth: the forcing launch above copied level n into h_prev
-        // and left h unchanged, so the step reads h_prev and writes h (no
-        // copy into the workspace and back); the LDS-resident 1-D kernel
-        // steps in place through mpdata_step
-        int rc = use_resident(plan)
-                     ? mpdata_step(plan, h, nullptr, cc[0], cc[1], cc[2], 1)
-                     : one_step<T>(plan, (const T *)h_prev, (T *)h, nullptr, cc[0], cc[1], cc[2],
-                                   step_path(plan), false);
-        if (rc) return rc;
-        for (int d = 0; d < nd; d++) {
-            rc = mpdata_step(plan, qq[d], nullptr, cc[0], cc[1], cc[2], 1);
+        int rc;
+        if (use_resident(plan)) {
+            // the LDS-resident 1-D kernel steps in place: level n becomes the
+            // previous level and the explicit half of the forcing is added in
+            // place, then every field is stepped
+            e = mp::sw_force_launch<T>(plan->g, (const T *)h, (T *)h_prev, qq, qp, grav, sp, dt,
+                                       1, plan->stream);
+            if (e != hipSuccess) return hip_fail(e, "shallow-water forcing launch");
+            rc = mpdata_step(plan, h, nullptr, cc[0], cc[1], cc[2], 1);
+            for (int d = 0; d < nd && !rc; d++)
+                rc = mpdata_step(plan, qq[d], nullptr, cc[0], cc[1], cc[2], 1);
+            if (rc) return rc;
+        } else {
+            // per momentum component: level n saved to q_prev, the explicit
+            // half of the forcing written to the workspace's alternate buffer,
+            // the step from there into q[d] (h still at level n throughout);
+            // the first launch also saves h to h_prev, from which the depth
+            // is then stepped into h.  No field is copied into the workspace.
+            T *alt = (T *)plan->L.psi_alt;
+            const int path = step_path(plan);
+            for (int d = 0; d < nd; d++) {
+                e = mp::sw_force1_launch<T>(plan->g, d, (const T *)h, d == 0 ? (T *)h_prev : nullptr,
+                                            qq[d], qp[d], alt, grav, sp, dt, plan->stream);
+                if (e != hipSuccess) return hip_fail(e, "shallow-water forcing launch");
+                rc = one_step<T>(plan, alt, qq[d], nullptr, cc[0], cc[1], cc[2], path, false);
+                if (rc) return rc;
+            }
+            rc = one_step<T>(plan, (const T *)h_prev, (T *)h, nullptr, cc[0], cc[1], cc[2], path,
+                             false);
             if (rc) return rc;
         }
         // forcing at n+1 from the advected depth

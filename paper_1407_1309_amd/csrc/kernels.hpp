@@ -151,5 +151,10 @@ template <typename T>
 hipError_t sw_force_launch(const Geom &g, const T *h, T *h_prev, T *const q[3],
                            T *const q_prev[3], double grav, const double dx[3], double dt,
                            int save, hipStream_t s);
+// One momentum component's save-phase forcing written to `out` (q kept at
+// level n and copied to q_prev; h copied to h_prev when h_prev is not NULL).
+template <typename T>
+hipError_t sw_force1_launch(const Geom &g, int d, const T *h, T *h_prev, const T *q, T *q_prev,
+                            T *out, double grav, const double dx[3], double dt, hipStream_t s);
 
 }  // namespace mp

@@ -86,6 +86,34 @@ __global__ void k_sw_force(Geom g, const T *__restrict__ h, T *__restrict__ h_pr
     }
 }
 
+// The save-phase forcing of one momentum component d written elsewhere: out
+// = q + (dt/2)(-g h dh/dx_d) (the same expressions as above), q itself left
+// at level n and copied to qp; h_prev, when given, receives h.  The step
+// then advects out into q, with no copy of q into the workspace.
+template <typename T>
+__global__ void k_sw_force1(Geom g, int d, const T *__restrict__ h, T *__restrict__ h_prev,
+                            const T *__restrict__ q, T *__restrict__ qp, T *__restrict__ out,
+                            T ngrav, T tdx, T half_dt)
+{
+    const int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+    const int64_t M = e[0] * e[1] * e[2];
+    const int64_t st[3] = {e[1] * e[2], e[2], 1};
+    for (int64_t t = (int64_t)blockIdx.x * SB + threadIdx.x; t < M;
+         t += (int64_t)gridDim.x * SB) {
+        int v[3];
+        unflat3(t, e, v);
+        const T hc = h[t];
+        if (h_prev) h_prev[t] = hc;
+        const int64_t base = t - (int64_t)v[d] * st[d];
+        const T hp = h[base + map_cell(v[d] + 1, e[d], g.bc[d]) * st[d]];
+        const T hm = h[base + map_cell(v[d] - 1, e[d], g.bc[d]) * st[d]];
+        const T f = ngrav * hc * (hp - hm) / tdx;
+        const T qc = q[t];
+        qp[t] = qc;
+        out[t] = qc + half_dt * f;
+    }
+}
+
 unsigned blocks_for(int64_t n)
 {
     int64_t b = cdiv(n, SB);
@@ -127,6 +155,17 @@ hipError_t sw_force_launch(const Geom &g, const T *h, T *h_prev, T *const q[3],
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t sw_force1_launch(const Geom &g, int d, const T *h, T *h_prev, const T *q, T *q_prev,
+                            T *out, double grav, const double dx[3], double dt, hipStream_t s)
+{
+    if (d < 0 || d >= g.nd || !q || !q_prev || !out) return hipErrorInvalidValue;
+    const int64_t M = g.n[0] * g.n[1] * g.n[2];
+    k_sw_force1<T><<<blocks_for(M), SB, 0, s>>>(g, d, h, h_prev, q, q_prev, out, (T)(-grav),
+                                                (T)(2.0 * dx[d]), (T)(0.5 * dt));
+    return hipGetLastError();
+}
+
 template hipError_t vip_launch<float>(const Geom &, const float *const[3], const float *,
                                       const float *const[3], const float *, double,
                                       const double[3], float *const[3], hipStream_t);
@@ -139,5 +178,11 @@ template hipError_t sw_force_launch<float>(const Geom &, const float *, float *,
 template hipError_t sw_force_launch<double>(const Geom &, const double *, double *,
                                             double *const[3], double *const[3], double,
                                             const double[3], double, int, hipStream_t);
+template hipError_t sw_force1_launch<float>(const Geom &, int, const float *, float *,
+                                            const float *, float *, float *, double,
+                                            const double[3], double, hipStream_t);
+template hipError_t sw_force1_launch<double>(const Geom &, int, const double *, double *,
+                                             const double *, double *, double *, double,
+                                             const double[3], double, hipStream_t);
 
 }  // namespace mp
