@@ -240,8 +240,11 @@ int mpdata_courant_max(mpdata_plan *plan, const void *g, const void *c0,
  * constant).  lambda_T = dJ/dpsi_T.  grad_psi0 and grad_c0..grad_c2
  * (NULL for d >= n_dims) are overwritten.  The forward trajectory is kept
  * only every ckpt_every steps (1 <= ckpt_every <= n_steps) and recomputed in
- * between; memory for the checkpoints comes from the plan's workspace, sized
- * by mpdata_adj_workspace_bytes.  Waits for completion.  Periodic walls:
+ * between, one segment at a time, keeping that segment's states and per-pass
+ * records; memory for the checkpoints and the segment comes from the plan's
+ * workspace, sized by mpdata_adj_workspace_bytes (it grows with ckpt_every
+ * as about 1 + 7 (n_iters - 1) cell fields per step of a segment in 2-D,
+ * with the limiter).  Waits for completion.  Periodic walls:
  * the gradient of the shared wall 0 / wall n_d is returned in entry 0, and
  * entry n_d is zero.
  * Derivatives at non-differentiable points: d[u]+/du = 1 only for u > 0,

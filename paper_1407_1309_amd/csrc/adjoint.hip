@@ -745,7 +745,10 @@ int64_t nwalls(const Geom &g, int d)
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
-// workspace carving for the adjoint (shared by sizing and use)
+// workspace carving for the adjoint (shared by sizing and use).  The pass
+// records (X, V, W, bu, bd) are kept for every step of a segment: slot k
+// holds step s0 + k's, at a fixed stride from slot 0; select(k) points the
+// record pointers at slot k.
 template <typename T> struct AdjWs {
     T *ck;          // checkpoints
     T *seg;         // states of one segment
@@ -757,6 +760,24 @@ template <typename T> struct AdjWs {
     T *Ab[3], *Vb[3], *Cb[3];
     T *tmp;         // output of a recomputed step
     size_t bytes;
+    // slot 0 of the records and the distance between slots (elements)
+    T *X0[8], *V0[8][3], *W0[8][3], *bu0[8], *bd0[8];
+    size_t rec_stride;
+    int nslots;
+
+    void select(int k)
+    {
+        auto at = [&](T *b) -> T * { return b ? b + (size_t)k * rec_stride : nullptr; };
+        for (int p = 0; p < 8; p++) {
+            X[p] = at(X0[p]);
+            bu[p] = at(bu0[p]);
+            bd[p] = at(bd0[p]);
+            for (int d = 0; d < 3; d++) {
+                V[p][d] = at(V0[p][d]);
+                W[p][d] = at(W0[p][d]);
+            }
+        }
+    }
 };
 
 template <typename T>
@@ -774,21 +795,27 @@ AdjWs<T> carve_adj(const Geom &g, int n_iters, bool fct, int n_steps, int ckpt, 
     w.ck = take((size_t)N * nck);
     w.seg = take((size_t)N * ckpt);
     for (int p = 0; p < 8; p++) {
-        w.X[p] = nullptr;
-        w.bu[p] = w.bd[p] = nullptr;
-        for (int d = 0; d < 3; d++) w.V[p][d] = w.W[p][d] = nullptr;
+        w.X0[p] = nullptr;
+        w.bu0[p] = w.bd0[p] = nullptr;
+        for (int d = 0; d < 3; d++) w.V0[p][d] = w.W0[p][d] = nullptr;
     }
+    const size_t rec_begin = off;
     for (int p = 1; p < n_iters; p++) {
-        w.X[p] = take(N);
+        w.X0[p] = take(N);
         for (int d = 0; d < g.nd; d++) {
-            w.V[p][d] = take(nwalls(g, d));
-            w.W[p][d] = fct ? take(nwalls(g, d)) : w.V[p][d];
+            w.V0[p][d] = take(nwalls(g, d));
+            w.W0[p][d] = fct ? take(nwalls(g, d)) : w.V0[p][d];
         }
         if (fct) {
-            w.bu[p] = take(N);
-            w.bd[p] = take(N);
+            w.bu0[p] = take(N);
+            w.bd0[p] = take(N);
         }
     }
+    // every take is a multiple of 256 bytes, hence of sizeof(T)
+    w.rec_stride = (off - rec_begin) / sizeof(T);
+    w.nslots = ckpt < n_steps ? ckpt : (n_steps > 0 ? n_steps : 1);
+    off += (off - rec_begin) * (size_t)(w.nslots - 1);
+    w.select(0);
     w.yb = take(N);
     w.xb = take(N);
     w.pnb = take(N);
@@ -878,8 +905,9 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
     return hipGetLastError();
 }
 
-// reverse of one step: w.yb = dJ/dpsi_{n+1} on entry, dJ/dpsi_n on exit;
-// w.Cb accumulates dJ/dc
+// reverse of one step from its pass records (the selected slot of w, written
+// by record_step from the same psi_n): w.yb = dJ/dpsi_{n+1} on entry,
+// dJ/dpsi_n on exit; w.Cb accumulates dJ/dc
 template <typename T>
 hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStream_t s)
 {
@@ -888,8 +916,7 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
     const int n = a.n_iters;
     const int64_t N = ncells(g);
     const unsigned cb = (unsigned)cdiv(N, B);
-    hipError_t e = record_step<T>(a, w, psi_n, nullptr, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     // Buffers whose first writer in a pass assigns need no clearing: the
     // 2-D donor transpose writes xb (and, in the last pass, the advector
     // adjoint); the limiter transpose writes Vb.  The entries of a periodic
@@ -1021,13 +1048,17 @@ template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
         int s1 = s0 + ck < a.n_steps ? s0 + ck : a.n_steps;
         e = hipMemcpyAsync(w.seg, w.ck + (size_t)sg * N, nb, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
-        for (int st = s0; st < s1 - 1; st++) {
+        // recompute the segment, keeping every step's pass records (the
+        // recording launches also produce the next state)
+        for (int st = s0; st < s1; st++) {
             const T *in = w.seg + (size_t)(st - s0) * N;
-            T *out = w.seg + (size_t)(st - s0 + 1) * N;
-            e = a.plain_step ? a.plain_step(a.plain_ctx, in, out) : record_step<T>(a, w, in, out, s);
+            T *out = st < s1 - 1 ? w.seg + (size_t)(st - s0 + 1) * N : nullptr;
+            w.select(st - s0);
+            e = record_step<T>(a, w, in, out, s);
             if (e != hipSuccess) return e;
         }
         for (int st = s1 - 1; st >= s0; st--) {
+            w.select(st - s0);
             e = reverse_step<T>(a, w, w.seg + (size_t)(st - s0) * N, s);
             if (e != hipSuccess) return e;
         }
