@@ -252,17 +252,26 @@ __global__ void k_donor_adj_walls(Geom g, const T *__restrict__ x, const T *cd, 
 // block per row segment), so no index division per thread.
 // mode bit 0: write xb (instead of adding to it), plus xadd when given;
 // bit 1: write the wall adjoints (the periodic wall n of a dimension is
-// never written).
+// never written).  z0..z2 (cell fields, NULL when unused, never read here)
+// are set to zero at the thread's cell, for the scatter-add kernels that
+// follow (in place of separate clearing launches).
 template <typename T>
 __global__ void __launch_bounds__(B)
     k_donor_adj2d(int n0, int n1, int bc0, int bc1, int bpr, int flux_is_vel, int mode,
                   const T *__restrict__ x, const T *__restrict__ c0, const T *__restrict__ c1,
                   const T *__restrict__ yb, const T *__restrict__ xadd, T *__restrict__ xb,
-                  T *__restrict__ cb0, T *__restrict__ cb1)
+                  T *__restrict__ cb0, T *__restrict__ cb1, T *__restrict__ z0,
+                  T *__restrict__ z1, T *__restrict__ z2)
 {
     const int i = blockIdx.x / bpr;
     const int j = (blockIdx.x - i * bpr) * B + threadIdx.x;
     if (j >= n1) return;
+    {
+        const int64_t k = (int64_t)i * n1 + j;
+        if (z0) z0[k] = T(0);
+        if (z1) z1[k] = T(0);
+        if (z2) z2[k] = T(0);
+    }
     const bool o0 = bc0 == BC_OPEN, o1 = bc1 == BC_OPEN;
     const bool top = o0 && i == 0, bot = o0 && i == n0 - 1;
     const bool lft = o1 && j == 0, rgt = o1 && j == n1 - 1;
@@ -667,17 +676,19 @@ bool fast_donor_adj(const Geom &g, const void *G)
 // transpose of a donor-cell pass: xb += (dy/dx)^T yb, cb_d += (dy/dc_d)^T yb;
 // with the 2-D kernel, mode bit 0 writes xb (= ... + xadd) and bit 1 writes
 // the wall adjoints instead of adding (other paths: mode must be 0)
+// (2-D kernel only: zero[] cell fields are set to zero, see k_donor_adj2d)
 template <typename T>
 void donor_adj(const Geom &g, const T *x, const T *const c[3], const T *G, int flux_is_vel,
                const T *yb, T *xb, T *const cb[3], hipStream_t s, int mode = 0,
-               const T *xadd = nullptr)
+               const T *xadd = nullptr, T *const *zero = nullptr)
 {
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
     if (fast_donor_adj(g, G)) {
         const int bpr = (int)cdiv(g.n[1], B);
         k_donor_adj2d<T><<<(unsigned)(bpr * g.n[0]), B, 0, s>>>(
             (int)g.n[0], (int)g.n[1], g.bc[0], g.bc[1], bpr, flux_is_vel, mode, x, c[0], c[1],
-            yb, xadd, xb, cb[0], cb[1]);
+            yb, xadd, xb, cb[0], cb[1], zero ? zero[0] : nullptr, zero ? zero[1] : nullptr,
+            zero ? zero[2] : nullptr);
         return;
     }
     with_nd(g.nd, [&](auto ND) {
@@ -921,19 +932,22 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
     // 2-D donor transpose writes xb (and, in the last pass, the advector
     // adjoint); the limiter transpose writes Vb.  The entries of a periodic
     // dimension's wall n are never written and stay zero from adjoint_run.
+    // With the 2-D donor transpose, the accumulators the later kernels of a
+    // pass scatter into (the limiter coefficients' adjoints, and in the
+    // first reversed pass the psi^n adjoint) are zeroed by that pass's donor
+    // transpose, which runs before them and reads none of them.
     const bool fast = fast_donor_adj(g, a.G);
-    {
+    if (!fast) {
         Bufs<T> f;
         f.push(w.pnb, N);
-        if (!fast)
-            for (int d = 0; d < g.nd; d++) f.push(w.Ab[d], nwalls(g, d));
+        for (int d = 0; d < g.nd; d++) f.push(w.Ab[d], nwalls(g, d));
         clear_n<T>(f, s);
     }
     for (int it = n; it >= 2; it--) {
         const T *x = w.X[it - 1];
-        {
+        if (!fast) {
             Bufs<T> f;
-            if (!fast) f.push(w.xb, N);
+            f.push(w.xb, N);
             if (fct) {
                 f.push(w.bub, N);
                 f.push(w.bdb, N);
@@ -944,7 +958,10 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
         {
             const T *Wc[3] = {w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2]};
             const int mode = fast ? (1 | (it == n ? 2 : 0)) : 0;
-            donor_adj<T>(g, x, Wc, a.G, iga ? 1 : 0, w.yb, w.xb, w.Ab, s, mode);
+            T *const zero[3] = {it == n ? w.pnb : nullptr, fct ? w.bub : nullptr,
+                                fct ? w.bdb : nullptr};
+            donor_adj<T>(g, x, Wc, a.G, iga ? 1 : 0, w.yb, w.xb, w.Ab, s, mode, nullptr,
+                         fast ? zero : nullptr);
         }
         // limiter
         if (fct) {
@@ -984,7 +1001,9 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
     // donor-cell pass of the input field with the input advector, plus the
     // limiter's direct dependence on psi^n
     if (fast) {
-        donor_adj<T>(g, psi_n, a.c, a.G, 0, w.yb, w.xb, w.Cb, s, 1, w.pnb);
+        // (pnb was zeroed by the first reversed pass; with no corrective
+        // pass there is nothing to add)
+        donor_adj<T>(g, psi_n, a.c, a.G, 0, w.yb, w.xb, w.Cb, s, 1, n >= 2 ? w.pnb : nullptr);
     } else {
         e = fill<T>(w.xb, N, s);
         donor_adj<T>(g, psi_n, a.c, a.G, 0, w.yb, w.xb, w.Cb, s);

@@ -56,7 +56,7 @@ def test_adjoint_vs_oracle(shape, bc, n_iters, opts, dtype):
 NOG_CASES = []
 for shape, bc in [((33, 29), 0), ((33, 29), 1), ((70, 131), 1), ((40, 64), 0)]:
     for n_iters, opts in [(2, FCT), (3, FCT), (2, 0), (3, 0), (2, IGA | FCT), (2, IGA),
-                          (3, TOT | FCT), (2, FCT | mpdata.OPT_KAHAN)]:
+                          (3, TOT | FCT), (2, FCT | mpdata.OPT_KAHAN), (1, 0)]:
         NOG_CASES.append((shape, bc, n_iters, opts))
 
 
