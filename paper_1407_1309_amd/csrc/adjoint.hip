@@ -441,88 +441,108 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
 }
 
 // 2-D transpose of the pseudo-velocity (no third-order terms) with the
-// scatter staged in LDS: a workgroup owns a tile of TPR x TPC walls and
-// accumulates its contributions to the cell adjoint and to the other
-// dimension's advector adjoint in two LDS boxes (the tile plus a one-cell
-// rim, in coordinates before the boundary map), then adds each non-zero box
-// entry to the mapped global entry with one atomic -- about one global
-// atomic per target instead of one per contribution.
-constexpr int TPR = 4, TPC = 64;                  // tile rows x columns (walls)
+// scatter staged in LDS.  A workgroup owns a tile of TPR x TPC cells and
+// both walls each cell owns (its low dimension-0 and low dimension-1 wall,
+// plus the far edge walls along the tile grid's last row / column): it
+// accumulates their contributions to the cell adjoint and to the advector
+// adjoints of the other dimension's walls (cross terms) in three LDS boxes
+// (the tile plus a one-cell rim, in coordinates before the boundary map),
+// then adds each non-zero box entry to the mapped global entry with one
+// atomic -- about one global atomic per target instead of one per
+// contribution, and one flush for both wall sets.
+constexpr int TPR = 4, TPC = 64;                  // tile rows x columns (cells)
 constexpr int BXR = TPR + 2, BXC = TPC + 2;       // LDS box: rows / columns
 
+// one wall of dimension WD at unmapped (i, j) of the tile at (i0, j0):
+// contributions to the cell adjoint (box XB) and to the dimension-(1-WD)
+// walls' advector adjoint (box CBo); its own advector adjoint goes to cb_own
 template <typename T, int WD>
-__global__ void __launch_bounds__(TPR * TPC)
-k_pseudo_adj2t(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
-               const T *G, const T *__restrict__ Vb, T *xb, T *cb0, T *cb1)
+__device__ __forceinline__ void pseudo_wall2(const Geom &g, unsigned opts,
+                                             const T *__restrict__ x, const T *const c[2],
+                                             const T *G, T vb, int i, int j, int i0, int j0,
+                                             T *XB, T *CBo, T *cb_own)
 {
     constexpr int d = WD, o = 1 - WD;
+    // box entry of unmapped coordinates (i, j)
+    auto bx = [&](int bi, int bj) { return (bi - i0 + 1) * BXC + (bj - j0 + 1); };
+    const bool iga = opts & OPT_IGA;
+    I3 p{{i, j, 0}};
+    I3 L = sh1(p, d, -1), R = p;
+    T u = c[d][wi(g, d, p)];
+    T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
+    T Gb = T(0.5) * (GL + GR);
+    const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
+    T xL = x[ci(g, L)], xR = x[ci(g, R)];
+    T ub = T(0), fn, fd;
+    T nA = xR - xL, dA = xR + xL;
+    T A;
+    frac_vd(iga, nA, dA, T(2), A, fn, fd);
+    ub += (sgnv(u) - T(2) * u * iGb) * A * vb;
+    T Ab = (fabs(u) - u * u * iGb) * vb;
+    atomicAdd(&XB[bx(R.v[0], R.v[1])], (fn + fd) * Ab);
+    atomicAdd(&XB[bx(L.v[0], L.v[1])], (-fn + fd) * Ab);
+    I3 Lo = sh1(L, o, 1), Ro = sh1(R, o, 1);
+    T cbar = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, Lo)] + c[o][wi(g, o, R)] +
+                        c[o][wi(g, o, Ro)]);
+    I3 Rp = sh1(R, o, 1), Lp = sh1(L, o, 1), Rm = sh1(R, o, -1), Lm = sh1(L, o, -1);
+    T a = x[ci(g, Rp)], b = x[ci(g, Lp)], ee = x[ci(g, Rm)], f = x[ci(g, Lm)];
+    T nB = a + b - ee - f, dB = a + b + ee + f;
+    T Bv;
+    frac_vd(iga, nB, dB, T(4), Bv, fn, fd);
+    ub += T(-0.5) * cbar * iGb * Bv * vb;
+    T cbar_b = T(-0.5) * u * iGb * Bv * vb;
+    T Bb = T(-0.5) * u * cbar * iGb * vb;
+    atomicAdd(&XB[bx(Rp.v[0], Rp.v[1])], (fn + fd) * Bb);
+    atomicAdd(&XB[bx(Lp.v[0], Lp.v[1])], (fn + fd) * Bb);
+    atomicAdd(&XB[bx(Rm.v[0], Rm.v[1])], (-fn + fd) * Bb);
+    atomicAdd(&XB[bx(Lm.v[0], Lm.v[1])], (-fn + fd) * Bb);
+    if (cbar_b != T(0)) {
+        T q = T(0.25) * cbar_b;
+        atomicAdd(&CBo[bx(L.v[0], L.v[1])], q);
+        atomicAdd(&CBo[bx(Lo.v[0], Lo.v[1])], q);
+        atomicAdd(&CBo[bx(R.v[0], R.v[1])], q);
+        atomicAdd(&CBo[bx(Ro.v[0], Ro.v[1])], q);
+    }
+    aadd(cb_own, wi(g, d, p), ub);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPR * TPC)
+k_pseudo_adj2(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
+              const T *G, const T *__restrict__ Vb0, const T *__restrict__ Vb1, T *xb, T *cb0,
+              T *cb1)
+{
     __shared__ T XB[BXR * BXC];
-    __shared__ T CB[BXR * BXC];
-    const int e0 = (int)g.n[0] + (d == 0), e1 = (int)g.n[1] + (d == 1);
-    const int tiles_c = (e1 + TPC - 1) / TPC;
+    __shared__ T CB0[BXR * BXC];   // dimension-0 walls (from dimension-1 walls' cross terms)
+    __shared__ T CB1[BXR * BXC];   // dimension-1 walls (from dimension-0 walls' cross terms)
+    const int n0 = (int)g.n[0], n1 = (int)g.n[1];
+    // tiles cover the cells and the far edge walls: rows 0..n0, columns 0..n1
+    const int tiles_c = (n1 + 1 + TPC - 1) / TPC;
     const int i0 = (blockIdx.x / tiles_c) * TPR, j0 = (blockIdx.x % tiles_c) * TPC;
     const int tid = threadIdx.x;
     for (int k = tid; k < BXR * BXC; k += TPR * TPC) {
         XB[k] = T(0);
-        CB[k] = T(0);
+        CB0[k] = T(0);
+        CB1[k] = T(0);
     }
     __syncthreads();
-    // box entry of unmapped coordinates (i, j)
-    auto bx = [&](int i, int j) { return (i - i0 + 1) * BXC + (j - j0 + 1); };
     const int i = i0 + tid / TPC, j = j0 + tid % TPC;
     const T *c[2] = {c0, c1};
-    T *cbp[2] = {cb0, cb1};
-    if (i < e0 && j < e1) {
-        const int64_t t = (int64_t)i * e1 + j;
-        const T vb = Vb[t];
-        if (vb != T(0)) {
-            const bool iga = opts & OPT_IGA;
-            I3 p{{i, j, 0}};
-            I3 L = sh1(p, d, -1), R = p;
-            T u = c[d][wi(g, d, p)];
-            T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
-            T Gb = T(0.5) * (GL + GR);
-            const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
-            T xL = x[ci(g, L)], xR = x[ci(g, R)];
-            T ub = T(0), fn, fd;
-            T nA = xR - xL, dA = xR + xL;
-            T A;
-            frac_vd(iga, nA, dA, T(2), A, fn, fd);
-            ub += (sgnv(u) - T(2) * u * iGb) * A * vb;
-            T Ab = (fabs(u) - u * u * iGb) * vb;
-            atomicAdd(&XB[bx(R.v[0], R.v[1])], (fn + fd) * Ab);
-            atomicAdd(&XB[bx(L.v[0], L.v[1])], (-fn + fd) * Ab);
-            I3 Lo = sh1(L, o, 1), Ro = sh1(R, o, 1);
-            T cbar = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, Lo)] + c[o][wi(g, o, R)] +
-                                c[o][wi(g, o, Ro)]);
-            I3 Rp = sh1(R, o, 1), Lp = sh1(L, o, 1), Rm = sh1(R, o, -1), Lm = sh1(L, o, -1);
-            T a = x[ci(g, Rp)], b = x[ci(g, Lp)], ee = x[ci(g, Rm)], f = x[ci(g, Lm)];
-            T nB = a + b - ee - f, dB = a + b + ee + f;
-            T Bv;
-            frac_vd(iga, nB, dB, T(4), Bv, fn, fd);
-            ub += T(-0.5) * cbar * iGb * Bv * vb;
-            T cbar_b = T(-0.5) * u * iGb * Bv * vb;
-            T Bb = T(-0.5) * u * cbar * iGb * vb;
-            atomicAdd(&XB[bx(Rp.v[0], Rp.v[1])], (fn + fd) * Bb);
-            atomicAdd(&XB[bx(Lp.v[0], Lp.v[1])], (fn + fd) * Bb);
-            atomicAdd(&XB[bx(Rm.v[0], Rm.v[1])], (-fn + fd) * Bb);
-            atomicAdd(&XB[bx(Lm.v[0], Lm.v[1])], (-fn + fd) * Bb);
-            if (cbar_b != T(0)) {
-                T q = T(0.25) * cbar_b;
-                atomicAdd(&CB[bx(L.v[0], L.v[1])], q);
-                atomicAdd(&CB[bx(Lo.v[0], Lo.v[1])], q);
-                atomicAdd(&CB[bx(R.v[0], R.v[1])], q);
-                atomicAdd(&CB[bx(Ro.v[0], Ro.v[1])], q);
-            }
-            aadd(cbp[d], wi(g, d, p), ub);
-        }
+    if (i <= n0 && j < n1) {                       // dimension-0 wall (i, j)
+        const T vb = Vb0[(int64_t)i * n1 + j];
+        if (vb != T(0)) pseudo_wall2<T, 0>(g, opts, x, c, G, vb, i, j, i0, j0, XB, CB1, cb0);
+    }
+    if (i < n0 && j <= n1) {                       // dimension-1 wall (i, j)
+        const T vb = Vb1[(int64_t)i * (n1 + 1) + j];
+        if (vb != T(0)) pseudo_wall2<T, 1>(g, opts, x, c, G, vb, i, j, i0, j0, XB, CB0, cb1);
     }
     __syncthreads();
     // flush: box entries to the mapped global entries
     for (int k = tid; k < BXR * BXC; k += TPR * TPC) {
         I3 q{{i0 - 1 + k / BXC, j0 - 1 + k % BXC, 0}};
         if (XB[k] != T(0)) aadd(xb, ci(g, q), XB[k]);
-        if (CB[k] != T(0)) aadd(cbp[o], wi(g, o, q), CB[k]);
+        if (CB0[k] != T(0)) aadd(cb0, wi(g, 0, q), CB0[k]);
+        if (CB1[k] != T(0)) aadd(cb1, wi(g, 1, q), CB1[k]);
     }
 }
 
@@ -713,21 +733,27 @@ void pseudo_adj_dispatch(const Geom &g, int d, unsigned blocks, hipStream_t s, u
                          const T *x, const T *c0, const T *c1, const T *c2, const T *G,
                          const T *Vb, T *xb, T *cb0, T *cb1, T *cb2)
 {
-    if (g.nd == 2 && !(opts & OPT_TOT)) {
-        const int64_t e0 = g.n[0] + (d == 0), e1 = g.n[1] + (d == 1);
-        const unsigned tb = (unsigned)(cdiv(e0, TPR) * cdiv(e1, TPC));
-        if (d == 0)
-            k_pseudo_adj2t<T, 0><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb, xb, cb0, cb1);
-        else
-            k_pseudo_adj2t<T, 1><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb, xb, cb0, cb1);
-        return;
-    }
 #define MP_P(ND, D) \
     k_pseudo_adj<T, ND, D><<<blocks, B, 0, s>>>(g, opts, x, c0, c1, c2, G, Vb, xb, cb0, cb1, cb2)
     if (g.nd == 1) MP_P(1, 0);
     else if (g.nd == 2) { if (d == 0) MP_P(2, 0); else MP_P(2, 1); }
     else { if (d == 0) MP_P(3, 0); else if (d == 1) MP_P(3, 1); else MP_P(3, 2); }
 #undef MP_P
+}
+
+// 2-D without third-order terms: both wall dimensions in one launch
+bool pseudo_adj_both(const Geom &g, unsigned opts)
+{
+    return g.nd == 2 && !(opts & OPT_TOT);
+}
+
+template <typename T>
+void pseudo_adj2_launch(const Geom &g, hipStream_t s, unsigned opts, const T *x, const T *c0,
+                        const T *c1, const T *G, const T *Vb0, const T *Vb1, T *xb, T *cb0,
+                        T *cb1)
+{
+    const unsigned tb = (unsigned)(cdiv(g.n[0] + 1, TPR) * cdiv(g.n[1] + 1, TPC));
+    k_pseudo_adj2<T><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb0, Vb1, xb, cb0, cb1);
 }
 
 template <typename T>
@@ -991,9 +1017,14 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
         }
         const T *cin[3];
         for (int d = 0; d < 3; d++) cin[d] = (it == 2) ? a.c[d] : w.W[it - 2][d];
-        for (int d = 0; d < g.nd; d++)
-            pseudo_adj_dispatch<T>(g, d, (unsigned)cdiv(nwalls(g, d), B), s, a.opts, x, cin[0],
-                                   cin[1], cin[2], a.G, w.Vb[d], w.xb, tgt[0], tgt[1], tgt[2]);
+        if (pseudo_adj_both(g, a.opts))
+            pseudo_adj2_launch<T>(g, s, a.opts, x, cin[0], cin[1], a.G, w.Vb[0], w.Vb[1], w.xb,
+                                  tgt[0], tgt[1]);
+        else
+            for (int d = 0; d < g.nd; d++)
+                pseudo_adj_dispatch<T>(g, d, (unsigned)cdiv(nwalls(g, d), B), s, a.opts, x,
+                                       cin[0], cin[1], cin[2], a.G, w.Vb[d], w.xb, tgt[0], tgt[1],
+                                       tgt[2]);
         T *t = w.yb;
         w.yb = w.xb;
         w.xb = t;
