@@ -583,6 +583,55 @@ __global__ void k_limit_adj(Geom g, const T *__restrict__ V, const T *__restrict
     if (wd == 2) aadd(bdb, kR, dnb);
 }
 
+// 2-D: both wall sets in one launch, a thread per (row, column) of the
+// (n0+1) x (n1+1) grid handling the dimension-0 wall (i, j) (j < n1) and the
+// dimension-1 wall (i, j) (i < n0), each with the body of k_limit_adj
+template <typename T, int WD>
+__device__ __forceinline__ void limit_wall2(const Geom &g, int i, int j, int64_t t,
+                                            const T *__restrict__ V, const T *__restrict__ bup,
+                                            const T *__restrict__ bdn, const T *__restrict__ Wb,
+                                            T *Vb, T *bub, T *bdb)
+{
+    constexpr int d = WD;
+    I3 p{{i, j, 0}};
+    // periodic: wall n is wall 0 (its own thread); nothing reads entry n
+    if (g.bc[d] == BC_PERIODIC && p.v[d] == (int)g.n[d]) return;
+    T wb = Wb[t];
+    if (wb == T(0)) {
+        Vb[t] = T(0);
+        return;
+    }
+    I3 L = sh1(p, d, -1), R = p;
+    int64_t kL = ci(g, L), kR = ci(g, R);
+    T v = V[wi(g, d, p)];
+    T up = T(1), dn = T(1);
+    int wu = 0, wd = 0;
+    if (bdn[kL] < up) { up = bdn[kL]; wu = 1; }
+    if (bup[kR] < up) { up = bup[kR]; wu = 2; }
+    if (bup[kL] < dn) { dn = bup[kL]; wd = 1; }
+    if (bdn[kR] < dn) { dn = bdn[kR]; wd = 2; }
+    Vb[t] = ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb;   // first writer
+    T upb = pos(v) * wb, dnb = neg(v) * wb;
+    if (wu == 1) aadd(bdb, kL, upb);
+    if (wu == 2) aadd(bub, kR, upb);
+    if (wd == 1) aadd(bub, kL, dnb);
+    if (wd == 2) aadd(bdb, kR, dnb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(B)
+k_limit_adj2(Geom g, const T *__restrict__ V0, const T *__restrict__ V1,
+             const T *__restrict__ bup, const T *__restrict__ bdn, const T *__restrict__ Wb0,
+             const T *__restrict__ Wb1, T *Vb0, T *Vb1, T *bub, T *bdb)
+{
+    const int n0 = (int)g.n[0], n1 = (int)g.n[1];
+    const int i = blockIdx.y, j = blockIdx.x * B + threadIdx.x;
+    if (j > n1) return;
+    if (j < n1) limit_wall2<T, 0>(g, i, j, (int64_t)i * n1 + j, V0, bup, bdn, Wb0, Vb0, bub, bdb);
+    if (i < n0)
+        limit_wall2<T, 1>(g, i, j, (int64_t)i * (n1 + 1) + j, V1, bup, bdn, Wb1, Vb1, bub, bdb);
+}
+
 // transpose of the limiter coefficients (bounds, in/out fluxes) per cell
 template <typename T, int ND>
 __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
@@ -991,13 +1040,20 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
         }
         // limiter
         if (fct) {
-            for (int d = 0; d < g.nd; d++)
-                with_nd_d(g.nd, d, [&](auto ND, auto WD) {
-                    k_limit_adj<T, decltype(ND)::value, decltype(WD)::value>
-                        <<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
-                            g, w.V[it - 1][d], w.bu[it - 1], w.bd[it - 1], w.Ab[d], w.Vb[d],
-                            w.bub, w.bdb);
-                });
+            if (g.nd == 2 && g.n[0] < 65535) {     // one grid row per cell row
+                const dim3 grid((unsigned)cdiv(g.n[1] + 1, B), (unsigned)(g.n[0] + 1));
+                k_limit_adj2<T><<<grid, B, 0, s>>>(g, w.V[it - 1][0], w.V[it - 1][1],
+                                                   w.bu[it - 1], w.bd[it - 1], w.Ab[0], w.Ab[1],
+                                                   w.Vb[0], w.Vb[1], w.bub, w.bdb);
+            } else {
+                for (int d = 0; d < g.nd; d++)
+                    with_nd_d(g.nd, d, [&](auto ND, auto WD) {
+                        k_limit_adj<T, decltype(ND)::value, decltype(WD)::value>
+                            <<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
+                                g, w.V[it - 1][d], w.bu[it - 1], w.bd[it - 1], w.Ab[d],
+                                w.Vb[d], w.bub, w.bdb);
+                    });
+            }
             beta_adj_dispatch<T>(g, cb, s, a.opts, psi_n, x, w.V[it - 1][0], w.V[it - 1][1],
                                  w.V[it - 1][2], a.G, w.bub, w.bdb, w.xb, w.pnb, w.Vb[0],
                                  w.Vb[1], w.Vb[2]);
