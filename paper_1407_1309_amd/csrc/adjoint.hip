@@ -941,14 +941,16 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
     const int km = (a.opts & OPT_KAHAN) ? 2 : 0;   // Kahan-compensated donor update
     T *first = n > 1 ? w.X[1] : out;
     if (!a.G && pass2d_supported(g.nd, n > 1 ? n : 2, a.opts, 0, g.n)) {
-        // 2-D: donor kernel, then one launch per corrective pass that also
-        // writes the records (raw and limited velocities, coefficients)
-        if (first) {
+        // 2-D: one launch per corrective pass that also writes the records
+        // (raw and limited velocities, coefficients); the first folds the
+        // donor pass in and keeps its result as the pass input record
+        if (n == 1 && first) {
             e = donor2d_launch<T>(g, a.opts, psi_n, a.c[0], a.c[1], first, nullptr, s);
             if (e != hipSuccess) return e;
         }
         for (int it = 2; it <= n; it++) {
-            const T *x = w.X[it - 1];
+            const bool donor = it == 2;
+            const T *x = donor ? psi_n : w.X[it - 1];
             const T *c0 = it == 2 ? a.c[0] : w.W[it - 2][0];
             const T *c1 = it == 2 ? a.c[1] : w.W[it - 2][1];
             PassRecord<T> rec;
@@ -958,9 +960,10 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
                 rec.bu = w.bu[it - 1];
                 rec.bd = w.bd[it - 1];
             }
+            if (donor) rec.xd = w.X[1];
             T *y = (it < n) ? w.X[it] : out;
-            e = pass2d_launch<T>(g, a.opts, x, c0, c1, psi_n, y, w.W[it - 1][0], w.W[it - 1][1],
-                                 s, rec);
+            e = pass2d_launch<T>(g, a.opts, x, c0, c1, donor ? nullptr : psi_n, y,
+                                 w.W[it - 1][0], w.W[it - 1][1], s, rec);
             if (e != hipSuccess) return e;
         }
         return hipGetLastError();

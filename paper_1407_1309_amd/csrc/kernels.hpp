@@ -79,10 +79,12 @@ hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_
 // pseudo-velocities at the same walls, limiter coefficients of the cells.
 template <typename T> struct PassRecord {
     T *v0 = nullptr, *v1 = nullptr, *bu = nullptr, *bd = nullptr;
+    T *xd = nullptr;   // the folded donor pass's result (psi_n NULL launches only)
 };
 bool pass2d_supported(int nd, int n_iters, unsigned opts, int has_g, const int64_t n[3]);
 // y may be NULL (no result needed); psi_n NULL: x is psi^n and the donor
-// pass is folded in (the first corrective pass; no records); tile_rows:
+// pass is folded in (the first corrective pass; rec.xd, when given,
+// receives the donor result); tile_rows:
 // rows per wavefront chunk (0 = built-in default)
 template <typename T>
 hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,

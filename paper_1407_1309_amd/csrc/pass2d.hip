@@ -114,6 +114,7 @@ template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR> struct March {
     const T *x, *pn, *c0, *c1;
     T *y, *w0, *w1;
     T *v0r, *v1r, *bur, *bdr;          // records: raw velocities, coefficients
+    T *xd;                             // record of the donor pass's result (DONOR)
     T fx[PF], fp[PF], f0[PF], f1[PF];
     Ring<T, 4> xq, xl, c0q, c1q, mxq, mnq, pq;
     Ring<T, 2> xr, v0q, buq, bdq, aq0, aq1;
@@ -168,6 +169,8 @@ template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR> struct March {
             x_a = edge_cols(donor_update(kahan, pc, f0hi - f0lo, f1hi - f1lo));
             if (bc0 == BC_OPEN && a >= n0) x_a = AT(xq, 4, 1);   // rows past the end
             pn_a = pc;
+            // the donor result of the chunk's own rows and columns
+            if (xd && a >= i0 && a < i1 && out_lane) xd[(int64_t)a * n1 + ocol] = x_a;
         } else {
             x_a = fx[S];
             pn_a = fp[S];
@@ -393,7 +396,7 @@ __global__ void __launch_bounds__(WAVE)
              const T *__restrict__ x, const T *__restrict__ c0, const T *__restrict__ c1,
              const T *__restrict__ psi_n, T *__restrict__ y, T *__restrict__ w0,
              T *__restrict__ w1, T *__restrict__ v0r, T *__restrict__ v1r,
-             T *__restrict__ bur, T *__restrict__ bdr)
+             T *__restrict__ bur, T *__restrict__ bdr, T *__restrict__ xd)
 {
     constexpr int HL = Lanes<DONOR>::HL, HR = Lanes<DONOR>::HR, OW = Lanes<DONOR>::OW;
     const int b = blockIdx.x;
@@ -424,6 +427,7 @@ __global__ void __launch_bounds__(WAVE)
     m.v1r = v1r;
     m.bur = bur;
     m.bdr = bdr;
+    m.xd = DONOR ? xd : nullptr;
     m.ccol = map_cell(col, n1, bc1);
     m.wcol = map_wall(col, n1, bc1);
     m.ocol = col;
@@ -540,7 +544,8 @@ hipError_t launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T
     const int64_t blocks = strips * cdiv(n0, th);
     k_pass2d<T, FCT, IGA, ABS, DONOR><<<(unsigned)blocks, WAVE, 0, s>>>(
         (int)n0, (int)n1, g.bc[0], g.bc[1], (int)th, (int)strips, (opts & OPT_DFL) ? 1 : 0,
-        (opts & OPT_KAHAN) ? 1 : 0, x, c0, c1, psi_n, y, w0, w1, rec.v0, rec.v1, rec.bu, rec.bd);
+        (opts & OPT_KAHAN) ? 1 : 0, x, c0, c1, psi_n, y, w0, w1, rec.v0, rec.v1, rec.bu, rec.bd,
+        rec.xd);
     return hipGetLastError();
 }
 
