@@ -453,11 +453,36 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
 constexpr int TPR = 4, TPC = 64;                  // tile rows x columns (cells)
 constexpr int BXR = TPR + 2, BXC = TPC + 2;       // LDS box: rows / columns
 
+// 2-D boundary map with compile-time boundary types (coordinates at most one
+// period outside the range) and 32-bit flat indices (n0 n1 < 2^31)
+template <int BC> __device__ __forceinline__ int wc2(int q, int n)
+{
+    if constexpr (BC == BC_PERIODIC) return q < 0 ? q + n : (q >= n ? q - n : q);
+    else return q < 0 ? 0 : (q >= n ? n - 1 : q);
+}
+template <int BC> __device__ __forceinline__ int ww2(int f, int n)
+{
+    if constexpr (BC == BC_PERIODIC) return f < 0 ? f + n : (f >= n ? f - n : f);
+    else return f < 0 ? 0 : (f > n ? n : f);
+}
+template <int BC0, int BC1> struct Map2 {
+    int n0, n1;
+    __device__ __forceinline__ int cell(const I3 &q) const
+    {
+        return wc2<BC0>(q.v[0], n0) * n1 + wc2<BC1>(q.v[1], n1);
+    }
+    __device__ __forceinline__ int wall(int d, const I3 &q) const
+    {
+        return d == 0 ? ww2<BC0>(q.v[0], n0) * n1 + wc2<BC1>(q.v[1], n1)
+                      : wc2<BC0>(q.v[0], n0) * (n1 + 1) + ww2<BC1>(q.v[1], n1);
+    }
+};
+
 // one wall of dimension WD at unmapped (i, j) of the tile at (i0, j0):
 // contributions to the cell adjoint (box XB) and to the dimension-(1-WD)
 // walls' advector adjoint (box CBo); its own advector adjoint goes to cb_own
-template <typename T, int WD>
-__device__ __forceinline__ void pseudo_wall2(const Geom &g, unsigned opts,
+template <typename T, int WD, int BC0, int BC1>
+__device__ __forceinline__ void pseudo_wall2(const Map2<BC0, BC1> &g, unsigned opts,
                                              const T *__restrict__ x, const T *const c[2],
                                              const T *G, T vb, int i, int j, int i0, int j0,
                                              T *XB, T *CBo, T *cb_own)
@@ -468,11 +493,11 @@ __device__ __forceinline__ void pseudo_wall2(const Geom &g, unsigned opts,
     const bool iga = opts & OPT_IGA;
     I3 p{{i, j, 0}};
     I3 L = sh1(p, d, -1), R = p;
-    T u = c[d][wi(g, d, p)];
-    T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
+    T u = c[d][g.wall(d, p)];
+    T GL = G ? G[g.cell(L)] : T(1), GR = G ? G[g.cell(R)] : T(1);
     T Gb = T(0.5) * (GL + GR);
     const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
-    T xL = x[ci(g, L)], xR = x[ci(g, R)];
+    T xL = x[g.cell(L)], xR = x[g.cell(R)];
     T ub = T(0), fn, fd;
     T nA = xR - xL, dA = xR + xL;
     T A;
@@ -482,10 +507,10 @@ __device__ __forceinline__ void pseudo_wall2(const Geom &g, unsigned opts,
     atomicAdd(&XB[bx(R.v[0], R.v[1])], (fn + fd) * Ab);
     atomicAdd(&XB[bx(L.v[0], L.v[1])], (-fn + fd) * Ab);
     I3 Lo = sh1(L, o, 1), Ro = sh1(R, o, 1);
-    T cbar = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, Lo)] + c[o][wi(g, o, R)] +
-                        c[o][wi(g, o, Ro)]);
+    T cbar = T(0.25) * (c[o][g.wall(o, L)] + c[o][g.wall(o, Lo)] + c[o][g.wall(o, R)] +
+                        c[o][g.wall(o, Ro)]);
     I3 Rp = sh1(R, o, 1), Lp = sh1(L, o, 1), Rm = sh1(R, o, -1), Lm = sh1(L, o, -1);
-    T a = x[ci(g, Rp)], b = x[ci(g, Lp)], ee = x[ci(g, Rm)], f = x[ci(g, Lm)];
+    T a = x[g.cell(Rp)], b = x[g.cell(Lp)], ee = x[g.cell(Rm)], f = x[g.cell(Lm)];
     T nB = a + b - ee - f, dB = a + b + ee + f;
     T Bv;
     frac_vd(iga, nB, dB, T(4), Bv, fn, fd);
@@ -503,19 +528,20 @@ __device__ __forceinline__ void pseudo_wall2(const Geom &g, unsigned opts,
         atomicAdd(&CBo[bx(R.v[0], R.v[1])], q);
         atomicAdd(&CBo[bx(Ro.v[0], Ro.v[1])], q);
     }
-    aadd(cb_own, wi(g, d, p), ub);
+    aadd(cb_own, (int64_t)g.wall(d, p), ub);
 }
 
-template <typename T>
+template <typename T, int BC0, int BC1>
 __global__ void __launch_bounds__(TPR * TPC)
-k_pseudo_adj2(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
+k_pseudo_adj2(Geom gg, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
               const T *G, const T *__restrict__ Vb0, const T *__restrict__ Vb1, T *xb, T *cb0,
               T *cb1)
 {
+    const Map2<BC0, BC1> g{(int)gg.n[0], (int)gg.n[1]};
     __shared__ T XB[BXR * BXC];
     __shared__ T CB0[BXR * BXC];   // dimension-0 walls (from dimension-1 walls' cross terms)
     __shared__ T CB1[BXR * BXC];   // dimension-1 walls (from dimension-0 walls' cross terms)
-    const int n0 = (int)g.n[0], n1 = (int)g.n[1];
+    const int n0 = g.n0, n1 = g.n1;
     // tiles cover the cells and the far edge walls: rows 0..n0, columns 0..n1
     const int tiles_c = (n1 + 1 + TPC - 1) / TPC;
     const int i0 = (blockIdx.x / tiles_c) * TPR, j0 = (blockIdx.x % tiles_c) * TPC;
@@ -540,9 +566,9 @@ k_pseudo_adj2(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, const
     // flush: box entries to the mapped global entries
     for (int k = tid; k < BXR * BXC; k += TPR * TPC) {
         I3 q{{i0 - 1 + k / BXC, j0 - 1 + k % BXC, 0}};
-        if (XB[k] != T(0)) aadd(xb, ci(g, q), XB[k]);
-        if (CB0[k] != T(0)) aadd(cb0, wi(g, 0, q), CB0[k]);
-        if (CB1[k] != T(0)) aadd(cb1, wi(g, 1, q), CB1[k]);
+        if (XB[k] != T(0)) aadd(xb, (int64_t)g.cell(q), XB[k]);
+        if (CB0[k] != T(0)) aadd(cb0, (int64_t)g.wall(0, q), CB0[k]);
+        if (CB1[k] != T(0)) aadd(cb1, (int64_t)g.wall(1, q), CB1[k]);
     }
 }
 
@@ -793,7 +819,7 @@ void pseudo_adj_dispatch(const Geom &g, int d, unsigned blocks, hipStream_t s, u
 // 2-D without third-order terms: both wall dimensions in one launch
 bool pseudo_adj_both(const Geom &g, unsigned opts)
 {
-    return g.nd == 2 && !(opts & OPT_TOT);
+    return g.nd == 2 && !(opts & OPT_TOT) && (g.n[0] + 1) * (g.n[1] + 1) < ((int64_t)1 << 31);
 }
 
 template <typename T>
@@ -802,7 +828,14 @@ void pseudo_adj2_launch(const Geom &g, hipStream_t s, unsigned opts, const T *x,
                         T *cb1)
 {
     const unsigned tb = (unsigned)(cdiv(g.n[0] + 1, TPR) * cdiv(g.n[1] + 1, TPC));
-    k_pseudo_adj2<T><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb0, Vb1, xb, cb0, cb1);
+#define MP_K(B0, B1) \
+    k_pseudo_adj2<T, B0, B1><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb0, Vb1, xb, cb0, cb1)
+    const bool p0 = g.bc[0] == BC_PERIODIC, p1 = g.bc[1] == BC_PERIODIC;
+    if (p0 && p1) MP_K(BC_PERIODIC, BC_PERIODIC);
+    else if (p0) MP_K(BC_PERIODIC, BC_OPEN);
+    else if (p1) MP_K(BC_OPEN, BC_PERIODIC);
+    else MP_K(BC_OPEN, BC_OPEN);
+#undef MP_K
 }
 
 template <typename T>
