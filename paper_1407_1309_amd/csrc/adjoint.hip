@@ -263,8 +263,17 @@ __global__ void __launch_bounds__(B)
                   T *__restrict__ cb0, T *__restrict__ cb1, T *__restrict__ z0,
                   T *__restrict__ z1, T *__restrict__ z2)
 {
-    const int i = blockIdx.x / bpr;
-    const int j = (blockIdx.x - i * bpr) * B + threadIdx.x;
+    // block b runs on XCD b % 8: each XCD takes a contiguous range of row
+    // segments, so the rows above and below a segment are read by blocks on
+    // the same XCD, through its L2
+    int b;
+    {
+        const int nblk = (int)gridDim.x;
+        const int x8 = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
+        b = x8 * per + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3);
+    }
+    const int i = b / bpr;
+    const int j = (b - i * bpr) * B + threadIdx.x;
     if (j >= n1) return;
     {
         const int64_t k = (int64_t)i * n1 + j;
