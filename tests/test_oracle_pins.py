@@ -770,3 +770,55 @@ def test_diag_and_courant():
     cm = oracle.courant_max((2, 2), [c0, c1], g=g)
     # cell (1,1): max(0.4, 0.2) + max(0.1, 0.25) = 0.65, / 0.5
     assert abs(cm - 1.3) < 1e-15
+
+
+# ---------------------------------------------------------------- compensated sum of diag
+def test_diag_sum_is_compensated():
+    """The conservation diagnostic (Sect. 1: the scheme conserves sum G psi)
+    sums with compensation.  Cancellation cases that plain left-to-right
+    summation gets wrong: [2^53, 1, -2^53, 1] sums to 1 uncompensated and 2
+    exactly; [1, 2^100, 1, -2^100] defeats Kahan's form (the compensation
+    is lost when a later term dwarfs the running sum) but not Neumaier's.
+    A dropped or mis-signed compensation term fails one of them."""
+    for vals, exact in (([2.0 ** 53, 1.0, -2.0 ** 53, 1.0], 2.0),
+                        ([1.0, 2.0 ** 100, 1.0, -2.0 ** 100], 2.0),
+                        ([1e16, 3.0, 3.0, -1e16], 6.0),
+                        ([-2.0 ** 60, 7.0, 2.0 ** 60, -1.0, 1.0], 7.0)):
+        psi = np.array(vals)
+        s, mn, mx, bad = oracle.diag(psi)
+        assert s == exact, (vals, s)
+        assert (mn, mx, bad) == (min(vals), max(vals), 0)
+        # the same values as G * psi products (exact ones: G = 0.5, psi doubled)
+        s2, _, _, _ = oracle.diag(2.0 * psi, np.full(psi.shape, 0.5))
+        assert s2 == exact
+        # plain summation really differs here (the pin has teeth)
+        naive = 0.0
+        for v in vals:
+            naive += v
+        assert naive != exact
+
+
+def test_diag_sum_matches_exact_summation():
+    """On ill-conditioned data (terms of random sign spanning 2^-40..2^40,
+    sum of order 1) the compensated sum of the rounded G*psi products stays
+    within 2 ulp of their exactly rounded sum (math.fsum, an exact
+    summation), where plain summation is off by many orders more.  Neumaier's
+    bound: |error| <= 2u|S| + O(n u^2) sum|x|."""
+    gen = np.random.default_rng(123)
+    n = 4096
+    mag = 2.0 ** gen.uniform(-40, 40, size=n)
+    gm = gen.uniform(0.5, 2.0, size=n)
+    small = gen.uniform(-1, 1, size=n)
+    # pairs +x, -x under the same G cancel exactly; the small terms remain
+    psi = np.concatenate([mag, -mag, small])
+    g = np.concatenate([gm, gm, np.ones(n)])
+    perm = gen.permutation(psi.size)
+    psi, g = psi[perm], g[perm]
+    terms = g * psi                       # the products the sum is defined over
+    exact = math.fsum(terms.tolist())
+    s, _, _, _ = oracle.diag(psi.reshape(96, 128), g.reshape(96, 128))
+    assert abs(s - exact) <= 2 * np.spacing(abs(exact)), (s, exact)
+    naive = float(np.sum(terms[:0]))
+    for t in terms:
+        naive += t
+    assert abs(naive - exact) > 1e3 * np.spacing(abs(exact))
