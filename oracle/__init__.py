@@ -21,14 +21,15 @@ from . import build as _build
 BC_PERIODIC, BC_OPEN = 0, 1
 OPT_FCT, OPT_IGA, OPT_TOT, OPT_ABS, OPT_DFL, OPT_KAHAN = 1, 2, 4, 8, 16, 32
 
-_LIB = None
+_LIBS = {}
 _DP = ctypes.POINTER(ctypes.c_double)
 
 
-def _lib():
-    global _LIB
-    if _LIB is None:
-        path = _build.OUT
+def _lib(parallel=False):
+    """The oracle library: single-threaded, or (parallel=True) the same
+    source built with OpenMP over each stage's outermost loop (same bits)."""
+    if parallel not in _LIBS:
+        path = _build.OUT_OMP if parallel else _build.OUT
         srcs = [os.path.join(_build.HERE, s) for s in _build.SOURCES]
         newest = max(os.path.getmtime(s) for s in srcs if os.path.exists(s))
         if not os.path.exists(path) or os.path.getmtime(path) < newest:
@@ -45,8 +46,14 @@ def _lib():
             lib.orc_adjoint.argtypes = [ctypes.c_int, L3, I3, ctypes.c_int, ctypes.c_uint,
                                         _DP, _DP, _DP, _DP, _DP, ctypes.c_long, ctypes.c_long,
                                         _DP, _DP, _DP, _DP, _DP]
-        _LIB = lib
-    return _LIB
+        lib.orc_threads.restype = ctypes.c_int
+        _LIBS[parallel] = lib
+    return _LIBS[parallel]
+
+
+def threads(parallel=True):
+    """Threads the stage loops of step() use in the given build."""
+    return int(_lib(parallel).orc_threads())
 
 
 def _ptr(a):
@@ -81,15 +88,16 @@ def _check_c(psi_shape, c):
             raise ValueError(f"c[{d}] has shape {cd.shape}, expected {tuple(want)}")
 
 
-def step(psi, c, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1):
-    """Return psi advanced by n_steps MPDATA steps (input not modified)."""
+def step(psi, c, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1, parallel=False):
+    """Return psi advanced by n_steps MPDATA steps (input not modified).
+    parallel=True runs the OpenMP build of the same source (same bits)."""
     psi = np.array(psi, dtype=np.float64, copy=True, order="C")
     c = [_f64(x) for x in c]
     _check_c(psi.shape, c)
     g = _f64(g)
     ndims, n, bcs = _dims(psi.shape, bc)
     cc = c + [None] * (3 - ndims)
-    rc = _lib().orc_step(ndims, n, bcs, int(n_iters), int(opts), _ptr(psi), _ptr(g),
+    rc = _lib(parallel).orc_step(ndims, n, bcs, int(n_iters), int(opts), _ptr(psi), _ptr(g),
                          _ptr(cc[0]), _ptr(cc[1]), _ptr(cc[2]), int(n_steps))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
@@ -244,8 +252,10 @@ def courant_max(psi_shape, c, g=None, bc=BC_PERIODIC):
 
 
 def adjoint(psi0, c, lambda_T, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1,
-            ckpt_every=0):
+            ckpt_every=0, parallel=False):
     """Reverse-mode gradient of J through n_steps steps, given dJ/dpsi_T.
+    parallel=True runs the OpenMP build (its forward recomputations share
+    their stage loops among threads; same bits).
 
     Returns (grad_psi0, [grad_c0, grad_c1, ...])."""
     psi0 = _f64(psi0)
@@ -258,7 +268,7 @@ def adjoint(psi0, c, lambda_T, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_step
     gc = [np.zeros_like(x) for x in c]
     cc = c + [None] * (3 - ndims)
     gg = gc + [None] * (3 - ndims)
-    lib = _lib()
+    lib = _lib(parallel)
     if not hasattr(lib, "orc_adjoint"):
         raise RuntimeError("oracle built without the adjoint")
     rc = lib.orc_adjoint(ndims, n, bcs, int(n_iters), int(opts), _ptr(psi0), _ptr(g),

@@ -32,6 +32,15 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* The outermost loop of each stage (over dimension 0) may be shared among
+ * threads: built with -fopenmp this file is the multi-core CPU baseline.
+ * Every iteration writes its own cells or walls only and reads arrays that
+ * the stage does not write, so any thread count gives the same bits. */
+#define ROWS_IN_PARALLEL _Pragma("omp parallel for schedule(static)")
 
 typedef struct {
     int ndims;
@@ -174,8 +183,9 @@ static double donor_flux(const grid_t *g, int d, const double *x,
 static void donor_pass(const grid_t *g, const double *x, double *const c[3],
                        const double *G, int iga_flux, double *out)
 {
-    long p[3];
-    for (p[0] = 0; p[0] < g->n[0]; p[0]++)
+    ROWS_IN_PARALLEL
+    for (long i0 = 0; i0 < g->n[0]; i0++) {
+        long p[3] = {i0, 0, 0};
         for (p[1] = 0; p[1] < g->n[1]; p[1]++)
             for (p[2] = 0; p[2] < g->n[2]; p[2]++) {
                 double acc = 0.0;
@@ -209,6 +219,7 @@ static void donor_pass(const grid_t *g, const double *x, double *const c[3],
                     out[cidx(g, p)] = at(g, x, p) - r;
                 }
             }
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -341,12 +352,14 @@ static void antidiffusive_velocity(const grid_t *g, const double *x,
     for (int d = 0; d < g->ndims; d++) {
         long e[3] = {g->n[0], g->n[1], g->n[2]};
         e[d] += 1;
-        long p[3];
-        for (p[0] = 0; p[0] < e[0]; p[0]++)
+        ROWS_IN_PARALLEL
+        for (long i0 = 0; i0 < e[0]; i0++) {
+            long p[3] = {i0, 0, 0};
             for (p[1] = 0; p[1] < e[1]; p[1]++)
                 for (p[2] = 0; p[2] < e[2]; p[2]++)
                     V[d][(p[0] * e[1] + p[1]) * e[2] + p[2]] =
                         pseudo_velocity(g, d, x, c, G, p);
+        }
     }
 }
 
@@ -367,8 +380,9 @@ static void fct_limit(const grid_t *g, const double *psi_n, const double *x,
                       const double *G, double *V[3], double *const Vlim[3],
                       double *beta_up, double *beta_dn)
 {
-    long p[3];
-    for (p[0] = 0; p[0] < g->n[0]; p[0]++)
+    ROWS_IN_PARALLEL
+    for (long i0 = 0; i0 < g->n[0]; i0++) {
+        long p[3] = {i0, 0, 0};
         for (p[1] = 0; p[1] < g->n[1]; p[1]++)
             for (p[2] = 0; p[2] < g->n[2]; p[2]++) {
                 double mx = at(g, psi_n, p), mn = mx;
@@ -406,11 +420,14 @@ static void fct_limit(const grid_t *g, const double *psi_n, const double *x,
                 beta_up[k] = fin > 0.0 ? Gi * (mx - xi) / fin : 1.0;
                 beta_dn[k] = fout > 0.0 ? Gi * (xi - mn) / fout : 1.0;
             }
+    }
 
     for (int d = 0; d < g->ndims; d++) {
         long e[3] = {g->n[0], g->n[1], g->n[2]};
         e[d] += 1;
-        for (p[0] = 0; p[0] < e[0]; p[0]++)
+        ROWS_IN_PARALLEL
+        for (long i0 = 0; i0 < e[0]; i0++) {
+            long p[3] = {i0, 0, 0};
             for (p[1] = 0; p[1] < e[1]; p[1]++)
                 for (p[2] = 0; p[2] < e[2]; p[2]++) {
                     long L[3], R[3];
@@ -427,6 +444,7 @@ static void fct_limit(const grid_t *g, const double *psi_n, const double *x,
                     Vlim[d][(p[0] * e[1] + p[1]) * e[2] + p[2]] =
                         pos(v) * up + neg(v) * dn;
                 }
+        }
     }
 }
 
@@ -554,6 +572,16 @@ int orc_step(int ndims, const long n[3], const int bc[3], int n_iters,
     free(tmp);
     work_free(&w);
     return 0;
+}
+
+/* Threads the stage loops use (1 unless built with -fopenmp). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */

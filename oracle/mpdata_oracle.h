@@ -67,6 +67,10 @@ int orc_adjoint(int ndims, const long n[3], const int bc[3], int n_iters,
                 double *grad_psi0, double *grad_c0, double *grad_c1,
                 double *grad_c2);
 
+/* Threads the stage loops of orc_step use: 1, or the OpenMP thread count
+ * when the file is built with -fopenmp (the multi-core CPU baseline). */
+int orc_threads(void);
+
 #ifdef __cplusplus
 }
 #endif
