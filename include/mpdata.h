@@ -110,7 +110,9 @@ size_t mpdata_workspace_bytes(const mpdata_desc *desc);
  * least mpdata_workspace_bytes(desc) bytes, 256-byte aligned, owned by the
  * caller and kept alive until mpdata_destroy) and `hip_stream` (a
  * hipStream_t; NULL = the default stream).
- * Rejects: n_dims outside 1..3, a shape < 1 (< 3 along a periodic dimension),
+ * Rejects: n_dims outside 1..3, a shape < 1 (< 3 along a periodic dimension)
+ * or >= 2^30 (cells and walls of a dimension are indexed in 32 bits with
+ * halo offsets), more than 2^40 cells,
  * n_iters outside 1..8, unknown option bits, bc or dtype values
  * (MPDATA_EINVAL); the infinite gauge with n_iters > 2 (MPDATA_EUNSUPPORTED:
  * its pseudo-velocity is a flux, not a Courant number, so it cannot drive a
@@ -224,13 +226,22 @@ int mpdata_sw_step(mpdata_plan *plan, void *h, void *const q[3], void *h_prev,
 /* Diagnostics of psi (waits for the result): out[0] = sum of G*psi over the
  * finite cells (FP64, compensated), out[1] = min, out[2] = max of the finite
  * values, *n_nonfinite = number of NaN/Inf cells.  Returns MPDATA_ENONFINITE
- * (after filling the outputs) when *n_nonfinite > 0.  g may be NULL. */
+ * (after filling the outputs) when *n_nonfinite > 0.  g may be NULL.
+ * The sum is the conserved quantity of the flux form (Sect. 1: the scheme is
+ * conservative); the non-finite count is the run-time counterpart of the
+ * paper's NaN checks in debug builds (Sect. 2.4).  Every step kernel lets a
+ * NaN or infinity in psi or in the advector reach psi of the next step
+ * (the donor-cell flux is formed as a product with the advector), so a
+ * failed run shows here. */
 int mpdata_diag(mpdata_plan *plan, const void *psi, const void *g,
                 double out_sum_min_max[3], int64_t *n_nonfinite);
 
 /* max over cells of sum_d max(|c_d| on the two d-walls of the cell) / G
  * (waits for the result).  A value above 1 means the donor-cell pass can
- * empty a cell, so sign preservation (Sect. 1) is no longer guaranteed. */
+ * empty a cell, so sign preservation (Sect. 1) is no longer guaranteed.
+ * Cells whose walls or G hold a NaN or infinity are left out of the
+ * maximum and make the call return MPDATA_ENONFINITE (after *out is
+ * written): the input check before a run. */
 int mpdata_courant_max(mpdata_plan *plan, const void *g, const void *c0,
                        const void *c1, const void *c2, double *out);
 
@@ -332,8 +343,10 @@ int mpdata_step_per_grid(mpdata_plan *plan, void *psi_packed,
  * made by mpdata_step (the fused 2-D kernel, the 3-D donor + corrective
  * pair, the resident 1-D kernel -- one launch for all steps of a call -- or
  * the staged kernel sequence): a HIP event on the plan's stream before the
- * first of them and one after the latest, so time between the launches of
- * separate mpdata_step calls is included.  m = 0 switches timing off.
+ * first of them and one after the m-th (or, if fewer were made, one
+ * recorded by mpdata_timing_read), with no event in between, so time
+ * between the launches of separate mpdata_step calls is included.  m = 0
+ * switches timing off.
  * Timing does not change results.  mpdata_timing_read waits for the
  * recorded launches and returns the elapsed milliseconds of the window,
  * the number of launches in it and the name of what was launched (a static

@@ -33,8 +33,8 @@ def sources():
 
 
 KERNEL_SOURCE = {"k_fused2d": "fused2d.hpp", "k_fused2d_batched": "fused2d.hpp",
-                 "k_corr3d": "fused3d.hip", "k_donor3d": "fused3d.hip",
-                 "k_donor3d+k_corr3d": "fused3d.hip", "k_resident1d": "resident1d.hip",
+                 "k_step3d": "step3d.hip", "k_donor3d": "fused3d.hip",
+                 "k_resident1d": "resident1d.hip",
                  "k_pass2d": "pass2d.hip", "k_donor2d": "pass2d.hip"}
 
 

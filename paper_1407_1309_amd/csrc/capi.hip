@@ -105,8 +105,11 @@ int check_desc(const mpdata_desc *d, mp::Geom *g)
             if (d->shape[k] < lo)
                 return fail(MPDATA_EINVAL, "shape[%d] = %lld below %lld", k,
                             (long long)d->shape[k], (long long)lo);
-            if (d->shape[k] > (int64_t)1 << 31)
-                return fail(MPDATA_EINVAL, "shape[%d] too large", k);
+            // kernels index cells and walls of one dimension in 32 bits,
+            // with halo offsets of a few cells on either side
+            if (d->shape[k] >= (int64_t)1 << 30)
+                return fail(MPDATA_EINVAL, "shape[%d] = %lld is 2^30 or more", k,
+                            (long long)d->shape[k]);
             g->n[k] = d->shape[k];
             g->bc[k] = d->bc[k];
         } else {
@@ -193,8 +196,10 @@ struct mpdata_plan {
 namespace {
 
 // Brackets of a timed launch: timer_begin records the window's start event
-// before the first timed launch; timer_end moves the stop event after the
-// launch.  Launches beyond the limit are not timed.
+// before the first timed launch; timer_end records the stop event after the
+// last one the window holds (no event between the launches, so the window
+// covers the same back-to-back launches as an untimed run).  Launches beyond
+// the limit are not timed.
 bool timer_begin(mpdata_plan *p, const char *name)
 {
     if (!p->timing || p->t_launches >= p->t_limit) return false;
@@ -205,8 +210,8 @@ bool timer_begin(mpdata_plan *p, const char *name)
 
 void timer_end(mpdata_plan *p)
 {
-    (void)hipEventRecord(p->tev[1], p->stream);
     p->t_launches++;
+    if (p->t_launches == p->t_limit) (void)hipEventRecord(p->tev[1], p->stream);
 }
 
 // kernels of one step: stage by stage, the whole-step fused kernels, or the
@@ -222,7 +227,7 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
     const char *name = path == PATH_PASS2D ? "k_pass2d"
                        : !fused            ? "staged step"
                        : p->desc.n_dims == 3
-                           ? (p->desc.n_iters == 1 ? "k_donor3d" : "k_donor3d+k_corr3d")
+                           ? (p->desc.n_iters == 1 ? "k_donor3d" : "k_step3d")
                            : "k_fused2d";
     bool tm = timed && timer_begin(p, name);
     if (path == PATH_PASS2D) {
@@ -245,7 +250,7 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
         }
     } else if (fused && p->desc.n_dims == 3) {
         e = mp::fused3d_step<T>(p->g, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, c2,
-                                G, (T *)p->L.tmp[0], p->tile_rows, p->stream);
+                                G, p->tile_rows, p->stream);
     } else if (fused) {
         mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1], p->tile_rows};
         e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, G,
@@ -924,11 +929,14 @@ int mpdata_courant_max(mpdata_plan *plan, const void *g, const void *c0, const v
                                       (const float *)c2, (const float *)g, plan->L.part,
                                       plan->L.out + 4, plan->stream);
     if (e != hipSuccess) return hip_fail(e, "courant launch");
-    double h;
-    e = hipMemcpyAsync(&h, plan->L.out + 4, sizeof h, hipMemcpyDeviceToHost, plan->stream);
+    double h[2];
+    e = hipMemcpyAsync(h, plan->L.out + 4, sizeof h, hipMemcpyDeviceToHost, plan->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
     if (e != hipSuccess) return hip_fail(e, "courant copy");
-    *out = h;
+    *out = h[0];
+    if (h[1] > 0)
+        return fail(MPDATA_ENONFINITE, "%lld cells with a non-finite advector or G",
+                    (long long)h[1]);
     return MPDATA_OK;
 }
 
@@ -1372,7 +1380,13 @@ int mpdata_timing_read(mpdata_plan *plan, double *total_ms, int *launches, const
     *launches = plan->t_launches;
     if (kernel) *kernel = plan->tname;
     if (plan->t_launches == 0) return MPDATA_OK;
-    hipError_t e = hipEventSynchronize(plan->tev[1]);
+    hipError_t e = hipSuccess;
+    if (plan->t_launches < plan->t_limit) {
+        // the window is not full: close it now, after the launches made
+        e = hipEventRecord(plan->tev[1], plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    e = hipEventSynchronize(plan->tev[1]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     float ms = 0.0f;
     e = hipEventElapsedTime(&ms, plan->tev[0], plan->tev[1]);

@@ -73,6 +73,25 @@ __device__ inline void unflat3(int64_t t, const int64_t e[3], int v[3])
 template <typename T> __device__ inline T pos(T u) { return u > T(0) ? u : T(0); }
 template <typename T> __device__ inline T neg(T u) { return u < T(0) ? u : T(0); }
 
+// Donor-cell flux of eq. F across a wall with advector u, between the cell
+// below the wall (value xl) and the cell above it (xr): [u]+ xl + [u]- xr.
+// Formed as a product with u, so that a NaN or infinite advector makes the
+// flux, and with it the two cells beside the wall, non-finite: the sum form
+// with [u]+ = max(u, 0) and [u]- = min(u, 0) turns a NaN advector into 0
+// and hides it from the diagnostics.  For finite values the two forms are
+// equal (the dropped product of the sum is a signed zero).  upwind() keeps
+// the derivative with respect to u at u = 0 equal to 0 (the kink convention
+// of the reverse mode) when T is a dual number; upwind_fp() is the plain
+// floating-point form, where at u = 0 either cell gives +-0.
+template <typename T> __device__ inline T upwind(T u, T xl, T xr)
+{
+    return u * (u > T(0) ? xl : (u < T(0) ? xr : T(0)));
+}
+template <typename T> __device__ __forceinline__ T upwind_fp(T u, T xl, T xr)
+{
+    return u * (u > T(0) ? xl : xr);
+}
+
 // Quotients.
 // FP64: the quotients of a stage are formed together.  When every lane's
 // divisors are zero or normal and below 2^1000 in magnitude (a wave-uniform

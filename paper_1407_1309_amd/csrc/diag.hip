@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(DB) k_courant_part(Geom g, const T *c0, const 
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
     const T *c[3] = {c0, c1, c2};
-    double best = 0.0;
+    double best = 0.0, bad = 0.0;
     int64_t stride = (int64_t)gridDim.x * DB;
     for (int64_t t = (int64_t)blockIdx.x * DB + threadIdx.x; t < N; t += stride) {
         int64_t p[3];
@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(DB) k_courant_part(Geom g, const T *c0, const 
         p[1] = r % g.n[1];
         p[0] = r / g.n[1];
         double s = 0.0;
+        bool fin = true;
         for (int d = 0; d < g.nd; d++) {
             int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
             e[d] += 1;
@@ -144,23 +145,43 @@ __global__ void __launch_bounds__(DB) k_courant_part(Geom g, const T *c0, const 
             int64_t lo = (q[0] * e[1] + q[1]) * e[2] + q[2];
             q[d] = map_wall(p[d] + 1, g.n[d], g.bc[d]);
             int64_t hi = (q[0] * e[1] + q[1]) * e[2] + q[2];
-            s += fmax(fabs((double)c[d][lo]), fabs((double)c[d][hi]));
+            const double a = fabs((double)c[d][lo]), b = fabs((double)c[d][hi]);
+            fin = fin && isfinite(a + b);      // fmax alone would pass over a NaN
+            s += fmax(a, b);
         }
-        if (G) s /= (double)G[t];
+        if (G) {
+            const double gt = (double)G[t];
+            fin = fin && isfinite(gt);
+            s /= gt;
+        }
+        if (!fin || !isfinite(s)) {
+            bad += 1.0;
+            continue;
+        }
         best = fmax(best, s);
     }
-    Acc A = {0.0, 0.0, INFINITY, best, 0.0};
+    Acc A = {0.0, 0.0, INFINITY, best, bad};
     block_reduce(A);
-    if (threadIdx.x == 0) part[5 * blockIdx.x + 3] = A.mx;
+    if (threadIdx.x == 0) {
+        part[5 * blockIdx.x + 3] = A.mx;
+        part[5 * blockIdx.x + 4] = A.bad;
+    }
 }
 
+// out[0] = largest finite Courant sum, out[1] = cells with a non-finite one
 __global__ void __launch_bounds__(DB) k_courant_final(const double *part, int nparts, double *out)
 {
-    double best = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += DB) best = fmax(best, part[5 * i + 3]);
-    Acc A = {0.0, 0.0, INFINITY, best, 0.0};
+    double best = 0.0, bad = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += DB) {
+        best = fmax(best, part[5 * i + 3]);
+        bad += part[5 * i + 4];
+    }
+    Acc A = {0.0, 0.0, INFINITY, best, bad};
     block_reduce(A);
-    if (threadIdx.x == 0) out[0] = A.mx;
+    if (threadIdx.x == 0) {
+        out[0] = A.mx;
+        out[1] = A.bad;
+    }
 }
 
 int blocks_for(int64_t N)

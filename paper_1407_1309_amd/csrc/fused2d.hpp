@@ -346,9 +346,9 @@ template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Str
 
         // donor-cell pass at row t-1
         T x = AT(pq, C::QP, 1);
-        T f0lo = pos(AT(dc0, 2, 1)) * AT(pq, C::QP, 2) + neg(AT(dc0, 2, 1)) * x;
-        T f0hi = pos(AT(dc0, 2, 0)) * x + neg(AT(dc0, 2, 0)) * AT(pq, C::QP, 0);
-        T f1lo = pos(AT(dc1, 2, 1)) * from_left(x) + neg(AT(dc1, 2, 1)) * x;
+        T f0lo = upwind_fp(AT(dc0, 2, 1), AT(pq, C::QP, 2), x);
+        T f0hi = upwind_fp(AT(dc0, 2, 0), x, AT(pq, C::QP, 0));
+        T f1lo = upwind_fp(AT(dc1, 2, 1), from_left(x), x);
         T f1hi = from_right(f1lo);
         T y = donor_update<KH>(x, f0hi - f0lo, f1hi - f1lo);
         T cn0 = AT(dc0, 2, 1), cn1 = AT(dc1, 2, 1);

@@ -45,7 +45,8 @@ template <typename T>
 hipError_t diag_launch(const T *psi, const T *G, int64_t N, double *part, double *out,
                        hipStream_t s);
 
-// out[0] = max over cells of sum_d max(|c_d| lo, |c_d| hi) / G.
+// out[0] = max over cells of sum_d max(|c_d| lo, |c_d| hi) / G where it is
+// finite; out[1] = the number of cells where it is not.
 template <typename T>
 hipError_t courant_launch(const Geom &g, const T *c0, const T *c1, const T *c2, const T *G,
                           double *part, double *out, hipStream_t s);
@@ -64,12 +65,17 @@ template <typename T>
 hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
                         T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s);
 
-// ---- 3-D, two passes without the limiter: donor kernel + corrective kernel
+// ---- 3-D, two passes without the limiter: one launch per step (step3d.hip;
+// the donor-only step and the fallback are the kernel pair of fused3d.hip)
+bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3]);
+template <typename T>
+hipError_t step3d_launch(const Geom &g, unsigned opts, const T *psi_n, T *psi_out, const T *c0,
+                         const T *c1, const T *c2, const T *G, int tile_planes, hipStream_t s);
 bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], const int bc[3]);
 template <typename T>
 hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_n, T *psi_out,
-                        const T *c0, const T *c1, const T *c2, const T *G, T *y1buf,
-                        int tile_planes, hipStream_t s);
+                        const T *c0, const T *c1, const T *c2, const T *G, int tile_planes,
+                        hipStream_t s);
 
 // ---- one corrective pass of a 2-D step in one launch (pass2d.hip) --------
 // G = 1, no third-order terms, any boundaries; x: previous pass's result,

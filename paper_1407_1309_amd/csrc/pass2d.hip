@@ -162,9 +162,9 @@ template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR> struct March {
             load(S);
             const T pc = AT(pq, 4, 1), pm = AT(pq, 4, 2), pp = AT(pq, 4, 0);
             const T u0lo = AT(c0q, 4, 1), u0hi = AT(c0q, 4, 0), u1 = AT(c1q, 4, 1);
-            const T f0lo = pos(u0lo) * pm + neg(u0lo) * pc;
-            const T f0hi = pos(u0hi) * pc + neg(u0hi) * pp;
-            const T f1lo = pos(u1) * from_left(pc) + neg(u1) * pc;
+            const T f0lo = upwind_fp(u0lo, pm, pc);
+            const T f0hi = upwind_fp(u0hi, pc, pp);
+            const T f1lo = upwind_fp(u1, from_left(pc), pc);
             const T f1hi = from_right(f1lo);
             x_a = edge_cols(donor_update(kahan, pc, f0hi - f0lo, f1hi - f1lo));
             if (bc0 == BC_OPEN && a >= n0) x_a = AT(xq, 4, 1);   // rows past the end
@@ -509,10 +509,10 @@ __global__ void __launch_bounds__(DB)
     const int64_t r1 = (int64_t)row * (n1 + 1);
     const T u1lo = c1[r1 + j];
     const T u1hi = c1[r1 + wrap_wall(j + 1, n1, bc1)];
-    const T f0lo = pos(u0lo) * x[rm + j] + neg(u0lo) * xc;
-    const T f0hi = pos(u0hi) * xc + neg(u0hi) * x[rp + j];
-    const T f1lo = pos(u1lo) * x[r + jm] + neg(u1lo) * xc;
-    const T f1hi = pos(u1hi) * xc + neg(u1hi) * x[r + jp];
+    const T f0lo = upwind_fp(u0lo, x[rm + j], xc);
+    const T f0hi = upwind_fp(u0hi, xc, x[rp + j]);
+    const T f1lo = upwind_fp(u1lo, x[r + jm], xc);
+    const T f1hi = upwind_fp(u1hi, xc, x[r + jp]);
     out[r + j] = donor_update(kahan != 0, xc, f0hi - f0lo, f1hi - f1lo);
     if (copy) copy[r + j] = xc;
 }

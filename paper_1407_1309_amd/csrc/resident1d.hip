@@ -88,8 +88,8 @@ __global__ void __launch_bounds__(RB) k_resident1d(int n, int bc, int n_iters, u
         // donor-cell pass: F -> Y
         for (int i = tid; i < n; i += RB) {
             T ul = C[mw(i, n, bc)], uh = C[mw(i + 1, n, bc)];
-            T flo = pos(ul) * F[mc(i - 1, n, bc)] + neg(ul) * F[i];
-            T fhi = pos(uh) * F[i] + neg(uh) * F[mc(i + 1, n, bc)];
+            T flo = upwind_fp(ul, F[mc(i - 1, n, bc)], F[i]);
+            T fhi = upwind_fp(uh, F[i], F[mc(i + 1, n, bc)]);
             T acc = fhi - flo;
             Y[i] = upd(F[i], acc, i);
         }

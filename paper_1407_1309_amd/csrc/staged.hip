@@ -89,7 +89,7 @@ __global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c
             if (flux_is_vel)
                 fl[s] = u;
             else
-                fl[s] = pos(u) * cell(g, x, shifted(w, d, -1)) + neg(u) * cell(g, x, w);
+                fl[s] = upwind(u, cell(g, x, shifted(w, d, -1)), cell(g, x, w));
         }
         acc += fl[1] - fl[0];
         if (kahan) {

@@ -1,0 +1,478 @@
+// step3d.hip -- a whole 3-D MPDATA step with two passes and no limiter in
+// one launch (donor-cell pass, pseudo-velocity with its cross and
+// third-order terms, corrective pass; infinite gauge, variable G, both
+// boundary types).
+//
+// A workgroup of SJ x SK threads owns a tile of SJ x SK (j, k) output
+// columns and marches along i over a chunk of planes.  In the iteration
+// that brings plane t on chip it
+//   1. stores the planes its global loads fetched during the previous
+//      iteration into LDS rings: psi^n (plane t+1, the tile with a ring of 3
+//      cells), the dimension-0 advector (wall t+1), the dimension-1 and
+//      dimension-2 advectors and G (plane t), each on the tile with a ring
+//      of 2 cells; then issues the loads of the next iteration;
+//   2. forms the donor-cell result y1 of plane t on the tile and its ring of
+//      2 cells from LDS, so y1 never goes through HBM;
+//   3. forms the pseudo-velocities (eq. adf_vel with the multi-dimensional
+//      cross terms and the third-order terms): V0 at the wall between planes
+//      t-2 and t-1 of its own column, V1 and V2 at plane t-2 on the low walls
+//      of its own cell (the tile's far edge walls by the first threads);
+//   4. applies the corrective pass to plane t-2 of its own column.
+// Three barriers per plane.  Every thread computes one output cell (the
+// ring's y1 cells are shared out as a second cell to the first threads), so
+// no thread only recomputes a halo.
+//
+// Boundaries: every global read goes through the boundary map (periodic
+// wrap / open clamp), so ring positions hold mapped values.  The y1 of a
+// cell outside an open domain must be the edge cell's (what the stage-by-
+// stage path reads there): in j and k it is computed at the clamped
+// position, in i it is read from the edge plane's ring slot.
+//
+// The donor-cell arithmetic is that of k_donor3d (fused3d.hip), term by
+// term in the same order, so the two give the same bits.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mp {
+namespace {
+
+constexpr int SJ = 16, SK = 32, NT = SJ * SK;   // output tile and threads
+constexpr int BJ = SJ + 4, BK = SK + 4;         // y1 box: tile + ring of 2
+constexpr int PJ = SJ + 6, PK = SK + 6;         // psi^n box: tile + ring of 3
+constexpr int NY = BJ * BK;                     // cells of a y1 box plane
+constexpr int NP = PJ * PK;                     // cells of a psi^n box plane
+constexpr int N1 = (BJ + 1) * BK;               // dimension-1 walls of the box
+constexpr int N2 = BJ * (BK + 1);               // dimension-2 walls of the box
+static_assert(NY <= 2 * NT && NP <= 2 * NT && N1 <= 2 * NT && N2 <= 2 * NT,
+              "each thread loads at most two entries of every box plane");
+static_assert(SK <= NT && SK + SJ <= NT, "far-edge walls need that many threads");
+
+struct G3s {
+    int n0, n1, n2;
+    int bc0, bc1, bc2;
+};
+
+template <typename T, bool IGA> __device__ __forceinline__ T fr3(T num, T den, T m)
+{
+    if (IGA) return num * (T(1) / m);
+    return den == T(0) ? T(0) : num / den;
+}
+
+// ring slot of a virtual plane index t >= -12
+__device__ __forceinline__ int slot3(int t) { return (t + 12) % 3; }
+__device__ __forceinline__ int slot4(int t) { return (t + 12) & 3; }
+
+// in-plane offset of box entry e of a box with `w` entries per row, the
+// box's origin at (jb, kb) in global cell (or wall) coordinates; `wall_j` /
+// `wall_k` mark the dimension whose coordinate is a wall index.  -1 when e
+// is past the box.
+__device__ __forceinline__ int64_t box_offset(int e, int n_e, int w, int jb, int kb, bool wall_j,
+                                              bool wall_k, const G3s &g, int64_t row_len)
+{
+    if (e >= n_e) return -1;
+    const int bj = e / w, bk = e % w;
+    const int64_t j = wall_j ? map_wall(jb + bj, g.n1, g.bc1) : map_cell(jb + bj, g.n1, g.bc1);
+    const int64_t k = wall_k ? map_wall(kb + bk, g.n2, g.bc2) : map_cell(kb + bk, g.n2, g.bc2);
+    return j * row_len + k;
+}
+
+template <typename T, bool HAS_G, bool IGA, bool TOT>
+__global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int tiles_j, int nblk,
+                                               int kahan, const T *__restrict__ x,
+                                               const T *__restrict__ c0,
+                                               const T *__restrict__ c1,
+                                               const T *__restrict__ c2,
+                                               const T *__restrict__ G, T *__restrict__ out)
+{
+    __shared__ T Ps[3][NP];                              // psi^n, planes t-1..t+1
+    __shared__ T Ys[4][NY];                              // y1, planes t-3..t
+    __shared__ T C0s[4][NY];                             // c0, walls t-2..t+1
+    __shared__ T C1s[3][N1];                             // c1, planes t-2..t
+    __shared__ T C2s[3][N2];                             // c2, planes t-2..t
+    __shared__ T Gs[HAS_G ? 3 : 1][HAS_G ? NY : 1];      // G, planes t-2..t
+    __shared__ T V1s[(SJ + 1) * SK];                     // V1 at plane t-2
+    __shared__ T V2s[SJ * (SK + 1)];                     // V2 at plane t-2
+
+    const int tid = threadIdx.x;
+    const int r = tid / SK, l = tid % SK;
+    // The hardware deals workgroup b to XCD b % 8; tiles are numbered so that
+    // consecutive tiles (which share ring cells) run on one XCD and its L2.
+    int b;
+    {
+        const int xq = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
+        b = xq * per + (xq < rem ? xq : rem) + (blockIdx.x >> 3);
+    }
+    const int tk = b % tiles_k;
+    b /= tiles_k;
+    const int tj = b % tiles_j;
+    const int ch = b / tiles_j;
+    const int j0 = tj * SJ, k0 = tk * SK;
+    const int i0 = ch * th, i1 = min(i0 + th, g.n0);
+    const int64_t pl = (int64_t)g.n1 * g.n2, pl1 = (int64_t)(g.n1 + 1) * g.n2,
+                  pl2 = (int64_t)g.n1 * (g.n2 + 1);
+
+    // in-plane offsets of the box entries this thread loads (two per array)
+    int64_t oP[2], oY[2], o1[2], o2[2];
+    for (int m = 0; m < 2; m++) {
+        const int e = tid + m * NT;
+        oP[m] = box_offset(e, NP, PK, j0 - 3, k0 - 3, false, false, g, g.n2);
+        oY[m] = box_offset(e, NY, BK, j0 - 2, k0 - 2, false, false, g, g.n2);
+        o1[m] = box_offset(e, N1, BK, j0 - 2, k0 - 2, true, false, g, g.n2);
+        o2[m] = box_offset(e, N2, BK + 1, j0 - 2, k0 - 2, false, true, g, g.n2 + 1);
+    }
+    // y1 cells this thread forms: box entries tid and tid + NT, each at its
+    // effective position (the clamped cell outside an open domain)
+    int ye[2], yp[2];
+    bool yon[2];
+    for (int m = 0; m < 2; m++) {
+        const int e = tid + m * NT;
+        yon[m] = e < NY;
+        const int bj = yon[m] ? e / BK : 0, bk = yon[m] ? e % BK : 0;
+        int ej = bj, ek = bk;
+        if (g.bc1 == BC_OPEN) ej = min(max(j0 - 2 + bj, 0), g.n1 - 1) - (j0 - 2);
+        if (g.bc2 == BC_OPEN) ek = min(max(k0 - 2 + bk, 0), g.n2 - 1) - (k0 - 2);
+        ye[m] = ej * BK + ek;      // effective entry in the y1 box
+        yp[m] = bj * BK + bk;      // where the result goes
+    }
+
+    // prefetched plane values (stored to LDS at the start of the next
+    // iteration): psi^n, c0 (two entries each), c1, c2, G
+    T fP[2], fC0[2], fC1[2], fC2[2], fG[2];
+    auto fetch = [&](int t) {
+        const int64_t ip = map_cell(t + 1, g.n0, g.bc0) * pl;     // psi^n plane t+1
+        const int64_t iw = map_wall(t + 1, g.n0, g.bc0) * pl;     // c0 wall t+1
+        const int64_t ic = map_cell(t, g.n0, g.bc0);              // plane t
+        for (int m = 0; m < 2; m++) {
+            if (oP[m] >= 0) fP[m] = x[ip + oP[m]];
+            if (oY[m] >= 0) fC0[m] = c0[iw + oY[m]];
+            if (o1[m] >= 0) fC1[m] = c1[ic * pl1 + o1[m]];
+            if (o2[m] >= 0) fC2[m] = c2[ic * pl2 + o2[m]];
+            if (HAS_G && oY[m] >= 0) fG[m] = G[ic * pl + oY[m]];
+        }
+    };
+    auto store = [&](int t) {
+        const int sp = slot3(t + 1), sw = slot4(t + 1), sc = slot3(t);
+        for (int m = 0; m < 2; m++) {
+            const int e = tid + m * NT;
+            if (oP[m] >= 0) Ps[sp][e] = fP[m];
+            if (oY[m] >= 0) C0s[sw][e] = fC0[m];
+            if (o1[m] >= 0) C1s[sc][e] = fC1[m];
+            if (o2[m] >= 0) C2s[sc][e] = fC2[m];
+            if (HAS_G && oY[m] >= 0) Gs[sc][e] = fG[m];
+        }
+    };
+
+    const int t_first = i0 - 2, t_last = i1 + 1;
+    // prologue: psi^n planes t_first-1 and t_first, c0 wall t_first
+    {
+        const int64_t ipm = map_cell(t_first - 1, g.n0, g.bc0) * pl;
+        const int64_t ip0 = map_cell(t_first, g.n0, g.bc0) * pl;
+        const int64_t iw0 = map_wall(t_first, g.n0, g.bc0) * pl;
+        for (int m = 0; m < 2; m++) {
+            const int e = tid + m * NT;
+            if (oP[m] >= 0) {
+                Ps[slot3(t_first - 1)][e] = x[ipm + oP[m]];
+                Ps[slot3(t_first)][e] = x[ip0 + oP[m]];
+            }
+            if (oY[m] >= 0) C0s[slot4(t_first)][e] = c0[iw0 + oY[m]];
+        }
+    }
+    fetch(t_first);
+
+    const bool open0 = g.bc0 == BC_OPEN;
+    // y1 ring slot of virtual plane q (open: planes outside the domain read
+    // the edge plane)
+    auto yslot = [&](int q) { return slot4(open0 ? min(max(q, 0), g.n0 - 1) : q); };
+    // own cell in the boxes
+    const int bj = r + 2, bk = l + 2;
+    const int cy = bj * BK + bk;
+    const bool own_out = j0 + r < g.n1 && k0 + l < g.n2;
+    T v0_lo = T(0);      // V0 at the low wall of the plane being corrected
+
+    for (int t = t_first; t <= t_last; t++) {
+        store(t);
+        if (t < t_last) fetch(t + 1);
+        __syncthreads();   // (B1) plane t's inputs are in LDS
+
+        // ---- donor-cell pass: y1 of plane t on the box ----
+        if (!open0 || (t >= 0 && t < g.n0)) {
+            const int pm = slot3(t - 1), p0 = slot3(t), pp = slot3(t + 1);
+            const int wl = slot4(t), wh = slot4(t + 1), sc = slot3(t), sy = slot4(t);
+            for (int m = 0; m < 2; m++) {
+                if (!yon[m]) continue;
+                const int ee = ye[m];
+                const int ej = ee / BK, ek = ee % BK;
+                const int q = (ej + 1) * PK + (ek + 1);        // psi^n box entry
+                const T xc = Ps[p0][q];
+                T dv[3];
+                {
+                    T flo = upwind_fp(C0s[wl][ee], Ps[pm][q], xc);
+                    T fhi = upwind_fp(C0s[wh][ee], xc, Ps[pp][q]);
+                    dv[0] = fhi - flo;
+                }
+                {
+                    T flo = upwind_fp(C1s[sc][ej * BK + ek], Ps[p0][q - PK], xc);
+                    T fhi = upwind_fp(C1s[sc][(ej + 1) * BK + ek], xc, Ps[p0][q + PK]);
+                    dv[1] = fhi - flo;
+                }
+                {
+                    T flo = upwind_fp(C2s[sc][ej * (BK + 1) + ek], Ps[p0][q - 1], xc);
+                    T fhi = upwind_fp(C2s[sc][ej * (BK + 1) + ek + 1], xc, Ps[p0][q + 1]);
+                    dv[2] = fhi - flo;
+                }
+                T y;
+                if (kahan) {
+                    T ks = xc, kc = T(0);
+#pragma unroll
+                    for (int d = 0; d < 3; d++)
+                        kahan_add(ks, kc, -(HAS_G ? dv[d] / Gs[sc][ee] : dv[d]));
+                    y = ks;
+                } else {
+                    T acc = T(0);
+                    acc += dv[0];
+                    acc += dv[1];
+                    acc += dv[2];
+                    y = xc - (HAS_G ? acc / Gs[sc][ee] : acc);
+                }
+                Ys[sy][yp[m]] = y;
+            }
+        }
+        __syncthreads();   // (B2) y1 of plane t is in LDS
+
+        // ---- pseudo-velocities ----
+        const int p = t - 2;
+        const int sA = yslot(p - 1), sB = yslot(p), sC = yslot(p + 1), sD = yslot(p + 2);
+        const int cs = slot3(p), cs1 = slot3(p + 1);      // c1, c2, G planes p, p+1
+        const int ws = slot4(p), ws1 = slot4(p + 1);      // c0 walls p, p+1
+        const T *YA = Ys[sA], *YB = Ys[sB], *YC = Ys[sC];
+
+        // V0 at wall p+1 (planes p | p+1) of column (bj, bk)
+        auto vel0 = [&]() -> T {
+            const int c = cy;
+            T ig = T(1);
+            if (HAS_G) {
+                T one[1] = {T(1)}, gb[1] = {T(0.5) * (Gs[cs][c] + Gs[cs1][c])}, q[1];
+                quotients<1>(one, gb, q);
+                ig = q[0];
+            }
+            const T xL = YB[c], xR = YC[c];
+            const T u = C0s[ws1][c];
+            T A = fr3<T, IGA>(xR - xL, xR + xL, T(2));
+            T v = (fabs(u) - u * u * ig) * A;
+            const int w1 = bj * BK + bk, w1p = (bj + 1) * BK + bk;
+            const T s1a = C1s[cs][w1] + C1s[cs1][w1], s1b = C1s[cs][w1p] + C1s[cs1][w1p];
+            const int w2 = bj * (BK + 1) + bk;
+            const T s2a = C2s[cs][w2] + C2s[cs1][w2], s2b = C2s[cs][w2 + 1] + C2s[cs1][w2 + 1];
+            const T cb1 = T(0.25) * (s1a + s1b);
+            const T cb2 = T(0.25) * (s2a + s2b);
+            // o = 1 (j)
+            T a1 = YC[c + BK], b1 = YB[c + BK], e1 = YC[c - BK], f1 = YB[c - BK];
+            v -= T(0.5) * u * cb1 * ig * fr3<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
+            // o = 2 (k)
+            T a2 = YC[c + 1], b2 = YB[c + 1], e2 = YC[c - 1], f2 = YB[c - 1];
+            v -= T(0.5) * u * cb2 * ig * fr3<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
+            if (TOT) {
+                const T xR2 = Ys[sD][c], xL2 = YA[c];
+                v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
+                     fr3<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
+                v += (fabs(u) * cb1 * ig - T(2) * u * u * cb1 * (ig * ig)) *
+                     fr3<T, IGA>(a1 - b1 - e1 + f1, a1 + b1 + e1 + f1, T(4));
+                v += (fabs(u) * cb2 * ig - T(2) * u * u * cb2 * (ig * ig)) *
+                     fr3<T, IGA>(a2 - b2 - e2 + f2, a2 + b2 + e2 + f2, T(4));
+                T num = T(0), den = T(0);
+                for (int sd = 0; sd < 2; sd++) {
+                    const T *Yp = sd ? YC : YB;
+                    T pp_ = Yp[c + BK + 1], mp_ = Yp[c - BK + 1], pm_ = Yp[c + BK - 1],
+                      mm_ = Yp[c - BK - 1];
+                    num += pp_ - mp_ - pm_ + mm_;
+                    den += pp_ + mp_ + pm_ + mm_;
+                }
+                v += -(T(2) / T(3)) * u * cb1 * cb2 * (ig * ig) * fr3<T, IGA>(num, den, T(8));
+            }
+            return v;
+        };
+        // V1 at plane p, wall between box rows wj-1 | wj, lane wk
+        auto vel1 = [&](int wj, int wk) -> T {
+            const int c = wj * BK + wk;
+            T ig = T(1);
+            if (HAS_G) {
+                T one[1] = {T(1)}, gb[1] = {T(0.5) * (Gs[cs][c - BK] + Gs[cs][c])}, q[1];
+                quotients<1>(one, gb, q);
+                ig = q[0];
+            }
+            const T xL = YB[c - BK], xR = YB[c];
+            const T u = C1s[cs][c];
+            T A = fr3<T, IGA>(xR - xL, xR + xL, T(2));
+            T v = (fabs(u) - u * u * ig) * A;
+            const T cb0 = T(0.25) * ((C0s[ws][c - BK] + C0s[ws1][c - BK]) + (C0s[ws][c] + C0s[ws1][c]));
+            const int w2 = wj * (BK + 1) + wk, w2m = (wj - 1) * (BK + 1) + wk;
+            const T cb2 = T(0.25) * ((C2s[cs][w2m] + C2s[cs][w2m + 1]) + (C2s[cs][w2] + C2s[cs][w2 + 1]));
+            // o = 0 (i)
+            T a0 = YC[c], b0 = YC[c - BK], e0 = YA[c], f0 = YA[c - BK];
+            v -= T(0.5) * u * cb0 * ig * fr3<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
+            // o = 2 (k)
+            T a2 = YB[c + 1], b2 = YB[c - BK + 1], e2 = YB[c - 1], f2 = YB[c - BK - 1];
+            v -= T(0.5) * u * cb2 * ig * fr3<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
+            if (TOT) {
+                const T xR2 = YB[c + BK], xL2 = YB[c - 2 * BK];
+                v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
+                     fr3<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
+                v += (fabs(u) * cb0 * ig - T(2) * u * u * cb0 * (ig * ig)) *
+                     fr3<T, IGA>(a0 - b0 - e0 + f0, a0 + b0 + e0 + f0, T(4));
+                v += (fabs(u) * cb2 * ig - T(2) * u * u * cb2 * (ig * ig)) *
+                     fr3<T, IGA>(a2 - b2 - e2 + f2, a2 + b2 + e2 + f2, T(4));
+                T num = T(0), den = T(0);
+                for (int sd = 0; sd < 2; sd++) {
+                    const int cc = sd ? c : c - BK;
+                    T pp_ = YC[cc + 1], mp_ = YA[cc + 1], pm_ = YC[cc - 1], mm_ = YA[cc - 1];
+                    num += pp_ - mp_ - pm_ + mm_;
+                    den += pp_ + mp_ + pm_ + mm_;
+                }
+                v += -(T(2) / T(3)) * u * cb0 * cb2 * (ig * ig) * fr3<T, IGA>(num, den, T(8));
+            }
+            return v;
+        };
+        // V2 at plane p, wall between box lanes wk-1 | wk, row wj
+        auto vel2 = [&](int wj, int wk) -> T {
+            const int c = wj * BK + wk;
+            T ig = T(1);
+            if (HAS_G) {
+                T one[1] = {T(1)}, gb[1] = {T(0.5) * (Gs[cs][c - 1] + Gs[cs][c])}, q[1];
+                quotients<1>(one, gb, q);
+                ig = q[0];
+            }
+            const T xL = YB[c - 1], xR = YB[c];
+            const T u = C2s[cs][wj * (BK + 1) + wk];
+            T A = fr3<T, IGA>(xR - xL, xR + xL, T(2));
+            T v = (fabs(u) - u * u * ig) * A;
+            const T cb0 = T(0.25) * ((C0s[ws][c - 1] + C0s[ws1][c - 1]) + (C0s[ws][c] + C0s[ws1][c]));
+            const T cb1 = T(0.25) * ((C1s[cs][c - 1] + C1s[cs][c - 1 + BK]) + (C1s[cs][c] + C1s[cs][c + BK]));
+            // o = 0 (i)
+            T a0 = YC[c], b0 = YC[c - 1], e0 = YA[c], f0 = YA[c - 1];
+            v -= T(0.5) * u * cb0 * ig * fr3<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
+            // o = 1 (j)
+            T a1 = YB[c + BK], b1 = YB[c + BK - 1], e1 = YB[c - BK], f1 = YB[c - BK - 1];
+            v -= T(0.5) * u * cb1 * ig * fr3<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
+            if (TOT) {
+                const T xR2 = YB[c + 1], xL2 = YB[c - 2];
+                v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
+                     fr3<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
+                v += (fabs(u) * cb0 * ig - T(2) * u * u * cb0 * (ig * ig)) *
+                     fr3<T, IGA>(a0 - b0 - e0 + f0, a0 + b0 + e0 + f0, T(4));
+                v += (fabs(u) * cb1 * ig - T(2) * u * u * cb1 * (ig * ig)) *
+                     fr3<T, IGA>(a1 - b1 - e1 + f1, a1 + b1 + e1 + f1, T(4));
+                T num = T(0), den = T(0);
+                for (int sd = 0; sd < 2; sd++) {
+                    const int cc = sd ? c : c - 1;
+                    T pp_ = YC[cc + BK], mp_ = YA[cc + BK], pm_ = YC[cc - BK], mm_ = YA[cc - BK];
+                    num += pp_ - mp_ - pm_ + mm_;
+                    den += pp_ + mp_ + pm_ + mm_;
+                }
+                v += -(T(2) / T(3)) * u * cb0 * cb1 * (ig * ig) * fr3<T, IGA>(num, den, T(8));
+            }
+            return v;
+        };
+
+        const T v0_hi = vel0();
+        V1s[r * SK + l] = vel1(bj, bk);
+        V2s[r * (SK + 1) + l] = vel2(bj, bk);
+        if (tid < SK) V1s[SJ * SK + tid] = vel1(SJ + 2, tid + 2);            // far j edge
+        else if (tid < SK + SJ) V2s[(tid - SK) * (SK + 1) + SK] = vel2(tid - SK + 2, SK + 2);
+        T g_own = T(1);
+        if (HAS_G) g_own = Gs[cs][cy];
+        __syncthreads();   // (B3) V1, V2 of plane p are in LDS
+
+        // ---- corrective pass at plane p ----
+        if (p >= i0 && p < i1 && own_out) {
+            const T xo = YB[cy];
+            const T V0lo = v0_lo, V0hi = v0_hi;
+            const T V1lo = V1s[r * SK + l], V1hi = V1s[(r + 1) * SK + l];
+            const T V2lo = V2s[r * (SK + 1) + l], V2hi = V2s[r * (SK + 1) + l + 1];
+            T f0lo, f0hi, f1lo, f1hi, f2lo, f2hi;
+            if (IGA) {
+                f0lo = V0lo; f0hi = V0hi; f1lo = V1lo; f1hi = V1hi; f2lo = V2lo; f2hi = V2hi;
+            } else {
+                f0lo = pos(V0lo) * YA[cy] + neg(V0lo) * xo;
+                f0hi = pos(V0hi) * xo + neg(V0hi) * YC[cy];
+                f1lo = pos(V1lo) * YB[cy - BK] + neg(V1lo) * xo;
+                f1hi = pos(V1hi) * xo + neg(V1hi) * YB[cy + BK];
+                f2lo = pos(V2lo) * YB[cy - 1] + neg(V2lo) * xo;
+                f2hi = pos(V2hi) * xo + neg(V2hi) * YB[cy + 1];
+            }
+            T res;
+            if (kahan) {
+                T dv[3] = {f0hi - f0lo, f1hi - f1lo, f2hi - f2lo};
+                if (HAS_G) {
+                    T gg[3] = {g_own, g_own, g_own}, qq[3];
+                    quotients<3>(dv, gg, qq);
+                    dv[0] = qq[0];
+                    dv[1] = qq[1];
+                    dv[2] = qq[2];
+                }
+                T ks = xo, kc = T(0);
+#pragma unroll
+                for (int d = 0; d < 3; d++) kahan_add(ks, kc, -dv[d]);
+                res = ks;
+            } else {
+                T acc = T(0);
+                acc += f0hi - f0lo;
+                acc += f1hi - f1lo;
+                acc += f2hi - f2lo;
+                if (HAS_G) {
+                    T nn[1] = {acc}, dd[1] = {g_own}, qq[1];
+                    quotients<1>(nn, dd, qq);
+                    acc = qq[0];
+                }
+                res = xo - acc;
+            }
+            out[((int64_t)p * g.n1 + (j0 + r)) * g.n2 + (k0 + l)] = res;
+        }
+        v0_lo = v0_hi;
+    }
+}
+
+}  // namespace
+
+bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3])
+{
+    if (nd != 3 || n_iters != 2 || (opts & (OPT_FCT | OPT_ABS | OPT_DFL))) return false;
+    // 32-bit plane and row indices inside the kernel
+    if (n[0] >= (1 << 30) || n[1] >= (1 << 30) || n[2] >= (1 << 30)) return false;
+    return true;
+}
+
+template <typename T>
+hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi_out, const T *c0,
+                         const T *c1, const T *c2, const T *G, int tile_planes, hipStream_t s)
+{
+    G3s g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
+    const int tiles_k = (g.n2 + SK - 1) / SK, tiles_j = (g.n1 + SJ - 1) / SJ;
+    int th = tile_planes > 0 ? tile_planes : 64;
+    if (th > g.n0) th = g.n0;
+    const int64_t chunks = cdiv(g.n0, th);
+    const int64_t blocks = (int64_t)tiles_k * tiles_j * chunks;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
+    const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
+#define MP_S3(HG, IG, TO)                                                                       \
+    k_step3d<T, HG, IG, TO><<<(unsigned)blocks, NT, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, \
+                                                           kahan, psi_n, c0, c1, c2, G, psi_out)
+    if (G) {
+        if (iga) { if (tot) MP_S3(true, true, true); else MP_S3(true, true, false); }
+        else { if (tot) MP_S3(true, false, true); else MP_S3(true, false, false); }
+    } else {
+        if (iga) { if (tot) MP_S3(false, true, true); else MP_S3(false, true, false); }
+        else { if (tot) MP_S3(false, false, true); else MP_S3(false, false, false); }
+    }
+#undef MP_S3
+    return hipGetLastError();
+}
+
+template hipError_t step3d_launch<float>(const Geom &, unsigned, const float *, float *,
+                                         const float *, const float *, const float *,
+                                         const float *, int, hipStream_t);
+template hipError_t step3d_launch<double>(const Geom &, unsigned, const double *, double *,
+                                          const double *, const double *, const double *,
+                                          const double *, int, hipStream_t);
+
+}  // namespace mp

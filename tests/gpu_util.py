@@ -1,17 +1,58 @@
 """Helpers for the GPU parity tests (HIP path via the C ABI vs the oracle)."""
+import json
+import os
+
 import numpy as np
 import torch
 
 from paper_1407_1309_amd import mpdata
 
+# the stated bar: relative L2 over the field
 TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+# element-wise bar, relative to the field's largest magnitude: it catches a
+# localised error (a wrong boundary row, one bad tile) that the L2 norm of a
+# large field dilutes below TOL.  FP64: 1e-11 (the largest seen over every
+# step-parity case is 4.3e-13).  FP32: 5e-5 -- the FP32 path rounds every
+# stage to 24 bits and the limiter takes its min/max and sign decisions on
+# those values; the largest seen is 1.2e-5 (six shallow-water steps), under
+# 5e-6 for the plain step cases.
+EL_TOL = {torch.float64: 1e-11, torch.float32: 5e-5}
+
+
+def _log(rel, dev_max):
+    path = os.environ.get("MPDATA_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps({"test": os.environ.get("PYTEST_CURRENT_TEST", ""),
+                                "rel_l2": rel, "max_dev": dev_max}) + "\n")
+
+
+def max_dev(a, ref):
+    """Largest element-wise deviation relative to the largest |ref|."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.max(np.abs(ref)) if ref.size else 0.0
+    d = np.max(np.abs(a - ref)) if ref.size else 0.0
+    return float(d / (scale if scale > 0 else 1.0))
 
 
 def rel_l2(a, ref):
     a = np.asarray(a, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     den = np.linalg.norm(ref.ravel())
-    return np.linalg.norm((a - ref).ravel()) / (den if den > 0 else 1.0)
+    rel = np.linalg.norm((a - ref).ravel()) / (den if den > 0 else 1.0)
+    if os.environ.get("MPDATA_PARITY_LOG"):
+        _log(float(rel), max_dev(a, ref))
+    return rel
+
+
+def assert_parity(out, ref, dtype, what=""):
+    """Relative L2 within TOL and every element within EL_TOL of the peak."""
+    rel = rel_l2(out, ref)
+    dmax = max_dev(out, ref)
+    assert rel <= TOL[dtype], (what, "rel-L2", rel)
+    assert dmax <= EL_TOL[dtype], (what, "max element deviation", dmax)
+    return rel, dmax
 
 
 def as_dtype(x, dtype):

@@ -49,6 +49,9 @@ def _desc(shape, dtype=mpdata.F64, n_iters=2, opts=0, bc=0, has_g=0):
     (dict(shape=(8,), bc=5), mpdata.EINVAL),
     (dict(shape=(8,), dtype=7), mpdata.EINVAL),
     (dict(shape=(8,), opts=mpdata.OPT_IGA, n_iters=3), mpdata.EUNSUPPORTED),
+    (dict(shape=(1 << 31,)), mpdata.EINVAL),              # 32-bit per-dimension indices
+    (dict(shape=(1 << 30,)), mpdata.EINVAL),
+    (dict(shape=(4, 1 << 30), bc=1), mpdata.EINVAL),
 ])
 def test_init_rejects_bad_descriptors(kw, code):
     L = mpdata.lib()

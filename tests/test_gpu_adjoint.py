@@ -132,13 +132,15 @@ def _J(plan, psi, c, obs, n_steps):
     return 0.5 * float(torch.sum((p - obs) ** 2)), p
 
 
-def _workload(n, n_steps, ck):
+def _workload(n, n_steps, ck, kernel=mpdata.KERNEL_STAGED):
     w = synth.case_adjoint(n=n, n_steps=n_steps)
     case = w["case"]
-    plan = mpdata.Plan(case.psi.shape, n_iters=2, opts=FCT, kernel=mpdata.KERNEL_STAGED,
+    plan = mpdata.Plan(case.psi.shape, n_iters=2, opts=FCT, kernel=kernel,
                        adj_steps=n_steps, ckpt_every=ck)
     psi = dev(case.psi, torch.float64)
     c = [dev(x, torch.float64) for x in case.c]
+    if kernel == mpdata.KERNEL_AUTO:
+        plan.autotune(psi, c)        # the benchmark's plan: fused sweeps, tuned chunks
     obs = dev(w["psi_perturbed"], torch.float64)
     plan.step(obs, [dev(x, torch.float64) for x in w["c_perturbed"]], n_steps=n_steps)
     _, out = _J(plan, psi, c, obs, n_steps)
@@ -156,7 +158,9 @@ def _richardson(central, h):
     return r2, abs(r1 - r2) <= 3e-7 * abs(r2)
 
 
-def test_adjoint_workload_point_checks_vs_fd():
+@pytest.mark.parametrize("kernel", [mpdata.KERNEL_STAGED, mpdata.KERNEL_AUTO],
+                         ids=["staged", "bench_plan"])
+def test_adjoint_workload_point_checks_vs_fd(kernel):
     """Full adjoint workload (2-D periodic 1024^2, FP64, n_iters=2 with the
     limiter, 200 steps, checkpoint every 20): finite differences of
     J = 1/2 ||psi_T - psi_obs||^2 at single initial cells and single walls
@@ -168,9 +172,13 @@ def test_adjoint_workload_point_checks_vs_fd():
     different one-sided slopes and a central difference averages them).
     Where the limiter's coefficient is near its singular point (in/out-flux
     sum close to 0) J is smooth but very strongly curved, so a point whose
-    extrapolated difference quotients do not converge is not used."""
+    extrapolated difference quotients do not converge is not used; at
+    least 12 of the 24 points must converge (measured: 14 with the
+    stage-by-stage plan, 18 with the benchmark's plan, whose state sweeps
+    run the fused kernel).  Both plans are checked: the benchmark times the
+    automatic choice with autotuned chunks."""
     n_steps, ck = 200, 20
-    plan, psi, c, obs, gp, gc = _workload(1024, n_steps, ck)
+    plan, psi, c, obs, gp, gc = _workload(1024, n_steps, ck, kernel)
     gen = np.random.default_rng(11)
     checks = []
     g_np = gp.cpu().numpy()
@@ -212,7 +220,8 @@ def test_adjoint_workload_point_checks_vs_fd():
             continue
         assert abs(fd - ad) <= 1e-6 * abs(ad), (what, idx, ad, fd)
         n_ok += 1
-    assert n_ok >= 6, n_ok
+    print(f"FD points converged: {n_ok} of {len(checks)}", flush=True)
+    assert n_ok >= 12, n_ok
 
 
 def test_adjoint_directions_vs_fd():

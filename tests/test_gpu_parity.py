@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_1407_1309_amd import mpdata, synth
-from tests.gpu_util import TOL, as_dtype, dev, gpu_run, rel_l2
+from tests.gpu_util import TOL, as_dtype, assert_parity, dev, gpu_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -55,8 +55,7 @@ def test_parity_small(shape, bc, opts, dtype):
     ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=n_steps)
     for kernel in KERNELS:
         out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, n_steps, kernel=kernel)
-        err = rel_l2(out, ref)
-        assert err <= TOL[dtype], (kernel, err)
+        assert_parity(out, ref, dtype, kernel)
 
 
 KAHAN = mpdata.OPT_KAHAN
@@ -80,7 +79,7 @@ def test_parity_kahan(shape, bc, opts, dtype):
         ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=5)
         for kernel in KERNELS:
             out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 5, kernel=kernel)
-            assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
+            assert_parity(out, ref, dtype, (kernel, with_g))
 
 
 ABS = mpdata.OPT_ABS
@@ -103,7 +102,7 @@ def test_parity_abs(shape, bc, opts, dtype):
         ref = oracle.step(psi, c, g=g, n_iters=3, opts=opts, bc=bc, n_steps=5)
         for kernel in KERNELS:
             out = gpu_run(psi, c, g, dtype, 3, opts, bc, 5, kernel=kernel)
-            assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
+            assert_parity(out, ref, dtype, (kernel, with_g))
 
 
 DFL = mpdata.OPT_DFL
@@ -128,7 +127,7 @@ def test_parity_dfl(shape, bc, opts, dtype):
         ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=5)
         for kernel in KERNELS:
             out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 5, kernel=kernel)
-            assert rel_l2(out, ref) <= TOL[dtype], (kernel, with_g)
+            assert_parity(out, ref, dtype, (kernel, with_g))
 
 
 def test_abs_option_errors():
@@ -152,7 +151,7 @@ def test_parity_pass_counts(n_iters):
     ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=FCT, n_steps=3)
     for kernel in KERNELS:
         out = gpu_run(psi, c, g, torch.float64, n_iters, FCT, 0, 3, kernel=kernel)
-        assert rel_l2(out, ref) <= 1e-12
+        assert_parity(out, ref, torch.float64)
 
 
 def test_parity_1d_workload_full():
@@ -160,7 +159,7 @@ def test_parity_1d_workload_full():
     case = synth.case_1d()
     ref = oracle.step(case.psi, case.c, n_iters=2, n_steps=case.n_steps)
     out = gpu_run(case.psi, case.c, None, torch.float64, 2, 0, 0, case.n_steps)
-    assert rel_l2(out, ref) <= 1e-12
+    assert_parity(out, ref, torch.float64)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
@@ -172,7 +171,7 @@ def test_parity_2d_workload_full(dtype):
     c = [as_dtype(x, dtype) for x in case.c]
     ref = oracle.step(psi, c, n_iters=3, opts=FCT, n_steps=2)
     out = gpu_run(psi, c, None, dtype, 3, FCT, 0, 2)
-    assert rel_l2(out, ref) <= TOL[dtype]
+    assert_parity(out, ref, dtype)
 
 
 def _subblock_check(case, out, dtype, n_steps, centres, half=6, step_radius=3):
@@ -205,7 +204,7 @@ def _subblock_check(case, out, dtype, n_steps, centres, half=6, step_radius=3):
             b = min(hi[d], ctr[d] + half + 1) - lo[d]
             core.append(slice(a, b))
         got = out[ix][tuple(core)]
-        errs.append(rel_l2(got, ref[tuple(core)]))
+        errs.append(assert_parity(got, ref[tuple(core)], dtype, ctr)[0])
     return max(errs)
 
 
@@ -275,7 +274,7 @@ def test_degenerate_cases(shape, bc):
             ref = oracle.step(k, cn, n_iters=n_iters, opts=opts, bc=0, n_steps=3)
             for kernel in KERNELS:
                 out = gpu_run(k, cn, None, torch.float64, n_iters, opts, 0, 3, kernel=kernel)
-                assert rel_l2(out, ref) <= 1e-12, (opts, kernel)
+                assert_parity(out, ref, torch.float64, (opts, kernel))
                 assert np.max(np.abs(out - 0.75)) <= 1e-13, (opts, kernel)
 
 
@@ -426,7 +425,7 @@ def test_parity_1d_resident(opts, bc, dtype):
         psi, c, g = as_dtype(psi, dtype), [as_dtype(x, dtype) for x in c], as_dtype(g, dtype)
         ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=25)
         out = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 25, kernel=mpdata.KERNEL_FUSED)
-        assert rel_l2(out, ref) <= TOL[dtype], with_g
+        assert_parity(out, ref, dtype, with_g)
 
 
 F3_CASES = []
@@ -447,8 +446,8 @@ def test_parity_3d_fused(shape, bc, n_iters, opts, dtype):
         ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=3)
         fused = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 3, kernel=mpdata.KERNEL_FUSED)
         staged = gpu_run(psi, c, g, dtype, n_iters, opts, bc, 3, kernel=mpdata.KERNEL_STAGED)
-        assert rel_l2(fused, ref) <= TOL[dtype], with_g
-        assert rel_l2(fused, staged) <= TOL[dtype], with_g
+        assert_parity(fused, ref, dtype, with_g)
+        assert_parity(fused, staged, dtype, with_g)
 
 
 def test_3d_fused_chunk_independent():

@@ -87,12 +87,24 @@ def test_sw_step_vs_oracle(n_steps, shape, opts, dtype):
     c = _walls(shape, dtype)
     plan.sw_step(H, Q, HP, QP, c, dt, dx, grav=grav, eps=eps, n_steps=n_steps)
     torch.cuda.synchronize()
-    tol = TOL[dtype] * (1 if n_steps == 1 else 10)
+    tol = TOL[dtype]
+    _report_worst("h", _host(H), rh, rh)
     assert rel_l2(_host(H), rh) <= tol
     assert rel_l2(_host(HP), rhp) <= tol
     for d in range(len(shape)):
+        _report_worst(f"q{d}", _host(Q[d]), rq[d], rh)
         assert rel_l2(_host(Q[d]), rq[d]) <= tol
         assert rel_l2(_host(QP[d]), rqp[d]) <= tol
+
+
+def _report_worst(name, got, ref, depth):
+    """Print the largest deviation, where it is and the depth there (the
+    depth cut-off at eps decides the velocity of a cell)."""
+    dv = np.abs(got - ref)
+    k = np.unravel_index(int(np.argmax(dv)), dv.shape)
+    print(f"{name}: rel-L2 {rel_l2(got, ref):.2e}, worst {dv[k]:.2e} at {tuple(int(i) for i in k)}"
+          f" (|ref| {abs(ref[k]):.2e}, depth {depth[k]:.3e}, peak {np.max(np.abs(ref)):.2e})",
+          flush=True)
 
 
 def test_sw_zero_steps_and_lake_at_rest():
@@ -123,8 +135,8 @@ def _lambda_1d(t):
 def test_sw_drop_1d_paper_setup(dtype):
     """The 1-D drop of Sect. 5.3 (320 cells, dx = 0.05, dt = 0.01, 300 steps,
     iga + fct + dfl) on the GPU: the same bounds against the analytic
-    solution as the oracle's pin, mass conserved, and close to the oracle's
-    own run (rounding differences grow only at the thin drop edge)."""
+    solution as the oracle's pin, mass conserved, and the oracle's own run
+    at the stated bar after all 300 steps."""
     n, dx, dt, T = 320, 0.05, 0.01, 3.0
     x = (np.arange(n) + 0.5 - n / 2) * dx
     h0 = np.maximum(1.0 - x ** 2, 0.0)
@@ -145,7 +157,8 @@ def test_sw_drop_1d_paper_setup(dtype):
     mass_tol = 1e-12 if dtype == torch.float64 else 1e-5
     assert abs(h.sum() - h0.sum()) <= mass_tol * h0.sum()
     rh, _ = oracle.sw_run(h0, [np.zeros(n)], 300, dt, dx, eps=1e-8)
-    assert rel_l2(h, rh) <= (1e-9 if dtype == torch.float64 else 1e-4)
+    _report_worst("h", h, rh, rh)
+    assert rel_l2(h, rh) <= TOL[dtype]
 
 
 def test_sw_drop_2d_paper_solution():

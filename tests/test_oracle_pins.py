@@ -822,3 +822,23 @@ def test_diag_sum_matches_exact_summation():
     for t in terms:
         naive += t
     assert abs(naive - exact) > 1e3 * np.spacing(abs(exact))
+
+
+# ---------------------------------------------------------------- multi-core build
+@pytest.mark.parametrize("shape,bc,opts", [((37, 29), 0, FCT), ((9, 7, 11), 1, IGA | TOT),
+                                           ((64,), 0, FCT | TOT), ((20, 30), 1, FCT | KAHAN)])
+def test_openmp_build_same_bits(shape, bc, opts):
+    """The OpenMP build of the oracle (the multi-core CPU baseline) shares
+    each stage's outermost loop among threads; every iteration writes only its
+    own cells, so the result is the single-threaded one bit for bit."""
+    gen = synth.rng(17)
+    g = gen.uniform(0.7, 1.3, size=shape)
+    c = synth.random_advector(shape, 0.4, gen)
+    if bc == 0:
+        c = synth.periodic_fix(c)
+    psi = gen.uniform(0.0, 1.0, size=shape) if not opts & IGA else gen.normal(size=shape)
+    n_iters = 2 if opts & IGA else 3
+    a = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=4)
+    b = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=bc, n_steps=4, parallel=True)
+    assert np.array_equal(a, b)
+    assert oracle.threads(parallel=False) == 1
