@@ -236,6 +236,21 @@ int mpdata_sw_step(mpdata_plan *plan, void *h, void *const q[3], void *h_prev,
 int mpdata_diag(mpdata_plan *plan, const void *psi, const void *g,
                 double out_sum_min_max[3], int64_t *n_nonfinite);
 
+/* mpdata_diag for callers that cannot allocate device memory or hold a
+ * plan's workspace (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and outputs, with the
+ * block partials and the result in a fixed device array of the library
+ * (41 KB per device, kept until the process ends); no plan, no workspace,
+ * no allocation.  psi (and g, or NULL) are device arrays of n_cells values
+ * of `dtype` (MPDATA_F32 / MPDATA_F64), 1 <= n_cells <= 2^40 (else
+ * MPDATA_EINVAL); work is enqueued on hip_stream (a hipStream_t, NULL =
+ * default) and the call waits for the result.  Returns MPDATA_ENONFINITE
+ * (after filling the outputs) when *n_nonfinite > 0.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (from several
+ * threads or streams) race and must be serialised by the caller. */
+int mpdata_diag_noalloc(int dtype, int64_t n_cells, const void *psi, const void *g,
+                        void *hip_stream, double out_sum_min_max[3], int64_t *n_nonfinite);
+
 /* max over cells of sum_d max(|c_d| on the two d-walls of the cell) / G
  * (waits for the result).  A value above 1 means the donor-cell pass can
  * empty a cell, so sign preservation (Sect. 1) is no longer guaranteed.

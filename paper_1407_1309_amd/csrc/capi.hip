@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1404,6 +1405,86 @@ void mpdata_destroy(mpdata_plan *plan)
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free diagnostics
+// mpdata_diag_noalloc keeps the block partials and the result in `scratch`, a
+// file-scope device array of fixed size, instead of a plan's workspace.  In
+// host code the array's name stands for a host-side shadow, not device
+// memory: its device address is looked up once per device, with that device
+// current, and only that address is passed to kernels and copies.
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+// partials of at most 1024 blocks (5 doubles each) and the result (4 doubles)
+constexpr int NOALLOC_PART = 5 * 1024;
+constexpr int NOALLOC_DOUBLES = NOALLOC_PART + 8;
+
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// device address of the current device's scratch array
+int scratch_ptr(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(MPDATA_EUNSUPPORTED, "device %d beyond the %d the library keeps scratch for",
+                    dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+        if (!p) return fail(MPDATA_EHIP, "hipGetSymbolAddress returned NULL");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPDATA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpdata_diag_noalloc(int dtype, int64_t n_cells, const void *psi, const void *g,
+                        void *hip_stream, double out_sum_min_max[3], int64_t *n_nonfinite)
+{
+    TraceRange trace_range("mpdata_diag_noalloc");
+    if (!psi || !out_sum_min_max || !n_nonfinite) return fail(MPDATA_EINVAL, "NULL argument");
+    if (dtype != MPDATA_F32 && dtype != MPDATA_F64)
+        return fail(MPDATA_EINVAL, "unknown dtype %d", dtype);
+    if (n_cells < 1 || n_cells > ((int64_t)1 << 40))
+        return fail(MPDATA_EINVAL, "n_cells %lld outside 1..2^40", (long long)n_cells);
+    if (mp::diag_max_blocks() * 5 > NOALLOC_PART)
+        return fail(MPDATA_EINVAL, "the scratch array holds fewer partials than one call makes");
+    double *base = nullptr;
+    int rc = scratch_ptr(&base);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    double *part = base, *res = base + NOALLOC_PART;
+    hipError_t e = dtype == MPDATA_F64
+                       ? mp::diag_launch<double>((const double *)psi, (const double *)g, n_cells,
+                                                 part, res, s)
+                       : mp::diag_launch<float>((const float *)psi, (const float *)g, n_cells,
+                                                part, res, s);
+    if (e != hipSuccess) return hip_fail(e, "diag launch");
+    double h[4];
+    e = hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "diag copy");
+    out_sum_min_max[0] = h[0];
+    out_sum_min_max[1] = h[1];
+    out_sum_min_max[2] = h[2];
+    *n_nonfinite = (int64_t)h[3];
+    if (*n_nonfinite > 0)
+        return fail(MPDATA_ENONFINITE, "%lld non-finite values", (long long)*n_nonfinite);
+    return MPDATA_OK;
 }
 
 }  // extern "C"

@@ -35,7 +35,7 @@ EXPORTS = [
     "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read", "mpdata_step_rhs",
     "mpdata_osc_step", "mpdata_vip_advector", "mpdata_sw_step", "mpdata_set_cancel_flag",
     "mpdata_steps_done", "mpdata_tlm_step", "mpdata_tlm_workspace_bytes",
-    "mpdata_destroy", "mpdata_last_error",
+    "mpdata_diag_noalloc", "mpdata_destroy", "mpdata_last_error",
 ]
 
 
@@ -75,6 +75,9 @@ def lib():
         L.mpdata_diag.argtypes = [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
         L.mpdata_courant_max.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)]
+        L.mpdata_diag_noalloc.argtypes = [ctypes.c_int, ctypes.c_int64, _VP, _VP, _VP,
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64)]
         L.mpdata_adv_adj.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int,
                                      _VP, _VP, _VP, _VP, _VP]
         L.mpdata_adj_workspace_bytes.argtypes = [DP, ctypes.c_int, ctypes.c_int]
@@ -538,6 +541,23 @@ class BatchedPlan:
             out.append(packed[off:off + n].reshape(shp))
             off += n
         return out
+
+
+def diag_noalloc(psi, g=None):
+    """(sum G psi, min, max, n_nonfinite) of a contiguous device field
+    without a plan or workspace (mpdata_diag_noalloc: the library's fixed
+    scratch array); runs on torch's current stream and waits."""
+    if not (psi.is_cuda and psi.is_contiguous()):
+        raise ValueError("psi must be a contiguous device tensor")
+    if g is not None and (g.dtype != psi.dtype or g.shape != psi.shape or not g.is_contiguous()):
+        raise ValueError("g must match psi")
+    out = (ctypes.c_double * 3)()
+    bad = ctypes.c_int64(0)
+    rc = lib().mpdata_diag_noalloc(_dtype_code(psi.dtype), psi.numel(), _ptr(psi), _ptr(g),
+                                   _stream(psi.device), out, ctypes.byref(bad))
+    if rc not in (OK, ENONFINITE):
+        _check(rc)
+    return out[0], out[1], out[2], int(bad.value)
 
 
 def step(psi, c, g=None, n_iters=2, opts=0, bc=BC_PERIODIC, n_steps=1, kernel=KERNEL_AUTO):
