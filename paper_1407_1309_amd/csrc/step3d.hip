@@ -18,7 +18,7 @@
 //      t-2 and t-1 of its own column, V1 and V2 at plane t-2 on the low walls
 //      of its own cell (the tile's far edge walls by the first threads);
 //   4. applies the corrective pass to plane t-2 of its own column.
-// Three barriers per plane.  Every thread computes one output cell (the
+// Two barriers per plane.  Every thread computes one output cell (the
 // ring's y1 cells are shared out as a second cell to the first threads), so
 // no thread only recomputes a halo.
 //
@@ -46,6 +46,7 @@ constexpr int N2 = BJ * (BK + 1);               // dimension-2 walls of the box
 static_assert(NY <= 2 * NT && NP <= 2 * NT && N1 <= 2 * NT && N2 <= 2 * NT,
               "each thread loads at most two entries of every box plane");
 static_assert(SK <= NT && SK + SJ <= NT, "far-edge walls need that many threads");
+static_assert(NY - NT == 4 * BK + 4 * SJ && NY - NT <= NT, "ring cells: one per thread at most");
 
 struct G3s {
     int n0, n1, n2;
@@ -120,14 +121,32 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         o1[m] = box_offset(e, N1, BK, j0 - 2, k0 - 2, true, false, g, g.n2);
         o2[m] = box_offset(e, N2, BK + 1, j0 - 2, k0 - 2, false, true, g, g.n2 + 1);
     }
-    // y1 cells this thread forms: box entries tid and tid + NT, each at its
-    // effective position (the clamped cell outside an open domain)
+    // y1 cells this thread forms, each at its effective position (the
+    // clamped cell outside an open domain): first its own column's cell,
+    // then, for the first NRING threads, one cell of the ring of 2 around
+    // the tile (rows 0-1, rows SJ+2..SJ+3, then lanes 0-1 and SK+2..SK+3 of
+    // the rows between)
+    constexpr int NRING = NY - NT;
     int ye[2], yp[2];
     bool yon[2];
     for (int m = 0; m < 2; m++) {
-        const int e = tid + m * NT;
-        yon[m] = e < NY;
-        const int bj = yon[m] ? e / BK : 0, bk = yon[m] ? e % BK : 0;
+        int bj, bk;
+        if (m == 0) {
+            bj = r + 2;
+            bk = l + 2;
+        } else if (tid < 2 * BK) {
+            bj = tid / BK;
+            bk = tid % BK;
+        } else if (tid < 4 * BK) {
+            bj = SJ + 2 + (tid - 2 * BK) / BK;
+            bk = (tid - 2 * BK) % BK;
+        } else {
+            const int q = tid - 4 * BK;
+            bj = 2 + q / 4;
+            bk = (q & 3) < 2 ? (q & 3) : SK + (q & 3);
+        }
+        yon[m] = m == 0 || tid < NRING;
+        if (!yon[m]) bj = bk = 0;
         int ej = bj, ek = bk;
         if (g.bc1 == BC_OPEN) ej = min(max(j0 - 2 + bj, 0), g.n1 - 1) - (j0 - 2);
         if (g.bc2 == BC_OPEN) ek = min(max(k0 - 2 + bk, 0), g.n2 - 1) - (k0 - 2);
@@ -188,6 +207,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
     const int cy = bj * BK + bk;
     const bool own_out = j0 + r < g.n1 && k0 + l < g.n2;
     T v0_lo = T(0);      // V0 at the low wall of the plane being corrected
+    T y_own = T(0);      // y1 of plane t of the thread's own column
 
     for (int t = t_first; t <= t_last; t++) {
         store(t);
@@ -235,9 +255,15 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                     y = xc - (HAS_G ? acc / Gs[sc][ee] : acc);
                 }
                 Ys[sy][yp[m]] = y;
+                if (m == 0) y_own = y;
             }
         }
-        __syncthreads();   // (B2) y1 of plane t is in LDS
+        // No barrier here: the pseudo-velocities of plane t-2 read y1 of
+        // planes t-3..t-1 only (written before the barrier above), except
+        // the third-order term of V0, which takes plane t of the thread's
+        // own column from y_own (or, past an open domain's last plane, the
+        // edge plane's slot).  The ring cells of plane t are read from the
+        // next iteration on, after its barrier.
 
         // ---- pseudo-velocities ----
         const int p = t - 2;
@@ -272,7 +298,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             T a2 = YC[c + 1], b2 = YB[c + 1], e2 = YC[c - 1], f2 = YB[c - 1];
             v -= T(0.5) * u * cb2 * ig * fr3<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
             if (TOT) {
-                const T xR2 = Ys[sD][c], xL2 = YA[c];
+                const T xR2 = (open0 && t >= g.n0) ? Ys[sD][c] : y_own, xL2 = YA[c];
                 v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
                      fr3<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
                 v += (fabs(u) * cb1 * ig - T(2) * u * u * cb1 * (ig * ig)) *
@@ -447,7 +473,7 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
 {
     G3s g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
     const int tiles_k = (g.n2 + SK - 1) / SK, tiles_j = (g.n1 + SJ - 1) / SJ;
-    int th = tile_planes > 0 ? tile_planes : 64;
+    int th = tile_planes > 0 ? tile_planes : 96;
     if (th > g.n0) th = g.n0;
     const int64_t chunks = cdiv(g.n0, th);
     const int64_t blocks = (int64_t)tiles_k * tiles_j * chunks;
