@@ -223,6 +223,22 @@ int mpdata_sw_step(mpdata_plan *plan, void *h, void *const q[3], void *h_prev,
                    void *const q_prev[3], void *const c[3], double dt, const double dx[3],
                    double grav, double eps, int n_steps);
 
+/* Diagnostics of every step call's result, formed by the step itself.  With
+ * on != 0, each later mpdata_step call on the plan also forms the
+ * diagnostics of mpdata_diag (sum of G*psi, min, max, non-finite count) of
+ * the field it leaves in psi, and mpdata_step_diag returns those of the last
+ * call (waits for them).  The fused 2-D step accumulates them in its last
+ * launch while it stores each cell (one partial per wavefront, then one
+ * small merge launch: no second read of psi); the other kernels are
+ * followed by a diagnostics pass over psi.  mpdata_step_diag returns
+ * MPDATA_EINVAL when no step call has formed them since they were switched
+ * on, and MPDATA_ENONFINITE (after filling the outputs) when the field holds
+ * NaN or Inf values.  The conserved sum is the flux form's invariant
+ * (Sect. 1); the non-finite count is the run-time counterpart of the NaN
+ * checks of Sect. 2.4.  Switching off (on = 0) drops the last result. */
+int mpdata_set_step_diag(mpdata_plan *plan, int on);
+int mpdata_step_diag(mpdata_plan *plan, double out_sum_min_max[3], int64_t *n_nonfinite);
+
 /* Diagnostics of psi (waits for the result): out[0] = sum of G*psi over the
  * finite cells (FP64, compensated), out[1] = min, out[2] = max of the finite
  * values, *n_nonfinite = number of NaN/Inf cells.  Returns MPDATA_ENONFINITE

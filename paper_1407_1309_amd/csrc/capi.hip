@@ -133,10 +133,16 @@ struct Layout {
     void *bup, *bdn;
     double *part;   // diag partials (5 per block)
     double *out;    // diag result (4) + courant result (1)
+    double *spart;  // step diagnostics: partials written by the fused 2-D step
+    double *sdiag;  // step diagnostics: result (4)
     size_t bytes;
 };
 
-Layout carve(const mp::Geom &g, int dtype, void *base)
+// fused 2-D chunks shorter than this run without the in-kernel diagnostics
+// (the partial buffer is sized for chunks of at least this many rows)
+constexpr int SDIAG_MIN_ROWS = 16;
+
+Layout carve(const mp::Geom &g, int dtype, void *base, int n_iters = 1, unsigned opts = 0)
 {
     Layout L;
     memset(&L, 0, sizeof L);
@@ -145,6 +151,10 @@ Layout carve(const mp::Geom &g, int dtype, void *base)
     int64_t N = cells_of(g);
     L.part = (double *)c.take(sizeof(double) * 5 * mp::diag_max_blocks());
     L.out = (double *)c.take(sizeof(double) * 8);
+    L.sdiag = (double *)c.take(sizeof(double) * 8);
+    if (g.nd == 2)
+        L.spart = (double *)c.take(
+            sizeof(double) * 5 * mp::fused2d_max_parts(g.n[0], g.n[1], n_iters, opts, SDIAG_MIN_ROWS));
     L.psi_alt = c.take(es * N);
     L.tmp[0] = c.take(es * N);
     L.tmp[1] = c.take(es * N);
@@ -192,6 +202,9 @@ struct mpdata_plan {
     // stop flag (host memory, caller-owned) and the last call's step count
     const volatile int *cancel = nullptr;
     int64_t steps_done = 0;
+    // diagnostics of each mpdata_step call's result (mpdata_set_step_diag)
+    bool step_diag = false;
+    bool sdiag_ready = false;
 };
 
 namespace {
@@ -221,7 +234,7 @@ enum { PATH_STAGED = 0, PATH_FUSED = 1, PATH_PASS2D = 2 };
 
 template <typename T>
 int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0, const T *c1,
-             const T *c2, int path, bool timed = false)
+             const T *c2, int path, bool timed = false, int *dparts = nullptr)
 {
     hipError_t e = hipSuccess;
     const bool fused = path == PATH_FUSED;
@@ -255,7 +268,7 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
     } else if (fused) {
         mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1], p->tile_rows};
         e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, G,
-                                p->stream);
+                                p->stream, dparts ? p->L.spart : nullptr, dparts);
     } else {
         mp::StagedArgs<T> a;
         a.g = p->g;
@@ -315,6 +328,27 @@ bool use_resident(const mpdata_plan *p)
     return p->kernel != MPDATA_KERNEL_STAGED && resident_available(p);
 }
 
+// Diagnostics of a step call's result (mpdata_set_step_diag): the final merge
+// of the partials the fused 2-D step's last launch wrote (dparts > 0), else
+// a diagnostics pass over psi.
+template <typename T>
+int step_diag_finish(mpdata_plan *p, const T *psi, const T *G, int dparts)
+{
+    hipError_t e = dparts > 0 ? mp::diag_final_launch(p->L.spart, dparts, p->L.sdiag, p->stream)
+                              : mp::diag_launch<T>(psi, G, cells_of(p->g), p->L.part,
+                                                   p->L.sdiag, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "step diagnostics launch");
+    p->sdiag_ready = true;
+    return MPDATA_OK;
+}
+
+// true when the fused 2-D step can write the diagnostics partials itself
+bool step_diag_in_kernel(const mpdata_plan *p, int path)
+{
+    return p->step_diag && path == PATH_FUSED && p->desc.n_dims == 2 &&
+           (p->tile_rows == 0 || p->tile_rows >= SDIAG_MIN_ROWS);
+}
+
 // Step loop with a stop flag: every step runs to completion (stream
 // synchronisation) before the flag is read and the next step launched; the
 // state alternates between psi and the workspace buffer and is copied back
@@ -360,6 +394,10 @@ int run_steps_polled(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c
         if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
         if (e != hipSuccess) return hip_fail(e, "copy of the last completed step");
     }
+    if (p->step_diag) {
+        int r = step_diag_finish<T>(p, psi, G, 0);
+        if (r) return r;
+    }
     return rc;
 }
 
@@ -368,7 +406,8 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
               int n_steps)
 {
     p->steps_done = 0;
-    if (n_steps == 0) return MPDATA_OK;
+    p->sdiag_ready = false;
+    if (n_steps == 0) return p->step_diag ? step_diag_finish<T>(p, psi, G, 0) : MPDATA_OK;
     if (p->cancel) return run_steps_polled<T>(p, psi, G, c0, c1, c2, n_steps);
     if (use_resident(p)) {
         bool tm = timer_begin(p, "k_resident1d");
@@ -377,7 +416,7 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
         if (tm) timer_end(p);
         if (e != hipSuccess) return hip_fail(e, "resident 1-D launch");
         p->steps_done = n_steps;
-        return MPDATA_OK;
+        return p->step_diag ? step_diag_finish<T>(p, psi, G, 0) : MPDATA_OK;
     }
     const int path = step_path(p);
     if (path == PATH_STAGED && p->desc.n_iters >= 2) {
@@ -389,7 +428,7 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
             if (rc) return rc;
         }
         p->steps_done = n_steps;
-        return MPDATA_OK;
+        return p->step_diag ? step_diag_finish<T>(p, psi, G, 0) : MPDATA_OK;
     }
     int64_t N = cells_of(p->g);
     T *alt = (T *)p->L.psi_alt;
@@ -400,15 +439,20 @@ int run_steps(mpdata_plan *p, T *psi, const T *G, const T *c0, const T *c1, cons
         cur = alt;
         nxt = psi;
     }
+    // the last launch of the call also writes the diagnostics partials when
+    // the fused 2-D step can (dparts receives their number)
+    int dparts = 0;
+    const bool in_kernel = step_diag_in_kernel(p, path);
     for (int s = 0; s < n_steps; s++) {
-        int rc = one_step<T>(p, cur, nxt, G, c0, c1, c2, path, true);
+        int rc = one_step<T>(p, cur, nxt, G, c0, c1, c2, path, true,
+                             in_kernel && s == n_steps - 1 ? &dparts : nullptr);
         if (rc) return rc;
         T *t = cur;
         cur = nxt;
         nxt = t;
     }
     p->steps_done = n_steps;
-    return MPDATA_OK;
+    return p->step_diag ? step_diag_finish<T>(p, psi, G, dparts) : MPDATA_OK;
 }
 
 }  // namespace
@@ -421,7 +465,7 @@ size_t mpdata_workspace_bytes(const mpdata_desc *desc)
 {
     mp::Geom g;
     if (check_desc(desc, &g) != MPDATA_OK) return 0;
-    return carve(g, desc->dtype, nullptr).bytes;
+    return carve(g, desc->dtype, nullptr, desc->n_iters, desc->opts).bytes;
 }
 
 int mpdata_init(const mpdata_desc *desc, void *workspace, size_t ws_bytes, void *hip_stream,
@@ -432,7 +476,7 @@ int mpdata_init(const mpdata_desc *desc, void *workspace, size_t ws_bytes, void 
     mp::Geom g;
     int rc = check_desc(desc, &g);
     if (rc) return rc;
-    size_t need = carve(g, desc->dtype, nullptr).bytes;
+    size_t need = carve(g, desc->dtype, nullptr, desc->n_iters, desc->opts).bytes;
     if (!workspace) return fail(MPDATA_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
     if ((uintptr_t)workspace % ALIGN) return fail(MPDATA_EWORKSPACE, "workspace not 256-byte aligned");
     if (ws_bytes < need)
@@ -445,7 +489,7 @@ int mpdata_init(const mpdata_desc *desc, void *workspace, size_t ws_bytes, void 
     p->ws_bytes = ws_bytes;
     p->stream = (hipStream_t)hip_stream;
     p->kernel = MPDATA_KERNEL_AUTO;
-    p->L = carve(g, desc->dtype, workspace);
+    p->L = carve(g, desc->dtype, workspace, desc->n_iters, desc->opts);
     *out = p;
     return MPDATA_OK;
 }
@@ -627,6 +671,35 @@ int mpdata_step(mpdata_plan *plan, void *psi, const void *g, const void *c0, con
                                  (const double *)c1, (const double *)c2, n_steps);
     return run_steps<float>(plan, (float *)psi, (const float *)g, (const float *)c0,
                             (const float *)c1, (const float *)c2, n_steps);
+}
+
+int mpdata_set_step_diag(mpdata_plan *plan, int on)
+{
+    if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
+    if (plan->batched) return fail(MPDATA_EINVAL, "step diagnostics need a single-grid plan");
+    plan->step_diag = on != 0;
+    plan->sdiag_ready = false;
+    return MPDATA_OK;
+}
+
+int mpdata_step_diag(mpdata_plan *plan, double out[3], int64_t *n_nonfinite)
+{
+    TraceRange trace_range("mpdata_step_diag");
+    if (!plan || !out || !n_nonfinite) return fail(MPDATA_EINVAL, "NULL argument");
+    if (!plan->sdiag_ready)
+        return fail(MPDATA_EINVAL, "no mpdata_step call with step diagnostics on since they were "
+                                   "switched on");
+    double h[4];
+    hipError_t e = hipMemcpyAsync(h, plan->L.sdiag, sizeof h, hipMemcpyDeviceToHost, plan->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "step diagnostics copy");
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+    *n_nonfinite = (int64_t)h[3];
+    if (*n_nonfinite > 0)
+        return fail(MPDATA_ENONFINITE, "%lld non-finite values", (long long)*n_nonfinite);
+    return MPDATA_OK;
 }
 
 int mpdata_step_rhs(mpdata_plan *plan, void *psi, const void *g, const void *c0,
@@ -947,7 +1020,7 @@ size_t mpdata_adj_workspace_bytes(const mpdata_desc *desc, int n_steps, int ckpt
     mp::Geom g;
     if (check_desc(desc, &g) != MPDATA_OK) return 0;
     if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps) return 0;
-    size_t base = carve(g, desc->dtype, nullptr).bytes;
+    size_t base = carve(g, desc->dtype, nullptr, desc->n_iters, desc->opts).bytes;
     return base + mp::adj_extra_bytes(g, desc->dtype == MPDATA_F64 ? 8 : 4, desc->n_iters,
                                       n_steps, ckpt_every);
 }

@@ -2,9 +2,9 @@
 // Courant-number check.
 //
 // Two-level deterministic reduction: a fixed grid of blocks writes one
-// partial each (FP64 Neumaier-compensated sum, min, max, non-finite count),
-// one block combines the partials in index order.  The result does not
-// depend on scheduling.
+// partial each (FP64 Neumaier-compensated sum, min, max, non-finite count;
+// wavefront butterflies inside a block), one block combines the partials in
+// index order.  The result does not depend on scheduling.
 #include <math.h>
 
 #include "common.hpp"
@@ -48,30 +48,42 @@ __device__ inline void acc_merge(Acc &A, const Acc &B)
     A.bad += B.bad;
 }
 
+// Reduction of one block's accumulators: a butterfly within each wavefront
+// (lane-to-lane exchanges, no LDS), then the waves' results merged in wave
+// order by the first wave.  The data flow is fixed, so the result does not
+// depend on scheduling.
+__device__ inline Acc lane_xor(const Acc &A, int m)
+{
+    return {__shfl_xor(A.s, m), __shfl_xor(A.c, m), __shfl_xor(A.mn, m), __shfl_xor(A.mx, m),
+            __shfl_xor(A.bad, m)};
+}
+
 __device__ void block_reduce(Acc &A)
 {
-    __shared__ double sh[5][DB];
-    int t = threadIdx.x;
-    sh[0][t] = A.s;
-    sh[1][t] = A.c;
-    sh[2][t] = A.mn;
-    sh[3][t] = A.mx;
-    sh[4][t] = A.bad;
-    __syncthreads();
-    for (int w = DB / 2; w > 0; w >>= 1) {
-        if (t < w) {
-            Acc X = {sh[0][t], sh[1][t], sh[2][t], sh[3][t], sh[4][t]};
-            Acc Y = {sh[0][t + w], sh[1][t + w], sh[2][t + w], sh[3][t + w], sh[4][t + w]};
-            acc_merge(X, Y);
-            sh[0][t] = X.s;
-            sh[1][t] = X.c;
-            sh[2][t] = X.mn;
-            sh[3][t] = X.mx;
-            sh[4][t] = X.bad;
-        }
-        __syncthreads();
+    constexpr int W = 64, NW = DB / W;
+    __shared__ double sh[5][NW];
+#pragma unroll
+    for (int m = W / 2; m > 0; m >>= 1) {
+        const Acc B = lane_xor(A, m);
+        acc_merge(A, B);
     }
-    A = {sh[0][0], sh[1][0], sh[2][0], sh[3][0], sh[4][0]};
+    const int t = threadIdx.x, w = t / W;
+    if ((t % W) == 0) {
+        sh[0][w] = A.s;
+        sh[1][w] = A.c;
+        sh[2][w] = A.mn;
+        sh[3][w] = A.mx;
+        sh[4][w] = A.bad;
+    }
+    __syncthreads();
+    if (t == 0) {
+        A = {sh[0][0], sh[1][0], sh[2][0], sh[3][0], sh[4][0]};
+        for (int k = 1; k < NW; k++) {
+            const Acc B = {sh[0][k], sh[1][k], sh[2][k], sh[3][k], sh[4][k]};
+            acc_merge(A, B);
+        }
+    }
+    __syncthreads();
 }
 
 template <typename T>
@@ -203,6 +215,12 @@ hipError_t diag_launch(const T *psi, const T *G, int64_t N, double *part, double
     int nb = blocks_for(N);
     k_diag_part<T><<<nb, DB, 0, s>>>(psi, G, N, part);
     k_diag_final<<<1, DB, 0, s>>>(part, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t diag_final_launch(const double *part, int nparts, double *out, hipStream_t s)
+{
+    k_diag_final<<<1, DB, 0, s>>>(part, nparts, out);
     return hipGetLastError();
 }
 

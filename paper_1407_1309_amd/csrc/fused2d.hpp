@@ -301,9 +301,67 @@ template <int NI, bool FCT> struct Cfg {
 // Prefetch distance (rows in flight ahead of the one being consumed).
 constexpr int PF = 2;
 
+// Diagnostics of the cells a lane stores (the conserved sum G psi of Sect. 1
+// with G = 1, the extrema, and the non-finite count of the NaN checks of
+// Sect. 2.4), accumulated in FP64 with Neumaier's compensation and reduced
+// over the wave at the end of a chunk into one partial (sum, compensation,
+// min, max, count), the layout of the diagnostics kernels' partials.  A
+// non-finite value is recognised from its exponent bits: this file is built
+// assuming NaN-free floating-point arithmetic, so no floating-point test is
+// trusted to see one.
+struct StepDiag {
+    double s, c, mn, mx, bad;
+
+    __device__ __forceinline__ void init()
+    {
+        s = c = bad = 0.0;
+        mn = __builtin_huge_val();
+        mx = -__builtin_huge_val();
+    }
+    template <typename T> __device__ __forceinline__ void add(T y, bool on)
+    {
+        const double v = (double)y;
+        // this file is built assuming no NaN arithmetic: the empty asm hides
+        // where the bits came from, so the test of them is not folded away
+        long long b = __double_as_longlong(v);
+        asm volatile("" : "+v"(b));
+        const bool nonfin = ((b >> 52) & 0x7ff) == 0x7ff;
+        const bool fin = on && !nonfin;
+        const double term = fin ? v : 0.0;
+        const double t = s + term;
+        c += fabs(s) >= fabs(term) ? (s - t) + term : (term - t) + s;
+        s = t;
+        mn = fin ? fmin(mn, v) : mn;
+        mx = fin ? fmax(mx, v) : mx;
+        bad += (on && nonfin) ? 1.0 : 0.0;
+    }
+    // butterfly over the wave (fixed data flow: deterministic); lane 0 writes
+    __device__ __forceinline__ void wave_write(double *p)
+    {
+#pragma unroll
+        for (int m = WAVE / 2; m > 0; m >>= 1) {
+            const double s2 = __shfl_xor(s, m), c2 = __shfl_xor(c, m), mn2 = __shfl_xor(mn, m),
+                         mx2 = __shfl_xor(mx, m), b2 = __shfl_xor(bad, m);
+            const double ss = s + s2, bb = ss - s, e = (s - (ss - bb)) + (s2 - bb);
+            s = ss;
+            c = c + c2 + e;
+            mn = fmin(mn, mn2);
+            mx = fmax(mx, mx2);
+            bad += b2;
+        }
+        if ((threadIdx.x & (WAVE - 1)) == 0) {
+            p[0] = s;
+            p[1] = c;
+            p[2] = mn;
+            p[3] = mx;
+            p[4] = bad;
+        }
+    }
+};
+
 // State of one wavefront marching down rows i0..i1-1 of a 64-column strip
 // (quotients in fast or safe mode, see qset).
-template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Strip {
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool DG, bool SAFE> struct Strip {
     using C = Cfg<NI, FCT>;
     int n0, n1, i0, i1, jj, rr;
     int64_t ld1;
@@ -316,6 +374,7 @@ template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Str
     Ring<T, 2> dc0, dc1;
     T fp[PF], f0[PF], f1[PF];
     Pass<T> ps[C::NP > 0 ? C::NP : 1];
+    StepDiag dg;       // DG: diagnostics of the cells this lane stores
 
     // advance the load pointers one row, wrapping at n0 (selects, not a
     // branch, so that a row of the unrolled loop stays one basic block)
@@ -367,19 +426,21 @@ template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE> struct Str
         if constexpr (NPASS == C::NP) {     // warm-up rows store nothing
             const bool row_out = t - C::LAG >= i0 && t - C::LAG < i1;
             if (out_lane && row_out) *orow = y;
+            if constexpr (DG) dg.add(y, out_lane && row_out);
             orow += row_out ? n1 : 0;
         }
     }
 };
 
 // iterations t .. t+N-1 with phases P0 .. P0+N-1, NPASS corrective passes
-template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE, int N, int P0, int NPASS,
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool DG, bool SAFE, int N, int P0,
+          int NPASS,
           int I = 0>
-__device__ __forceinline__ void iter_block(Strip<T, NI, FCT, ABS, KH, SAFE> &st, int t)
+__device__ __forceinline__ void iter_block(Strip<T, NI, FCT, ABS, KH, DG, SAFE> &st, int t)
 {
     if constexpr (I < N) {
         st.template iter<P0 + I, NPASS>(t + I);
-        iter_block<T, NI, FCT, ABS, KH, SAFE, N, P0, NPASS, I + 1>(st, t);
+        iter_block<T, NI, FCT, ABS, KH, DG, SAFE, N, P0, NPASS, I + 1>(st, t);
     }
 }
 
@@ -390,27 +451,29 @@ __device__ __forceinline__ void iter_block(Strip<T, NI, FCT, ABS, KH, SAFE> &st,
 // the donor pass only, and each following group of four runs one corrective
 // pass more (stage K: iterations 4K-1 .. 4K+2, K passes), all in straight
 // code; from relative iteration 4 NP - 1 on every pass runs.
-template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE, int K = 0>
-__device__ __forceinline__ void warm_up(Strip<T, NI, FCT, ABS, KH, SAFE> &st, int t_begin)
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool DG, bool SAFE, int K = 0>
+__device__ __forceinline__ void warm_up(Strip<T, NI, FCT, ABS, KH, DG, SAFE> &st, int t_begin)
 {
     constexpr int NP = Cfg<NI, FCT>::NP;
     if constexpr (K < NP) {
         constexpr int start = K == 0 ? 0 : 4 * K - 1, len = K == 0 ? 3 : 4;
-        iter_block<T, NI, FCT, ABS, KH, SAFE, len, start, K>(st, t_begin + start);
-        warm_up<T, NI, FCT, ABS, KH, SAFE, K + 1>(st, t_begin);
+        iter_block<T, NI, FCT, ABS, KH, DG, SAFE, len, start, K>(st, t_begin + start);
+        warm_up<T, NI, FCT, ABS, KH, DG, SAFE, K + 1>(st, t_begin);
     }
 }
 
 // One chunk of one strip; returns true when fast mode met a divisor outside
 // its range (the rows stored are then not to be kept).
-template <typename T, int NI, bool FCT, bool ABS, bool KH, bool SAFE>
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool DG, bool SAFE>
 __device__ __forceinline__ bool strip_pass(int n0, int n1, const T *__restrict__ psi_n,
                                            T *__restrict__ psi_out, const T *__restrict__ c0,
-                                           const T *__restrict__ c1, int jstrip0, int i0, int i1)
+                                           const T *__restrict__ c1, int jstrip0, int i0, int i1,
+                                           StepDiag &dg)
 {
     using C = Cfg<NI, FCT>;
-    Strip<T, NI, FCT, ABS, KH, SAFE> st;
+    Strip<T, NI, FCT, ABS, KH, DG, SAFE> st;
     st.bad = 0;
+    st.dg.init();
     const int lane = threadIdx.x & (WAVE - 1);
     // global column of this lane (may lie outside [0, n1) in the halo)
     const int col = jstrip0 - C::H + lane;
@@ -459,41 +522,51 @@ __device__ __forceinline__ bool strip_pass(int n0, int n1, const T *__restrict__
     // warm-up (W iterations; a chunk has th + 4 NI - 1 > W), then the full
     // rows in blocks of U and UT whose phases continue from W
     constexpr int W = C::NP == 0 ? 0 : 4 * C::NP - 1;
-    warm_up<T, NI, FCT, ABS, KH, SAFE>(st, t_begin);
+    warm_up<T, NI, FCT, ABS, KH, DG, SAFE>(st, t_begin);
     int t = t_begin + W;
     for (; t + C::U - 1 <= t_end; t += C::U)
-        iter_block<T, NI, FCT, ABS, KH, SAFE, C::U, W, C::NP>(st, t);
+        iter_block<T, NI, FCT, ABS, KH, DG, SAFE, C::U, W, C::NP>(st, t);
     if constexpr (C::UT < C::U) {
-        for (; t <= t_end; t += C::UT) iter_block<T, NI, FCT, ABS, KH, SAFE, C::UT, W, C::NP>(st, t);
+        for (; t <= t_end; t += C::UT) iter_block<T, NI, FCT, ABS, KH, DG, SAFE, C::UT, W, C::NP>(st, t);
     } else {
-        if (t <= t_end) iter_block<T, NI, FCT, ABS, KH, SAFE, C::U, W, C::NP>(st, t);
+        if (t <= t_end) iter_block<T, NI, FCT, ABS, KH, DG, SAFE, C::U, W, C::NP>(st, t);
     }
+    dg = st.dg;
     return st.bad != 0;
 }
 
 // Fast mode, then (rarely, wave-uniformly) the same chunk again in safe mode.
-template <typename T, int NI, bool FCT, bool ABS, bool KH>
+// DG: the diagnostics of the rows kept, reduced over the wave, are written as
+// partial `part_idx` of dpart (sum, compensation, min, max, non-finite count).
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool DG>
 __device__ __forceinline__ void strip_body(int n0, int n1, const T *__restrict__ psi_n,
                                            T *__restrict__ psi_out, const T *__restrict__ c0,
-                                           const T *__restrict__ c1, int jstrip0, int i0, int i1)
+                                           const T *__restrict__ c1, int jstrip0, int i0, int i1,
+                                           double *__restrict__ dpart, int part_idx)
 {
-    if (strip_pass<T, NI, FCT, ABS, KH, false>(n0, n1, psi_n, psi_out, c0, c1, jstrip0, i0, i1))
-        strip_pass<T, NI, FCT, ABS, KH, true>(n0, n1, psi_n, psi_out, c0, c1, jstrip0, i0, i1);
+    StepDiag dg;
+    if (strip_pass<T, NI, FCT, ABS, KH, DG, false>(n0, n1, psi_n, psi_out, c0, c1, jstrip0, i0,
+                                                   i1, dg))
+        strip_pass<T, NI, FCT, ABS, KH, DG, true>(n0, n1, psi_n, psi_out, c0, c1, jstrip0, i0, i1,
+                                                  dg);
+    if constexpr (DG) dg.wave_write(dpart + 5 * (int64_t)part_idx);
 }
 
-template <typename T, int NI, bool FCT, bool ABS, bool KH>
+template <typename T, int NI, bool FCT, bool ABS, bool KH, bool DG>
 __global__ void __launch_bounds__(WAVE) k_fused2d(int n0, int n1, int th, int strips,
                                                   const T *__restrict__ psi_n,
                                                   T *__restrict__ psi_out,
                                                   const T *__restrict__ c0,
-                                                  const T *__restrict__ c1)
+                                                  const T *__restrict__ c1,
+                                                  double *__restrict__ dpart)
 {
     using C = Cfg<NI, FCT>;
     int b = blockIdx.x;
     int strip = b % strips, chunk = b / strips;
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT, ABS, KH>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1);
+    strip_body<T, NI, FCT, ABS, KH, DG>(n0, n1, psi_n, psi_out, c0, c1, strip * C::OW, i0, i1,
+                                        dpart, b);
 }
 
 template <typename T, int NI, bool FCT, bool ABS, bool KH>
@@ -529,8 +602,9 @@ __global__ void __launch_bounds__(WAVE) k_fused2d_batched(const BatchGrid *__res
     int n0 = (int)g.n0, n1 = (int)g.n1;
     int i0 = chunk * th;
     int i1 = i0 + th < n0 ? i0 + th : n0;
-    strip_body<T, NI, FCT, ABS, KH>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi,
-                                    c0 + g.off_c0, c1 + g.off_c1, strip * C::OW, i0, i1);
+    strip_body<T, NI, FCT, ABS, KH, false>(n0, n1, psi_n + g.off_psi, psi_out + g.off_psi,
+                                           c0 + g.off_c0, c1 + g.off_c1, strip * C::OW, i0, i1,
+                                           nullptr, 0);
 }
 
 // default rows per chunk (when not tuned): about two waves per SIMD, so the
@@ -547,7 +621,7 @@ int64_t rows_per_chunk(int64_t n0, int64_t strips)
 
 template <typename T, int NI, bool FCT, bool ABS, bool KH>
 hipError_t launch(const Fused2DShape &sh, const T *psi_n, T *psi_out, const T *c0,
-                  const T *c1, hipStream_t s)
+                  const T *c1, double *dpart, int *dparts, hipStream_t s)
 {
     using C = Cfg<NI, FCT>;
     int64_t strips = cdiv(sh.n1, C::OW);
@@ -555,8 +629,14 @@ hipError_t launch(const Fused2DShape &sh, const T *psi_n, T *psi_out, const T *c
     if (th > sh.n0) th = sh.n0;
     int64_t chunks = cdiv(sh.n0, th);
     int64_t blocks = strips * chunks;
-    k_fused2d<T, NI, FCT, ABS, KH><<<(unsigned)blocks, WAVE, 0, s>>>(
-        (int)sh.n0, (int)sh.n1, (int)th, (int)strips, psi_n, psi_out, c0, c1);
+    if (dpart) {
+        if (dparts) *dparts = (int)blocks;
+        k_fused2d<T, NI, FCT, ABS, KH, true><<<(unsigned)blocks, WAVE, 0, s>>>(
+            (int)sh.n0, (int)sh.n1, (int)th, (int)strips, psi_n, psi_out, c0, c1, dpart);
+    } else {
+        k_fused2d<T, NI, FCT, ABS, KH, false><<<(unsigned)blocks, WAVE, 0, s>>>(
+            (int)sh.n0, (int)sh.n1, (int)th, (int)strips, psi_n, psi_out, c0, c1, nullptr);
+    }
     return hipGetLastError();
 }
 
@@ -574,16 +654,17 @@ hipError_t launch_batched(const BatchGrid *g, int n_grids, int n_tiles, int th, 
 
 template <typename T>
 hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
-                        T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s)
+                        T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s,
+                        double *dpart, int *dparts)
 {
     if (G || sh.bc0 != BC_PERIODIC || sh.bc1 != BC_PERIODIC) return hipErrorNotSupported;
     if (psi_n == psi_out) return hipErrorInvalidValue;   // a chunk may be recomputed (qset)
     bool fct = opts & OPT_FCT;
     const bool kahan = opts & OPT_KAHAN;
     const bool absf = (opts & OPT_ABS) && n_iters > 1;
-#define MP_L(NI, F, A)                                                                   \
-    (kahan ? launch<T, NI, F, A, true>(sh, psi_n, psi_out, c0, c1, s)                    \
-           : launch<T, NI, F, A, false>(sh, psi_n, psi_out, c0, c1, s))
+#define MP_L(NI, F, A)                                                                     \
+    (kahan ? launch<T, NI, F, A, true>(sh, psi_n, psi_out, c0, c1, dpart, dparts, s)       \
+           : launch<T, NI, F, A, false>(sh, psi_n, psi_out, c0, c1, dpart, dparts, s))
     if (absf) {
         switch (n_iters * 2 + (fct ? 1 : 0)) {
         case 4: return MP_L(2, false, true);

@@ -14,6 +14,11 @@ bool fused2d_supported(int nd, int n_iters, unsigned opts, int has_g, int bc0, i
 
 int fused2d_tile_rows() { return 64; }
 
+int64_t fused2d_max_parts(int64_t n0, int64_t n1, int n_iters, unsigned opts, int min_rows)
+{
+    return cdiv(n1, fused2d_strip_cols(n_iters, opts)) * cdiv(n0, min_rows);
+}
+
 int fused2d_strip_cols(int n_iters, unsigned opts)
 {
     int np = n_iters - 1;
@@ -23,7 +28,7 @@ int fused2d_strip_cols(int n_iters, unsigned opts)
 
 template hipError_t fused2d_step<double>(const Fused2DShape &, int, unsigned, const double *,
                                          double *, const double *, const double *, const double *,
-                                         hipStream_t);
+                                         hipStream_t, double *, int *);
 template hipError_t fused2d_batched_step<double>(const BatchGrid *, int, int, int, int, unsigned,
                                                  int, int, const double *, double *,
                                                  const double *, const double *, hipStream_t);

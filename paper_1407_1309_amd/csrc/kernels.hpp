@@ -44,6 +44,8 @@ int diag_max_blocks();
 template <typename T>
 hipError_t diag_launch(const T *psi, const T *G, int64_t N, double *part, double *out,
                        hipStream_t s);
+// the final merge alone, over nparts partials written by another kernel
+hipError_t diag_final_launch(const double *part, int nparts, double *out, hipStream_t s);
 
 // out[0] = max over cells of sum_d max(|c_d| lo, |c_d| hi) / G where it is
 // finite; out[1] = the number of cells where it is not.
@@ -61,9 +63,17 @@ struct Fused2DShape {
 // true if a fused kernel exists for this configuration
 bool fused2d_supported(int nd, int n_iters, unsigned opts, int has_g, int bc0, int bc1);
 
+// dpart != NULL: the launch also writes the diagnostics of the cells it
+// stores, one partial per wave (5 doubles: sum, compensation, min, max,
+// non-finite count) into dpart, and their number into *dparts; the final
+// merge is diag_final_launch
 template <typename T>
 hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, const T *psi_n,
-                        T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s);
+                        T *psi_out, const T *c0, const T *c1, const T *G, hipStream_t s,
+                        double *dpart = nullptr, int *dparts = nullptr);
+// the wave partials the fused 2-D step writes per 64-column strip chunk: an
+// upper bound for chunks of at least min_rows rows
+int64_t fused2d_max_parts(int64_t n0, int64_t n1, int n_iters, unsigned opts, int min_rows);
 
 // ---- 3-D, two passes without the limiter: one launch per step (step3d.hip;
 // the donor-only step and the fallback are the kernel pair of fused3d.hip)

@@ -35,7 +35,8 @@ EXPORTS = [
     "mpdata_autotune_batched", "mpdata_timing", "mpdata_timing_read", "mpdata_step_rhs",
     "mpdata_osc_step", "mpdata_vip_advector", "mpdata_sw_step", "mpdata_set_cancel_flag",
     "mpdata_steps_done", "mpdata_tlm_step", "mpdata_tlm_workspace_bytes",
-    "mpdata_diag_noalloc", "mpdata_destroy", "mpdata_last_error",
+    "mpdata_diag_noalloc", "mpdata_set_step_diag", "mpdata_step_diag",
+    "mpdata_destroy", "mpdata_last_error",
 ]
 
 
@@ -75,6 +76,9 @@ def lib():
         L.mpdata_diag.argtypes = [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
         L.mpdata_courant_max.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)]
+        L.mpdata_set_step_diag.argtypes = [_VP, ctypes.c_int]
+        L.mpdata_step_diag.argtypes = [_VP, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
         L.mpdata_diag_noalloc.argtypes = [ctypes.c_int, ctypes.c_int64, _VP, _VP, _VP,
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]
@@ -407,6 +411,20 @@ class Plan:
         out = (ctypes.c_double * 3)()
         bad = ctypes.c_int64(0)
         rc = lib().mpdata_diag(self._handle, _ptr(psi), _ptr(g), out, ctypes.byref(bad))
+        if rc not in (OK, ENONFINITE):
+            _check(rc)
+        return out[0], out[1], out[2], int(bad.value)
+
+    def set_step_diag(self, on=True):
+        """Have every later step call form the diagnostics of its result."""
+        _check(lib().mpdata_set_step_diag(self._handle, 1 if on else 0))
+
+    def step_diag(self):
+        """(sum G psi, min, max, n_nonfinite) of the last step call's result."""
+        self._bind_stream()
+        out = (ctypes.c_double * 3)()
+        bad = ctypes.c_int64(0)
+        rc = lib().mpdata_step_diag(self._handle, out, ctypes.byref(bad))
         if rc not in (OK, ENONFINITE):
             _check(rc)
         return out[0], out[1], out[2], int(bad.value)
