@@ -6,10 +6,14 @@
 // their states, and every step is reversed stage by stage.  The forward
 // recompute of a step runs the staged kernels and keeps each pass's input
 // field, raw and limited pseudo-velocities and limiter coefficients; the
-// reverse kernels are the transposes of those stages, one thread per
-// forward output (cell or wall), scattering into the adjoints of the values
-// that output read (through the boundary map) with hardware floating-point
-// atomics.
+// reverse kernels are the transposes of those stages.  The donor-cell and
+// limiter transposes, and in 2-D without third-order terms the
+// pseudo-velocity transpose, gather: every adjoint entry is summed by one
+// thread over the forward outputs that read it (through the boundary map),
+// in a fixed order, so these gradients are the same bits on every run.  The
+// general pseudo-velocity transpose (1-D, 3-D, third-order terms) scatters
+// from one thread per wall with hardware floating-point atomics, whose
+// order -- and so the last bits of the sums -- can change between runs.
 //
 // Conventions at non-differentiable points: d[u]+/du = [u > 0],
 // d[u]-/du = [u < 0], d|u|/du = [u > 0] - [u < 0]; max/min pass the
@@ -449,30 +453,26 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
     }
 }
 
-// 2-D transpose of the pseudo-velocity (no third-order terms) with the
-// scatter staged in LDS.  A workgroup owns a tile of TPR x TPC cells and
-// both walls each cell owns (its low dimension-0 and low dimension-1 wall,
-// plus the far edge walls along the tile grid's last row / column): it
-// accumulates their contributions to the cell adjoint and to the advector
-// adjoints of the other dimension's walls (cross terms) in three LDS boxes
-// (the tile plus a one-cell rim, in coordinates before the boundary map),
-// then adds each non-zero box entry to the mapped global entry with one
-// atomic -- about one global atomic per target instead of one per
-// contribution, and one flush for both wall sets.
-constexpr int TPR = 4, TPC = 64;                  // tile rows x columns (cells)
-constexpr int BXR = TPR + 2, BXC = TPC + 2;       // LDS box: rows / columns
-
-// 2-D boundary map with compile-time boundary types (coordinates at most one
-// period outside the range) and 32-bit flat indices (n0 n1 < 2^31)
+// 2-D boundary map with compile-time boundary types (coordinates at most two
+// periods outside the range: the halo of a one-cell-wide dimension) and
+// 32-bit flat indices (n0 n1 < 2^31)
 template <int BC> __device__ __forceinline__ int wc2(int q, int n)
 {
-    if constexpr (BC == BC_PERIODIC) return q < 0 ? q + n : (q >= n ? q - n : q);
-    else return q < 0 ? 0 : (q >= n ? n - 1 : q);
+    if constexpr (BC == BC_PERIODIC) {
+        q = q < 0 ? q + n : (q >= n ? q - n : q);
+        return q < 0 ? q + n : (q >= n ? q - n : q);
+    } else {
+        return q < 0 ? 0 : (q >= n ? n - 1 : q);
+    }
 }
 template <int BC> __device__ __forceinline__ int ww2(int f, int n)
 {
-    if constexpr (BC == BC_PERIODIC) return f < 0 ? f + n : (f >= n ? f - n : f);
-    else return f < 0 ? 0 : (f > n ? n : f);
+    if constexpr (BC == BC_PERIODIC) {
+        f = f < 0 ? f + n : (f >= n ? f - n : f);
+        return f < 0 ? f + n : (f >= n ? f - n : f);
+    } else {
+        return f < 0 ? 0 : (f > n ? n : f);
+    }
 }
 template <int BC0, int BC1> struct Map2 {
     int n0, n1;
@@ -487,228 +487,304 @@ template <int BC0, int BC1> struct Map2 {
     }
 };
 
-// one wall of dimension WD at unmapped (i, j) of the tile at (i0, j0):
-// contributions to the cell adjoint (box XB) and to the dimension-(1-WD)
-// walls' advector adjoint (box CBo); its own advector adjoint goes to cb_own
+// Deterministic 2-D transpose of the pseudo-velocity (no third-order
+// terms).  A workgroup owns a tile of GR x GC cells, their low walls of both
+// dimensions and, along an open dimension, the far edge walls of its last
+// tile.  Phase 1 evaluates, for every wall the tile's cells read (the tile's
+// walls plus a one-wall halo, in coordinates before the boundary map), the
+// adjoint the wall sends to each of its stencil roles, into LDS; phase 2 has
+// every cell sum what its roles receive, and every owned wall its own term
+// plus the cross terms, in a fixed order.  Each adjoint entry has one writer
+// and one summation order: the same bits on every run.
+constexpr int GR = 8, GC = 64, GT = GR * GC;
+constexpr int Q0R = GR + 1, Q0C = GC + 2;   // dimension-0 walls: rows i0..i0+GR, cols j0-1..j0+GC
+constexpr int Q1R = GR + 2, Q1C = GC + 1;   // dimension-1 walls: rows i0-1..i0+GR, cols j0..j0+GC
+constexpr int NQ0 = Q0R * Q0C, NQ1 = Q1R * Q1C;
+// what a wall sends: to its right / left cell (the A term), to the cells
+// beside them on the +o / -o side (the B term), to the dimension-o walls of
+// its cross-advector mean (a quarter each), and to its own advector
+enum { KR, KL, KP, KM, KQ, KU, NK };
+
 template <typename T, int WD, int BC0, int BC1>
-__device__ __forceinline__ void pseudo_wall2(const Map2<BC0, BC1> &g, unsigned opts,
+__device__ __forceinline__ void pseudo_coef2(const Map2<BC0, BC1> &g, unsigned opts,
                                              const T *__restrict__ x, const T *const c[2],
-                                             const T *G, T vb, int i, int j, int i0, int j0,
-                                             T *XB, T *CBo, T *cb_own)
+                                             const T *G, T vb, int i, int j, T k[NK])
 {
     constexpr int d = WD, o = 1 - WD;
-    // box entry of unmapped coordinates (i, j)
-    auto bx = [&](int bi, int bj) { return (bi - i0 + 1) * BXC + (bj - j0 + 1); };
     const bool iga = opts & OPT_IGA;
-    I3 p{{i, j, 0}};
-    I3 L = sh1(p, d, -1), R = p;
-    T u = c[d][g.wall(d, p)];
-    T GL = G ? G[g.cell(L)] : T(1), GR = G ? G[g.cell(R)] : T(1);
-    T Gb = T(0.5) * (GL + GR);
-    const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
-    T xL = x[g.cell(L)], xR = x[g.cell(R)];
-    T ub = T(0), fn, fd;
-    T nA = xR - xL, dA = xR + xL;
-    T A;
-    frac_vd(iga, nA, dA, T(2), A, fn, fd);
-    ub += (sgnv(u) - T(2) * u * iGb) * A * vb;
-    T Ab = (fabs(u) - u * u * iGb) * vb;
-    atomicAdd(&XB[bx(R.v[0], R.v[1])], (fn + fd) * Ab);
-    atomicAdd(&XB[bx(L.v[0], L.v[1])], (-fn + fd) * Ab);
-    I3 Lo = sh1(L, o, 1), Ro = sh1(R, o, 1);
-    T cbar = T(0.25) * (c[o][g.wall(o, L)] + c[o][g.wall(o, Lo)] + c[o][g.wall(o, R)] +
-                        c[o][g.wall(o, Ro)]);
-    I3 Rp = sh1(R, o, 1), Lp = sh1(L, o, 1), Rm = sh1(R, o, -1), Lm = sh1(L, o, -1);
-    T a = x[g.cell(Rp)], b = x[g.cell(Lp)], ee = x[g.cell(Rm)], f = x[g.cell(Lm)];
-    T nB = a + b - ee - f, dB = a + b + ee + f;
+    const I3 p{{i, j, 0}};
+    const I3 L = sh1(p, d, -1), R = p;
+    const T u = c[d][g.wall(d, p)];
+    T iGb = T(1);
+    if (G) iGb = T(1) / (T(0.5) * (G[g.cell(L)] + G[g.cell(R)]));
+    const T xL = x[g.cell(L)], xR = x[g.cell(R)];
+    T fn, fd, A;
+    frac_vd(iga, xR - xL, xR + xL, T(2), A, fn, fd);
+    T ub = (sgnv(u) - T(2) * u * iGb) * A * vb;
+    const T Ab = (fabs(u) - u * u * iGb) * vb;
+    k[KR] = (fn + fd) * Ab;
+    k[KL] = (-fn + fd) * Ab;
+    const I3 Lo = sh1(L, o, 1), Ro = sh1(R, o, 1);
+    const T cbar = T(0.25) * (c[o][g.wall(o, L)] + c[o][g.wall(o, Lo)] + c[o][g.wall(o, R)] +
+                              c[o][g.wall(o, Ro)]);
+    const T a = x[g.cell(sh1(R, o, 1))], b = x[g.cell(sh1(L, o, 1))];
+    const T e = x[g.cell(sh1(R, o, -1))], f = x[g.cell(sh1(L, o, -1))];
     T Bv;
-    frac_vd(iga, nB, dB, T(4), Bv, fn, fd);
+    frac_vd(iga, a + b - e - f, a + b + e + f, T(4), Bv, fn, fd);
     ub += T(-0.5) * cbar * iGb * Bv * vb;
-    T cbar_b = T(-0.5) * u * iGb * Bv * vb;
-    T Bb = T(-0.5) * u * cbar * iGb * vb;
-    atomicAdd(&XB[bx(Rp.v[0], Rp.v[1])], (fn + fd) * Bb);
-    atomicAdd(&XB[bx(Lp.v[0], Lp.v[1])], (fn + fd) * Bb);
-    atomicAdd(&XB[bx(Rm.v[0], Rm.v[1])], (-fn + fd) * Bb);
-    atomicAdd(&XB[bx(Lm.v[0], Lm.v[1])], (-fn + fd) * Bb);
-    if (cbar_b != T(0)) {
-        T q = T(0.25) * cbar_b;
-        atomicAdd(&CBo[bx(L.v[0], L.v[1])], q);
-        atomicAdd(&CBo[bx(Lo.v[0], Lo.v[1])], q);
-        atomicAdd(&CBo[bx(R.v[0], R.v[1])], q);
-        atomicAdd(&CBo[bx(Ro.v[0], Ro.v[1])], q);
-    }
-    aadd(cb_own, (int64_t)g.wall(d, p), ub);
+    const T Bb = T(-0.5) * u * cbar * iGb * vb;
+    k[KP] = (fn + fd) * Bb;
+    k[KM] = (-fn + fd) * Bb;
+    k[KQ] = T(0.25) * (T(-0.5) * u * iGb * Bv * vb);
+    k[KU] = ub;
 }
 
 template <typename T, int BC0, int BC1>
-__global__ void __launch_bounds__(TPR * TPC)
-k_pseudo_adj2(Geom gg, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
-              const T *G, const T *__restrict__ Vb0, const T *__restrict__ Vb1, T *xb, T *cb0,
-              T *cb1)
+__global__ void __launch_bounds__(GT)
+k_pseudo_adj2g(Geom gg, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
+               const T *G, const T *__restrict__ Vb0, const T *__restrict__ Vb1, T *xb, T *cb0,
+               T *cb1)
 {
     const Map2<BC0, BC1> g{(int)gg.n[0], (int)gg.n[1]};
-    __shared__ T XB[BXR * BXC];
-    __shared__ T CB0[BXR * BXC];   // dimension-0 walls (from dimension-1 walls' cross terms)
-    __shared__ T CB1[BXR * BXC];   // dimension-1 walls (from dimension-0 walls' cross terms)
+    __shared__ T K0[NK][NQ0];
+    __shared__ T K1[NK][NQ1];
     const int n0 = g.n0, n1 = g.n1;
-    // tiles cover the cells and the far edge walls: rows 0..n0, columns 0..n1
-    const int tiles_c = (n1 + 1 + TPC - 1) / TPC;
-    const int i0 = (blockIdx.x / tiles_c) * TPR, j0 = (blockIdx.x % tiles_c) * TPC;
-    const int tid = threadIdx.x;
-    for (int k = tid; k < BXR * BXC; k += TPR * TPC) {
-        XB[k] = T(0);
-        CB0[k] = T(0);
-        CB1[k] = T(0);
-    }
-    __syncthreads();
-    const int i = i0 + tid / TPC, j = j0 + tid % TPC;
+    const int tiles_c = (n1 + GC - 1) / GC;
+    const int i0 = (int)(blockIdx.x / tiles_c) * GR, j0 = (int)(blockIdx.x % tiles_c) * GC;
+    // the last wall row / column a cell of the tile reads; entries beyond
+    // them, and walls an open dimension does not have, hold zeros
+    const int ilim = min(i0 + GR, n0), jlim = min(j0 + GC, n1);
     const T *c[2] = {c0, c1};
-    if (i <= n0 && j < n1) {                       // dimension-0 wall (i, j)
-        const T vb = Vb0[(int64_t)i * n1 + j];
-        if (vb != T(0)) pseudo_wall2<T, 0>(g, opts, x, c, G, vb, i, j, i0, j0, XB, CB1, cb0);
+    // the stencil loads do not wait for the test of vb (a zero vb zeroes
+    // the coefficients afterwards)
+    for (int e = threadIdx.x; e < NQ0; e += GT) {
+        T k[NK] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        const int i = i0 + e / Q0C, j = j0 - 1 + e % Q0C;
+        bool ok = i <= ilim && j <= jlim;
+        if (BC1 == BC_OPEN) ok = ok && j >= 0 && j < n1;
+        if (ok) {
+            const T vb = Vb0[g.wall(0, I3{{i, j, 0}})];
+            pseudo_coef2<T, 0>(g, opts, x, c, G, vb, i, j, k);
+            if (vb == T(0))
+#pragma unroll
+                for (int r = 0; r < NK; r++) k[r] = T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < NK; r++) K0[r][e] = k[r];
     }
-    if (i < n0 && j <= n1) {                       // dimension-1 wall (i, j)
-        const T vb = Vb1[(int64_t)i * (n1 + 1) + j];
-        if (vb != T(0)) pseudo_wall2<T, 1>(g, opts, x, c, G, vb, i, j, i0, j0, XB, CB0, cb1);
+    for (int f = threadIdx.x; f < NQ1; f += GT) {
+        T k[NK] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        const int i = i0 - 1 + f / Q1C, j = j0 + f % Q1C;
+        bool ok = i <= ilim && j <= jlim;
+        if (BC0 == BC_OPEN) ok = ok && i >= 0 && i < n0;
+        if (ok) {
+            const T vb = Vb1[g.wall(1, I3{{i, j, 0}})];
+            pseudo_coef2<T, 1>(g, opts, x, c, G, vb, i, j, k);
+            if (vb == T(0))
+#pragma unroll
+                for (int r = 0; r < NK; r++) k[r] = T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < NK; r++) K1[r][f] = k[r];
     }
     __syncthreads();
-    // flush: box entries to the mapped global entries
-    for (int k = tid; k < BXR * BXC; k += TPR * TPC) {
-        I3 q{{i0 - 1 + k / BXC, j0 - 1 + k % BXC, 0}};
-        if (XB[k] != T(0)) aadd(xb, (int64_t)g.cell(q), XB[k]);
-        if (CB0[k] != T(0)) aadd(cb0, (int64_t)g.wall(0, q), CB0[k]);
-        if (CB1[k] != T(0)) aadd(cb1, (int64_t)g.wall(1, q), CB1[k]);
+    const int qi = i0 + (int)threadIdx.x / GC, qj = j0 + (int)threadIdx.x % GC;
+    if (qi >= n0 || qj >= n1) return;
+    // coefficient kind r of the wall at unmapped (i, j); zero outside the box
+    auto k0 = [&](int r, int i, int j) -> T {
+        const int a = i - i0, b = j - (j0 - 1);
+        return (a >= 0 && a < Q0R && b >= 0 && b < Q0C) ? K0[r][a * Q0C + b] : T(0);
+    };
+    auto k1 = [&](int r, int i, int j) -> T {
+        const int a = i - (i0 - 1), b = j - j0;
+        return (a >= 0 && a < Q1R && b >= 0 && b < Q1C) ? K1[r][a * Q1C + b] : T(0);
+    };
+    // the unmapped positions the boundary map sends to row qi / column qj:
+    // the cell itself, and past an open edge the position beyond it
+    int pr[3], pc[3], nr = 0, nc = 0;
+    pr[nr++] = qi;
+    if (BC0 == BC_OPEN && qi == 0) pr[nr++] = -1;
+    if (BC0 == BC_OPEN && qi == n0 - 1) pr[nr++] = n0;
+    pc[nc++] = qj;
+    if (BC1 == BC_OPEN && qj == 0) pc[nc++] = -1;
+    if (BC1 == BC_OPEN && qj == n1 - 1) pc[nc++] = n1;
+    // the cell: every role of every wall that lands on it
+    T acc = T(0);
+    for (int s = 0; s < nr; s++)
+        for (int t = 0; t < nc; t++) {
+            const int X0 = pr[s], X1 = pc[t];
+            acc += k0(KR, X0, X1) + k0(KL, X0 + 1, X1);                  // A term, d = 0
+            acc += k0(KP, X0, X1 - 1) + k0(KP, X0 + 1, X1 - 1);          // B term, +o side
+            acc += k0(KM, X0, X1 + 1) + k0(KM, X0 + 1, X1 + 1);          // B term, -o side
+            acc += k1(KR, X0, X1) + k1(KL, X0, X1 + 1);                  // A term, d = 1
+            acc += k1(KP, X0 - 1, X1) + k1(KP, X0 - 1, X1 + 1);
+            acc += k1(KM, X0 + 1, X1) + k1(KM, X0 + 1, X1 + 1);
+        }
+    xb[(int64_t)qi * n1 + qj] += acc;
+    // owned dimension-0 walls: the cell's low wall, and at an open far edge
+    // the edge wall; own term plus the cross terms of the dimension-1 walls
+    // whose cross-advector mean reads them
+    for (int w = 0; w < 2; w++) {
+        const int Y0 = w == 0 ? qi : n0;
+        if (w == 1 && !(BC0 == BC_OPEN && qi == n0 - 1)) continue;
+        T v = k0(KU, Y0, qj);
+        for (int t = 0; t < nc; t++) {
+            const int Z1 = pc[t];
+            v += k1(KQ, Y0, Z1 + 1) + k1(KQ, Y0 - 1, Z1 + 1) + k1(KQ, Y0, Z1) +
+                 k1(KQ, Y0 - 1, Z1);
+        }
+        cb0[(int64_t)Y0 * n1 + qj] += v;
+    }
+    for (int w = 0; w < 2; w++) {
+        const int Y1 = w == 0 ? qj : n1;
+        if (w == 1 && !(BC1 == BC_OPEN && qj == n1 - 1)) continue;
+        T v = k1(KU, qi, Y1);
+        for (int s = 0; s < nr; s++) {
+            const int Z0 = pr[s];
+            v += k0(KQ, Z0 + 1, Y1) + k0(KQ, Z0 + 1, Y1 - 1) + k0(KQ, Z0, Y1) +
+                 k0(KQ, Z0, Y1 - 1);
+        }
+        cb1[(int64_t)qi * (n1 + 1) + Y1] += v;
     }
 }
 
-// transpose of the limited velocity W = [V]+ up + [V]- dn at dimension-d walls
-template <typename T, int ND, int WD>
-__global__ void k_limit_adj(Geom g, const T *__restrict__ V, const T *__restrict__ bup,
-                            const T *__restrict__ bdn, const T *__restrict__ Wb, T *Vb, T *bub,
-                            T *bdb)
-{
-    constexpr int d = WD;   // wall dimension (compile time)
-    int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
-    e[d] += 1;
-    int64_t M = e[0] * e[1] * e[2];
-    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
-    if (t >= M) return;
-    I3 p = unflat_i3(t, e);
-    // periodic: wall n is wall 0 (its own thread); nothing reads entry n
-    if (g.bc[d] == BC_PERIODIC && p.v[d] == (int)g.n[d]) return;
-    T wb = Wb[t];
-    if (wb == T(0)) {
-        Vb[t] = T(0);
-        return;
-    }
-    I3 L = sh1(p, d, -1), R = p;
-    int64_t kL = ci(g, L), kR = ci(g, R);
-    T v = V[wi(g, d, p)];
-    T up = T(1), dn = T(1);
-    int wu = 0, wd = 0;
-    if (bdn[kL] < up) { up = bdn[kL]; wu = 1; }
-    if (bup[kR] < up) { up = bup[kR]; wu = 2; }
-    if (bup[kL] < dn) { dn = bup[kL]; wd = 1; }
-    if (bdn[kR] < dn) { dn = bdn[kR]; wd = 2; }
-    Vb[t] = ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb;   // first writer
-    T upb = pos(v) * wb, dnb = neg(v) * wb;
-    if (wu == 1) aadd(bdb, kL, upb);
-    if (wu == 2) aadd(bub, kR, upb);
-    if (wd == 1) aadd(bub, kL, dnb);
-    if (wd == 2) aadd(bdb, kR, dnb);
-}
+// ---- atomic-free limiter transposes -------------------------------------
+// The limited velocity W = [V]+ up + [V]- dn of a wall routes its adjoint to
+// the limiter coefficient of the cell that attains up / dn; the limiter
+// coefficients of a cell route theirs to the cell and face neighbours that
+// attain the bounds, to the neighbours' fluxes and to the cell's walls.  As
+// scatters these need atomics, whose order -- and so the rounding of the
+// sums -- changes from run to run.  Here every adjoint entry is written by
+// one thread that sums its contributions in a fixed order, so the gradient
+// is the same bits on every run.
 
-// 2-D: both wall sets in one launch, a thread per (row, column) of the
-// (n0+1) x (n1+1) grid handling the dimension-0 wall (i, j) (j < n1) and the
-// dimension-1 wall (i, j) (i < n0), each with the body of k_limit_adj
-template <typename T, int WD>
-__device__ __forceinline__ void limit_wall2(const Geom &g, int i, int j, int64_t t,
-                                            const T *__restrict__ V, const T *__restrict__ bup,
-                                            const T *__restrict__ bdn, const T *__restrict__ Wb,
-                                            T *Vb, T *bub, T *bdb)
-{
-    constexpr int d = WD;
-    I3 p{{i, j, 0}};
-    // periodic: wall n is wall 0 (its own thread); nothing reads entry n
-    if (g.bc[d] == BC_PERIODIC && p.v[d] == (int)g.n[d]) return;
-    T wb = Wb[t];
-    if (wb == T(0)) {
-        Vb[t] = T(0);
-        return;
-    }
-    I3 L = sh1(p, d, -1), R = p;
-    int64_t kL = ci(g, L), kR = ci(g, R);
-    T v = V[wi(g, d, p)];
-    T up = T(1), dn = T(1);
-    int wu = 0, wd = 0;
-    if (bdn[kL] < up) { up = bdn[kL]; wu = 1; }
-    if (bup[kR] < up) { up = bup[kR]; wu = 2; }
-    if (bup[kL] < dn) { dn = bup[kL]; wd = 1; }
-    if (bdn[kR] < dn) { dn = bdn[kR]; wd = 2; }
-    Vb[t] = ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb;   // first writer
-    T upb = pos(v) * wb, dnb = neg(v) * wb;
-    if (wu == 1) aadd(bdb, kL, upb);
-    if (wu == 2) aadd(bub, kR, upb);
-    if (wd == 1) aadd(bub, kL, dnb);
-    if (wd == 2) aadd(bdb, kR, dnb);
-}
+// the decision of one wall (mapped coordinates w, wall dimension d): its
+// cells L, R, which of them attains up and dn (0: the constant 1, 1: L,
+// 2: R), the adjoints sent (upb, dnb) and the velocity adjoint
+template <typename T> struct LimWall {
+    int64_t kL, kR;
+    int wu, wd;
+    T upb, dnb, vb;
+};
 
 template <typename T>
-__global__ void __launch_bounds__(B)
-k_limit_adj2(Geom g, const T *__restrict__ V0, const T *__restrict__ V1,
-             const T *__restrict__ bup, const T *__restrict__ bdn, const T *__restrict__ Wb0,
-             const T *__restrict__ Wb1, T *Vb0, T *Vb1, T *bub, T *bdb)
+__device__ __forceinline__ LimWall<T> lim_wall(const Geom &g, int d, const I3 &w, const T *V,
+                                               const T *bup, const T *bdn, const T *Wb)
 {
-    const int n0 = (int)g.n[0], n1 = (int)g.n[1];
-    const int i = blockIdx.y, j = blockIdx.x * B + threadIdx.x;
-    if (j > n1) return;
-    if (j < n1) limit_wall2<T, 0>(g, i, j, (int64_t)i * n1 + j, V0, bup, bdn, Wb0, Vb0, bub, bdb);
-    if (i < n0)
-        limit_wall2<T, 1>(g, i, j, (int64_t)i * (n1 + 1) + j, V1, bup, bdn, Wb1, Vb1, bub, bdb);
+    LimWall<T> r;
+    const int64_t kw = wi(g, d, w);
+    r.kL = ci(g, sh1(w, d, -1));
+    r.kR = ci(g, w);
+    const T wb = Wb[kw];
+    const T v = V[kw];
+    T up = T(1), dn = T(1);
+    r.wu = r.wd = 0;
+    if (bdn[r.kL] < up) { up = bdn[r.kL]; r.wu = 1; }
+    if (bup[r.kR] < up) { up = bup[r.kR]; r.wu = 2; }
+    if (bup[r.kL] < dn) { dn = bup[r.kL]; r.wd = 1; }
+    if (bdn[r.kR] < dn) { dn = bdn[r.kR]; r.wd = 2; }
+    r.vb = ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb;
+    r.upb = pos(v) * wb;
+    r.dnb = neg(v) * wb;
+    if (wb == T(0)) r.wu = r.wd = 0;
+    return r;
 }
 
-// transpose of the limiter coefficients (bounds, in/out fluxes) per cell
+// transpose of the limited velocities of all wall dimensions, one thread per
+// cell: it writes the velocity adjoint of the cell's low walls (and of an
+// open dimension's far edge wall), and sums into bub, bdb of the cell what
+// each of its 2 ND walls sends it (low then high wall, dimension by
+// dimension; the right-cell role before the left-cell role, which at an
+// open edge wall are the same cell).  bub and bdb are written, not added to.
 template <typename T, int ND>
-__global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
-                           const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
-                           const T *G, const T *__restrict__ bub, const T *__restrict__ bdb,
-                           T *xb, T *pnb, T *Vb0, T *Vb1, T *Vb2)
+__global__ void __launch_bounds__(B)
+k_limit_adj_gather(Geom g, const T *V0, const T *V1, const T *V2, const T *__restrict__ bup,
+                   const T *__restrict__ bdn, const T *Wb0, const T *Wb1, const T *Wb2, T *Vb0,
+                   T *Vb1, T *Vb2, T *__restrict__ bub, T *__restrict__ bdb)
 {
-    int64_t N = g.n[0] * g.n[1] * g.n[2];
-    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    const int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
     if (t >= N) return;
-    T bu_b = bub[t], bd_b = bdb[t];
-    if (bu_b == T(0) && bd_b == T(0)) return;
+    const T *V[3] = {V0, V1, V2}, *Wb[3] = {Wb0, Wb1, Wb2};
+    T *Vb[3] = {Vb0, Vb1, Vb2};
+    const I3 p = unflat_i3(t, g.n);
+    T su = T(0), sd = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        const int n = (int)g.n[d];
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            // one cell along a periodic dimension: its high wall is its low wall
+            if (side == 1 && g.bc[d] == BC_PERIODIC && n == 1) continue;
+            I3 w = p;
+            w.v[d] = wrap_wall(p.v[d] + side, n, g.bc[d]);
+            const LimWall<T> r = lim_wall<T>(g, d, w, V[d], bup, bdn, Wb[d]);
+            // the cell owns its low wall, and at an open far edge the edge wall
+            if (side == 0 || (g.bc[d] == BC_OPEN && p.v[d] == n - 1)) Vb[d][wi(g, d, w)] = r.vb;
+            if (r.kR == t) {
+                if (r.wu == 2) su += r.upb;
+                if (r.wd == 2) sd += r.dnb;
+            }
+            if (r.kL == t) {
+                if (r.wu == 1) sd += r.upb;
+                if (r.wd == 1) su += r.dnb;
+            }
+        }
+    }
+    bub[t] = su;
+    bdb[t] = sd;
+}
+
+// limiter-coefficient transpose, phase 1 (one thread per cell): the adjoints
+// of the cell's in- and out-flux, of its bounds and of its own value, and
+// which cell attains each bound (slot 0 the cell, 1 + 2d + (s > 0) the face
+// neighbour -e_d / +e_d; bit 3 / 7: the bound is psi^n's value, not x's),
+// stored for phase 2.  F[0..4] = finb, foutb, mxb, mnb, own-value adjoint.
+template <typename T, int ND>
+__global__ void __launch_bounds__(B)
+k_beta_adj_a(Geom g, unsigned opts, const T *__restrict__ psi_n, const T *__restrict__ x,
+             const T *V0, const T *V1, const T *V2, const T *G, const T *__restrict__ bub,
+             const T *__restrict__ bdb, T *__restrict__ F0, T *__restrict__ F1,
+             T *__restrict__ F2, T *__restrict__ F3, T *__restrict__ F4, int *__restrict__ code)
+{
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    const int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= N) return;
+    const T bu_b = bub[t], bd_b = bdb[t];
+    if (bu_b == T(0) && bd_b == T(0)) {
+        F0[t] = F1[t] = F2[t] = F3[t] = F4[t] = T(0);
+        code[t] = 0;
+        return;
+    }
     const bool iga = opts & OPT_IGA;
     const T *V[3] = {V0, V1, V2};
-    T *Vb[3] = {Vb0, Vb1, Vb2};
-    I3 p = unflat_i3(t, g.n);
+    const I3 p = unflat_i3(t, g.n);
     T mx = psi_n[t], mn = mx;
-    int64_t amx = t, amn = t;
-    int smx = 0, smn = 0;
-    T v = x[t];
+    int amx = 0, amn = 0, smx = 0, smn = 0;
+    const T v = x[t];
     if (v > mx) { mx = v; smx = 1; }
     if (v < mn) { mn = v; smn = 1; }
     for (int d = 0; d < ND; d++)
         for (int s = -1; s <= 1; s += 2) {
-            int64_t kq = ci(g, sh1(p, d, s));
-            T a = psi_n[kq], b = x[kq];
-            if (a > mx) { mx = a; amx = kq; smx = 0; }
-            if (a < mn) { mn = a; amn = kq; smn = 0; }
-            if (b > mx) { mx = b; amx = kq; smx = 1; }
-            if (b < mn) { mn = b; amn = kq; smn = 1; }
+            const int64_t kq = ci(g, sh1(p, d, s));
+            const int slot = 1 + 2 * d + (s > 0);
+            const T a = psi_n[kq], b = x[kq];
+            if (a > mx) { mx = a; amx = slot; smx = 0; }
+            if (a < mn) { mn = a; amn = slot; smn = 0; }
+            if (b > mx) { mx = b; amx = slot; smx = 1; }
+            if (b < mn) { mn = b; amn = slot; smn = 1; }
         }
-    T xi = v;
+    const T xi = v;
     T fin = T(0), fout = T(0);
     for (int d = 0; d < ND; d++) {
-        T vlo = V[d][wi(g, d, p)], vhi = V[d][wi(g, d, sh1(p, d, 1))];
-        T wm = iga ? T(1) : x[ci(g, sh1(p, d, -1))];
-        T wp = iga ? T(1) : x[ci(g, sh1(p, d, 1))];
-        T wc = iga ? T(1) : xi;
+        const T vlo = V[d][wi(g, d, p)], vhi = V[d][wi(g, d, sh1(p, d, 1))];
+        const T wm = iga ? T(1) : x[ci(g, sh1(p, d, -1))];
+        const T wp = iga ? T(1) : x[ci(g, sh1(p, d, 1))];
+        const T wc = iga ? T(1) : xi;
         fin += pos(vlo) * wm - neg(vhi) * wp;
         fout += pos(vhi) * wc - neg(vlo) * wc;
     }
-    T Gi = G ? G[t] : T(1);
+    const T Gi = G ? G[t] : T(1);
     T finb = T(0), foutb = T(0), mxb = T(0), mnb = T(0), xib = T(0);
     if (fin > T(0) && bu_b != T(0)) {
         const T r = T(1) / fin, gq = Gi * r * bu_b;
@@ -722,24 +798,366 @@ __global__ void k_beta_adj(Geom g, unsigned opts, const T *__restrict__ psi_n,
         mnb -= gq;
         foutb -= (xi - mn) * r * gq;
     }
-    aadd(smx ? xb : pnb, amx, mxb);
-    aadd(smn ? xb : pnb, amn, mnb);
-    for (int d = 0; d < ND; d++) {
-        int64_t wlo = wi(g, d, p), whi = wi(g, d, sh1(p, d, 1));
-        int64_t km = ci(g, sh1(p, d, -1)), kp = ci(g, sh1(p, d, 1));
-        T vlo = V[d][wlo], vhi = V[d][whi];
-        T wm = iga ? T(1) : x[km];
-        T wp = iga ? T(1) : x[kp];
-        T wc = iga ? T(1) : xi;
-        aadd(Vb[d], wlo, (vlo > T(0) ? wm : T(0)) * finb - (vlo < T(0) ? wc : T(0)) * foutb);
-        aadd(Vb[d], whi, (vhi > T(0) ? wc : T(0)) * foutb - (vhi < T(0) ? wp : T(0)) * finb);
-        if (!iga) {
-            aadd(xb, km, pos(vlo) * finb);
-            aadd(xb, kp, -neg(vhi) * finb);
+    if (!iga)
+        for (int d = 0; d < ND; d++) {
+            const T vlo = V[d][wi(g, d, p)], vhi = V[d][wi(g, d, sh1(p, d, 1))];
             xib += (pos(vhi) - neg(vlo)) * foutb;
         }
+    F0[t] = finb;
+    F1[t] = foutb;
+    F2[t] = mxb;
+    F3[t] = mnb;
+    F4[t] = xib;
+    code[t] = amx | (smx << 3) | (amn << 4) | (smn << 7);
+}
+
+// the cell a bound slot of cell c points at (mapped)
+// (selects: no indexing of c by a run-time dimension)
+__device__ __forceinline__ int64_t slot_cell(const Geom &g, const I3 &c, int64_t kc, int slot)
+{
+    if (slot == 0) return kc;
+    I3 t = c;
+    t.v[0] += slot == 1 ? -1 : (slot == 2 ? 1 : 0);
+    t.v[1] += slot == 3 ? -1 : (slot == 4 ? 1 : 0);
+    t.v[2] += slot == 5 ? -1 : (slot == 6 ? 1 : 0);
+    return ci(g, t);
+}
+
+// limiter-coefficient transpose, phase 2 (one thread per cell q): adds to
+// xb(q) and pnb(q) what the cells whose bounds or fluxes read q send it, and
+// to the velocity adjoint of q's low walls (and an open far edge wall) what
+// the wall's two cells send it, in a fixed order.
+template <typename T, int ND>
+__global__ void __launch_bounds__(B)
+k_beta_adj_b(Geom g, unsigned opts, const T *__restrict__ x, const T *V0, const T *V1,
+             const T *V2, const T *__restrict__ F0, const T *__restrict__ F1,
+             const T *__restrict__ F2, const T *__restrict__ F3, const T *__restrict__ F4,
+             const int *__restrict__ code, T *__restrict__ xb, T *__restrict__ pnb, T *Vb0,
+             T *Vb1, T *Vb2)
+{
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    const int64_t q = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (q >= N) return;
+    const bool iga = opts & OPT_IGA;
+    const T *V[3] = {V0, V1, V2};
+    T *Vb[3] = {Vb0, Vb1, Vb2};
+    const I3 pq = unflat_i3(q, g.n);
+    T ax = F4[q], ap = T(0);
+    // candidates: q itself, then its face neighbours (-e0, +e0, -e1, ...),
+    // each cell once; a neighbour that maps onto q is q itself, already
+    // counted (the checks below test every role of a candidate)
+#pragma unroll
+    for (int k = 0; k < 1 + 2 * ND; k++) {
+        I3 c = pq;
+        int64_t kc = q;
+        if (k > 0) {
+            const int d = (k - 1) >> 1, s = ((k - 1) & 1) ? 1 : -1;
+            // two cells along a periodic dimension: both neighbours are one cell
+            if (s > 0 && g.bc[d] == BC_PERIODIC && g.n[d] == 2) continue;
+            c = sh1(pq, d, s);
+            if (g.bc[d] == BC_OPEN && (c.v[d] < 0 || c.v[d] >= (int)g.n[d])) continue;
+            c.v[d] = wrap_cell(c.v[d], (int)g.n[d], g.bc[d]);
+            kc = ci(g, c);
+            if (kc == q) continue;
+        }
+        const int cd = code[kc];
+        if (slot_cell(g, c, kc, cd & 7) == q) {
+            if (cd & 8) ax += F2[kc];
+            else ap += F2[kc];
+        }
+        if (slot_cell(g, c, kc, (cd >> 4) & 7) == q) {
+            if (cd & 128) ax += F3[kc];
+            else ap += F3[kc];
+        }
+        if (!iga) {
+            const T finb = F0[kc];
+#pragma unroll
+            for (int d = 0; d < ND; d++) {
+                // q is c's -e_d neighbour: c's in-flux through its low wall
+                if (ci(g, sh1(c, d, -1)) == q) ax += pos(V[d][wi(g, d, c)]) * finb;
+                // q is c's +e_d neighbour: through its high wall
+                if (ci(g, sh1(c, d, 1)) == q) ax += -neg(V[d][wi(g, d, sh1(c, d, 1))]) * finb;
+            }
+        }
     }
-    aadd(xb, t, xib);
+    xb[q] += ax;
+    pnb[q] += ap;
+    // velocity adjoint of q's low walls (and an open far edge wall): from the
+    // wall's right cell (whose low wall it is) and its left cell (high wall)
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        const int n = (int)g.n[d];
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            if (side == 1 && !(g.bc[d] == BC_OPEN && pq.v[d] == n - 1)) continue;
+            I3 w = pq;
+            w.v[d] = pq.v[d] + side;                  // the wall, unmapped
+            const int64_t kw = wi(g, d, w);
+            const T vw = V[d][kw];
+            T acc = T(0);
+            // right cell: the wall is its low wall
+            if (w.v[d] < n || g.bc[d] == BC_PERIODIC) {
+                I3 R = w;
+                R.v[d] = wrap_cell(w.v[d], n, g.bc[d]);
+                const int64_t kR = ci(g, R);
+                if (wi(g, d, R) == kw) {
+                    const T wm = iga ? T(1) : x[ci(g, sh1(R, d, -1))];
+                    const T wc = iga ? T(1) : x[kR];
+                    acc += (vw > T(0) ? wm : T(0)) * F0[kR] - (vw < T(0) ? wc : T(0)) * F1[kR];
+                }
+            }
+            // left cell: the wall is its high wall
+            if (w.v[d] > 0 || g.bc[d] == BC_PERIODIC) {
+                I3 L = w;
+                L.v[d] = wrap_cell(w.v[d] - 1, n, g.bc[d]);
+                const int64_t kL = ci(g, L);
+                if (wi(g, d, sh1(L, d, 1)) == kw) {
+                    const T wc = iga ? T(1) : x[kL];
+                    const T wp = iga ? T(1) : x[ci(g, sh1(L, d, 1))];
+                    acc += (vw > T(0) ? wc : T(0)) * F1[kL] - (vw < T(0) ? wp : T(0)) * F0[kL];
+                }
+            }
+            Vb[d][kw] += acc;
+        }
+    }
+}
+
+// 2-D: the limiter transposes (limited velocities, then coefficients) in
+// one launch.  A workgroup owns a tile of LR x LC cells (a thread per cell),
+// their low walls and, along an open dimension, the far edge walls of its
+// last tile.  Phase 1, for the tile and a ring of one cell: what the cell's
+// four walls send its limiter coefficients (the limited-velocity transpose),
+// then what those coefficients send on -- to the cells attaining the
+// bounds, through the in-flux to the face neighbours, and to the cell's
+// walls -- into LDS (the cell's own shares stay in registers).  Phase 2, per
+// tile cell: the cell and wall adjoints gathered in a fixed order, written
+// once.  Periodic extents are at least 3 (as every plan requires), so the
+// face neighbours of a cell are four distinct cells.
+constexpr int LR = 8, LC = 64, LT = LR * LC;
+constexpr int ER = LR + 2, EC = LC + 2, NE = ER * EC;   // tile + ring of one cell
+static_assert(NE - LT <= LT, "the ring takes one more entry per thread at most");
+
+template <typename T, int BC0, int BC1>
+__global__ void __launch_bounds__(LT)
+k_limiter_adj2g(Geom gg, unsigned opts, const T *__restrict__ psi_n, const T *__restrict__ x,
+                const T *__restrict__ V0, const T *__restrict__ V1, const T *__restrict__ bup,
+                const T *__restrict__ bdn, const T *__restrict__ Wb0, const T *__restrict__ Wb1,
+                const T *__restrict__ G, T *__restrict__ Vb0, T *__restrict__ Vb1,
+                T *__restrict__ xb, T *__restrict__ pnb)
+{
+    const Map2<BC0, BC1> g{(int)gg.n[0], (int)gg.n[1]};
+    __shared__ int Ecd[NE];                 // bound codes (as k_beta_adj_a)
+    __shared__ T Emx[NE], Emn[NE];          // bound adjoints
+    __shared__ T Elo[2][NE], Ehi[2][NE];    // in-flux shares to the -e_d / +e_d neighbour
+    __shared__ T Eqh[2][NE];                // share to the high wall of dimension d
+    const int n0 = g.n0, n1 = g.n1;
+    const int tiles_c = (n1 + LC - 1) / LC;
+    const int i0 = (int)(blockIdx.x / tiles_c) * LR, j0 = (int)(blockIdx.x % tiles_c) * LC;
+    const int ilim = min(i0 + LR, n0), jlim = min(j0 + LC, n1);
+    const bool iga = opts & OPT_IGA;
+    const T *V[2] = {V0, V1}, *Wb[2] = {Wb0, Wb1};
+    const int tid = threadIdx.x;
+    // the own cell's shares: its own-value adjoint, to its low walls, and the
+    // limited-velocity adjoint of its low walls and (open) far edge walls
+    T own_x = T(0), own_ql[2] = {T(0), T(0)}, own_qh[2] = {T(0), T(0)};
+    T own_vb[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+#pragma unroll
+    for (int it = 0; it < 2; it++) {
+        const int e = tid + it * LT;
+        if (e >= NE) break;
+        int a, b;   // box position: cell (i0 - 1 + a, j0 - 1 + b)
+        if (e < LT) {
+            a = 1 + e / LC;
+            b = 1 + e % LC;
+        } else {
+            const int k = e - LT;
+            if (k < EC) { a = 0; b = k; }
+            else if (k < 2 * EC) { a = ER - 1; b = k - EC; }
+            else { a = 1 + (k - 2 * EC) / 2; b = ((k - 2 * EC) & 1) ? EC - 1 : 0; }
+        }
+        const int idx = a * EC + b;
+        const I3 c{{i0 - 1 + a, j0 - 1 + b, 0}};
+        bool ok = c.v[0] <= ilim && c.v[1] <= jlim;
+        if (BC0 == BC_OPEN) ok = ok && c.v[0] >= 0 && c.v[0] < n0;
+        if (BC1 == BC_OPEN) ok = ok && c.v[1] >= 0 && c.v[1] < n1;
+        int cd = 0;
+        T fmx = T(0), fmn = T(0), plo[2] = {T(0), T(0)}, phi[2] = {T(0), T(0)};
+        T ql[2] = {T(0), T(0)}, qh[2] = {T(0), T(0)}, xo = T(0);
+        if (ok) {
+            const int kc = g.cell(c);
+            // limited-velocity transpose: what the cell's walls send bub, bdb
+            T su = T(0), sd = T(0), vl[2], vh[2];
+#pragma unroll
+            for (int d = 0; d < 2; d++)
+#pragma unroll
+                for (int side = 0; side < 2; side++) {
+                    const I3 w = sh1(c, d, side);
+                    const int kw = g.wall(d, w), kL = g.cell(sh1(w, d, -1)), kR = g.cell(w);
+                    const T wb = Wb[d][kw], v = V[d][kw];
+                    const T dL = bdn[kL], uR = bup[kR], uL = bup[kL], dR = bdn[kR];
+                    T up = T(1), dn = T(1);
+                    int wu = 0, wd = 0;
+                    if (dL < up) { up = dL; wu = 1; }
+                    if (uR < up) { up = uR; wu = 2; }
+                    if (uL < dn) { dn = uL; wd = 1; }
+                    if (dR < dn) { dn = dR; wd = 2; }
+                    const T vb = ((v > T(0) ? up : T(0)) + (v < T(0) ? dn : T(0))) * wb;
+                    const T upb = pos(v) * wb, dnb = neg(v) * wb;
+                    if (wb == T(0)) wu = wd = 0;
+                    if (kR == kc) {
+                        if (wu == 2) su += upb;
+                        if (wd == 2) sd += dnb;
+                    }
+                    if (kL == kc) {
+                        if (wu == 1) sd += upb;
+                        if (wd == 1) su += dnb;
+                    }
+                    if (side == 0) {
+                        vl[d] = v;
+                        if (e < LT) own_vb[d][0] = vb;
+                    } else {
+                        vh[d] = v;
+                        if (e < LT) own_vb[d][1] = vb;
+                    }
+                }
+            // coefficient transpose (as k_beta_adj_a)
+            if (su != T(0) || sd != T(0)) {
+                T mx = psi_n[kc], mn = mx;
+                int amx = 0, amn = 0, smx = 0, smn = 0;
+                const T xi = x[kc];
+                if (xi > mx) { mx = xi; smx = 1; }
+                if (xi < mn) { mn = xi; smn = 1; }
+                T xm[2], xp[2];
+#pragma unroll
+                for (int d = 0; d < 2; d++)
+#pragma unroll
+                    for (int sg = 0; sg < 2; sg++) {
+                        const int kq = g.cell(sh1(c, d, sg ? 1 : -1));
+                        const int slot = 1 + 2 * d + sg;
+                        const T pa = psi_n[kq], pb = x[kq];
+                        if (sg) xp[d] = pb; else xm[d] = pb;
+                        if (pa > mx) { mx = pa; amx = slot; smx = 0; }
+                        if (pa < mn) { mn = pa; amn = slot; smn = 0; }
+                        if (pb > mx) { mx = pb; amx = slot; smx = 1; }
+                        if (pb < mn) { mn = pb; amn = slot; smn = 1; }
+                    }
+                T fin = T(0), fout = T(0);
+#pragma unroll
+                for (int d = 0; d < 2; d++) {
+                    const T wm = iga ? T(1) : xm[d], wp = iga ? T(1) : xp[d];
+                    const T wc = iga ? T(1) : xi;
+                    fin += pos(vl[d]) * wm - neg(vh[d]) * wp;
+                    fout += pos(vh[d]) * wc - neg(vl[d]) * wc;
+                }
+                const T Gi = G ? G[kc] : T(1);
+                T finb = T(0), foutb = T(0);
+                if (fin > T(0) && su != T(0)) {
+                    const T r = T(1) / fin, gq = Gi * r * su;
+                    fmx += gq;
+                    xo -= gq;
+                    finb -= (mx - xi) * r * gq;
+                }
+                if (fout > T(0) && sd != T(0)) {
+                    const T r = T(1) / fout, gq = Gi * r * sd;
+                    xo += gq;
+                    fmn -= gq;
+                    foutb -= (xi - mn) * r * gq;
+                }
+#pragma unroll
+                for (int d = 0; d < 2; d++) {
+                    const T wm = iga ? T(1) : xm[d], wp = iga ? T(1) : xp[d];
+                    const T wc = iga ? T(1) : xi;
+                    ql[d] = (vl[d] > T(0) ? wm : T(0)) * finb - (vl[d] < T(0) ? wc : T(0)) * foutb;
+                    qh[d] = (vh[d] > T(0) ? wc : T(0)) * foutb - (vh[d] < T(0) ? wp : T(0)) * finb;
+                    if (!iga) {
+                        plo[d] = pos(vl[d]) * finb;
+                        phi[d] = -neg(vh[d]) * finb;
+                        xo += (pos(vh[d]) - neg(vl[d])) * foutb;
+                    }
+                }
+                cd = amx | (smx << 3) | (amn << 4) | (smn << 7);
+            }
+        }
+        Ecd[idx] = cd;
+        Emx[idx] = fmx;
+        Emn[idx] = fmn;
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            Elo[d][idx] = plo[d];
+            Ehi[d][idx] = phi[d];
+            Eqh[d][idx] = qh[d];
+        }
+        if (e < LT) {
+            own_x = xo;
+#pragma unroll
+            for (int d = 0; d < 2; d++) {
+                own_ql[d] = ql[d];
+                own_qh[d] = qh[d];
+            }
+        }
+    }
+    __syncthreads();
+    const int a = 1 + tid / LC, b = 1 + tid % LC;
+    const I3 q{{i0 - 1 + a, j0 - 1 + b, 0}};
+    if (q.v[0] >= n0 || q.v[1] >= n1) return;
+    const int kq = g.cell(q);
+    const int iq = a * EC + b;
+    const int nn[2] = {n0, n1};
+    const bool op[2] = {BC0 == BC_OPEN, BC1 == BC_OPEN};
+    T ax = own_x, ap = T(0);
+    // bounds: the cell itself, then its face neighbours (-e0, +e0, -e1, +e1)
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        I3 c = q;
+        int ic = iq;
+        if (k > 0) {
+            const int d = (k - 1) >> 1, sg = ((k - 1) & 1) ? 1 : -1;
+            c = sh1(q, d, sg);
+            if (op[d] && (c.v[d] < 0 || c.v[d] >= nn[d])) continue;
+            ic = iq + (d == 0 ? sg * EC : sg);
+        }
+        const int cd = Ecd[ic];
+        const int smx = cd & 7, smn = (cd >> 4) & 7;
+        // the cell a bound slot of c points at (selects: no indexing of c by a
+        // run-time dimension)
+        auto target = [&](int slot) {
+            const int ti = c.v[0] + (slot == 1 ? -1 : (slot == 2 ? 1 : 0));
+            const int tj = c.v[1] + (slot == 3 ? -1 : (slot == 4 ? 1 : 0));
+            return g.cell(I3{{ti, tj, 0}});
+        };
+        if (target(smx) == kq) {
+            if (cd & 8) ax += Emx[ic];
+            else ap += Emx[ic];
+        }
+        if (target(smn) == kq) {
+            if (cd & 128) ax += Emn[ic];
+            else ap += Emn[ic];
+        }
+    }
+    // in-flux: the +e_d neighbour's share to its -e_d side, the -e_d
+    // neighbour's to its +e_d side; at an open edge the cell's own share
+    // beyond the edge comes back to it
+#pragma unroll
+    for (int d = 0; d < 2; d++) {
+        const int st = d == 0 ? EC : 1;
+        if (!op[d] || q.v[d] < nn[d] - 1) ax += Elo[d][iq + st];
+        if (!op[d] || q.v[d] > 0) ax += Ehi[d][iq - st];
+        if (op[d] && q.v[d] == 0) ax += Elo[d][iq];
+        if (op[d] && q.v[d] == nn[d] - 1) ax += Ehi[d][iq];
+    }
+    xb[kq] += ax;
+    pnb[kq] += ap;
+    // velocity adjoints of the owned walls: the limited-velocity share, the
+    // cell's share to its low wall and the -e_d neighbour's to its high wall
+    T *Vb[2] = {Vb0, Vb1};
+#pragma unroll
+    for (int d = 0; d < 2; d++) {
+        const int st = d == 0 ? EC : 1;
+        T v = own_vb[d][0] + own_ql[d];
+        if (!op[d] || q.v[d] > 0) v += Eqh[d][iq - st];
+        Vb[d][g.wall(d, q)] = v;
+        if (op[d] && q.v[d] == nn[d] - 1) Vb[d][g.wall(d, sh1(q, d, 1))] = own_vb[d][1] + own_qh[d];
+    }
 }
 
 // Run f with the dimension count (and a wall dimension) as compile-time
@@ -836,9 +1254,9 @@ void pseudo_adj2_launch(const Geom &g, hipStream_t s, unsigned opts, const T *x,
                         const T *c1, const T *G, const T *Vb0, const T *Vb1, T *xb, T *cb0,
                         T *cb1)
 {
-    const unsigned tb = (unsigned)(cdiv(g.n[0] + 1, TPR) * cdiv(g.n[1] + 1, TPC));
+    const unsigned tb = (unsigned)(cdiv(g.n[0], GR) * cdiv(g.n[1], GC));
 #define MP_K(B0, B1) \
-    k_pseudo_adj2<T, B0, B1><<<tb, TPR * TPC, 0, s>>>(g, opts, x, c0, c1, G, Vb0, Vb1, xb, cb0, cb1)
+    k_pseudo_adj2g<T, B0, B1><<<tb, GT, 0, s>>>(g, opts, x, c0, c1, G, Vb0, Vb1, xb, cb0, cb1)
     const bool p0 = g.bc[0] == BC_PERIODIC, p1 = g.bc[1] == BC_PERIODIC;
     if (p0 && p1) MP_K(BC_PERIODIC, BC_PERIODIC);
     else if (p0) MP_K(BC_PERIODIC, BC_OPEN);
@@ -847,19 +1265,44 @@ void pseudo_adj2_launch(const Geom &g, hipStream_t s, unsigned opts, const T *x,
 #undef MP_K
 }
 
-template <typename T>
-void beta_adj_dispatch(const Geom &g, unsigned blocks, hipStream_t s, unsigned opts,
-                       const T *psi_n, const T *x, const T *V0, const T *V1, const T *V2,
-                       const T *G, const T *bub, const T *bdb, T *xb, T *pnb, T *Vb0, T *Vb1,
-                       T *Vb2)
+// true if the 2-D one-launch limiter transpose applies
+bool limiter_adj_tiled(const Geom &g)
 {
-#define MP_B(ND) \
-    k_beta_adj<T, ND><<<blocks, B, 0, s>>>(g, opts, psi_n, x, V0, V1, V2, G, bub, bdb, xb, pnb, \
-                                          Vb0, Vb1, Vb2)
-    if (g.nd == 1) MP_B(1);
-    else if (g.nd == 2) MP_B(2);
-    else MP_B(3);
-#undef MP_B
+    return g.nd == 2 && (g.n[0] + 1) * (g.n[1] + 1) < ((int64_t)1 << 31);
+}
+
+// transposes of the limiter (limited velocities, then coefficients), each
+// entry gathered by one thread in a fixed order (bub, bdb, F, code: the
+// three-kernel path's intermediates, unused by the 2-D one-launch kernel)
+template <typename T>
+void limiter_adj(const Geom &g, unsigned opts, hipStream_t s, const T *psi_n, const T *x,
+                 const T *const V[3], const T *bup, const T *bdn, const T *const Wb[3],
+                 const T *G, T *bub, T *bdb, T *const F[5], int *code, T *xb, T *pnb,
+                 T *const Vb[3])
+{
+    if (limiter_adj_tiled(g)) {
+        const unsigned tb = (unsigned)(cdiv(g.n[0], LR) * cdiv(g.n[1], LC));
+#define MP_L(B0, B1)                                                                          \
+    k_limiter_adj2g<T, B0, B1><<<tb, LT, 0, s>>>(g, opts, psi_n, x, V[0], V[1], bup, bdn, Wb[0], \
+                                                 Wb[1], G, Vb[0], Vb[1], xb, pnb)
+        const bool p0 = g.bc[0] == BC_PERIODIC, p1 = g.bc[1] == BC_PERIODIC;
+        if (p0 && p1) MP_L(BC_PERIODIC, BC_PERIODIC);
+        else if (p0) MP_L(BC_PERIODIC, BC_OPEN);
+        else if (p1) MP_L(BC_OPEN, BC_PERIODIC);
+        else MP_L(BC_OPEN, BC_OPEN);
+#undef MP_L
+        return;
+    }
+    const unsigned cb = (unsigned)cdiv(g.n[0] * g.n[1] * g.n[2], B);
+    with_nd(g.nd, [&](auto ND) {
+        constexpr int nd = decltype(ND)::value;
+        k_limit_adj_gather<T, nd><<<cb, B, 0, s>>>(g, V[0], V[1], V[2], bup, bdn, Wb[0], Wb[1],
+                                                   Wb[2], Vb[0], Vb[1], Vb[2], bub, bdb);
+        k_beta_adj_a<T, nd><<<cb, B, 0, s>>>(g, opts, psi_n, x, V[0], V[1], V[2], G, bub, bdb,
+                                             F[0], F[1], F[2], F[3], F[4], code);
+        k_beta_adj_b<T, nd><<<cb, B, 0, s>>>(g, opts, x, V[0], V[1], V[2], F[0], F[1], F[2],
+                                             F[3], F[4], code, xb, pnb, Vb[0], Vb[1], Vb[2]);
+    });
 }
 
 int64_t ncells(const Geom &g) { return g.n[0] * g.n[1] * g.n[2]; }
@@ -885,6 +1328,8 @@ template <typename T> struct AdjWs {
     T *W[8][3];     // limited pseudo-velocities (== V without the limiter)
     T *bu[8], *bd[8];
     T *yb, *xb, *pnb, *bub, *bdb;
+    T *F[5];        // limiter-coefficient transpose, per cell (k_beta_adj_a)
+    int *code;      // which cells attain the bounds (k_beta_adj_a)
     T *Ab[3], *Vb[3], *Cb[3];
     T *tmp;         // output of a recomputed step
     size_t bytes;
@@ -949,6 +1394,11 @@ AdjWs<T> carve_adj(const Geom &g, int n_iters, bool fct, int n_steps, int ckpt, 
     w.pnb = take(N);
     w.bub = take(N);
     w.bdb = take(N);
+    const bool staged_lim = fct && !limiter_adj_tiled(g);
+    for (int k = 0; k < 5; k++) w.F[k] = staged_lim ? take(N) : nullptr;
+    // N ints, in whole T
+    w.code = staged_lim ? (int *)take((size_t)(N * sizeof(int) + sizeof(T) - 1) / sizeof(T))
+                        : nullptr;
     w.tmp = take(N);
     for (int d = 0; d < 3; d++) w.Ab[d] = w.Vb[d] = w.Cb[d] = nullptr;
     for (int d = 0; d < g.nd; d++) {
@@ -1068,40 +1518,22 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
         if (!fast) {
             Bufs<T> f;
             f.push(w.xb, N);
-            if (fct) {
-                f.push(w.bub, N);
-                f.push(w.bdb, N);
-            }
             clear_n<T>(f, s);
         }
         // corrective donor-cell pass
         {
             const T *Wc[3] = {w.W[it - 1][0], w.W[it - 1][1], w.W[it - 1][2]};
             const int mode = fast ? (1 | (it == n ? 2 : 0)) : 0;
-            T *const zero[3] = {it == n ? w.pnb : nullptr, fct ? w.bub : nullptr,
-                                fct ? w.bdb : nullptr};
+            T *const zero[3] = {it == n ? w.pnb : nullptr, nullptr, nullptr};
             donor_adj<T>(g, x, Wc, a.G, iga ? 1 : 0, w.yb, w.xb, w.Ab, s, mode, nullptr,
                          fast ? zero : nullptr);
         }
         // limiter
         if (fct) {
-            if (g.nd == 2 && g.n[0] < 65535) {     // one grid row per cell row
-                const dim3 grid((unsigned)cdiv(g.n[1] + 1, B), (unsigned)(g.n[0] + 1));
-                k_limit_adj2<T><<<grid, B, 0, s>>>(g, w.V[it - 1][0], w.V[it - 1][1],
-                                                   w.bu[it - 1], w.bd[it - 1], w.Ab[0], w.Ab[1],
-                                                   w.Vb[0], w.Vb[1], w.bub, w.bdb);
-            } else {
-                for (int d = 0; d < g.nd; d++)
-                    with_nd_d(g.nd, d, [&](auto ND, auto WD) {
-                        k_limit_adj<T, decltype(ND)::value, decltype(WD)::value>
-                            <<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(
-                                g, w.V[it - 1][d], w.bu[it - 1], w.bd[it - 1], w.Ab[d],
-                                w.Vb[d], w.bub, w.bdb);
-                    });
-            }
-            beta_adj_dispatch<T>(g, cb, s, a.opts, psi_n, x, w.V[it - 1][0], w.V[it - 1][1],
-                                 w.V[it - 1][2], a.G, w.bub, w.bdb, w.xb, w.pnb, w.Vb[0],
-                                 w.Vb[1], w.Vb[2]);
+            const T *V[3] = {w.V[it - 1][0], w.V[it - 1][1], w.V[it - 1][2]};
+            const T *Wb[3] = {w.Ab[0], w.Ab[1], w.Ab[2]};
+            limiter_adj<T>(g, a.opts, s, psi_n, x, V, w.bu[it - 1], w.bd[it - 1], Wb, a.G,
+                           w.bub, w.bdb, w.F, w.code, w.xb, w.pnb, w.Vb);
         } else {
             for (int d = 0; d < g.nd; d++)
                 k_copy<T><<<(unsigned)cdiv(nwalls(g, d), B), B, 0, s>>>(w.Vb[d], w.Ab[d],

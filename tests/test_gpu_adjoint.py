@@ -107,6 +107,65 @@ def test_adjoint_without_g_vs_oracle(shape, bc, n_iters, opts, dtype):
             assert not bool(a.select(d, -1).any())
 
 
+TINY = [((1, 5), 1), ((2, 3), 1), ((5, 1), 1), ((1,), 1), ((2,), 1), ((2, 1, 3), 1),
+        ((3, 3), 0), ((3, 4, 3), 0), ((3,), 0)]
+
+
+@pytest.mark.parametrize("n_iters,opts", [(2, FCT), (3, FCT), (2, IGA | FCT)])
+@pytest.mark.parametrize("shape,bc", TINY)
+def test_adjoint_tiny_grids_vs_oracle(shape, bc, n_iters, opts):
+    """Grids one to three cells wide (open: from one cell; periodic: the
+    smallest extent a plan accepts), where the boundary map sends several
+    stencil positions of a wall or cell onto one cell and the gathering
+    transposes must count each of them once."""
+    gen = synth.rng(5)
+    c = synth.random_advector(shape, 0.4, gen)
+    if bc == 0:
+        c = synth.periodic_fix(c)
+    m = max(min(shape), 2)
+    psi = synth.blob_field(shape, 4, (m / 6, m / 3), "normal" if opts & IGA else "uniform", gen,
+                           periodic=(bc == 0)) + (0.0 if opts & IGA else 0.05)
+    lam = gen.normal(size=shape)
+    n_steps, ck = 5, 2
+    ref_psi, ref_c = oracle.adjoint(psi, c, lam, n_iters=n_iters, opts=opts, bc=bc,
+                                    n_steps=n_steps, ckpt_every=ck)
+    plan = mpdata.Plan(shape, n_iters=n_iters, opts=opts, bc=bc, adj_steps=n_steps,
+                       ckpt_every=ck)
+    gp, gc = plan.adv_adj(dev(psi, torch.float64), [dev(x, torch.float64) for x in c],
+                          dev(lam, torch.float64), n_steps=n_steps, ckpt_every=ck)
+    assert rel_l2(gp.cpu().numpy(), ref_psi) <= 1e-10
+    for a, b in zip(gc, ref_c):
+        assert rel_l2(a.cpu().numpy(), b) <= 1e-10
+
+
+@pytest.mark.parametrize("bc,opts,with_g", [(0, FCT, False), (1, FCT, True), (0, IGA | FCT, True),
+                                            (1, 0, False)])
+def test_adjoint_bitwise_repeatable(bc, opts, with_g):
+    """2-D without third-order terms every transpose gathers in a fixed
+    order: two calls on the same inputs give the same bits (with atomic
+    scatters the order of the additions, hence their rounding, would change
+    from call to call)."""
+    shape = (200, 150)
+    gen, psi, c, g = _setup(shape, bc, opts, seed=17 + bc, with_g=with_g)
+    lam = gen.normal(size=shape)
+    plan = mpdata.Plan(shape, n_iters=2, opts=opts, bc=bc, has_g=with_g, adj_steps=8,
+                       ckpt_every=4)
+    args = (dev(psi, torch.float64), [dev(x, torch.float64) for x in c],
+            dev(lam, torch.float64))
+    gd = dev(g, torch.float64) if with_g else None
+    gp1, gc1 = plan.adv_adj(*args, g=gd, n_steps=8, ckpt_every=4)
+    gp2, gc2 = plan.adv_adj(*args, g=gd, n_steps=8, ckpt_every=4)
+    torch.cuda.synchronize()
+    assert torch.equal(gp1, gp2)
+    for a, b in zip(gc1, gc2):
+        assert torch.equal(a, b)
+    ref_psi, ref_c = oracle.adjoint(psi, c, lam, g=g, n_iters=2, opts=opts, bc=bc, n_steps=8,
+                                    ckpt_every=4)
+    assert rel_l2(gp1.cpu().numpy(), ref_psi) <= 1e-10
+    for a, b in zip(gc1, ref_c):
+        assert rel_l2(a.cpu().numpy(), b) <= 1e-10
+
+
 @pytest.mark.parametrize("n_iters,opts", [(2, FCT), (3, FCT), (2, FCT | mpdata.OPT_KAHAN)])
 def test_adjoint_fused_state_sweeps_vs_oracle(n_iters, opts):
     """Periodic, no G, FCT: the checkpointing and segment sweeps run the fused
