@@ -86,9 +86,12 @@ enum { MPDATA_F32 = 0, MPDATA_F64 = 1 };
 
 /* kernel selection for mpdata_set_kernel */
 enum {
-    MPDATA_KERNEL_AUTO = 0,    /* fused kernel where one exists, else staged */
+    MPDATA_KERNEL_AUTO = 0,    /* fused kernel where one exists, else the 2-D
+                                  single-pass kernel, else staged           */
     MPDATA_KERNEL_STAGED = 1,  /* one launch per stage (cross-check path)    */
-    MPDATA_KERNEL_FUSED = 2    /* all passes of a step in one launch         */
+    MPDATA_KERNEL_FUSED = 2,   /* all passes of a step in one launch         */
+    MPDATA_KERNEL_PASS = 3     /* 2-D: one launch per corrective pass (the
+                                  kernel the adjoint records with)          */
 };
 
 typedef struct mpdata_desc {
@@ -124,7 +127,9 @@ int mpdata_init(const mpdata_desc *desc, void *workspace, size_t ws_bytes,
 int mpdata_set_stream(mpdata_plan *plan, void *hip_stream);
 
 /* Choose the step kernel (MPDATA_KERNEL_*).  FUSED returns
- * MPDATA_EUNSUPPORTED when no fused kernel covers the plan. */
+ * MPDATA_EUNSUPPORTED when no fused kernel covers the plan, PASS when the
+ * plan is not 2-D with n_iters >= 2.  FUSED and PASS give the same bits
+ * where both apply (2-D periodic, G = 1, no tot / iga / dfl). */
 int mpdata_set_kernel(mpdata_plan *plan, int kernel);
 
 /* Rows per wavefront chunk of the fused 2-D kernel and of the 2-D

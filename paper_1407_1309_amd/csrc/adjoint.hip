@@ -1432,7 +1432,8 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
     hipError_t e;
     const int km = (a.opts & OPT_KAHAN) ? 2 : 0;   // Kahan-compensated donor update
     T *first = n > 1 ? w.X[1] : out;
-    if (!a.G && pass2d_supported(g.nd, n > 1 ? n : 2, a.opts, 0, g.n)) {
+    // (the separate 2-D donor launch of n_iters = 1 takes G = 1 only)
+    if (pass2d_supported(g.nd, n > 1 ? n : 2, a.opts, a.G != nullptr, g.n) && (n > 1 || !a.G)) {
         // 2-D: one launch per corrective pass that also writes the records
         // (raw and limited velocities, coefficients); the first folds the
         // donor pass in and keeps its result as the pass input record
@@ -1454,7 +1455,7 @@ hipError_t record_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, T *out,
             }
             if (donor) rec.xd = w.X[1];
             T *y = (it < n) ? w.X[it] : out;
-            e = pass2d_launch<T>(g, a.opts, x, c0, c1, donor ? nullptr : psi_n, y,
+            e = pass2d_launch<T>(g, a.opts, x, c0, c1, donor ? nullptr : psi_n, a.G, y,
                                  w.W[it - 1][0], w.W[it - 1][1], s, rec);
             if (e != hipSuccess) return e;
         }

@@ -256,7 +256,8 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
             T *w0 = last ? nullptr : (T *)p->L.faces[set][0];
             T *w1 = last ? nullptr : (T *)p->L.faces[set][1];
             e = mp::pass2d_launch<T>(p->g, p->desc.opts, x, c[0], c[1], it == 2 ? nullptr : psi_n,
-                                     y, w0, w1, p->stream, mp::PassRecord<T>(), p->tile_rows);
+                                     G, y, w0, w1, p->stream, mp::PassRecord<T>(),
+                                     p->tile_rows);
             c[0] = w0;
             c[1] = w1;
             set ^= 1;
@@ -308,7 +309,8 @@ bool resident_available(const mpdata_plan *p)
 
 bool use_fused(const mpdata_plan *p)
 {
-    return p->kernel != MPDATA_KERNEL_STAGED && fused_available(p);
+    return (p->kernel == MPDATA_KERNEL_AUTO || p->kernel == MPDATA_KERNEL_FUSED) &&
+           fused_available(p);
 }
 
 bool use_pass2d(const mpdata_plan *p)
@@ -497,10 +499,14 @@ int mpdata_init(const mpdata_desc *desc, void *workspace, size_t ws_bytes, void 
 int mpdata_set_kernel(mpdata_plan *plan, int kernel)
 {
     if (!plan) return fail(MPDATA_EINVAL, "plan is NULL");
-    if (kernel < MPDATA_KERNEL_AUTO || kernel > MPDATA_KERNEL_FUSED)
+    if (kernel < MPDATA_KERNEL_AUTO || kernel > MPDATA_KERNEL_PASS)
         return fail(MPDATA_EINVAL, "unknown kernel %d", kernel);
     if (kernel == MPDATA_KERNEL_FUSED && !fused_available(plan) && !resident_available(plan))
         return fail(MPDATA_EUNSUPPORTED, "no fused kernel for this plan");
+    if (kernel == MPDATA_KERNEL_PASS &&
+        !mp::pass2d_supported(plan->desc.n_dims, plan->desc.n_iters, plan->desc.opts,
+                              plan->desc.has_g, plan->g.n))
+        return fail(MPDATA_EUNSUPPORTED, "no single-pass kernel for this plan");
     plan->kernel = kernel;
     return MPDATA_OK;
 }

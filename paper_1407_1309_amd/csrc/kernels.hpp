@@ -88,9 +88,10 @@ hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_
                         hipStream_t s);
 
 // ---- one corrective pass of a 2-D step in one launch (pass2d.hip) --------
-// G = 1, no third-order terms, any boundaries; x: previous pass's result,
-// c0/c1: previous pass's advector, y (distinct from x and psi_n): result;
-// w0/w1 (both or neither): limited velocities for a following pass
+// no third-order terms, any boundaries; x: previous pass's result, c0/c1:
+// previous pass's advector, G: NULL for G = 1, y (distinct from x and
+// psi_n): result; w0/w1 (both or neither): limited velocities for a
+// following pass
 // Optional records of a pass for the adjoint (written with w0 / w1): raw
 // pseudo-velocities at the same walls, limiter coefficients of the cells.
 template <typename T> struct PassRecord {
@@ -104,7 +105,7 @@ bool pass2d_supported(int nd, int n_iters, unsigned opts, int has_g, const int64
 // rows per wavefront chunk (0 = built-in default)
 template <typename T>
 hipError_t pass2d_launch(const Geom &g, unsigned opts, const T *x, const T *c0, const T *c1,
-                         const T *psi_n, T *y, T *w0, T *w1, hipStream_t s,
+                         const T *psi_n, const T *G, T *y, T *w0, T *w1, hipStream_t s,
                          const PassRecord<T> &rec = PassRecord<T>(), int tile_rows = 0);
 // donor-cell pass of a 2-D grid, G = 1 (Kahan per opts); copy (optional)
 // receives x unchanged

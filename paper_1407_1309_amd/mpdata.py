@@ -24,7 +24,7 @@ OK, EINVAL, EWORKSPACE, EHIP, ENONFINITE, ECANCELLED, EUNSUPPORTED = 0, -1, -2, 
 OPT_FCT, OPT_IGA, OPT_TOT, OPT_ABS, OPT_DFL, OPT_KAHAN = 1, 2, 4, 8, 16, 32
 BC_PERIODIC, BC_OPEN = 0, 1
 F32, F64 = 0, 1
-KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2
+KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED, KERNEL_PASS = 0, 1, 2, 3
 
 EXPORTS = [
     "mpdata_workspace_bytes", "mpdata_init", "mpdata_set_stream", "mpdata_set_kernel",

@@ -66,7 +66,8 @@ def test_step_diag_safe_mode_redo():
 
 
 PATHS = [((64, 70), 1, 2, FCT, False, mpdata.KERNEL_AUTO),        # 2-D single pass
-         ((64, 70), 0, 3, FCT | TOT, True, mpdata.KERNEL_AUTO),    # staged (G, tot)
+         ((64, 70), 0, 3, FCT | TOT, True, mpdata.KERNEL_AUTO),    # single pass (G, tot)
+         ((64, 70), 0, 3, FCT | TOT, True, mpdata.KERNEL_STAGED),  # stage by stage
          ((64, 70), 0, 3, FCT, False, mpdata.KERNEL_STAGED),
          ((12, 14, 70), 1, 2, TOT | IGA, True, mpdata.KERNEL_AUTO),  # 3-D one launch
          ((300,), 0, 2, FCT, False, mpdata.KERNEL_AUTO)]             # 1-D resident
