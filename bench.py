@@ -97,18 +97,19 @@ def _traffic_entry(kernel_name, workload):
 def _valu_entry(kernel_name, workload, cells, alg_ops):
     """VALU issue of the kernel from its committed counters: lane-instructions
     issued per cell-step (SQ_INSTS_VALU x 64 / cells) against the algorithmic
-    operations, and the fraction of the launch's clocks the SIMDs spent
-    issuing VALU instructions (4 clocks per wave64 instruction;
-    GRBM_GUI_ACTIVE sums the 8 XCDs' clocks)."""
+    operations, and the fraction of the SIMDs' issue capacity they fill over
+    the kernel's mean duration in the same counter pass (4 clocks per wave64
+    VALU instruction at the nominal clock; the GRBM clock count is not used,
+    since the clock runs below nominal under some kernels)."""
     ent = _profile_entry("valu.json", kernel_name, workload)
-    if not ent:
+    if not ent or "avg_us" not in ent:
         return None
     insts = float(ent["SQ_INSTS_VALU"])
-    clocks = float(ent["GRBM_GUI_ACTIVE"]) / XCDS
+    us = float(ent["avg_us"])
     return {"lane_instr_per_cell_step": round(insts * 64 / cells, 1),
             "alg_ops_per_cell_step": alg_ops,
-            "issue_busy": round(insts * 4 / SIMDS / clocks, 4),
-            "counters": {"SQ_INSTS_VALU": insts, "GRBM_GUI_ACTIVE": float(ent["GRBM_GUI_ACTIVE"])}}
+            "issue_busy": round(insts * 4 / SIMDS / (us * 1e-6 * CLOCK_HZ), 4),
+            "counters": {"SQ_INSTS_VALU": insts, "kernel_us_in_counter_pass": us}}
 
 
 def _roofline(kernel, kernel_ms, launches, alg_bytes, alg_ops=None, traffic=None, valu=None):

@@ -231,11 +231,14 @@ def test_adjoint_workload_point_checks_vs_fd(kernel):
     different one-sided slopes and a central difference averages them).
     Where the limiter's coefficient is near its singular point (in/out-flux
     sum close to 0) J is smooth but very strongly curved, so a point whose
-    extrapolated difference quotients do not converge is not used; at
-    least 12 of the 24 points must converge (measured: 14 with the
-    stage-by-stage plan, 18 with the benchmark's plan, whose state sweeps
-    run the fused kernel).  Both plans are checked: the benchmark times the
-    automatic choice with autotuned chunks."""
+    extrapolated difference quotients do not converge is not used.  Every
+    kernel here is deterministic, so the count of converged points is a
+    fixed property of the plan: 18 of the 24 with the benchmark's plan
+    (fused forward kernel; the adjoint's recording launches give its bits),
+    14 with the stage-by-stage plan; both are required (a change that
+    breaks the agreement of adjoint and forward shows as fewer).  Both plans
+    are checked: the benchmark times the automatic choice with autotuned
+    chunks."""
     n_steps, ck = 200, 20
     plan, psi, c, obs, gp, gc = _workload(1024, n_steps, ck, kernel)
     gen = np.random.default_rng(11)
@@ -280,7 +283,7 @@ def test_adjoint_workload_point_checks_vs_fd(kernel):
         assert abs(fd - ad) <= 1e-6 * abs(ad), (what, idx, ad, fd)
         n_ok += 1
     print(f"FD points converged: {n_ok} of {len(checks)}", flush=True)
-    assert n_ok >= 12, n_ok
+    assert n_ok >= (18 if kernel == mpdata.KERNEL_AUTO else 14), n_ok
 
 
 def test_adjoint_directions_vs_fd():
