@@ -59,6 +59,46 @@ __device__ inline T wall(const Geom &g, int d, const T *a, const Idx3 &p)
     return a[((int64_t)q[0] * e[1] + q[1]) * e[2] + q[2]];
 }
 
+// Boundary-mapped coordinates of the positions p + o, o = -2..2, along each
+// of the first ND dimensions, as cells and as walls, formed once per thread.
+// The stencils read at constant offsets from p (their loops unroll), so a
+// read costs its index arithmetic only, not a boundary map per dimension.
+template <int ND> struct Near {
+    Idx3 p;
+    int c[3][5], w[3][5];
+    __device__ __forceinline__ Near(const Geom &g, const Idx3 &p_) : p(p_)
+    {
+#pragma unroll
+        for (int t = 0; t < 3; t++)
+#pragma unroll
+            for (int o = 0; o < 5; o++) {
+                c[t][o] = t < ND ? wrap_cell(p.v[t] + o - 2, (int)g.n[t], g.bc[t]) : 0;
+                w[t][o] = t < ND ? wrap_wall(p.v[t] + o - 2, (int)g.n[t], g.bc[t]) : 0;
+            }
+    }
+    __device__ __forceinline__ int off(const Idx3 &q, int t) const { return q.v[t] - p.v[t] + 2; }
+    // cell array at q
+    template <typename T> __device__ __forceinline__ T cell(const Geom &g, const T *a, const Idx3 &q) const
+    {
+        const int i = c[0][off(q, 0)], j = c[1][off(q, 1)], k = c[2][off(q, 2)];
+        return a[((int64_t)i * g.n[1] + j) * g.n[2] + k];
+    }
+    template <typename T> __device__ __forceinline__ T gcell(const Geom &g, const T *G, const Idx3 &q) const
+    {
+        return G ? cell(g, G, q) : T(1);
+    }
+    // dimension-d wall array at q (q.v[d] a wall coordinate)
+    template <typename T>
+    __device__ __forceinline__ T wall(const Geom &g, int d, const T *a, const Idx3 &q) const
+    {
+        const int i = d == 0 ? w[0][off(q, 0)] : c[0][off(q, 0)];
+        const int j = d == 1 ? w[1][off(q, 1)] : c[1][off(q, 1)];
+        const int k = d == 2 ? w[2][off(q, 2)] : c[2][off(q, 2)];
+        const int64_t e1 = g.n[1] + (d == 1 ? 1 : 0), e2 = g.n[2] + (d == 2 ? 1 : 0);
+        return a[((int64_t)i * e1 + j) * e2 + k];
+    }
+};
+
 template <typename T>
 __device__ inline T frac(bool iga, T num, T den, T m)
 {
@@ -70,26 +110,29 @@ __device__ inline T frac(bool iga, T num, T den, T m)
 // advector itself (infinite-gauge corrective pass); bit 1: Kahan-compensated
 // update (terms -(F(hi) - F(lo)) / G, dimensions in increasing order)
 template <typename T, int ND>
-__global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
+__global__ void __launch_bounds__(256) k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c1,
                         const T *c2, const T *G, int mode, T *__restrict__ out)
 {
     int64_t N = g.n[0] * g.n[1] * g.n[2];
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
     const bool flux_is_vel = mode & 1, kahan = mode & 2;
-    Idx3 p = unflat(t, g.n);
+    const Idx3 p = unflat(t, g.n);
+    const Near<ND> nr(g, p);
     const T *c[3] = {c0, c1, c2};
     T acc = T(0);
     T ks = x[t], kc = T(0);
+#pragma unroll
     for (int d = 0; d < ND; d++) {
         T fl[2];
+#pragma unroll
         for (int s = 0; s < 2; s++) {
             Idx3 w = shifted(p, d, s);
-            T u = wall(g, d, c[d], w);
+            T u = nr.wall(g, d, c[d], w);
             if (flux_is_vel)
                 fl[s] = u;
             else
-                fl[s] = upwind(u, cell(g, x, shifted(w, d, -1)), cell(g, x, w));
+                fl[s] = upwind(u, nr.cell(g, x, shifted(w, d, -1)), nr.cell(g, x, w));
         }
         acc += fl[1] - fl[0];
         if (kahan) {
@@ -109,7 +152,7 @@ __global__ void k_donor(Geom g, const T *__restrict__ x, const T *c0, const T *c
 // antidiffusive pseudo-velocity at every dimension-d wall (eq. adf_vel, its
 // cross terms and the third-order terms)
 template <typename T, int ND, int WD>
-__global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T *c0,
+__global__ void __launch_bounds__(256) k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T *c0,
                          const T *c1, const T *c2, const T *G, T *__restrict__ V)
 {
     constexpr int d = WD;   // wall dimension (compile time: no dynamic indexing)
@@ -120,23 +163,26 @@ __global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T
     if (t >= M) return;
     const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT, absf = opts & OPT_ABS;
     // psi value entering a psi-fraction: |psi| under the abs option
+    const Idx3 p = unflat(t, e);
+    const Near<ND> nr(g, p);
     auto xv = [&](const Idx3 &q) -> T {
-        T v = cell(g, x, q);
+        T v = nr.cell(g, x, q);
         return absf ? fabs(v) : v;
     };
     const T *c[3] = {c0, c1, c2};
-    Idx3 p = unflat(t, e);
     Idx3 L = shifted(p, d, -1), R = p;
-    T u = wall(g, d, c[d], p);
-    T ig = T(1) / (T(0.5) * (gcell(g, G, L) + gcell(g, G, R)));   // 1 / mean G
+    T u = nr.wall(g, d, c[d], p);
+    T ig = T(1);                                                   // 1 / mean G
+    if (G) ig = T(1) / (T(0.5) * (nr.cell(g, G, L) + nr.cell(g, G, R)));
     T xL = xv(L), xR = xv(R);
     T V_ = (fabs(u) - u * u * ig) * frac(iga, xR - xL, xR + xL, T(2));
 
     T cb[3] = {T(0), T(0), T(0)};
+#pragma unroll
     for (int o = 0; o < ND; o++) {
         if (o == d) continue;
-        cb[o] = T(0.25) * (wall(g, o, c[o], L) + wall(g, o, c[o], shifted(L, o, 1)) +
-                           wall(g, o, c[o], R) + wall(g, o, c[o], shifted(R, o, 1)));
+        cb[o] = T(0.25) * (nr.wall(g, o, c[o], L) + nr.wall(g, o, c[o], shifted(L, o, 1)) +
+                           nr.wall(g, o, c[o], R) + nr.wall(g, o, c[o], shifted(R, o, 1)));
         T a = xv(shifted(R, o, 1)), b = xv(shifted(L, o, 1));
         T e_ = xv(shifted(R, o, -1)), f = xv(shifted(L, o, -1));
         V_ -= T(0.5) * u * cb[o] * ig * frac(iga, a + b - e_ - f, a + b + e_ + f, T(4));
@@ -145,9 +191,10 @@ __global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T
         // divergent-flow term: -c / (2 Gb) times the mean of the two cells'
         // advector divergences sum_o (c_o(hi) - c_o(lo))
         T dv = T(0);
+#pragma unroll
         for (int o = 0; o < ND; o++)
-            dv += (wall(g, o, c[o], shifted(L, o, 1)) - wall(g, o, c[o], L)) +
-                  (wall(g, o, c[o], shifted(R, o, 1)) - wall(g, o, c[o], R));
+            dv += (nr.wall(g, o, c[o], shifted(L, o, 1)) - nr.wall(g, o, c[o], L)) +
+                  (nr.wall(g, o, c[o], shifted(R, o, 1)) - nr.wall(g, o, c[o], R));
         // under iga the pseudo-velocity is a unit-field flux, so this
         // psi-free term carries the wall mean of psi
         if (iga) dv *= T(0.5) * (xL + xR);
@@ -157,6 +204,7 @@ __global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T
         T xR2 = xv(shifted(R, d, 1)), xL2 = xv(shifted(L, d, -1));
         T D = frac(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
         V_ += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) * D;
+#pragma unroll
         for (int o = 0; o < ND; o++) {
             if (o == d) continue;
             T a = xv(shifted(R, o, 1)), b = xv(shifted(L, o, 1));
@@ -168,6 +216,7 @@ __global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T
             int o1 = (d == 0) ? 1 : 0;
             int o2 = (d == 2) ? 1 : 2;
             T num = T(0), den = T(0);
+#pragma unroll
             for (int s = 0; s < 2; s++) {
                 Idx3 S = s ? R : L;
                 T vpp = xv(shifted(shifted(S, o1, 1), o2, 1));
@@ -185,7 +234,7 @@ __global__ void k_pseudo(Geom g, unsigned opts, const T *__restrict__ x, const T
 
 // limiter coefficients per cell (Sect. 3.1.4)
 template <typename T, int ND>
-__global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
+__global__ void __launch_bounds__(256) k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
                            const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
                            const T *G, T *__restrict__ bup, T *__restrict__ bdn)
 {
@@ -194,23 +243,27 @@ __global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
     if (t >= N) return;
     const bool iga = opts & OPT_IGA;
     const T *V[3] = {V0, V1, V2};
-    Idx3 p = unflat(t, g.n);
+    const Idx3 p = unflat(t, g.n);
+    const Near<ND> nr(g, p);
     T xi = x[t];
     T mx = psi_n[t], mn = mx;
     mx = fmax(mx, xi);
     mn = fmin(mn, xi);
+#pragma unroll
     for (int d = 0; d < ND; d++)
+#pragma unroll
         for (int s = -1; s <= 1; s += 2) {
             Idx3 q = shifted(p, d, s);
-            T a = cell(g, psi_n, q), b = cell(g, x, q);
+            T a = nr.cell(g, psi_n, q), b = nr.cell(g, x, q);
             mx = fmax(fmax(mx, a), b);
             mn = fmin(fmin(mn, a), b);
         }
     T fin = T(0), fout = T(0);
+#pragma unroll
     for (int d = 0; d < ND; d++) {
-        T vlo = wall(g, d, V[d], p), vhi = wall(g, d, V[d], shifted(p, d, 1));
-        T wm = iga ? T(1) : cell(g, x, shifted(p, d, -1));
-        T wp = iga ? T(1) : cell(g, x, shifted(p, d, 1));
+        T vlo = nr.wall(g, d, V[d], p), vhi = nr.wall(g, d, V[d], shifted(p, d, 1));
+        T wm = iga ? T(1) : nr.cell(g, x, shifted(p, d, -1));
+        T wp = iga ? T(1) : nr.cell(g, x, shifted(p, d, 1));
         T wi = iga ? T(1) : xi;
         fin += pos(vlo) * wm - neg(vhi) * wp;
         fout += pos(vhi) * wi - neg(vlo) * wi;
@@ -222,7 +275,7 @@ __global__ void k_fct_beta(Geom g, unsigned opts, const T *__restrict__ psi_n,
 
 // limited pseudo-velocity at every dimension-d wall
 template <typename T, int ND, int WD>
-__global__ void k_fct_limit(Geom g, const T *__restrict__ V, const T *__restrict__ bup,
+__global__ void __launch_bounds__(256) k_fct_limit(Geom g, const T *__restrict__ V, const T *__restrict__ bup,
                             const T *__restrict__ bdn, T *__restrict__ W)
 {
     constexpr int d = WD;   // wall dimension (compile time)
@@ -231,11 +284,12 @@ __global__ void k_fct_limit(Geom g, const T *__restrict__ V, const T *__restrict
     int64_t M = e[0] * e[1] * e[2];
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= M) return;
-    Idx3 p = unflat(t, e);
+    const Idx3 p = unflat(t, e);
+    const Near<ND> nr(g, p);
     Idx3 L = shifted(p, d, -1), R = p;
     T v = V[t];
-    T up = fmin(fmin(T(1), cell(g, bdn, L)), cell(g, bup, R));
-    T dn = fmin(fmin(T(1), cell(g, bup, L)), cell(g, bdn, R));
+    T up = fmin(fmin(T(1), nr.cell(g, bdn, L)), nr.cell(g, bup, R));
+    T dn = fmin(fmin(T(1), nr.cell(g, bup, L)), nr.cell(g, bdn, R));
     W[t] = pos(v) * up + neg(v) * dn;
 }
 
