@@ -264,8 +264,12 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
             x = y;
         }
     } else if (fused && p->desc.n_dims == 3) {
+        mp::Fused3DWork<T> w{(T *)p->L.tmp[0],
+                             {(T *)p->L.faces[0][0], (T *)p->L.faces[0][1], (T *)p->L.faces[0][2]},
+                             (T *)p->L.bup,
+                             (T *)p->L.bdn};
         e = mp::fused3d_step<T>(p->g, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, c2,
-                                G, p->tile_rows, p->stream);
+                                G, p->tile_rows, p->stream, w);
     } else if (fused) {
         mp::Fused2DShape sh{p->g.n[0], p->g.n[1], p->g.bc[0], p->g.bc[1], p->tile_rows};
         e = mp::fused2d_step<T>(sh, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, G,

@@ -114,7 +114,8 @@ __global__ void __launch_bounds__(256) k_donor3d(G3 g, int kahan, int tiles_k, i
 bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], const int bc[3])
 {
     (void)bc;
-    if (nd != 3 || !(n_iters == 1 || n_iters == 2) || (opts & (OPT_FCT | OPT_ABS | OPT_DFL)))
+    // (n_iters = 1: the limiter has nothing to limit)
+    if (nd != 3 || !(n_iters == 1 || n_iters == 2) || (opts & (OPT_ABS | OPT_DFL)))
         return false;
     if (n_iters == 2) return step3d_supported(nd, n_iters, opts, n);
     return n[0] < (1 << 30) && n[1] < (1 << 30) && n[2] < (1 << 30);
@@ -123,11 +124,24 @@ bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], c
 template <typename T>
 hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *psi_n, T *psi_out,
                         const T *c0, const T *c1, const T *c2, const T *G, int tile_planes,
-                        hipStream_t s)
+                        hipStream_t s, const Fused3DWork<T> &w)
 {
     if (n_iters == 2) {
         if (!step3d_supported(geom.nd, n_iters, opts, geom.n)) return hipErrorNotSupported;
-        return step3d_launch<T>(geom, opts, psi_n, psi_out, c0, c1, c2, G, tile_planes, s);
+        if (!(opts & OPT_FCT))
+            return step3d_launch<T>(geom, opts, psi_n, psi_out, c0, c1, c2, G, tile_planes, s);
+        // with the limiter: donor pass and raw pseudo-velocities in one
+        // launch, then the coefficients and the limited corrective pass
+        Step3dOut<T> vo;
+        vo.y1 = w.y1;
+        vo.v0 = w.v[0];
+        vo.v1 = w.v[1];
+        vo.v2 = w.v[2];
+        hipError_t e = step3d_launch<T>(geom, opts & ~OPT_FCT, psi_n, nullptr, c0, c1, c2, G,
+                                        tile_planes, s, vo);
+        if (e != hipSuccess) return e;
+        const T *V[3] = {w.v[0], w.v[1], w.v[2]};
+        return fct_correct_launch<T>(geom, opts, psi_n, w.y1, V, G, w.bup, w.bdn, psi_out, s);
     }
     if (n_iters != 1) return hipErrorNotSupported;
     G3 g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
@@ -146,9 +160,11 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
 
 template hipError_t fused3d_step<float>(const Geom &, int, unsigned, const float *, float *,
                                         const float *, const float *, const float *,
-                                        const float *, int, hipStream_t);
+                                        const float *, int, hipStream_t,
+                                        const Fused3DWork<float> &);
 template hipError_t fused3d_step<double>(const Geom &, int, unsigned, const double *, double *,
                                          const double *, const double *, const double *,
-                                         const double *, int, hipStream_t);
+                                         const double *, int, hipStream_t,
+                                         const Fused3DWork<double> &);
 
 }  // namespace mp

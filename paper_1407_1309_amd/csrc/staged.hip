@@ -293,6 +293,54 @@ __global__ void __launch_bounds__(256) k_fct_limit(Geom g, const T *__restrict__
     W[t] = pos(v) * up + neg(v) * dn;
 }
 
+// limited velocities at the cell's walls and the corrective donor-cell
+// update in one kernel (one thread per cell): the arithmetic of k_fct_limit
+// followed by k_donor, term by term, without the limited velocities going
+// through memory.  mode bit 0: the flux is the limited velocity itself
+// (infinite gauge); bit 1: Kahan-compensated update.
+template <typename T, int ND>
+__global__ void __launch_bounds__(256)
+k_limcorr(Geom g, const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
+          const T *__restrict__ bup, const T *__restrict__ bdn, const T *G, int mode,
+          T *__restrict__ out)
+{
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const bool flux_is_vel = mode & 1, kahan = mode & 2;
+    const Idx3 p = unflat(t, g.n);
+    const Near<ND> nr(g, p);
+    const T *V[3] = {V0, V1, V2};
+    T acc = T(0);
+    T ks = x[t], kc = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        T fl[2];
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const Idx3 w = shifted(p, d, s);
+            const Idx3 L = shifted(w, d, -1), R = w;
+            const T v = nr.wall(g, d, V[d], w);
+            const T up = fmin(fmin(T(1), nr.cell(g, bdn, L)), nr.cell(g, bup, R));
+            const T dn = fmin(fmin(T(1), nr.cell(g, bup, L)), nr.cell(g, bdn, R));
+            const T u = pos(v) * up + neg(v) * dn;
+            fl[s] = flux_is_vel ? u : upwind(u, nr.cell(g, x, L), nr.cell(g, x, R));
+        }
+        acc += fl[1] - fl[0];
+        if (kahan) {
+            T term = fl[1] - fl[0];
+            if (G) term = term / G[t];
+            kahan_add(ks, kc, -term);
+        }
+    }
+    if (kahan) {
+        out[t] = ks;
+        return;
+    }
+    T r = G ? acc / G[t] : acc;
+    out[t] = x[t] - r;
+}
+
 template <typename T>
 int64_t wall_count(const Geom &g, int d)
 {
@@ -389,6 +437,22 @@ hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, const T *x,
+                              const T *const V[3], const T *G, T *bup, T *bdn, T *y,
+                              hipStream_t s)
+{
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    const unsigned cb = (unsigned)cdiv(N, 256);
+    const int mode = ((opts & OPT_IGA) ? 1 : 0) | ((opts & OPT_KAHAN) ? 2 : 0);
+    with_nd(g.nd, [&](auto ND) {
+        constexpr int nd = decltype(ND)::value;
+        k_fct_beta<T, nd><<<cb, 256, 0, s>>>(g, opts, psi_n, x, V[0], V[1], V[2], G, bup, bdn);
+        k_limcorr<T, nd><<<cb, 256, 0, s>>>(g, x, V[0], V[1], V[2], bup, bdn, G, mode, y);
+    });
+    return hipGetLastError();
+}
+
 #define MP_INST(T)                                                                            \
     template hipError_t launch_donor<T>(const Geom &, const T *, const T *const[3], const T *, \
                                         int, T *, hipStream_t);                               \
@@ -396,7 +460,10 @@ hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
                                          const T *, T *const[3], hipStream_t);                \
     template hipError_t launch_fct<T>(const Geom &, unsigned, const T *, const T *,            \
                                       const T *const[3], const T *, T *, T *, T *const[3],    \
-                                      hipStream_t);
+                                      hipStream_t);                                           \
+    template hipError_t fct_correct_launch<T>(const Geom &, unsigned, const T *, const T *,    \
+                                              const T *const[3], const T *, T *, T *, T *,     \
+                                              hipStream_t);
 MP_INST(float)
 MP_INST(double)
 #undef MP_INST

@@ -83,7 +83,8 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                                                const T *__restrict__ c0,
                                                const T *__restrict__ c1,
                                                const T *__restrict__ c2,
-                                               const T *__restrict__ G, T *__restrict__ out)
+                                               const T *__restrict__ G, T *__restrict__ out,
+                                               Step3dOut<T> vo)
 {
     __shared__ T Ps[3][NP];                              // psi^n, planes t-1..t+1
     __shared__ T Ys[4][NY];                              // y1, planes t-3..t
@@ -400,16 +401,51 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         };
 
         const T v0_hi = vel0();
-        V1s[r * SK + l] = vel1(bj, bk);
-        V2s[r * (SK + 1) + l] = vel2(bj, bk);
-        if (tid < SK) V1s[SJ * SK + tid] = vel1(SJ + 2, tid + 2);            // far j edge
-        else if (tid < SK + SJ) V2s[(tid - SK) * (SK + 1) + SK] = vel2(tid - SK + 2, SK + 2);
+        if (vo.y1) {
+            // output mode: the donor result and the raw pseudo-velocities of
+            // the chunk's planes (V0 at its walls), each entry by its owner
+            // -- the low walls of the tile's cells, and along an open
+            // dimension the domain's far edge walls -- for the limiter's
+            // kernels, instead of the corrective pass
+            const int jj = j0 + r, kk = k0 + l;
+            const int64_t n1 = g.n1, n2 = g.n2;
+            const bool o0 = g.bc0 == BC_OPEN, o1 = g.bc1 == BC_OPEN, o2 = g.bc2 == BC_OPEN;
+            const int w0 = p + 1;
+            if (own_out && ((w0 >= i0 && w0 < i1) || (o0 && w0 == g.n0 && i1 == g.n0)))
+                vo.v0[((int64_t)w0 * n1 + jj) * n2 + kk] = v0_hi;
+            if (p >= i0 && p < i1) {
+                if (own_out) vo.y1[((int64_t)p * n1 + jj) * n2 + kk] = YB[cy];
+                if (kk < g.n2 && (jj < g.n1 || (o1 && jj == g.n1)))
+                    vo.v1[((int64_t)p * (n1 + 1) + jj) * n2 + kk] = vel1(bj, bk);
+                if (jj < g.n1 && (kk < g.n2 || (o2 && kk == g.n2)))
+                    vo.v2[((int64_t)p * n1 + jj) * (n2 + 1) + kk] = vel2(bj, bk);
+                if (tid < SK) {                                            // far j edge
+                    const int je = j0 + SJ, ke = k0 + tid;
+                    if (o1 && je == g.n1 && ke < g.n2)
+                        vo.v1[((int64_t)p * (n1 + 1) + je) * n2 + ke] = vel1(SJ + 2, tid + 2);
+                } else if (tid < SK + SJ) {                                // far k edge
+                    const int je = j0 + tid - SK, ke = k0 + SK;
+                    if (o2 && ke == g.n2 && je < g.n1)
+                        vo.v2[((int64_t)p * n1 + je) * (n2 + 1) + ke] =
+                            vel2(tid - SK + 2, SK + 2);
+                }
+            }
+        } else {
+            V1s[r * SK + l] = vel1(bj, bk);
+            V2s[r * (SK + 1) + l] = vel2(bj, bk);
+            if (tid < SK) V1s[SJ * SK + tid] = vel1(SJ + 2, tid + 2);        // far j edge
+            else if (tid < SK + SJ)
+                V2s[(tid - SK) * (SK + 1) + SK] = vel2(tid - SK + 2, SK + 2);
+        }
         T g_own = T(1);
         if (HAS_G) g_own = Gs[cs][cy];
-        __syncthreads();   // (B3) V1, V2 of plane p are in LDS
+        // (B3) V1, V2 of plane p are in LDS; and (in both modes) no thread
+        // stores the next planes into the rings before every thread is done
+        // reading this iteration's
+        __syncthreads();
 
         // ---- corrective pass at plane p ----
-        if (p >= i0 && p < i1 && own_out) {
+        if (!vo.y1 && p >= i0 && p < i1 && own_out) {
             const T xo = YB[cy];
             const T V0lo = v0_lo, V0hi = v0_hi;
             const T V1lo = V1s[r * SK + l], V1hi = V1s[(r + 1) * SK + l];
@@ -461,7 +497,8 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
 
 bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3])
 {
-    if (nd != 3 || n_iters != 2 || (opts & (OPT_FCT | OPT_ABS | OPT_DFL))) return false;
+    // (with the limiter the kernel runs in output mode, see fused3d_step)
+    if (nd != 3 || n_iters != 2 || (opts & (OPT_ABS | OPT_DFL))) return false;
     // 32-bit plane and row indices inside the kernel
     if (n[0] >= (1 << 30) || n[1] >= (1 << 30) || n[2] >= (1 << 30)) return false;
     return true;
@@ -469,7 +506,8 @@ bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3])
 
 template <typename T>
 hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi_out, const T *c0,
-                         const T *c1, const T *c2, const T *G, int tile_planes, hipStream_t s)
+                         const T *c1, const T *c2, const T *G, int tile_planes, hipStream_t s,
+                         const Step3dOut<T> &vo)
 {
     G3s g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
     const int tiles_k = (g.n2 + SK - 1) / SK, tiles_j = (g.n1 + SJ - 1) / SJ;
@@ -482,7 +520,7 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
     const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
 #define MP_S3(HG, IG, TO)                                                                       \
     k_step3d<T, HG, IG, TO><<<(unsigned)blocks, NT, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, \
-                                                           kahan, psi_n, c0, c1, c2, G, psi_out)
+                                                           kahan, psi_n, c0, c1, c2, G, psi_out, vo)
     if (G) {
         if (iga) { if (tot) MP_S3(true, true, true); else MP_S3(true, true, false); }
         else { if (tot) MP_S3(true, false, true); else MP_S3(true, false, false); }
@@ -496,9 +534,11 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
 
 template hipError_t step3d_launch<float>(const Geom &, unsigned, const float *, float *,
                                          const float *, const float *, const float *,
-                                         const float *, int, hipStream_t);
+                                         const float *, int, hipStream_t,
+                                         const Step3dOut<float> &);
 template hipError_t step3d_launch<double>(const Geom &, unsigned, const double *, double *,
                                           const double *, const double *, const double *,
-                                          const double *, int, hipStream_t);
+                                          const double *, int, hipStream_t,
+                                          const Step3dOut<double> &);
 
 }  // namespace mp
