@@ -264,10 +264,13 @@ int one_step(mpdata_plan *p, const T *psi_n, T *psi_out, const T *G, const T *c0
             x = y;
         }
     } else if (fused && p->desc.n_dims == 3) {
-        mp::Fused3DWork<T> w{(T *)p->L.tmp[0],
-                             {(T *)p->L.faces[0][0], (T *)p->L.faces[0][1], (T *)p->L.faces[0][2]},
-                             (T *)p->L.bup,
-                             (T *)p->L.bdn};
+        mp::Fused3DWork<T> w;
+        for (int k = 0; k < 2; k++) {
+            w.cell[k] = (T *)p->L.tmp[k];
+            for (int d = 0; d < 3; d++) w.wall[k][d] = (T *)p->L.faces[k][d];
+        }
+        w.bup = (T *)p->L.bup;
+        w.bdn = (T *)p->L.bdn;
         e = mp::fused3d_step<T>(p->g, p->desc.n_iters, p->desc.opts, psi_n, psi_out, c0, c1, c2,
                                 G, p->tile_rows, p->stream, w);
     } else if (fused) {

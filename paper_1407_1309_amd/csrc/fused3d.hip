@@ -115,9 +115,8 @@ bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], c
 {
     (void)bc;
     // (n_iters = 1: the limiter has nothing to limit)
-    if (nd != 3 || !(n_iters == 1 || n_iters == 2) || (opts & (OPT_ABS | OPT_DFL)))
-        return false;
-    if (n_iters == 2) return step3d_supported(nd, n_iters, opts, n);
+    if (nd != 3 || n_iters < 1 || (opts & (OPT_ABS | OPT_DFL))) return false;
+    if (n_iters >= 2) return step3d_supported(nd, n_iters, opts, n);
     return n[0] < (1 << 30) && n[1] < (1 << 30) && n[2] < (1 << 30);
 }
 
@@ -126,22 +125,56 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
                         const T *c0, const T *c1, const T *c2, const T *G, int tile_planes,
                         hipStream_t s, const Fused3DWork<T> &w)
 {
-    if (n_iters == 2) {
+    if (n_iters >= 2) {
         if (!step3d_supported(geom.nd, n_iters, opts, geom.n)) return hipErrorNotSupported;
-        if (!(opts & OPT_FCT))
+        const bool fct = opts & OPT_FCT;
+        if (n_iters == 2 && !fct)
             return step3d_launch<T>(geom, opts, psi_n, psi_out, c0, c1, c2, G, tile_planes, s);
-        // with the limiter: donor pass and raw pseudo-velocities in one
-        // launch, then the coefficients and the limited corrective pass
-        Step3dOut<T> vo;
-        vo.y1 = w.y1;
-        vo.v0 = w.v[0];
-        vo.v1 = w.v[1];
-        vo.v2 = w.v[2];
-        hipError_t e = step3d_launch<T>(geom, opts & ~OPT_FCT, psi_n, nullptr, c0, c1, c2, G,
-                                        tile_planes, s, vo);
-        if (e != hipSuccess) return e;
-        const T *V[3] = {w.v[0], w.v[1], w.v[2]};
-        return fct_correct_launch<T>(geom, opts, psi_n, w.y1, V, G, w.bup, w.bdn, psi_out, s);
+        // pass by pass: the 3-D kernel forms the pass's raw
+        // pseudo-velocities (pass 2 from the donor pass it forms itself,
+        // which it also writes; later passes from the previous result),
+        // then cell kernels apply the limiter and the corrective pass.
+        // Buffers: the pass input in cell[xs], its advector in wall[as]
+        // (the input advector for pass 2), its raw velocities into the
+        // other wall set, its limited velocities (the next advector) into
+        // wall[as] once the raw ones are formed.
+        const int mode = ((opts & OPT_IGA) ? 1 : 0) | ((opts & OPT_KAHAN) ? 2 : 0);
+        const T *x = nullptr;
+        const T *adv[3] = {c0, c1, c2};
+        int xs = 0, as = 1;
+        for (int it = 2; it <= n_iters; it++) {
+            const bool last = it == n_iters;
+            const int vs = 1 - as;                   // wall set for this pass's raw velocities
+            Step3dOut<T> vo;
+            vo.xin = x;
+            if (!x) vo.y1 = w.cell[0];               // pass 2: keep the donor result
+            vo.v0 = w.wall[vs][0];
+            vo.v1 = w.wall[vs][1];
+            vo.v2 = w.wall[vs][2];
+            hipError_t e = step3d_launch<T>(geom, opts & ~OPT_FCT, psi_n, nullptr, adv[0], adv[1],
+                                            adv[2], G, tile_planes, s, vo);
+            if (e != hipSuccess) return e;
+            const T *xp = x ? x : w.cell[0];
+            T *y = last ? psi_out : w.cell[1 - xs];
+            const T *V[3] = {w.wall[vs][0], w.wall[vs][1], w.wall[vs][2]};
+            if (fct) {
+                T *W[3] = {nullptr, nullptr, nullptr};
+                if (!last)
+                    for (int d = 0; d < 3; d++) W[d] = w.wall[as][d];
+                // (the next pass's advector W stays in wall[as]; its raw
+                // velocities go to the set that held V)
+                e = fct_correct_launch<T>(geom, opts, psi_n, xp, V, G, w.bup, w.bdn, y, W, s);
+                for (int d = 0; d < 3; d++) adv[d] = W[d];
+            } else {
+                e = launch_donor<T>(geom, xp, V, G, mode, y, s);
+                for (int d = 0; d < 3; d++) adv[d] = V[d];
+                as = vs;                             // the next advector is V
+            }
+            if (e != hipSuccess) return e;
+            x = y;
+            xs = 1 - xs;
+        }
+        return hipGetLastError();
     }
     if (n_iters != 1) return hipErrorNotSupported;
     G3 g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};

@@ -75,15 +75,19 @@ hipError_t fused2d_step(const Fused2DShape &sh, int n_iters, unsigned opts, cons
 // upper bound for chunks of at least min_rows rows
 int64_t fused2d_max_parts(int64_t n0, int64_t n1, int n_iters, unsigned opts, int min_rows);
 
-// ---- 3-D, two passes: one launch per step without the limiter (step3d.hip;
-// the donor-only step is k_donor3d in fused3d.hip); with the limiter the
-// same kernel writes the donor result and the raw pseudo-velocities, then
-// the limiter coefficients and the limited corrective pass follow
-// (staged.hip: fct_correct_launch)
-// Output mode of the 3-D step kernel (y1 non-NULL): instead of the
-// corrective pass, the donor result y1 (cells) and the raw pseudo-velocities
-// v0, v1, v2 (walls, n_d + 1 along d).
+// ---- 3-D: a two-pass step without the limiter is one launch (step3d.hip;
+// the donor-only step is k_donor3d in fused3d.hip).  With the limiter, or
+// more passes, the same kernel forms each pass's raw pseudo-velocities (the
+// first pass's input by its donor pass, a later pass's read from memory)
+// and cell kernels apply the limiter and the corrective pass (staged.hip:
+// fct_correct_launch, launch_donor).
+// Modes of the 3-D step kernel: xin non-NULL: the pass input is read from
+// xin (and c0..c2 are that pass's advector) instead of formed by the donor
+// pass; v0 non-NULL (output mode): instead of the corrective pass, the raw
+// pseudo-velocities v0, v1, v2 (walls, n_d + 1 along d) and, when y1 is
+// non-NULL, the donor result y1 are written.
 template <typename T> struct Step3dOut {
+    const T *xin = nullptr;
     T *y1 = nullptr, *v0 = nullptr, *v1 = nullptr, *v2 = nullptr;
 };
 bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3]);
@@ -91,9 +95,10 @@ template <typename T>
 hipError_t step3d_launch(const Geom &g, unsigned opts, const T *psi_n, T *psi_out, const T *c0,
                          const T *c1, const T *c2, const T *G, int tile_planes, hipStream_t s,
                          const Step3dOut<T> &vo = Step3dOut<T>());
-// workspace of the 3-D step with the limiter (cells: y1, bup, bdn; walls: v)
+// workspace of the 3-D step by passes: two cell fields, two sets of wall
+// fields, the limiter coefficients
 template <typename T> struct Fused3DWork {
-    T *y1, *v[3], *bup, *bdn;
+    T *cell[2], *wall[2][3], *bup, *bdn;
 };
 bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], const int bc[3]);
 template <typename T>
@@ -101,11 +106,13 @@ hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_
                         const T *c0, const T *c1, const T *c2, const T *G, int tile_planes,
                         hipStream_t s, const Fused3DWork<T> &w);
 // the limiter's coefficients of a pass (from its input x and raw
-// pseudo-velocities V), then its limited corrective donor-cell pass: x -> y
+// pseudo-velocities V), then its limited corrective donor-cell pass: x -> y;
+// W (entries NULL: not wanted) receives the limited velocities, the next
+// pass's advector
 template <typename T>
 hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, const T *x,
                               const T *const V[3], const T *G, T *bup, T *bdn, T *y,
-                              hipStream_t s);
+                              T *const W[3], hipStream_t s);
 
 // ---- one corrective pass of a 2-D step in one launch (pass2d.hip) --------
 // no third-order terms, any boundaries; x: previous pass's result, c0/c1:

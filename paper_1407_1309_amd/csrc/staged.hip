@@ -296,13 +296,15 @@ __global__ void __launch_bounds__(256) k_fct_limit(Geom g, const T *__restrict__
 // limited velocities at the cell's walls and the corrective donor-cell
 // update in one kernel (one thread per cell): the arithmetic of k_fct_limit
 // followed by k_donor, term by term, without the limited velocities going
-// through memory.  mode bit 0: the flux is the limited velocity itself
-// (infinite gauge); bit 1: Kahan-compensated update.
+// through memory -- unless a following pass needs them as its advector:
+// then W0..W2 (non-NULL) receive each cell's low walls and, along an open
+// dimension, the far edge wall.  mode bit 0: the flux is the limited
+// velocity itself (infinite gauge); bit 1: Kahan-compensated update.
 template <typename T, int ND>
 __global__ void __launch_bounds__(256)
 k_limcorr(Geom g, const T *__restrict__ x, const T *V0, const T *V1, const T *V2,
           const T *__restrict__ bup, const T *__restrict__ bdn, const T *G, int mode,
-          T *__restrict__ out)
+          T *__restrict__ out, T *W0, T *W1, T *W2)
 {
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,6 +313,7 @@ k_limcorr(Geom g, const T *__restrict__ x, const T *V0, const T *V1, const T *V2
     const Idx3 p = unflat(t, g.n);
     const Near<ND> nr(g, p);
     const T *V[3] = {V0, V1, V2};
+    T *Wo[3] = {W0, W1, W2};
     T acc = T(0);
     T ks = x[t], kc = T(0);
 #pragma unroll
@@ -324,6 +327,11 @@ k_limcorr(Geom g, const T *__restrict__ x, const T *V0, const T *V1, const T *V2
             const T up = fmin(fmin(T(1), nr.cell(g, bdn, L)), nr.cell(g, bup, R));
             const T dn = fmin(fmin(T(1), nr.cell(g, bup, L)), nr.cell(g, bdn, R));
             const T u = pos(v) * up + neg(v) * dn;
+            if (Wo[d] && (s == 0 || (g.bc[d] == BC_OPEN && p.v[d] == (int)g.n[d] - 1))) {
+                int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+                e[d] += 1;
+                Wo[d][((int64_t)w.v[0] * e[1] + w.v[1]) * e[2] + w.v[2]] = u;
+            }
             fl[s] = flux_is_vel ? u : upwind(u, nr.cell(g, x, L), nr.cell(g, x, R));
         }
         acc += fl[1] - fl[0];
@@ -440,7 +448,7 @@ hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
 template <typename T>
 hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, const T *x,
                               const T *const V[3], const T *G, T *bup, T *bdn, T *y,
-                              hipStream_t s)
+                              T *const W[3], hipStream_t s)
 {
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
     const unsigned cb = (unsigned)cdiv(N, 256);
@@ -448,7 +456,8 @@ hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, cons
     with_nd(g.nd, [&](auto ND) {
         constexpr int nd = decltype(ND)::value;
         k_fct_beta<T, nd><<<cb, 256, 0, s>>>(g, opts, psi_n, x, V[0], V[1], V[2], G, bup, bdn);
-        k_limcorr<T, nd><<<cb, 256, 0, s>>>(g, x, V[0], V[1], V[2], bup, bdn, G, mode, y);
+        k_limcorr<T, nd><<<cb, 256, 0, s>>>(g, x, V[0], V[1], V[2], bup, bdn, G, mode, y, W[0],
+                                            W[1], W[2]);
     });
     return hipGetLastError();
 }
@@ -463,7 +472,7 @@ hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, cons
                                       hipStream_t);                                           \
     template hipError_t fct_correct_launch<T>(const Geom &, unsigned, const T *, const T *,    \
                                               const T *const[3], const T *, T *, T *, T *,     \
-                                              hipStream_t);
+                                              T *const[3], hipStream_t);
 MP_INST(float)
 MP_INST(double)
 #undef MP_INST

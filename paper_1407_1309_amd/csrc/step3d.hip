@@ -77,7 +77,7 @@ __device__ __forceinline__ int64_t box_offset(int e, int n_e, int w, int jb, int
     return j * row_len + k;
 }
 
-template <typename T, bool HAS_G, bool IGA, bool TOT>
+template <typename T, bool HAS_G, bool IGA, bool TOT, bool XIN>
 __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int tiles_j, int nblk,
                                                int kahan, const T *__restrict__ x,
                                                const T *__restrict__ c0,
@@ -155,15 +155,25 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         yp[m] = bj * BK + bk;      // where the result goes
     }
 
+    // pass mode: the pass input is read (plane t into the y1 ring, on the
+    // box, at boundary-mapped positions -- what the donor pass forms at the
+    // clamped positions) instead of formed by the donor pass
+    const T *xin = XIN ? vo.xin : nullptr;
+    const bool open0 = g.bc0 == BC_OPEN;
     // prefetched plane values (stored to LDS at the start of the next
-    // iteration): psi^n, c0 (two entries each), c1, c2, G
+    // iteration): psi^n (donor pass) or the pass input, c0 (two entries
+    // each), c1, c2, G
     T fP[2], fC0[2], fC1[2], fC2[2], fG[2];
     auto fetch = [&](int t) {
         const int64_t ip = map_cell(t + 1, g.n0, g.bc0) * pl;     // psi^n plane t+1
         const int64_t iw = map_wall(t + 1, g.n0, g.bc0) * pl;     // c0 wall t+1
         const int64_t ic = map_cell(t, g.n0, g.bc0);              // plane t
         for (int m = 0; m < 2; m++) {
-            if (oP[m] >= 0) fP[m] = x[ip + oP[m]];
+            if (xin) {
+                if (oY[m] >= 0) fP[m] = xin[ic * pl + oY[m]];
+            } else if (oP[m] >= 0) {
+                fP[m] = x[ip + oP[m]];
+            }
             if (oY[m] >= 0) fC0[m] = c0[iw + oY[m]];
             if (o1[m] >= 0) fC1[m] = c1[ic * pl1 + o1[m]];
             if (o2[m] >= 0) fC2[m] = c2[ic * pl2 + o2[m]];
@@ -172,9 +182,16 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
     };
     auto store = [&](int t) {
         const int sp = slot3(t + 1), sw = slot4(t + 1), sc = slot3(t);
+        // (pass mode, open: planes outside the domain are not stored, so
+        // the edge plane's slot stays what those planes read)
+        const bool xplane = xin && (!open0 || (t >= 0 && t < g.n0));
         for (int m = 0; m < 2; m++) {
             const int e = tid + m * NT;
-            if (oP[m] >= 0) Ps[sp][e] = fP[m];
+            if (xin) {
+                if (xplane && oY[m] >= 0) Ys[slot4(t)][e] = fP[m];
+            } else if (oP[m] >= 0) {
+                Ps[sp][e] = fP[m];
+            }
             if (oY[m] >= 0) C0s[sw][e] = fC0[m];
             if (o1[m] >= 0) C1s[sc][e] = fC1[m];
             if (o2[m] >= 0) C2s[sc][e] = fC2[m];
@@ -190,7 +207,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         const int64_t iw0 = map_wall(t_first, g.n0, g.bc0) * pl;
         for (int m = 0; m < 2; m++) {
             const int e = tid + m * NT;
-            if (oP[m] >= 0) {
+            if (!xin && oP[m] >= 0) {
                 Ps[slot3(t_first - 1)][e] = x[ipm + oP[m]];
                 Ps[slot3(t_first)][e] = x[ip0 + oP[m]];
             }
@@ -199,7 +216,6 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
     }
     fetch(t_first);
 
-    const bool open0 = g.bc0 == BC_OPEN;
     // y1 ring slot of virtual plane q (open: planes outside the domain read
     // the edge plane)
     auto yslot = [&](int q) { return slot4(open0 ? min(max(q, 0), g.n0 - 1) : q); };
@@ -216,7 +232,9 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         __syncthreads();   // (B1) plane t's inputs are in LDS
 
         // ---- donor-cell pass: y1 of plane t on the box ----
-        if (!open0 || (t >= 0 && t < g.n0)) {
+        if (xin) {
+            if (!open0 || (t >= 0 && t < g.n0)) y_own = Ys[slot4(t)][cy];
+        } else if (!open0 || (t >= 0 && t < g.n0)) {
             const int pm = slot3(t - 1), p0 = slot3(t), pp = slot3(t + 1);
             const int wl = slot4(t), wh = slot4(t + 1), sc = slot3(t), sy = slot4(t);
             for (int m = 0; m < 2; m++) {
@@ -401,7 +419,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         };
 
         const T v0_hi = vel0();
-        if (vo.y1) {
+        if (vo.v0) {
             // output mode: the donor result and the raw pseudo-velocities of
             // the chunk's planes (V0 at its walls), each entry by its owner
             // -- the low walls of the tile's cells, and along an open
@@ -414,7 +432,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             if (own_out && ((w0 >= i0 && w0 < i1) || (o0 && w0 == g.n0 && i1 == g.n0)))
                 vo.v0[((int64_t)w0 * n1 + jj) * n2 + kk] = v0_hi;
             if (p >= i0 && p < i1) {
-                if (own_out) vo.y1[((int64_t)p * n1 + jj) * n2 + kk] = YB[cy];
+                if (own_out && vo.y1) vo.y1[((int64_t)p * n1 + jj) * n2 + kk] = YB[cy];
                 if (kk < g.n2 && (jj < g.n1 || (o1 && jj == g.n1)))
                     vo.v1[((int64_t)p * (n1 + 1) + jj) * n2 + kk] = vel1(bj, bk);
                 if (jj < g.n1 && (kk < g.n2 || (o2 && kk == g.n2)))
@@ -445,7 +463,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         __syncthreads();
 
         // ---- corrective pass at plane p ----
-        if (!vo.y1 && p >= i0 && p < i1 && own_out) {
+        if (!vo.v0 && p >= i0 && p < i1 && own_out) {
             const T xo = YB[cy];
             const T V0lo = v0_lo, V0hi = v0_hi;
             const T V1lo = V1s[r * SK + l], V1hi = V1s[(r + 1) * SK + l];
@@ -497,8 +515,9 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
 
 bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3])
 {
-    // (with the limiter the kernel runs in output mode, see fused3d_step)
-    if (nd != 3 || n_iters != 2 || (opts & (OPT_ABS | OPT_DFL))) return false;
+    // (with the limiter or more than two passes the kernel runs pass by
+    // pass in output mode, see fused3d_step)
+    if (nd != 3 || n_iters < 2 || (opts & (OPT_ABS | OPT_DFL))) return false;
     // 32-bit plane and row indices inside the kernel
     if (n[0] >= (1 << 30) || n[1] >= (1 << 30) || n[2] >= (1 << 30)) return false;
     return true;
@@ -518,9 +537,17 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
     const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
-#define MP_S3(HG, IG, TO)                                                                       \
-    k_step3d<T, HG, IG, TO><<<(unsigned)blocks, NT, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, \
-                                                           kahan, psi_n, c0, c1, c2, G, psi_out, vo)
+#define MP_S3(HG, IG, TO)                                                                     \
+    do {                                                                                      \
+        if (vo.xin)                                                                           \
+            k_step3d<T, HG, IG, TO, true><<<(unsigned)blocks, NT, 0, s>>>(                    \
+                g, th, tiles_k, tiles_j, (int)blocks, kahan, psi_n, c0, c1, c2, G, psi_out,   \
+                vo);                                                                          \
+        else                                                                                  \
+            k_step3d<T, HG, IG, TO, false><<<(unsigned)blocks, NT, 0, s>>>(                   \
+                g, th, tiles_k, tiles_j, (int)blocks, kahan, psi_n, c0, c1, c2, G, psi_out,   \
+                vo);                                                                          \
+    } while (0)
     if (G) {
         if (iga) { if (tot) MP_S3(true, true, true); else MP_S3(true, true, false); }
         else { if (tot) MP_S3(true, false, true); else MP_S3(true, false, false); }

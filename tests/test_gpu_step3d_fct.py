@@ -1,6 +1,8 @@
-"""3-D two-pass steps with the limiter: the one-launch 3-D kernel writes the
-donor result and the raw pseudo-velocities, then the limiter coefficients
-and the limited corrective pass run as two cell kernels.  Against the oracle
+"""3-D steps with the limiter or more than two passes: the one-launch 3-D
+kernel forms each pass's raw pseudo-velocities (pass 2 from the donor pass
+it forms itself, later passes from the previous result) and writes them,
+then the limiter coefficients and the limited corrective pass run as two
+cell kernels (without the limiter, the corrective pass alone).  Against the oracle
 (every element within the element-wise bar): every option mix with and
 without G, both boundary types and mixed ones, tiles and plane chunks with
 ragged tails, FP64 and FP32, and a larger grid."""
@@ -32,8 +34,8 @@ def _case(shape, bcs, opts, with_g, seed):
     return psi, c, g
 
 
-def _run(psi, c, g, bcs, opts, dtype, n_steps, kernel=mpdata.KERNEL_AUTO):
-    plan = mpdata.Plan(psi.shape, dtype=dtype, n_iters=2, opts=opts, bc=list(bcs),
+def _run(psi, c, g, bcs, opts, dtype, n_steps, kernel=mpdata.KERNEL_AUTO, n_iters=2):
+    plan = mpdata.Plan(psi.shape, dtype=dtype, n_iters=n_iters, opts=opts, bc=list(bcs),
                        has_g=g is not None, kernel=kernel)
     p = dev(psi, dtype)
     plan.timing(1)
@@ -86,3 +88,19 @@ def test_step3d_fct_close_to_staged():
                    kernel=mpdata.KERNEL_STAGED)
     assert name == "staged step"
     assert rel_l2(a, b) <= 1e-13
+
+
+@pytest.mark.parametrize("n_iters", [3, 4])
+@pytest.mark.parametrize("with_g", [False, True], ids=["g1", "g"])
+@pytest.mark.parametrize("opts", [0, FCT, TOT, FCT | TOT, FCT | KAHAN])
+@pytest.mark.parametrize("shape,bcs", [((23, 17, 40), (1, 0, 1)), ((130, 21, 34), (0, 0, 0)),
+                                       ((15, 36, 33), (1, 1, 1))],
+                         ids=lambda v: "x".join(map(str, v)))
+def test_step3d_more_passes_vs_oracle(shape, bcs, opts, with_g, n_iters):
+    """Three and four passes: each later pass reads the previous result and
+    takes the previous pass's limited (or raw) velocities as its advector."""
+    psi, c, g = _case(shape, bcs, opts, with_g, seed=sum(shape) + 3 * opts + n_iters)
+    ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=list(bcs), n_steps=3)
+    out, name = _run(psi, c, g, bcs, opts, torch.float64, 3, n_iters=n_iters)
+    assert name == "k_step3d", name
+    assert_parity(out, ref, torch.float64, f"{shape} {bcs} opts={opts} n_iters={n_iters}")
