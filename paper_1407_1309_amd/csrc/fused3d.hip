@@ -114,8 +114,8 @@ __global__ void __launch_bounds__(256) k_donor3d(G3 g, int kahan, int tiles_k, i
 bool fused3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3], const int bc[3])
 {
     (void)bc;
-    // (n_iters = 1: the limiter has nothing to limit)
-    if (nd != 3 || n_iters < 1 || (opts & (OPT_ABS | OPT_DFL))) return false;
+    // (n_iters = 1: the limiter, abs and dfl have nothing to act on)
+    if (nd != 3 || n_iters < 1) return false;
     if (n_iters >= 2) return step3d_supported(nd, n_iters, opts, n);
     return n[0] < (1 << 30) && n[1] < (1 << 30) && n[2] < (1 << 30);
 }

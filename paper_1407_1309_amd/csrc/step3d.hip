@@ -33,6 +33,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace mp {
 namespace {
 
@@ -77,7 +79,7 @@ __device__ __forceinline__ int64_t box_offset(int e, int n_e, int w, int jb, int
     return j * row_len + k;
 }
 
-template <typename T, bool HAS_G, bool IGA, bool TOT, bool XIN>
+template <typename T, bool HAS_G, bool IGA, bool ABS, bool DFL, bool TOT, bool XIN>
 __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int tiles_j, int nblk,
                                                int kahan, const T *__restrict__ x,
                                                const T *__restrict__ c0,
@@ -292,6 +294,8 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         const T *YA = Ys[sA], *YB = Ys[sB], *YC = Ys[sC];
 
         // V0 at wall p+1 (planes p | p+1) of column (bj, bk)
+        // psi value entering a psi-fraction: |psi| under the abs option
+        auto ya = [](T v) -> T { return ABS ? fabs(v) : v; };
         auto vel0 = [&]() -> T {
             const int c = cy;
             T ig = T(1);
@@ -300,7 +304,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 quotients<1>(one, gb, q);
                 ig = q[0];
             }
-            const T xL = YB[c], xR = YC[c];
+            const T xL = ya(YB[c]), xR = ya(YC[c]);
             const T u = C0s[ws1][c];
             T A = fr3<T, IGA>(xR - xL, xR + xL, T(2));
             T v = (fabs(u) - u * u * ig) * A;
@@ -311,13 +315,24 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             const T cb1 = T(0.25) * (s1a + s1b);
             const T cb2 = T(0.25) * (s2a + s2b);
             // o = 1 (j)
-            T a1 = YC[c + BK], b1 = YB[c + BK], e1 = YC[c - BK], f1 = YB[c - BK];
+            T a1 = ya(YC[c + BK]), b1 = ya(YB[c + BK]), e1 = ya(YC[c - BK]), f1 = ya(YB[c - BK]);
             v -= T(0.5) * u * cb1 * ig * fr3<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
             // o = 2 (k)
-            T a2 = YC[c + 1], b2 = YB[c + 1], e2 = YC[c - 1], f2 = YB[c - 1];
+            T a2 = ya(YC[c + 1]), b2 = ya(YB[c + 1]), e2 = ya(YC[c - 1]), f2 = ya(YB[c - 1]);
             v -= T(0.5) * u * cb2 * ig * fr3<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
+            if (DFL) {
+                // divergent-flow term: the mean of the two cells' advector
+                // divergences (planes p and p+1 of the column), times
+                // -c / (2 Gb); under iga times the wall mean of psi
+                const int ws2 = slot4(p + 2);
+                T dv = (C0s[ws1][c] - C0s[ws][c]) + (C0s[ws2][c] - C0s[ws1][c]);
+                dv += (C1s[cs][w1p] - C1s[cs][w1]) + (C1s[cs1][w1p] - C1s[cs1][w1]);
+                dv += (C2s[cs][w2 + 1] - C2s[cs][w2]) + (C2s[cs1][w2 + 1] - C2s[cs1][w2]);
+                if (IGA) dv *= T(0.5) * (xL + xR);
+                v -= T(0.25) * u * ig * dv;
+            }
             if (TOT) {
-                const T xR2 = (open0 && t >= g.n0) ? Ys[sD][c] : y_own, xL2 = YA[c];
+                const T xR2 = (open0 && t >= g.n0) ? ya(Ys[sD][c]) : ya(y_own), xL2 = ya(YA[c]);
                 v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
                      fr3<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
                 v += (fabs(u) * cb1 * ig - T(2) * u * u * cb1 * (ig * ig)) *
@@ -327,8 +342,8 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 T num = T(0), den = T(0);
                 for (int sd = 0; sd < 2; sd++) {
                     const T *Yp = sd ? YC : YB;
-                    T pp_ = Yp[c + BK + 1], mp_ = Yp[c - BK + 1], pm_ = Yp[c + BK - 1],
-                      mm_ = Yp[c - BK - 1];
+                    T pp_ = ya(Yp[c + BK + 1]), mp_ = ya(Yp[c - BK + 1]), pm_ = ya(Yp[c + BK - 1]),
+                      mm_ = ya(Yp[c - BK - 1]);
                     num += pp_ - mp_ - pm_ + mm_;
                     den += pp_ + mp_ + pm_ + mm_;
                 }
@@ -345,7 +360,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 quotients<1>(one, gb, q);
                 ig = q[0];
             }
-            const T xL = YB[c - BK], xR = YB[c];
+            const T xL = ya(YB[c - BK]), xR = ya(YB[c]);
             const T u = C1s[cs][c];
             T A = fr3<T, IGA>(xR - xL, xR + xL, T(2));
             T v = (fabs(u) - u * u * ig) * A;
@@ -353,13 +368,21 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             const int w2 = wj * (BK + 1) + wk, w2m = (wj - 1) * (BK + 1) + wk;
             const T cb2 = T(0.25) * ((C2s[cs][w2m] + C2s[cs][w2m + 1]) + (C2s[cs][w2] + C2s[cs][w2 + 1]));
             // o = 0 (i)
-            T a0 = YC[c], b0 = YC[c - BK], e0 = YA[c], f0 = YA[c - BK];
+            T a0 = ya(YC[c]), b0 = ya(YC[c - BK]), e0 = ya(YA[c]), f0 = ya(YA[c - BK]);
             v -= T(0.5) * u * cb0 * ig * fr3<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
             // o = 2 (k)
-            T a2 = YB[c + 1], b2 = YB[c - BK + 1], e2 = YB[c - 1], f2 = YB[c - BK - 1];
+            T a2 = ya(YB[c + 1]), b2 = ya(YB[c - BK + 1]), e2 = ya(YB[c - 1]), f2 = ya(YB[c - BK - 1]);
             v -= T(0.5) * u * cb2 * ig * fr3<T, IGA>(a2 + b2 - e2 - f2, a2 + b2 + e2 + f2, T(4));
+            if (DFL) {
+                // cells (p, wj-1) and (p, wj)
+                T dv = (C0s[ws1][c - BK] - C0s[ws][c - BK]) + (C0s[ws1][c] - C0s[ws][c]);
+                dv += (C1s[cs][c] - C1s[cs][c - BK]) + (C1s[cs][c + BK] - C1s[cs][c]);
+                dv += (C2s[cs][w2m + 1] - C2s[cs][w2m]) + (C2s[cs][w2 + 1] - C2s[cs][w2]);
+                if (IGA) dv *= T(0.5) * (xL + xR);
+                v -= T(0.25) * u * ig * dv;
+            }
             if (TOT) {
-                const T xR2 = YB[c + BK], xL2 = YB[c - 2 * BK];
+                const T xR2 = ya(YB[c + BK]), xL2 = ya(YB[c - 2 * BK]);
                 v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
                      fr3<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
                 v += (fabs(u) * cb0 * ig - T(2) * u * u * cb0 * (ig * ig)) *
@@ -369,7 +392,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 T num = T(0), den = T(0);
                 for (int sd = 0; sd < 2; sd++) {
                     const int cc = sd ? c : c - BK;
-                    T pp_ = YC[cc + 1], mp_ = YA[cc + 1], pm_ = YC[cc - 1], mm_ = YA[cc - 1];
+                    T pp_ = ya(YC[cc + 1]), mp_ = ya(YA[cc + 1]), pm_ = ya(YC[cc - 1]), mm_ = ya(YA[cc - 1]);
                     num += pp_ - mp_ - pm_ + mm_;
                     den += pp_ + mp_ + pm_ + mm_;
                 }
@@ -386,20 +409,29 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 quotients<1>(one, gb, q);
                 ig = q[0];
             }
-            const T xL = YB[c - 1], xR = YB[c];
+            const T xL = ya(YB[c - 1]), xR = ya(YB[c]);
             const T u = C2s[cs][wj * (BK + 1) + wk];
             T A = fr3<T, IGA>(xR - xL, xR + xL, T(2));
             T v = (fabs(u) - u * u * ig) * A;
             const T cb0 = T(0.25) * ((C0s[ws][c - 1] + C0s[ws1][c - 1]) + (C0s[ws][c] + C0s[ws1][c]));
             const T cb1 = T(0.25) * ((C1s[cs][c - 1] + C1s[cs][c - 1 + BK]) + (C1s[cs][c] + C1s[cs][c + BK]));
             // o = 0 (i)
-            T a0 = YC[c], b0 = YC[c - 1], e0 = YA[c], f0 = YA[c - 1];
+            T a0 = ya(YC[c]), b0 = ya(YC[c - 1]), e0 = ya(YA[c]), f0 = ya(YA[c - 1]);
             v -= T(0.5) * u * cb0 * ig * fr3<T, IGA>(a0 + b0 - e0 - f0, a0 + b0 + e0 + f0, T(4));
             // o = 1 (j)
-            T a1 = YB[c + BK], b1 = YB[c + BK - 1], e1 = YB[c - BK], f1 = YB[c - BK - 1];
+            T a1 = ya(YB[c + BK]), b1 = ya(YB[c + BK - 1]), e1 = ya(YB[c - BK]), f1 = ya(YB[c - BK - 1]);
             v -= T(0.5) * u * cb1 * ig * fr3<T, IGA>(a1 + b1 - e1 - f1, a1 + b1 + e1 + f1, T(4));
+            if (DFL) {
+                // cells (p, wj, wk-1) and (p, wj, wk)
+                const int w2 = wj * (BK + 1) + wk;
+                T dv = (C0s[ws1][c - 1] - C0s[ws][c - 1]) + (C0s[ws1][c] - C0s[ws][c]);
+                dv += (C1s[cs][c - 1 + BK] - C1s[cs][c - 1]) + (C1s[cs][c + BK] - C1s[cs][c]);
+                dv += (C2s[cs][w2] - C2s[cs][w2 - 1]) + (C2s[cs][w2 + 1] - C2s[cs][w2]);
+                if (IGA) dv *= T(0.5) * (xL + xR);
+                v -= T(0.25) * u * ig * dv;
+            }
             if (TOT) {
-                const T xR2 = YB[c + 1], xL2 = YB[c - 2];
+                const T xR2 = ya(YB[c + 1]), xL2 = ya(YB[c - 2]);
                 v += (T(3) * u * fabs(u) * ig - T(2) * u * u * u * (ig * ig) - u) * (T(1) / T(3)) *
                      fr3<T, IGA>(xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4));
                 v += (fabs(u) * cb0 * ig - T(2) * u * u * cb0 * (ig * ig)) *
@@ -409,7 +441,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 T num = T(0), den = T(0);
                 for (int sd = 0; sd < 2; sd++) {
                     const int cc = sd ? c : c - 1;
-                    T pp_ = YC[cc + BK], mp_ = YA[cc + BK], pm_ = YC[cc - BK], mm_ = YA[cc - BK];
+                    T pp_ = ya(YC[cc + BK]), mp_ = ya(YA[cc + BK]), pm_ = ya(YC[cc - BK]), mm_ = ya(YA[cc - BK]);
                     num += pp_ - mp_ - pm_ + mm_;
                     den += pp_ + mp_ + pm_ + mm_;
                 }
@@ -517,7 +549,7 @@ bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3])
 {
     // (with the limiter or more than two passes the kernel runs pass by
     // pass in output mode, see fused3d_step)
-    if (nd != 3 || n_iters < 2 || (opts & (OPT_ABS | OPT_DFL))) return false;
+    if (nd != 3 || n_iters < 2) return false;
     // 32-bit plane and row indices inside the kernel
     if (n[0] >= (1 << 30) || n[1] >= (1 << 30) || n[2] >= (1 << 30)) return false;
     return true;
@@ -536,26 +568,35 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
     const int64_t blocks = (int64_t)tiles_k * tiles_j * chunks;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
-    const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
-#define MP_S3(HG, IG, TO)                                                                     \
-    do {                                                                                      \
-        if (vo.xin)                                                                           \
-            k_step3d<T, HG, IG, TO, true><<<(unsigned)blocks, NT, 0, s>>>(                    \
-                g, th, tiles_k, tiles_j, (int)blocks, kahan, psi_n, c0, c1, c2, G, psi_out,   \
-                vo);                                                                          \
-        else                                                                                  \
-            k_step3d<T, HG, IG, TO, false><<<(unsigned)blocks, NT, 0, s>>>(                   \
-                g, th, tiles_k, tiles_j, (int)blocks, kahan, psi_n, c0, c1, c2, G, psi_out,   \
-                vo);                                                                          \
-    } while (0)
-    if (G) {
-        if (iga) { if (tot) MP_S3(true, true, true); else MP_S3(true, true, false); }
-        else { if (tot) MP_S3(true, false, true); else MP_S3(true, false, false); }
-    } else {
-        if (iga) { if (tot) MP_S3(false, true, true); else MP_S3(false, true, false); }
-        else { if (tot) MP_S3(false, false, true); else MP_S3(false, false, false); }
-    }
-#undef MP_S3
+    const bool iga = opts & OPT_IGA, absf = opts & OPT_ABS, dfl = opts & OPT_DFL,
+               tot = opts & OPT_TOT;
+    auto go = [&](auto HG, auto IG, auto AB, auto DF, auto TO, auto XI) {
+        k_step3d<T, decltype(HG)::value, decltype(IG)::value, decltype(AB)::value,
+                 decltype(DF)::value, decltype(TO)::value, decltype(XI)::value>
+            <<<(unsigned)blocks, NT, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, kahan, psi_n,
+                                             c0, c1, c2, G, psi_out, vo);
+    };
+    using TT = std::true_type;
+    using FF = std::false_type;
+    auto by_x = [&](auto HG, auto IG, auto AB, auto DF, auto TO) {
+        if (vo.xin) go(HG, IG, AB, DF, TO, TT{});
+        else go(HG, IG, AB, DF, TO, FF{});
+    };
+    auto by_t = [&](auto HG, auto IG, auto AB, auto DF) {
+        if (tot) by_x(HG, IG, AB, DF, TT{});
+        else by_x(HG, IG, AB, DF, FF{});
+    };
+    auto by_d = [&](auto HG, auto IG, auto AB) {
+        if (dfl) by_t(HG, IG, AB, TT{});
+        else by_t(HG, IG, AB, FF{});
+    };
+    auto by_m = [&](auto HG) {       // psi-fractions: plain, infinite gauge or |psi|
+        if (iga) by_d(HG, TT{}, FF{});
+        else if (absf) by_d(HG, FF{}, TT{});
+        else by_d(HG, FF{}, FF{});
+    };
+    if (G) by_m(TT{});
+    else by_m(FF{});
     return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ FCT, IGA, TOT, DFL, ABS = (mpdata.OPT_FCT, mpdata.OPT_IGA, mpdata.OPT_TOT, mpdat
 
 # (shape, bc, n_iters, opts, kernel family)
 PATHS = [((128, 96), 0, 3, FCT, "k_fused2d"), ((96, 130), 1, 2, IGA | FCT | DFL, "k_pass2d"),
-         ((20, 18, 70), 1, 3, FCT, "k_step3d"), ((20, 18, 70), 1, 3, ABS | FCT, "staged step"),
+         ((20, 18, 70), 1, 3, FCT, "k_step3d"), ((20, 18, 70), 1, 3, ABS | FCT, "k_step3d"),
+         ((96, 130), 1, 1, 0, "staged step"),
          ((300,), 0, 2, FCT, "k_resident1d"), ((12, 20, 70), 0, 2, IGA | TOT, "k_step3d")]
 
 

@@ -94,7 +94,8 @@ for shape in [(300,), (150, 197), (37, 29, 41)]:
 @pytest.mark.parametrize("shape,bc,opts", ABS_CASES)
 def test_parity_abs(shape, bc, opts, dtype):
     """abs option (|psi| in the psi-fractions) on variable-sign fields through
-    the staged, fused 2-D and resident 1-D kernels, with and without G."""
+    the staged, fused 2-D, one-pass 2-D, 3-D and resident 1-D kernels, with
+    and without G."""
     for with_g in (False, True):
         psi, c, g = _inputs(shape, bc, opts, seed=len(shape) * 100 + bc * 10 + opts + with_g,
                             with_g=with_g)
@@ -116,9 +117,9 @@ for shape in [(300,), (150, 197), (37, 29, 41)]:
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 @pytest.mark.parametrize("shape,bc,opts", DFL_CASES)
 def test_parity_dfl(shape, bc, opts, dtype):
-    """Divergent-flow term through the staged and resident 1-D kernels, on
-    divergent (open) and non-divergent (periodic) advectors, with and
-    without G."""
+    """Divergent-flow term through the staged, one-pass 2-D, 3-D and
+    resident 1-D kernels, on divergent (open) and non-divergent (periodic)
+    advectors, with and without G."""
     n_iters = 2 if opts & IGA else 3
     for with_g in (False, True):
         psi, c, g = _inputs(shape, bc, opts, seed=len(shape) * 100 + bc * 10 + opts + with_g,
@@ -430,7 +431,8 @@ def test_parity_1d_resident(opts, bc, dtype):
 
 F3_CASES = []
 for shape, bc in [((9, 37, 130), 1), ((10, 16, 64), 0), ((7, 45, 70), 0), ((12, 20, 67), 1)]:
-    for n_iters, opts in [(1, 0), (2, 0), (2, TOT), (2, IGA), (2, IGA | TOT), (2, IGA | TOT | 32)]:
+    for n_iters, opts in [(1, 0), (2, 0), (2, TOT), (2, IGA), (2, IGA | TOT), (2, IGA | TOT | 32),
+                          (2, 8), (2, 8 | TOT), (2, 16), (2, 16 | IGA | TOT), (1, 8 | 16)]:
         F3_CASES.append((shape, bc, n_iters, opts))
 
 

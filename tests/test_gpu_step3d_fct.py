@@ -5,7 +5,9 @@ then the limiter coefficients and the limited corrective pass run as two
 cell kernels (without the limiter, the corrective pass alone).  Against the oracle
 (every element within the element-wise bar): every option mix with and
 without G, both boundary types and mixed ones, tiles and plane chunks with
-ragged tails, FP64 and FP32, and a larger grid."""
+ragged tails, FP64 and FP32, and a larger grid; the abs option (|psi| in
+the psi-fractions, on variable-sign fields) and the divergent-flow term
+included."""
 import numpy as np
 import pytest
 import torch
@@ -16,6 +18,7 @@ from tests.gpu_util import as_dtype, assert_parity, dev, rel_l2
 
 pytestmark = pytest.mark.gpu
 FCT, IGA, TOT, KAHAN = mpdata.OPT_FCT, mpdata.OPT_IGA, mpdata.OPT_TOT, mpdata.OPT_KAHAN
+ABS, DFL = mpdata.OPT_ABS, mpdata.OPT_DFL
 
 
 def _case(shape, bcs, opts, with_g, seed):
@@ -29,8 +32,9 @@ def _case(shape, bcs, opts, with_g, seed):
             hi[d], lo[d] = -1, 0
             c[d][tuple(hi)] = c[d][tuple(lo)]
     m = min(shape)
-    psi = synth.blob_field(shape, 4, (m / 6, m / 3), "normal" if opts & IGA else "uniform", gen,
-                           periodic=False) + (0.0 if opts & IGA else 0.05)
+    signed = opts & (IGA | ABS)
+    psi = synth.blob_field(shape, 4, (m / 6, m / 3), "normal" if signed else "uniform", gen,
+                           periodic=False) + (0.0 if signed else 0.05)
     return psi, c, g
 
 
@@ -46,7 +50,8 @@ def _run(psi, c, g, bcs, opts, dtype, n_steps, kernel=mpdata.KERNEL_AUTO, n_iter
     return p.double().cpu().numpy(), name
 
 
-OPTS = [FCT, FCT | IGA, FCT | TOT, FCT | TOT | IGA, FCT | KAHAN, FCT | TOT | IGA | KAHAN]
+OPTS = [FCT, FCT | IGA, FCT | TOT, FCT | TOT | IGA, FCT | KAHAN, FCT | TOT | IGA | KAHAN,
+        FCT | ABS, FCT | ABS | TOT, FCT | DFL, FCT | DFL | TOT | IGA]
 CASES = [((12, 11, 10), (1, 1, 1)), ((37, 45, 70), (1, 1, 1)), ((20, 33, 65), (0, 0, 0)),
          ((23, 17, 40), (1, 0, 1)), ((200, 20, 33), (0, 1, 0))]
 
@@ -92,7 +97,8 @@ def test_step3d_fct_close_to_staged():
 
 @pytest.mark.parametrize("n_iters", [3, 4])
 @pytest.mark.parametrize("with_g", [False, True], ids=["g1", "g"])
-@pytest.mark.parametrize("opts", [0, FCT, TOT, FCT | TOT, FCT | KAHAN])
+@pytest.mark.parametrize("opts", [0, FCT, TOT, FCT | TOT, FCT | KAHAN, ABS | FCT, DFL | FCT,
+                                  DFL | TOT])
 @pytest.mark.parametrize("shape,bcs", [((23, 17, 40), (1, 0, 1)), ((130, 21, 34), (0, 0, 0)),
                                        ((15, 36, 33), (1, 1, 1))],
                          ids=lambda v: "x".join(map(str, v)))
