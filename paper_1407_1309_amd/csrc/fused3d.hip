@@ -1,6 +1,8 @@
 // fused3d.hip -- the 3-D donor-cell step (n_iters = 1) in one launch, and
-// the dispatch of the 3-D steps: two passes without the limiter go to the
-// one-launch kernel of step3d.hip.
+// the dispatch of the 3-D steps: two passes without the limiter are one
+// launch of the kernel of step3d.hip; with the limiter, or more passes, the
+// same kernel forms each pass's raw pseudo-velocities and the cell kernels
+// of staged.hip apply the limiter and the corrective pass, pass by pass.
 //
 //   k_donor3d : donor-cell pass, psi^n -> y.  Each thread owns a (j, k)
 //               column and marches along i over a chunk of planes, keeping
