@@ -453,13 +453,14 @@ __global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, con
     }
 }
 
-// 2-D boundary map with compile-time boundary types (coordinates at most two
-// periods outside the range: the halo of a one-cell-wide dimension) and
-// 32-bit flat indices (n0 n1 < 2^31)
+// 2-D boundary map with compile-time boundary types and 32-bit flat indices
+// (n0 n1 < 2^31).  The tiled kernels read coordinates from -2 to n + 1
+// (a tile's ring of one cell and its neighbours), which one period's shift
+// brings into range when a periodic extent is at least 3 (as every plan
+// requires, and the launchers check).
 template <int BC> __device__ __forceinline__ int wc2(int q, int n)
 {
     if constexpr (BC == BC_PERIODIC) {
-        q = q < 0 ? q + n : (q >= n ? q - n : q);
         return q < 0 ? q + n : (q >= n ? q - n : q);
     } else {
         return q < 0 ? 0 : (q >= n ? n - 1 : q);
@@ -468,7 +469,6 @@ template <int BC> __device__ __forceinline__ int wc2(int q, int n)
 template <int BC> __device__ __forceinline__ int ww2(int f, int n)
 {
     if constexpr (BC == BC_PERIODIC) {
-        f = f < 0 ? f + n : (f >= n ? f - n : f);
         return f < 0 ? f + n : (f >= n ? f - n : f);
     } else {
         return f < 0 ? 0 : (f > n ? n : f);
@@ -590,15 +590,22 @@ k_pseudo_adj2g(Geom gg, unsigned opts, const T *__restrict__ x, const T *c0, con
     __syncthreads();
     const int qi = i0 + (int)threadIdx.x / GC, qj = j0 + (int)threadIdx.x % GC;
     if (qi >= n0 || qj >= n1) return;
-    // coefficient kind r of the wall at unmapped (i, j); zero outside the box
-    auto k0 = [&](int r, int i, int j) -> T {
+    // coefficient kind r of the wall at unmapped (i, j); zero outside the
+    // box.  The cell's own position and its neighbours are always inside
+    // (unchecked reads, CK false); only the positions past an open edge can
+    // fall outside.
+    auto k0 = [&](auto CK, int r, int i, int j) -> T {
         const int a = i - i0, b = j - (j0 - 1);
+        if (!decltype(CK)::value) return K0[r][a * Q0C + b];
         return (a >= 0 && a < Q0R && b >= 0 && b < Q0C) ? K0[r][a * Q0C + b] : T(0);
     };
-    auto k1 = [&](int r, int i, int j) -> T {
+    auto k1 = [&](auto CK, int r, int i, int j) -> T {
         const int a = i - (i0 - 1), b = j - j0;
+        if (!decltype(CK)::value) return K1[r][a * Q1C + b];
         return (a >= 0 && a < Q1R && b >= 0 && b < Q1C) ? K1[r][a * Q1C + b] : T(0);
     };
+    using Un = std::false_type;
+    using Ck = std::true_type;
     // the unmapped positions the boundary map sends to row qi / column qj:
     // the cell itself, and past an open edge the position beyond it
     int pr[3], pc[3], nr = 0, nc = 0;
@@ -609,42 +616,52 @@ k_pseudo_adj2g(Geom gg, unsigned opts, const T *__restrict__ x, const T *c0, con
     if (BC1 == BC_OPEN && qj == 0) pc[nc++] = -1;
     if (BC1 == BC_OPEN && qj == n1 - 1) pc[nc++] = n1;
     // the cell: every role of every wall that lands on it
+    auto roles = [&](auto CK, int X0, int X1, T &acc) {
+        acc += k0(CK, KR, X0, X1) + k0(CK, KL, X0 + 1, X1);              // A term, d = 0
+        acc += k0(CK, KP, X0, X1 - 1) + k0(CK, KP, X0 + 1, X1 - 1);      // B term, +o side
+        acc += k0(CK, KM, X0, X1 + 1) + k0(CK, KM, X0 + 1, X1 + 1);      // B term, -o side
+        acc += k1(CK, KR, X0, X1) + k1(CK, KL, X0, X1 + 1);              // A term, d = 1
+        acc += k1(CK, KP, X0 - 1, X1) + k1(CK, KP, X0 - 1, X1 + 1);
+        acc += k1(CK, KM, X0 + 1, X1) + k1(CK, KM, X0 + 1, X1 + 1);
+    };
     T acc = T(0);
+    roles(Un{}, qi, qj, acc);
     for (int s = 0; s < nr; s++)
-        for (int t = 0; t < nc; t++) {
-            const int X0 = pr[s], X1 = pc[t];
-            acc += k0(KR, X0, X1) + k0(KL, X0 + 1, X1);                  // A term, d = 0
-            acc += k0(KP, X0, X1 - 1) + k0(KP, X0 + 1, X1 - 1);          // B term, +o side
-            acc += k0(KM, X0, X1 + 1) + k0(KM, X0 + 1, X1 + 1);          // B term, -o side
-            acc += k1(KR, X0, X1) + k1(KL, X0, X1 + 1);                  // A term, d = 1
-            acc += k1(KP, X0 - 1, X1) + k1(KP, X0 - 1, X1 + 1);
-            acc += k1(KM, X0 + 1, X1) + k1(KM, X0 + 1, X1 + 1);
-        }
+        for (int t = 0; t < nc; t++)
+            if (s > 0 || t > 0) roles(Ck{}, pr[s], pc[t], acc);
     xb[(int64_t)qi * n1 + qj] += acc;
     // owned dimension-0 walls: the cell's low wall, and at an open far edge
     // the edge wall; own term plus the cross terms of the dimension-1 walls
     // whose cross-advector mean reads them
-    for (int w = 0; w < 2; w++) {
-        const int Y0 = w == 0 ? qi : n0;
-        if (w == 1 && !(BC0 == BC_OPEN && qi == n0 - 1)) continue;
-        T v = k0(KU, Y0, qj);
-        for (int t = 0; t < nc; t++) {
-            const int Z1 = pc[t];
-            v += k1(KQ, Y0, Z1 + 1) + k1(KQ, Y0 - 1, Z1 + 1) + k1(KQ, Y0, Z1) +
-                 k1(KQ, Y0 - 1, Z1);
-        }
-        cb0[(int64_t)Y0 * n1 + qj] += v;
+    auto cross0 = [&](auto CK, int Y0, int Z1) {
+        return k1(CK, KQ, Y0, Z1 + 1) + k1(CK, KQ, Y0 - 1, Z1 + 1) + k1(CK, KQ, Y0, Z1) +
+               k1(CK, KQ, Y0 - 1, Z1);
+    };
+    {
+        T v = k0(Un{}, KU, qi, qj);
+        v += cross0(Un{}, qi, qj);
+        for (int t = 1; t < nc; t++) v += cross0(Ck{}, qi, pc[t]);
+        cb0[(int64_t)qi * n1 + qj] += v;
     }
-    for (int w = 0; w < 2; w++) {
-        const int Y1 = w == 0 ? qj : n1;
-        if (w == 1 && !(BC1 == BC_OPEN && qj == n1 - 1)) continue;
-        T v = k1(KU, qi, Y1);
-        for (int s = 0; s < nr; s++) {
-            const int Z0 = pr[s];
-            v += k0(KQ, Z0 + 1, Y1) + k0(KQ, Z0 + 1, Y1 - 1) + k0(KQ, Z0, Y1) +
-                 k0(KQ, Z0, Y1 - 1);
-        }
-        cb1[(int64_t)qi * (n1 + 1) + Y1] += v;
+    if (BC0 == BC_OPEN && qi == n0 - 1) {
+        T v = k0(Ck{}, KU, n0, qj);
+        for (int t = 0; t < nc; t++) v += cross0(Ck{}, n0, pc[t]);
+        cb0[(int64_t)n0 * n1 + qj] += v;
+    }
+    auto cross1 = [&](auto CK, int Z0, int Y1) {
+        return k0(CK, KQ, Z0 + 1, Y1) + k0(CK, KQ, Z0 + 1, Y1 - 1) + k0(CK, KQ, Z0, Y1) +
+               k0(CK, KQ, Z0, Y1 - 1);
+    };
+    {
+        T v = k1(Un{}, KU, qi, qj);
+        v += cross1(Un{}, qi, qj);
+        for (int s = 1; s < nr; s++) v += cross1(Ck{}, pr[s], qj);
+        cb1[(int64_t)qi * (n1 + 1) + qj] += v;
+    }
+    if (BC1 == BC_OPEN && qj == n1 - 1) {
+        T v = k1(Ck{}, KU, qi, n1);
+        for (int s = 0; s < nr; s++) v += cross1(Ck{}, pr[s], n1);
+        cb1[(int64_t)qi * (n1 + 1) + n1] += v;
     }
 }
 
@@ -1244,9 +1261,18 @@ void pseudo_adj_dispatch(const Geom &g, int d, unsigned blocks, hipStream_t s, u
 }
 
 // 2-D without third-order terms: both wall dimensions in one launch
+// (periodic extents of at least 3: the tiled kernels' boundary map wraps
+// once)
+bool tiled2_extents(const Geom &g)
+{
+    for (int d = 0; d < 2; d++)
+        if (g.bc[d] == BC_PERIODIC && g.n[d] < 3) return false;
+    return (g.n[0] + 1) * (g.n[1] + 1) < ((int64_t)1 << 31);
+}
+
 bool pseudo_adj_both(const Geom &g, unsigned opts)
 {
-    return g.nd == 2 && !(opts & OPT_TOT) && (g.n[0] + 1) * (g.n[1] + 1) < ((int64_t)1 << 31);
+    return g.nd == 2 && !(opts & OPT_TOT) && tiled2_extents(g);
 }
 
 template <typename T>
@@ -1268,7 +1294,7 @@ void pseudo_adj2_launch(const Geom &g, hipStream_t s, unsigned opts, const T *x,
 // true if the 2-D one-launch limiter transpose applies
 bool limiter_adj_tiled(const Geom &g)
 {
-    return g.nd == 2 && (g.n[0] + 1) * (g.n[1] + 1) < ((int64_t)1 << 31);
+    return g.nd == 2 && tiled2_extents(g);
 }
 
 // transposes of the limiter (limited velocities, then coefficients), each
