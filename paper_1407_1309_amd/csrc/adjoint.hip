@@ -1122,6 +1122,13 @@ k_limiter_adj2g(Geom gg, unsigned opts, const T *__restrict__ psi_n, const T *__
     const int nn[2] = {n0, n1};
     const bool op[2] = {BC0 == BC_OPEN, BC1 == BC_OPEN};
     T ax = own_x, ap = T(0);
+    // Away from an open edge the boundary map sends no neighbour of a
+    // neighbour onto the cell (periodic extents are at least 3), so a bound
+    // slot of neighbour k points at the cell exactly when it is the slot
+    // back along k's offset; at an open edge the clamped positions are
+    // compared.
+    const bool edge = (op[0] && (q.v[0] == 0 || q.v[0] == n0 - 1)) ||
+                      (op[1] && (q.v[1] == 0 || q.v[1] == n1 - 1));
     // bounds: the cell itself, then its face neighbours (-e0, +e0, -e1, +e1)
 #pragma unroll
     for (int k = 0; k < 5; k++) {
@@ -1135,18 +1142,21 @@ k_limiter_adj2g(Geom gg, unsigned opts, const T *__restrict__ psi_n, const T *__
         }
         const int cd = Ecd[ic];
         const int smx = cd & 7, smn = (cd >> 4) & 7;
+        // slot back to the cell from neighbour k: 0, then +e0, -e0, +e1, -e1
+        constexpr int back[5] = {0, 2, 1, 4, 3};
         // the cell a bound slot of c points at (selects: no indexing of c by a
         // run-time dimension)
         auto target = [&](int slot) {
+            if (!edge) return slot == back[k];
             const int ti = c.v[0] + (slot == 1 ? -1 : (slot == 2 ? 1 : 0));
             const int tj = c.v[1] + (slot == 3 ? -1 : (slot == 4 ? 1 : 0));
-            return g.cell(I3{{ti, tj, 0}});
+            return g.cell(I3{{ti, tj, 0}}) == kq;
         };
-        if (target(smx) == kq) {
+        if (target(smx)) {
             if (cd & 8) ax += Emx[ic];
             else ap += Emx[ic];
         }
-        if (target(smn) == kq) {
+        if (target(smn)) {
             if (cd & 128) ax += Emn[ic];
             else ap += Emn[ic];
         }

@@ -252,7 +252,8 @@ def test_degenerate_cases(shape, bc):
     nd = len(shape)
     gen = synth.rng(81)
     walls = [tuple(n + (1 if e == d else 0) for e, n in enumerate(shape)) for d in range(nd)]
-    for opts in (0, FCT, TOT | FCT, IGA | TOT, mpdata.OPT_KAHAN | FCT):
+    for opts in (0, FCT, TOT | FCT, IGA | TOT, mpdata.OPT_KAHAN | FCT, mpdata.OPT_ABS | FCT,
+                 mpdata.OPT_DFL | FCT):
         n_iters = 2 if opts & IGA else 3
         # psi == 0 stays 0 exactly
         c = [gen.uniform(-0.2 / nd, 0.2 / nd, size=w) for w in walls]
