@@ -273,6 +273,95 @@ __global__ void __launch_bounds__(256) k_fct_beta(Geom g, unsigned opts, const T
     bdn[t] = fout > T(0) ? Gi * (xi - mn) / fout : T(1);
 }
 
+// 3-D limiter coefficients, the arithmetic of k_fct_beta term by term, with
+// one thread per (j, k) column marching along i over BETA_PLANES planes:
+// psi^n and x of the planes i-1, i, i+1 and the dimension-0 walls stay in
+// registers (read once per plane instead of once per neighbour), the
+// in-plane neighbours come through L1/L2, and no flat index is divided
+// back into coordinates.  Blocks of 64 (k) x 4 (j) columns, numbered so
+// that each XCD runs a contiguous range of tiles (see fused3d.hip).
+constexpr int BETA_PLANES = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fct_beta3d(Geom g, unsigned opts, int tiles_k, int tiles_j, int nblk,
+             const T *__restrict__ psi_n, const T *__restrict__ x, const T *__restrict__ V0,
+             const T *__restrict__ V1, const T *__restrict__ V2, const T *__restrict__ G,
+             T *__restrict__ bup, T *__restrict__ bdn)
+{
+    int b;
+    {
+        const int xcd = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
+        b = xcd * per + (xcd < rem ? xcd : rem) + (blockIdx.x >> 3);
+    }
+    const int tk = b % tiles_k;
+    b /= tiles_k;
+    const int tj = b % tiles_j;
+    const int ch = b / tiles_j;
+    const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
+    const int k = tk * 64 + (threadIdx.x & 63);
+    const int j = tj * 4 + (threadIdx.x >> 6);
+    const int i0 = ch * BETA_PLANES;
+    const int i1 = min(i0 + BETA_PLANES, n0);
+    if (k >= n2 || j >= n1) return;
+    const bool iga = opts & OPT_IGA;
+    const int64_t pl = (int64_t)n1 * n2, pl1 = (int64_t)(n1 + 1) * n2,
+                  pl2 = (int64_t)n1 * (n2 + 1);
+    // in-plane offsets of the column and its neighbours (boundary-mapped)
+    const int64_t o = (int64_t)j * n2 + k;
+    const int64_t ojm = (int64_t)wrap_cell(j - 1, n1, g.bc[1]) * n2 + k;
+    const int64_t ojp = (int64_t)wrap_cell(j + 1, n1, g.bc[1]) * n2 + k;
+    const int64_t okm = (int64_t)j * n2 + wrap_cell(k - 1, n2, g.bc[2]);
+    const int64_t okp = (int64_t)j * n2 + wrap_cell(k + 1, n2, g.bc[2]);
+    const int64_t w1lo = (int64_t)j * n2 + k;
+    const int64_t w1hi = (int64_t)wrap_wall(j + 1, n1, g.bc[1]) * n2 + k;
+    const int64_t w2lo = (int64_t)j * (n2 + 1) + k;
+    const int64_t w2hi = (int64_t)j * (n2 + 1) + wrap_wall(k + 1, n2, g.bc[2]);
+
+    const int64_t im = (int64_t)wrap_cell(i0 - 1, n0, g.bc[0]) * pl;
+    T pm = psi_n[im + o], xm = x[im + o];
+    T pc = psi_n[i0 * pl + o], xc = x[i0 * pl + o];
+    T v0lo = V0[(int64_t)wrap_wall(i0, n0, g.bc[0]) * pl + o];
+    for (int i = i0; i < i1; i++) {
+        const int64_t ic = (int64_t)i * pl;
+        const int64_t ip = (int64_t)wrap_cell(i + 1, n0, g.bc[0]) * pl;
+        const T pp = psi_n[ip + o], xp = x[ip + o];
+        const T v0hi = V0[(int64_t)wrap_wall(i + 1, n0, g.bc[0]) * pl + o];
+        const T xjm = x[ic + ojm], xjp = x[ic + ojp], xkm = x[ic + okm], xkp = x[ic + okp];
+        const T xi = xc;
+        T mx = pc, mn = mx;
+        mx = fmax(mx, xi);
+        mn = fmin(mn, xi);
+        // face neighbours in the order -e0, +e0, -e1, +e1, -e2, +e2
+        const T na[6] = {pm, pp, psi_n[ic + ojm], psi_n[ic + ojp], psi_n[ic + okm],
+                         psi_n[ic + okp]};
+        const T nb[6] = {xm, xp, xjm, xjp, xkm, xkp};
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            mx = fmax(fmax(mx, na[q]), nb[q]);
+            mn = fmin(fmin(mn, na[q]), nb[q]);
+        }
+        const T vlo[3] = {v0lo, V1[(int64_t)i * pl1 + w1lo], V2[(int64_t)i * pl2 + w2lo]};
+        const T vhi[3] = {v0hi, V1[(int64_t)i * pl1 + w1hi], V2[(int64_t)i * pl2 + w2hi]};
+        T fin = T(0), fout = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const T wm = iga ? T(1) : nb[2 * d], wp = iga ? T(1) : nb[2 * d + 1];
+            const T wi = iga ? T(1) : xi;
+            fin += pos(vlo[d]) * wm - neg(vhi[d]) * wp;
+            fout += pos(vhi[d]) * wi - neg(vlo[d]) * wi;
+        }
+        const T Gi = G ? G[ic + o] : T(1);
+        bup[ic + o] = fin > T(0) ? Gi * (mx - xi) / fin : T(1);
+        bdn[ic + o] = fout > T(0) ? Gi * (xi - mn) / fout : T(1);
+        pm = pc;
+        pc = pp;
+        xm = xc;
+        xc = xp;
+        v0lo = v0hi;
+    }
+}
+
 // limited pseudo-velocity at every dimension-d wall
 template <typename T, int ND, int WD>
 __global__ void __launch_bounds__(256) k_fct_limit(Geom g, const T *__restrict__ V, const T *__restrict__ bup,
@@ -426,15 +515,29 @@ hipError_t launch_pseudo(const Geom &g, unsigned opts, const T *x, const T *cons
 }
 
 template <typename T>
-hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
-                      const T *const V[3], const T *G, T *bup, T *bdn, T *const W[3],
-                      hipStream_t s)
+void fct_beta_launch(const Geom &g, unsigned opts, const T *psi_n, const T *x,
+                     const T *const V[3], const T *G, T *bup, T *bdn, hipStream_t s)
 {
-    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    const int64_t tk = cdiv(g.n[2], 64), tj = cdiv(g.n[1], 4);
+    const int64_t nb = tk * tj * cdiv(g.n[0], BETA_PLANES);
+    if (g.nd == 3 && nb <= INT32_MAX) {
+        k_fct_beta3d<T><<<(unsigned)nb, 256, 0, s>>>(g, opts, (int)tk, (int)tj, (int)nb, psi_n,
+                                                       x, V[0], V[1], V[2], G, bup, bdn);
+        return;
+    }
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
     with_nd(g.nd, [&](auto ND) {
         k_fct_beta<T, decltype(ND)::value><<<(unsigned)cdiv(N, 256), 256, 0, s>>>(
             g, opts, psi_n, x, V[0], V[1], V[2], G, bup, bdn);
     });
+}
+
+template <typename T>
+hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
+                      const T *const V[3], const T *G, T *bup, T *bdn, T *const W[3],
+                      hipStream_t s)
+{
+    fct_beta_launch<T>(g, opts, psi_n, x, V, G, bup, bdn, s);
     for (int d = 0; d < g.nd; d++) {
         unsigned wb = (unsigned)cdiv(wall_count<T>(g, d), 256);
         with_nd_d(g.nd, d, [&](auto ND, auto WD) {
@@ -453,9 +556,9 @@ hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, cons
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
     const unsigned cb = (unsigned)cdiv(N, 256);
     const int mode = ((opts & OPT_IGA) ? 1 : 0) | ((opts & OPT_KAHAN) ? 2 : 0);
+    fct_beta_launch<T>(g, opts, psi_n, x, V, G, bup, bdn, s);
     with_nd(g.nd, [&](auto ND) {
         constexpr int nd = decltype(ND)::value;
-        k_fct_beta<T, nd><<<cb, 256, 0, s>>>(g, opts, psi_n, x, V[0], V[1], V[2], G, bup, bdn);
         k_limcorr<T, nd><<<cb, 256, 0, s>>>(g, x, V[0], V[1], V[2], bup, bdn, G, mode, y, W[0],
                                             W[1], W[2]);
     });
