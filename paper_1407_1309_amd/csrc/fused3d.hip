@@ -153,6 +153,12 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
             vo.v0 = w.wall[vs][0];
             vo.v1 = w.wall[vs][1];
             vo.v2 = w.wall[vs][2];
+            // pass 2 with the limiter: the same launch forms the coefficients
+            const bool beta_in = fct && !x;
+            if (beta_in) {
+                vo.bup = w.bup;
+                vo.bdn = w.bdn;
+            }
             hipError_t e = step3d_launch<T>(geom, opts & ~OPT_FCT, psi_n, nullptr, adv[0], adv[1],
                                             adv[2], G, tile_planes, s, vo);
             if (e != hipSuccess) return e;
@@ -165,7 +171,9 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
                     for (int d = 0; d < 3; d++) W[d] = w.wall[as][d];
                 // (the next pass's advector W stays in wall[as]; its raw
                 // velocities go to the set that held V)
-                e = fct_correct_launch<T>(geom, opts, psi_n, xp, V, G, w.bup, w.bdn, y, W, s);
+                e = beta_in ? limcorr_launch<T>(geom, opts, xp, V, G, w.bup, w.bdn, y, W, s)
+                            : fct_correct_launch<T>(geom, opts, psi_n, xp, V, G, w.bup, w.bdn, y,
+                                                    W, s);
                 for (int d = 0; d < 3; d++) adv[d] = W[d];
             } else {
                 e = launch_donor<T>(geom, xp, V, G, mode, y, s);

@@ -85,10 +85,12 @@ int64_t fused2d_max_parts(int64_t n0, int64_t n1, int n_iters, unsigned opts, in
 // xin (and c0..c2 are that pass's advector) instead of formed by the donor
 // pass; v0 non-NULL (output mode): instead of the corrective pass, the raw
 // pseudo-velocities v0, v1, v2 (walls, n_d + 1 along d) and, when y1 is
-// non-NULL, the donor result y1 are written.
+// non-NULL, the donor result y1 are written; bup / bdn non-NULL (output
+// mode without xin): the limiter coefficients of the pass as well (cells).
 template <typename T> struct Step3dOut {
     const T *xin = nullptr;
     T *y1 = nullptr, *v0 = nullptr, *v1 = nullptr, *v2 = nullptr;
+    T *bup = nullptr, *bdn = nullptr;
 };
 bool step3d_supported(int nd, int n_iters, unsigned opts, const int64_t n[3]);
 template <typename T>
@@ -113,6 +115,11 @@ template <typename T>
 hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, const T *x,
                               const T *const V[3], const T *G, T *bup, T *bdn, T *y,
                               T *const W[3], hipStream_t s);
+// the second half alone, from coefficients already formed
+template <typename T>
+hipError_t limcorr_launch(const Geom &g, unsigned opts, const T *x, const T *const V[3],
+                          const T *G, const T *bup, const T *bdn, T *y, T *const W[3],
+                          hipStream_t s);
 
 // ---- one corrective pass of a 2-D step in one launch (pass2d.hip) --------
 // no third-order terms, any boundaries; x: previous pass's result, c0/c1:

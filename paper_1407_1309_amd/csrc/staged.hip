@@ -553,10 +553,18 @@ hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, cons
                               const T *const V[3], const T *G, T *bup, T *bdn, T *y,
                               T *const W[3], hipStream_t s)
 {
+    fct_beta_launch<T>(g, opts, psi_n, x, V, G, bup, bdn, s);
+    return limcorr_launch<T>(g, opts, x, V, G, bup, bdn, y, W, s);
+}
+
+template <typename T>
+hipError_t limcorr_launch(const Geom &g, unsigned opts, const T *x, const T *const V[3],
+                          const T *G, const T *bup, const T *bdn, T *y, T *const W[3],
+                          hipStream_t s)
+{
     const int64_t N = g.n[0] * g.n[1] * g.n[2];
     const unsigned cb = (unsigned)cdiv(N, 256);
     const int mode = ((opts & OPT_IGA) ? 1 : 0) | ((opts & OPT_KAHAN) ? 2 : 0);
-    fct_beta_launch<T>(g, opts, psi_n, x, V, G, bup, bdn, s);
     with_nd(g.nd, [&](auto ND) {
         constexpr int nd = decltype(ND)::value;
         k_limcorr<T, nd><<<cb, 256, 0, s>>>(g, x, V[0], V[1], V[2], bup, bdn, G, mode, y, W[0],
@@ -575,7 +583,10 @@ hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, cons
                                       hipStream_t);                                           \
     template hipError_t fct_correct_launch<T>(const Geom &, unsigned, const T *, const T *,    \
                                               const T *const[3], const T *, T *, T *, T *,     \
-                                              T *const[3], hipStream_t);
+                                              T *const[3], hipStream_t);                       \
+    template hipError_t limcorr_launch<T>(const Geom &, unsigned, const T *, const T *const[3], \
+                                          const T *, const T *, const T *, T *, T *const[3],   \
+                                          hipStream_t);
 MP_INST(float)
 MP_INST(double)
 #undef MP_INST

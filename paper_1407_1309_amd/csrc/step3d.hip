@@ -64,6 +64,12 @@ template <typename T, bool IGA> __device__ __forceinline__ T fr3(T num, T den, T
 // ring slot of a virtual plane index t >= -12
 __device__ __forceinline__ int slot3(int t) { return (t + 12) % 3; }
 __device__ __forceinline__ int slot4(int t) { return (t + 12) & 3; }
+// psi^n ring slot: planes t-1..t+1 (three slots), or t-3..t+1 (five) when
+// the kernel also forms the limiter coefficients of plane t-2
+template <bool BETA> __device__ __forceinline__ int slotp(int t)
+{
+    return BETA ? (t + 15) % 5 : (t + 12) % 3;
+}
 
 // in-plane offset of box entry e of a box with `w` entries per row, the
 // box's origin at (jb, kb) in global cell (or wall) coordinates; `wall_j` /
@@ -79,7 +85,7 @@ __device__ __forceinline__ int64_t box_offset(int e, int n_e, int w, int jb, int
     return j * row_len + k;
 }
 
-template <typename T, bool HAS_G, bool IGA, bool ABS, bool DFL, bool TOT, bool XIN>
+template <typename T, bool HAS_G, bool IGA, bool ABS, bool DFL, bool TOT, bool XIN, bool BETA>
 __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int tiles_j, int nblk,
                                                int kahan, const T *__restrict__ x,
                                                const T *__restrict__ c0,
@@ -88,7 +94,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                                                const T *__restrict__ G, T *__restrict__ out,
                                                Step3dOut<T> vo)
 {
-    __shared__ T Ps[3][NP];                              // psi^n, planes t-1..t+1
+    __shared__ T Ps[BETA ? 5 : 3][NP];                   // psi^n, planes t-1..t+1 (BETA: t-3..)
     __shared__ T Ys[4][NY];                              // y1, planes t-3..t
     __shared__ T C0s[4][NY];                             // c0, walls t-2..t+1
     __shared__ T C1s[3][N1];                             // c1, planes t-2..t
@@ -183,7 +189,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         }
     };
     auto store = [&](int t) {
-        const int sp = slot3(t + 1), sw = slot4(t + 1), sc = slot3(t);
+        const int sp = slotp<BETA>(t + 1), sw = slot4(t + 1), sc = slot3(t);
         // (pass mode, open: planes outside the domain are not stored, so
         // the edge plane's slot stays what those planes read)
         const bool xplane = xin && (!open0 || (t >= 0 && t < g.n0));
@@ -210,8 +216,8 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         for (int m = 0; m < 2; m++) {
             const int e = tid + m * NT;
             if (!xin && oP[m] >= 0) {
-                Ps[slot3(t_first - 1)][e] = x[ipm + oP[m]];
-                Ps[slot3(t_first)][e] = x[ip0 + oP[m]];
+                Ps[slotp<BETA>(t_first - 1)][e] = x[ipm + oP[m]];
+                Ps[slotp<BETA>(t_first)][e] = x[ip0 + oP[m]];
             }
             if (oY[m] >= 0) C0s[slot4(t_first)][e] = c0[iw0 + oY[m]];
         }
@@ -237,7 +243,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         if (xin) {
             if (!open0 || (t >= 0 && t < g.n0)) y_own = Ys[slot4(t)][cy];
         } else if (!open0 || (t >= 0 && t < g.n0)) {
-            const int pm = slot3(t - 1), p0 = slot3(t), pp = slot3(t + 1);
+            const int pm = slotp<BETA>(t - 1), p0 = slotp<BETA>(t), pp = slotp<BETA>(t + 1);
             const int wl = slot4(t), wh = slot4(t + 1), sc = slot3(t), sy = slot4(t);
             for (int m = 0; m < 2; m++) {
                 if (!yon[m]) continue;
@@ -465,19 +471,32 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 vo.v0[((int64_t)w0 * n1 + jj) * n2 + kk] = v0_hi;
             if (p >= i0 && p < i1) {
                 if (own_out && vo.y1) vo.y1[((int64_t)p * n1 + jj) * n2 + kk] = YB[cy];
+                const T v1o = vel1(bj, bk), v2o = vel2(bj, bk);
                 if (kk < g.n2 && (jj < g.n1 || (o1 && jj == g.n1)))
-                    vo.v1[((int64_t)p * (n1 + 1) + jj) * n2 + kk] = vel1(bj, bk);
+                    vo.v1[((int64_t)p * (n1 + 1) + jj) * n2 + kk] = v1o;
                 if (jj < g.n1 && (kk < g.n2 || (o2 && kk == g.n2)))
-                    vo.v2[((int64_t)p * n1 + jj) * (n2 + 1) + kk] = vel2(bj, bk);
+                    vo.v2[((int64_t)p * n1 + jj) * (n2 + 1) + kk] = v2o;
+                if (BETA) {
+                    // the coefficients read the high walls of the own cell
+                    V1s[r * SK + l] = v1o;
+                    V2s[r * (SK + 1) + l] = v2o;
+                }
                 if (tid < SK) {                                            // far j edge
                     const int je = j0 + SJ, ke = k0 + tid;
-                    if (o1 && je == g.n1 && ke < g.n2)
-                        vo.v1[((int64_t)p * (n1 + 1) + je) * n2 + ke] = vel1(SJ + 2, tid + 2);
+                    const bool wr = o1 && je == g.n1 && ke < g.n2;
+                    if (BETA || wr) {
+                        const T v = vel1(SJ + 2, tid + 2);
+                        if (wr) vo.v1[((int64_t)p * (n1 + 1) + je) * n2 + ke] = v;
+                        if (BETA) V1s[SJ * SK + tid] = v;
+                    }
                 } else if (tid < SK + SJ) {                                // far k edge
                     const int je = j0 + tid - SK, ke = k0 + SK;
-                    if (o2 && ke == g.n2 && je < g.n1)
-                        vo.v2[((int64_t)p * n1 + je) * (n2 + 1) + ke] =
-                            vel2(tid - SK + 2, SK + 2);
+                    const bool wr = o2 && ke == g.n2 && je < g.n1;
+                    if (BETA || wr) {
+                        const T v = vel2(tid - SK + 2, SK + 2);
+                        if (wr) vo.v2[((int64_t)p * n1 + je) * (n2 + 1) + ke] = v;
+                        if (BETA) V2s[(tid - SK) * (SK + 1) + SK] = v;
+                    }
                 }
             }
         } else {
@@ -489,10 +508,55 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         }
         T g_own = T(1);
         if (HAS_G) g_own = Gs[cs][cy];
+        // psi^n of plane p at the own cell and its face neighbours, for the
+        // limiter coefficients (read before the barrier: the ring slot of
+        // plane p-1 takes plane t+2 in the next iteration)
+        T pn[7];
+        if (BETA) {
+            const int qo = (r + 3) * PK + (l + 3);
+            const T *P0 = Ps[slotp<BETA>(p)];
+            pn[0] = P0[qo];
+            pn[1] = Ps[slotp<BETA>(p - 1)][qo];
+            pn[2] = Ps[slotp<BETA>(p + 1)][qo];
+            pn[3] = P0[qo - PK];
+            pn[4] = P0[qo + PK];
+            pn[5] = P0[qo - 1];
+            pn[6] = P0[qo + 1];
+        }
         // (B3) V1, V2 of plane p are in LDS; and (in both modes) no thread
         // stores the next planes into the rings before every thread is done
         // reading this iteration's
         __syncthreads();
+
+        // ---- limiter coefficients of plane p (BETA; the arithmetic of the
+        // cell kernel k_fct_beta term by term) ----
+        if (BETA && p >= i0 && p < i1 && own_out) {
+            const T xi = YB[cy];
+            T mx = pn[0], mn = mx;
+            mx = fmax(mx, xi);
+            mn = fmin(mn, xi);
+            // face neighbours in the order -e0, +e0, -e1, +e1, -e2, +e2
+            const T nb[6] = {YA[cy], YC[cy], YB[cy - BK], YB[cy + BK], YB[cy - 1], YB[cy + 1]};
+#pragma unroll
+            for (int q = 0; q < 6; q++) {
+                mx = fmax(fmax(mx, pn[1 + q]), nb[q]);
+                mn = fmin(fmin(mn, pn[1 + q]), nb[q]);
+            }
+            const T vlo[3] = {v0_lo, V1s[r * SK + l], V2s[r * (SK + 1) + l]};
+            const T vhi[3] = {v0_hi, V1s[(r + 1) * SK + l], V2s[r * (SK + 1) + l + 1]};
+            T fin = T(0), fout = T(0);
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const T wm = IGA ? T(1) : nb[2 * d], wp = IGA ? T(1) : nb[2 * d + 1];
+                const T wi = IGA ? T(1) : xi;
+                fin += pos(vlo[d]) * wm - neg(vhi[d]) * wp;
+                fout += pos(vhi[d]) * wi - neg(vlo[d]) * wi;
+            }
+            const T Gi = HAS_G ? g_own : T(1);
+            const int64_t idx = ((int64_t)p * g.n1 + (j0 + r)) * g.n2 + (k0 + l);
+            vo.bup[idx] = fin > T(0) ? Gi * (mx - xi) / fin : T(1);
+            vo.bdn[idx] = fout > T(0) ? Gi * (xi - mn) / fout : T(1);
+        }
 
         // ---- corrective pass at plane p ----
         if (!vo.v0 && p >= i0 && p < i1 && own_out) {
@@ -560,6 +624,8 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
                          const T *c1, const T *c2, const T *G, int tile_planes, hipStream_t s,
                          const Step3dOut<T> &vo)
 {
+    // the coefficients are formed only in output mode with the donor pass inside
+    if (vo.bup && (!vo.bdn || !vo.v0 || vo.xin)) return hipErrorInvalidValue;
     G3s g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
     const int tiles_k = (g.n2 + SK - 1) / SK, tiles_j = (g.n1 + SJ - 1) / SJ;
     int th = tile_planes > 0 ? tile_planes : 96;
@@ -570,17 +636,20 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
     const int kahan = (opts & OPT_KAHAN) ? 1 : 0;
     const bool iga = opts & OPT_IGA, absf = opts & OPT_ABS, dfl = opts & OPT_DFL,
                tot = opts & OPT_TOT;
-    auto go = [&](auto HG, auto IG, auto AB, auto DF, auto TO, auto XI) {
+    auto go = [&](auto HG, auto IG, auto AB, auto DF, auto TO, auto XI, auto BE) {
         k_step3d<T, decltype(HG)::value, decltype(IG)::value, decltype(AB)::value,
-                 decltype(DF)::value, decltype(TO)::value, decltype(XI)::value>
-            <<<(unsigned)blocks, NT, 0, s>>>(g, th, tiles_k, tiles_j, (int)blocks, kahan, psi_n,
-                                             c0, c1, c2, G, psi_out, vo);
+                 decltype(DF)::value, decltype(TO)::value, decltype(XI)::value,
+                 decltype(BE)::value><<<(unsigned)blocks, NT, 0, s>>>(
+            g, th, tiles_k, tiles_j, (int)blocks, kahan, psi_n, c0, c1, c2, G, psi_out, vo);
     };
     using TT = std::true_type;
     using FF = std::false_type;
+    // pass mode reads its input; the coefficients are formed only with the
+    // donor pass inside (pass 2)
     auto by_x = [&](auto HG, auto IG, auto AB, auto DF, auto TO) {
-        if (vo.xin) go(HG, IG, AB, DF, TO, TT{});
-        else go(HG, IG, AB, DF, TO, FF{});
+        if (vo.xin) go(HG, IG, AB, DF, TO, TT{}, FF{});
+        else if (vo.bup) go(HG, IG, AB, DF, TO, FF{}, TT{});
+        else go(HG, IG, AB, DF, TO, FF{}, FF{});
     };
     auto by_t = [&](auto HG, auto IG, auto AB, auto DF) {
         if (tot) by_x(HG, IG, AB, DF, TT{});
