@@ -1,8 +1,9 @@
 // fused3d.hip -- the 3-D donor-cell step (n_iters = 1) in one launch, and
 // the dispatch of the 3-D steps: two passes without the limiter are one
 // launch of the kernel of step3d.hip; with the limiter, or more passes, the
-// same kernel forms each pass's raw pseudo-velocities and the cell kernels
-// of staged.hip apply the limiter and the corrective pass, pass by pass.
+// same kernel forms each pass's raw pseudo-velocities (and the limiter
+// coefficients) and a cell kernel of staged.hip applies the limited
+// velocities and the corrective pass, pass by pass.
 //
 //   k_donor3d : donor-cell pass, psi^n -> y.  Each thread owns a (j, k)
 //               column and marches along i over a chunk of planes, keeping
@@ -134,8 +135,9 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
             return step3d_launch<T>(geom, opts, psi_n, psi_out, c0, c1, c2, G, tile_planes, s);
         // pass by pass: the 3-D kernel forms the pass's raw
         // pseudo-velocities (pass 2 from the donor pass it forms itself,
-        // which it also writes; later passes from the previous result),
-        // then cell kernels apply the limiter and the corrective pass.
+        // which it also writes; later passes from the previous result) and
+        // the limiter coefficients, then a cell kernel applies the limited
+        // velocities and the corrective pass.
         // Buffers: the pass input in cell[xs], its advector in wall[as]
         // (the input advector for pass 2), its raw velocities into the
         // other wall set, its limited velocities (the next advector) into
@@ -153,9 +155,8 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
             vo.v0 = w.wall[vs][0];
             vo.v1 = w.wall[vs][1];
             vo.v2 = w.wall[vs][2];
-            // pass 2 with the limiter: the same launch forms the coefficients
-            const bool beta_in = fct && !x;
-            if (beta_in) {
+            // with the limiter the same launch forms the coefficients
+            if (fct) {
                 vo.bup = w.bup;
                 vo.bdn = w.bdn;
             }
@@ -171,9 +172,7 @@ hipError_t fused3d_step(const Geom &geom, int n_iters, unsigned opts, const T *p
                     for (int d = 0; d < 3; d++) W[d] = w.wall[as][d];
                 // (the next pass's advector W stays in wall[as]; its raw
                 // velocities go to the set that held V)
-                e = beta_in ? limcorr_launch<T>(geom, opts, xp, V, G, w.bup, w.bdn, y, W, s)
-                            : fct_correct_launch<T>(geom, opts, psi_n, xp, V, G, w.bup, w.bdn, y,
-                                                    W, s);
+                e = limcorr_launch<T>(geom, opts, xp, V, G, w.bup, w.bdn, y, W, s);
                 for (int d = 0; d < 3; d++) adv[d] = W[d];
             } else {
                 e = launch_donor<T>(geom, xp, V, G, mode, y, s);

@@ -79,8 +79,9 @@ int64_t fused2d_max_parts(int64_t n0, int64_t n1, int n_iters, unsigned opts, in
 // the donor-only step is k_donor3d in fused3d.hip).  With the limiter, or
 // more passes, the same kernel forms each pass's raw pseudo-velocities (the
 // first pass's input by its donor pass, a later pass's read from memory)
-// and cell kernels apply the limiter and the corrective pass (staged.hip:
-// fct_correct_launch, launch_donor).
+// and, with the limiter, the limiter coefficients; a cell kernel applies
+// the limited velocities and the corrective pass (staged.hip:
+// limcorr_launch, or launch_donor without the limiter).
 // Modes of the 3-D step kernel: xin non-NULL: the pass input is read from
 // xin (and c0..c2 are that pass's advector) instead of formed by the donor
 // pass; v0 non-NULL (output mode): instead of the corrective pass, the raw
@@ -107,15 +108,9 @@ template <typename T>
 hipError_t fused3d_step(const Geom &g, int n_iters, unsigned opts, const T *psi_n, T *psi_out,
                         const T *c0, const T *c1, const T *c2, const T *G, int tile_planes,
                         hipStream_t s, const Fused3DWork<T> &w);
-// the limiter's coefficients of a pass (from its input x and raw
-// pseudo-velocities V), then its limited corrective donor-cell pass: x -> y;
-// W (entries NULL: not wanted) receives the limited velocities, the next
-// pass's advector
-template <typename T>
-hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, const T *x,
-                              const T *const V[3], const T *G, T *bup, T *bdn, T *y,
-                              T *const W[3], hipStream_t s);
-// the second half alone, from coefficients already formed
+// the limited corrective donor-cell pass of a pass from its input x, raw
+// pseudo-velocities V and limiter coefficients: x -> y; W (entries NULL: not
+// wanted) receives the limited velocities, the next pass's advector
 template <typename T>
 hipError_t limcorr_launch(const Geom &g, unsigned opts, const T *x, const T *const V[3],
                           const T *G, const T *bup, const T *bdn, T *y, T *const W[3],

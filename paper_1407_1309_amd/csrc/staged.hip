@@ -549,15 +549,6 @@ hipError_t launch_fct(const Geom &g, unsigned opts, const T *psi_n, const T *x,
 }
 
 template <typename T>
-hipError_t fct_correct_launch(const Geom &g, unsigned opts, const T *psi_n, const T *x,
-                              const T *const V[3], const T *G, T *bup, T *bdn, T *y,
-                              T *const W[3], hipStream_t s)
-{
-    fct_beta_launch<T>(g, opts, psi_n, x, V, G, bup, bdn, s);
-    return limcorr_launch<T>(g, opts, x, V, G, bup, bdn, y, W, s);
-}
-
-template <typename T>
 hipError_t limcorr_launch(const Geom &g, unsigned opts, const T *x, const T *const V[3],
                           const T *G, const T *bup, const T *bdn, T *y, T *const W[3],
                           hipStream_t s)
@@ -581,9 +572,6 @@ hipError_t limcorr_launch(const Geom &g, unsigned opts, const T *x, const T *con
     template hipError_t launch_fct<T>(const Geom &, unsigned, const T *, const T *,            \
                                       const T *const[3], const T *, T *, T *, T *const[3],    \
                                       hipStream_t);                                           \
-    template hipError_t fct_correct_launch<T>(const Geom &, unsigned, const T *, const T *,    \
-                                              const T *const[3], const T *, T *, T *, T *,     \
-                                              T *const[3], hipStream_t);                       \
     template hipError_t limcorr_launch<T>(const Geom &, unsigned, const T *, const T *const[3], \
                                           const T *, const T *, const T *, T *, T *const[3],   \
                                           hipStream_t);

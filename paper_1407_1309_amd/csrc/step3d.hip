@@ -64,11 +64,12 @@ template <typename T, bool IGA> __device__ __forceinline__ T fr3(T num, T den, T
 // ring slot of a virtual plane index t >= -12
 __device__ __forceinline__ int slot3(int t) { return (t + 12) % 3; }
 __device__ __forceinline__ int slot4(int t) { return (t + 12) & 3; }
-// psi^n ring slot: planes t-1..t+1 (three slots), or t-3..t+1 (five) when
-// the kernel also forms the limiter coefficients of plane t-2
+// psi^n ring slot: planes t-1..t+1 (three slots), or t-4..t+1 (six) when
+// the kernel also forms the limiter coefficients of plane t-2 (read after
+// the second barrier, while the next iteration may already store plane t+2)
 template <bool BETA> __device__ __forceinline__ int slotp(int t)
 {
-    return BETA ? (t + 15) % 5 : (t + 12) % 3;
+    return BETA ? (t + 18) % 6 : (t + 12) % 3;
 }
 
 // in-plane offset of box entry e of a box with `w` entries per row, the
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                                                const T *__restrict__ G, T *__restrict__ out,
                                                Step3dOut<T> vo)
 {
-    __shared__ T Ps[BETA ? 5 : 3][NP];                   // psi^n, planes t-1..t+1 (BETA: t-3..)
+    __shared__ T Ps[BETA ? 6 : 3][NP];                   // psi^n, planes t-1..t+1 (BETA: t-4..)
     __shared__ T Ys[4][NY];                              // y1, planes t-3..t
     __shared__ T C0s[4][NY];                             // c0, walls t-2..t+1
     __shared__ T C1s[3][N1];                             // c1, planes t-2..t
@@ -172,13 +173,21 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
     // iteration): psi^n (donor pass) or the pass input, c0 (two entries
     // each), c1, c2, G
     T fP[2], fC0[2], fC1[2], fC2[2], fG[2];
+    T fQ0 = T(0), fQ1 = T(0);   // pass mode with the coefficients: psi^n entries
     auto fetch = [&](int t) {
         const int64_t ip = map_cell(t + 1, g.n0, g.bc0) * pl;     // psi^n plane t+1
         const int64_t iw = map_wall(t + 1, g.n0, g.bc0) * pl;     // c0 wall t+1
         const int64_t ic = map_cell(t, g.n0, g.bc0);              // plane t
+        #pragma unroll
         for (int m = 0; m < 2; m++) {
-            if (xin) {
+            if (XIN) {
                 if (oY[m] >= 0) fP[m] = xin[ic * pl + oY[m]];
+                // (an entry past the box loads entry 0 and is not stored)
+                if (BETA) {
+                    const T v = x[ip + (oP[m] >= 0 ? oP[m] : 0)];
+                    if (m) fQ1 = v;
+                    else fQ0 = v;
+                }
             } else if (oP[m] >= 0) {
                 fP[m] = x[ip + oP[m]];
             }
@@ -192,11 +201,13 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         const int sp = slotp<BETA>(t + 1), sw = slot4(t + 1), sc = slot3(t);
         // (pass mode, open: planes outside the domain are not stored, so
         // the edge plane's slot stays what those planes read)
-        const bool xplane = xin && (!open0 || (t >= 0 && t < g.n0));
+        const bool xplane = XIN && (!open0 || (t >= 0 && t < g.n0));
+        #pragma unroll
         for (int m = 0; m < 2; m++) {
             const int e = tid + m * NT;
-            if (xin) {
+            if (XIN) {
                 if (xplane && oY[m] >= 0) Ys[slot4(t)][e] = fP[m];
+                if (BETA && oP[m] >= 0) Ps[sp][e] = m ? fQ1 : fQ0;
             } else if (oP[m] >= 0) {
                 Ps[sp][e] = fP[m];
             }
@@ -213,9 +224,10 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         const int64_t ipm = map_cell(t_first - 1, g.n0, g.bc0) * pl;
         const int64_t ip0 = map_cell(t_first, g.n0, g.bc0) * pl;
         const int64_t iw0 = map_wall(t_first, g.n0, g.bc0) * pl;
+        #pragma unroll
         for (int m = 0; m < 2; m++) {
             const int e = tid + m * NT;
-            if (!xin && oP[m] >= 0) {
+            if ((!XIN || BETA) && oP[m] >= 0) {
                 Ps[slotp<BETA>(t_first - 1)][e] = x[ipm + oP[m]];
                 Ps[slotp<BETA>(t_first)][e] = x[ip0 + oP[m]];
             }
@@ -240,7 +252,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         __syncthreads();   // (B1) plane t's inputs are in LDS
 
         // ---- donor-cell pass: y1 of plane t on the box ----
-        if (xin) {
+        if (XIN) {
             if (!open0 || (t >= 0 && t < g.n0)) y_own = Ys[slot4(t)][cy];
         } else if (!open0 || (t >= 0 && t < g.n0)) {
             const int pm = slotp<BETA>(t - 1), p0 = slotp<BETA>(t), pp = slotp<BETA>(t + 1);
@@ -508,20 +520,18 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         }
         T g_own = T(1);
         if (HAS_G) g_own = Gs[cs][cy];
-        // psi^n of plane p at the own cell and its face neighbours, for the
-        // limiter coefficients (read before the barrier: the ring slot of
-        // plane p-1 takes plane t+2 in the next iteration)
-        T pn[7];
+        // the pass input at the own cell of plane p and its face neighbours,
+        // for the limiter coefficients (read before the barrier: in pass
+        // mode the next iteration stores plane t+1 into the slot of p-1)
+        T xn[7];
         if (BETA) {
-            const int qo = (r + 3) * PK + (l + 3);
-            const T *P0 = Ps[slotp<BETA>(p)];
-            pn[0] = P0[qo];
-            pn[1] = Ps[slotp<BETA>(p - 1)][qo];
-            pn[2] = Ps[slotp<BETA>(p + 1)][qo];
-            pn[3] = P0[qo - PK];
-            pn[4] = P0[qo + PK];
-            pn[5] = P0[qo - 1];
-            pn[6] = P0[qo + 1];
+            xn[0] = YB[cy];
+            xn[1] = YA[cy];
+            xn[2] = YC[cy];
+            xn[3] = YB[cy - BK];
+            xn[4] = YB[cy + BK];
+            xn[5] = YB[cy - 1];
+            xn[6] = YB[cy + 1];
         }
         // (B3) V1, V2 of plane p are in LDS; and (in both modes) no thread
         // stores the next planes into the rings before every thread is done
@@ -531,23 +541,34 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         // ---- limiter coefficients of plane p (BETA; the arithmetic of the
         // cell kernel k_fct_beta term by term) ----
         if (BETA && p >= i0 && p < i1 && own_out) {
-            const T xi = YB[cy];
+            // psi^n of the same cells (planes p-1..p+1 stay in the ring until
+            // the iteration after next)
+            T pn[7];
+            const int qo = (r + 3) * PK + (l + 3);
+            const T *P0 = Ps[slotp<BETA>(p)];
+            pn[0] = P0[qo];
+            pn[1] = Ps[slotp<BETA>(p - 1)][qo];
+            pn[2] = Ps[slotp<BETA>(p + 1)][qo];
+            pn[3] = P0[qo - PK];
+            pn[4] = P0[qo + PK];
+            pn[5] = P0[qo - 1];
+            pn[6] = P0[qo + 1];
+            const T xi = xn[0];
             T mx = pn[0], mn = mx;
             mx = fmax(mx, xi);
             mn = fmin(mn, xi);
             // face neighbours in the order -e0, +e0, -e1, +e1, -e2, +e2
-            const T nb[6] = {YA[cy], YC[cy], YB[cy - BK], YB[cy + BK], YB[cy - 1], YB[cy + 1]};
 #pragma unroll
             for (int q = 0; q < 6; q++) {
-                mx = fmax(fmax(mx, pn[1 + q]), nb[q]);
-                mn = fmin(fmin(mn, pn[1 + q]), nb[q]);
+                mx = fmax(fmax(mx, pn[1 + q]), xn[1 + q]);
+                mn = fmin(fmin(mn, pn[1 + q]), xn[1 + q]);
             }
             const T vlo[3] = {v0_lo, V1s[r * SK + l], V2s[r * (SK + 1) + l]};
             const T vhi[3] = {v0_hi, V1s[(r + 1) * SK + l], V2s[r * (SK + 1) + l + 1]};
             T fin = T(0), fout = T(0);
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                const T wm = IGA ? T(1) : nb[2 * d], wp = IGA ? T(1) : nb[2 * d + 1];
+                const T wm = IGA ? T(1) : xn[1 + 2 * d], wp = IGA ? T(1) : xn[2 + 2 * d];
                 const T wi = IGA ? T(1) : xi;
                 fin += pos(vlo[d]) * wm - neg(vhi[d]) * wp;
                 fout += pos(vhi[d]) * wi - neg(vlo[d]) * wi;
@@ -624,8 +645,8 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
                          const T *c1, const T *c2, const T *G, int tile_planes, hipStream_t s,
                          const Step3dOut<T> &vo)
 {
-    // the coefficients are formed only in output mode with the donor pass inside
-    if (vo.bup && (!vo.bdn || !vo.v0 || vo.xin)) return hipErrorInvalidValue;
+    // the coefficients are formed only in output mode
+    if (vo.bup && (!vo.bdn || !vo.v0)) return hipErrorInvalidValue;
     G3s g{(int)geom.n[0], (int)geom.n[1], (int)geom.n[2], geom.bc[0], geom.bc[1], geom.bc[2]};
     const int tiles_k = (g.n2 + SK - 1) / SK, tiles_j = (g.n1 + SJ - 1) / SJ;
     int th = tile_planes > 0 ? tile_planes : 96;
@@ -644,12 +665,15 @@ hipError_t step3d_launch(const Geom &geom, unsigned opts, const T *psi_n, T *psi
     };
     using TT = std::true_type;
     using FF = std::false_type;
-    // pass mode reads its input; the coefficients are formed only with the
-    // donor pass inside (pass 2)
+    // pass mode reads its input; with bup / bdn the coefficients too
     auto by_x = [&](auto HG, auto IG, auto AB, auto DF, auto TO) {
-        if (vo.xin) go(HG, IG, AB, DF, TO, TT{}, FF{});
-        else if (vo.bup) go(HG, IG, AB, DF, TO, FF{}, TT{});
-        else go(HG, IG, AB, DF, TO, FF{}, FF{});
+        if (vo.xin) {
+            if (vo.bup) go(HG, IG, AB, DF, TO, TT{}, TT{});
+            else go(HG, IG, AB, DF, TO, TT{}, FF{});
+        } else {
+            if (vo.bup) go(HG, IG, AB, DF, TO, FF{}, TT{});
+            else go(HG, IG, AB, DF, TO, FF{}, FF{});
+        }
     };
     auto by_t = [&](auto HG, auto IG, auto AB, auto DF) {
         if (tot) by_x(HG, IG, AB, DF, TT{});
