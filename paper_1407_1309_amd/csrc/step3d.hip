@@ -1,7 +1,8 @@
 // step3d.hip -- a whole 3-D MPDATA step with two passes and no limiter in
 // one launch (donor-cell pass, pseudo-velocity with its cross and
-// third-order terms, corrective pass; infinite gauge, variable G, both
-// boundary types).
+// third-order terms, corrective pass; infinite gauge, |psi| fractions, the
+// divergent-flow term, variable G, both boundary types), and the passes of
+// longer steps or steps with the limiter (modes below).
 //
 // A workgroup of SJ x SK threads owns a tile of SJ x SK (j, k) output
 // columns and marches along i over a chunk of planes.  In the iteration
@@ -21,6 +22,14 @@
 // Two barriers per plane.  Every thread computes one output cell (the
 // ring's y1 cells are shared out as a second cell to the first threads), so
 // no thread only recomputes a halo.
+//
+// Modes for steps with the limiter or more passes (Step3dOut): in output
+// mode step 4 is replaced by writing the donor result and the raw V0, V1, V2
+// of each plane (each wall by its owner), and with BETA also the limiter
+// coefficients of plane t-2 (Sect. 3.1.4: the bounds over the cell and its
+// face neighbours of psi^n and the pass input, the in- and out-fluxes, and
+// their quotients), which needs psi^n of planes t-3..t-1 (a six-plane
+// ring); in pass mode (XIN) step 2 is replaced by reading the pass input.
 //
 // Boundaries: every global read goes through the boundary map (periodic
 // wrap / open clamp), so ring positions hold mapped values.  The y1 of a
