@@ -66,6 +66,24 @@ def test_3d_recipe_100_steps_ragged():
     assert_parity(out, ref, torch.float64, "3-D 37x45x70, 100 steps")
 
 
+@pytest.mark.parametrize("n_iters", [2, 3])
+def test_3d_recipe_with_limiter_100_steps(n_iters):
+    """The 3-D recipe with the limiter added (its coefficients formed in the
+    pseudo-velocity launch of every pass, then the limited corrective pass)
+    on 33 x 36 x 40 cells, all 100 steps; three passes without iga (defined
+    for two passes only)."""
+    case = synth.case_3d(shape=(33, 36, 40), sigma=(1.5, 5.0), seed=17)
+    case.opts |= FCT
+    if n_iters == 3:
+        case.opts &= ~mpdata.OPT_IGA
+        case.psi = np.abs(case.psi)
+    case.n_iters = n_iters
+    out = _run_like_bench(case, torch.float64, case.n_steps)
+    ref = oracle.step(case.psi, case.c, g=case.g, n_iters=n_iters, opts=case.opts, bc=1,
+                      n_steps=case.n_steps, parallel=True)
+    assert_parity(out, ref, torch.float64, f"3-D 33x36x40 + fct, n_iters={n_iters}, 100 steps")
+
+
 def test_1d_recipe_1000_steps_elementwise():
     case = synth.case_1d()
     out = _run_like_bench(case, torch.float64, case.n_steps)
