@@ -6,14 +6,13 @@
 // their states, and every step is reversed stage by stage.  The forward
 // recompute of a step runs the staged kernels and keeps each pass's input
 // field, raw and limited pseudo-velocities and limiter coefficients; the
-// reverse kernels are the transposes of those stages.  The donor-cell and
-// limiter transposes, and in 2-D without third-order terms the
-// pseudo-velocity transpose, gather: every adjoint entry is summed by one
-// thread over the forward outputs that read it (through the boundary map),
-// in a fixed order, so these gradients are the same bits on every run.  The
-// general pseudo-velocity transpose (1-D, 3-D, third-order terms) scatters
-// from one thread per wall with hardware floating-point atomics, whose
-// order -- and so the last bits of the sums -- can change between runs.
+// reverse kernels are the transposes of those stages.  Every transpose
+// gathers: each adjoint entry is summed by one thread over the forward
+// outputs that read it (through the boundary map), in a fixed order -- the
+// pseudo-velocity transpose in 2-D without third-order terms from
+// coefficients its workgroup keeps in LDS, otherwise from per-position slots
+// each wall writes to workspace -- so the gradients are the same bits on
+// every run; no kernel uses atomics.
 //
 // Conventions at non-differentiable points: d[u]+/du = [u > 0],
 // d[u]-/du = [u < 0], d|u|/du = [u > 0] - [u < 0]; max/min pass the
@@ -82,11 +81,6 @@ __device__ inline int64_t wi(const Geom &g, int d, const I3 &p)
         q[t] = (t == d) ? wrap_wall(p.v[t], (int)g.n[t], g.bc[t])
                         : wrap_cell(p.v[t], (int)g.n[t], g.bc[t]);
     return ((int64_t)q[0] * e[1] + q[1]) * e[2] + q[2];
-}
-
-template <typename T> __device__ inline void aadd(T *a, int64_t k, T v)
-{
-    if (v != T(0)) unsafeAtomicAdd(a + k, v);
 }
 
 template <typename T> __device__ inline T sgnv(T u) { return T((u > T(0)) - (u < T(0))); }
@@ -331,126 +325,303 @@ __global__ void __launch_bounds__(B)
     if (rgt) put(ac, cb1, w1hi, ((u1hi > T(0) ? xc : T(0)) + (u1hi < T(0) ? xc : T(0))) * F1hi);
 }
 
-// transpose of the pseudo-velocity at every dimension-d wall
-template <typename T, int ND, int WD>
-__global__ void k_pseudo_adj(Geom g, unsigned opts, const T *__restrict__ x, const T *c0,
-                             const T *c1, const T *c2, const T *G, const T *__restrict__ Vb,
-                             T *xb, T *cb0, T *cb1, T *cb2)
+// Deterministic transpose of the pseudo-velocity (1-D, 3-D, and 2-D with
+// the third-order terms), phase 1: every wall of dimension WD sums what it
+// sends to each stencil position -- its right cell R = p, left cell
+// L = p - e_d, R + e_d, L - e_d, R and L shifted by +-e_o along each other
+// dimension o, and (3-D third-order term) R and L shifted by +-e_o1 +-e_o2
+// -- into that position's slot, in the order of the terms; its own advector
+// adjoint into U and a quarter of each cross-mean adjoint into Q.  Every
+// slot entry has one writer.  Phase 2 (k_pseudo_gather_cells / _walls) has
+// every cell and wall sum the slots that land on it in a fixed order, so the
+// sums are the same bits on every run.  Slots of a wall: 0 R, 1 L, 2 R+e_d,
+// 3 L-e_d, then per other dimension (ascending) R+e_o, L+e_o, R-e_o, L-e_o,
+// then (3-D) for L and then R: (+o1,+o2), (-o1,+o2), (+o1,-o2), (-o1,-o2).
+template <int ND> constexpr int pseudo_slots() { return 4 + 4 * (ND - 1) + (ND == 3 ? 8 : 0); }
+
+// offset from the wall's right cell of slot k (wall dimension d)
+template <int ND>
+__device__ __forceinline__ void slot_offset(int d, int k, int off[3])
 {
-    constexpr int d = WD;   // wall dimension (compile time: no dynamic indexing)
+    off[0] = off[1] = off[2] = 0;
+    if (k < 4) {
+        off[d] = k == 0 ? 0 : (k == 1 ? -1 : (k == 2 ? 1 : -2));
+        return;
+    }
+    int o[2] = {0, 0}, n = 0;
+    for (int t = 0; t < ND; t++)
+        if (t != d) o[n++] = t;
+    if (k < 4 + 4 * (ND - 1)) {
+        const int oi = (k - 4) >> 2, r = (k - 4) & 3;
+        off[d] = (r & 1) ? -1 : 0;               // R, L, R, L
+        off[o[oi]] = (r < 2) ? 1 : -1;           // +e_o twice, then -e_o twice
+        return;
+    }
+    const int q = k - 4 - 4 * (ND - 1);           // (3-D) the eight corners
+    off[d] = (q < 4) ? -1 : 0;                    // L first, then R
+    off[o[0]] = (q & 1) ? -1 : 1;
+    off[o[1]] = (q & 2) ? -1 : 1;
+}
+
+template <typename T, int ND, int WD>
+__global__ void __launch_bounds__(B)
+k_pseudo_adj_slots(Geom g, unsigned opts, const T *__restrict__ x, const T *c0, const T *c1,
+                   const T *c2, const T *G, const T *__restrict__ Vb, T *__restrict__ S,
+                   T *__restrict__ U, T *__restrict__ Q)
+{
+    constexpr int d = WD;
+    constexpr int NS = pseudo_slots<ND>();
     int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
     e[d] += 1;
-    int64_t M = e[0] * e[1] * e[2];
-    int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    const int64_t M = e[0] * e[1] * e[2];
+    const int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
     if (t >= M) return;
-    T vb = Vb[t];
-    if (vb == T(0)) return;
-    const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
-    const T *c[3] = {c0, c1, c2};
-    T *cb[3] = {cb0, cb1, cb2};
-    I3 p = unflat_i3(t, e);
-    I3 L = sh1(p, d, -1), R = p;
-    T u = c[d][wi(g, d, p)];
-    T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
-    T Gb = T(0.5) * (GL + GR);
-    const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
-    int64_t kL = ci(g, L), kR = ci(g, R);
-    T xL = x[kL], xR = x[kR];
-    T ub = T(0), fn, fd;
-
-    T nA = xR - xL, dA = xR + xL;
-    T A;
-    frac_vd(iga, nA, dA, T(2), A, fn, fd);
-    ub += (sgnv(u) - T(2) * u * iGb) * A * vb;
-    T Ab = (fabs(u) - u * u * iGb) * vb;
-    aadd(xb, kR, (fn + fd) * Ab);
-    aadd(xb, kL, (-fn + fd) * Ab);
-
-    T cbar[3] = {T(0), T(0), T(0)}, cbar_b[3] = {T(0), T(0), T(0)};
-    for (int o = 0; o < ND; o++) {
-        if (o == d) continue;
-        cbar[o] = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, sh1(L, o, 1))] +
-                             c[o][wi(g, o, R)] + c[o][wi(g, o, sh1(R, o, 1))]);
-        int64_t kRp = ci(g, sh1(R, o, 1)), kLp = ci(g, sh1(L, o, 1));
-        int64_t kRm = ci(g, sh1(R, o, -1)), kLm = ci(g, sh1(L, o, -1));
-        T a = x[kRp], b = x[kLp], ee = x[kRm], f = x[kLm];
-        T nB = a + b - ee - f, dB = a + b + ee + f;
-        T Bv;
-        frac_vd(iga, nB, dB, T(4), Bv, fn, fd);
-        ub += T(-0.5) * cbar[o] * iGb * Bv * vb;
-        cbar_b[o] += T(-0.5) * u * iGb * Bv * vb;
-        T Bb = T(-0.5) * u * cbar[o] * iGb * vb;
-        aadd(xb, kRp, (fn + fd) * Bb);
-        aadd(xb, kLp, (fn + fd) * Bb);
-        aadd(xb, kRm, (-fn + fd) * Bb);
-        aadd(xb, kLm, (-fn + fd) * Bb);
+    T acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) acc[k] = T(0);
+    T ub = T(0);
+    T cbar_b[3] = {T(0), T(0), T(0)};
+    const T vb = Vb[t];
+    if (vb != T(0)) {
+        const bool iga = opts & OPT_IGA, tot = opts & OPT_TOT;
+        const T *c[3] = {c0, c1, c2};
+        const I3 p = unflat_i3(t, e);
+        const I3 L = sh1(p, d, -1), R = p;
+        const T u = c[d][wi(g, d, p)];
+        const T GL = G ? G[ci(g, L)] : T(1), GR = G ? G[ci(g, R)] : T(1);
+        const T Gb = T(0.5) * (GL + GR);
+        const T iGb = T(1) / Gb, iGb2 = iGb * iGb;
+        const T xL = x[ci(g, L)], xR = x[ci(g, R)];
+        T fn, fd;
+        T A;
+        frac_vd(iga, xR - xL, xR + xL, T(2), A, fn, fd);
+        ub += (sgnv(u) - T(2) * u * iGb) * A * vb;
+        const T Ab = (fabs(u) - u * u * iGb) * vb;
+        acc[0] += (fn + fd) * Ab;
+        acc[1] += (-fn + fd) * Ab;
+        T cbar[3] = {T(0), T(0), T(0)};
+        {
+            int oi = 0;
+#pragma unroll
+            for (int o = 0; o < ND; o++) {
+                if (o == d) continue;
+                cbar[o] = T(0.25) * (c[o][wi(g, o, L)] + c[o][wi(g, o, sh1(L, o, 1))] +
+                                     c[o][wi(g, o, R)] + c[o][wi(g, o, sh1(R, o, 1))]);
+                const T a = x[ci(g, sh1(R, o, 1))], b = x[ci(g, sh1(L, o, 1))];
+                const T ee = x[ci(g, sh1(R, o, -1))], f = x[ci(g, sh1(L, o, -1))];
+                T Bv;
+                frac_vd(iga, a + b - ee - f, a + b + ee + f, T(4), Bv, fn, fd);
+                ub += T(-0.5) * cbar[o] * iGb * Bv * vb;
+                cbar_b[o] += T(-0.5) * u * iGb * Bv * vb;
+                const T Bb = T(-0.5) * u * cbar[o] * iGb * vb;
+                acc[4 + 4 * oi + 0] += (fn + fd) * Bb;
+                acc[4 + 4 * oi + 1] += (fn + fd) * Bb;
+                acc[4 + 4 * oi + 2] += (-fn + fd) * Bb;
+                acc[4 + 4 * oi + 3] += (-fn + fd) * Bb;
+                oi++;
+            }
+        }
+        if (tot) {
+            const T xR2 = x[ci(g, sh1(R, d, 1))], xL2 = x[ci(g, sh1(L, d, -1))];
+            T Dv;
+            frac_vd(iga, xR2 - xR - xL + xL2, xR2 + xR + xL + xL2, T(4), Dv, fn, fd);
+            const T cD = (T(3) * u * fabs(u) * iGb - T(2) * u * u * u * iGb2 - u) / T(3);
+            ub += (T(6) * fabs(u) * iGb - T(6) * u * u * iGb2 - T(1)) / T(3) * Dv * vb;
+            const T Db = cD * vb;
+            acc[2] += (fn + fd) * Db;
+            acc[0] += (-fn + fd) * Db;
+            acc[1] += (-fn + fd) * Db;
+            acc[3] += (fn + fd) * Db;
+            int oi = 0;
+#pragma unroll
+            for (int o = 0; o < ND; o++) {
+                if (o == d) continue;
+                const T a = x[ci(g, sh1(R, o, 1))], b = x[ci(g, sh1(L, o, 1))];
+                const T ee = x[ci(g, sh1(R, o, -1))], f = x[ci(g, sh1(L, o, -1))];
+                T Ev;
+                frac_vd(iga, a - b - ee + f, a + b + ee + f, T(4), Ev, fn, fd);
+                const T cE = fabs(u) * cbar[o] * iGb - T(2) * u * u * cbar[o] * iGb2;
+                ub += (sgnv(u) * cbar[o] * iGb - T(4) * u * cbar[o] * iGb2) * Ev * vb;
+                cbar_b[o] += (fabs(u) * iGb - T(2) * u * u * iGb2) * Ev * vb;
+                const T Eb = cE * vb;
+                acc[4 + 4 * oi + 0] += (fn + fd) * Eb;
+                acc[4 + 4 * oi + 1] += (-fn + fd) * Eb;
+                acc[4 + 4 * oi + 2] += (-fn + fd) * Eb;
+                acc[4 + 4 * oi + 3] += (fn + fd) * Eb;
+                oi++;
+            }
+            if constexpr (ND == 3) {
+                constexpr int o1 = (d == 0) ? 1 : 0;
+                constexpr int o2 = (d == 2) ? 1 : 2;
+                T xs[2][4];
+                T num = T(0), den = T(0);
+#pragma unroll
+                for (int sd = 0; sd < 2; sd++) {
+                    const I3 SS = sd ? R : L;
+                    xs[sd][0] = x[ci(g, sh2(SS, o1, 1, o2, 1))];
+                    xs[sd][1] = x[ci(g, sh2(SS, o1, -1, o2, 1))];
+                    xs[sd][2] = x[ci(g, sh2(SS, o1, 1, o2, -1))];
+                    xs[sd][3] = x[ci(g, sh2(SS, o1, -1, o2, -1))];
+                    num += xs[sd][0] - xs[sd][1] - xs[sd][2] + xs[sd][3];
+                    den += xs[sd][0] + xs[sd][1] + xs[sd][2] + xs[sd][3];
+                }
+                T Tv;
+                frac_vd(iga, num, den, T(8), Tv, fn, fd);
+                const T k = -(T(2) / T(3)) * iGb2;
+                ub += k * cbar[o1] * cbar[o2] * Tv * vb;
+                cbar_b[o1] += k * u * cbar[o2] * Tv * vb;
+                cbar_b[o2] += k * u * cbar[o1] * Tv * vb;
+                const T Tb = k * u * cbar[o1] * cbar[o2] * vb;
+                const T sg[4] = {T(1), T(-1), T(-1), T(1)};
+#pragma unroll
+                for (int sd = 0; sd < 2; sd++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) acc[12 + 4 * sd + q] += (sg[q] * fn + fd) * Tb;
+            }
+        }
     }
-    if (tot) {
-        int64_t kR2 = ci(g, sh1(R, d, 1)), kL2 = ci(g, sh1(L, d, -1));
-        T xR2 = x[kR2], xL2 = x[kL2];
-        T nD = xR2 - xR - xL + xL2, dD = xR2 + xR + xL + xL2;
-        T Dv;
-        frac_vd(iga, nD, dD, T(4), Dv, fn, fd);
-        T cD = (T(3) * u * fabs(u) * iGb - T(2) * u * u * u * iGb2 - u) / T(3);
-        ub += (T(6) * fabs(u) * iGb - T(6) * u * u * iGb2 - T(1)) / T(3) * Dv * vb;
-        T Db = cD * vb;
-        aadd(xb, kR2, (fn + fd) * Db);
-        aadd(xb, kR, (-fn + fd) * Db);
-        aadd(xb, kL, (-fn + fd) * Db);
-        aadd(xb, kL2, (fn + fd) * Db);
+#pragma unroll
+    for (int k = 0; k < NS; k++) S[(int64_t)k * M + t] = acc[k];
+    U[t] = ub;
+    {
+        int oi = 0;
+#pragma unroll
         for (int o = 0; o < ND; o++) {
             if (o == d) continue;
-            int64_t kRp = ci(g, sh1(R, o, 1)), kLp = ci(g, sh1(L, o, 1));
-            int64_t kRm = ci(g, sh1(R, o, -1)), kLm = ci(g, sh1(L, o, -1));
-            T a = x[kRp], b = x[kLp], ee = x[kRm], f = x[kLm];
-            T nE = a - b - ee + f, dE = a + b + ee + f;
-            T Ev;
-            frac_vd(iga, nE, dE, T(4), Ev, fn, fd);
-            T cE = fabs(u) * cbar[o] * iGb - T(2) * u * u * cbar[o] * iGb2;
-            ub += (sgnv(u) * cbar[o] * iGb - T(4) * u * cbar[o] * iGb2) * Ev * vb;
-            cbar_b[o] += (fabs(u) * iGb - T(2) * u * u * iGb2) * Ev * vb;
-            T Eb = cE * vb;
-            aadd(xb, kRp, (fn + fd) * Eb);
-            aadd(xb, kLp, (-fn + fd) * Eb);
-            aadd(xb, kRm, (-fn + fd) * Eb);
-            aadd(xb, kLm, (fn + fd) * Eb);
-        }
-        if (ND == 3) {
-            int o1 = (d == 0) ? 1 : 0;
-            int o2 = (d == 2) ? 1 : 2;
-            int64_t kp[2][4];
-            T num = T(0), den = T(0);
-            for (int s = 0; s < 2; s++) {
-                I3 S = s ? R : L;
-                kp[s][0] = ci(g, sh2(S, o1, 1, o2, 1));
-                kp[s][1] = ci(g, sh2(S, o1, -1, o2, 1));
-                kp[s][2] = ci(g, sh2(S, o1, 1, o2, -1));
-                kp[s][3] = ci(g, sh2(S, o1, -1, o2, -1));
-                T vpp = x[kp[s][0]], vmp = x[kp[s][1]], vpm = x[kp[s][2]], vmm = x[kp[s][3]];
-                num += vpp - vmp - vpm + vmm;
-                den += vpp + vmp + vpm + vmm;
-            }
-            T Tv;
-            frac_vd(iga, num, den, T(8), Tv, fn, fd);
-            T k = -(T(2) / T(3)) * iGb2;
-            ub += k * cbar[o1] * cbar[o2] * Tv * vb;
-            cbar_b[o1] += k * u * cbar[o2] * Tv * vb;
-            cbar_b[o2] += k * u * cbar[o1] * Tv * vb;
-            T Tb = k * u * cbar[o1] * cbar[o2] * vb;
-            const T sg[4] = {T(1), T(-1), T(-1), T(1)};
-            for (int s = 0; s < 2; s++)
-                for (int q = 0; q < 4; q++) aadd(xb, kp[s][q], (sg[q] * fn + fd) * Tb);
+            Q[(int64_t)oi * M + t] = T(0.25) * cbar_b[o];
+            oi++;
         }
     }
-    aadd(cb[d], wi(g, d, p), ub);
-    for (int o = 0; o < ND; o++) {
-        if (o == d || cbar_b[o] == T(0)) continue;
-        T q = T(0.25) * cbar_b[o];
-        aadd(cb[o], wi(g, o, L), q);
-        aadd(cb[o], wi(g, o, sh1(L, o, 1)), q);
-        aadd(cb[o], wi(g, o, R), q);
-        aadd(cb[o], wi(g, o, sh1(R, o, 1)), q);
+}
+
+// the unmapped coordinates in [-2, n+1] that the boundary map sends to
+// cell coordinate q (at most five: an open extent of one cell)
+__device__ __forceinline__ int cell_preimages(int q, int n, int bc, int u[5])
+{
+    int m = 0;
+    if (bc == BC_PERIODIC) {
+        for (int v = q - 2 * n; v <= q + 2 * n; v += n)
+            if (v >= -2 && v <= n + 1) u[m++] = v;
+    } else {
+        u[m++] = q;
+        if (q == 0) {
+            u[m++] = -1;
+            u[m++] = -2;
+        }
+        if (q == n - 1) {
+            u[m++] = n;
+            u[m++] = n + 1;
+        }
     }
+    return m;
+}
+
+// phase 2 for the cells: xb[q] += every slot whose position maps onto q
+// (wall dimensions ascending, slots in order, preimages in order)
+template <typename T, int ND>
+__global__ void __launch_bounds__(B)
+k_pseudo_gather_cells(Geom g, const T *__restrict__ S0, const T *__restrict__ S1,
+                      const T *__restrict__ S2, T *__restrict__ xb)
+{
+    constexpr int NS = pseudo_slots<ND>();
+    const int64_t N = g.n[0] * g.n[1] * g.n[2];
+    const int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= N) return;
+    const I3 q = unflat_i3(t, g.n);
+    int uu[3][5], nu[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a < ND) {
+            nu[a] = cell_preimages(q.v[a], (int)g.n[a], g.bc[a], uu[a]);
+        } else {
+            nu[a] = 1;
+            uu[a][0] = 0;
+        }
+    }
+    const T *Sd[3] = {S0, S1, S2};
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+        e[d] += 1;
+        const int64_t M = e[0] * e[1] * e[2];
+        for (int k = 0; k < NS; k++) {
+            int off[3];
+            slot_offset<ND>(d, k, off);
+            for (int a0 = 0; a0 < nu[0]; a0++)
+                for (int a1 = 0; a1 < nu[1]; a1++)
+                    for (int a2 = 0; a2 < nu[2]; a2++) {
+                        const int p0 = uu[0][a0] - off[0], p1 = uu[1][a1] - off[1],
+                                  p2 = uu[2][a2] - off[2];
+                        const int pv[3] = {p0, p1, p2};
+                        bool ok = true;
+#pragma unroll
+                        for (int b = 0; b < 3; b++)
+                            ok = ok && pv[b] >= 0 && pv[b] < (int)e[b];
+                        // a periodic dimension's wall n is wall 0, not a wall of its own
+                        if (ok && g.bc[d] == BC_PERIODIC && pv[d] == (int)g.n[d]) ok = false;
+                        if (ok) acc += Sd[d][(int64_t)k * M + ((int64_t)p0 * e[1] + p1) * e[2] + p2];
+                    }
+        }
+    }
+    xb[t] += acc;
+}
+
+// phase 2 for the dimension-o walls: cb[w] += the wall's own share, then the
+// cross-mean shares of the other dimensions' walls that land on it (their
+// left cell's and right cell's o-walls, low then high)
+template <typename T, int ND, int WO>
+__global__ void __launch_bounds__(B)
+k_pseudo_gather_walls(Geom g, const T *__restrict__ U, const T *__restrict__ Q0,
+                      const T *__restrict__ Q1, const T *__restrict__ Q2, T *__restrict__ cb)
+{
+    constexpr int o = WO;
+    int64_t eo[3] = {g.n[0], g.n[1], g.n[2]};
+    eo[o] += 1;
+    const int64_t M = eo[0] * eo[1] * eo[2];
+    const int64_t t = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (t >= M) return;
+    const I3 w = unflat_i3(t, eo);
+    T v = U[t];
+    const T *Qd[3] = {Q0, Q1, Q2};
+    // preimages of the wall coordinate along o (walls 0..n) and of the cell
+    // coordinates along the other dimensions
+    int fo[2], nfo = 0;
+    if (g.bc[o] == BC_PERIODIC) {
+        if (w.v[o] < (int)g.n[o]) fo[nfo++] = w.v[o];
+        if (w.v[o] == 0) fo[nfo++] = (int)g.n[o];
+    } else {
+        fo[nfo++] = w.v[o];
+    }
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        if (d == o) continue;
+        int oi = 0;   // index of o among the dimensions != d
+        for (int t2 = 0; t2 < o; t2++)
+            if (t2 != d) oi++;
+        int64_t e[3] = {g.n[0], g.n[1], g.n[2]};
+        e[d] += 1;
+        const int64_t Md = e[0] * e[1] * e[2];
+        int ud[5];
+        const int nud = cell_preimages(w.v[d], (int)g.n[d], g.bc[d], ud);
+        // roles: L (low o-wall), L + e_o, R, R + e_o
+        for (int r = 0; r < 4; r++) {
+            const int dl = (r < 2) ? 1 : 0;      // L = p - e_d: p_d = u_d + 1
+            const int dh = (r & 1) ? 1 : 0;      // o-wall p_o + 1
+            for (int a = 0; a < nud; a++)
+                for (int b = 0; b < nfo; b++) {
+                    int pv[3] = {w.v[0], w.v[1], w.v[2]};
+                    pv[d] = ud[a] + dl;
+                    pv[o] = fo[b] - dh;
+                    bool ok = pv[d] >= 0 && pv[d] <= (int)g.n[d] && pv[o] >= 0 &&
+                              pv[o] < (int)g.n[o];
+                    if (ok && g.bc[d] == BC_PERIODIC && pv[d] == (int)g.n[d]) ok = false;
+                    if (ok)
+                        v += Qd[d][(int64_t)oi * Md + ((int64_t)pv[0] * e[1] + pv[1]) * e[2] + pv[2]];
+                }
+        }
+    }
+    cb[t] += v;
 }
 
 // 2-D boundary map with compile-time boundary types and 32-bit flat indices
@@ -1255,19 +1426,36 @@ void donor_adj(const Geom &g, const T *x, const T *const c[3], const T *G, int f
     }
 }
 
-// launches with the dimension count (and wall dimension) as template
-// parameters, so the stencil indices are static
+int64_t ncells(const Geom &g);
+int64_t nwalls(const Geom &g, int d);
+
+// the deterministic transpose of every other case (see k_pseudo_adj_slots):
+// slots of every wall dimension, then the gathers; S / U / Q: per wall
+// dimension, pseudo_slots<nd>() / 1 / nd - 1 wall fields of workspace
 template <typename T>
-void pseudo_adj_dispatch(const Geom &g, int d, unsigned blocks, hipStream_t s, unsigned opts,
-                         const T *x, const T *c0, const T *c1, const T *c2, const T *G,
-                         const T *Vb, T *xb, T *cb0, T *cb1, T *cb2)
+void pseudo_adj_slots_launch(const Geom &g, hipStream_t s, unsigned opts, const T *x,
+                             const T *const c[3], const T *G, T *const Vb[3], T *xb,
+                             T *const cb[3], T *const S[3], T *const U[3], T *const Q[3])
 {
-#define MP_P(ND, D) \
-    k_pseudo_adj<T, ND, D><<<blocks, B, 0, s>>>(g, opts, x, c0, c1, c2, G, Vb, xb, cb0, cb1, cb2)
-    if (g.nd == 1) MP_P(1, 0);
-    else if (g.nd == 2) { if (d == 0) MP_P(2, 0); else MP_P(2, 1); }
-    else { if (d == 0) MP_P(3, 0); else if (d == 1) MP_P(3, 1); else MP_P(3, 2); }
-#undef MP_P
+    with_nd(g.nd, [&](auto ND) {
+        constexpr int nd = decltype(ND)::value;
+        for (int d = 0; d < nd; d++) {
+            const unsigned wb = (unsigned)cdiv(nwalls(g, d), B);
+            with_nd_d(nd, d, [&](auto ND2, auto WD) {
+                k_pseudo_adj_slots<T, decltype(ND2)::value, decltype(WD)::value>
+                    <<<wb, B, 0, s>>>(g, opts, x, c[0], c[1], c[2], G, Vb[d], S[d], U[d], Q[d]);
+            });
+        }
+        const unsigned cbk = (unsigned)cdiv(ncells(g), B);
+        k_pseudo_gather_cells<T, nd><<<cbk, B, 0, s>>>(g, S[0], S[1], S[2], xb);
+        for (int o = 0; o < nd; o++) {
+            const unsigned wb = (unsigned)cdiv(nwalls(g, o), B);
+            with_nd_d(nd, o, [&](auto ND2, auto WO) {
+                k_pseudo_gather_walls<T, decltype(ND2)::value, decltype(WO)::value>
+                    <<<wb, B, 0, s>>>(g, U[o], Q[0], Q[1], Q[2], cb[o]);
+            });
+        }
+    });
 }
 
 // 2-D without third-order terms: both wall dimensions in one launch
@@ -1367,6 +1555,7 @@ template <typename T> struct AdjWs {
     T *F[5];        // limiter-coefficient transpose, per cell (k_beta_adj_a)
     int *code;      // which cells attain the bounds (k_beta_adj_a)
     T *Ab[3], *Vb[3], *Cb[3];
+    T *PS[3], *PU[3], *PQ[3];   // pseudo-velocity transpose slots (not the 2-D tiled path)
     T *tmp;         // output of a recomputed step
     size_t bytes;
     // slot 0 of the records and the distance between slots (elements)
@@ -1390,7 +1579,8 @@ template <typename T> struct AdjWs {
 };
 
 template <typename T>
-AdjWs<T> carve_adj(const Geom &g, int n_iters, bool fct, int n_steps, int ckpt, char *base)
+AdjWs<T> carve_adj(const Geom &g, int n_iters, bool fct, int n_steps, int ckpt, char *base,
+                   bool slots)
 {
     AdjWs<T> w;
     size_t off = 0;
@@ -1441,6 +1631,15 @@ AdjWs<T> carve_adj(const Geom &g, int n_iters, bool fct, int n_steps, int ckpt, 
         w.Ab[d] = take(nwalls(g, d));
         w.Vb[d] = take(nwalls(g, d));
         w.Cb[d] = take(nwalls(g, d));
+    }
+    const int ns = g.nd == 1 ? pseudo_slots<1>() : (g.nd == 2 ? pseudo_slots<2>() : pseudo_slots<3>());
+    for (int d = 0; d < 3; d++) {
+        w.PS[d] = w.PU[d] = w.PQ[d] = nullptr;
+        if (slots && d < g.nd) {
+            w.PS[d] = take((size_t)ns * nwalls(g, d));
+            w.PU[d] = take(nwalls(g, d));
+            if (g.nd > 1) w.PQ[d] = take((size_t)(g.nd - 1) * nwalls(g, d));
+        }
     }
     w.bytes = off;
     return w;
@@ -1591,10 +1790,8 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
             pseudo_adj2_launch<T>(g, s, a.opts, x, cin[0], cin[1], a.G, w.Vb[0], w.Vb[1], w.xb,
                                   tgt[0], tgt[1]);
         else
-            for (int d = 0; d < g.nd; d++)
-                pseudo_adj_dispatch<T>(g, d, (unsigned)cdiv(nwalls(g, d), B), s, a.opts, x,
-                                       cin[0], cin[1], cin[2], a.G, w.Vb[d], w.xb, tgt[0], tgt[1],
-                                       tgt[2]);
+            pseudo_adj_slots_launch<T>(g, s, a.opts, x, cin, a.G, w.Vb, w.xb, tgt, w.PS, w.PU,
+                                       w.PQ);
         T *t = w.yb;
         w.yb = w.xb;
         w.xb = t;
@@ -1619,11 +1816,14 @@ hipError_t reverse_step(const AdjArgs<T> &a, AdjWs<T> &w, const T *psi_n, hipStr
 
 }  // namespace
 
-size_t adj_extra_bytes(const Geom &g, size_t es, int n_iters, int n_steps, int ckpt_every)
+size_t adj_extra_bytes(const Geom &g, size_t es, int n_iters, unsigned opts, int n_steps,
+                       int ckpt_every)
 {
     // FCT on/off changes the layout; size for the larger one
-    if (es == 8) return carve_adj<double>(g, n_iters, true, n_steps, ckpt_every, nullptr).bytes;
-    return carve_adj<float>(g, n_iters, true, n_steps, ckpt_every, nullptr).bytes;
+    const bool slots = !pseudo_adj_both(g, opts);
+    if (es == 8)
+        return carve_adj<double>(g, n_iters, true, n_steps, ckpt_every, nullptr, slots).bytes;
+    return carve_adj<float>(g, n_iters, true, n_steps, ckpt_every, nullptr, slots).bytes;
 }
 
 template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
@@ -1632,7 +1832,7 @@ template <typename T> hipError_t adjoint_run(const AdjArgs<T> &a, hipStream_t s)
     const int64_t N = ncells(g);
     const size_t nb = (size_t)N * sizeof(T);
     AdjWs<T> w = carve_adj<T>(g, a.n_iters, (a.opts & OPT_FCT) != 0, a.n_steps, a.ckpt_every,
-                              a.ws);
+                              a.ws, !pseudo_adj_both(g, a.opts));
     hipError_t e;
     // forward sweep: checkpoint at the start of every segment
     const int ck = a.ckpt_every;

@@ -27,7 +27,8 @@ template <typename T> struct AdjArgs {
     void *plain_ctx = nullptr;
 };
 
-size_t adj_extra_bytes(const Geom &g, size_t es, int n_iters, int n_steps, int ckpt_every);
+size_t adj_extra_bytes(const Geom &g, size_t es, int n_iters, unsigned opts, int n_steps,
+                       int ckpt_every);
 
 template <typename T>
 void adj_fill_args(AdjArgs<T> &a, const Geom &g, int n_iters, unsigned opts, const T *psi0,

@@ -1035,7 +1035,7 @@ size_t mpdata_adj_workspace_bytes(const mpdata_desc *desc, int n_steps, int ckpt
     if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps) return 0;
     size_t base = carve(g, desc->dtype, nullptr, desc->n_iters, desc->opts).bytes;
     return base + mp::adj_extra_bytes(g, desc->dtype == MPDATA_F64 ? 8 : 4, desc->n_iters,
-                                      n_steps, ckpt_every);
+                                      desc->opts, n_steps, ckpt_every);
 }
 
 }  // extern "C"
