@@ -62,6 +62,8 @@ def _parse():
                     help="Kahan-compensated donor-cell updates (the library-default summation)")
     ap.add_argument("--abs", action="store_true", help="|psi| in the psi-fractions")
     ap.add_argument("--dfl", action="store_true", help="divergent-flow pseudo-velocity term")
+    ap.add_argument("--fct", action="store_true",
+                    help="add the limiter (3-D and 1-D workloads; the 2-D ones have it)")
     ap.add_argument("--xcd-order", type=int, default=1,
                     help="batched tile order with --tile-rows: 1 grouped per XCD, 0 grid by grid")
     ap.add_argument("--tile-rows", type=int, default=None,
@@ -183,8 +185,9 @@ def bench_single(args, torch, mpdata, synth, oracle):
     else:
         case = synth.case_1d()
         name = "1d_periodic_500_iters2"
-    for flag, bit in (("kahan", mpdata.OPT_KAHAN), ("abs", mpdata.OPT_ABS), ("dfl", mpdata.OPT_DFL)):
-        if getattr(args, flag):
+    for flag, bit in (("kahan", mpdata.OPT_KAHAN), ("abs", mpdata.OPT_ABS), ("dfl", mpdata.OPT_DFL),
+                      ("fct", mpdata.OPT_FCT)):
+        if getattr(args, flag) and not case.opts & bit:
             case.opts |= bit
             name += "_" + flag
     dtype = torch.float32 if f32 else torch.float64
@@ -237,6 +240,11 @@ def bench_single(args, torch, mpdata, synth, oracle):
     roof = _roofline(kname, kern_ms, n_launch, alg_bytes,
                      alg_ops=ops * N if ops else None, traffic=_traffic_entry(kname, wl),
                      valu=_valu_entry(kname, wl, N, ops) if ops else None)
+    if kname == "k_step3d" and (case.opts & mpdata.OPT_FCT or case.n_iters > 2):
+        # the window spans every launch of a step: the 3-D kernel per pass
+        # and the limited corrective pass (or donor pass) after it
+        roof["kernel"] = "k_step3d + " + ("k_limcorr" if case.opts & mpdata.OPT_FCT
+                                          else "k_donor") + " (whole step)"
 
     out = {
         "metric": "Mcell-steps/s", "value": round(value, 3), "unit": "Mcell-steps/s",
