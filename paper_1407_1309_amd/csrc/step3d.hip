@@ -56,7 +56,10 @@ constexpr int N1 = (BJ + 1) * BK;               // dimension-1 walls of the box
 constexpr int N2 = BJ * (BK + 1);               // dimension-2 walls of the box
 static_assert(NY <= 2 * NT && NP <= 2 * NT && N1 <= 2 * NT && N2 <= 2 * NT,
               "each thread loads at most two entries of every box plane");
+static_assert(NT <= NY && NT <= NP && NT <= N1 && NT <= N2, "entry 0 of every box plane is in it");
 static_assert(SK <= NT && SK + SJ <= NT, "far-edge walls need that many threads");
+constexpr int WAVE64 = 64;
+static_assert(NT % WAVE64 == 0, "whole waves");
 static_assert(NY - NT == 4 * BK + 4 * SJ && NY - NT <= NT, "ring cells: one per thread at most");
 
 struct G3s {
@@ -132,25 +135,42 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                   pl2 = (int64_t)g.n1 * (g.n2 + 1);
 
     // in-plane offsets of the box entries this thread loads (two per array)
+    // and their places in the LDS planes.  Entry 0 (e = tid) is in every
+    // box.  Entry 1 (e = tid + NT) exists for the first lanes only: whole
+    // waves past a box skip it by a branch on the wave index, which is
+    // uniform; a lane past the box in the one wave that straddles its end
+    // loads and stores its entry 0 again (same address, same value), so no
+    // load or store needs a per-lane branch.
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE64);
+    const bool hasP = wv * WAVE64 < NP - NT, hasY = wv * WAVE64 < NY - NT,
+               has1 = wv * WAVE64 < N1 - NT, has2 = wv * WAVE64 < N2 - NT;
     int64_t oP[2], oY[2], o1[2], o2[2];
+    int eP[2], eY[2], eW1[2], eW2[2];
     for (int m = 0; m < 2; m++) {
         const int e = tid + m * NT;
         oP[m] = box_offset(e, NP, PK, j0 - 3, k0 - 3, false, false, g, g.n2);
         oY[m] = box_offset(e, NY, BK, j0 - 2, k0 - 2, false, false, g, g.n2);
         o1[m] = box_offset(e, N1, BK, j0 - 2, k0 - 2, true, false, g, g.n2);
         o2[m] = box_offset(e, N2, BK + 1, j0 - 2, k0 - 2, false, true, g, g.n2 + 1);
+        eP[m] = eY[m] = eW1[m] = eW2[m] = e;
     }
+    if (oP[1] < 0) oP[1] = oP[0], eP[1] = tid;
+    if (oY[1] < 0) oY[1] = oY[0], eY[1] = tid;
+    if (o1[1] < 0) o1[1] = o1[0], eW1[1] = tid;
+    if (o2[1] < 0) o2[1] = o2[0], eW2[1] = tid;
     // y1 cells this thread forms, each at its effective position (the
     // clamped cell outside an open domain): first its own column's cell,
     // then, for the first NRING threads, one cell of the ring of 2 around
     // the tile (rows 0-1, rows SJ+2..SJ+3, then lanes 0-1 and SK+2..SK+3 of
-    // the rows between)
+    // the rows between).  Waves past the ring skip the second cell (uniform
+    // branch); the lanes past it in the wave that straddles its end form
+    // their own cell again and store the same value to the same place.
     constexpr int NRING = NY - NT;
+    const bool hasR = wv * WAVE64 < NRING;
     int ye[2], yp[2];
-    bool yon[2];
     for (int m = 0; m < 2; m++) {
         int bj, bk;
-        if (m == 0) {
+        if (m == 0 || tid >= NRING) {
             bj = r + 2;
             bk = l + 2;
         } else if (tid < 2 * BK) {
@@ -164,8 +184,6 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             bj = 2 + q / 4;
             bk = (q & 3) < 2 ? (q & 3) : SK + (q & 3);
         }
-        yon[m] = m == 0 || tid < NRING;
-        if (!yon[m]) bj = bk = 0;
         int ej = bj, ek = bk;
         if (g.bc1 == BC_OPEN) ej = min(max(j0 - 2 + bj, 0), g.n1 - 1) - (j0 - 2);
         if (g.bc2 == BC_OPEN) ek = min(max(k0 - 2 + bk, 0), g.n2 - 1) - (k0 - 2);
@@ -183,51 +201,68 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
     // each), c1, c2, G
     T fP[2], fC0[2], fC1[2], fC2[2], fG[2];
     T fQ0 = T(0), fQ1 = T(0);   // pass mode with the coefficients: psi^n entries
-    auto fetch = [&](int t) {
-        const int64_t ip = map_cell(t + 1, g.n0, g.bc0) * pl;     // psi^n plane t+1
-        const int64_t iw = map_wall(t + 1, g.n0, g.bc0) * pl;     // c0 wall t+1
-        const int64_t ic = map_cell(t, g.n0, g.bc0);              // plane t
+    // The boundary map along i and the ring slots are carried from plane to
+    // plane (a wrap test each) instead of formed by a division per use: wt /
+    // wt1 are planes t / t+1 wrapped periodically, r3 / r6 the slots
+    // slot3(t) / slotp<true>(t) of the plane being brought on chip.
+    const int t_first = i0 - 2, t_last = i1 + 1;
+    int r3 = slot3(t_first), r6 = slotp<true>(t_first);
+    auto sl3 = [&](int k) {     // slot3(t + k), |k| <= 3
+        const int v = r3 + k;
+        return v < 0 ? v + 3 : (v >= 3 ? v - 3 : v);
+    };
+    auto slp = [&](int k) {     // slotp<BETA>(t + k), -5 <= k <= 2
+        if (!BETA) return sl3(k);
+        const int v = r6 + k;
+        return v < 0 ? v + 6 : (v >= 6 ? v - 6 : v);
+    };
+    auto fetch = [&](int t, int wt, int wt1) {
+        // psi^n plane t+1, c0 wall t+1, plane t (open: clamped)
+        const int64_t ip = (int64_t)(open0 ? min(max(t + 1, 0), g.n0 - 1) : wt1) * pl;
+        const int64_t iw = (int64_t)(open0 ? min(max(t + 1, 0), g.n0) : wt1) * pl;
+        const int64_t ic = open0 ? min(max(t, 0), g.n0 - 1) : wt;
         #pragma unroll
         for (int m = 0; m < 2; m++) {
+            const bool dP = m == 0 || hasP, dY = m == 0 || hasY, d1 = m == 0 || has1,
+                       d2 = m == 0 || has2;
             if (XIN) {
-                if (oY[m] >= 0) fP[m] = xin[ic * pl + oY[m]];
-                // (an entry past the box loads entry 0 and is not stored)
-                if (BETA) {
-                    const T v = x[ip + (oP[m] >= 0 ? oP[m] : 0)];
+                if (dY) fP[m] = xin[ic * pl + oY[m]];
+                if (BETA && dP) {
+                    const T v = x[ip + oP[m]];
                     if (m) fQ1 = v;
                     else fQ0 = v;
                 }
-            } else if (oP[m] >= 0) {
+            } else if (dP) {
                 fP[m] = x[ip + oP[m]];
             }
-            if (oY[m] >= 0) fC0[m] = c0[iw + oY[m]];
-            if (o1[m] >= 0) fC1[m] = c1[ic * pl1 + o1[m]];
-            if (o2[m] >= 0) fC2[m] = c2[ic * pl2 + o2[m]];
-            if (HAS_G && oY[m] >= 0) fG[m] = G[ic * pl + oY[m]];
+            if (dY) fC0[m] = c0[iw + oY[m]];
+            if (d1) fC1[m] = c1[ic * pl1 + o1[m]];
+            if (d2) fC2[m] = c2[ic * pl2 + o2[m]];
+            if (HAS_G && dY) fG[m] = G[ic * pl + oY[m]];
         }
     };
-    auto store = [&](int t) {
-        const int sp = slotp<BETA>(t + 1), sw = slot4(t + 1), sc = slot3(t);
+    auto store = [&](int t) {   // t: the plane of r3 / r6
+        const int sp = slp(1), sw = slot4(t + 1), sc = sl3(0);
         // (pass mode, open: planes outside the domain are not stored, so
         // the edge plane's slot stays what those planes read)
         const bool xplane = XIN && (!open0 || (t >= 0 && t < g.n0));
         #pragma unroll
         for (int m = 0; m < 2; m++) {
-            const int e = tid + m * NT;
+            const bool dP = m == 0 || hasP, dY = m == 0 || hasY, d1 = m == 0 || has1,
+                       d2 = m == 0 || has2;
             if (XIN) {
-                if (xplane && oY[m] >= 0) Ys[slot4(t)][e] = fP[m];
-                if (BETA && oP[m] >= 0) Ps[sp][e] = m ? fQ1 : fQ0;
-            } else if (oP[m] >= 0) {
-                Ps[sp][e] = fP[m];
+                if (xplane && dY) Ys[slot4(t)][eY[m]] = fP[m];
+                if (BETA && dP) Ps[sp][eP[m]] = m ? fQ1 : fQ0;
+            } else if (dP) {
+                Ps[sp][eP[m]] = fP[m];
             }
-            if (oY[m] >= 0) C0s[sw][e] = fC0[m];
-            if (o1[m] >= 0) C1s[sc][e] = fC1[m];
-            if (o2[m] >= 0) C2s[sc][e] = fC2[m];
-            if (HAS_G && oY[m] >= 0) Gs[sc][e] = fG[m];
+            if (dY) C0s[sw][eY[m]] = fC0[m];
+            if (d1) C1s[sc][eW1[m]] = fC1[m];
+            if (d2) C2s[sc][eW2[m]] = fC2[m];
+            if (HAS_G && dY) Gs[sc][eY[m]] = fG[m];
         }
     };
 
-    const int t_first = i0 - 2, t_last = i1 + 1;
     // prologue: psi^n planes t_first-1 and t_first, c0 wall t_first
     {
         const int64_t ipm = map_cell(t_first - 1, g.n0, g.bc0) * pl;
@@ -235,15 +270,16 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         const int64_t iw0 = map_wall(t_first, g.n0, g.bc0) * pl;
         #pragma unroll
         for (int m = 0; m < 2; m++) {
-            const int e = tid + m * NT;
-            if ((!XIN || BETA) && oP[m] >= 0) {
-                Ps[slotp<BETA>(t_first - 1)][e] = x[ipm + oP[m]];
-                Ps[slotp<BETA>(t_first)][e] = x[ip0 + oP[m]];
+            if ((!XIN || BETA) && (m == 0 || hasP)) {
+                Ps[slotp<BETA>(t_first - 1)][eP[m]] = x[ipm + oP[m]];
+                Ps[slotp<BETA>(t_first)][eP[m]] = x[ip0 + oP[m]];
             }
-            if (oY[m] >= 0) C0s[slot4(t_first)][e] = c0[iw0 + oY[m]];
+            if (m == 0 || hasY) C0s[slot4(t_first)][eY[m]] = c0[iw0 + oY[m]];
         }
     }
-    fetch(t_first);
+    int w1 = (int)map_cell(t_first + 1, g.n0, BC_PERIODIC);
+    int w2 = w1 + 1 == g.n0 ? 0 : w1 + 1;
+    fetch(t_first, (int)map_cell(t_first, g.n0, BC_PERIODIC), w1);
 
     // y1 ring slot of virtual plane q (open: planes outside the domain read
     // the edge plane)
@@ -255,19 +291,20 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
     T v0_lo = T(0);      // V0 at the low wall of the plane being corrected
     T y_own = T(0);      // y1 of plane t of the thread's own column
 
-    for (int t = t_first; t <= t_last; t++) {
+    for (int t = t_first; t <= t_last; t++, r3 = r3 == 2 ? 0 : r3 + 1, r6 = r6 == 5 ? 0 : r6 + 1,
+                                         w1 = w2, w2 = w2 + 1 == g.n0 ? 0 : w2 + 1) {
         store(t);
-        if (t < t_last) fetch(t + 1);
+        if (t < t_last) fetch(t + 1, w1, w2);
         __syncthreads();   // (B1) plane t's inputs are in LDS
 
         // ---- donor-cell pass: y1 of plane t on the box ----
         if (XIN) {
             if (!open0 || (t >= 0 && t < g.n0)) y_own = Ys[slot4(t)][cy];
         } else if (!open0 || (t >= 0 && t < g.n0)) {
-            const int pm = slotp<BETA>(t - 1), p0 = slotp<BETA>(t), pp = slotp<BETA>(t + 1);
-            const int wl = slot4(t), wh = slot4(t + 1), sc = slot3(t), sy = slot4(t);
+            const int pm = slp(-1), p0 = slp(0), pp = slp(1);
+            const int wl = slot4(t), wh = slot4(t + 1), sc = sl3(0), sy = slot4(t);
             for (int m = 0; m < 2; m++) {
-                if (!yon[m]) continue;
+                if (m == 1 && !hasR) continue;
                 const int ee = ye[m];
                 const int ej = ee / BK, ek = ee % BK;
                 const int q = (ej + 1) * PK + (ek + 1);        // psi^n box entry
@@ -316,7 +353,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         // ---- pseudo-velocities ----
         const int p = t - 2;
         const int sA = yslot(p - 1), sB = yslot(p), sC = yslot(p + 1), sD = yslot(p + 2);
-        const int cs = slot3(p), cs1 = slot3(p + 1);      // c1, c2, G planes p, p+1
+        const int cs = sl3(-2), cs1 = sl3(-1);            // c1, c2, G planes p, p+1
         const int ws = slot4(p), ws1 = slot4(p + 1);      // c0 walls p, p+1
         const T *YA = Ys[sA], *YB = Ys[sB], *YC = Ys[sC];
 
@@ -554,10 +591,10 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             // the iteration after next)
             T pn[7];
             const int qo = (r + 3) * PK + (l + 3);
-            const T *P0 = Ps[slotp<BETA>(p)];
+            const T *P0 = Ps[slp(-2)];
             pn[0] = P0[qo];
-            pn[1] = Ps[slotp<BETA>(p - 1)][qo];
-            pn[2] = Ps[slotp<BETA>(p + 1)][qo];
+            pn[1] = Ps[slp(-3)][qo];
+            pn[2] = Ps[slp(-1)][qo];
             pn[3] = P0[qo - PK];
             pn[4] = P0[qo + PK];
             pn[5] = P0[qo - 1];
