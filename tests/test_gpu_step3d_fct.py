@@ -110,3 +110,20 @@ def test_step3d_more_passes_vs_oracle(shape, bcs, opts, with_g, n_iters):
     out, name = _run(psi, c, g, bcs, opts, torch.float64, 3, n_iters=n_iters)
     assert name == "k_step3d", name
     assert_parity(out, ref, torch.float64, f"{shape} {bcs} opts={opts} n_iters={n_iters}")
+
+
+@pytest.mark.parametrize("n_iters,opts", [(2, TOT | IGA), (2, FCT | TOT), (3, FCT), (3, DFL | FCT)])
+@pytest.mark.parametrize("shape,bcs", [((3, 17, 40), (0, 0, 0)), ((3, 9, 70), (0, 1, 1)),
+                                       ((4, 20, 33), (0, 1, 0)), ((1, 20, 33), (1, 1, 1)),
+                                       ((2, 35, 36), (1, 0, 1))],
+                         ids=lambda v: "x".join(map(str, v)))
+def test_step3d_thin_first_dimension_vs_oracle(shape, bcs, n_iters, opts):
+    """The fewest planes each boundary type allows along the marching
+    dimension (3 periodic, 1 and 2 open): every plane of a chunk is near
+    both ends, so the plane map's wrap or clamp and the ring slots of the
+    warm-up and drain planes all come into play."""
+    psi, c, g = _case(shape, bcs, opts, True, seed=sum(shape) + opts + n_iters)
+    ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=list(bcs), n_steps=3)
+    out, name = _run(psi, c, g, bcs, opts, torch.float64, 3, n_iters=n_iters)
+    assert name == "k_step3d", name
+    assert_parity(out, ref, torch.float64, f"{shape} {bcs} opts={opts} n_iters={n_iters}")
