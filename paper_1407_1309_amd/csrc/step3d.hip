@@ -84,6 +84,32 @@ template <bool BETA> __device__ __forceinline__ int slotp(int t)
     return BETA ? (t + 18) % 6 : (t + 12) % 3;
 }
 
+// Reciprocals 1 / d[k] as one FP64 quotient set (the range test and the
+// refined hardware reciprocal of the quotient sets in common.hpp, numerator
+// 1), and whether the set took the refined form: then n * q[k] has the bits
+// of that set's quotient n / d[k] for any n, so a later quotient by the same
+// divisor can reuse q[k]; else q[k] is the IEEE quotient and such a later
+// quotient must divide.
+template <int K> __device__ __forceinline__ bool rcp_set(const double (&d)[K], double (&q)[K])
+{
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < K; k++)
+        ok = ok && __builtin_amdgcn_class(d[k], 0x168) && fabs(d[k]) < 0x1p1000;
+    if (__builtin_amdgcn_ballot_w64(!ok) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            double r = __builtin_amdgcn_rcp(d[k]);
+            r = fma(fma(-d[k], r, 1.0), r, r);
+            q[k] = 1.0 * r;
+        }
+        return true;
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) q[k] = 1.0 / d[k];
+    return false;
+}
+
 // in-plane offset of box entry e of a box with `w` entries per row, the
 // box's origin at (jb, kb) in global cell (or wall) coordinates; `wall_j` /
 // `wall_k` mark the dimension whose coordinate is a wall index.  -1 when e
@@ -360,14 +386,31 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         // V0 at wall p+1 (planes p | p+1) of column (bj, bk)
         // psi value entering a psi-fraction: |psi| under the abs option
         auto ya = [](T v) -> T { return ABS ? fabs(v) : v; };
+        // 1 / mean G at the own cell's three low walls, formed as one set
+        // (one range test for the quotients; the far-edge walls form their
+        // own); in FP64 without the coefficients the set also holds 1 / G of
+        // the own cell for the corrective pass's quotient (gfast: the set
+        // took the refined form)
+        T igo[4] = {T(1), T(1), T(1), T(1)};
+        bool gfast = false;
+        if (HAS_G) {
+            T gb[4] = {T(0.5) * (Gs[cs][cy] + Gs[cs1][cy]), T(0.5) * (Gs[cs][cy - BK] + Gs[cs][cy]),
+                       T(0.5) * (Gs[cs][cy - 1] + Gs[cs][cy]), Gs[cs][cy]};
+            if constexpr (std::is_same<T, double>::value && !BETA) {
+                gfast = rcp_set<4>(gb, igo);
+            } else {
+                // (with the coefficients the launch is in output mode: no
+                // corrective pass; gfast stays false)
+                T one[3] = {T(1), T(1), T(1)}, g3[3] = {gb[0], gb[1], gb[2]}, q3[3];
+                quotients<3>(one, g3, q3);
+                igo[0] = q3[0];
+                igo[1] = q3[1];
+                igo[2] = q3[2];
+            }
+        }
         auto vel0 = [&]() -> T {
             const int c = cy;
-            T ig = T(1);
-            if (HAS_G) {
-                T one[1] = {T(1)}, gb[1] = {T(0.5) * (Gs[cs][c] + Gs[cs1][c])}, q[1];
-                quotients<1>(one, gb, q);
-                ig = q[0];
-            }
+            const T ig = igo[0];
             const T xL = ya(YB[c]), xR = ya(YC[c]);
             const T u = C0s[ws1][c];
             T A = fr3<T, IGA>(xR - xL, xR + xL, T(2));
@@ -416,10 +459,11 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             return v;
         };
         // V1 at plane p, wall between box rows wj-1 | wj, lane wk
-        auto vel1 = [&](int wj, int wk) -> T {
+        // (own: the own cell's wall, whose 1 / mean G is in igo)
+        auto vel1 = [&](int wj, int wk, bool own) -> T {
             const int c = wj * BK + wk;
-            T ig = T(1);
-            if (HAS_G) {
+            T ig = igo[1];
+            if (HAS_G && !own) {
                 T one[1] = {T(1)}, gb[1] = {T(0.5) * (Gs[cs][c - BK] + Gs[cs][c])}, q[1];
                 quotients<1>(one, gb, q);
                 ig = q[0];
@@ -465,10 +509,10 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             return v;
         };
         // V2 at plane p, wall between box lanes wk-1 | wk, row wj
-        auto vel2 = [&](int wj, int wk) -> T {
+        auto vel2 = [&](int wj, int wk, bool own) -> T {
             const int c = wj * BK + wk;
-            T ig = T(1);
-            if (HAS_G) {
+            T ig = igo[2];
+            if (HAS_G && !own) {
                 T one[1] = {T(1)}, gb[1] = {T(0.5) * (Gs[cs][c - 1] + Gs[cs][c])}, q[1];
                 quotients<1>(one, gb, q);
                 ig = q[0];
@@ -529,7 +573,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 vo.v0[((int64_t)w0 * n1 + jj) * n2 + kk] = v0_hi;
             if (p >= i0 && p < i1) {
                 if (own_out && vo.y1) vo.y1[((int64_t)p * n1 + jj) * n2 + kk] = YB[cy];
-                const T v1o = vel1(bj, bk), v2o = vel2(bj, bk);
+                const T v1o = vel1(bj, bk, true), v2o = vel2(bj, bk, true);
                 if (kk < g.n2 && (jj < g.n1 || (o1 && jj == g.n1)))
                     vo.v1[((int64_t)p * (n1 + 1) + jj) * n2 + kk] = v1o;
                 if (jj < g.n1 && (kk < g.n2 || (o2 && kk == g.n2)))
@@ -543,7 +587,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                     const int je = j0 + SJ, ke = k0 + tid;
                     const bool wr = o1 && je == g.n1 && ke < g.n2;
                     if (BETA || wr) {
-                        const T v = vel1(SJ + 2, tid + 2);
+                        const T v = vel1(SJ + 2, tid + 2, false);
                         if (wr) vo.v1[((int64_t)p * (n1 + 1) + je) * n2 + ke] = v;
                         if (BETA) V1s[SJ * SK + tid] = v;
                     }
@@ -551,18 +595,18 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                     const int je = j0 + tid - SK, ke = k0 + SK;
                     const bool wr = o2 && ke == g.n2 && je < g.n1;
                     if (BETA || wr) {
-                        const T v = vel2(tid - SK + 2, SK + 2);
+                        const T v = vel2(tid - SK + 2, SK + 2, false);
                         if (wr) vo.v2[((int64_t)p * n1 + je) * (n2 + 1) + ke] = v;
                         if (BETA) V2s[(tid - SK) * (SK + 1) + SK] = v;
                     }
                 }
             }
         } else {
-            V1s[r * SK + l] = vel1(bj, bk);
-            V2s[r * (SK + 1) + l] = vel2(bj, bk);
-            if (tid < SK) V1s[SJ * SK + tid] = vel1(SJ + 2, tid + 2);        // far j edge
+            V1s[r * SK + l] = vel1(bj, bk, true);
+            V2s[r * (SK + 1) + l] = vel2(bj, bk, true);
+            if (tid < SK) V1s[SJ * SK + tid] = vel1(SJ + 2, tid + 2, false);  // far j edge
             else if (tid < SK + SJ)
-                V2s[(tid - SK) * (SK + 1) + SK] = vel2(tid - SK + 2, SK + 2);
+                V2s[(tid - SK) * (SK + 1) + SK] = vel2(tid - SK + 2, SK + 2, false);
         }
         T g_own = T(1);
         if (HAS_G) g_own = Gs[cs][cy];
@@ -646,11 +690,16 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
             if (kahan) {
                 T dv[3] = {f0hi - f0lo, f1hi - f1lo, f2hi - f2lo};
                 if (HAS_G) {
-                    T gg[3] = {g_own, g_own, g_own}, qq[3];
-                    quotients<3>(dv, gg, qq);
-                    dv[0] = qq[0];
-                    dv[1] = qq[1];
-                    dv[2] = qq[2];
+                    if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+                        for (int d = 0; d < 3; d++) dv[d] = gfast ? dv[d] * igo[3] : dv[d] / g_own;
+                    } else {
+                        T gg[3] = {g_own, g_own, g_own}, qq[3];
+                        quotients<3>(dv, gg, qq);
+                        dv[0] = qq[0];
+                        dv[1] = qq[1];
+                        dv[2] = qq[2];
+                    }
                 }
                 T ks = xo, kc = T(0);
 #pragma unroll
@@ -662,9 +711,13 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 acc += f1hi - f1lo;
                 acc += f2hi - f2lo;
                 if (HAS_G) {
-                    T nn[1] = {acc}, dd[1] = {g_own}, qq[1];
-                    quotients<1>(nn, dd, qq);
-                    acc = qq[0];
+                    if constexpr (std::is_same<T, double>::value) {
+                        acc = gfast ? acc * igo[3] : acc / g_own;
+                    } else {
+                        T nn[1] = {acc}, dd[1] = {g_own}, qq[1];
+                        quotients<1>(nn, dd, qq);
+                        acc = qq[0];
+                    }
                 }
                 res = xo - acc;
             }
