@@ -168,8 +168,11 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
     // loads and stores its entry 0 again (same address, same value), so no
     // load or store needs a per-lane branch.
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE64);
-    const bool hasP = wv * WAVE64 < NP - NT, hasY = wv * WAVE64 < NY - NT,
-               has1 = wv * WAVE64 < N1 - NT, has2 = wv * WAVE64 < N2 - NT;
+    // (one flag for the psi^n box, one shared by the y1-sized boxes: a wave
+    // that reaches into any of them runs the entry-1 work of all of them,
+    // the boxes it is past by duplicates)
+    constexpr int NW = (NY > N1 ? (NY > N2 ? NY : N2) : (N1 > N2 ? N1 : N2));
+    const bool hasP = wv * WAVE64 < NP - NT, hasW = wv * WAVE64 < NW - NT;
     int64_t oP[2], oY[2], o1[2], o2[2];
     int eP[2], eY[2], eW1[2], eW2[2];
     for (int m = 0; m < 2; m++) {
@@ -249,22 +252,22 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         const int64_t ic = open0 ? min(max(t, 0), g.n0 - 1) : wt;
         #pragma unroll
         for (int m = 0; m < 2; m++) {
-            const bool dP = m == 0 || hasP, dY = m == 0 || hasY, d1 = m == 0 || has1,
-                       d2 = m == 0 || has2;
-            if (XIN) {
-                if (dY) fP[m] = xin[ic * pl + oY[m]];
-                if (BETA && dP) {
+            if (m == 0 || hasP) {
+                if (!XIN) {
+                    fP[m] = x[ip + oP[m]];
+                } else if (BETA) {
                     const T v = x[ip + oP[m]];
                     if (m) fQ1 = v;
                     else fQ0 = v;
                 }
-            } else if (dP) {
-                fP[m] = x[ip + oP[m]];
             }
-            if (dY) fC0[m] = c0[iw + oY[m]];
-            if (d1) fC1[m] = c1[ic * pl1 + o1[m]];
-            if (d2) fC2[m] = c2[ic * pl2 + o2[m]];
-            if (HAS_G && dY) fG[m] = G[ic * pl + oY[m]];
+            if (m == 0 || hasW) {
+                if (XIN) fP[m] = xin[ic * pl + oY[m]];
+                fC0[m] = c0[iw + oY[m]];
+                fC1[m] = c1[ic * pl1 + o1[m]];
+                fC2[m] = c2[ic * pl2 + o2[m]];
+                if (HAS_G) fG[m] = G[ic * pl + oY[m]];
+            }
         }
     };
     auto store = [&](int t) {   // t: the plane of r3 / r6
@@ -274,18 +277,17 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
         const bool xplane = XIN && (!open0 || (t >= 0 && t < g.n0));
         #pragma unroll
         for (int m = 0; m < 2; m++) {
-            const bool dP = m == 0 || hasP, dY = m == 0 || hasY, d1 = m == 0 || has1,
-                       d2 = m == 0 || has2;
-            if (XIN) {
-                if (xplane && dY) Ys[slot4(t)][eY[m]] = fP[m];
-                if (BETA && dP) Ps[sp][eP[m]] = m ? fQ1 : fQ0;
-            } else if (dP) {
-                Ps[sp][eP[m]] = fP[m];
+            if (m == 0 || hasP) {
+                if (!XIN) Ps[sp][eP[m]] = fP[m];
+                else if (BETA) Ps[sp][eP[m]] = m ? fQ1 : fQ0;
             }
-            if (dY) C0s[sw][eY[m]] = fC0[m];
-            if (d1) C1s[sc][eW1[m]] = fC1[m];
-            if (d2) C2s[sc][eW2[m]] = fC2[m];
-            if (HAS_G && dY) Gs[sc][eY[m]] = fG[m];
+            if (m == 0 || hasW) {
+                if (XIN && xplane) Ys[slot4(t)][eY[m]] = fP[m];
+                C0s[sw][eY[m]] = fC0[m];
+                C1s[sc][eW1[m]] = fC1[m];
+                C2s[sc][eW2[m]] = fC2[m];
+                if (HAS_G) Gs[sc][eY[m]] = fG[m];
+            }
         }
     };
 
@@ -300,7 +302,7 @@ __global__ void __launch_bounds__(NT) k_step3d(G3s g, int th, int tiles_k, int t
                 Ps[slotp<BETA>(t_first - 1)][eP[m]] = x[ipm + oP[m]];
                 Ps[slotp<BETA>(t_first)][eP[m]] = x[ip0 + oP[m]];
             }
-            if (m == 0 || hasY) C0s[slot4(t_first)][eY[m]] = c0[iw0 + oY[m]];
+            if (m == 0 || hasW) C0s[slot4(t_first)][eY[m]] = c0[iw0 + oY[m]];
         }
     }
     int w1 = (int)map_cell(t_first + 1, g.n0, BC_PERIODIC);
