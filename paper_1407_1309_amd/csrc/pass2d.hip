@@ -205,6 +205,7 @@ template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR, bool HG, bool TO
     static constexpr int XR = TOT ? 4 : 2;     // right-neighbour ring (ages 0..1+SH)
     static constexpr int GQ = TOT ? 8 : 4;     // G ring (ages 0..CO+2+SH)
     int n0, n1, i0, i1, bc0, rr, rw;   // rr: next cell row to load, rw: next wall row
+    int pr, pw;                        // rr, rw wrapped periodically (carried row to row)
     int lane_lo, lane_hi;              // lanes of columns 0 and n1-1 (edge strips)
     bool dfl, kahan, out_lane, w1_lane, fix_lo, fix_hi, prefill;
     int64_t ocol, ccol, wcol;          // per-lane column offsets
@@ -219,11 +220,17 @@ template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR, bool HG, bool TO
     Ring<T, XR> xr;
     Ring<T, 2> v0q, v1q, buq, bdq, aq0, aq1;
 
-    // x (or psi^n), psi^n, c1 and G of cell row rr and the dimension-0 wall rw
+    // x (or psi^n), psi^n, c1 and G of cell row r_cell and the dimension-0
+    // wall r_wall
     __device__ __forceinline__ void fetch(int r_cell, int r_wall, T &vx, T &vp, T &v1, T &v0,
                                           T &vg)
     {
-        const int64_t r = map_cell(r_cell, n0, bc0), w = map_wall(r_wall, n0, bc0);
+        fetch_at(map_cell(r_cell, n0, bc0), map_wall(r_wall, n0, bc0), vx, vp, v1, v0, vg);
+    }
+    // the same at mapped rows r (cell) and w (wall)
+    __device__ __forceinline__ void fetch_at(int64_t r, int64_t w, T &vx, T &vp, T &v1, T &v0,
+                                             T &vg)
+    {
         vx = x[r * n1 + ccol];
         if (FCT && !DONOR) vp = pn[r * n1 + ccol];
         v1 = c1[r * (n1 + 1) + wcol];
@@ -231,11 +238,18 @@ template <typename T, bool FCT, bool IGA, bool ABS, bool DONOR, bool HG, bool TO
         if (HG) vg = G[r * n1 + ccol];
     }
 
+    // rows rr / rw: open, clamped; periodic, the carried wrapped indices (a
+    // wrap test per row instead of a division)
     __device__ __forceinline__ void load(int k)
     {
-        fetch(rr, rw, fx[k], fp[k], f1[k], f0[k], fg[k]);
+        const bool open = bc0 == BC_OPEN;
+        const int r = open ? min(max(rr, 0), n0 - 1) : pr;
+        const int w = open ? min(max(rw, 0), n0) : pw;
+        fetch_at(r, w, fx[k], fp[k], f1[k], f0[k], fg[k]);
         rr++;
         rw++;
+        pr = pr + 1 == n0 ? 0 : pr + 1;
+        pw = pw + 1 == n0 ? 0 : pw + 1;
     }
 
     // G of cell row a - k (1 without HG)
@@ -672,6 +686,8 @@ __global__ void __launch_bounds__(WAVE)
         m.rr = a_begin;
         m.rw = a_begin + 1;
     }
+    m.pr = (int)map_cell(m.rr, n0, BC_PERIODIC);
+    m.pw = (int)map_cell(m.rw, n0, BC_PERIODIC);
 #pragma unroll
     for (int k = 0; k < PF; k++) m.load(k);
     for (int a = a_begin; a <= a_end; a += unroll<TOT>())
