@@ -220,3 +220,20 @@ def test_pass_kernel_rejected_where_absent():
         mpdata.Plan((300,), n_iters=2, kernel=mpdata.KERNEL_PASS)
     with pytest.raises(mpdata.MPDATAError):
         mpdata.Plan((64, 64), n_iters=1, kernel=mpdata.KERNEL_PASS)
+
+
+@pytest.mark.parametrize("with_g", [False, True], ids=["g1", "g"])
+@pytest.mark.parametrize("bcs", [(PER, PER), (PER, OPEN)], ids=["pp", "po"])
+@pytest.mark.parametrize("opts", [IGA | FCT | DFL, TOT | FCT, FCT | DFL, TOT | IGA | FCT])
+@pytest.mark.parametrize("shape", [(3, 70), (4, 61), (5, 130)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_pass2d_few_periodic_rows(shape, opts, bcs, with_g):
+    """Fewer periodic rows than a chunk's march: the rows a chunk loads wrap
+    around the domain several times (the row map is carried from row to
+    row), against the oracle with a non-constant field."""
+    psi, c = _inputs(shape, bcs, opts, seed=shape[0] * 97 + opts + bcs[1] + with_g)
+    g = _g_field(shape, seed=opts + shape[0]) if with_g else None
+    for n_iters in ([2] if opts & IGA else [2, 3]):
+        ref = oracle.step(psi, c, g=g, n_iters=n_iters, opts=opts, bc=list(bcs), n_steps=3)
+        out, name = _run(psi, c, bcs, opts, n_iters, 3, torch.float64, g=g)
+        assert name == "k_pass2d", name
+        assert_parity(out, ref, torch.float64, f"{shape} n_iters={n_iters}")
