@@ -24,8 +24,11 @@ CFLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
 
 # Per-file device flags.  The fused 2-D kernel assumes NaN-free data, so its
 # min/max need no operand quieting (IEEE-mode fmax/fmin otherwise cost an
-# extra instruction per operand).
-FILE_FLAGS = {"fused2d_f32.hip": ["-fno-honor-nans"], "fused2d_f64.hip": ["-fno-honor-nans"]}
+# extra instruction per operand); its row loop is one long basic block per
+# row, which the back end's ILP-first scheduler interleaves better (measured:
+# 2-D FP64 -1.9 %, FP32 -4 %, batched FP32 -5 %; the same bits).
+_FUSED2D = ["-fno-honor-nans", "-mllvm", "-amdgpu-sched-strategy=max-ilp"]
+FILE_FLAGS = {"fused2d_f32.hip": _FUSED2D, "fused2d_f64.hip": _FUSED2D}
 
 
 def sources():
@@ -51,6 +54,11 @@ def source_hash(kernel=None):
         if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
             h.update(open(os.path.join(CSRC, f), "rb").read())
+    # the device flags of the files that instantiate the kernel
+    stem = own.rsplit(".", 1)[0] if own else ""
+    for f in sorted(FILE_FLAGS):
+        if own is None or f.startswith(stem):
+            h.update(" ".join(FILE_FLAGS[f]).encode())
     return h.hexdigest()[:16]
 
 
